@@ -1,0 +1,85 @@
+"""The problem statement written out densely (Section 1).
+
+A(E) = E I - H - Sigma^r_L - Sigma^r_R (equation defineA; no phonon term),
+with E replaced by z = E + i eta and the on-site potential V added to H.
+G^r solves A G^r = I and G^< solves A G^< = Sigma^< (G^r)+ (equation
+defineGless1), so G^< = G^r Sigma^< G^r+.  G^> on the diagonal is taken from
+G^> - G^< = G^r - G^r+.
+
+Everything is a plain dense computation: assemble A, LU-factor it with
+partial pivoting (scipy/LAPACK), solve for the needed columns.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def dense_h(h) -> np.ndarray:
+    """H as a dense float64 array (accepts dense arrays, scipy sparse, or an
+    object with a dense_h() method)."""
+    if hasattr(h, "dense_h"):
+        return h.dense_h()
+    if hasattr(h, "toarray"):
+        return h.toarray().astype(np.float64)
+    return np.asarray(h, dtype=np.float64)
+
+
+def assemble_a(h: np.ndarray, v, z: complex, contacts, sig_r) -> np.ndarray:
+    """A = z I - H - diag(V) - sum_c Sigma^r_c placed on contact c's sites."""
+    n = h.shape[0]
+    a = -h.astype(np.complex128)
+    a[np.diag_indices(n)] += z
+    if v is not None:
+        a[np.diag_indices(n)] -= np.asarray(v, dtype=np.float64)
+    for sites, s in zip(contacts, sig_r):
+        a[np.ix_(sites, sites)] -= s
+    return a
+
+
+def full_greens(h, v, e: float, eta: float, contacts, sig_r, sig_less):
+    """Full matrices (G^r, G^<) at one energy; sig_r / sig_less are lists of
+    dense contact blocks in the site order of `contacts`."""
+    hd = dense_h(h)
+    a = assemble_a(hd, v, complex(e, eta), contacts, sig_r)
+    lu = sla.lu_factor(a)
+    g = sla.lu_solve(lu, np.eye(a.shape[0], dtype=np.complex128))
+    n = a.shape[0]
+    sl = np.zeros((n, n), np.complex128)
+    for sites, s in zip(contacts, sig_less):
+        sl[np.ix_(sites, sites)] += s
+    gl = g @ sl @ g.conj().T
+    return g, gl
+
+
+def diag_greens(h, v, energies, eta: float, contacts, sig_r, sig_less):
+    """diag G^r, diag G^<, diag G^> for every energy.
+
+    sig_r[c] and sig_less[c] are [nE, nc, nc] arrays for contact c.
+    Returns three complex128 arrays [nE, n]."""
+    hd = dense_h(h)
+    n = hd.shape[0]
+    energies = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+    ne = energies.size
+    dgr = np.zeros((ne, n), np.complex128)
+    dgl = np.zeros((ne, n), np.complex128)
+    eye = np.eye(n, dtype=np.complex128)
+    for k, e in enumerate(energies):
+        a = assemble_a(hd, v, complex(e, eta), contacts, [s[k] for s in sig_r])
+        lu = sla.lu_factor(a)
+        g = sla.lu_solve(lu, eye)
+        dgr[k] = np.diag(g)
+        acc = np.zeros(n, np.complex128)
+        for sites, s in zip(contacts, sig_less):
+            gc = g[:, sites]                       # columns of G^r on the contact
+            # (G Sigma^< G+)_jj = sum_ab G_ja S_ab conj(G_jb)
+            acc += np.einsum("ja,ab,jb->j", gc, s[k], gc.conj())
+        dgl[k] = acc
+    dgg = dgl + dgr - dgr.conj()
+    return dgr, dgl, dgg
+
+
+def density(dgl: np.ndarray, cweights: np.ndarray) -> np.ndarray:
+    """n_i = sum_E c_E (-i G^<_ii(E)) (real part kept; the imaginary part is
+    zero up to rounding because G^< is skew-Hermitian)."""
+    return np.real(-1j * (np.asarray(cweights)[:, None] * dgl).sum(axis=0))

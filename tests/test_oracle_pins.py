@@ -1,0 +1,289 @@
+"""Pins of the CPU oracle against facts other than itself.
+
+Each test checks the oracle (definition.py, rgf.py, brute.py, gradient.py)
+against something the mathematics or the physics fixes independently:
+50-digit brute force, closed forms of the uniform hard-wall waveguide
+(written here from the characteristic roots of the 1-D chain, not from the
+square-root form the input generator uses), unit transmission per open mode,
+the Bloch band count of the pristine tube, the Keldysh identities, and
+finite differences.
+"""
+import numpy as np
+import pytest
+
+from inputs import devices, leads, workloads
+from oracle import brute, definition, gradient, rgf
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+def _problem(wl, energies=None):
+    e = wl.energies if energies is None else np.asarray(energies)
+    sl, sr, ll, lr = wl.self_energies(e)
+    return e, [sl, sr], [ll, lr]
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+# ---------------------------------------------------------------------------
+# brute force (no LAPACK) <-> dense <-> RGF
+# ---------------------------------------------------------------------------
+
+def test_dense_matches_mpmath_bruteforce():
+    wl = workloads.small_grid(6, 4, n_energies=2, emin=0.05, emax=0.25, eta=1e-3, noise=0.05, seed=11)
+    e, sr, sl = _problem(wl)
+    h = wl.device.dense_h()
+    dgr, dgl, _ = definition.diag_greens(h, None, e, wl.eta, wl.device.contacts, sr, sl)
+    for k in range(len(e)):
+        bgr, bgl = brute.diag_greens(h, None, e[k], wl.eta, wl.device.contacts,
+                                     [s[k] for s in sr], [s[k] for s in sl])
+        assert _rel(dgr[k], bgr) < 1e-11
+        assert _rel(dgl[k], bgl) < 1e-10
+
+
+def test_rgf_matches_mpmath_bruteforce_directly():
+    wl = workloads.small_grid(7, 3, n_energies=2, emin=0.02, emax=0.2, eta=1e-4, noise=0.1, seed=5)
+    e, sr, sl = _problem(wl)
+    h = wl.device.dense_h()
+    rgr, rgl, _ = rgf.diag_greens(wl.device.scipy_h(), None, e, wl.eta, wl.device.layers,
+                                  wl.device.contacts, sr, sl)
+    for k in range(len(e)):
+        bgr, bgl = brute.diag_greens(h, None, e[k], wl.eta, wl.device.contacts,
+                                     [s[k] for s in sr], [s[k] for s in sl])
+        assert _rel(rgr[k], bgr) < 1e-11
+        assert _rel(rgl[k], bgl) < 1e-10
+
+
+def test_rgf_matches_dense_fd_with_potential():
+    v = np.random.default_rng(3).uniform(-0.1, 0.1, 20 * 12)
+    dev = devices.fd2d(20, 12, potential=None)
+    wl = workloads.Workload("t", dev, np.linspace(0.0, 0.4, 3), 1e-6, (0.1, 0.05), 0.025)
+    e, sr, sl = _problem(wl)
+    dgr, dgl, dgg = definition.diag_greens(dev.scipy_h(), v, e, wl.eta, dev.contacts, sr, sl)
+    rgr, rgl, rgg = rgf.diag_greens(dev.scipy_h(), v, e, wl.eta, dev.layers, dev.contacts, sr, sl)
+    assert _rel(rgr, dgr) < 1e-10
+    assert _rel(rgl, dgl) < 1e-9
+    assert _rel(rgg, dgg) < 1e-9
+
+
+def test_rgf_matches_dense_tube():
+    wl = workloads.nanotube(n_cells=4, n_energies=3)
+    e, sr, sl = _problem(wl, [-0.8, 0.1, 0.9])
+    dev = wl.device
+    dgr, dgl, _ = definition.diag_greens(dev.scipy_h(), None, e, wl.eta, dev.contacts, sr, sl)
+    rgr, rgl, _ = rgf.diag_greens(dev.scipy_h(), None, e, wl.eta, dev.layers, dev.contacts, sr, sl)
+    assert _rel(rgr, dgr) < 1e-9
+    assert _rel(rgl, dgl) < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# closed forms of the uniform hard-wall waveguide
+# ---------------------------------------------------------------------------
+
+def _chain_root(z, eps_long, t0):
+    """Decaying root lambda (|lambda| < 1) of t0 l^2 + (z - eps_long) l + t0 = 0."""
+    r = np.roots([t0, z - eps_long, t0])
+    return r[np.argmin(np.abs(r))]
+
+
+def _waveguide_closed_form(ny, nx, t0, z, f_l, f_r):
+    """diag G^r and diag G^< of an ny x nx uniform waveguide between two
+    identical semi-infinite leads, mode by mode.
+
+    Mode m: transverse energy eps_m, longitudinal chain on-site 2 t0 + eps_m,
+    hopping -t0.  Infinite chain: G(y, y') = C lambda^|y - y'| with
+    C = 1 / (z - eps' + 2 t0 lambda).  Lead self-energy of the mode is
+    -t0 lambda, Gamma_m = 2 t0 Im(lambda)."""
+    x = np.arange(1, nx + 1)
+    gr = np.zeros((ny, nx), np.complex128)
+    gl = np.zeros((ny, nx), np.complex128)
+    y = np.arange(ny)
+    for m in range(1, nx + 1):
+        phi2 = (2.0 / (nx + 1)) * np.sin(m * np.pi * x / (nx + 1)) ** 2
+        eps_long = 2 * t0 + 2 * t0 * (1 - np.cos(m * np.pi / (nx + 1)))
+        lam = _chain_root(z, eps_long, t0)
+        c = 1.0 / (z - eps_long + 2 * t0 * lam)
+        gam = 2 * t0 * lam.imag
+        gr += np.outer(np.full(ny, c), phi2)
+        occ = f_l * gam * np.abs(c * lam ** y) ** 2 + f_r * gam * np.abs(c * lam ** (ny - 1 - y)) ** 2
+        gl += 1j * np.outer(occ, phi2)
+    return gr.ravel(), gl.ravel()
+
+
+@pytest.mark.parametrize("eta", [1e-6, 1e-2])
+def test_dense_matches_waveguide_closed_form(eta):
+    ny, nx = 16, 8
+    wl = workloads.uniform_waveguide(ny, nx, n_energies=5, emax=0.6, eta=eta)
+    e, sr, sl = _problem(wl)
+    dgr, dgl, _ = definition.diag_greens(wl.device.scipy_h(), None, e, eta, wl.device.contacts, sr, sl)
+    t0 = wl.device.lead["t0"]
+    for k in range(len(e)):
+        f_l = leads.fermi(e[k], wl.mu[0], wl.kt)
+        f_r = leads.fermi(e[k], wl.mu[1], wl.kt)
+        cgr, cgl = _waveguide_closed_form(ny, nx, t0, complex(e[k], eta), f_l, f_r)
+        assert _rel(dgr[k], cgr) < 1e-10
+        assert _rel(dgl[k], cgl) < 1e-9
+
+
+def test_rgf_matches_waveguide_closed_form_cfg_shape():
+    """64 x 32 uniform waveguide at its 16 energies (the small FP64 workload)."""
+    wl = workloads.uniform_waveguide()
+    e, sr, sl = _problem(wl)
+    rgr, rgl, _ = rgf.diag_greens(wl.device.scipy_h(), None, e, wl.eta, wl.device.layers,
+                                  wl.device.contacts, sr, sl)
+    t0 = wl.device.lead["t0"]
+    for k in range(len(e)):
+        f_l = leads.fermi(e[k], wl.mu[0], wl.kt)
+        f_r = leads.fermi(e[k], wl.mu[1], wl.kt)
+        cgr, cgl = _waveguide_closed_form(64, 32, t0, complex(e[k], wl.eta), f_l, f_r)
+        assert _rel(rgr[k], cgr) < 1e-9
+        if np.max(np.abs(cgl)) > 0:
+            assert _rel(rgl[k], cgl) < 1e-8
+
+
+def test_unit_transmission_per_open_mode():
+    ny, nx = 10, 6
+    wl = workloads.uniform_waveguide(ny, nx, n_energies=1, eta=1e-9)
+    t0 = wl.device.lead["t0"]
+    _, eps = leads.transverse_modes(nx, t0)
+    for e in [0.5, 2.0, 6.0, 15.0]:
+        s = leads.fd_lead_sigma(complex(e, 1e-9), nx, t0)
+        g, _ = definition.full_greens(wl.device.scipy_h(), None, e, 1e-9, wl.device.contacts,
+                                      [s, s], [0 * s, 0 * s])
+        l0, ln = wl.device.contacts
+        g1n = g[np.ix_(l0, ln)]
+        gam = leads.gamma(s)
+        t = np.trace(gam @ g1n @ gam @ g1n.conj().T).real
+        n_open = int(np.sum((e > eps) & (e < eps + 4 * t0)))
+        assert abs(t - n_open) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Keldysh identities
+# ---------------------------------------------------------------------------
+
+def test_lesser_is_skew_hermitian_and_occupation_nonnegative():
+    wl = workloads.small_grid(8, 5, n_energies=3, eta=1e-3, noise=0.05, seed=2)
+    e, sr, sl = _problem(wl)
+    for k in range(len(e)):
+        g, gl = definition.full_greens(wl.device.scipy_h(), None, e[k], wl.eta, wl.device.contacts,
+                                       [s[k] for s in sr], [s[k] for s in sl])
+        assert np.max(np.abs(gl + gl.conj().T)) < 1e-12 * np.max(np.abs(gl))
+        d = np.diag(gl)
+        assert np.max(np.abs(d.real)) < 1e-12 * np.max(np.abs(d))
+        assert np.min((-1j * d).real) > -1e-14
+
+
+def test_spectral_identity_with_eta_broadening():
+    """G^r - G^r+ = -i G^r (Gamma_L + Gamma_R + 2 eta I) G^r+."""
+    wl = workloads.small_grid(9, 4, n_energies=2, eta=1e-2, noise=0.05, seed=9)
+    e, sr, _ = _problem(wl)
+    n = wl.device.n
+    for k in range(len(e)):
+        g, _ = definition.full_greens(wl.device.scipy_h(), None, e[k], wl.eta, wl.device.contacts,
+                                      [s[k] for s in sr], [0 * s[k] for s in sr])
+        gam = np.zeros((n, n), np.complex128)
+        for sites, s in zip(wl.device.contacts, sr):
+            gam[np.ix_(sites, sites)] += leads.gamma(s[k])
+        gam += 2 * wl.eta * np.eye(n)
+        lhs = g - g.conj().T
+        rhs = -1j * g @ gam @ g.conj().T
+        assert _rel(lhs, rhs) < 1e-11
+
+
+def test_equilibrium_lesser():
+    """mu_L = mu_R: G^< = -f (G^r - G^r+) - 2 i eta f G^r G^r+."""
+    dev = devices.fd2d(8, 4)
+    wl = workloads.Workload("eq", dev, np.array([0.05, 0.2]), 1e-2, (0.1, 0.1), 0.025)
+    e, sr, sl = _problem(wl)
+    for k in range(len(e)):
+        g, gl = definition.full_greens(dev.scipy_h(), None, e[k], wl.eta, dev.contacts,
+                                       [s[k] for s in sr], [s[k] for s in sl])
+        f = leads.fermi(e[k], 0.1, 0.025)
+        rhs = -f * (g - g.conj().T) - 2j * wl.eta * f * g @ g.conj().T
+        assert _rel(gl, rhs) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# lead self-energies (inputs): two independent constructions must agree
+# ---------------------------------------------------------------------------
+
+def test_sancho_rubio_matches_closed_form_fd_lead():
+    nx, t0 = 6, 9.0985
+    h00 = 4 * t0 * np.eye(nx) - t0 * (np.eye(nx, k=1) + np.eye(nx, k=-1))
+    h01 = -t0 * np.eye(nx)
+    for e in [0.05, 3.0, 12.0]:
+        z = complex(e, 1e-4)
+        g_right, g_left = leads.sancho_rubio(h00, h01, z)
+        s_sr = h01.T @ g_left @ h01
+        s_cf = leads.fd_lead_sigma(z, nx, t0)
+        assert _rel(s_sr, s_cf) < 1e-9
+
+
+def test_sancho_rubio_surface_dyson_fixed_point_tube():
+    h00, h01 = devices.zigzag_tube_blocks(10, -2.7)
+    z = complex(0.7, 1e-3)
+    gr, gl = leads.sancho_rubio(h00, h01, z)
+    eye = np.eye(h00.shape[0])
+    assert _rel(gr, np.linalg.inv(z * eye - h00 - h01 @ gr @ h01.T)) < 1e-10
+    assert _rel(gl, np.linalg.inv(z * eye - h00 - h01.T @ gl @ h01)) < 1e-10
+
+
+def test_tube_transmission_counts_bloch_bands():
+    h00, h01 = devices.zigzag_tube_blocks(10, -2.7)
+    ks = np.linspace(0, 2 * np.pi, 2001)
+    bands = np.array([np.linalg.eigvalsh(h00 + h01 * np.exp(1j * k) + h01.T * np.exp(-1j * k))
+                      for k in ks])
+    dev = devices.zigzag_tube(3, 10, -2.7, disorder=0.0)
+    for e in [0.2, 0.75, 1.6, 2.2]:
+        # right-moving channels = half the number of crossings of E over a period
+        crossings = np.sum(np.diff(np.sign(bands - e), axis=0) != 0)
+        n_ch = crossings // 2
+        z = complex(e, 1e-8)
+        s_l, s_r = leads.tube_lead_sigmas(z, h00, h01)
+        g, _ = definition.full_greens(dev.scipy_h(), None, e, 1e-8, dev.contacts, [s_l, s_r],
+                                      [0 * s_l, 0 * s_r])
+        g1n = g[np.ix_(dev.contacts[0], dev.contacts[1])]
+        t = np.trace(leads.gamma(s_l) @ g1n @ leads.gamma(s_r) @ g1n.conj().T).real
+        assert abs(t - n_ch) < 1e-4, (e, t, n_ch)
+
+
+# ---------------------------------------------------------------------------
+# gradient
+# ---------------------------------------------------------------------------
+
+def test_gradient_matches_central_differences():
+    wl = workloads.small_grid(6, 4, n_energies=3, emin=0.02, emax=0.3, eta=1e-3)
+    dev = wl.device
+    e, sr, sl = _problem(wl)
+    cw = wl.quad_weights()
+    v0 = np.random.default_rng(7).uniform(-0.03, 0.03, dev.n)
+    nbar = np.random.default_rng(8).uniform(0.5, 1.5, dev.n)
+    vbar = gradient.density_vjp(dev.scipy_h(), v0, e, wl.eta, dev.contacts, sr, sl, cw, nbar)
+    h = 1e-6
+    for k in [0, 5, 11, 17, 23]:
+        vp, vm = v0.copy(), v0.copy()
+        vp[k] += h
+        vm[k] -= h
+        np_ = gradient.density(dev.scipy_h(), vp, e, wl.eta, dev.contacts, sr, sl, cw)
+        nm = gradient.density(dev.scipy_h(), vm, e, wl.eta, dev.contacts, sr, sl, cw)
+        fd = np.dot(nbar, np_ - nm) / (2 * h)
+        assert abs(fd - vbar[k]) < 1e-6 * max(1.0, np.max(np.abs(vbar)))
+
+
+def test_gradient_single_site_closed_form():
+    """n = 1: n = c f Gamma / |A|^2 with A = z - V - Sigma, so
+    dn/dV = c f Gamma 2 Re(A) / |A|^4."""
+    sig = np.array([[0.1 - 0.3j]])
+    z = complex(0.4, 1e-3)
+    v = np.array([0.05])
+    f, c = 0.7, 0.2
+    gam = -2 * sig[0, 0].imag
+    sless = np.array([[1j * f * gam]])
+    vbar = gradient.density_vjp(np.zeros((1, 1)), v, [z.real], z.imag, [np.array([0])],
+                                [sig[None]], [sless[None]], np.array([c]), np.array([1.0]))
+    a = z - v[0] - sig[0, 0]
+    expect = c * f * gam * 2 * a.real / abs(a) ** 4
+    assert abs(vbar[0] - expect) < 1e-12 * abs(expect)
