@@ -1,0 +1,198 @@
+/*
+ * ndnegf -- nested-dissection NEGF solver for MI355X (gfx950): C ABI.
+ *
+ * The library computes, for every energy E of a grid, the diagonals of the
+ * retarded, lesser and greater Green's functions of an open device
+ *
+ *     A(E) G^r = I,   A(E) G^< = Sigma^< (G^r)^+,
+ *     A(E) = (E + i eta) I - H - diag(V) - Sigma^r_L - Sigma^r_R
+ *
+ * (Section 1, equations defineGless1 and defineA, without the phonon term),
+ * by the method of Section 3: a block LDL^T factorization of A over a
+ * nested-dissection tree of point clusters (fold), the inversion of the root
+ * separator block, and a top-down extraction (selected inversion) of every
+ * diagonal block of G^r and G^<; diag G^> follows from G^> - G^< = G^r - G^r+.
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers are ndg_c128 = {re, im} doubles, the layout of
+ *     std::complex<double> and torch.complex128.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory on the plan's device.  The caller owns every buffer it
+ *     passes; the library never keeps a caller pointer after a call returns.
+ *   - No call throws.  Every call returns an ndg_status; on failure
+ *     ndg_last_error() returns a message for the calling thread.
+ *   - Argument and structural errors are reported synchronously.  Numerical
+ *     faults inside kernels (a singular pivot, a non-finite value) are written
+ *     to a device status word and read with ndg_plan_status() after the
+ *     stream has been synchronised.
+ *   - Sites are numbered 0..n-1 by the caller; all per-site inputs and outputs
+ *     use the caller's numbering (the internal cluster ordering is hidden).
+ */
+#ifndef NDNEGF_H
+#define NDNEGF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ndg_symbolic ndg_symbolic; /* separator tree + symbolic analysis (host) */
+typedef struct ndg_plan ndg_plan;         /* device workspace + launch schedule        */
+
+typedef struct {
+  double re, im;
+} ndg_c128;
+
+typedef enum {
+  NDG_OK = 0,
+  NDG_EINVAL = -1,     /* bad argument, size or layout                                  */
+  NDG_ENOTSYM = -2,    /* H is not symmetric (the method needs a complex-symmetric A)   */
+  NDG_ECONTACT = -3,   /* a contact cannot be kept inside one cluster                   */
+  NDG_ESINGULAR = -4,  /* a zero pivot was met while inverting a cluster block          */
+  NDG_ENOMEM = -5,     /* device allocation failed                                      */
+  NDG_EHIP = -6,       /* a HIP runtime call failed                                     */
+  NDG_ENONFINITE = -7  /* a non-finite value reached an output                          */
+} ndg_status;
+
+typedef enum { NDG_FP64 = 0, NDG_MIXED = 1 } ndg_precision;
+
+/* Tree options.  A zeroed struct (or NULL) selects the defaults. */
+typedef struct {
+  int32_t leaf_max;    /* regions of at most this many points become leaves (default 64)     */
+  int32_t max_cluster; /* clusters larger than this are split into a chain (default/max 64)  */
+  int32_t tree_kind;   /* 0 nested dissection (default); 1 layer chain, the partition that
+                          reproduces RGF (Section 3.2, Fig. 6); 2 contacts merged into the top
+                          of the tree (Section 3.2, Fig. 7)                                   */
+} ndg_tree_opts;
+
+/* Summary of a symbolic analysis.  Operation counts follow Section 4.1's
+ * convention (an i x j by j x k product counts ijk, an i x i inversion i^3),
+ * in complex multiply-adds per energy; flops = 8 real flops per complex
+ * multiply-add. */
+typedef struct {
+  int64_t n;
+  int32_t nclusters;
+  int32_t max_height;     /* number of tree levels (leaves are height 1)                  */
+  int32_t max_cluster;    /* largest cluster s_i                                          */
+  int32_t max_boundary;   /* largest boundary b_i (ancestor points coupled after fill)    */
+  int32_t ncontacts;
+  int32_t reserved;
+  int64_t nnz_boundary;   /* sum of b_i                                                   */
+  double ops_fold_inv, ops_fold_psi, ops_fold_update; /* fold: pivot inverses, Psi, Schur updates */
+  double ops_gr_off, ops_gr_diag;                      /* G^r extraction                          */
+  double ops_gl_chain, ops_gl_off, ops_gl_diag;        /* G^< source terms and extraction         */
+  double ops_total;
+  double ops_rgf_equiv;   /* RGF count for a layered device of the same size (0 if unknown) */
+  int64_t workspace_bytes_per_energy; /* device workspace a plan needs per energy in flight */
+} ndg_info;
+
+/* ---------------------------------------------------------------------------
+ * Symbolic analysis (host only, no device work).
+ *
+ * Builds the separator tree of Section 3.2 for the graph of H plus the dense
+ * contact blocks, orders the points cluster by cluster with descendants
+ * before ancestors, and computes for every cluster i the boundary B_i
+ * (ancestor points coupled to the subtree of i after fill), the front
+ * [i, B_i], and the level schedule (clusters of one height are independent,
+ * rule 1 of Section 3.2).
+ *
+ *   n            number of sites
+ *   rowptr, col, val   host CSR of the real symmetric H, 0-based, full
+ *                pattern (both triangles and the diagonal), n+1 / nnz / nnz
+ *                entries.  Copied.
+ *   ncontacts    number of contacts (usually 2: left, right)
+ *   contact_sites[c], contact_n[c]   host array of the sites of contact c;
+ *                the contact self-energy blocks passed to ndg_solve are
+ *                indexed in this order.  Each contact is kept inside one
+ *                cluster (Section 3.1 takes Sigma^< block diagonal).
+ *   coords       host n x 3 row-major site coordinates (any unit), or NULL
+ *                for a purely graph-based dissection.
+ *   opts         tree options or NULL.
+ *   out          receives the analysis; free with ndg_symbolic_destroy.
+ * Errors: NDG_EINVAL (bad sizes / indices), NDG_ENOTSYM (H not symmetric),
+ * NDG_ECONTACT (overlapping contacts, or a contact larger than max_cluster).
+ */
+ndg_status ndg_analyze(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
+                       int32_t ncontacts, const int32_t* const* contact_sites,
+                       const int32_t* contact_n, const double* coords,
+                       const ndg_tree_opts* opts, ndg_symbolic** out);
+void ndg_symbolic_destroy(ndg_symbolic* sy);
+ndg_status ndg_symbolic_info(const ndg_symbolic* sy, ndg_info* out);
+
+/* Copies the tree into caller-owned host arrays (any may be NULL):
+ *   perm[n]              perm[k] = caller site at internal position k
+ *   cl_off[nclusters+1]  cluster i owns internal positions [cl_off[i], cl_off[i+1])
+ *   parent[nclusters]    parent cluster, -1 for a root
+ *   height[nclusters]    leaves 1
+ *   bptr[nclusters+1], bidx[nnz_boundary]   B_i as internal positions
+ * Clusters are numbered in post-order (descendants before ancestors). */
+ndg_status ndg_symbolic_arrays(const ndg_symbolic* sy, int32_t* perm, int32_t* cl_off,
+                               int32_t* parent, int32_t* height, int64_t* bptr, int32_t* bidx);
+
+/* ---------------------------------------------------------------------------
+ * Plan: device workspace and launch schedule for up to max_batch energies in
+ * flight at once (ndg_solve processes larger energy grids in batches).
+ * Allocates all device memory a solve needs, so ndg_solve itself allocates
+ * nothing.  The plan copies what it needs from `sy`; `sy` may be destroyed
+ * afterwards.  device = HIP device ordinal.  A plan must not be used from two
+ * streams at once.
+ * Errors: NDG_EINVAL, NDG_ENOMEM, NDG_EHIP.
+ */
+ndg_status ndg_plan_create(const ndg_symbolic* sy, int32_t max_batch, int32_t device,
+                           ndg_plan** out);
+ndg_status ndg_plan_destroy(ndg_plan* plan);
+ndg_status ndg_plan_info(const ndg_plan* plan, ndg_info* out);
+
+/* ---------------------------------------------------------------------------
+ * Solve: diagonals of G^r, G^<, G^> at nE energies (Section 3.2: fold, root
+ * inversion, G^r extraction; G^< by its four steps), enqueued on `stream`
+ * (a hipStream_t, NULL = default stream); returns once enqueued.
+ *
+ *   E[nE]            device, energies (real); the complex energy is E + i eta
+ *   eta              broadening (>= 0), also the caller's choice for the leads
+ *   V[n]             device, real on-site potential added to diag(H), or NULL
+ *   sig_r[c]         host array of ncontacts device pointers; contact c's
+ *                    retarded self-energy, [nE][nc][nc] row-major in the site
+ *                    order given to ndg_analyze; complex symmetric
+ *   sig_less[c]      same for the lesser self-energy (skew-Hermitian)
+ *   diag_gr, diag_gless, diag_ggreater   device outputs [nE][n] in the
+ *                    caller's site order; diag_ggreater may be NULL
+ *   pivot_norm       device output [nE] or NULL: per energy, the largest
+ *                    infinity norm of a pivot-block inverse (A_ii^(fold))^{-1}
+ *                    over all clusters.  With ||A|| it bounds the rounding
+ *                    error of the extraction: the diagonal blocks are sums
+ *                    A_ii^{-1} + Psi G Psi^T whose terms grow like this norm
+ *                    when E nears an eigenvalue of a closed cluster.
+ *   prec             NDG_FP64: every step in double precision.
+ * Errors (synchronous): NDG_EINVAL for null pointers, nE < 0, eta < 0 or a
+ * precision the plan does not support; NDG_EHIP if a launch fails.
+ * Numerical faults: see ndg_plan_status.
+ */
+ndg_status ndg_solve(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
+                     const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
+                     ndg_c128* diag_gr, ndg_c128* diag_gless, ndg_c128* diag_ggreater,
+                     double* pivot_norm, ndg_precision prec, void* stream);
+
+/* Status word of the last solves on this plan (call after synchronising the
+ * stream).  *code = NDG_OK, NDG_ESINGULAR (a pivot of magnitude 0 in a
+ * cluster inverse) or NDG_ENONFINITE; *energy and *cluster identify the first
+ * fault recorded (-1 if none).  Reading clears the word. */
+ndg_status ndg_plan_status(ndg_plan* plan, int32_t* code, int32_t* energy, int32_t* cluster);
+
+/* Test access: copies one stored block of the most recent batch of energies
+ * to host memory.  which: 0 = pivot inverse (s x s), 1 = Psi (s x b),
+ * 2 = front of G^r over [i, B_i] (f x f), 3 = front of G^< (f x f);
+ * energy indexes the last batch (0 .. batch-1).  Row-major, host `out` of
+ * s*s / s*b / f*f entries.  Synchronises the device. */
+ndg_status ndg_plan_export_block(ndg_plan* plan, int32_t which, int32_t energy, int32_t cluster,
+                                 ndg_c128* out);
+
+const char* ndg_status_string(int32_t status);
+const char* ndg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NDNEGF_H */

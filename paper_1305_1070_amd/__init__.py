@@ -1,0 +1,209 @@
+"""Nested-dissection NEGF solver for MI355X: Python binding of libndnegf.so.
+
+The binding marshals arguments for the C entry points (include/ndnegf.h);
+every step of the computation runs in the library's HIP kernels.  PyTorch is
+used only for device memory and streams.
+
+    sym  = analyze(n, rowptr, col, val, contacts, coords)     # host, once per geometry
+    plan = Plan(sym, max_batch=64)                             # device workspace
+    gr, gl, gg = plan.solve(E, eta, sig_r, sig_less, V=None)   # torch tensors on the GPU
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import NDG_FP64, NDG_MIXED, NdgError, load  # noqa: F401
+
+__all__ = ["analyze", "Symbolic", "Plan", "load", "NdgError", "NDG_FP64", "NDG_MIXED",
+           "ndg_analyze", "ndg_symbolic_info", "ndg_symbolic_arrays", "ndg_plan_create",
+           "ndg_plan_destroy", "ndg_plan_info", "ndg_solve", "ndg_plan_status",
+           "ndg_plan_export_block", "ndg_status_string", "ndg_last_error"]
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+# ----------------------------------------------------------------------------
+# thin wrappers with the C names
+# ----------------------------------------------------------------------------
+
+def ndg_analyze(n, rowptr, col, val, contacts, coords=None, leaf_max=0, max_cluster=0,
+                tree_kind=0):
+    lib = load()
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    cs = [np.ascontiguousarray(c, dtype=np.int32) for c in contacts]
+    cptrs = (_lib.I32P * max(1, len(cs)))(*[_ptr(c, C.c_int32) for c in cs])
+    cn = np.array([len(c) for c in cs] or [0], dtype=np.int32)
+    cc = None
+    if coords is not None:
+        coords = np.ascontiguousarray(coords, dtype=np.float64).reshape(n, 3)
+        cc = _ptr(coords, C.c_double)
+    opts = _lib.TreeOpts(leaf_max, max_cluster, tree_kind)
+    out = C.c_void_p()
+    _lib.check(lib.ndg_analyze(n, _ptr(rowptr, C.c_int64), _ptr(col, C.c_int32),
+                               _ptr(val, C.c_double), len(cs), cptrs, _ptr(cn, C.c_int32), cc,
+                               C.byref(opts), C.byref(out)))
+    return out
+
+
+def ndg_symbolic_info(sy) -> dict:
+    info = _lib.Info()
+    _lib.check(load().ndg_symbolic_info(sy, C.byref(info)))
+    return info.as_dict()
+
+
+def ndg_symbolic_arrays(sy) -> dict:
+    info = ndg_symbolic_info(sy)
+    n, nc, nb = info["n"], info["nclusters"], info["nnz_boundary"]
+    out = {"perm": np.zeros(n, np.int32), "cl_off": np.zeros(nc + 1, np.int32),
+           "parent": np.zeros(nc, np.int32), "height": np.zeros(nc, np.int32),
+           "bptr": np.zeros(nc + 1, np.int64), "bidx": np.zeros(max(1, nb), np.int32)}
+    _lib.check(load().ndg_symbolic_arrays(
+        sy, _ptr(out["perm"], C.c_int32), _ptr(out["cl_off"], C.c_int32),
+        _ptr(out["parent"], C.c_int32), _ptr(out["height"], C.c_int32),
+        _ptr(out["bptr"], C.c_int64), _ptr(out["bidx"], C.c_int32)))
+    out["bidx"] = out["bidx"][:nb]
+    return out
+
+
+def ndg_plan_create(sy, max_batch: int, device: int = 0):
+    out = C.c_void_p()
+    _lib.check(load().ndg_plan_create(sy, max_batch, device, C.byref(out)))
+    return out
+
+
+def ndg_plan_destroy(plan):
+    _lib.check(load().ndg_plan_destroy(plan))
+
+
+def ndg_plan_info(plan) -> dict:
+    info = _lib.Info()
+    _lib.check(load().ndg_plan_info(plan, C.byref(info)))
+    return info.as_dict()
+
+
+def ndg_solve(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, dgr_ptr, dgl_ptr, dgg_ptr,
+              pivot_ptr, prec, stream_ptr):
+    nc = len(sig_r_ptrs)
+    sr = (C.c_void_p * max(1, nc))(*sig_r_ptrs)
+    sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
+    _lib.check(load().ndg_solve(plan, ne, e_ptr, eta, v_ptr, sr, sl, dgr_ptr, dgl_ptr, dgg_ptr,
+                                pivot_ptr, prec, stream_ptr))
+
+
+def ndg_plan_status(plan):
+    code, e, cl = C.c_int32(), C.c_int32(), C.c_int32()
+    _lib.check(load().ndg_plan_status(plan, C.byref(code), C.byref(e), C.byref(cl)))
+    return code.value, e.value, cl.value
+
+
+def ndg_plan_export_block(plan, which, energy, cluster, count):
+    out = np.zeros(max(1, count), np.complex128)
+    _lib.check(load().ndg_plan_export_block(plan, which, energy, cluster, out.ctypes.data))
+    return out[:count]
+
+
+def ndg_status_string(code: int) -> str:
+    return load().ndg_status_string(code).decode()
+
+
+def ndg_last_error() -> str:
+    return load().ndg_last_error().decode()
+
+
+# ----------------------------------------------------------------------------
+# convenience objects
+# ----------------------------------------------------------------------------
+
+class Symbolic:
+    """Separator tree and symbolic analysis of one device geometry (host)."""
+
+    def __init__(self, handle, ncontacts, contact_sizes):
+        self.handle = handle
+        self.ncontacts = ncontacts
+        self.contact_sizes = contact_sizes
+
+    def info(self) -> dict:
+        return ndg_symbolic_info(self.handle)
+
+    def arrays(self) -> dict:
+        return ndg_symbolic_arrays(self.handle)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib._lib is not None:
+            _lib._lib.ndg_symbolic_destroy(self.handle)
+            self.handle = None
+
+
+def analyze(n, rowptr, col, val, contacts, coords=None, leaf_max=0, max_cluster=0, tree_kind=0):
+    h = ndg_analyze(n, rowptr, col, val, contacts, coords, leaf_max, max_cluster, tree_kind)
+    return Symbolic(h, len(contacts), [len(c) for c in contacts])
+
+
+class Plan:
+    """Device workspace for up to max_batch energies in flight."""
+
+    def __init__(self, sym: Symbolic, max_batch: int = 64, device: int = 0):
+        self.sym = sym
+        self.device = device
+        self.handle = ndg_plan_create(sym.handle, max_batch, device)
+        self.max_batch = max_batch
+        self._info = ndg_plan_info(self.handle)
+
+    def info(self) -> dict:
+        return dict(self._info)
+
+    def solve(self, E, eta, sig_r, sig_less, V=None, out=None, prec=NDG_FP64, stream=None,
+              pivot_norm=None):
+        """E: float64 [nE]; sig_r / sig_less: lists of complex128 [nE, nc, nc];
+        V: float64 [n] or None; all torch tensors on this plan's GPU.  Returns
+        (diag G^r, diag G^<, diag G^>) as complex128 [nE, n] tensors.
+        pivot_norm: optional float64 [nE] tensor receiving, per energy, the
+        largest infinity norm of a pivot-block inverse."""
+        import torch
+        n = self._info["n"]
+        ne = int(E.shape[0])
+        dev = E.device
+        if dev.type != "cuda":
+            raise ValueError("inputs must be GPU tensors")
+        for t in list(sig_r) + list(sig_less) + ([V] if V is not None else []):
+            if t.device != dev or not t.is_contiguous():
+                raise ValueError("all inputs must be contiguous tensors on the plan's device")
+        if E.dtype != torch.float64 or not E.is_contiguous():
+            raise ValueError("E must be a contiguous float64 tensor")
+        for k, (a, b) in enumerate(zip(sig_r, sig_less)):
+            ncs = self.sym.contact_sizes[k]
+            for t in (a, b):
+                if t.dtype != torch.complex128 or tuple(t.shape) != (ne, ncs, ncs):
+                    raise ValueError("contact %d self-energy must be complex128 [nE, %d, %d]"
+                                     % (k, ncs, ncs))
+        if V is not None and (V.dtype != torch.float64 or V.numel() != n):
+            raise ValueError("V must be float64 [n]")
+        if out is None:
+            out = tuple(torch.empty((ne, n), dtype=torch.complex128, device=dev) for _ in range(3))
+        gr, gl, gg = out
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        ndg_solve(self.handle, ne, E.data_ptr(), float(eta), V.data_ptr() if V is not None else None,
+                  [t.data_ptr() for t in sig_r], [t.data_ptr() for t in sig_less],
+                  gr.data_ptr(), gl.data_ptr(), gg.data_ptr() if gg is not None else None,
+                  pivot_norm.data_ptr() if pivot_norm is not None else None,
+                  prec, C.c_void_p(st.cuda_stream))
+        return gr, gl, gg
+
+    def status(self):
+        return ndg_plan_status(self.handle)
+
+    def export_block(self, which: int, energy: int, cluster: int, shape):
+        cnt = int(np.prod(shape))
+        return ndg_plan_export_block(self.handle, which, energy, cluster, cnt).reshape(shape)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib._lib is not None:
+            _lib._lib.ndg_plan_destroy(self.handle)
+            self.handle = None

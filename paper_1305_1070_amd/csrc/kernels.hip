@@ -1,0 +1,648 @@
+// HIP kernels for gfx950 (CDNA4): the fold (block LDL^T over the separator
+// tree), the root inversion and the top-down extraction of G^r and G^<
+// (Section 3.2), batched over energies x clusters of one tree level.
+//
+// Data: every (energy, cluster) owns dense complex128 blocks in HBM (see
+// ClusterDesc).  Dense complex products run on the FP64 matrix cores:
+// v_mfma_f64_16x16x4_f64 on split real/imaginary planes, four real MFMAs per
+// complex 16x16x4 step, operands staged through LDS in 16-deep K chunks.
+// Pivot blocks (s <= 64) are inverted on chip by Gauss-Jordan elimination
+// with partial pivoting (row search by one wavefront's shuffles).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace ndg {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int KC = 16;  // K chunk staged in LDS per step
+
+struct GemmSmem {
+  double ar[64][KC + 1], ai[64][KC + 1];
+  double br[KC][64 + 1], bi[KC][64 + 1];
+};
+
+struct ZTile {
+  v4d re[2][2];
+  v4d im[2][2];
+};
+
+__device__ inline void ztile_zero(ZTile& a) {
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      a.re[m][n] = v4d{0, 0, 0, 0};
+      a.im[m][n] = v4d{0, 0, 0, 0};
+    }
+}
+
+__device__ inline double2 cz() { return make_double2(0.0, 0.0); }
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// acc += A (64 x K) * B (K x 64).  fa(i, k) and fb(k, j) return the complex
+// operand (and 0 outside the live range); A_IFAST / B_KFAST select which index
+// runs fastest across threads while staging, to match the memory layout.
+// Every thread of the 256-thread block must call this.
+template <bool A_IFAST, bool B_KFAST, class FA, class FB>
+__device__ void zgemm_acc(int K, FA fa, FB fb, ZTile& acc, GemmSmem& sm) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = t + 256 * q;
+      int i, kk;
+      if (A_IFAST) { i = idx & 63; kk = idx >> 6; }
+      else { kk = idx & (KC - 1); i = idx / KC; }
+      const double2 v = (k0 + kk < K) ? fa(i, k0 + kk) : cz();
+      sm.ar[i][kk] = v.x;
+      sm.ai[i][kk] = v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = t + 256 * q;
+      int kk, j;
+      if (B_KFAST) { kk = idx & (KC - 1); j = idx / KC; }
+      else { j = idx & 63; kk = idx >> 6; }
+      const double2 v = (k0 + kk < K) ? fb(k0 + kk, j) : cz();
+      sm.br[kk][j] = v.x;
+      sm.bi[kk][j] = v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < KC; k4 += 4) {
+      const int kq = k4 + (lane >> 4);
+      double are[2], aim[2], bre[2], bim[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int i = wr + m * 16 + (lane & 15);
+        are[m] = sm.ar[i][kq];
+        aim[m] = sm.ai[i][kq];
+      }
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const int j = wc + n * 16 + (lane & 15);
+        bre[n] = sm.br[kq][j];
+        bim[n] = sm.bi[kq][j];
+      }
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bre[n], acc.re[m][n], 0, 0, 0);
+          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim[m], bim[n], acc.re[m][n], 0, 0, 0);
+          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bim[n], acc.im[m][n], 0, 0, 0);
+          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[m], bre[n], acc.im[m][n], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// Calls fs(i, j, re, im) for every tile element this thread holds
+// (v_mfma_f64_16x16x4: lane l, register r -> row l/16 + 4r, column l%16).
+template <class FS>
+__device__ inline void ztile_store(const ZTile& acc, FS fs) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = wr + m * 16 + (lane >> 4) + 4 * r;
+        const int j = wc + n * 16 + (lane & 15);
+        fs(i, j, acc.re[m][n][r], acc.im[m][n][r]);
+      }
+}
+
+__device__ inline void raise_fault(int32_t* status, int code, int e, int cl) {
+  if (atomicCAS(status, 0, code) == 0) {
+    atomicExch(status + 1, e);
+    atomicExch(status + 2, cl);
+  }
+}
+
+__device__ inline double2* slab(const Ctx& c, int e) { return c.ws + (int64_t)e * c.stride; }
+
+// ---------------------------------------------------------------------------
+// Fold: assemble the front [i, B_i] of A^(l) for cluster i.  The front holds
+// the rows of cluster i of A (its entries towards i and B_i, mirrored to the
+// B_i rows) plus the Schur contributions of its children, placed by the
+// children's relative index maps (extend-add, one child at a time so no two
+// threads write one entry at once).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
+  const int cl = cls[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[cl];
+  double2* S = slab(c, e);
+  double2* F = S + d.o_fg;
+  const int f = d.f, s = d.s;
+  const int t = threadIdx.x;
+  for (int64_t q = t; q < (int64_t)f * f; q += 256) F[q] = cz();
+  __syncthreads();
+  for (int kp = c.kids_ptr[cl]; kp < c.kids_ptr[cl + 1]; ++kp) {
+    const int ch = c.kids[kp];
+    const ClusterDesc dc = c.cl[ch];
+    const int bc = dc.b;
+    const int32_t* rel = c.relmap + dc.bptr;
+    const double2* U = S + dc.o_upd;
+    for (int64_t q = t; q < (int64_t)bc * bc; q += 256) {
+      const int r = (int)(q / bc), cc = (int)(q % bc);
+      const int64_t pos = (int64_t)rel[r] * f + rel[cc];
+      const double2 u = U[q];
+      double2 v = F[pos];
+      v.x += u.x;
+      v.y += u.y;
+      F[pos] = v;
+    }
+    __syncthreads();
+  }
+  // rows of cluster i of -H (mirrored into the B_i rows: A is symmetric)
+  for (int p = d.hptr0 + t; p < d.hptr1; p += 256) {
+    const int r = c.hrow[p], fc = c.hcol[p];
+    const double hv = c.hval[p];
+    F[(int64_t)r * f + fc].x -= hv;
+    if (fc >= s) F[(int64_t)fc * f + r].x -= hv;
+  }
+  __syncthreads();
+  const double ez = c.E[c.e0 + e];
+  for (int r = t; r < s; r += 256) {
+    const double v = c.V ? c.V[c.perm[d.pt_off + r]] : 0.0;
+    double2 a = F[(int64_t)r * f + r];
+    a.x += ez - v;
+    a.y += c.eta;
+    F[(int64_t)r * f + r] = a;
+  }
+  __syncthreads();
+  if (d.contact >= 0) {
+    const int cc = d.contact, nc = c.nc[cc];
+    const double2* sg = c.sig_r[cc] + (int64_t)(c.e0 + e) * nc * nc;
+    const int32_t* loc = c.clocal[cc];
+    for (int q = t; q < nc * nc; q += 256) {
+      const int a = q / nc, b = q % nc;
+      const int64_t pos = (int64_t)loc[a] * f + loc[b];
+      const double2 sv = sg[q];
+      double2 v = F[pos];
+      v.x -= sv.x;
+      v.y -= sv.y;
+      F[pos] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pivot block inverse by Gauss-Jordan elimination with partial pivoting, on
+// chip (s <= 64).  Writes (A_ii^(fold))^{-1}; for the root this is G_root.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_factor(Ctx c, const int32_t* cls) {
+  __shared__ double Mr[64][65], Mi[64][65];
+  __shared__ double prr[64], pri[64], pcr[64], pci[64];
+  __shared__ int piv[64];
+  __shared__ int sp;
+  const int cl = cls[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[cl];
+  double2* S = slab(c, e);
+  const double2* F = S + d.o_fg;
+  const int f = d.f, s = d.s;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int q = t; q < s * s; q += 256) {
+    const int i = q / s, j = q % s;
+    const double2 v = F[(int64_t)i * f + j];
+    Mr[i][j] = v.x;
+    Mi[i][j] = v.y;
+  }
+  __syncthreads();
+  bool singular = false;
+  for (int k = 0; k < s; ++k) {
+    if (w == 0) {
+      const int row = k + lane;
+      double mag = -1.0;
+      if (row < s) mag = fabs(Mr[row][k]) + fabs(Mi[row][k]);
+      int arg = row;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double om = __shfl_xor(mag, off);
+        const int oa = __shfl_xor(arg, off);
+        if (om > mag || (om == mag && oa < arg)) { mag = om; arg = oa; }
+      }
+      if (lane == 0) { sp = arg; piv[k] = arg; }
+    }
+    __syncthreads();
+    const int p = sp;
+    if (p != k && t < s) {
+      double tr = Mr[k][t], ti = Mi[k][t];
+      Mr[k][t] = Mr[p][t]; Mi[k][t] = Mi[p][t];
+      Mr[p][t] = tr; Mi[p][t] = ti;
+    }
+    __syncthreads();
+    if (t < s) {
+      prr[t] = Mr[k][t]; pri[t] = Mi[k][t];
+      pcr[t] = Mr[t][k]; pci[t] = Mi[t][k];
+    }
+    __syncthreads();
+    const double ar = prr[k], ai = pri[k];
+    const double den = ar * ar + ai * ai;
+    double dr = 0.0, di = 0.0;
+    if (den > 0.0) { dr = ar / den; di = -ai / den; }
+    else singular = true;
+    for (int q = t; q < s * s; q += 256) {
+      const int i = q / s, j = q % s;
+      // row k scaled by d = 1 / a_kk
+      const double rr = prr[j] * dr - pri[j] * di, ri = prr[j] * di + pri[j] * dr;
+      if (i == k) {
+        if (j == k) { Mr[i][j] = dr; Mi[i][j] = di; }
+        else { Mr[i][j] = rr; Mi[i][j] = ri; }
+      } else {
+        const double fr = pcr[i], fi = pci[i];
+        if (j == k) {
+          Mr[i][j] = -(fr * dr - fi * di);
+          Mi[i][j] = -(fr * di + fi * dr);
+        } else {
+          Mr[i][j] -= fr * rr - fi * ri;
+          Mi[i][j] -= fr * ri + fi * rr;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges on the columns, last interchange first
+  for (int k = s - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k && t < s) {
+      double tr = Mr[t][k], ti = Mi[t][k];
+      Mr[t][k] = Mr[t][p]; Mi[t][k] = Mi[t][p];
+      Mr[t][p] = tr; Mi[t][p] = ti;
+    }
+    __syncthreads();
+  }
+  if (singular && t == 0) raise_fault(c.status, -4, c.e0 + e, cl);
+  double2* Ainv = S + d.o_ainv;
+  for (int q = t; q < s * s; q += 256) {
+    const int i = q / s, j = q % s;
+    Ainv[q] = make_double2(Mr[i][j], Mi[i][j]);
+  }
+  if (c.pivot_norm && w == 0) {
+    // infinity norm of the inverse: one row per lane, then a wave maximum
+    double rs = 0.0;
+    if (lane < s)
+      for (int j = 0; j < s; ++j) rs += sqrt(Mr[lane][j] * Mr[lane][j] + Mi[lane][j] * Mi[lane][j]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+    // non-negative doubles order like their bit patterns
+    if (lane == 0)
+      atomicMax(reinterpret_cast<unsigned long long*>(c.pivot_norm + c.e0 + e),
+                (unsigned long long)__double_as_longlong(rs));
+  }
+}
+
+// Psi_{i,B_i} = -A_ii^{-1} A_{i,B_i}: one 64-column tile per block.
+__global__ void __launch_bounds__(256) k_psi(Ctx c, const ColItem* items) {
+  __shared__ GemmSmem sm;
+  const ColItem it = items[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[it.cl];
+  double2* S = slab(c, e);
+  const double2* Ainv = S + d.o_ainv;
+  const double2* F = S + d.o_fg;
+  double2* Psi = S + d.o_psi;
+  const int s = d.s, b = d.b, f = d.f, j0 = it.tc * 64;
+  const int nj = min(64, b - j0);
+  ZTile acc;
+  ztile_zero(acc);
+  zgemm_acc<false, false>(
+      s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
+      [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm);
+  ztile_store(acc, [&](int i, int j, double re, double im) {
+    if (i < s && j < nj) Psi[(int64_t)i * b + j0 + j] = make_double2(-re, -im);
+  });
+}
+
+// Schur contribution of cluster i to its parent front:
+// U = F_BB + Psi^T F_{i,B} (b x b), one 64 x 64 tile per block.
+__global__ void __launch_bounds__(256) k_update(Ctx c, const UpdItem* items) {
+  __shared__ GemmSmem sm;
+  const UpdItem it = items[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[it.cl];
+  double2* S = slab(c, e);
+  const double2* F = S + d.o_fg;
+  const double2* Psi = S + d.o_psi;
+  double2* U = S + d.o_upd;
+  const int s = d.s, b = d.b, f = d.f;
+  const int i0 = it.tr * 64, j0 = it.tc * 64;
+  const int ni = min(64, b - i0), nj = min(64, b - j0);
+  ZTile acc;
+  ztile_zero(acc);
+  zgemm_acc<true, false>(
+      s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
+      [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm);
+  ztile_store(acc, [&](int i, int j, double re, double im) {
+    if (i < ni && j < nj) {
+      const double2 fb = F[(int64_t)(s + i0 + i) * f + s + j0 + j];
+      U[(int64_t)(i0 + i) * b + j0 + j] = make_double2(fb.x + re, fb.y + im);
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
+// G^< source along a contact's chain (contact cluster and its ancestors).
+// Forward solve L Z = E_c restricted to the chain: Z_c = I on the contact
+// sites, Z_i = sum over chain descendants d coupled to i of Psi_{d,i}^T Z_d
+// (passed up as V_d = Psi_d^T Z_d over B_d), then Zd_i = A_ii^{-1} Z_i.
+// Zf rows [0, s) end up holding Zd_i, rows [s, f) the contribution V_i.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_chain_fwd(Ctx c, const ChainItem* items) {
+  __shared__ GemmSmem sm;
+  const ChainItem it = items[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[it.cl];
+  const int cc = it.c, sc = c.nc[cc];
+  double2* S = slab(c, e);
+  double2* Zf = S + d.o_zf[cc];
+  const double2* Psi = S + d.o_psi;
+  const double2* Ainv = S + d.o_ainv;
+  const int s = d.s, b = d.b, f = d.f;
+  const int t = threadIdx.x;
+  for (int q = t; q < f * sc; q += 256) Zf[q] = cz();
+  __syncthreads();
+  const int ch = d.chain_child[cc];
+  if (ch >= 0) {
+    const ClusterDesc dc = c.cl[ch];
+    const double2* Zc = S + dc.o_zf[cc];
+    const int32_t* rel = c.relmap + dc.bptr;
+    for (int q = t; q < dc.b * sc; q += 256) {
+      const int r = q / sc, a = q % sc;
+      Zf[(int64_t)rel[r] * sc + a] = Zc[(int64_t)(dc.s + r) * sc + a];
+    }
+  } else if (d.contact == cc) {
+    const int32_t* loc = c.clocal[cc];
+    for (int a = t; a < sc; a += 256) Zf[(int64_t)loc[a] * sc + a] = make_double2(1.0, 0.0);
+  }
+  __syncthreads();
+  for (int i0 = 0; i0 < b; i0 += 64) {
+    const int ni = min(64, b - i0);
+    ZTile acc;
+    ztile_zero(acc);
+    zgemm_acc<true, false>(
+        s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
+        [&](int k, int j) { return j < sc ? Zf[(int64_t)k * sc + j] : cz(); }, acc, sm);
+    ztile_store(acc, [&](int i, int j, double re, double im) {
+      if (i < ni && j < sc) {
+        double2 v = Zf[(int64_t)(s + i0 + i) * sc + j];
+        v.x += re;
+        v.y += im;
+        Zf[(int64_t)(s + i0 + i) * sc + j] = v;
+      }
+    });
+  }
+  ZTile acc;
+  ztile_zero(acc);
+  zgemm_acc<false, false>(
+      s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
+      [&](int k, int j) { return j < sc ? Zf[(int64_t)k * sc + j] : cz(); }, acc, sm);
+  ztile_store(acc, [&](int i, int j, double re, double im) {
+    if (i < s && j < sc) Zf[(int64_t)i * sc + j] = make_double2(re, im);
+  });
+}
+
+// Back substitution along the chain: X = rows of the contact's column of G^r,
+// X_B gathered from the parent's front, X_i = Zd_i + Psi_i X_B.  Then the
+// source of the G^< extraction on the cluster's rows:
+// P_init = sum_c Zd_i Sigma^<_c (X_front)^+ (s x f), written into rows [0, s)
+// of the G^< front.  This is D^{-1} L^{-1} Sigma^< (G^r)^+ restricted to the
+// front, evaluated as (L^{-1} Sigma^<)(G^r)^+ so only s x sc panels are folded.
+__global__ void __launch_bounds__(256) k_chain_back(Ctx c, const int32_t* cls) {
+  __shared__ GemmSmem sm;
+  const int cl = cls[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[cl];
+  double2* S = slab(c, e);
+  const double2* Psi = S + d.o_psi;
+  double2* FP = S + d.o_fp;
+  const int s = d.s, b = d.b, f = d.f;
+  const int t = threadIdx.x;
+  bool first = true;
+  for (int cc = 0; cc < c.ncontacts; ++cc) {
+    if (!((d.chain_mask >> cc) & 1)) continue;
+    const int sc = c.nc[cc];
+    double2* Xf = S + d.o_xf[cc];
+    const double2* Zf = S + d.o_zf[cc];
+    double2* T = S + d.o_t[cc];
+    if (d.parent >= 0) {
+      const ClusterDesc dp = c.cl[d.parent];
+      const double2* Xp = S + dp.o_xf[cc];
+      const int32_t* rel = c.relmap + d.bptr;
+      for (int q = t; q < b * sc; q += 256) {
+        const int r = q / sc, a = q % sc;
+        Xf[(int64_t)(s + r) * sc + a] = Xp[(int64_t)rel[r] * sc + a];
+      }
+    }
+    __syncthreads();
+    {
+      ZTile acc;
+      ztile_zero(acc);
+      zgemm_acc<false, false>(
+          b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
+          [&](int k, int j) { return j < sc ? Xf[(int64_t)(s + k) * sc + j] : cz(); }, acc, sm);
+      ztile_store(acc, [&](int i, int j, double re, double im) {
+        if (i < s && j < sc) {
+          const double2 z = Zf[(int64_t)i * sc + j];
+          Xf[(int64_t)i * sc + j] = make_double2(z.x + re, z.y + im);
+        }
+      });
+    }
+    __syncthreads();
+    {
+      const double2* sl = c.sig_l[cc] + (int64_t)(c.e0 + e) * sc * sc;
+      ZTile acc;
+      ztile_zero(acc);
+      zgemm_acc<false, false>(
+          sc, [&](int i, int k) { return i < s ? Zf[(int64_t)i * sc + k] : cz(); },
+          [&](int k, int j) { return j < sc ? sl[(int64_t)k * sc + j] : cz(); }, acc, sm);
+      ztile_store(acc, [&](int i, int j, double re, double im) {
+        if (i < s && j < sc) T[(int64_t)i * sc + j] = make_double2(re, im);
+      });
+    }
+    __syncthreads();
+    for (int j0 = 0; j0 < f; j0 += 64) {
+      const int nj = min(64, f - j0);
+      ZTile acc;
+      ztile_zero(acc);
+      zgemm_acc<false, true>(
+          sc, [&](int i, int k) { return i < s ? T[(int64_t)i * sc + k] : cz(); },
+          [&](int k, int j) {
+            if (j >= nj) return cz();
+            const double2 x = Xf[(int64_t)(j0 + j) * sc + k];
+            return make_double2(x.x, -x.y);
+          },
+          acc, sm);
+      ztile_store(acc, [&](int i, int j, double re, double im) {
+        if (i < s && j < nj) {
+          double2* p = FP + (int64_t)i * f + j0 + j;
+          if (first) *p = make_double2(re, im);
+          else { double2 v = *p; v.x += re; v.y += im; *p = v; }
+        }
+      });
+    }
+    __syncthreads();
+    first = false;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Extraction (top-down).  For cluster i with parent p:
+//   G_{i,B} = Psi_i G_{B,B},        G_{B,B} gathered from p's front,
+//   P_{i,B} = P_init + Psi_i P_{B,B},
+// one 64-column tile per block; the front of i also receives G_{B,i} =
+// G_{i,B}^T (P_{B,i} = -P_{i,B}^+) and the gathered B x B block, which i's
+// children read.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_down_off(Ctx c, const ColItem* items, int lesser) {
+  __shared__ GemmSmem sm;
+  const ColItem it = items[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[it.cl];
+  const ClusterDesc dp = c.cl[d.parent];
+  double2* S = slab(c, e);
+  const double2* Psi = S + d.o_psi;
+  double2* X = S + (lesser ? d.o_fp : d.o_fg);
+  const double2* Xp = S + (lesser ? dp.o_fp : dp.o_fg);
+  const int32_t* rel = c.relmap + d.bptr;
+  const int s = d.s, b = d.b, f = d.f, fp = dp.f, j0 = it.tc * 64;
+  const int nj = min(64, b - j0);
+  const bool inner = c.kids_ptr[it.cl + 1] > c.kids_ptr[it.cl];
+  const bool has_src = lesser && d.chain_mask;
+  const int t = threadIdx.x;
+  if (inner) {
+    for (int q = t; q < b * nj; q += 256) {
+      const int k = q / nj, j = q % nj;
+      X[(int64_t)(s + k) * f + s + j0 + j] = Xp[(int64_t)rel[k] * fp + rel[j0 + j]];
+    }
+  }
+  ZTile acc;
+  ztile_zero(acc);
+  zgemm_acc<false, false>(
+      b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
+      [&](int k, int j) { return j < nj ? Xp[(int64_t)rel[k] * fp + rel[j0 + j]] : cz(); }, acc,
+      sm);
+  ztile_store(acc, [&](int i, int j, double re, double im) {
+    if (i < s && j < nj) {
+      double2 v = make_double2(re, im);
+      const int64_t pos = (int64_t)i * f + s + j0 + j;
+      if (has_src) { const double2 p0 = X[pos]; v.x += p0.x; v.y += p0.y; }
+      X[pos] = v;
+      if (inner) X[(int64_t)(s + j0 + j) * f + i] = lesser ? make_double2(-v.x, v.y) : v;
+    }
+  });
+}
+
+//   G_ii = A_ii^{-1} + Psi_i G_{B,i},  G_{B,i} = G_{i,B}^T
+//   P_ii = P_init + Psi_i P_{B,i},     P_{B,i} = -P_{i,B}^+
+__global__ void __launch_bounds__(256) k_down_diag(Ctx c, const int32_t* cls, int lesser) {
+  __shared__ GemmSmem sm;
+  const int cl = cls[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[cl];
+  double2* S = slab(c, e);
+  const double2* Psi = S + d.o_psi;
+  const double2* Ainv = S + d.o_ainv;
+  double2* X = S + (lesser ? d.o_fp : d.o_fg);
+  const int s = d.s, b = d.b, f = d.f;
+  const bool has_src = lesser && d.chain_mask;
+  ZTile acc;
+  ztile_zero(acc);
+  if (lesser) {
+    zgemm_acc<false, true>(
+        b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
+        [&](int k, int j) {
+          if (j >= s) return cz();
+          const double2 x = X[(int64_t)j * f + s + k];
+          return make_double2(-x.x, x.y);
+        },
+        acc, sm);
+  } else {
+    zgemm_acc<false, true>(
+        b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
+        [&](int k, int j) { return j < s ? X[(int64_t)j * f + s + k] : cz(); }, acc, sm);
+  }
+  ztile_store(acc, [&](int i, int j, double re, double im) {
+    if (i < s && j < s) {
+      double2 v = make_double2(re, im);
+      const int64_t pos = (int64_t)i * f + j;
+      if (lesser) {
+        if (has_src) { const double2 p0 = X[pos]; v.x += p0.x; v.y += p0.y; }
+      } else {
+        const double2 a = Ainv[i * s + j];
+        v.x += a.x;
+        v.y += a.y;
+      }
+      X[pos] = v;
+    }
+  });
+}
+
+// diag G^r, G^<, G^> in the caller's site order; G^> = G^< + G^r - (G^r)^*.
+__global__ void __launch_bounds__(256) k_epilogue(Ctx c, double2* dgr, double2* dgl, double2* dgg) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int e = blockIdx.y;
+  if (p >= c.n) return;
+  const int cl = c.owner[p];
+  const ClusterDesc d = c.cl[cl];
+  const int r = p - d.pt_off;
+  const double2* S = slab(c, e);
+  const double2 gr = S[d.o_fg + (int64_t)r * d.f + r];
+  const double2 gl = S[d.o_fp + (int64_t)r * d.f + r];
+  const int64_t o = (int64_t)(c.e0 + e) * c.n + c.perm[p];
+  dgr[o] = gr;
+  dgl[o] = gl;
+  if (dgg) dgg[o] = make_double2(gl.x, gl.y + 2.0 * gr.y);
+  if (!isfinite(gr.x) || !isfinite(gr.y) || !isfinite(gl.x) || !isfinite(gl.y))
+    raise_fault(c.status, -7, c.e0 + e, cl);
+}
+
+__global__ void k_fill_zero(double* p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+void launch_fill_zero(double* p, int64_t count, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count);
+}
+void launch_assemble(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st) {
+  if (ncl > 0) hipLaunchKernelGGL(k_assemble, dim3(ncl, nb), dim3(256), 0, st, c, cls);
+}
+void launch_factor(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st) {
+  if (ncl > 0) hipLaunchKernelGGL(k_factor, dim3(ncl, nb), dim3(256), 0, st, c, cls);
+}
+void launch_psi(const Ctx& c, const ColItem* it, int nit, int nb, hipStream_t st) {
+  if (nit > 0) hipLaunchKernelGGL(k_psi, dim3(nit, nb), dim3(256), 0, st, c, it);
+}
+void launch_update(const Ctx& c, const UpdItem* it, int nit, int nb, hipStream_t st) {
+  if (nit > 0) hipLaunchKernelGGL(k_update, dim3(nit, nb), dim3(256), 0, st, c, it);
+}
+void launch_chain_fwd(const Ctx& c, const ChainItem* it, int nit, int nb, hipStream_t st) {
+  if (nit > 0) hipLaunchKernelGGL(k_chain_fwd, dim3(nit, nb), dim3(256), 0, st, c, it);
+}
+void launch_down_off(const Ctx& c, const ColItem* it, int nit, int nb, bool lesser, hipStream_t st) {
+  if (nit > 0) hipLaunchKernelGGL(k_down_off, dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
+}
+void launch_down_diag(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, hipStream_t st) {
+  if (ncl > 0) hipLaunchKernelGGL(k_down_diag, dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
+}
+void launch_chain_back(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st) {
+  if (ncl > 0) hipLaunchKernelGGL(k_chain_back, dim3(ncl, nb), dim3(256), 0, st, c, cls);
+}
+void launch_epilogue(const Ctx& c, int nb, double2* dgr, double2* dgl, double2* dgg, hipStream_t st) {
+  hipLaunchKernelGGL(k_epilogue, dim3((c.n + 255) / 256, nb), dim3(256), 0, st, c, dgr, dgl, dgg);
+}
+
+}  // namespace ndg

@@ -1,0 +1,72 @@
+// Device-side data layout shared by the runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ndg {
+
+// Per-cluster descriptor (device).  Offsets are in complex elements inside
+// one energy's slab of the workspace; -1 when a block does not exist.
+struct ClusterDesc {
+  int64_t o_ainv;   // s x s   pivot-block inverse (A_ii^(fold))^{-1}
+  int64_t o_psi;    // s x b   Psi_{i,B_i} = -A_ii^{-1} A_{i,B_i}
+  int64_t o_upd;    // b x b   Schur contribution passed to the parent front
+  int64_t o_fg;     // f x f   front of G^r over [i, B_i] (assembled front during the fold)
+  int64_t o_fp;     // f x f   front of G^< (rows i hold the source term before extraction)
+  int64_t o_zf[2];  // f x sc  per contact on whose chain the cluster lies: forward solve
+  int64_t o_xf[2];  // f x sc  per contact: rows of the contact's column of G^r over the front
+  int64_t o_t[2];   // s x sc  per contact: scratch
+  int32_t s, b, f, parent;
+  int32_t pt_off;   // first internal position of the cluster
+  int32_t bptr;     // B_i / relmap entries start here
+  int32_t hptr0, hptr1;
+  int32_t contact;        // contact held by this cluster, or -1
+  int32_t chain_child[2]; // per contact: child on the contact's chain, -1 if none
+  int32_t chain_mask;     // bit c: the cluster is on contact c's chain
+};
+
+struct UpdItem { int32_t cl, tr, tc, pad; };   // Schur update tile (rows tr*64.., cols tc*64..)
+struct ColItem { int32_t cl, tc; };            // column tile of an s x b panel
+struct ChainItem { int32_t cl, c; };           // chain cluster and contact
+
+struct Ctx {
+  const ClusterDesc* cl;
+  const int32_t* relmap;
+  const int32_t* kids_ptr;   // per cluster: [kids_ptr[i], kids_ptr[i+1]) into kids
+  const int32_t* kids;
+  const int32_t* hrow;
+  const int32_t* hcol;
+  const double* hval;
+  const int32_t* perm;
+  const int32_t* owner;
+  const int32_t* clocal[2];  // contact site k -> local row in its cluster
+  int32_t nc[2];
+  int32_t ncontacts;
+  int32_t n;
+  double2* ws;
+  int64_t stride;            // complex elements per energy slab
+  const double* E;
+  int32_t e0;                // first energy of the batch
+  double eta;
+  const double* V;           // may be null
+  const double2* sig_r[2];
+  const double2* sig_l[2];
+  int32_t* status;           // [code, energy, cluster]
+  double* pivot_norm;        // [nE] or null: max over clusters of ||A_ii^{-1}||_inf
+};
+
+// Launchers (kernels.hip).  nb = energies in the batch.
+void launch_assemble(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st);
+void launch_factor(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st);
+void launch_psi(const Ctx& c, const ColItem* it, int nit, int nb, hipStream_t st);
+void launch_update(const Ctx& c, const UpdItem* it, int nit, int nb, hipStream_t st);
+void launch_chain_fwd(const Ctx& c, const ChainItem* it, int nit, int nb, hipStream_t st);
+void launch_down_off(const Ctx& c, const ColItem* it, int nit, int nb, bool lesser, hipStream_t st);
+void launch_down_diag(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, hipStream_t st);
+void launch_chain_back(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st);
+void launch_fill_zero(double* p, int64_t count, hipStream_t st);
+void launch_epilogue(const Ctx& c, int nb, double2* dgr, double2* dgl, double2* dgg, hipStream_t st);
+
+}  // namespace ndg

@@ -1,0 +1,374 @@
+// Plan creation (device workspace, level schedule) and solve orchestration.
+//
+// Per energy, the solve runs the three stages of Section 3.2 level by level:
+//   fold      heights 1 .. L:   assemble fronts, invert pivot blocks, Psi,
+//                               Schur contributions (and the forward solve
+//                               along each contact's chain for G^<);
+//   extract   heights L .. 1:   G^r off-diagonal and diagonal blocks, then the
+//                               G^< source on the contact chains and the G^<
+//                               blocks;
+//   epilogue  diagonals in the caller's site order, G^> from G^< + G^r - G^r+.
+// Clusters of one height are independent (rule 1 of Section 3.2), so every
+// launch covers (energies in the batch) x (clusters or tiles of one height).
+#include "runtime.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../include/ndnegf.h"
+#include "kernels.hpp"
+
+struct ndg_plan {
+  int device = 0;
+  int max_batch = 0;
+  int64_t n = 0;
+  int nclusters = 0;
+  int max_height = 0;
+  int ncontacts = 0;
+  int nc[2] = {0, 0};
+  int64_t stride = 0;  // complex elements per energy slab
+  ndg::OpCounts ops;
+  ndg_info info{};
+  std::vector<ndg::ClusterDesc> hdesc;
+  std::vector<int32_t> hdeg;   // children count (host)
+  // device arrays
+  ndg::ClusterDesc* d_cl = nullptr;
+  int32_t *d_relmap = nullptr, *d_kids_ptr = nullptr, *d_kids = nullptr;
+  int32_t *d_hrow = nullptr, *d_hcol = nullptr;
+  double* d_hval = nullptr;
+  int32_t *d_perm = nullptr, *d_owner = nullptr;
+  int32_t* d_clocal[2] = {nullptr, nullptr};
+  int32_t* d_levels = nullptr;       // clusters by height
+  ndg::ColItem* d_colitems = nullptr;
+  ndg::UpdItem* d_upditems = nullptr;
+  ndg::ChainItem* d_chainitems = nullptr;
+  int32_t* d_chaincls = nullptr;
+  std::vector<int> lvl_ptr, col_ptr, upd_ptr, chain_ptr, chaincl_ptr;  // per height (1-based)
+  double2* d_ws = nullptr;
+  int32_t* d_status = nullptr;
+  int last_batch = 0;
+};
+
+namespace ndg {
+
+namespace {
+
+int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
+
+// Lays out one energy slab; fills desc offsets.  Returns the slab size.
+int64_t layout(const Symbolic& sy, std::vector<ClusterDesc>& desc) {
+  const int nc = sy.nclusters;
+  desc.assign(nc, ClusterDesc{});
+  const int ncont = (int)sy.contact_cluster.size();
+  std::vector<int32_t> mask(nc, 0), chain_child(2 * nc, -1);
+  for (int c = 0; c < ncont && c < kMaxContacts; ++c) {
+    int prev = -1;
+    for (int k = sy.contact_cluster[c]; k >= 0; k = sy.parent[k]) {
+      mask[k] |= 1 << c;
+      chain_child[2 * k + c] = prev;
+      prev = k;
+    }
+  }
+  int64_t off = 0;
+  for (int k = 0; k < nc; ++k) {
+    ClusterDesc& d = desc[k];
+    d.s = sy.s(k);
+    d.b = sy.b(k);
+    d.f = d.s + d.b;
+    d.parent = sy.parent[k];
+    d.pt_off = sy.cl_off[k];
+    d.bptr = (int32_t)sy.bptr[k];
+    d.hptr0 = (int32_t)sy.hptr[k];
+    d.hptr1 = (int32_t)sy.hptr[k + 1];
+    d.contact = -1;
+    for (int c = 0; c < ncont; ++c)
+      if (sy.contact_cluster[c] == k) d.contact = c;
+    d.chain_mask = mask[k];
+    const int64_t s = d.s, b = d.b, f = d.f;
+    d.o_ainv = off; off = align8(off + s * s);
+    d.o_psi = off;  off = align8(off + s * b);
+    d.o_upd = off;  off = align8(off + b * b);
+    d.o_fg = off;   off = align8(off + f * f);
+    d.o_fp = off;   off = align8(off + f * f);
+    for (int c = 0; c < 2; ++c) {
+      d.chain_child[c] = chain_child[2 * k + c];
+      d.o_zf[c] = d.o_xf[c] = d.o_t[c] = -1;
+      if (c < ncont && ((mask[k] >> c) & 1)) {
+        const int64_t sc = (int64_t)sy.contact_local[c].size();
+        d.o_zf[c] = off; off = align8(off + f * sc);
+        d.o_xf[c] = off; off = align8(off + f * sc);
+        d.o_t[c] = off;  off = align8(off + s * sc);
+      }
+    }
+  }
+  return off;
+}
+
+template <class T>
+int upload(T** dst, const T* src, size_t count) {
+  *dst = nullptr;
+  if (count == 0) return 0;
+  if (hipMalloc((void**)dst, sizeof(T) * count) != hipSuccess) return NDG_ENOMEM;
+  if (hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice) != hipSuccess) return NDG_EHIP;
+  return 0;
+}
+
+void free_plan(ndg_plan* p) {
+  if (!p) return;
+  void* ptrs[] = {p->d_cl,        p->d_relmap,   p->d_kids_ptr,   p->d_kids,       p->d_hrow,
+                  p->d_hcol,      p->d_hval,     p->d_perm,       p->d_owner,      p->d_clocal[0],
+                  p->d_clocal[1], p->d_levels,   p->d_colitems,   p->d_upditems,   p->d_chainitems,
+                  p->d_chaincls,  p->d_ws,       p->d_status};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete p;
+}
+
+}  // namespace
+
+int64_t workspace_bytes_per_energy(const Symbolic& sy) {
+  std::vector<ClusterDesc> desc;
+  return layout(sy, desc) * 16;
+}
+
+int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int device, ndg_plan** out) {
+  if ((int)sy.contact_cluster.size() > kMaxContacts) {
+    set_error("ndg_plan_create: at most 2 contacts are supported");
+    return NDG_EINVAL;
+  }
+  if (sy.max_cluster > kMaxCluster) {
+    set_error("ndg_plan_create: a cluster exceeds 64 points");
+    return NDG_EINVAL;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    set_error("ndg_plan_create: no such HIP device");
+    return NDG_EHIP;
+  }
+  if (hipSetDevice(device) != hipSuccess) { set_error("ndg_plan_create: hipSetDevice failed"); return NDG_EHIP; }
+  auto* p = new ndg_plan;
+  p->device = device;
+  p->max_batch = max_batch;
+  p->n = sy.n;
+  p->nclusters = sy.nclusters;
+  p->max_height = sy.max_height;
+  p->ncontacts = (int)sy.contact_cluster.size();
+  for (int c = 0; c < p->ncontacts; ++c) p->nc[c] = (int)sy.contact_local[c].size();
+  p->ops = oc;
+  p->stride = layout(sy, p->hdesc);
+  const int nc = sy.nclusters, H = sy.max_height;
+  // schedules per height
+  std::vector<int32_t> levels;
+  std::vector<ColItem> cols;
+  std::vector<UpdItem> upds;
+  std::vector<ChainItem> chains;
+  std::vector<int32_t> chaincls;
+  p->lvl_ptr.assign(H + 1, 0);
+  p->col_ptr.assign(H + 1, 0);
+  p->upd_ptr.assign(H + 1, 0);
+  p->chain_ptr.assign(H + 1, 0);
+  p->chaincl_ptr.assign(H + 1, 0);
+  for (int h = 1; h <= H; ++h) {
+    for (int q = sy.level_ptr[h - 1]; q < sy.level_ptr[h]; ++q) {
+      const int k = sy.level_order[q];
+      levels.push_back(k);
+      const int b = sy.b(k);
+      const int nt = (b + 63) / 64;
+      for (int tc = 0; tc < nt; ++tc) cols.push_back(ColItem{k, tc});
+      for (int tr = 0; tr < nt; ++tr)
+        for (int tc = 0; tc < nt; ++tc) upds.push_back(UpdItem{k, tr, tc, 0});
+      if (p->hdesc[k].chain_mask) {
+        chaincls.push_back(k);
+        for (int c = 0; c < p->ncontacts; ++c)
+          if ((p->hdesc[k].chain_mask >> c) & 1) chains.push_back(ChainItem{k, c});
+      }
+    }
+    p->lvl_ptr[h] = (int)levels.size();
+    p->col_ptr[h] = (int)cols.size();
+    p->upd_ptr[h] = (int)upds.size();
+    p->chain_ptr[h] = (int)chains.size();
+    p->chaincl_ptr[h] = (int)chaincls.size();
+  }
+  std::vector<int32_t> kids_ptr(nc + 1, 0), kids;
+  for (int k = 0; k < nc; ++k) {
+    for (int32_t ch : sy.children[k]) kids.push_back(ch);
+    kids_ptr[k + 1] = (int32_t)kids.size();
+  }
+  int rc = 0;
+  rc = rc ? rc : upload(&p->d_cl, p->hdesc.data(), p->hdesc.size());
+  rc = rc ? rc : upload(&p->d_relmap, sy.relmap.data(), sy.relmap.size());
+  rc = rc ? rc : upload(&p->d_kids_ptr, kids_ptr.data(), kids_ptr.size());
+  rc = rc ? rc : upload(&p->d_kids, kids.data(), kids.size());
+  rc = rc ? rc : upload(&p->d_hrow, sy.hrow.data(), sy.hrow.size());
+  rc = rc ? rc : upload(&p->d_hcol, sy.hcol.data(), sy.hcol.size());
+  rc = rc ? rc : upload(&p->d_hval, sy.hval.data(), sy.hval.size());
+  rc = rc ? rc : upload(&p->d_perm, sy.perm.data(), sy.perm.size());
+  rc = rc ? rc : upload(&p->d_owner, sy.owner.data(), sy.owner.size());
+  for (int c = 0; c < p->ncontacts && !rc; ++c)
+    rc = upload(&p->d_clocal[c], sy.contact_local[c].data(), sy.contact_local[c].size());
+  rc = rc ? rc : upload(&p->d_levels, levels.data(), levels.size());
+  rc = rc ? rc : upload(&p->d_colitems, cols.data(), cols.size());
+  rc = rc ? rc : upload(&p->d_upditems, upds.data(), upds.size());
+  rc = rc ? rc : upload(&p->d_chainitems, chains.data(), chains.size());
+  rc = rc ? rc : upload(&p->d_chaincls, chaincls.data(), chaincls.size());
+  if (!rc) {
+    const size_t bytes = (size_t)p->stride * 16 * (size_t)max_batch;
+    if (hipMalloc((void**)&p->d_ws, bytes) != hipSuccess) rc = NDG_ENOMEM;
+  }
+  if (!rc) {
+    if (hipMalloc((void**)&p->d_status, 4 * sizeof(int32_t)) != hipSuccess) rc = NDG_ENOMEM;
+    else if (hipMemset(p->d_status, 0, 4 * sizeof(int32_t)) != hipSuccess) rc = NDG_EHIP;
+  }
+  if (rc) {
+    (void)hipGetLastError();
+    free_plan(p);
+    set_error(rc == NDG_ENOMEM ? "ndg_plan_create: device allocation failed" : "ndg_plan_create: HIP copy failed");
+    return rc;
+  }
+  std::memset(&p->info, 0, sizeof(p->info));
+  p->info.n = sy.n;
+  p->info.nclusters = nc;
+  p->info.max_height = H;
+  p->info.max_cluster = sy.max_cluster;
+  p->info.max_boundary = sy.max_boundary;
+  p->info.ncontacts = p->ncontacts;
+  p->info.nnz_boundary = (int64_t)sy.bidx.size();
+  p->info.ops_fold_inv = oc.fold_inv;
+  p->info.ops_fold_psi = oc.fold_psi;
+  p->info.ops_fold_update = oc.fold_update;
+  p->info.ops_gr_off = oc.gr_off;
+  p->info.ops_gr_diag = oc.gr_diag;
+  p->info.ops_gl_chain = oc.gl_chain;
+  p->info.ops_gl_off = oc.gl_off;
+  p->info.ops_gl_diag = oc.gl_diag;
+  p->info.ops_total = oc.total();
+  p->info.workspace_bytes_per_energy = p->stride * 16;
+  *out = p;
+  return NDG_OK;
+}
+
+int plan_destroy(ndg_plan* plan) {
+  if (!plan) return NDG_OK;
+  (void)hipSetDevice(plan->device);
+  free_plan(plan);
+  return NDG_OK;
+}
+
+int plan_info(const ndg_plan* plan, ndg_info* out) {
+  *out = plan->info;
+  return NDG_OK;
+}
+
+int plan_solve(ndg_plan* p, int nE, const double* E, double eta, const double* V,
+               const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
+               ndg_c128* dgl, ndg_c128* dgg, double* pivot_norm, int prec, void* stream) {
+  if (prec != NDG_FP64) {
+    set_error("ndg_solve: this plan supports NDG_FP64 only");
+    return NDG_EINVAL;
+  }
+  if (p->ncontacts > 0 && (!sig_r || !sig_less)) {
+    set_error("ndg_solve: contact self-energies missing");
+    return NDG_EINVAL;
+  }
+  for (int c = 0; c < p->ncontacts; ++c)
+    if (!sig_r[c] || !sig_less[c]) {
+      set_error("ndg_solve: NULL contact self-energy pointer");
+      return NDG_EINVAL;
+    }
+  if (hipSetDevice(p->device) != hipSuccess) { set_error("ndg_solve: hipSetDevice failed"); return NDG_EHIP; }
+  hipStream_t st = (hipStream_t)stream;
+  Ctx c{};
+  c.cl = p->d_cl;
+  c.relmap = p->d_relmap;
+  c.kids_ptr = p->d_kids_ptr;
+  c.kids = p->d_kids;
+  c.hrow = p->d_hrow;
+  c.hcol = p->d_hcol;
+  c.hval = p->d_hval;
+  c.perm = p->d_perm;
+  c.owner = p->d_owner;
+  c.ncontacts = p->ncontacts;
+  for (int q = 0; q < 2; ++q) {
+    c.clocal[q] = p->d_clocal[q];
+    c.nc[q] = p->nc[q];
+    c.sig_r[q] = q < p->ncontacts ? reinterpret_cast<const double2*>(sig_r[q]) : nullptr;
+    c.sig_l[q] = q < p->ncontacts ? reinterpret_cast<const double2*>(sig_less[q]) : nullptr;
+  }
+  c.n = (int32_t)p->n;
+  c.ws = p->d_ws;
+  c.stride = p->stride;
+  c.E = E;
+  c.eta = eta;
+  c.V = V;
+  c.status = p->d_status;
+  c.pivot_norm = pivot_norm;
+  if (pivot_norm) launch_fill_zero(pivot_norm, nE, st);  // a kernel, so graph capture stays valid
+  const int H = p->max_height;
+  for (int e0 = 0; e0 < nE; e0 += p->max_batch) {
+    const int nb = std::min(p->max_batch, nE - e0);
+    c.e0 = e0;
+    for (int h = 1; h <= H; ++h) {
+      const int l0 = p->lvl_ptr[h - 1], nl = p->lvl_ptr[h] - l0;
+      launch_assemble(c, p->d_levels + l0, nl, nb, st);
+      launch_factor(c, p->d_levels + l0, nl, nb, st);
+      launch_psi(c, p->d_colitems + p->col_ptr[h - 1], p->col_ptr[h] - p->col_ptr[h - 1], nb, st);
+      launch_update(c, p->d_upditems + p->upd_ptr[h - 1], p->upd_ptr[h] - p->upd_ptr[h - 1], nb, st);
+      launch_chain_fwd(c, p->d_chainitems + p->chain_ptr[h - 1], p->chain_ptr[h] - p->chain_ptr[h - 1], nb, st);
+    }
+    for (int h = H; h >= 1; --h) {
+      const int l0 = p->lvl_ptr[h - 1], nl = p->lvl_ptr[h] - l0;
+      const int c0 = p->col_ptr[h - 1], ncol = p->col_ptr[h] - c0;
+      launch_down_off(c, p->d_colitems + c0, ncol, nb, false, st);
+      launch_down_diag(c, p->d_levels + l0, nl, nb, false, st);
+      launch_chain_back(c, p->d_chaincls + p->chaincl_ptr[h - 1], p->chaincl_ptr[h] - p->chaincl_ptr[h - 1], nb, st);
+      launch_down_off(c, p->d_colitems + c0, ncol, nb, true, st);
+      launch_down_diag(c, p->d_levels + l0, nl, nb, true, st);
+    }
+    launch_epilogue(c, nb, reinterpret_cast<double2*>(dgr), reinterpret_cast<double2*>(dgl),
+                    reinterpret_cast<double2*>(dgg), st);
+    p->last_batch = nb;
+  }
+  if (hipGetLastError() != hipSuccess) { set_error("ndg_solve: kernel launch failed"); return NDG_EHIP; }
+  return NDG_OK;
+}
+
+int plan_status(ndg_plan* p, int32_t* code, int32_t* energy, int32_t* cluster) {
+  int32_t h[4] = {0, 0, 0, 0};
+  if (hipSetDevice(p->device) != hipSuccess ||
+      hipMemcpy(h, p->d_status, 4 * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemset(p->d_status, 0, 4 * sizeof(int32_t)) != hipSuccess) {
+    set_error("ndg_plan_status: HIP copy failed");
+    return NDG_EHIP;
+  }
+  *code = h[0];
+  *energy = h[0] ? h[1] : -1;
+  *cluster = h[0] ? h[2] : -1;
+  return NDG_OK;
+}
+
+int plan_export_block(ndg_plan* p, int which, int energy, int cluster, ndg_c128* out) {
+  if (cluster < 0 || cluster >= p->nclusters || energy < 0 || energy >= p->last_batch || which < 0 || which > 3) {
+    set_error("ndg_plan_export_block: index out of range");
+    return NDG_EINVAL;
+  }
+  const ClusterDesc& d = p->hdesc[cluster];
+  int64_t off, count;
+  switch (which) {
+    case 0: off = d.o_ainv; count = (int64_t)d.s * d.s; break;
+    case 1: off = d.o_psi; count = (int64_t)d.s * d.b; break;
+    case 2: off = d.o_fg; count = (int64_t)d.f * d.f; break;
+    default: off = d.o_fp; count = (int64_t)d.f * d.f; break;
+  }
+  if (count == 0) return NDG_OK;
+  if (hipSetDevice(p->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(out, p->d_ws + (int64_t)energy * p->stride + off, count * 16, hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("ndg_plan_export_block: HIP copy failed");
+    return NDG_EHIP;
+  }
+  return NDG_OK;
+}
+
+}  // namespace ndg

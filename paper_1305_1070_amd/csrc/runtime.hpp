@@ -1,0 +1,29 @@
+// Runtime of the library: plan (device workspace and level schedule) and
+// solve orchestration.  Host code; kernels live in kernels.hip.
+#pragma once
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/ndnegf.h"
+#include "tree.hpp"
+
+namespace ndg {
+
+constexpr int kMaxCluster = 64;  // largest cluster the pivot kernels hold on chip
+constexpr int kMaxContacts = 2;  // contacts handled by the chain kernels
+
+void set_error(const std::string& msg);
+
+int64_t workspace_bytes_per_energy(const Symbolic& sy);
+
+int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int device, ndg_plan** out);
+int plan_destroy(ndg_plan* plan);
+int plan_info(const ndg_plan* plan, ndg_info* out);
+int plan_solve(ndg_plan* plan, int nE, const double* E, double eta, const double* V,
+               const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
+               ndg_c128* dgl, ndg_c128* dgg, double* pivot_norm, int prec, void* stream);
+int plan_status(ndg_plan* plan, int32_t* code, int32_t* energy, int32_t* cluster);
+int plan_export_block(ndg_plan* plan, int which, int energy, int cluster, ndg_c128* out);
+
+}  // namespace ndg

@@ -1,0 +1,135 @@
+"""Host-side tests of the separator tree and symbolic analysis (no GPU):
+partition rules of Section 3.2, contacts kept whole, boundary sets, and the
+operation-count scaling of Section 4.1.  Also checks that the C ABI library
+loads and exports every entry point include/ndnegf.h declares."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1305_1070_amd as ndg
+from inputs import devices, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ndg.load()
+    hdr = open(os.path.join(ROOT, "include", "ndnegf.h")).read()
+    names = set(re.findall(r"\b(ndg_[a-z_]+)\s*\(", hdr))
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _tree(dev, **kw):
+    sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, **kw)
+    return sym, sym.info(), sym.arrays()
+
+
+def _check_partition(dev, arr):
+    perm, cl_off, parent, bptr, bidx = (arr[k] for k in ("perm", "cl_off", "parent", "bptr", "bidx"))
+    n = dev.n
+    nc = len(cl_off) - 1
+    assert sorted(perm.tolist()) == list(range(n))
+    iperm = np.empty(n, np.int64)
+    iperm[perm] = np.arange(n)
+    owner = np.empty(n, np.int64)
+    for c in range(nc):
+        owner[cl_off[c]:cl_off[c + 1]] = c
+        assert 0 < cl_off[c + 1] - cl_off[c] <= 64
+    # ancestor sets
+    anc = []
+    for c in range(nc):
+        a, p = set(), parent[c]
+        while p >= 0:
+            a.add(int(p))
+            p = parent[p]
+        anc.append(a)
+    # rule 1: every edge joins a cluster to itself, an ancestor or a descendant
+    h = dev.scipy_h().tocoo()
+    for i, j in zip(h.row, h.col):
+        ci, cj = owner[iperm[i]], owner[iperm[j]]
+        assert ci == cj or cj in anc[ci] or ci in anc[cj]
+    # contacts whole
+    for cs in dev.contacts:
+        assert len(set(owner[iperm[cs]].tolist())) == 1
+    # boundary sets: ancestor points, ascending, and contain every direct coupling
+    for c in range(nc):
+        b = bidx[bptr[c]:bptr[c + 1]]
+        assert np.all(np.diff(b) > 0)
+        for q in b:
+            assert owner[q] in anc[c]
+    # post-order: parents after children
+    for c in range(nc):
+        if parent[c] >= 0:
+            assert parent[c] > c
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_partition_rules_fd_grid(kind):
+    dev = devices.fd2d(40, 24)
+    sym, info, arr = _tree(dev, tree_kind=kind, leaf_max=16)
+    _check_partition(dev, arr)
+
+
+def test_partition_rules_tube_and_graph_only():
+    dev = devices.zigzag_tube(12, disorder=0.1)
+    _, _, arr = _tree(dev, leaf_max=24)
+    _check_partition(dev, arr)
+    # without coordinates: level-set separators
+    sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, None, leaf_max=24)
+    _check_partition(dev, sym.arrays())
+
+
+def test_rejects_nonsymmetric_h_and_oversized_contact():
+    dev = devices.fd2d(6, 4)
+    val = dev.val.copy()
+    # break symmetry of one off-diagonal value
+    p = next(p for p in range(dev.rowptr[0], dev.rowptr[1]) if dev.col[p] != 0)
+    val[p] += 1.0
+    with pytest.raises(ndg.NdgError) as ei:
+        ndg.analyze(dev.n, dev.rowptr, dev.col, val, dev.contacts, dev.coords)
+    assert ei.value.code == -2
+    big = devices.fd2d(6, 80)
+    with pytest.raises(ndg.NdgError) as ei:
+        ndg.analyze(big.n, big.rowptr, big.col, big.val, big.contacts, big.coords)
+    assert ei.value.code == -3
+    with pytest.raises(ndg.NdgError):
+        ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, [dev.contacts[0], dev.contacts[0]], dev.coords)
+
+
+def test_operation_count_scaling_square_and_rectangular():
+    """Section 4.1: square N x N devices cost O(N^3) with nested dissection
+    and O(N^4) with RGF; at fixed width the cost grows linearly in length."""
+    ns = [32, 48, 64, 96, 128]
+    nd_ops, rgf_ops = [], []
+    for n in ns:
+        dev = devices.fd2d(n, n)
+        # contacts neglected (Section 4.1): analyse without contacts
+        sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, [], dev.coords, leaf_max=16)
+        info = sym.info()
+        nd_ops.append(info["ops_total"])
+        rgf_ops.append(info["ops_rgf_equiv"])
+    s_nd = np.polyfit(np.log(ns), np.log(nd_ops), 1)[0]
+    s_rgf = np.polyfit(np.log(ns), np.log(rgf_ops), 1)[0]
+    assert 2.6 < s_nd < 3.4, s_nd
+    assert abs(s_rgf - 4.0) < 0.05
+    lens = [256, 512, 1024, 2048]
+    ops = []
+    for l in lens:
+        dev = devices.fd2d(l, 32)
+        sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, leaf_max=16)
+        ops.append(sym.info()["ops_total"])
+    s_len = np.polyfit(np.log(lens), np.log(ops), 1)[0]
+    assert 0.85 < s_len < 1.15, s_len
+
+
+def test_workspace_and_info_superlattice():
+    wl = workloads.superlattice(n_energies=1)
+    dev = wl.device
+    sym, info, arr = _tree(dev, leaf_max=16)
+    assert info["n"] == 65536 and info["max_cluster"] <= 64
+    assert info["ops_total"] < 0.2 * info["ops_rgf_equiv"]
+    assert 0 < info["workspace_bytes_per_energy"] < 2e9
