@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Throughput of the nested-dissection NEGF hot path on one MI355X.
+
+Workload: the quantum-well superlattice on a 1024 x 64 finite-difference
+grid (n = 65 536 sites, dense 64 x 64 contact self-energies), 512 energies in
+[0, 0.5] eV.  One step = diag G^r, diag G^< and diag G^> at all 512 energies
+(fold, root inversion, G^r and G^< extraction, epilogue), inputs already in
+device memory.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = ("energy points/sec (diag G^r+G^<) FP64 vs mixed at 1e-6; fwd+adjoint ms/energy")
+UNIT = "energy points/s"
+PEAK_FP64 = 78.6e12      # MI355X dense FP64 (matrix and vector), flop/s
+PEAK_HBM = 8.0e12        # MI355X HBM3E, bytes/s
+
+
+def _rgf_energy(args):
+    """One energy of the RGF oracle (cpu_baseline leg; runs in a worker)."""
+    idx, n_transport, n_transverse, n_energies = args
+    from inputs import workloads
+    from oracle import rgf
+    wl = workloads.superlattice(n_transport, n_transverse, n_energies=n_energies)
+    e = wl.energies[[idx]]
+    sl, sr, ll, lr = wl.self_energies(e)
+    d = wl.device
+    t = time.perf_counter()
+    gr, gl, _ = rgf.diag_greens(d.scipy_h(), None, e, wl.eta, d.layers, d.contacts, [sl, sr],
+                                [ll, lr])
+    return idx, time.perf_counter() - t, gr[0], gl[0]
+
+
+def cpu_baseline(idxs, wl_args):
+    """Times the RGF oracle on the host cores: one process per core, one BLAS
+    thread each, energies distributed over the pool."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, len(idxs)))
+    t0 = time.perf_counter()
+    res = {}
+    with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+        # warm the workers (imports) before timing
+        list(ex.map(_noop, range(cores)))
+        t0 = time.perf_counter()
+        for idx, dt, gr, gl in ex.map(_rgf_energy, [(i,) + wl_args for i in idxs]):
+            res[idx] = (gr, gl)
+    wall = time.perf_counter() - t0
+    return len(idxs) / wall, cores, wall, res
+
+
+def _noop(_):
+    import inputs.workloads  # noqa: F401
+    import oracle.rgf  # noqa: F401
+    return 0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=128, help="energies in flight per batch")
+    ap.add_argument("--leaf", type=int, default=16, help="leaf size of the separator tree")
+    ap.add_argument("--energies", type=int, default=512)
+    ap.add_argument("--cpu-sample", type=int, default=32,
+                    help="energies of the CPU oracle timing sample (0 disables it)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU; runs on more than one GPU are not part of this build "
+              "(the method shards over energies; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1305_1070_amd as ndg
+    from inputs import workloads
+
+    n_transport, n_transverse = 1024, 64
+    wl = workloads.superlattice(n_transport, n_transverse, n_energies=args.energies)
+    dev = wl.device
+    sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords,
+                      leaf_max=args.leaf)
+    info = sym.info()
+    plan = ndg.Plan(sym, max_batch=min(args.batch, args.energies))
+    cuda = torch.device("cuda:0")
+    sl, sr, ll, lr = wl.self_energies()
+    E = torch.tensor(wl.energies, dtype=torch.float64, device=cuda)
+    sig_r = [torch.from_numpy(a).to(cuda) for a in (sl, sr)]
+    sig_l = [torch.from_numpy(a).to(cuda) for a in (ll, lr)]
+    ne, n = args.energies, dev.n
+    out = tuple(torch.empty((ne, n), dtype=torch.complex128, device=cuda) for _ in range(3))
+    stream = torch.cuda.current_stream(cuda)
+
+    for _ in range(args.warmup):
+        plan.solve(E, wl.eta, sig_r, sig_l, out=out, stream=stream)
+    torch.cuda.synchronize()
+    status = plan.status()
+    plan.profile()  # clear
+    plan.set_profiling(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.solve(E, wl.eta, sig_r, sig_l, out=out, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.set_profiling(False)
+    ms_total = ev0.elapsed_time(ev1)
+    per_level = plan.profile()
+    status2 = plan.status()
+    # one entry per kernel function (G and P extractions share a kernel)
+    stats = {}
+    for r in per_level:
+        name = r["name"].split("(")[0]
+        a = stats.setdefault(name, {"name": name, "launches": 0, "ms": 0.0, "flops": 0.0,
+                                    "bytes": 0.0})
+        for k in ("launches", "ms", "flops", "bytes"):
+            a[k] += r[k]
+    stats = list(stats.values())
+    ms_per_step = ms_total / args.steps
+    value = ne / (ms_per_step / 1e3)
+
+    # dominant kernel and its roofline
+    dom = max(stats, key=lambda r: r["ms"])
+    t_dom = dom["ms"] / 1e3
+    ai = dom["flops"] / max(dom["bytes"], 1.0)
+    if dom["flops"] > 0 and ai >= PEAK_FP64 / PEAK_HBM:
+        roof = {"bound": "mfma", "achieved": dom["flops"] / t_dom / 1e12, "peak": PEAK_FP64 / 1e12,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": dom["bytes"] / t_dom / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom["name"]
+    roof["launches"] = dom["launches"] // args.steps
+    roof["avg_launch_us"] = dom["ms"] / dom["launches"] * 1e3
+    kernels = {r["name"]: {"ms_per_step": r["ms"] / args.steps,
+                           "tflops": r["flops"] / max(r["ms"], 1e-9) / 1e9,
+                           "gbs": r["bytes"] / max(r["ms"], 1e-9) / 1e6} for r in stats}
+
+    # CPU oracle on a bounded sample of the same workload, and parity there
+    cpu = None
+    parity = None
+    if args.cpu_sample > 0:
+        idxs = list(np.linspace(0, ne - 1, args.cpu_sample).round().astype(int))
+        rate, cores, cwall, res = cpu_baseline(idxs, (n_transport, n_transverse, ne))
+        cpu = {"value": rate, "unit": UNIT, "cores": cores, "kind": "oracle",
+               "sample": "%d of the %d energies (evenly spaced), plain RGF oracle, complex128, "
+                         "one process per core, %.1f s wall" % (len(idxs), ne, cwall)}
+        gr = out[0][idxs].cpu().numpy()
+        gl = out[1][idxs].cpu().numpy()
+        errs = []
+        for k, i in enumerate(idxs):
+            rgr, rgl = res[i]
+            errs.append(max(np.max(np.abs(gr[k] - rgr)) / np.max(np.abs(rgr)),
+                            np.max(np.abs(gl[k] - rgl)) / np.max(np.abs(rgl))))
+        errs = np.array(errs)
+        parity = {"energies": len(idxs), "max_rel_err": float(errs.max()),
+                  "median_rel_err": float(np.median(errs)),
+                  "above_1e-10": int(np.sum(errs > 1e-10))}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "precision_path": "fp64",
+        "config": {"workload": "superlattice 1024x64 FD grid, n=65536, dense 64x64 contact "
+                               "self-energies, %d energies in [0,0.5] eV, eta=1e-6" % ne,
+                   "energies": ne, "batch": plan.max_batch, "leaf_max": args.leaf,
+                   "clusters": info["nclusters"], "tree_levels": info["max_height"],
+                   "algorithmic_gflop_per_energy": info["ops_total"] * 8 / 1e9,
+                   "rgf_gflop_per_energy": info["ops_rgf_equiv"] * 8 / 1e9},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "parity_sample": parity,
+        "kernels": kernels,
+        "status": [status, status2],
+        "wall_s_timed": wall,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -158,12 +158,14 @@ ndg_status ndg_plan_info(const ndg_plan* plan, ndg_info* out);
  *   sig_less[c]      same for the lesser self-energy (skew-Hermitian)
  *   diag_gr, diag_gless, diag_ggreater   device outputs [nE][n] in the
  *                    caller's site order; diag_ggreater may be NULL
- *   pivot_norm       device output [nE] or NULL: per energy, the largest
- *                    infinity norm of a pivot-block inverse (A_ii^(fold))^{-1}
- *                    over all clusters.  With ||A|| it bounds the rounding
- *                    error of the extraction: the diagonal blocks are sums
- *                    A_ii^{-1} + Psi G Psi^T whose terms grow like this norm
- *                    when E nears an eigenvalue of a closed cluster.
+ *   growth           device output [nE] or NULL: per energy, the largest
+ *                    ||(A_ii^(fold))^{-1}||_inf ||A_{i,B_i}^(fold)||_inf over the
+ *                    non-root clusters, an upper bound of ||Psi_i||_inf.  The
+ *                    extraction forms G_{i,B} = Psi_i G_{B,B} and
+ *                    G_ii = A_ii^{-1} + Psi_i G_{B,i}; when E nears an eigenvalue
+ *                    of a closed cluster these terms grow like Psi while the sum
+ *                    stays moderate, and rounding errors grow with it.  Values
+ *                    near 1 mean a well-conditioned fold.
  *   prec             NDG_FP64: every step in double precision.
  * Errors (synchronous): NDG_EINVAL for null pointers, nE < 0, eta < 0 or a
  * precision the plan does not support; NDG_EHIP if a launch fails.
@@ -172,7 +174,7 @@ ndg_status ndg_plan_info(const ndg_plan* plan, ndg_info* out);
 ndg_status ndg_solve(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
                      const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
                      ndg_c128* diag_gr, ndg_c128* diag_gless, ndg_c128* diag_ggreater,
-                     double* pivot_norm, ndg_precision prec, void* stream);
+                     double* growth, ndg_precision prec, void* stream);
 
 /* Status word of the last solves on this plan (call after synchronising the
  * stream).  *code = NDG_OK, NDG_ESINGULAR (a pivot of magnitude 0 in a
@@ -187,6 +189,28 @@ ndg_status ndg_plan_status(ndg_plan* plan, int32_t* code, int32_t* energy, int32
  * s*s / s*b / f*f entries.  Synchronises the device. */
 ndg_status ndg_plan_export_block(ndg_plan* plan, int32_t which, int32_t energy, int32_t cluster,
                                  ndg_c128* out);
+
+/* Per-kernel timing.  With profiling enabled the plan records a HIP event
+ * pair around every kernel launch of ndg_solve on the solve's stream; the
+ * statistics hold, per kernel, the number of launches, the summed event time
+ * and the algorithmic work of those launches: flops (8 real flops per complex
+ * multiply-add, Section 4.1's counts) and bytes (each input block read once,
+ * each output block written once), one entry per kernel and tree level.
+ * ndg_plan_profile synchronises the device, copies at most `capacity`
+ * entries, sets *count and clears the statistics. */
+typedef struct {
+  char name[32];
+  int32_t height;   /* tree level of the launches (0 for the epilogue)   */
+  int32_t reserved;
+  int64_t launches;
+  double ms;
+  double flops;
+  double bytes;
+} ndg_kernel_stat;
+
+ndg_status ndg_plan_set_profiling(ndg_plan* plan, int32_t enable);
+ndg_status ndg_plan_profile(ndg_plan* plan, int32_t capacity, ndg_kernel_stat* out,
+                            int32_t* count);
 
 const char* ndg_status_string(int32_t status);
 const char* ndg_last_error(void);

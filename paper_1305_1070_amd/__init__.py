@@ -20,7 +20,8 @@ from ._lib import NDG_FP64, NDG_MIXED, NdgError, load  # noqa: F401
 __all__ = ["analyze", "Symbolic", "Plan", "load", "NdgError", "NDG_FP64", "NDG_MIXED",
            "ndg_analyze", "ndg_symbolic_info", "ndg_symbolic_arrays", "ndg_plan_create",
            "ndg_plan_destroy", "ndg_plan_info", "ndg_solve", "ndg_plan_status",
-           "ndg_plan_export_block", "ndg_status_string", "ndg_last_error"]
+           "ndg_plan_export_block", "ndg_plan_set_profiling", "ndg_plan_profile",
+           "ndg_status_string", "ndg_last_error"]
 
 
 def _ptr(a, ctype):
@@ -89,12 +90,12 @@ def ndg_plan_info(plan) -> dict:
 
 
 def ndg_solve(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, dgr_ptr, dgl_ptr, dgg_ptr,
-              pivot_ptr, prec, stream_ptr):
+              growth_ptr, prec, stream_ptr):
     nc = len(sig_r_ptrs)
     sr = (C.c_void_p * max(1, nc))(*sig_r_ptrs)
     sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
     _lib.check(load().ndg_solve(plan, ne, e_ptr, eta, v_ptr, sr, sl, dgr_ptr, dgl_ptr, dgg_ptr,
-                                pivot_ptr, prec, stream_ptr))
+                                growth_ptr, prec, stream_ptr))
 
 
 def ndg_plan_status(plan):
@@ -107,6 +108,20 @@ def ndg_plan_export_block(plan, which, energy, cluster, count):
     out = np.zeros(max(1, count), np.complex128)
     _lib.check(load().ndg_plan_export_block(plan, which, energy, cluster, out.ctypes.data))
     return out[:count]
+
+
+def ndg_plan_set_profiling(plan, enable: bool):
+    _lib.check(load().ndg_plan_set_profiling(plan, 1 if enable else 0))
+
+
+def ndg_plan_profile(plan) -> list:
+    cap = 4096
+    arr = (_lib.KernelStat * cap)()
+    cnt = C.c_int32()
+    _lib.check(load().ndg_plan_profile(plan, cap, arr, C.byref(cnt)))
+    return [{"name": arr[i].name.decode(), "height": arr[i].height,
+             "launches": arr[i].launches, "ms": arr[i].ms,
+             "flops": arr[i].flops, "bytes": arr[i].bytes} for i in range(cnt.value)]
 
 
 def ndg_status_string(code: int) -> str:
@@ -160,12 +175,12 @@ class Plan:
         return dict(self._info)
 
     def solve(self, E, eta, sig_r, sig_less, V=None, out=None, prec=NDG_FP64, stream=None,
-              pivot_norm=None):
+              growth=None):
         """E: float64 [nE]; sig_r / sig_less: lists of complex128 [nE, nc, nc];
         V: float64 [n] or None; all torch tensors on this plan's GPU.  Returns
         (diag G^r, diag G^<, diag G^>) as complex128 [nE, n] tensors.
-        pivot_norm: optional float64 [nE] tensor receiving, per energy, the
-        largest infinity norm of a pivot-block inverse."""
+        growth: optional float64 [nE] tensor receiving, per energy, the
+        largest ||A_ii^{-1}|| ||A_iB|| over the clusters (bound of ||Psi||)."""
         import torch
         n = self._info["n"]
         ne = int(E.shape[0])
@@ -192,12 +207,18 @@ class Plan:
         ndg_solve(self.handle, ne, E.data_ptr(), float(eta), V.data_ptr() if V is not None else None,
                   [t.data_ptr() for t in sig_r], [t.data_ptr() for t in sig_less],
                   gr.data_ptr(), gl.data_ptr(), gg.data_ptr() if gg is not None else None,
-                  pivot_norm.data_ptr() if pivot_norm is not None else None,
+                  growth.data_ptr() if growth is not None else None,
                   prec, C.c_void_p(st.cuda_stream))
         return gr, gl, gg
 
     def status(self):
         return ndg_plan_status(self.handle)
+
+    def set_profiling(self, enable: bool):
+        ndg_plan_set_profiling(self.handle, enable)
+
+    def profile(self) -> list:
+        return ndg_plan_profile(self.handle)
 
     def export_block(self, which: int, energy: int, cluster: int, shape):
         cnt = int(np.prod(shape))

@@ -44,6 +44,12 @@ class Info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("height", C.c_int32), ("reserved", C.c_int32),
+                ("launches", C.c_int64), ("ms", C.c_double),
+                ("flops", C.c_double), ("bytes", C.c_double)]
+
+
 P = C.c_void_p
 I32P = C.POINTER(C.c_int32)
 I64P = C.POINTER(C.c_int64)
@@ -63,6 +69,8 @@ SIGNATURES = {
                             P, C.c_int, P]),
     "ndg_plan_status": (C.c_int, [P, I32P, I32P, I32P]),
     "ndg_plan_export_block": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, P]),
+    "ndg_plan_set_profiling": (C.c_int, [P, C.c_int32]),
+    "ndg_plan_profile": (C.c_int, [P, C.c_int32, C.POINTER(KernelStat), C.POINTER(C.c_int32)]),
     "ndg_status_string": (C.c_char_p, [C.c_int32]),
     "ndg_last_error": (C.c_char_p, []),
 }

@@ -137,14 +137,14 @@ ndg_status ndg_plan_info(const ndg_plan* plan, ndg_info* out) {
 ndg_status ndg_solve(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
                      const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
                      ndg_c128* diag_gr, ndg_c128* diag_gless, ndg_c128* diag_ggreater,
-                     double* pivot_norm, ndg_precision prec, void* stream) {
+                     double* growth, ndg_precision prec, void* stream) {
   if (!plan) { set_error("ndg_solve: NULL plan"); return NDG_EINVAL; }
   if (nE < 0 || !(eta >= 0)) { set_error("ndg_solve: nE < 0 or eta < 0"); return NDG_EINVAL; }
   if (nE == 0) return NDG_OK;
   if (!E || !diag_gr || !diag_gless) { set_error("ndg_solve: NULL energy or output pointer"); return NDG_EINVAL; }
   if (prec != NDG_FP64 && prec != NDG_MIXED) { set_error("ndg_solve: unknown precision"); return NDG_EINVAL; }
   return (ndg_status)ndg::plan_solve(plan, nE, E, eta, V, sig_r, sig_less, diag_gr, diag_gless,
-                                     diag_ggreater, pivot_norm, (int)prec, stream);
+                                     diag_ggreater, growth, (int)prec, stream);
 }
 
 ndg_status ndg_plan_status(ndg_plan* plan, int32_t* code, int32_t* energy, int32_t* cluster) {
@@ -156,6 +156,20 @@ ndg_status ndg_plan_export_block(ndg_plan* plan, int32_t which, int32_t energy, 
                                  ndg_c128* out) {
   if (!plan || !out) { set_error("ndg_plan_export_block: NULL argument"); return NDG_EINVAL; }
   return (ndg_status)ndg::plan_export_block(plan, which, energy, cluster, out);
+}
+
+ndg_status ndg_plan_set_profiling(ndg_plan* plan, int32_t enable) {
+  if (!plan) { set_error("ndg_plan_set_profiling: NULL plan"); return NDG_EINVAL; }
+  return (ndg_status)ndg::plan_set_profiling(plan, enable != 0);
+}
+
+ndg_status ndg_plan_profile(ndg_plan* plan, int32_t capacity, ndg_kernel_stat* out,
+                            int32_t* count) {
+  if (!plan || !count || capacity < 0 || (capacity > 0 && !out)) {
+    set_error("ndg_plan_profile: bad argument");
+    return NDG_EINVAL;
+  }
+  return (ndg_status)ndg::plan_profile(plan, capacity, out, count);
 }
 
 const char* ndg_status_string(int32_t s) {

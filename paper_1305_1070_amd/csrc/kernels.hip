@@ -289,17 +289,23 @@ __global__ void __launch_bounds__(256) k_factor(Ctx c, const int32_t* cls) {
     const int i = q / s, j = q % s;
     Ainv[q] = make_double2(Mr[i][j], Mi[i][j]);
   }
-  if (c.pivot_norm && w == 0) {
-    // infinity norm of the inverse: one row per lane, then a wave maximum
-    double rs = 0.0;
-    if (lane < s)
-      for (int j = 0; j < s; ++j) rs += sqrt(Mr[lane][j] * Mr[lane][j] + Mi[lane][j] * Mi[lane][j]);
+  if (c.growth && w == 0 && d.b > 0) {
+    // ||A_ii^{-1}||_inf ||A_iB||_inf, one row per lane, then wave maxima
+    double ru = 0.0, rb = 0.0;
+    if (lane < s) {
+      for (int j = 0; j < s; ++j) ru += sqrt(Mr[lane][j] * Mr[lane][j] + Mi[lane][j] * Mi[lane][j]);
+      const double2* row = F + (int64_t)lane * f + s;
+      for (int j = 0; j < d.b; ++j) rb += sqrt(row[j].x * row[j].x + row[j].y * row[j].y);
+    }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+    for (int off = 32; off >= 1; off >>= 1) {
+      ru = fmax(ru, __shfl_xor(ru, off));
+      rb = fmax(rb, __shfl_xor(rb, off));
+    }
     // non-negative doubles order like their bit patterns
     if (lane == 0)
-      atomicMax(reinterpret_cast<unsigned long long*>(c.pivot_norm + c.e0 + e),
-                (unsigned long long)__double_as_longlong(rs));
+      atomicMax(reinterpret_cast<unsigned long long*>(c.growth + c.e0 + e),
+                (unsigned long long)__double_as_longlong(ru * rb));
   }
 }
 

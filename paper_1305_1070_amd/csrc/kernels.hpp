@@ -54,7 +54,7 @@ struct Ctx {
   const double2* sig_r[2];
   const double2* sig_l[2];
   int32_t* status;           // [code, energy, cluster]
-  double* pivot_norm;        // [nE] or null: max over clusters of ||A_ii^{-1}||_inf
+  double* growth;            // [nE] or null: max over clusters of ||A_ii^{-1}|| ||A_iB||
 };
 
 // Launchers (kernels.hip).  nb = energies in the batch.

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -50,11 +51,26 @@ struct ndg_plan {
   double2* d_ws = nullptr;
   int32_t* d_status = nullptr;
   int last_batch = 0;
+  // algorithmic cost per energy of each kernel class at each height
+  std::vector<double> cost_flops, cost_bytes;  // [kKernels * (H + 1)]
+  // profiling
+  bool profiling = false;
+  struct Rec { int kid, h; hipEvent_t a, b; double flops, bytes; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> event_pool;
 };
 
 namespace ndg {
 
 namespace {
+
+enum KernelId {
+  K_ASSEMBLE, K_FACTOR, K_PSI, K_UPDATE, K_CHAIN_FWD, K_DOWN_OFF_G, K_DOWN_DIAG_G, K_CHAIN_BACK,
+  K_DOWN_OFF_P, K_DOWN_DIAG_P, K_EPILOGUE, kKernels
+};
+const char* const kKernelNames[kKernels] = {
+    "k_assemble", "k_factor", "k_psi", "k_update", "k_chain_fwd", "k_down_off(G)",
+    "k_down_diag(G)", "k_chain_back", "k_down_off(P)", "k_down_diag(P)", "k_epilogue"};
 
 int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
@@ -124,6 +140,11 @@ void free_plan(ndg_plan* p) {
                   p->d_chaincls,  p->d_ws,       p->d_status};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  for (auto& r : p->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t ev : p->event_pool) (void)hipEventDestroy(ev);
   delete p;
 }
 
@@ -192,6 +213,36 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
     p->chain_ptr[h] = (int)chains.size();
     p->chaincl_ptr[h] = (int)chaincls.size();
   }
+  // algorithmic work per energy (complex multiply-add = 8 flops; bytes = 16 per
+  // complex element read or written once)
+  p->cost_flops.assign(kKernels * (H + 1), 0.0);
+  p->cost_bytes.assign(kKernels * (H + 1), 0.0);
+  auto addc = [&](int kid, int h, double fl, double by) {
+    p->cost_flops[kid * (H + 1) + h] += fl;
+    p->cost_bytes[kid * (H + 1) + h] += by;
+  };
+  for (int k = 0; k < nc; ++k) {
+    const int h = sy.height[k];
+    const double s = sy.s(k), b = sy.b(k), f = s + b;
+    const bool inner = !sy.children[k].empty();
+    double kidb = 0;
+    for (int32_t ch : sy.children[k]) kidb += (double)sy.b(ch) * sy.b(ch);
+    addc(K_ASSEMBLE, h, 0.0, 16.0 * (f * f + kidb));
+    addc(K_FACTOR, h, 8.0 * s * s * s, 16.0 * 2 * s * s);
+    addc(K_PSI, h, 8.0 * s * s * b, 16.0 * (s * s + 2 * s * b));
+    addc(K_UPDATE, h, 8.0 * s * b * b, 16.0 * (2 * s * b + 2 * b * b));
+    for (int q : {K_DOWN_OFF_G, K_DOWN_OFF_P})
+      addc(q, h, 8.0 * s * b * b, 16.0 * (s * b + b * b + s * b + (inner ? s * b + b * b : 0.0)));
+    for (int q : {K_DOWN_DIAG_G, K_DOWN_DIAG_P}) addc(q, h, 8.0 * s * s * b, 16.0 * (2 * s * b + 2 * s * s));
+    for (int c = 0; c < p->ncontacts; ++c) {
+      if (!((p->hdesc[k].chain_mask >> c) & 1)) continue;
+      const double sc = p->nc[c];
+      addc(K_CHAIN_FWD, h, 8.0 * (s * b * sc + s * s * sc), 16.0 * (s * b + s * s + 2 * f * sc));
+      addc(K_CHAIN_BACK, h, 8.0 * (s * b * sc + s * sc * sc + s * sc * f),
+           16.0 * (s * b + 3 * f * sc + s * sc + sc * sc + s * f));
+    }
+  }
+  addc(K_EPILOGUE, 0, 0.0, 16.0 * 5.0 * (double)sy.n);
   std::vector<int32_t> kids_ptr(nc + 1, 0), kids;
   for (int k = 0; k < nc; ++k) {
     for (int32_t ch : sy.children[k]) kids.push_back(ch);
@@ -264,7 +315,7 @@ int plan_info(const ndg_plan* plan, ndg_info* out) {
 
 int plan_solve(ndg_plan* p, int nE, const double* E, double eta, const double* V,
                const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
-               ndg_c128* dgl, ndg_c128* dgg, double* pivot_norm, int prec, void* stream) {
+               ndg_c128* dgl, ndg_c128* dgg, double* growth, int prec, void* stream) {
   if (prec != NDG_FP64) {
     set_error("ndg_solve: this plan supports NDG_FP64 only");
     return NDG_EINVAL;
@@ -304,34 +355,97 @@ int plan_solve(ndg_plan* p, int nE, const double* E, double eta, const double* V
   c.eta = eta;
   c.V = V;
   c.status = p->d_status;
-  c.pivot_norm = pivot_norm;
-  if (pivot_norm) launch_fill_zero(pivot_norm, nE, st);  // a kernel, so graph capture stays valid
+  c.growth = growth;
+  if (growth) launch_fill_zero(growth, nE, st);  // a kernel, so graph capture stays valid
   const int H = p->max_height;
+  // profiling: an event pair around each launch, with its algorithmic work
+  auto take_event = [&]() {
+    hipEvent_t ev = nullptr;
+    if (!p->event_pool.empty()) { ev = p->event_pool.back(); p->event_pool.pop_back(); }
+    else (void)hipEventCreate(&ev);
+    return ev;
+  };
+  auto timed = [&](int kid, int h, int nb, auto&& launch) {
+    if (!p->profiling) { launch(); return; }
+    ndg_plan::Rec r{kid, h, take_event(), take_event(), p->cost_flops[kid * (H + 1) + h] * nb,
+                    p->cost_bytes[kid * (H + 1) + h] * nb};
+    (void)hipEventRecord(r.a, st);
+    launch();
+    (void)hipEventRecord(r.b, st);
+    p->recs.push_back(r);
+  };
   for (int e0 = 0; e0 < nE; e0 += p->max_batch) {
     const int nb = std::min(p->max_batch, nE - e0);
     c.e0 = e0;
     for (int h = 1; h <= H; ++h) {
       const int l0 = p->lvl_ptr[h - 1], nl = p->lvl_ptr[h] - l0;
-      launch_assemble(c, p->d_levels + l0, nl, nb, st);
-      launch_factor(c, p->d_levels + l0, nl, nb, st);
-      launch_psi(c, p->d_colitems + p->col_ptr[h - 1], p->col_ptr[h] - p->col_ptr[h - 1], nb, st);
-      launch_update(c, p->d_upditems + p->upd_ptr[h - 1], p->upd_ptr[h] - p->upd_ptr[h - 1], nb, st);
-      launch_chain_fwd(c, p->d_chainitems + p->chain_ptr[h - 1], p->chain_ptr[h] - p->chain_ptr[h - 1], nb, st);
+      const ColItem* ci = p->d_colitems + p->col_ptr[h - 1];
+      const int ncol = p->col_ptr[h] - p->col_ptr[h - 1];
+      const UpdItem* ui = p->d_upditems + p->upd_ptr[h - 1];
+      const int nupd = p->upd_ptr[h] - p->upd_ptr[h - 1];
+      const ChainItem* chi = p->d_chainitems + p->chain_ptr[h - 1];
+      const int nch = p->chain_ptr[h] - p->chain_ptr[h - 1];
+      timed(K_ASSEMBLE, h, nb, [&] { launch_assemble(c, p->d_levels + l0, nl, nb, st); });
+      timed(K_FACTOR, h, nb, [&] { launch_factor(c, p->d_levels + l0, nl, nb, st); });
+      if (ncol) timed(K_PSI, h, nb, [&] { launch_psi(c, ci, ncol, nb, st); });
+      if (nupd) timed(K_UPDATE, h, nb, [&] { launch_update(c, ui, nupd, nb, st); });
+      if (nch) timed(K_CHAIN_FWD, h, nb, [&] { launch_chain_fwd(c, chi, nch, nb, st); });
     }
     for (int h = H; h >= 1; --h) {
       const int l0 = p->lvl_ptr[h - 1], nl = p->lvl_ptr[h] - l0;
       const int c0 = p->col_ptr[h - 1], ncol = p->col_ptr[h] - c0;
-      launch_down_off(c, p->d_colitems + c0, ncol, nb, false, st);
-      launch_down_diag(c, p->d_levels + l0, nl, nb, false, st);
-      launch_chain_back(c, p->d_chaincls + p->chaincl_ptr[h - 1], p->chaincl_ptr[h] - p->chaincl_ptr[h - 1], nb, st);
-      launch_down_off(c, p->d_colitems + c0, ncol, nb, true, st);
-      launch_down_diag(c, p->d_levels + l0, nl, nb, true, st);
+      const int k0 = p->chaincl_ptr[h - 1], nck = p->chaincl_ptr[h] - k0;
+      if (ncol) timed(K_DOWN_OFF_G, h, nb, [&] { launch_down_off(c, p->d_colitems + c0, ncol, nb, false, st); });
+      timed(K_DOWN_DIAG_G, h, nb, [&] { launch_down_diag(c, p->d_levels + l0, nl, nb, false, st); });
+      if (nck) timed(K_CHAIN_BACK, h, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, st); });
+      if (ncol) timed(K_DOWN_OFF_P, h, nb, [&] { launch_down_off(c, p->d_colitems + c0, ncol, nb, true, st); });
+      timed(K_DOWN_DIAG_P, h, nb, [&] { launch_down_diag(c, p->d_levels + l0, nl, nb, true, st); });
     }
-    launch_epilogue(c, nb, reinterpret_cast<double2*>(dgr), reinterpret_cast<double2*>(dgl),
-                    reinterpret_cast<double2*>(dgg), st);
+    timed(K_EPILOGUE, 0, nb, [&] {
+      launch_epilogue(c, nb, reinterpret_cast<double2*>(dgr), reinterpret_cast<double2*>(dgl),
+                      reinterpret_cast<double2*>(dgg), st);
+    });
     p->last_batch = nb;
   }
   if (hipGetLastError() != hipSuccess) { set_error("ndg_solve: kernel launch failed"); return NDG_EHIP; }
+  return NDG_OK;
+}
+
+int plan_set_profiling(ndg_plan* p, bool enable) {
+  p->profiling = enable;
+  return NDG_OK;
+}
+
+int plan_profile(ndg_plan* p, int capacity, ndg_kernel_stat* out, int32_t* count) {
+  if (hipSetDevice(p->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    set_error("ndg_plan_profile: device synchronisation failed");
+    return NDG_EHIP;
+  }
+  const int H = p->max_height;
+  std::vector<ndg_kernel_stat> acc(kKernels * (H + 1));
+  std::memset(acc.data(), 0, sizeof(ndg_kernel_stat) * acc.size());
+  for (int k = 0; k < kKernels; ++k)
+    for (int h = 0; h <= H; ++h) {
+      ndg_kernel_stat& a = acc[k * (H + 1) + h];
+      std::snprintf(a.name, sizeof(a.name), "%s", kKernelNames[k]);
+      a.height = h;
+    }
+  for (auto& r : p->recs) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    ndg_kernel_stat& a = acc[r.kid * (H + 1) + r.h];
+    a.launches += 1;
+    a.ms += ms;
+    a.flops += r.flops;
+    a.bytes += r.bytes;
+    p->event_pool.push_back(r.a);
+    p->event_pool.push_back(r.b);
+  }
+  p->recs.clear();
+  int m = 0;
+  for (auto& a : acc)
+    if (a.launches > 0 && m < capacity) out[m++] = a;
+  *count = m;
   return NDG_OK;
 }
 

@@ -28,9 +28,10 @@ def gpu_solve(ndg, wl, energies=None, max_batch=64, tree_kind=0, leaf_max=0, V=N
     Vt = None
     if V is not None:
         Vt = torch.tensor(np.asarray(V, dtype=np.float64), device=cuda)
-    gr, gl, gg = plan.solve(E, wl.eta, sig_r, sig_l, V=Vt)
+    growth = torch.zeros(len(e), dtype=torch.float64, device=cuda)
+    gr, gl, gg = plan.solve(E, wl.eta, sig_r, sig_l, V=Vt, growth=growth)
     torch.cuda.synchronize()
-    out = (gr.cpu().numpy(), gl.cpu().numpy(), gg.cpu().numpy())
+    out = (gr.cpu().numpy(), gl.cpu().numpy(), gg.cpu().numpy(), growth.cpu().numpy())
     status = plan.status()
     if keep_plan:
         return out, status, plan, sym

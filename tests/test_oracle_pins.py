@@ -287,3 +287,16 @@ def test_gradient_single_site_closed_form():
     a = z - v[0] - sig[0, 0]
     expect = c * f * gam * 2 * a.real / abs(a) ** 4
     assert abs(vbar[0] - expect) < 1e-12 * abs(expect)
+
+
+def test_sparse_lu_rows_match_dense_definition():
+    from oracle import sparse
+    wl = workloads.small_grid(14, 9, n_energies=3, emin=0.02, emax=0.4, eta=1e-4, noise=0.05, seed=12)
+    dev = wl.device
+    e, sr, sl = _problem(wl)
+    v = np.random.default_rng(2).uniform(-0.02, 0.02, dev.n)
+    dgr, dgl, _ = definition.diag_greens(dev.scipy_h(), v, e, wl.eta, dev.contacts, sr, sl)
+    sites = np.array([0, 5, 17, 40, 63, 100, dev.n - 1])
+    gr, gl = sparse.sampled_diag(dev.scipy_h(), v, e, wl.eta, dev.contacts, sr, sl, sites)
+    assert _rel(gr, dgr[:, sites]) < 1e-12
+    assert _rel(gl, dgl[:, sites]) < 1e-11
