@@ -1,0 +1,151 @@
+// Device helpers shared by the kernel files: complex tiles on the FP64
+// matrix cores, fault reporting, workspace addressing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace ndg {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int KC = 16;  // K chunk staged in LDS per step
+
+struct GemmSmem {
+  double ar[64][KC + 1], ai[64][KC + 1];
+  double br[KC][64 + 1], bi[KC][64 + 1];
+};
+
+struct ZTile {
+  v4d re[2][2];
+  v4d im[2][2];
+};
+
+__device__ inline void ztile_zero(ZTile& a) {
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      a.re[m][n] = v4d{0, 0, 0, 0};
+      a.im[m][n] = v4d{0, 0, 0, 0};
+    }
+}
+
+__device__ inline double2 cz() { return make_double2(0.0, 0.0); }
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Tile shapes: a 256-thread block computes a TM x 64 complex tile, TM in
+// {64, 32, 16} (TM follows the cluster size so small clusters do not fill
+// matrix-core tiles with padding).  Waves: 2 x 2 of 32 x 32 for TM = 64,
+// 1 x 4 of TM x 16 otherwise.
+template <int TM>
+struct TileShape {
+  static constexpr int WM = TM == 64 ? 2 : 1;        // waves along M
+  static constexpr int WN = 4 / WM;                  // waves along N
+  static constexpr int MB = TM / WM / 16;            // 16-row blocks per wave
+  static constexpr int NB = 64 / WN / 16;            // 16-column blocks per wave
+};
+
+// acc += A (TM x K) * B (K x 64).  fa(i, k) and fb(k, j) return the complex
+// operand (and 0 outside the live range); A_IFAST / B_KFAST select which index
+// runs fastest across threads while staging, to match the memory layout.
+// Every thread of the 256-thread block must call this.
+template <int TM, bool A_IFAST, bool B_KFAST, class FA, class FB>
+__device__ void zgemm_acc_t(int K, FA fa, FB fb, ZTile& acc, GemmSmem& sm) {
+  using T = TileShape<TM>;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+    for (int q = 0; q < TM / 16; ++q) {
+      const int idx = t + 256 * q;
+      int i, kk;
+      if (A_IFAST) { i = idx % TM; kk = idx / TM; }
+      else { kk = idx & (KC - 1); i = idx / KC; }
+      const double2 v = (k0 + kk < K) ? fa(i, k0 + kk) : cz();
+      sm.ar[i][kk] = v.x;
+      sm.ai[i][kk] = v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = t + 256 * q;
+      int kk, j;
+      if (B_KFAST) { kk = idx & (KC - 1); j = idx / KC; }
+      else { j = idx & 63; kk = idx >> 6; }
+      const double2 v = (k0 + kk < K) ? fb(k0 + kk, j) : cz();
+      sm.br[kk][j] = v.x;
+      sm.bi[kk][j] = v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < KC; k4 += 4) {
+      const int kq = k4 + (lane >> 4);
+      double are[2], aim[2], bre[2], bim[2];
+#pragma unroll
+      for (int m = 0; m < T::MB; ++m) {
+        const int i = wr + m * 16 + (lane & 15);
+        are[m] = sm.ar[i][kq];
+        aim[m] = sm.ai[i][kq];
+      }
+#pragma unroll
+      for (int n = 0; n < T::NB; ++n) {
+        const int j = wc + n * 16 + (lane & 15);
+        bre[n] = sm.br[kq][j];
+        bim[n] = sm.bi[kq][j];
+      }
+#pragma unroll
+      for (int m = 0; m < T::MB; ++m)
+#pragma unroll
+        for (int n = 0; n < T::NB; ++n) {
+          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bre[n], acc.re[m][n], 0, 0, 0);
+          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim[m], bim[n], acc.re[m][n], 0, 0, 0);
+          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bim[n], acc.im[m][n], 0, 0, 0);
+          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[m], bre[n], acc.im[m][n], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+}
+
+template <bool A_IFAST, bool B_KFAST, class FA, class FB>
+__device__ void zgemm_acc(int K, FA fa, FB fb, ZTile& acc, GemmSmem& sm) {
+  zgemm_acc_t<64, A_IFAST, B_KFAST>(K, fa, fb, acc, sm);
+}
+
+// Calls fs(i, j, re, im) for every tile element this thread holds
+// (v_mfma_f64_16x16x4: lane l, register r -> row l/16 + 4r, column l%16).
+template <int TM, class FS>
+__device__ inline void ztile_store_t(const ZTile& acc, FS fs) {
+  using T = TileShape<TM>;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
+#pragma unroll
+  for (int m = 0; m < T::MB; ++m)
+#pragma unroll
+    for (int n = 0; n < T::NB; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = wr + m * 16 + (lane >> 4) + 4 * r;
+        const int j = wc + n * 16 + (lane & 15);
+        fs(i, j, acc.re[m][n][r], acc.im[m][n][r]);
+      }
+}
+
+template <class FS>
+__device__ inline void ztile_store(const ZTile& acc, FS fs) {
+  ztile_store_t<64>(acc, fs);
+}
+
+__device__ inline void raise_fault(int32_t* status, int code, int e, int cl) {
+  if (atomicCAS(status, 0, code) == 0) {
+    atomicExch(status + 1, e);
+    atomicExch(status + 2, cl);
+  }
+}
+
+__device__ inline double2* slab(const Ctx& c, int e) { return c.ws + (int64_t)e * c.stride; }
+
+}  // namespace ndg

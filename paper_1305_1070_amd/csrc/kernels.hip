@@ -10,125 +10,10 @@
 // with partial pivoting (row search by one wavefront's shuffles).
 #include <hip/hip_runtime.h>
 
+#include "device_common.hpp"
 #include "kernels.hpp"
 
 namespace ndg {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-constexpr int KC = 16;  // K chunk staged in LDS per step
-
-struct GemmSmem {
-  double ar[64][KC + 1], ai[64][KC + 1];
-  double br[KC][64 + 1], bi[KC][64 + 1];
-};
-
-struct ZTile {
-  v4d re[2][2];
-  v4d im[2][2];
-};
-
-__device__ inline void ztile_zero(ZTile& a) {
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int n = 0; n < 2; ++n) {
-      a.re[m][n] = v4d{0, 0, 0, 0};
-      a.im[m][n] = v4d{0, 0, 0, 0};
-    }
-}
-
-__device__ inline double2 cz() { return make_double2(0.0, 0.0); }
-__device__ inline double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-// acc += A (64 x K) * B (K x 64).  fa(i, k) and fb(k, j) return the complex
-// operand (and 0 outside the live range); A_IFAST / B_KFAST select which index
-// runs fastest across threads while staging, to match the memory layout.
-// Every thread of the 256-thread block must call this.
-template <bool A_IFAST, bool B_KFAST, class FA, class FB>
-__device__ void zgemm_acc(int K, FA fa, FB fb, ZTile& acc, GemmSmem& sm) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  for (int k0 = 0; k0 < K; k0 += KC) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = t + 256 * q;
-      int i, kk;
-      if (A_IFAST) { i = idx & 63; kk = idx >> 6; }
-      else { kk = idx & (KC - 1); i = idx / KC; }
-      const double2 v = (k0 + kk < K) ? fa(i, k0 + kk) : cz();
-      sm.ar[i][kk] = v.x;
-      sm.ai[i][kk] = v.y;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = t + 256 * q;
-      int kk, j;
-      if (B_KFAST) { kk = idx & (KC - 1); j = idx / KC; }
-      else { j = idx & 63; kk = idx >> 6; }
-      const double2 v = (k0 + kk < K) ? fb(k0 + kk, j) : cz();
-      sm.br[kk][j] = v.x;
-      sm.bi[kk][j] = v.y;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k4 = 0; k4 < KC; k4 += 4) {
-      const int kq = k4 + (lane >> 4);
-      double are[2], aim[2], bre[2], bim[2];
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const int i = wr + m * 16 + (lane & 15);
-        are[m] = sm.ar[i][kq];
-        aim[m] = sm.ai[i][kq];
-      }
-#pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        const int j = wc + n * 16 + (lane & 15);
-        bre[n] = sm.br[kq][j];
-        bim[n] = sm.bi[kq][j];
-      }
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int n = 0; n < 2; ++n) {
-          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bre[n], acc.re[m][n], 0, 0, 0);
-          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim[m], bim[n], acc.re[m][n], 0, 0, 0);
-          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bim[n], acc.im[m][n], 0, 0, 0);
-          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[m], bre[n], acc.im[m][n], 0, 0, 0);
-        }
-    }
-    __syncthreads();
-  }
-}
-
-// Calls fs(i, j, re, im) for every tile element this thread holds
-// (v_mfma_f64_16x16x4: lane l, register r -> row l/16 + 4r, column l%16).
-template <class FS>
-__device__ inline void ztile_store(const ZTile& acc, FS fs) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int n = 0; n < 2; ++n)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = wr + m * 16 + (lane >> 4) + 4 * r;
-        const int j = wc + n * 16 + (lane & 15);
-        fs(i, j, acc.re[m][n][r], acc.im[m][n][r]);
-      }
-}
-
-__device__ inline void raise_fault(int32_t* status, int code, int e, int cl) {
-  if (atomicCAS(status, 0, code) == 0) {
-    atomicExch(status + 1, e);
-    atomicExch(status + 2, cl);
-  }
-}
-
-__device__ inline double2* slab(const Ctx& c, int e) { return c.ws + (int64_t)e * c.stride; }
 
 // ---------------------------------------------------------------------------
 // Fold: assemble the front [i, B_i] of A^(l) for cluster i.  The front holds
@@ -201,10 +86,11 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
 // Pivot block inverse by Gauss-Jordan elimination with partial pivoting, on
 // chip (s <= 64).  Writes (A_ii^(fold))^{-1}; for the root this is G_root.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_factor(Ctx c, const int32_t* cls) {
-  __shared__ double Mr[64][65], Mi[64][65];
-  __shared__ double prr[64], pri[64], pcr[64], pci[64];
-  __shared__ int piv[64];
+template <int SM, int NT>
+__global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
+  __shared__ double Mr[SM][SM + 1], Mi[SM][SM + 1];
+  __shared__ double prr[SM], pri[SM], pcr[SM], pci[SM];
+  __shared__ int piv[SM];
   __shared__ int sp;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
@@ -213,7 +99,7 @@ __global__ void __launch_bounds__(256) k_factor(Ctx c, const int32_t* cls) {
   const double2* F = S + d.o_fg;
   const int f = d.f, s = d.s;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int q = t; q < s * s; q += 256) {
+  for (int q = t; q < s * s; q += NT) {
     const int i = q / s, j = q % s;
     const double2 v = F[(int64_t)i * f + j];
     Mr[i][j] = v.x;
@@ -253,7 +139,7 @@ __global__ void __launch_bounds__(256) k_factor(Ctx c, const int32_t* cls) {
     double dr = 0.0, di = 0.0;
     if (den > 0.0) { dr = ar / den; di = -ai / den; }
     else singular = true;
-    for (int q = t; q < s * s; q += 256) {
+    for (int q = t; q < s * s; q += NT) {
       const int i = q / s, j = q % s;
       // row k scaled by d = 1 / a_kk
       const double rr = prr[j] * dr - pri[j] * di, ri = prr[j] * di + pri[j] * dr;
@@ -285,7 +171,7 @@ __global__ void __launch_bounds__(256) k_factor(Ctx c, const int32_t* cls) {
   }
   if (singular && t == 0) raise_fault(c.status, -4, c.e0 + e, cl);
   double2* Ainv = S + d.o_ainv;
-  for (int q = t; q < s * s; q += 256) {
+  for (int q = t; q < s * s; q += NT) {
     const int i = q / s, j = q % s;
     Ainv[q] = make_double2(Mr[i][j], Mi[i][j]);
   }
@@ -310,6 +196,7 @@ __global__ void __launch_bounds__(256) k_factor(Ctx c, const int32_t* cls) {
 }
 
 // Psi_{i,B_i} = -A_ii^{-1} A_{i,B_i}: one 64-column tile per block.
+template <int TM>
 __global__ void __launch_bounds__(256) k_psi(Ctx c, const ColItem* items) {
   __shared__ GemmSmem sm;
   const ColItem it = items[blockIdx.x];
@@ -323,10 +210,10 @@ __global__ void __launch_bounds__(256) k_psi(Ctx c, const ColItem* items) {
   const int nj = min(64, b - j0);
   ZTile acc;
   ztile_zero(acc);
-  zgemm_acc<false, false>(
+  zgemm_acc_t<TM, false, false>(
       s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
       [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm);
-  ztile_store(acc, [&](int i, int j, double re, double im) {
+  ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
     if (i < s && j < nj) Psi[(int64_t)i * b + j0 + j] = make_double2(-re, -im);
   });
 }
@@ -511,6 +398,7 @@ __global__ void __launch_bounds__(256) k_chain_back(Ctx c, const int32_t* cls) {
 // G_{i,B}^T (P_{B,i} = -P_{i,B}^+) and the gathered B x B block, which i's
 // children read.
 // ---------------------------------------------------------------------------
+template <int TM>
 __global__ void __launch_bounds__(256) k_down_off(Ctx c, const ColItem* items, int lesser) {
   __shared__ GemmSmem sm;
   const ColItem it = items[blockIdx.x];
@@ -535,11 +423,11 @@ __global__ void __launch_bounds__(256) k_down_off(Ctx c, const ColItem* items, i
   }
   ZTile acc;
   ztile_zero(acc);
-  zgemm_acc<false, false>(
+  zgemm_acc_t<TM, false, false>(
       b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
       [&](int k, int j) { return j < nj ? Xp[(int64_t)rel[k] * fp + rel[j0 + j]] : cz(); }, acc,
       sm);
-  ztile_store(acc, [&](int i, int j, double re, double im) {
+  ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
     if (i < s && j < nj) {
       double2 v = make_double2(re, im);
       const int64_t pos = (int64_t)i * f + s + j0 + j;
@@ -552,6 +440,7 @@ __global__ void __launch_bounds__(256) k_down_off(Ctx c, const ColItem* items, i
 
 //   G_ii = A_ii^{-1} + Psi_i G_{B,i},  G_{B,i} = G_{i,B}^T
 //   P_ii = P_init + Psi_i P_{B,i},     P_{B,i} = -P_{i,B}^+
+template <int TM>
 __global__ void __launch_bounds__(256) k_down_diag(Ctx c, const int32_t* cls, int lesser) {
   __shared__ GemmSmem sm;
   const int cl = cls[blockIdx.x];
@@ -566,7 +455,7 @@ __global__ void __launch_bounds__(256) k_down_diag(Ctx c, const int32_t* cls, in
   ZTile acc;
   ztile_zero(acc);
   if (lesser) {
-    zgemm_acc<false, true>(
+    zgemm_acc_t<TM, false, true>(
         b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
         [&](int k, int j) {
           if (j >= s) return cz();
@@ -575,11 +464,11 @@ __global__ void __launch_bounds__(256) k_down_diag(Ctx c, const int32_t* cls, in
         },
         acc, sm);
   } else {
-    zgemm_acc<false, true>(
+    zgemm_acc_t<TM, false, true>(
         b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
         [&](int k, int j) { return j < s ? X[(int64_t)j * f + s + k] : cz(); }, acc, sm);
   }
-  ztile_store(acc, [&](int i, int j, double re, double im) {
+  ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
     if (i < s && j < s) {
       double2 v = make_double2(re, im);
       const int64_t pos = (int64_t)i * f + j;
@@ -626,11 +515,17 @@ void launch_fill_zero(double* p, int64_t count, hipStream_t st) {
 void launch_assemble(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st) {
   if (ncl > 0) hipLaunchKernelGGL(k_assemble, dim3(ncl, nb), dim3(256), 0, st, c, cls);
 }
-void launch_factor(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st) {
-  if (ncl > 0) hipLaunchKernelGGL(k_factor, dim3(ncl, nb), dim3(256), 0, st, c, cls);
+void launch_factor(const Ctx& c, const int32_t* cls, int ncl, int nb, int cls_size, hipStream_t st) {
+  if (ncl <= 0) return;
+  if (cls_size <= 16) hipLaunchKernelGGL((k_factor<16, 64>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
+  else if (cls_size <= 32) hipLaunchKernelGGL((k_factor<32, 64>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
+  else hipLaunchKernelGGL((k_factor<64, 256>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
 }
-void launch_psi(const Ctx& c, const ColItem* it, int nit, int nb, hipStream_t st) {
-  if (nit > 0) hipLaunchKernelGGL(k_psi, dim3(nit, nb), dim3(256), 0, st, c, it);
+void launch_psi(const Ctx& c, const ColItem* it, int nit, int nb, int cls_size, hipStream_t st) {
+  if (nit <= 0) return;
+  if (cls_size <= 16) hipLaunchKernelGGL((k_psi<16>), dim3(nit, nb), dim3(256), 0, st, c, it);
+  else if (cls_size <= 32) hipLaunchKernelGGL((k_psi<32>), dim3(nit, nb), dim3(256), 0, st, c, it);
+  else hipLaunchKernelGGL((k_psi<64>), dim3(nit, nb), dim3(256), 0, st, c, it);
 }
 void launch_update(const Ctx& c, const UpdItem* it, int nit, int nb, hipStream_t st) {
   if (nit > 0) hipLaunchKernelGGL(k_update, dim3(nit, nb), dim3(256), 0, st, c, it);
@@ -638,11 +533,19 @@ void launch_update(const Ctx& c, const UpdItem* it, int nit, int nb, hipStream_t
 void launch_chain_fwd(const Ctx& c, const ChainItem* it, int nit, int nb, hipStream_t st) {
   if (nit > 0) hipLaunchKernelGGL(k_chain_fwd, dim3(nit, nb), dim3(256), 0, st, c, it);
 }
-void launch_down_off(const Ctx& c, const ColItem* it, int nit, int nb, bool lesser, hipStream_t st) {
-  if (nit > 0) hipLaunchKernelGGL(k_down_off, dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
+void launch_down_off(const Ctx& c, const ColItem* it, int nit, int nb, bool lesser, int cls_size,
+                     hipStream_t st) {
+  if (nit <= 0) return;
+  if (cls_size <= 16) hipLaunchKernelGGL((k_down_off<16>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
+  else if (cls_size <= 32) hipLaunchKernelGGL((k_down_off<32>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
+  else hipLaunchKernelGGL((k_down_off<64>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
 }
-void launch_down_diag(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, hipStream_t st) {
-  if (ncl > 0) hipLaunchKernelGGL(k_down_diag, dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
+void launch_down_diag(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, int cls_size,
+                      hipStream_t st) {
+  if (ncl <= 0) return;
+  if (cls_size <= 16) hipLaunchKernelGGL((k_down_diag<16>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
+  else if (cls_size <= 32) hipLaunchKernelGGL((k_down_diag<32>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
+  else hipLaunchKernelGGL((k_down_diag<64>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
 }
 void launch_chain_back(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st) {
   if (ncl > 0) hipLaunchKernelGGL(k_chain_back, dim3(ncl, nb), dim3(256), 0, st, c, cls);

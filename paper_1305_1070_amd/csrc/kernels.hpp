@@ -59,13 +59,21 @@ struct Ctx {
 
 // Launchers (kernels.hip).  nb = energies in the batch.
 void launch_assemble(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st);
-void launch_factor(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st);
-void launch_psi(const Ctx& c, const ColItem* it, int nit, int nb, hipStream_t st);
+// cls_size: the largest cluster size s of the launch (selects the tile shape)
+void launch_factor(const Ctx& c, const int32_t* cls, int ncl, int nb, int cls_size, hipStream_t st);
+void launch_psi(const Ctx& c, const ColItem* it, int nit, int nb, int cls_size, hipStream_t st);
 void launch_update(const Ctx& c, const UpdItem* it, int nit, int nb, hipStream_t st);
 void launch_chain_fwd(const Ctx& c, const ChainItem* it, int nit, int nb, hipStream_t st);
-void launch_down_off(const Ctx& c, const ColItem* it, int nit, int nb, bool lesser, hipStream_t st);
-void launch_down_diag(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, hipStream_t st);
+void launch_down_off(const Ctx& c, const ColItem* it, int nit, int nb, bool lesser, int cls_size,
+                     hipStream_t st);
+void launch_down_diag(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, int cls_size,
+                      hipStream_t st);
 void launch_chain_back(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st);
+// small fronts: f <= 32 (one wave per front) or f <= 64 (four waves)
+void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int front_size, hipStream_t st);
+void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, size_t lds_bytes,
+                          int front_size, hipStream_t st);
+constexpr int kSmallFront = 64;  // fronts up to this size are handled whole on chip
 void launch_fill_zero(double* p, int64_t count, hipStream_t st);
 void launch_epilogue(const Ctx& c, int nb, double2* dgr, double2* dgl, double2* dgg, hipStream_t st);
 

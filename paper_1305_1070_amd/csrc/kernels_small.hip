@@ -1,0 +1,298 @@
+// Small fronts (f = s + b <= 64) handled whole on chip, one block per
+// (energy, cluster).  Most clusters of a nested-dissection tree are small
+// (leaves and the separators just above them), and tiling their products
+// into 64 x 64 matrix-core tiles would mostly multiply padding.
+//
+// Fold: the front [[F_ii, F_iB], [F_Bi, F_BB]] is assembled in LDS and
+// reduced by s steps of Gauss-Jordan elimination with partial pivoting among
+// the rows of cluster i, applied to the whole front.  Stored in place, the
+// result is
+//     [[ F_ii^{-1},          F_ii^{-1} F_iB           ],
+//      [ -F_Bi F_ii^{-1},    F_BB - F_Bi F_ii^{-1} F_iB ]]
+// i.e. the pivot inverse, -Psi_{i,B}, Psi^T and the Schur contribution to the
+// parent front (Section 3.2, fold: Psi_ij = -A_ii^{-1} A_ij and
+// A_jk += Psi_ij^T A_ik for j, k in B_i) -- all in one pass.
+//
+// Extraction: G_{i,B} = Psi G_{B,B}, G_ii = A_ii^{-1} + Psi G_{B,i}, and the
+// same with P (G^<), with the gathered B x B blocks and Psi held in LDS.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace ndg {
+
+template <int SF, int NT>
+__global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
+  constexpr int SLD = SF + 1;  // padded row length in LDS
+  __shared__ double Fr[SF * SLD], Fi[SF * SLD];
+  __shared__ double prr[SF], pri[SF], pcr[SF], pci[SF];
+  __shared__ double rowb[SF];
+  __shared__ int piv[SF];
+  __shared__ int sp;
+  const int cl = cls[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[cl];
+  double2* S = slab(c, e);
+  const int f = d.f, s = d.s, b = d.b;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int j = t & 31; j < f; j += 32)
+    for (int i = t >> 5; i < f; i += NT / 32) {
+      Fr[i * SLD + j] = 0.0;
+      Fi[i * SLD + j] = 0.0;
+    }
+  __syncthreads();
+  // children's Schur contributions, one child at a time
+  for (int kp = c.kids_ptr[cl]; kp < c.kids_ptr[cl + 1]; ++kp) {
+    const ClusterDesc dc = c.cl[c.kids[kp]];
+    const int bc = dc.b;
+    const int32_t* rel = c.relmap + dc.bptr;
+    const double2* U = S + dc.o_upd;
+    for (int q = t; q < bc * bc; q += NT) {
+      const int r = q / bc, cc = q - r * bc;
+      const int pos = rel[r] * SLD + rel[cc];
+      const double2 u = U[q];
+      Fr[pos] += u.x;
+      Fi[pos] += u.y;
+    }
+    __syncthreads();
+  }
+  // rows of cluster i of -H, mirrored into the B rows
+  for (int p = d.hptr0 + t; p < d.hptr1; p += NT) {
+    const int r = c.hrow[p], fc = c.hcol[p];
+    const double hv = c.hval[p];
+    Fr[r * SLD + fc] -= hv;
+    if (fc >= s) Fr[fc * SLD + r] -= hv;
+  }
+  __syncthreads();
+  const double ez = c.E[c.e0 + e];
+  for (int r = t; r < s; r += NT) {
+    const double v = c.V ? c.V[c.perm[d.pt_off + r]] : 0.0;
+    Fr[r * SLD + r] += ez - v;
+    Fi[r * SLD + r] += c.eta;
+  }
+  __syncthreads();
+  if (d.contact >= 0) {
+    const int cc = d.contact, nc = c.nc[cc];
+    const double2* sg = c.sig_r[cc] + (int64_t)(c.e0 + e) * nc * nc;
+    const int32_t* loc = c.clocal[cc];
+    for (int q = t; q < nc * nc; q += NT) {
+      const int a = q / nc, bb = q - a * nc;
+      const double2 sv = sg[q];
+      Fr[loc[a] * SLD + loc[bb]] -= sv.x;
+      Fi[loc[a] * SLD + loc[bb]] -= sv.y;
+    }
+    __syncthreads();
+  }
+  if (c.growth && t < s) {
+    double rb = 0.0;
+    for (int j = s; j < f; ++j) rb += sqrt(Fr[t * SLD + j] * Fr[t * SLD + j] + Fi[t * SLD + j] * Fi[t * SLD + j]);
+    rowb[t] = rb;
+  }
+  bool singular = false;
+  for (int k = 0; k < s; ++k) {
+    if (w == 0) {
+      const int row = k + lane;
+      double mag = -1.0;
+      if (row < s) mag = fabs(Fr[row * SLD + k]) + fabs(Fi[row * SLD + k]);
+      int arg = row;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double om = __shfl_xor(mag, off);
+        const int oa = __shfl_xor(arg, off);
+        if (om > mag || (om == mag && oa < arg)) { mag = om; arg = oa; }
+      }
+      if (lane == 0) { sp = arg; piv[k] = arg; }
+    }
+    __syncthreads();
+    const int p = sp;
+    if (p != k && t < f) {
+      const double tr = Fr[k * SLD + t], ti = Fi[k * SLD + t];
+      Fr[k * SLD + t] = Fr[p * SLD + t];
+      Fi[k * SLD + t] = Fi[p * SLD + t];
+      Fr[p * SLD + t] = tr;
+      Fi[p * SLD + t] = ti;
+    }
+    __syncthreads();
+    if (t < f) {
+      prr[t] = Fr[k * SLD + t]; pri[t] = Fi[k * SLD + t];
+      pcr[t] = Fr[t * SLD + k]; pci[t] = Fi[t * SLD + k];
+    }
+    __syncthreads();
+    const double ar = prr[k], ai = pri[k];
+    const double den = ar * ar + ai * ai;
+    double dr = 0.0, di = 0.0;
+    if (den > 0.0) { dr = ar / den; di = -ai / den; }
+    else singular = true;
+    // rank-one update of the whole front: column j = lane mod 32 (+32),
+    // rows strided by NT / 32
+    for (int j = t & 31; j < f; j += 32) {
+      const double rr = prr[j] * dr - pri[j] * di, ri = prr[j] * di + pri[j] * dr;
+      for (int i = t >> 5; i < f; i += NT / 32) {
+        const int pos = i * SLD + j;
+        if (i == k) {
+          if (j == k) { Fr[pos] = dr; Fi[pos] = di; }
+          else { Fr[pos] = rr; Fi[pos] = ri; }
+        } else {
+          const double fr = pcr[i], fi = pci[i];
+          if (j == k) {
+            Fr[pos] = -(fr * dr - fi * di);
+            Fi[pos] = -(fr * di + fi * dr);
+          } else {
+            Fr[pos] -= fr * rr - fi * ri;
+            Fi[pos] -= fr * ri + fi * rr;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges on the eliminated columns, last one first
+  for (int k = s - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k && t < f) {
+      const double tr = Fr[t * SLD + k], ti = Fi[t * SLD + k];
+      Fr[t * SLD + k] = Fr[t * SLD + p];
+      Fi[t * SLD + k] = Fi[t * SLD + p];
+      Fr[t * SLD + p] = tr;
+      Fi[t * SLD + p] = ti;
+    }
+    __syncthreads();
+  }
+  if (singular && t == 0) raise_fault(c.status, -4, c.e0 + e, cl);
+  double2* Ainv = S + d.o_ainv;
+  double2* Psi = S + d.o_psi;
+  double2* Upd = S + d.o_upd;
+  for (int q = t; q < s * s; q += NT) {
+    const int i = q / s, j = q - i * s;
+    Ainv[q] = make_double2(Fr[i * SLD + j], Fi[i * SLD + j]);
+  }
+  for (int q = t; q < s * b; q += NT) {
+    const int i = q / b, j = q - i * b;
+    Psi[q] = make_double2(-Fr[i * SLD + s + j], -Fi[i * SLD + s + j]);
+  }
+  for (int q = t; q < b * b; q += NT) {
+    const int i = q / b, j = q - i * b;
+    Upd[q] = make_double2(Fr[(s + i) * SLD + s + j], Fi[(s + i) * SLD + s + j]);
+  }
+  if (c.growth && w == 0 && b > 0) {
+    double ru = 0.0, rb = 0.0;
+    if (lane < s) {
+      for (int j = 0; j < s; ++j)
+        ru += sqrt(Fr[lane * SLD + j] * Fr[lane * SLD + j] + Fi[lane * SLD + j] * Fi[lane * SLD + j]);
+      rb = rowb[lane];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      ru = fmax(ru, __shfl_xor(ru, off));
+      rb = fmax(rb, __shfl_xor(rb, off));
+    }
+    if (lane == 0)
+      atomicMax(reinterpret_cast<unsigned long long*>(c.growth + c.e0 + e),
+                (unsigned long long)__double_as_longlong(ru * rb));
+  }
+}
+
+// Extraction of G^r and then G^< for one small front.  Dynamic LDS holds
+// Psi (s x b), the gathered B x B block of the parent's front and X_{i,B}.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls) {
+  extern __shared__ double2 sm[];
+  const int cl = cls[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[cl];
+  double2* S = slab(c, e);
+  const int f = d.f, s = d.s, b = d.b;
+  const int t = threadIdx.x;
+  const bool inner = c.kids_ptr[cl + 1] > c.kids_ptr[cl];
+  const bool chain = d.chain_mask != 0;
+  const double2* Ainv = S + d.o_ainv;
+  double2* Psl = sm;              // s x b
+  double2* XBB = sm + s * b;      // b x b
+  double2* XIB = XBB + b * b;     // s x b
+  const double2* Psi = S + d.o_psi;
+  for (int q = t; q < s * b; q += NT) Psl[q] = Psi[q];
+  const int32_t* rel = c.relmap + d.bptr;
+  for (int lesser = 0; lesser < 2; ++lesser) {
+    double2* X = S + (lesser ? d.o_fp : d.o_fg);
+    const bool src = lesser && chain;
+    if (b > 0) {
+      const ClusterDesc dp = c.cl[d.parent];
+      const double2* Xp = S + (lesser ? dp.o_fp : dp.o_fg);
+      const int fp = dp.f;
+      for (int q = t; q < b * b; q += NT) {
+        const int k = q / b, j = q - k * b;
+        XBB[q] = Xp[(int64_t)rel[k] * fp + rel[j]];
+      }
+    }
+    __syncthreads();
+    // X_{i,B} = P_init + Psi X_{B,B}
+    for (int q = t; q < s * b; q += NT) {
+      const int r = q / b, j = q - r * b;
+      double2 acc = src ? X[(int64_t)r * f + s + j] : cz();
+      for (int k = 0; k < b; ++k) {
+        const double2 a = Psl[r * b + k], x = XBB[k * b + j];
+        acc.x += a.x * x.x - a.y * x.y;
+        acc.y += a.x * x.y + a.y * x.x;
+      }
+      XIB[q] = acc;
+    }
+    __syncthreads();
+    // X_ii = (A_ii^{-1} | P_init) + Psi X_{B,i}
+    for (int q = t; q < s * s; q += NT) {
+      const int r = q / s, j = q - r * s;
+      double2 acc;
+      if (lesser) acc = src ? X[(int64_t)r * f + j] : cz();
+      else acc = Ainv[q];
+      for (int k = 0; k < b; ++k) {
+        const double2 a = Psl[r * b + k];
+        double2 x = XIB[j * b + k];  // X_{B,i}[k][j] from X_{i,B}[j][k]
+        if (lesser) x = make_double2(-x.x, x.y);
+        acc.x += a.x * x.x - a.y * x.y;
+        acc.y += a.x * x.y + a.y * x.x;
+      }
+      X[(int64_t)r * f + j] = acc;
+    }
+    for (int q = t; q < s * b; q += NT) {
+      const int r = q / b, j = q - r * b;
+      const double2 v = XIB[q];
+      X[(int64_t)r * f + s + j] = v;
+      if (inner) X[(int64_t)(s + j) * f + r] = lesser ? make_double2(-v.x, v.y) : v;
+    }
+    if (inner)
+      for (int q = t; q < b * b; q += NT) {
+        const int k = q / b, j = q - k * b;
+        X[(int64_t)(s + k) * f + s + j] = XBB[q];
+      }
+    __syncthreads();
+  }
+}
+
+void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int front_size, hipStream_t st) {
+  if (ncl <= 0) return;
+  if (front_size <= 32) hipLaunchKernelGGL((k_fold_small<32, 64>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
+  else if (front_size <= 48) hipLaunchKernelGGL((k_fold_small<48, 128>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
+  else hipLaunchKernelGGL((k_fold_small<64, 256>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+}
+
+void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, size_t lds_bytes,
+                          int front_size, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    // the gathered B x B block can exceed 64 KB; gfx950 gives a block up to 160 KB
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_extract_small<256>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_extract_small<128>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  if (ncl <= 0) return;
+  if (front_size <= 32)
+    hipLaunchKernelGGL((k_extract_small<64>), dim3(ncl, nb), dim3(64), lds_bytes, st, c, cls);
+  else if (front_size <= 48)
+    hipLaunchKernelGGL((k_extract_small<128>), dim3(ncl, nb), dim3(128), lds_bytes, st, c, cls);
+  else
+    hipLaunchKernelGGL((k_extract_small<256>), dim3(ncl, nb), dim3(256), lds_bytes, st, c, cls);
+}
+
+}  // namespace ndg

@@ -48,6 +48,12 @@ struct ndg_plan {
   ndg::ChainItem* d_chainitems = nullptr;
   int32_t* d_chaincls = nullptr;
   std::vector<int> lvl_ptr, col_ptr, upd_ptr, chain_ptr, chaincl_ptr;  // per height (1-based)
+  // per height, the clusters split into size classes: fronts f <= 32, f <= 64
+  // (whole on chip), then larger fronts with s <= 16, s <= 32, s <= 64
+  // (separate kernels, tile height following s)
+  struct Group { int cl0 = 0, ncl = 0, col0 = 0, ncol = 0, upd0 = 0, nupd = 0, size = 0; size_t lds = 0; };
+  static constexpr int kClasses = 6;
+  std::vector<Group> groups;  // [(H + 1) * kClasses]
   double2* d_ws = nullptr;
   int32_t* d_status = nullptr;
   int last_batch = 0;
@@ -66,11 +72,12 @@ namespace {
 
 enum KernelId {
   K_ASSEMBLE, K_FACTOR, K_PSI, K_UPDATE, K_CHAIN_FWD, K_DOWN_OFF_G, K_DOWN_DIAG_G, K_CHAIN_BACK,
-  K_DOWN_OFF_P, K_DOWN_DIAG_P, K_EPILOGUE, kKernels
+  K_DOWN_OFF_P, K_DOWN_DIAG_P, K_EPILOGUE, K_FOLD_SMALL, K_EXTRACT_SMALL, kKernels
 };
 const char* const kKernelNames[kKernels] = {
     "k_assemble", "k_factor", "k_psi", "k_update", "k_chain_fwd", "k_down_off(G)",
-    "k_down_diag(G)", "k_chain_back", "k_down_off(P)", "k_down_diag(P)", "k_epilogue"};
+    "k_down_diag(G)", "k_chain_back", "k_down_off(P)", "k_down_diag(P)", "k_epilogue",
+    "k_fold_small", "k_extract_small"};
 
 int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
@@ -192,21 +199,48 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   p->upd_ptr.assign(H + 1, 0);
   p->chain_ptr.assign(H + 1, 0);
   p->chaincl_ptr.assign(H + 1, 0);
+  p->groups.assign((H + 1) * ndg_plan::kClasses, ndg_plan::Group{});
+  auto class_of = [&](int k) {
+    const int s_ = sy.s(k), f = s_ + sy.b(k);
+    if (f <= 32) return 0;
+    if (f <= 48) return 1;
+    if (f <= kSmallFront) return 2;
+    return s_ <= 16 ? 3 : s_ <= 32 ? 4 : 5;
+  };
   for (int h = 1; h <= H; ++h) {
-    for (int q = sy.level_ptr[h - 1]; q < sy.level_ptr[h]; ++q) {
-      const int k = sy.level_order[q];
-      levels.push_back(k);
-      const int b = sy.b(k);
-      const int nt = (b + 63) / 64;
-      for (int tc = 0; tc < nt; ++tc) cols.push_back(ColItem{k, tc});
-      for (int tr = 0; tr < nt; ++tr)
-        for (int tc = 0; tc < nt; ++tc) upds.push_back(UpdItem{k, tr, tc, 0});
+    std::vector<int32_t> lv(sy.level_order.begin() + sy.level_ptr[h - 1],
+                            sy.level_order.begin() + sy.level_ptr[h]);
+    std::stable_sort(lv.begin(), lv.end(), [&](int32_t a, int32_t b) { return class_of(a) < class_of(b); });
+    for (int q = 0; q < ndg_plan::kClasses; ++q) {
+      ndg_plan::Group& g = p->groups[h * ndg_plan::kClasses + q];
+      g.cl0 = (int)levels.size();
+      g.col0 = (int)cols.size();
+      g.upd0 = (int)upds.size();
+      for (int32_t k : lv) {
+        if (class_of(k) != q) continue;
+        const int s_ = sy.s(k), b = sy.b(k);
+        levels.push_back(k);
+        g.ncl++;
+        if (q <= 2) {
+          g.size = std::max(g.size, s_ + b);
+          g.lds = std::max(g.lds, (size_t)(2 * s_ * b + b * b) * 16);
+        } else {
+          g.size = std::max(g.size, s_);
+          const int nt = (b + 63) / 64;
+          for (int tc = 0; tc < nt; ++tc) cols.push_back(ColItem{k, tc});
+          for (int tr = 0; tr < nt; ++tr)
+            for (int tc = 0; tc < nt; ++tc) upds.push_back(UpdItem{k, tr, tc, 0});
+        }
+      }
+      g.ncol = (int)cols.size() - g.col0;
+      g.nupd = (int)upds.size() - g.upd0;
+    }
+    for (int32_t k : lv)
       if (p->hdesc[k].chain_mask) {
         chaincls.push_back(k);
         for (int c = 0; c < p->ncontacts; ++c)
           if ((p->hdesc[k].chain_mask >> c) & 1) chains.push_back(ChainItem{k, c});
       }
-    }
     p->lvl_ptr[h] = (int)levels.size();
     p->col_ptr[h] = (int)cols.size();
     p->upd_ptr[h] = (int)upds.size();
@@ -227,13 +261,20 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
     const bool inner = !sy.children[k].empty();
     double kidb = 0;
     for (int32_t ch : sy.children[k]) kidb += (double)sy.b(ch) * sy.b(ch);
-    addc(K_ASSEMBLE, h, 0.0, 16.0 * (f * f + kidb));
-    addc(K_FACTOR, h, 8.0 * s * s * s, 16.0 * 2 * s * s);
-    addc(K_PSI, h, 8.0 * s * s * b, 16.0 * (s * s + 2 * s * b));
-    addc(K_UPDATE, h, 8.0 * s * b * b, 16.0 * (2 * s * b + 2 * b * b));
-    for (int q : {K_DOWN_OFF_G, K_DOWN_OFF_P})
-      addc(q, h, 8.0 * s * b * b, 16.0 * (s * b + b * b + s * b + (inner ? s * b + b * b : 0.0)));
-    for (int q : {K_DOWN_DIAG_G, K_DOWN_DIAG_P}) addc(q, h, 8.0 * s * s * b, 16.0 * (2 * s * b + 2 * s * s));
+    if (s + b <= kSmallFront) {
+      // whole-front elimination: s steps over the f x f front
+      addc(K_FOLD_SMALL, h, 8.0 * s * f * f, 16.0 * (kidb + s * s + s * b + b * b));
+      addc(K_EXTRACT_SMALL, h, 2 * 8.0 * (s * b * b + s * s * b),
+           2 * 16.0 * (b * b + s * s + s * b + (inner ? s * b + b * b : 0.0)) + 16.0 * (s * b + s * s));
+    } else {
+      addc(K_ASSEMBLE, h, 0.0, 16.0 * (f * f + kidb));
+      addc(K_FACTOR, h, 8.0 * s * s * s, 16.0 * 2 * s * s);
+      addc(K_PSI, h, 8.0 * s * s * b, 16.0 * (s * s + 2 * s * b));
+      addc(K_UPDATE, h, 8.0 * s * b * b, 16.0 * (2 * s * b + 2 * b * b));
+      for (int q : {K_DOWN_OFF_G, K_DOWN_OFF_P})
+        addc(q, h, 8.0 * s * b * b, 16.0 * (s * b + b * b + s * b + (inner ? s * b + b * b : 0.0)));
+      for (int q : {K_DOWN_DIAG_G, K_DOWN_DIAG_P}) addc(q, h, 8.0 * s * s * b, 16.0 * (2 * s * b + 2 * s * s));
+    }
     for (int c = 0; c < p->ncontacts; ++c) {
       if (!((p->hdesc[k].chain_mask >> c) & 1)) continue;
       const double sc = p->nc[c];
@@ -378,28 +419,41 @@ int plan_solve(ndg_plan* p, int nE, const double* E, double eta, const double* V
     const int nb = std::min(p->max_batch, nE - e0);
     c.e0 = e0;
     for (int h = 1; h <= H; ++h) {
-      const int l0 = p->lvl_ptr[h - 1], nl = p->lvl_ptr[h] - l0;
-      const ColItem* ci = p->d_colitems + p->col_ptr[h - 1];
-      const int ncol = p->col_ptr[h] - p->col_ptr[h - 1];
-      const UpdItem* ui = p->d_upditems + p->upd_ptr[h - 1];
-      const int nupd = p->upd_ptr[h] - p->upd_ptr[h - 1];
       const ChainItem* chi = p->d_chainitems + p->chain_ptr[h - 1];
       const int nch = p->chain_ptr[h] - p->chain_ptr[h - 1];
-      timed(K_ASSEMBLE, h, nb, [&] { launch_assemble(c, p->d_levels + l0, nl, nb, st); });
-      timed(K_FACTOR, h, nb, [&] { launch_factor(c, p->d_levels + l0, nl, nb, st); });
-      if (ncol) timed(K_PSI, h, nb, [&] { launch_psi(c, ci, ncol, nb, st); });
-      if (nupd) timed(K_UPDATE, h, nb, [&] { launch_update(c, ui, nupd, nb, st); });
+      for (int q = 0; q < ndg_plan::kClasses; ++q) {
+        const ndg_plan::Group& g = p->groups[h * ndg_plan::kClasses + q];
+        if (!g.ncl) continue;
+        const int32_t* cl = p->d_levels + g.cl0;
+        if (q <= 2) {
+          timed(K_FOLD_SMALL, h, nb, [&] { launch_fold_small(c, cl, g.ncl, nb, g.size, st); });
+          continue;
+        }
+        timed(K_ASSEMBLE, h, nb, [&] { launch_assemble(c, cl, g.ncl, nb, st); });
+        timed(K_FACTOR, h, nb, [&] { launch_factor(c, cl, g.ncl, nb, g.size, st); });
+        if (g.ncol) timed(K_PSI, h, nb, [&] { launch_psi(c, p->d_colitems + g.col0, g.ncol, nb, g.size, st); });
+        if (g.nupd) timed(K_UPDATE, h, nb, [&] { launch_update(c, p->d_upditems + g.upd0, g.nupd, nb, st); });
+      }
       if (nch) timed(K_CHAIN_FWD, h, nb, [&] { launch_chain_fwd(c, chi, nch, nb, st); });
     }
     for (int h = H; h >= 1; --h) {
-      const int l0 = p->lvl_ptr[h - 1], nl = p->lvl_ptr[h] - l0;
-      const int c0 = p->col_ptr[h - 1], ncol = p->col_ptr[h] - c0;
       const int k0 = p->chaincl_ptr[h - 1], nck = p->chaincl_ptr[h] - k0;
-      if (ncol) timed(K_DOWN_OFF_G, h, nb, [&] { launch_down_off(c, p->d_colitems + c0, ncol, nb, false, st); });
-      timed(K_DOWN_DIAG_G, h, nb, [&] { launch_down_diag(c, p->d_levels + l0, nl, nb, false, st); });
+      // the G^< source on chain clusters first: the extraction of P reads it
       if (nck) timed(K_CHAIN_BACK, h, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, st); });
-      if (ncol) timed(K_DOWN_OFF_P, h, nb, [&] { launch_down_off(c, p->d_colitems + c0, ncol, nb, true, st); });
-      timed(K_DOWN_DIAG_P, h, nb, [&] { launch_down_diag(c, p->d_levels + l0, nl, nb, true, st); });
+      for (int q = 0; q < ndg_plan::kClasses; ++q) {
+        const ndg_plan::Group& g = p->groups[h * ndg_plan::kClasses + q];
+        if (!g.ncl) continue;
+        const int32_t* cl = p->d_levels + g.cl0;
+        if (q <= 2) {
+          timed(K_EXTRACT_SMALL, h, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, st); });
+          continue;
+        }
+        const ColItem* ci = p->d_colitems + g.col0;
+        if (g.ncol) timed(K_DOWN_OFF_G, h, nb, [&] { launch_down_off(c, ci, g.ncol, nb, false, g.size, st); });
+        timed(K_DOWN_DIAG_G, h, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, false, g.size, st); });
+        if (g.ncol) timed(K_DOWN_OFF_P, h, nb, [&] { launch_down_off(c, ci, g.ncol, nb, true, g.size, st); });
+        timed(K_DOWN_DIAG_P, h, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, true, g.size, st); });
+      }
     }
     timed(K_EPILOGUE, 0, nb, [&] {
       launch_epilogue(c, nb, reinterpret_cast<double2*>(dgr), reinterpret_cast<double2*>(dgl),
