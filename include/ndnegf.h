@@ -176,6 +176,37 @@ ndg_status ndg_solve(ndg_plan* plan, int32_t nE, const double* E, double eta, co
                      ndg_c128* diag_gr, ndg_c128* diag_gless, ndg_c128* diag_ggreater,
                      double* growth, ndg_precision prec, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Electron density and its gradient with respect to the on-site potential.
+ *
+ * ndg_density: density[i] = sum_E cE[E] (-i G^<_ii(E)), the G^< of ndg_solve
+ * (Section 1: the diagonal of G^< is the electron density per unit energy),
+ * accumulated over the energies in order (deterministic).
+ *   cE[nE]      device, quadrature weights (e.g. trapezoid dE / 2 pi)
+ *   density[n]  device output in the caller's site order (overwritten)
+ *
+ * ndg_density_vjp: vbar = (d density / d V)^T nbar, the vector-Jacobian
+ * product for a Newton step of the Schroedinger-Poisson loop.  With
+ * A = zI - H - diag(V) - Sigma and Lambda = diag(nbar),
+ *   vbar_k = sum_E cE[E] 2 Im[(G^< Lambda G^r)_kk],
+ * evaluated (without phonon self-energies) as
+ *   sum_c G_{k,c} Sigma^<_c X_c(k,:)^T,  X_c = A^{-1} Lambda conj(G_{:,c}),
+ * with G_{:,c} and X_c obtained by solves with the fold's factors, which are
+ * recomputed (not stored from a forward pass).  Needs
+ * ndg_plan_enable_adjoint once per plan (allocates its workspace).
+ *   nbar[n]     device, cotangent of density (caller order)
+ *   vbar[n]     device output (caller order, overwritten)
+ * Errors: as ndg_solve; NDG_EINVAL if the adjoint was not enabled.
+ */
+ndg_status ndg_density(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
+                       const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
+                       const double* cE, double* density, ndg_precision prec, void* stream);
+ndg_status ndg_plan_enable_adjoint(ndg_plan* plan);
+ndg_status ndg_density_vjp(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
+                           const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
+                           const double* cE, const double* nbar, double* vbar, ndg_precision prec,
+                           void* stream);
+
 /* Status word of the last solves on this plan (call after synchronising the
  * stream).  *code = NDG_OK, NDG_ESINGULAR (a pivot of magnitude 0 in a
  * cluster inverse) or NDG_ENONFINITE; *energy and *cluster identify the first

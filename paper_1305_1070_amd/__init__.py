@@ -21,6 +21,7 @@ __all__ = ["analyze", "Symbolic", "Plan", "load", "NdgError", "NDG_FP64", "NDG_M
            "ndg_analyze", "ndg_symbolic_info", "ndg_symbolic_arrays", "ndg_plan_create",
            "ndg_plan_destroy", "ndg_plan_info", "ndg_solve", "ndg_plan_status",
            "ndg_plan_export_block", "ndg_plan_set_profiling", "ndg_plan_profile",
+           "ndg_density", "ndg_plan_enable_adjoint", "ndg_density_vjp", "NDDensity",
            "ndg_status_string", "ndg_last_error"]
 
 
@@ -96,6 +97,28 @@ def ndg_solve(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, dgr_ptr, d
     sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
     _lib.check(load().ndg_solve(plan, ne, e_ptr, eta, v_ptr, sr, sl, dgr_ptr, dgl_ptr, dgg_ptr,
                                 growth_ptr, prec, stream_ptr))
+
+
+def ndg_density(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, ce_ptr, dens_ptr, prec,
+                stream_ptr):
+    nc = len(sig_r_ptrs)
+    sr = (C.c_void_p * max(1, nc))(*sig_r_ptrs)
+    sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
+    _lib.check(load().ndg_density(plan, ne, e_ptr, eta, v_ptr, sr, sl, ce_ptr, dens_ptr, prec,
+                                  stream_ptr))
+
+
+def ndg_plan_enable_adjoint(plan):
+    _lib.check(load().ndg_plan_enable_adjoint(plan))
+
+
+def ndg_density_vjp(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, ce_ptr, nbar_ptr,
+                    vbar_ptr, prec, stream_ptr):
+    nc = len(sig_r_ptrs)
+    sr = (C.c_void_p * max(1, nc))(*sig_r_ptrs)
+    sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
+    _lib.check(load().ndg_density_vjp(plan, ne, e_ptr, eta, v_ptr, sr, sl, ce_ptr, nbar_ptr,
+                                      vbar_ptr, prec, stream_ptr))
 
 
 def ndg_plan_status(plan):
@@ -211,6 +234,60 @@ class Plan:
                   prec, C.c_void_p(st.cuda_stream))
         return gr, gl, gg
 
+    def _check_inputs(self, E, sig_r, sig_less, V):
+        import torch
+        n = self._info["n"]
+        ne = int(E.shape[0])
+        dev = E.device
+        if dev.type != "cuda":
+            raise ValueError("inputs must be GPU tensors")
+        if E.dtype != torch.float64 or not E.is_contiguous():
+            raise ValueError("E must be a contiguous float64 tensor")
+        for t in list(sig_r) + list(sig_less) + ([V] if V is not None else []):
+            if t.device != dev or not t.is_contiguous():
+                raise ValueError("all inputs must be contiguous tensors on the plan's device")
+        for k, (a, b) in enumerate(zip(sig_r, sig_less)):
+            ncs = self.sym.contact_sizes[k]
+            for t in (a, b):
+                if t.dtype != torch.complex128 or tuple(t.shape) != (ne, ncs, ncs):
+                    raise ValueError("contact %d self-energy must be complex128 [nE, %d, %d]"
+                                     % (k, ncs, ncs))
+        if V is not None and (V.dtype != torch.float64 or V.numel() != n):
+            raise ValueError("V must be float64 [n]")
+        return n, ne, dev
+
+    def density(self, E, eta, sig_r, sig_less, cE, V=None, out=None, prec=NDG_FP64, stream=None):
+        """n_i = sum_E cE (-i G^<_ii); float64 [n] on the GPU."""
+        import torch
+        n, ne, dev = self._check_inputs(E, sig_r, sig_less, V)
+        if cE.dtype != torch.float64 or cE.numel() != ne or cE.device != dev:
+            raise ValueError("cE must be float64 [nE] on the plan's device")
+        out = torch.empty(n, dtype=torch.float64, device=dev) if out is None else out
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        ndg_density(self.handle, ne, E.data_ptr(), float(eta), V.data_ptr() if V is not None else None,
+                    [t.data_ptr() for t in sig_r], [t.data_ptr() for t in sig_less],
+                    cE.data_ptr(), out.data_ptr(), prec, C.c_void_p(st.cuda_stream))
+        return out
+
+    def enable_adjoint(self):
+        ndg_plan_enable_adjoint(self.handle)
+
+    def density_vjp(self, E, eta, sig_r, sig_less, cE, nbar, V=None, out=None, prec=NDG_FP64,
+                    stream=None):
+        """(d n / d V)^T nbar; float64 [n] on the GPU."""
+        import torch
+        n, ne, dev = self._check_inputs(E, sig_r, sig_less, V)
+        if nbar.dtype != torch.float64 or nbar.numel() != n or not nbar.is_contiguous():
+            raise ValueError("nbar must be a contiguous float64 [n] tensor")
+        out = torch.empty(n, dtype=torch.float64, device=dev) if out is None else out
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        ndg_density_vjp(self.handle, ne, E.data_ptr(), float(eta),
+                        V.data_ptr() if V is not None else None,
+                        [t.data_ptr() for t in sig_r], [t.data_ptr() for t in sig_less],
+                        cE.data_ptr(), nbar.data_ptr(), out.data_ptr(), prec,
+                        C.c_void_p(st.cuda_stream))
+        return out
+
     def status(self):
         return ndg_plan_status(self.handle)
 
@@ -228,3 +305,43 @@ class Plan:
         if getattr(self, "handle", None) and _lib._lib is not None:
             _lib._lib.ndg_plan_destroy(self.handle)
             self.handle = None
+
+
+def _autograd_function():
+    import torch
+
+    class NDDensity(torch.autograd.Function):
+        """density = NDDensity.apply(V, plan, E, eta, sig_r, sig_less, cE).
+
+        Forward: n_i(V) = sum_E cE (-i G^<_ii) by the library's fold and
+        extraction.  Backward: the library's adjoint (ndg_density_vjp) gives
+        Vbar = J^T nbar.  sig_r / sig_less are tuples of tensors treated as
+        constants."""
+
+        @staticmethod
+        def forward(ctx, V, plan, E, eta, sig_r, sig_less, cE):
+            ctx.plan, ctx.eta = plan, eta
+            ctx.sig_r, ctx.sig_less = tuple(sig_r), tuple(sig_less)
+            ctx.save_for_backward(V, E, cE)
+            return plan.density(E, eta, sig_r, sig_less, cE, V=V.contiguous())
+
+        @staticmethod
+        def backward(ctx, nbar):
+            V, E, cE = ctx.saved_tensors
+            vbar = ctx.plan.density_vjp(E, ctx.eta, ctx.sig_r, ctx.sig_less, cE,
+                                        nbar.contiguous().to(torch.float64), V=V.contiguous())
+            return vbar, None, None, None, None, None, None
+
+    return NDDensity
+
+
+class _LazyFunction:
+    _fn = None
+
+    def apply(self, *args):
+        if _LazyFunction._fn is None:
+            _LazyFunction._fn = _autograd_function()
+        return _LazyFunction._fn.apply(*args)
+
+
+NDDensity = _LazyFunction()

@@ -69,6 +69,11 @@ SIGNATURES = {
                             P, C.c_int, P]),
     "ndg_plan_status": (C.c_int, [P, I32P, I32P, I32P]),
     "ndg_plan_export_block": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, P]),
+    "ndg_density": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P), P, P,
+                              C.c_int, P]),
+    "ndg_plan_enable_adjoint": (C.c_int, [P]),
+    "ndg_density_vjp": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P), P,
+                                  P, P, C.c_int, P]),
     "ndg_plan_set_profiling": (C.c_int, [P, C.c_int32]),
     "ndg_plan_profile": (C.c_int, [P, C.c_int32, C.POINTER(KernelStat), C.POINTER(C.c_int32)]),
     "ndg_status_string": (C.c_char_p, [C.c_int32]),

@@ -147,6 +147,43 @@ ndg_status ndg_solve(ndg_plan* plan, int32_t nE, const double* E, double eta, co
                                      diag_ggreater, growth, (int)prec, stream);
 }
 
+static ndg_status check_common(const char* who, ndg_plan* plan, int32_t nE, const double* E, double eta,
+                               ndg_precision prec) {
+  if (!plan) { set_error(std::string(who) + ": NULL plan"); return NDG_EINVAL; }
+  if (nE < 0 || !(eta >= 0)) { set_error(std::string(who) + ": nE < 0 or eta < 0"); return NDG_EINVAL; }
+  if (nE > 0 && !E) { set_error(std::string(who) + ": NULL energies"); return NDG_EINVAL; }
+  if (prec != NDG_FP64 && prec != NDG_MIXED) { set_error(std::string(who) + ": unknown precision"); return NDG_EINVAL; }
+  return NDG_OK;
+}
+
+ndg_status ndg_density(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
+                       const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
+                       const double* cE, double* density, ndg_precision prec, void* stream) {
+  ndg_status st = check_common("ndg_density", plan, nE, E, eta, prec);
+  if (st != NDG_OK) return st;
+  if (!cE || !density) { set_error("ndg_density: NULL weights or output"); return NDG_EINVAL; }
+  return (ndg_status)ndg::plan_run(plan, ndg::kRunDensity, nE, E, eta, V, sig_r, sig_less, nullptr,
+                                   nullptr, nullptr, nullptr, cE, density, nullptr, nullptr,
+                                   (int)prec, stream);
+}
+
+ndg_status ndg_plan_enable_adjoint(ndg_plan* plan) {
+  if (!plan) { set_error("ndg_plan_enable_adjoint: NULL plan"); return NDG_EINVAL; }
+  return (ndg_status)ndg::plan_enable_adjoint(plan);
+}
+
+ndg_status ndg_density_vjp(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
+                           const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
+                           const double* cE, const double* nbar, double* vbar, ndg_precision prec,
+                           void* stream) {
+  ndg_status st = check_common("ndg_density_vjp", plan, nE, E, eta, prec);
+  if (st != NDG_OK) return st;
+  if (!cE || !nbar || !vbar) { set_error("ndg_density_vjp: NULL weights, cotangent or output"); return NDG_EINVAL; }
+  return (ndg_status)ndg::plan_run(plan, ndg::kRunVjp, nE, E, eta, V, sig_r, sig_less, nullptr,
+                                   nullptr, nullptr, nullptr, cE, nullptr, nbar, vbar, (int)prec,
+                                   stream);
+}
+
 ndg_status ndg_plan_status(ndg_plan* plan, int32_t* code, int32_t* energy, int32_t* cluster) {
   if (!plan || !code || !energy || !cluster) { set_error("ndg_plan_status: NULL argument"); return NDG_EINVAL; }
   return (ndg_status)ndg::plan_status(plan, code, energy, cluster);

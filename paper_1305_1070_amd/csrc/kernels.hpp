@@ -57,6 +57,21 @@ struct Ctx {
   double* growth;            // [nE] or null: max over clusters of ||A_ii^{-1}|| ||A_iB||
 };
 
+// Multi-right-hand-side solves with the factors of the fold (adjoint).
+struct RhsCtx {
+  double2* Y;         // [nb][n][m] right-hand sides, internal row order
+  double2* X;         // [nb][n][m] solutions
+  double2* Gc;        // [nb][n][m] contact columns of G^r
+  double2* Z;         // [nb][zstride] per-cluster front vectors (f x m)
+  const int64_t* o_vec;  // per-cluster offset into a Z slab
+  int64_t zstride;
+  int32_t n, m;
+  const int32_t* bidx;   // B_i as internal positions
+  const double* nbar;    // cotangent of the density (caller order)
+  double* part;          // [nb][n] per-energy partial gradients
+  int32_t contact_cluster[2];
+};
+
 // Launchers (kernels.hip).  nb = energies in the batch.
 void launch_assemble(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st);
 // cls_size: the largest cluster size s of the launch (selects the tile shape)
@@ -75,6 +90,14 @@ void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, siz
                           int front_size, hipStream_t st);
 constexpr int kSmallFront = 64;  // fronts up to this size are handled whole on chip
 void launch_fill_zero(double* p, int64_t count, hipStream_t st);
+void launch_rhs_contact(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st);
+void launch_rhs_lambda(const Ctx& c, const RhsCtx& r, int nb, hipStream_t st);
+void launch_rhs_fwd(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, hipStream_t st);
+void launch_rhs_back(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, hipStream_t st);
+void launch_vjp_accum(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st);
+void launch_zero(double* p, int64_t count, hipStream_t st);
+void launch_vjp_reduce(const Ctx& c, const RhsCtx& r, int nb, const double* cE, double* vbar, hipStream_t st);
+void launch_density(const Ctx& c, int nb, const double* cE, double* dens, hipStream_t st);
 void launch_epilogue(const Ctx& c, int nb, double2* dgr, double2* dgl, double2* dgg, hipStream_t st);
 
 }  // namespace ndg

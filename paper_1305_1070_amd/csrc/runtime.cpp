@@ -34,6 +34,7 @@ struct ndg_plan {
   ndg::OpCounts ops;
   ndg_info info{};
   std::vector<ndg::ClusterDesc> hdesc;
+  std::vector<int32_t> hbidx;
   std::vector<int32_t> hdeg;   // children count (host)
   // device arrays
   ndg::ClusterDesc* d_cl = nullptr;
@@ -56,6 +57,15 @@ struct ndg_plan {
   std::vector<Group> groups;  // [(H + 1) * kClasses]
   double2* d_ws = nullptr;
   int32_t* d_status = nullptr;
+  // adjoint workspace (ndg_plan_enable_adjoint): right-hand sides Y, solutions
+  // X, contact columns of G, per-cluster front vectors, per-energy partials
+  double2 *d_rY = nullptr, *d_rX = nullptr, *d_rG = nullptr, *d_rZ = nullptr;
+  int64_t* d_ovec = nullptr;
+  int32_t* d_bidx = nullptr;
+  double* d_part = nullptr;
+  int64_t zstride = 0;
+  int mmax = 0;
+  int contact_cl[2] = {-1, -1};
   int last_batch = 0;
   // algorithmic cost per energy of each kernel class at each height
   std::vector<double> cost_flops, cost_bytes;  // [kKernels * (H + 1)]
@@ -72,12 +82,13 @@ namespace {
 
 enum KernelId {
   K_ASSEMBLE, K_FACTOR, K_PSI, K_UPDATE, K_CHAIN_FWD, K_DOWN_OFF_G, K_DOWN_DIAG_G, K_CHAIN_BACK,
-  K_DOWN_OFF_P, K_DOWN_DIAG_P, K_EPILOGUE, K_FOLD_SMALL, K_EXTRACT_SMALL, kKernels
+  K_DOWN_OFF_P, K_DOWN_DIAG_P, K_EPILOGUE, K_FOLD_SMALL, K_EXTRACT_SMALL, K_RHS_FWD, K_RHS_BACK,
+  K_VJP, kKernels
 };
 const char* const kKernelNames[kKernels] = {
     "k_assemble", "k_factor", "k_psi", "k_update", "k_chain_fwd", "k_down_off(G)",
     "k_down_diag(G)", "k_chain_back", "k_down_off(P)", "k_down_diag(P)", "k_epilogue",
-    "k_fold_small", "k_extract_small"};
+    "k_fold_small", "k_extract_small", "k_rhs_fwd", "k_rhs_back", "k_vjp_accum"};
 
 int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
@@ -144,7 +155,8 @@ void free_plan(ndg_plan* p) {
   void* ptrs[] = {p->d_cl,        p->d_relmap,   p->d_kids_ptr,   p->d_kids,       p->d_hrow,
                   p->d_hcol,      p->d_hval,     p->d_perm,       p->d_owner,      p->d_clocal[0],
                   p->d_clocal[1], p->d_levels,   p->d_colitems,   p->d_upditems,   p->d_chainitems,
-                  p->d_chaincls,  p->d_ws,       p->d_status};
+                  p->d_chaincls,  p->d_ws,       p->d_status,     p->d_rY,         p->d_rX,
+                  p->d_rG,        p->d_rZ,       p->d_ovec,       p->d_bidx,       p->d_part};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& r : p->recs) {
@@ -187,6 +199,9 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   for (int c = 0; c < p->ncontacts; ++c) p->nc[c] = (int)sy.contact_local[c].size();
   p->ops = oc;
   p->stride = layout(sy, p->hdesc);
+  p->hbidx = sy.bidx;
+  for (int k = 0; k < (int)p->hdesc.size(); ++k)
+    if (p->hdesc[k].contact >= 0 && p->hdesc[k].contact < 2) p->contact_cl[p->hdesc[k].contact] = k;
   const int nc = sy.nclusters, H = sy.max_height;
   // schedules per height
   std::vector<int32_t> levels;
@@ -354,9 +369,55 @@ int plan_info(const ndg_plan* plan, ndg_info* out) {
   return NDG_OK;
 }
 
+int plan_enable_adjoint(ndg_plan* p) {
+  if (p->d_rY) return NDG_OK;
+  if (hipSetDevice(p->device) != hipSuccess) { set_error("ndg_plan_enable_adjoint: hipSetDevice failed"); return NDG_EHIP; }
+  int mmax = 1;
+  for (int c = 0; c < p->ncontacts; ++c) mmax = std::max(mmax, p->nc[c]);
+  std::vector<int64_t> ovec(p->nclusters);
+  int64_t off = 0;
+  for (int k = 0; k < p->nclusters; ++k) {
+    ovec[k] = off;
+    off += align8((int64_t)p->hdesc[k].f * mmax);
+  }
+  p->zstride = off;
+  p->mmax = mmax;
+  const size_t nb = (size_t)p->max_batch, nm = (size_t)p->n * mmax;
+  int rc = 0;
+  if (hipMalloc((void**)&p->d_rY, nb * nm * 16) != hipSuccess ||
+      hipMalloc((void**)&p->d_rX, nb * nm * 16) != hipSuccess ||
+      hipMalloc((void**)&p->d_rG, nb * nm * 16) != hipSuccess ||
+      hipMalloc((void**)&p->d_rZ, nb * (size_t)p->zstride * 16) != hipSuccess ||
+      hipMalloc((void**)&p->d_part, nb * (size_t)p->n * 8) != hipSuccess)
+    rc = NDG_ENOMEM;
+  if (!rc) rc = upload(&p->d_ovec, ovec.data(), ovec.size());
+  if (!rc) rc = upload(&p->d_bidx, p->hbidx.data(), p->hbidx.size());
+  if (rc) {
+    (void)hipGetLastError();
+    void* ptrs[] = {p->d_rY, p->d_rX, p->d_rG, p->d_rZ, p->d_part, p->d_ovec, p->d_bidx};
+    for (void* q : ptrs)
+      if (q) (void)hipFree(q);
+    p->d_rY = p->d_rX = p->d_rG = p->d_rZ = nullptr;
+    p->d_part = nullptr;
+    p->d_ovec = nullptr;
+    p->d_bidx = nullptr;
+    set_error("ndg_plan_enable_adjoint: device allocation failed");
+    return rc;
+  }
+  return NDG_OK;
+}
+
 int plan_solve(ndg_plan* p, int nE, const double* E, double eta, const double* V,
                const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
                ndg_c128* dgl, ndg_c128* dgg, double* growth, int prec, void* stream) {
+  return plan_run(p, kRunSolve, nE, E, eta, V, sig_r, sig_less, dgr, dgl, dgg, growth, nullptr,
+                  nullptr, nullptr, nullptr, prec, stream);
+}
+
+int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const double* V,
+             const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
+             ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
+             const double* nbar, double* vbar, int prec, void* stream) {
   if (prec != NDG_FP64) {
     set_error("ndg_solve: this plan supports NDG_FP64 only");
     return NDG_EINVAL;
@@ -398,6 +459,26 @@ int plan_solve(ndg_plan* p, int nE, const double* E, double eta, const double* V
   c.status = p->d_status;
   c.growth = growth;
   if (growth) launch_fill_zero(growth, nE, st);  // a kernel, so graph capture stays valid
+  if (mode == kRunDensity) launch_zero(density, p->n, st);
+  if (mode == kRunVjp) {
+    if (!p->d_rY) {
+      set_error("ndg_density_vjp: call ndg_plan_enable_adjoint first");
+      return NDG_EINVAL;
+    }
+    launch_zero(vbar, p->n, st);
+  }
+  RhsCtx r{};
+  r.Y = p->d_rY;
+  r.X = p->d_rX;
+  r.Gc = p->d_rG;
+  r.Z = p->d_rZ;
+  r.o_vec = p->d_ovec;
+  r.zstride = p->zstride;
+  r.n = (int32_t)p->n;
+  r.bidx = p->d_bidx;
+  r.nbar = nbar;
+  r.part = p->d_part;
+  for (int q = 0; q < 2; ++q) r.contact_cluster[q] = p->contact_cl[q];
   const int H = p->max_height;
   // profiling: an event pair around each launch, with its algorithmic work
   auto take_event = [&]() {
@@ -436,6 +517,32 @@ int plan_solve(ndg_plan* p, int nE, const double* E, double eta, const double* V
       }
       if (nch) timed(K_CHAIN_FWD, h, nb, [&] { launch_chain_fwd(c, chi, nch, nb, st); });
     }
+    if (mode == kRunVjp) {
+      launch_zero(r.part, (int64_t)nb * p->n, st);
+      for (int cc = 0; cc < p->ncontacts; ++cc) {
+        r.m = p->nc[cc];
+        // two solves with the factors: G_{:,c} = A^{-1} E_c, then
+        // X_c = A^{-1} (Lambda conj(G_{:,c}))
+        for (int pass = 0; pass < 2; ++pass) {
+          if (pass == 0) launch_rhs_contact(c, r, cc, nb, st);
+          else launch_rhs_lambda(c, r, nb, st);
+          RhsCtx rr = r;
+          rr.X = pass == 0 ? r.Gc : r.X;
+          for (int h = 1; h <= H; ++h)
+            timed(K_RHS_FWD, h, nb, [&] {
+              launch_rhs_fwd(c, rr, p->d_levels + p->lvl_ptr[h - 1], p->lvl_ptr[h] - p->lvl_ptr[h - 1], nb, st);
+            });
+          for (int h = H; h >= 1; --h)
+            timed(K_RHS_BACK, h, nb, [&] {
+              launch_rhs_back(c, rr, p->d_levels + p->lvl_ptr[h - 1], p->lvl_ptr[h] - p->lvl_ptr[h - 1], nb, st);
+            });
+        }
+        timed(K_VJP, 0, nb, [&] { launch_vjp_accum(c, r, cc, nb, st); });
+      }
+      launch_vjp_reduce(c, r, nb, cE, vbar, st);
+      p->last_batch = nb;
+      continue;
+    }
     for (int h = H; h >= 1; --h) {
       const int k0 = p->chaincl_ptr[h - 1], nck = p->chaincl_ptr[h] - k0;
       // the G^< source on chain clusters first: the extraction of P reads it
@@ -455,10 +562,13 @@ int plan_solve(ndg_plan* p, int nE, const double* E, double eta, const double* V
         timed(K_DOWN_DIAG_P, h, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, true, g.size, st); });
       }
     }
-    timed(K_EPILOGUE, 0, nb, [&] {
-      launch_epilogue(c, nb, reinterpret_cast<double2*>(dgr), reinterpret_cast<double2*>(dgl),
-                      reinterpret_cast<double2*>(dgg), st);
-    });
+    if (mode == kRunSolve)
+      timed(K_EPILOGUE, 0, nb, [&] {
+        launch_epilogue(c, nb, reinterpret_cast<double2*>(dgr), reinterpret_cast<double2*>(dgl),
+                        reinterpret_cast<double2*>(dgg), st);
+      });
+    else
+      launch_density(c, nb, cE, density, st);
     p->last_batch = nb;
   }
   if (hipGetLastError() != hipSuccess) { set_error("ndg_solve: kernel launch failed"); return NDG_EHIP; }

@@ -23,6 +23,12 @@ int plan_info(const ndg_plan* plan, ndg_info* out);
 int plan_solve(ndg_plan* plan, int nE, const double* E, double eta, const double* V,
                const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
                ndg_c128* dgl, ndg_c128* dgg, double* growth, int prec, void* stream);
+enum RunMode { kRunSolve = 0, kRunDensity = 1, kRunVjp = 2 };
+int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const double* V,
+             const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
+             ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
+             const double* nbar, double* vbar, int prec, void* stream);
+int plan_enable_adjoint(ndg_plan* plan);
 int plan_status(ndg_plan* plan, int32_t* code, int32_t* energy, int32_t* cluster);
 int plan_set_profiling(ndg_plan* plan, bool enable);
 int plan_profile(ndg_plan* plan, int capacity, ndg_kernel_stat* out, int32_t* count);
