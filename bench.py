@@ -75,6 +75,7 @@ def main():
     ap.add_argument("--batch", type=int, default=128, help="energies in flight per batch")
     ap.add_argument("--leaf", type=int, default=16, help="leaf size of the separator tree")
     ap.add_argument("--energies", type=int, default=512)
+    ap.add_argument("--no-adjoint", dest="adjoint", action="store_false")
     ap.add_argument("--cpu-sample", type=int, default=32,
                     help="energies of the CPU oracle timing sample (0 disables it)")
     args = ap.parse_args()
@@ -135,6 +136,52 @@ def main():
     ms_per_step = ms_total / args.steps
     value = ne / (ms_per_step / 1e3)
 
+    # mixed-precision path on the same inputs (timed the same way, no profiling)
+    out_m = tuple(torch.empty((ne, n), dtype=torch.complex128, device=cuda) for _ in range(3))
+    plan.solve(E, wl.eta, sig_r, sig_l, out=out_m, stream=stream, prec=ndg.NDG_MIXED)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.solve(E, wl.eta, sig_r, sig_l, out=out_m, stream=stream, prec=ndg.NDG_MIXED)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_mixed = ev0.elapsed_time(ev1) / args.steps
+    growth = torch.zeros(ne, dtype=torch.float64, device=cuda)
+    plan.solve(E, wl.eta, sig_r, sig_l, out=out, stream=stream, growth=growth)
+    torch.cuda.synchronize()
+    growth = growth.cpu().numpy()
+
+    # forward + adjoint on the adjoint workload (512 x 64, 256 energies)
+    adj = None
+    if args.adjoint:
+        wa = workloads.adjoint_device()
+        da = wa.device
+        syma = ndg.analyze(da.n, da.rowptr, da.col, da.val, da.contacts, da.coords,
+                           leaf_max=args.leaf)
+        pa = ndg.Plan(syma, max_batch=min(args.batch, 128))
+        pa.enable_adjoint()
+        sla, sra, lla, lra = wa.self_energies()
+        Ea = torch.tensor(wa.energies, device=cuda)
+        sra_t = [torch.from_numpy(a).to(cuda) for a in (sla, sra)]
+        sla_t = [torch.from_numpy(a).to(cuda) for a in (lla, lra)]
+        cEa = torch.tensor(wa.quad_weights(), device=cuda)
+        Va = torch.tensor(wa.potential, device=cuda)
+        nbar = torch.ones(da.n, dtype=torch.float64, device=cuda)
+        pa.density(Ea, wa.eta, sra_t, sla_t, cEa, V=Va)
+        pa.density_vjp(Ea, wa.eta, sra_t, sla_t, cEa, nbar, V=Va)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            pa.density(Ea, wa.eta, sra_t, sla_t, cEa, V=Va, stream=stream)
+            pa.density_vjp(Ea, wa.eta, sra_t, sla_t, cEa, nbar, V=Va, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_adj = ev0.elapsed_time(ev1) / args.steps
+        adj = {"workload": "512x64 FD grid, smooth +-50 meV V, %d energies" % wa.energies.size,
+               "fwd_plus_adjoint_ms_per_energy": ms_adj / wa.energies.size,
+               "ms_per_step": ms_adj}
+        del pa
+
     # dominant kernel and its roofline
     dom = max(stats, key=lambda r: r["ms"])
     t_dom = dom["ms"] / 1e3
@@ -163,17 +210,21 @@ def main():
         cpu = {"value": rate, "unit": UNIT, "cores": cores, "kind": "oracle",
                "sample": "%d of the %d energies (evenly spaced), plain RGF oracle, complex128, "
                          "one process per core, %.1f s wall" % (len(idxs), ne, cwall)}
-        gr = out[0][idxs].cpu().numpy()
-        gl = out[1][idxs].cpu().numpy()
-        errs = []
-        for k, i in enumerate(idxs):
-            rgr, rgl = res[i]
-            errs.append(max(np.max(np.abs(gr[k] - rgr)) / np.max(np.abs(rgr)),
-                            np.max(np.abs(gl[k] - rgl)) / np.max(np.abs(rgl))))
-        errs = np.array(errs)
-        parity = {"energies": len(idxs), "max_rel_err": float(errs.max()),
-                  "median_rel_err": float(np.median(errs)),
-                  "above_1e-10": int(np.sum(errs > 1e-10))}
+        parity = {"energies": len(idxs), "growth_below_30": int(np.sum(growth[idxs] < 30))}
+        for tag, o in (("fp64", out), ("mixed", out_m)):
+            gr = o[0][idxs].cpu().numpy()
+            gl = o[1][idxs].cpu().numpy()
+            errs = []
+            for k, i in enumerate(idxs):
+                rgr, rgl = res[i]
+                errs.append(max(np.max(np.abs(gr[k] - rgr)) / np.max(np.abs(rgr)),
+                                np.max(np.abs(gl[k] - rgl)) / np.max(np.abs(rgl))))
+            errs = np.array(errs)
+            good = growth[idxs] < 30
+            parity[tag] = {"max_rel_err": float(errs.max()), "median_rel_err": float(np.median(errs)),
+                           "max_rel_err_growth_below_30": float(errs[good].max()) if good.any() else None,
+                           "above_1e-10": int(np.sum(errs > 1e-10)),
+                           "above_1e-6": int(np.sum(errs > 1e-6))}
 
     line = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -186,6 +237,9 @@ def main():
                    "clusters": info["nclusters"], "tree_levels": info["max_height"],
                    "algorithmic_gflop_per_energy": info["ops_total"] * 8 / 1e9,
                    "rgf_gflop_per_energy": info["ops_rgf_equiv"] * 8 / 1e9},
+        "mixed": {"value": ne / (ms_mixed / 1e3), "ms_per_step": ms_mixed,
+                  "speedup_vs_fp64": ms_per_step / ms_mixed},
+        "adjoint": adj,
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity_sample": parity,

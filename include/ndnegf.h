@@ -167,6 +167,12 @@ ndg_status ndg_plan_info(const ndg_plan* plan, ndg_info* out);
  *                    stays moderate, and rounding errors grow with it.  Values
  *                    near 1 mean a well-conditioned fold.
  *   prec             NDG_FP64: every step in double precision.
+ *                    NDG_MIXED: the Schur-update products and the extraction
+ *                    products of fronts larger than 64 points run in complex
+ *                    FP32 on the matrix cores with FP32 accumulation (inputs
+ *                    rounded from FP64, results stored in FP64); pivot-block
+ *                    inverses, Psi, the contact clusters' factorization and all
+ *                    fronts of at most 64 points stay FP64.
  * Errors (synchronous): NDG_EINVAL for null pointers, nE < 0, eta < 0 or a
  * precision the plan does not support; NDG_EHIP if a launch fails.
  * Numerical faults: see ndg_plan_status.

@@ -139,6 +139,132 @@ __device__ inline void ztile_store(const ZTile& acc, FS fs) {
   ztile_store_t<64>(acc, fs);
 }
 
+
+// ---------------------------------------------------------------------------
+// Complex FP32 tiles on the FP32 matrix cores (mixed-precision path):
+// v_mfma_f32_16x16x4_f32 with FP32 accumulation; operands are read in FP64
+// and rounded to FP32 while staging.  Output layout: lane l, register r ->
+// row 4 (l / 16) + r, column l % 16.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+struct GemmSmem32 {
+  float ar[64][KC + 1], ai[64][KC + 1];
+  float br[KC][64 + 1], bi[KC][64 + 1];
+};
+
+struct ZTile32 {
+  v4f re[2][2];
+  v4f im[2][2];
+};
+
+__device__ inline void ztile32_zero(ZTile32& a) {
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      a.re[m][n] = v4f{0, 0, 0, 0};
+      a.im[m][n] = v4f{0, 0, 0, 0};
+    }
+}
+
+template <int TM, bool A_IFAST, bool B_KFAST, class FA, class FB>
+__device__ void zgemm32_acc_t(int K, FA fa, FB fb, ZTile32& acc, GemmSmem32& sm) {
+  using T = TileShape<TM>;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+    for (int q = 0; q < TM / 16; ++q) {
+      const int idx = t + 256 * q;
+      int i, kk;
+      if (A_IFAST) { i = idx % TM; kk = idx / TM; }
+      else { kk = idx & (KC - 1); i = idx / KC; }
+      const double2 v = (k0 + kk < K) ? fa(i, k0 + kk) : cz();
+      sm.ar[i][kk] = (float)v.x;
+      sm.ai[i][kk] = (float)v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = t + 256 * q;
+      int kk, j;
+      if (B_KFAST) { kk = idx & (KC - 1); j = idx / KC; }
+      else { j = idx & 63; kk = idx >> 6; }
+      const double2 v = (k0 + kk < K) ? fb(k0 + kk, j) : cz();
+      sm.br[kk][j] = (float)v.x;
+      sm.bi[kk][j] = (float)v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < KC; k4 += 4) {
+      const int kq = k4 + (lane >> 4);
+      float are[2], aim[2], bre[2], bim[2];
+#pragma unroll
+      for (int m = 0; m < T::MB; ++m) {
+        const int i = wr + m * 16 + (lane & 15);
+        are[m] = sm.ar[i][kq];
+        aim[m] = sm.ai[i][kq];
+      }
+#pragma unroll
+      for (int n = 0; n < T::NB; ++n) {
+        const int j = wc + n * 16 + (lane & 15);
+        bre[n] = sm.br[kq][j];
+        bim[n] = sm.bi[kq][j];
+      }
+#pragma unroll
+      for (int m = 0; m < T::MB; ++m)
+#pragma unroll
+        for (int n = 0; n < T::NB; ++n) {
+          acc.re[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[m], bre[n], acc.re[m][n], 0, 0, 0);
+          acc.re[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(-aim[m], bim[n], acc.re[m][n], 0, 0, 0);
+          acc.im[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[m], bim[n], acc.im[m][n], 0, 0, 0);
+          acc.im[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[m], bre[n], acc.im[m][n], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+}
+
+template <int TM, class FS>
+__device__ inline void ztile32_store_t(const ZTile32& acc, FS fs) {
+  using T = TileShape<TM>;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
+#pragma unroll
+  for (int m = 0; m < T::MB; ++m)
+#pragma unroll
+    for (int n = 0; n < T::NB; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = wr + m * 16 + 4 * (lane >> 4) + r;
+        const int j = wc + n * 16 + (lane & 15);
+        fs(i, j, (double)acc.re[m][n][r], (double)acc.im[m][n][r]);
+      }
+}
+
+// Precision-generic front ends: P64 = true selects the FP64 tiles.
+template <bool P64>
+struct Gemm;
+template <>
+struct Gemm<true> {
+  using Tile = ZTile;
+  using Smem = GemmSmem;
+  __device__ static void zero(Tile& a) { ztile_zero(a); }
+  template <int TM, bool AI, bool BK, class FA, class FB>
+  __device__ static void acc(int K, FA fa, FB fb, Tile& t, Smem& sm) { zgemm_acc_t<TM, AI, BK>(K, fa, fb, t, sm); }
+  template <int TM, class FS>
+  __device__ static void store(const Tile& t, FS fs) { ztile_store_t<TM>(t, fs); }
+};
+template <>
+struct Gemm<false> {
+  using Tile = ZTile32;
+  using Smem = GemmSmem32;
+  __device__ static void zero(Tile& a) { ztile32_zero(a); }
+  template <int TM, bool AI, bool BK, class FA, class FB>
+  __device__ static void acc(int K, FA fa, FB fb, Tile& t, Smem& sm) { zgemm32_acc_t<TM, AI, BK>(K, fa, fb, t, sm); }
+  template <int TM, class FS>
+  __device__ static void store(const Tile& t, FS fs) { ztile32_store_t<TM>(t, fs); }
+};
+
 __device__ inline void raise_fault(int32_t* status, int code, int e, int cl) {
   if (atomicCAS(status, 0, code) == 0) {
     atomicExch(status + 1, e);

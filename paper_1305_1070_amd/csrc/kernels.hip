@@ -220,8 +220,10 @@ __global__ void __launch_bounds__(256) k_psi(Ctx c, const ColItem* items) {
 
 // Schur contribution of cluster i to its parent front:
 // U = F_BB + Psi^T F_{i,B} (b x b), one 64 x 64 tile per block.
+template <bool P64>
 __global__ void __launch_bounds__(256) k_update(Ctx c, const UpdItem* items) {
-  __shared__ GemmSmem sm;
+  using GM = Gemm<P64>;
+  __shared__ typename GM::Smem sm;
   const UpdItem it = items[blockIdx.x];
   const int e = blockIdx.y;
   const ClusterDesc d = c.cl[it.cl];
@@ -232,12 +234,12 @@ __global__ void __launch_bounds__(256) k_update(Ctx c, const UpdItem* items) {
   const int s = d.s, b = d.b, f = d.f;
   const int i0 = it.tr * 64, j0 = it.tc * 64;
   const int ni = min(64, b - i0), nj = min(64, b - j0);
-  ZTile acc;
-  ztile_zero(acc);
-  zgemm_acc<true, false>(
+  typename GM::Tile acc;
+  GM::zero(acc);
+  GM::template acc<64, true, false>(
       s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
       [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm);
-  ztile_store(acc, [&](int i, int j, double re, double im) {
+  GM::template store<64>(acc, [&](int i, int j, double re, double im) {
     if (i < ni && j < nj) {
       const double2 fb = F[(int64_t)(s + i0 + i) * f + s + j0 + j];
       U[(int64_t)(i0 + i) * b + j0 + j] = make_double2(fb.x + re, fb.y + im);
@@ -398,9 +400,10 @@ __global__ void __launch_bounds__(256) k_chain_back(Ctx c, const int32_t* cls) {
 // G_{i,B}^T (P_{B,i} = -P_{i,B}^+) and the gathered B x B block, which i's
 // children read.
 // ---------------------------------------------------------------------------
-template <int TM>
+template <int TM, bool P64>
 __global__ void __launch_bounds__(256) k_down_off(Ctx c, const ColItem* items, int lesser) {
-  __shared__ GemmSmem sm;
+  using GM = Gemm<P64>;
+  __shared__ typename GM::Smem sm;
   const ColItem it = items[blockIdx.x];
   const int e = blockIdx.y;
   const ClusterDesc d = c.cl[it.cl];
@@ -421,13 +424,13 @@ __global__ void __launch_bounds__(256) k_down_off(Ctx c, const ColItem* items, i
       X[(int64_t)(s + k) * f + s + j0 + j] = Xp[(int64_t)rel[k] * fp + rel[j0 + j]];
     }
   }
-  ZTile acc;
-  ztile_zero(acc);
-  zgemm_acc_t<TM, false, false>(
+  typename GM::Tile acc;
+  GM::zero(acc);
+  GM::template acc<TM, false, false>(
       b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
       [&](int k, int j) { return j < nj ? Xp[(int64_t)rel[k] * fp + rel[j0 + j]] : cz(); }, acc,
       sm);
-  ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
+  GM::template store<TM>(acc, [&](int i, int j, double re, double im) {
     if (i < s && j < nj) {
       double2 v = make_double2(re, im);
       const int64_t pos = (int64_t)i * f + s + j0 + j;
@@ -440,9 +443,10 @@ __global__ void __launch_bounds__(256) k_down_off(Ctx c, const ColItem* items, i
 
 //   G_ii = A_ii^{-1} + Psi_i G_{B,i},  G_{B,i} = G_{i,B}^T
 //   P_ii = P_init + Psi_i P_{B,i},     P_{B,i} = -P_{i,B}^+
-template <int TM>
+template <int TM, bool P64>
 __global__ void __launch_bounds__(256) k_down_diag(Ctx c, const int32_t* cls, int lesser) {
-  __shared__ GemmSmem sm;
+  using GM = Gemm<P64>;
+  __shared__ typename GM::Smem sm;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
   const ClusterDesc d = c.cl[cl];
@@ -452,10 +456,10 @@ __global__ void __launch_bounds__(256) k_down_diag(Ctx c, const int32_t* cls, in
   double2* X = S + (lesser ? d.o_fp : d.o_fg);
   const int s = d.s, b = d.b, f = d.f;
   const bool has_src = lesser && d.chain_mask;
-  ZTile acc;
-  ztile_zero(acc);
+  typename GM::Tile acc;
+  GM::zero(acc);
   if (lesser) {
-    zgemm_acc_t<TM, false, true>(
+    GM::template acc<TM, false, true>(
         b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
         [&](int k, int j) {
           if (j >= s) return cz();
@@ -464,11 +468,11 @@ __global__ void __launch_bounds__(256) k_down_diag(Ctx c, const int32_t* cls, in
         },
         acc, sm);
   } else {
-    zgemm_acc_t<TM, false, true>(
+    GM::template acc<TM, false, true>(
         b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
         [&](int k, int j) { return j < s ? X[(int64_t)j * f + s + k] : cz(); }, acc, sm);
   }
-  ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
+  GM::template store<TM>(acc, [&](int i, int j, double re, double im) {
     if (i < s && j < s) {
       double2 v = make_double2(re, im);
       const int64_t pos = (int64_t)i * f + j;
@@ -528,24 +532,38 @@ void launch_psi(const Ctx& c, const ColItem* it, int nit, int nb, int cls_size, 
   else hipLaunchKernelGGL((k_psi<64>), dim3(nit, nb), dim3(256), 0, st, c, it);
 }
 void launch_update(const Ctx& c, const UpdItem* it, int nit, int nb, hipStream_t st) {
-  if (nit > 0) hipLaunchKernelGGL(k_update, dim3(nit, nb), dim3(256), 0, st, c, it);
+  if (nit <= 0) return;
+  if (c.mixed) hipLaunchKernelGGL((k_update<false>), dim3(nit, nb), dim3(256), 0, st, c, it);
+  else hipLaunchKernelGGL((k_update<true>), dim3(nit, nb), dim3(256), 0, st, c, it);
 }
 void launch_chain_fwd(const Ctx& c, const ChainItem* it, int nit, int nb, hipStream_t st) {
   if (nit > 0) hipLaunchKernelGGL(k_chain_fwd, dim3(nit, nb), dim3(256), 0, st, c, it);
 }
+template <bool P64>
+static void down_off_t(const Ctx& c, const ColItem* it, int nit, int nb, bool lesser, int cls_size,
+                       hipStream_t st) {
+  if (cls_size <= 16) hipLaunchKernelGGL((k_down_off<16, P64>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
+  else if (cls_size <= 32) hipLaunchKernelGGL((k_down_off<32, P64>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
+  else hipLaunchKernelGGL((k_down_off<64, P64>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
+}
 void launch_down_off(const Ctx& c, const ColItem* it, int nit, int nb, bool lesser, int cls_size,
                      hipStream_t st) {
   if (nit <= 0) return;
-  if (cls_size <= 16) hipLaunchKernelGGL((k_down_off<16>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
-  else if (cls_size <= 32) hipLaunchKernelGGL((k_down_off<32>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
-  else hipLaunchKernelGGL((k_down_off<64>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
+  if (c.mixed) down_off_t<false>(c, it, nit, nb, lesser, cls_size, st);
+  else down_off_t<true>(c, it, nit, nb, lesser, cls_size, st);
+}
+template <bool P64>
+static void down_diag_t(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, int cls_size,
+                        hipStream_t st) {
+  if (cls_size <= 16) hipLaunchKernelGGL((k_down_diag<16, P64>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
+  else if (cls_size <= 32) hipLaunchKernelGGL((k_down_diag<32, P64>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
+  else hipLaunchKernelGGL((k_down_diag<64, P64>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
 }
 void launch_down_diag(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, int cls_size,
                       hipStream_t st) {
   if (ncl <= 0) return;
-  if (cls_size <= 16) hipLaunchKernelGGL((k_down_diag<16>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
-  else if (cls_size <= 32) hipLaunchKernelGGL((k_down_diag<32>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
-  else hipLaunchKernelGGL((k_down_diag<64>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
+  if (c.mixed) down_diag_t<false>(c, cls, ncl, nb, lesser, cls_size, st);
+  else down_diag_t<true>(c, cls, ncl, nb, lesser, cls_size, st);
 }
 void launch_chain_back(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st) {
   if (ncl > 0) hipLaunchKernelGGL(k_chain_back, dim3(ncl, nb), dim3(256), 0, st, c, cls);

@@ -55,6 +55,7 @@ struct Ctx {
   const double2* sig_l[2];
   int32_t* status;           // [code, energy, cluster]
   double* growth;            // [nE] or null: max over clusters of ||A_ii^{-1}|| ||A_iB||
+  int32_t mixed;             // 1: Schur updates and extraction products on FP32 matrix cores
 };
 
 // Multi-right-hand-side solves with the factors of the fold (adjoint).

@@ -418,8 +418,8 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
              const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
              ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
              const double* nbar, double* vbar, int prec, void* stream) {
-  if (prec != NDG_FP64) {
-    set_error("ndg_solve: this plan supports NDG_FP64 only");
+  if (prec != NDG_FP64 && prec != NDG_MIXED) {
+    set_error("ndg_solve: unknown precision");
     return NDG_EINVAL;
   }
   if (p->ncontacts > 0 && (!sig_r || !sig_less)) {
@@ -458,6 +458,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   c.V = V;
   c.status = p->d_status;
   c.growth = growth;
+  c.mixed = prec == NDG_MIXED ? 1 : 0;
   if (growth) launch_fill_zero(growth, nE, st);  // a kernel, so graph capture stays valid
   if (mode == kRunDensity) launch_zero(density, p->n, st);
   if (mode == kRunVjp) {

@@ -12,7 +12,7 @@ def rel_err(x, ref):
 
 
 def gpu_solve(ndg, wl, energies=None, max_batch=64, tree_kind=0, leaf_max=0, V=None, sym=None,
-              keep_plan=False):
+              keep_plan=False, prec=0):
     import torch
     dev = wl.device
     e = wl.energies if energies is None else np.asarray(energies, dtype=np.float64)
@@ -29,7 +29,7 @@ def gpu_solve(ndg, wl, energies=None, max_batch=64, tree_kind=0, leaf_max=0, V=N
     if V is not None:
         Vt = torch.tensor(np.asarray(V, dtype=np.float64), device=cuda)
     growth = torch.zeros(len(e), dtype=torch.float64, device=cuda)
-    gr, gl, gg = plan.solve(E, wl.eta, sig_r, sig_l, V=Vt, growth=growth)
+    gr, gl, gg = plan.solve(E, wl.eta, sig_r, sig_l, V=Vt, growth=growth, prec=prec)
     torch.cuda.synchronize()
     out = (gr.cpu().numpy(), gl.cpu().numpy(), gg.cpu().numpy(), growth.cpu().numpy())
     status = plan.status()
