@@ -213,6 +213,41 @@ ndg_status ndg_density_vjp(ndg_plan* plan, int32_t nE, const double* E, double e
                            const double* cE, const double* nbar, double* vbar, ndg_precision prec,
                            void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched solve of several devices (plans) of uneven sizes in one launch.
+ *
+ * ndg_batch_solve captures, on its first call with a given argument set, the
+ * solves of all plans into one HIP graph -- one branch per device, so the
+ * devices' level-by-level kernels run concurrently -- and launches it with a
+ * single hipGraphLaunch on `stream`; later calls with identical arguments
+ * replay the instantiated graph.  Each args[i] holds the arguments ndg_solve
+ * takes for plans[i] (device pointers; the growth pointer may be NULL).  The
+ * plans must be distinct, on one device, and have profiling switched off.
+ * The graph is re-captured whenever a pointer, nE, eta or the precision
+ * differs from the cached set; the contents of the buffers may change
+ * freely between calls.  Capturing allocates no device memory.  `stream`
+ * must not be the legacy NULL stream (capture needs a created stream).
+ * Errors: NDG_EINVAL (bad arguments), NDG_EHIP (capture or launch failed).
+ */
+typedef struct ndg_batch ndg_batch;
+typedef struct {
+  int32_t nE;
+  const double* E;
+  double eta;
+  const double* V;
+  const ndg_c128* const* sig_r;     /* host array of ncontacts device pointers */
+  const ndg_c128* const* sig_less;
+  ndg_c128* diag_gr;
+  ndg_c128* diag_gless;
+  ndg_c128* diag_ggreater;
+  double* growth;
+} ndg_solve_args;
+
+ndg_status ndg_batch_create(int32_t nplans, ndg_plan* const* plans, ndg_batch** out);
+ndg_status ndg_batch_destroy(ndg_batch* batch);
+ndg_status ndg_batch_solve(ndg_batch* batch, const ndg_solve_args* args, ndg_precision prec,
+                           void* stream);
+
 /* Status word of the last solves on this plan (call after synchronising the
  * stream).  *code = NDG_OK, NDG_ESINGULAR (a pivot of magnitude 0 in a
  * cluster inverse) or NDG_ENONFINITE; *energy and *cluster identify the first

@@ -22,6 +22,7 @@ __all__ = ["analyze", "Symbolic", "Plan", "load", "NdgError", "NDG_FP64", "NDG_M
            "ndg_plan_destroy", "ndg_plan_info", "ndg_solve", "ndg_plan_status",
            "ndg_plan_export_block", "ndg_plan_set_profiling", "ndg_plan_profile",
            "ndg_density", "ndg_plan_enable_adjoint", "ndg_density_vjp", "NDDensity",
+           "ndg_batch_create", "ndg_batch_destroy", "ndg_batch_solve", "Batch",
            "ndg_status_string", "ndg_last_error"]
 
 
@@ -145,6 +146,34 @@ def ndg_plan_profile(plan) -> list:
     return [{"name": arr[i].name.decode(), "height": arr[i].height,
              "launches": arr[i].launches, "ms": arr[i].ms,
              "flops": arr[i].flops, "bytes": arr[i].bytes} for i in range(cnt.value)]
+
+
+def ndg_batch_create(plans):
+    arr = (C.c_void_p * len(plans))(*[p.value if isinstance(p, C.c_void_p) else p for p in plans])
+    out = C.c_void_p()
+    _lib.check(load().ndg_batch_create(len(plans), arr, C.byref(out)))
+    return out
+
+
+def ndg_batch_destroy(batch):
+    _lib.check(load().ndg_batch_destroy(batch))
+
+
+def ndg_batch_solve(batch, args, prec, stream_ptr):
+    """args: one dict per plan with the ndg_solve arguments as integers
+    (device addresses): nE, E, eta, V, sig_r (list), sig_less (list),
+    diag_gr, diag_gless, diag_ggreater, growth (None for NULL)."""
+    keep = []
+    arr = (_lib.SolveArgs * len(args))()
+    for k, a in enumerate(args):
+        nc = len(a["sig_r"])
+        sr = (C.c_void_p * max(1, nc))(*a["sig_r"])
+        sl = (C.c_void_p * max(1, nc))(*a["sig_less"])
+        keep += [sr, sl]
+        arr[k] = _lib.SolveArgs(a["nE"], a["E"], a["eta"], a["V"],
+                                C.cast(sr, C.POINTER(C.c_void_p)), C.cast(sl, C.POINTER(C.c_void_p)),
+                                a["diag_gr"], a["diag_gless"], a["diag_ggreater"], a["growth"])
+    _lib.check(load().ndg_batch_solve(batch, arr, prec, stream_ptr))
 
 
 def ndg_status_string(code: int) -> str:
@@ -304,6 +333,54 @@ class Plan:
     def __del__(self):
         if getattr(self, "handle", None) and _lib._lib is not None:
             _lib._lib.ndg_plan_destroy(self.handle)
+            self.handle = None
+
+
+class Batch:
+    """Several devices (plans) of uneven sizes solved by one graph launch.
+
+    solve() takes one tuple (E, eta, sig_r, sig_less, V) per plan and
+    returns one (diag G^r, diag G^<, diag G^>) per plan.  Outputs are kept
+    per batch and reused, so that repeated calls with the same input tensors
+    replay the captured graph; copy results that must survive the next call."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        self.handle = ndg_batch_create([p.handle for p in self.plans])
+        self._outs = None
+        self._stream = None
+
+    def solve(self, inputs, prec=NDG_FP64):
+        import torch
+        if len(inputs) != len(self.plans):
+            raise ValueError("one input tuple per plan")
+        shapes = []
+        for p, (E, eta, sig_r, sig_less, V) in zip(self.plans, inputs):
+            n, ne, dev = p._check_inputs(E, sig_r, sig_less, V)
+            shapes.append((ne, n, dev))
+        if self._outs is None or [tuple(o[0].shape) for o in self._outs] != [s[:2] for s in shapes]:
+            self._outs = [tuple(torch.empty((ne, n), dtype=torch.complex128, device=dev)
+                                for _ in range(3)) for ne, n, dev in shapes]
+        if self._stream is None:
+            # graph capture needs a created stream, not the legacy default one
+            self._stream = torch.cuda.Stream(device=shapes[0][2])
+        cur = torch.cuda.current_stream(shapes[0][2])
+        self._stream.wait_stream(cur)
+        args = []
+        for (E, eta, sig_r, sig_less, V), (gr, gl, gg) in zip(inputs, self._outs):
+            args.append({"nE": int(E.shape[0]), "E": E.data_ptr(), "eta": float(eta),
+                         "V": V.data_ptr() if V is not None else None,
+                         "sig_r": [t.data_ptr() for t in sig_r],
+                         "sig_less": [t.data_ptr() for t in sig_less],
+                         "diag_gr": gr.data_ptr(), "diag_gless": gl.data_ptr(),
+                         "diag_ggreater": gg.data_ptr(), "growth": None})
+        ndg_batch_solve(self.handle, args, prec, C.c_void_p(self._stream.cuda_stream))
+        cur.wait_stream(self._stream)
+        return list(self._outs)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib._lib is not None:
+            _lib._lib.ndg_batch_destroy(self.handle)
             self.handle = None
 
 

@@ -51,6 +51,15 @@ class KernelStat(C.Structure):
 
 
 P = C.c_void_p
+
+
+class SolveArgs(C.Structure):
+    _fields_ = [("nE", C.c_int32), ("E", C.c_void_p), ("eta", C.c_double), ("V", C.c_void_p),
+                ("sig_r", C.POINTER(C.c_void_p)), ("sig_less", C.POINTER(C.c_void_p)),
+                ("diag_gr", C.c_void_p), ("diag_gless", C.c_void_p),
+                ("diag_ggreater", C.c_void_p), ("growth", C.c_void_p)]
+
+
 I32P = C.POINTER(C.c_int32)
 I64P = C.POINTER(C.c_int64)
 F64P = C.POINTER(C.c_double)
@@ -76,6 +85,9 @@ SIGNATURES = {
                                   P, P, C.c_int, P]),
     "ndg_plan_set_profiling": (C.c_int, [P, C.c_int32]),
     "ndg_plan_profile": (C.c_int, [P, C.c_int32, C.POINTER(KernelStat), C.POINTER(C.c_int32)]),
+    "ndg_batch_create": (C.c_int, [C.c_int32, C.POINTER(P), C.POINTER(P)]),
+    "ndg_batch_destroy": (C.c_int, [P]),
+    "ndg_batch_solve": (C.c_int, [P, C.POINTER(SolveArgs), C.c_int, P]),
     "ndg_status_string": (C.c_char_p, [C.c_int32]),
     "ndg_last_error": (C.c_char_p, []),
 }

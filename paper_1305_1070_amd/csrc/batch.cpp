@@ -1,0 +1,182 @@
+// Batched solve of several devices in one graph launch.
+//
+// Energies and devices are independent problems (Section 3.2 processes one
+// energy at a time), so a batch of uneven devices is a set of independent
+// level-by-level launch sequences.  They are captured once into one HIP
+// graph with a branch per device (fork/join through events on per-device
+// capture streams) and replayed with a single hipGraphLaunch.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ndnegf.h"
+#include "runtime.hpp"
+
+struct ndg_batch {
+  std::vector<ndg_plan*> plans;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> done;
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  // the argument set the cached graph was captured with
+  std::vector<ndg_solve_args> key;
+  std::vector<std::vector<const ndg_c128*>> key_sig;
+  int key_prec = -1;
+};
+
+namespace {
+
+void release_graph(ndg_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->key.clear();
+  b->key_sig.clear();
+  b->key_prec = -1;
+}
+
+bool same_key(const ndg_batch* b, const ndg_solve_args* args, int prec) {
+  if (!b->exec || b->key_prec != prec || b->key.size() != b->plans.size()) return false;
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    const ndg_solve_args& a = args[i];
+    const ndg_solve_args& k = b->key[i];
+    if (a.nE != k.nE || a.E != k.E || a.eta != k.eta || a.V != k.V || a.diag_gr != k.diag_gr ||
+        a.diag_gless != k.diag_gless || a.diag_ggreater != k.diag_ggreater || a.growth != k.growth)
+      return false;
+    const int nc = ndg::plan_ncontacts(b->plans[i]);
+    for (int c = 0; c < nc; ++c)
+      if (a.sig_r[c] != b->key_sig[i][2 * c] || a.sig_less[c] != b->key_sig[i][2 * c + 1]) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+ndg_status ndg_batch_create(int32_t nplans, ndg_plan* const* plans, ndg_batch** out) {
+  if (!out || nplans <= 0 || !plans) { ndg::set_error("ndg_batch_create: bad argument"); return NDG_EINVAL; }
+  *out = nullptr;
+  for (int i = 0; i < nplans; ++i) {
+    if (!plans[i]) { ndg::set_error("ndg_batch_create: NULL plan"); return NDG_EINVAL; }
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) { ndg::set_error("ndg_batch_create: a plan appears twice"); return NDG_EINVAL; }
+  }
+  auto* b = new (std::nothrow) ndg_batch;
+  if (!b) { ndg::set_error("ndg_batch_create: out of host memory"); return NDG_ENOMEM; }
+  b->plans.assign(plans, plans + nplans);
+  if (hipSetDevice(ndg::plan_device(plans[0])) != hipSuccess ||
+      hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+    delete b;
+    ndg::set_error("ndg_batch_create: HIP event creation failed");
+    return NDG_EHIP;
+  }
+  for (int i = 0; i < nplans; ++i) {
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    // default priority: every stream of the library uses the default
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      ndg_batch_destroy(b);
+      ndg::set_error("ndg_batch_create: HIP stream creation failed");
+      return NDG_EHIP;
+    }
+    b->streams.push_back(s);
+    b->done.push_back(ev);
+  }
+  *out = b;
+  return NDG_OK;
+}
+
+ndg_status ndg_batch_destroy(ndg_batch* b) {
+  if (!b) return NDG_OK;
+  release_graph(b);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  delete b;
+  return NDG_OK;
+}
+
+ndg_status ndg_batch_solve(ndg_batch* b, const ndg_solve_args* args, ndg_precision prec,
+                           void* stream) {
+  if (!b || !args) { ndg::set_error("ndg_batch_solve: NULL argument"); return NDG_EINVAL; }
+  if (prec != NDG_FP64 && prec != NDG_MIXED) { ndg::set_error("ndg_batch_solve: unknown precision"); return NDG_EINVAL; }
+  const int np = (int)b->plans.size();
+  for (int i = 0; i < np; ++i) {
+    const ndg_solve_args& a = args[i];
+    if (a.nE <= 0 || !a.E || !a.diag_gr || !a.diag_gless || !(a.eta >= 0)) {
+      ndg::set_error("ndg_batch_solve: bad arguments for device " + std::to_string(i));
+      return NDG_EINVAL;
+    }
+    const int nc = ndg::plan_ncontacts(b->plans[i]);
+    if (nc > 0 && (!a.sig_r || !a.sig_less)) { ndg::set_error("ndg_batch_solve: missing self-energies"); return NDG_EINVAL; }
+    for (int c = 0; c < nc; ++c)
+      if (!a.sig_r[c] || !a.sig_less[c]) { ndg::set_error("ndg_batch_solve: NULL self-energy"); return NDG_EINVAL; }
+  }
+  for (int i = 0; i < np; ++i)
+    if (ndg::plan_profiling(b->plans[i])) {
+      // per-launch timing events cannot be recorded into a graph
+      ndg::set_error("ndg_batch_solve: switch profiling off on the batch's plans");
+      return NDG_EINVAL;
+    }
+  hipStream_t st = (hipStream_t)stream;
+  if (hipSetDevice(ndg::plan_device(b->plans[0])) != hipSuccess) { ndg::set_error("ndg_batch_solve: hipSetDevice failed"); return NDG_EHIP; }
+  if (!same_key(b, args, (int)prec)) {
+    release_graph(b);
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      ndg::set_error("ndg_batch_solve: hipStreamBeginCapture failed");
+      return NDG_EHIP;
+    }
+    int rc = NDG_OK;
+    (void)hipEventRecord(b->fork, st);
+    for (int i = 0; i < np && rc == NDG_OK; ++i) {
+      (void)hipStreamWaitEvent(b->streams[i], b->fork, 0);
+      const ndg_solve_args& a = args[i];
+      rc = ndg::plan_solve(b->plans[i], a.nE, a.E, a.eta, a.V, a.sig_r, a.sig_less, a.diag_gr,
+                           a.diag_gless, a.diag_ggreater, a.growth, (int)prec, b->streams[i]);
+      (void)hipEventRecord(b->done[i], b->streams[i]);
+      (void)hipStreamWaitEvent(st, b->done[i], 0);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &g);
+    if (rc != NDG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return (ndg_status)rc;
+    }
+    if (ec != hipSuccess || !g) { ndg::set_error("ndg_batch_solve: hipStreamEndCapture failed"); return NDG_EHIP; }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      ndg::set_error("ndg_batch_solve: hipGraphInstantiate failed");
+      return NDG_EHIP;
+    }
+    b->graph = g;
+    b->exec = ex;
+    b->key.assign(args, args + np);
+    b->key_sig.assign(np, {});
+    for (int i = 0; i < np; ++i) {
+      const int nc = ndg::plan_ncontacts(b->plans[i]);
+      for (int c = 0; c < nc; ++c) {
+        b->key_sig[i].push_back(args[i].sig_r[c]);
+        b->key_sig[i].push_back(args[i].sig_less[c]);
+      }
+      // the host arrays of pointers need not outlive the call
+      b->key[i].sig_r = nullptr;
+      b->key[i].sig_less = nullptr;
+    }
+    b->key_prec = (int)prec;
+  }
+  if (hipGraphLaunch(b->exec, st) != hipSuccess) {
+    ndg::set_error("ndg_batch_solve: hipGraphLaunch failed");
+    return NDG_EHIP;
+  }
+  return NDG_OK;
+}
+
+}  // extern "C"

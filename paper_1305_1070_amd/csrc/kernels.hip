@@ -66,19 +66,15 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
     F[(int64_t)r * f + r] = a;
   }
   __syncthreads();
-  if (d.contact >= 0) {
-    const int cc = d.contact, nc = c.nc[cc];
-    const double2* sg = c.sig_r[cc] + (int64_t)(c.e0 + e) * nc * nc;
-    const int32_t* loc = c.clocal[cc];
-    for (int q = t; q < nc * nc; q += 256) {
-      const int a = q / nc, b = q % nc;
-      const int64_t pos = (int64_t)loc[a] * f + loc[b];
-      const double2 sv = sg[q];
-      double2 v = F[pos];
-      v.x -= sv.x;
-      v.y -= sv.y;
-      F[pos] = v;
-    }
+  // contact self-energies: each entry of the front is listed once
+  for (int q = d.sptr0 + t; q < d.sptr1; q += 256) {
+    const int cc = c.scid[q], nc = c.nc[cc];
+    const double2 sv = c.sig_r[cc][(int64_t)(c.e0 + e) * nc * nc + c.sflat[q]];
+    const int64_t pos = (int64_t)c.srow[q] * f + c.scol[q];
+    double2 v = F[pos];
+    v.x -= sv.x;
+    v.y -= sv.y;
+    F[pos] = v;
   }
 }
 
@@ -277,35 +273,47 @@ __global__ void __launch_bounds__(256) k_chain_fwd(Ctx c, const ChainItem* items
       const int r = q / sc, a = q % sc;
       Zf[(int64_t)rel[r] * sc + a] = Zc[(int64_t)(dc.s + r) * sc + a];
     }
-  } else if (d.contact == cc) {
-    const int32_t* loc = c.clocal[cc];
-    for (int a = t; a < sc; a += 256) Zf[(int64_t)loc[a] * sc + a] = make_double2(1.0, 0.0);
   }
   __syncthreads();
-  for (int i0 = 0; i0 < b; i0 += 64) {
-    const int ni = min(64, b - i0);
+  // the contact's own columns: ones at its sites held by this cluster
+  {
+    const int32_t* pos = c.cpos[cc];
+    for (int a = t; a < sc; a += 256) {
+      const int r = pos[a] - d.pt_off;
+      if (r >= 0 && r < s) Zf[(int64_t)r * sc + a] = make_double2(1.0, 0.0);
+    }
+  }
+  __syncthreads();
+  // contacts wider than one tile: 64-column panels of Zf, independent
+  for (int j0 = 0; j0 < sc; j0 += 64) {
+    const int nj = min(64, sc - j0);
+    for (int i0 = 0; i0 < b; i0 += 64) {
+      const int ni = min(64, b - i0);
+      ZTile acc;
+      ztile_zero(acc);
+      zgemm_acc<true, false>(
+          s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
+          [&](int k, int j) { return j < nj ? Zf[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
+      ztile_store(acc, [&](int i, int j, double re, double im) {
+        if (i < ni && j < nj) {
+          double2 v = Zf[(int64_t)(s + i0 + i) * sc + j0 + j];
+          v.x += re;
+          v.y += im;
+          Zf[(int64_t)(s + i0 + i) * sc + j0 + j] = v;
+        }
+      });
+    }
+    // in place: the panel's rows [0, s) are all staged before any is written
     ZTile acc;
     ztile_zero(acc);
-    zgemm_acc<true, false>(
-        s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
-        [&](int k, int j) { return j < sc ? Zf[(int64_t)k * sc + j] : cz(); }, acc, sm);
+    zgemm_acc<false, false>(
+        s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
+        [&](int k, int j) { return j < nj ? Zf[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
     ztile_store(acc, [&](int i, int j, double re, double im) {
-      if (i < ni && j < sc) {
-        double2 v = Zf[(int64_t)(s + i0 + i) * sc + j];
-        v.x += re;
-        v.y += im;
-        Zf[(int64_t)(s + i0 + i) * sc + j] = v;
-      }
+      if (i < s && j < nj) Zf[(int64_t)i * sc + j0 + j] = make_double2(re, im);
     });
+    __syncthreads();
   }
-  ZTile acc;
-  ztile_zero(acc);
-  zgemm_acc<false, false>(
-      s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
-      [&](int k, int j) { return j < sc ? Zf[(int64_t)k * sc + j] : cz(); }, acc, sm);
-  ztile_store(acc, [&](int i, int j, double re, double im) {
-    if (i < s && j < sc) Zf[(int64_t)i * sc + j] = make_double2(re, im);
-  });
 }
 
 // Back substitution along the chain: X = rows of the contact's column of G^r,
@@ -341,30 +349,34 @@ __global__ void __launch_bounds__(256) k_chain_back(Ctx c, const int32_t* cls) {
       }
     }
     __syncthreads();
-    {
+    for (int j0 = 0; j0 < sc; j0 += 64) {
+      const int nj = min(64, sc - j0);
       ZTile acc;
       ztile_zero(acc);
       zgemm_acc<false, false>(
           b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
-          [&](int k, int j) { return j < sc ? Xf[(int64_t)(s + k) * sc + j] : cz(); }, acc, sm);
+          [&](int k, int j) { return j < nj ? Xf[(int64_t)(s + k) * sc + j0 + j] : cz(); }, acc, sm);
       ztile_store(acc, [&](int i, int j, double re, double im) {
-        if (i < s && j < sc) {
-          const double2 z = Zf[(int64_t)i * sc + j];
-          Xf[(int64_t)i * sc + j] = make_double2(z.x + re, z.y + im);
+        if (i < s && j < nj) {
+          const double2 z = Zf[(int64_t)i * sc + j0 + j];
+          Xf[(int64_t)i * sc + j0 + j] = make_double2(z.x + re, z.y + im);
         }
       });
     }
     __syncthreads();
     {
       const double2* sl = c.sig_l[cc] + (int64_t)(c.e0 + e) * sc * sc;
-      ZTile acc;
-      ztile_zero(acc);
-      zgemm_acc<false, false>(
-          sc, [&](int i, int k) { return i < s ? Zf[(int64_t)i * sc + k] : cz(); },
-          [&](int k, int j) { return j < sc ? sl[(int64_t)k * sc + j] : cz(); }, acc, sm);
-      ztile_store(acc, [&](int i, int j, double re, double im) {
-        if (i < s && j < sc) T[(int64_t)i * sc + j] = make_double2(re, im);
-      });
+      for (int j0 = 0; j0 < sc; j0 += 64) {
+        const int nj = min(64, sc - j0);
+        ZTile acc;
+        ztile_zero(acc);
+        zgemm_acc<false, false>(
+            sc, [&](int i, int k) { return i < s ? Zf[(int64_t)i * sc + k] : cz(); },
+            [&](int k, int j) { return j < nj ? sl[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
+        ztile_store(acc, [&](int i, int j, double re, double im) {
+          if (i < s && j < nj) T[(int64_t)i * sc + j0 + j] = make_double2(re, im);
+        });
+      }
     }
     __syncthreads();
     for (int j0 = 0; j0 < f; j0 += 64) {

@@ -22,7 +22,7 @@ struct ClusterDesc {
   int32_t pt_off;   // first internal position of the cluster
   int32_t bptr;     // B_i / relmap entries start here
   int32_t hptr0, hptr1;
-  int32_t contact;        // contact held by this cluster, or -1
+  int32_t sptr0, sptr1;   // contact self-energy entries of this front
   int32_t chain_child[2]; // per contact: child on the contact's chain, -1 if none
   int32_t chain_mask;     // bit c: the cluster is on contact c's chain
 };
@@ -41,7 +41,11 @@ struct Ctx {
   const double* hval;
   const int32_t* perm;
   const int32_t* owner;
-  const int32_t* clocal[2];  // contact site k -> local row in its cluster
+  const int32_t* cpos[2];    // contact site a -> internal position
+  const int32_t* srow;       // contact self-energy entries per front
+  const int32_t* scol;
+  const int32_t* scid;
+  const int32_t* sflat;
   int32_t nc[2];
   int32_t ncontacts;
   int32_t n;
@@ -70,7 +74,6 @@ struct RhsCtx {
   const int32_t* bidx;   // B_i as internal positions
   const double* nbar;    // cotangent of the density (caller order)
   double* part;          // [nb][n] per-energy partial gradients
-  int32_t contact_cluster[2];
 };
 
 // Launchers (kernels.hip).  nb = energies in the batch.

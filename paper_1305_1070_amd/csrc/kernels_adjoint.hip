@@ -38,8 +38,7 @@ __global__ void k_rhs_contact_ones(Ctx c, RhsCtx r, int cc) {
   double2* Y = r.Y + (int64_t)e * r.n * r.m;
   const int a = blockIdx.x * 256 + threadIdx.x;
   if (a >= c.nc[cc]) return;
-  const ClusterDesc d = c.cl[r.contact_cluster[cc]];
-  Y[(int64_t)(d.pt_off + c.clocal[cc][a]) * r.m + a] = make_double2(1.0, 0.0);
+  Y[(int64_t)c.cpos[cc][a] * r.m + a] = make_double2(1.0, 0.0);
 }
 
 // Y = Lambda conj(G_{:,c}) with Lambda = diag(nbar) in the caller's order.
@@ -154,28 +153,40 @@ __global__ void __launch_bounds__(256) k_rhs_back(Ctx c, RhsCtx r, const int32_t
   }
 }
 
-// part[e][row] += 2 Im[ sum_ab G[row,a] Sigma^<_c[a,b] X[row,b] ]
-__global__ void __launch_bounds__(256) k_vjp_accum(Ctx c, RhsCtx r, int cc) {
-  extern __shared__ double2 sl[];  // Sigma^<_c, m x m
+// T = G_{:,c} Sigma^<_c (n x m, written over Y, which is free by now):
+// 64 x 64 tiles on the FP64 matrix cores, grid = (row tiles * col tiles, nb).
+__global__ void __launch_bounds__(256) k_vjp_gemm(Ctx c, RhsCtx r, int cc) {
+  __shared__ GemmSmem sm;
   const int e = blockIdx.y;
   const int m = r.m;
+  const int ntc = (m + 63) / 64;
+  const int i0 = (blockIdx.x / ntc) * 64, j0 = (blockIdx.x % ntc) * 64;
+  const int ni = min(64, r.n - i0), nj = min(64, m - j0);
+  const double2* G = r.Gc + (int64_t)e * r.n * m;
   const double2* sg = c.sig_l[cc] + (int64_t)(c.e0 + e) * m * m;
-  for (int q = threadIdx.x; q < m * m; q += 256) sl[q] = sg[q];
-  __syncthreads();
+  double2* T = r.Y + (int64_t)e * r.n * m;
+  ZTile acc;
+  ztile_zero(acc);
+  zgemm_acc<false, false>(
+      m, [&](int i, int k) { return i < ni ? G[(int64_t)(i0 + i) * m + k] : cz(); },
+      [&](int k, int j) { return j < nj ? sg[(int64_t)k * m + j0 + j] : cz(); }, acc, sm);
+  ztile_store(acc, [&](int i, int j, double re, double im) {
+    if (i < ni && j < nj) T[(int64_t)(i0 + i) * m + j0 + j] = make_double2(re, im);
+  });
+}
+
+// part[e][row] += 2 Im[ sum_b T[row,b] X[row,b] ]
+__global__ void __launch_bounds__(256) k_vjp_accum(Ctx c, RhsCtx r, int cc) {
+  const int e = blockIdx.y;
   const int row = blockIdx.x * 256 + threadIdx.x;
   if (row >= r.n) return;
-  const double2* G = r.Gc + ((int64_t)e * r.n + row) * m;
+  const int m = r.m;
+  const double2* T = r.Y + ((int64_t)e * r.n + row) * m;
   const double2* X = r.X + ((int64_t)e * r.n + row) * m;
   double acc = 0.0;
   for (int bb = 0; bb < m; ++bb) {
-    double tr = 0.0, ti = 0.0;  // (G Sigma^<)[row, bb]
-    for (int a = 0; a < m; ++a) {
-      const double2 g = G[a], s_ = sl[a * m + bb];
-      tr += g.x * s_.x - g.y * s_.y;
-      ti += g.x * s_.y + g.y * s_.x;
-    }
-    const double2 x = X[bb];
-    acc += tr * x.y + ti * x.x;  // Im[(tr + i ti)(x.x + i x.y)]
+    const double2 t = T[bb], x = X[bb];
+    acc += t.x * x.y + t.y * x.x;  // Im[(t.x + i t.y)(x.x + i x.y)]
   }
   r.part[(int64_t)e * r.n + row] += 2.0 * acc;
 }
@@ -223,8 +234,9 @@ void launch_rhs_back(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl,
   if (ncl > 0) hipLaunchKernelGGL(k_rhs_back, dim3(ncl, nb), dim3(256), 0, st, c, r, cls);
 }
 void launch_vjp_accum(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_vjp_accum, dim3((r.n + 255) / 256, nb), dim3(256),
-                     (size_t)r.m * r.m * sizeof(double2), st, c, r, cc);
+  const int tiles = ((r.n + 63) / 64) * ((r.m + 63) / 64);
+  hipLaunchKernelGGL(k_vjp_gemm, dim3(tiles, nb), dim3(256), 0, st, c, r, cc);
+  hipLaunchKernelGGL(k_vjp_accum, dim3((r.n + 255) / 256, nb), dim3(256), 0, st, c, r, cc);
 }
 void launch_zero(double* p, int64_t count, hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count);

@@ -72,18 +72,14 @@ __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
     Fi[r * SLD + r] += c.eta;
   }
   __syncthreads();
-  if (d.contact >= 0) {
-    const int cc = d.contact, nc = c.nc[cc];
-    const double2* sg = c.sig_r[cc] + (int64_t)(c.e0 + e) * nc * nc;
-    const int32_t* loc = c.clocal[cc];
-    for (int q = t; q < nc * nc; q += NT) {
-      const int a = q / nc, bb = q - a * nc;
-      const double2 sv = sg[q];
-      Fr[loc[a] * SLD + loc[bb]] -= sv.x;
-      Fi[loc[a] * SLD + loc[bb]] -= sv.y;
-    }
-    __syncthreads();
+  // contact self-energies: each entry of the front is listed once
+  for (int q = d.sptr0 + t; q < d.sptr1; q += NT) {
+    const int cc = c.scid[q], nc = c.nc[cc];
+    const double2 sv = c.sig_r[cc][(int64_t)(c.e0 + e) * nc * nc + c.sflat[q]];
+    Fr[c.srow[q] * SLD + c.scol[q]] -= sv.x;
+    Fi[c.srow[q] * SLD + c.scol[q]] -= sv.y;
   }
+  __syncthreads();
   if (c.growth && t < s) {
     double rb = 0.0;
     for (int j = s; j < f; ++j) rb += sqrt(Fr[t * SLD + j] * Fr[t * SLD + j] + Fi[t * SLD + j] * Fi[t * SLD + j]);

@@ -42,7 +42,8 @@ struct ndg_plan {
   int32_t *d_hrow = nullptr, *d_hcol = nullptr;
   double* d_hval = nullptr;
   int32_t *d_perm = nullptr, *d_owner = nullptr;
-  int32_t* d_clocal[2] = {nullptr, nullptr};
+  int32_t* d_cpos[2] = {nullptr, nullptr};
+  int32_t *d_srow = nullptr, *d_scol = nullptr, *d_scid = nullptr, *d_sflat = nullptr;
   int32_t* d_levels = nullptr;       // clusters by height
   ndg::ColItem* d_colitems = nullptr;
   ndg::UpdItem* d_upditems = nullptr;
@@ -117,9 +118,8 @@ int64_t layout(const Symbolic& sy, std::vector<ClusterDesc>& desc) {
     d.bptr = (int32_t)sy.bptr[k];
     d.hptr0 = (int32_t)sy.hptr[k];
     d.hptr1 = (int32_t)sy.hptr[k + 1];
-    d.contact = -1;
-    for (int c = 0; c < ncont; ++c)
-      if (sy.contact_cluster[c] == k) d.contact = c;
+    d.sptr0 = (int32_t)sy.sptr[k];
+    d.sptr1 = (int32_t)sy.sptr[k + 1];
     d.chain_mask = mask[k];
     const int64_t s = d.s, b = d.b, f = d.f;
     d.o_ainv = off; off = align8(off + s * s);
@@ -131,7 +131,7 @@ int64_t layout(const Symbolic& sy, std::vector<ClusterDesc>& desc) {
       d.chain_child[c] = chain_child[2 * k + c];
       d.o_zf[c] = d.o_xf[c] = d.o_t[c] = -1;
       if (c < ncont && ((mask[k] >> c) & 1)) {
-        const int64_t sc = (int64_t)sy.contact_local[c].size();
+        const int64_t sc = (int64_t)sy.contact_pos[c].size();
         d.o_zf[c] = off; off = align8(off + f * sc);
         d.o_xf[c] = off; off = align8(off + f * sc);
         d.o_t[c] = off;  off = align8(off + s * sc);
@@ -153,10 +153,11 @@ int upload(T** dst, const T* src, size_t count) {
 void free_plan(ndg_plan* p) {
   if (!p) return;
   void* ptrs[] = {p->d_cl,        p->d_relmap,   p->d_kids_ptr,   p->d_kids,       p->d_hrow,
-                  p->d_hcol,      p->d_hval,     p->d_perm,       p->d_owner,      p->d_clocal[0],
-                  p->d_clocal[1], p->d_levels,   p->d_colitems,   p->d_upditems,   p->d_chainitems,
+                  p->d_hcol,      p->d_hval,     p->d_perm,       p->d_owner,      p->d_cpos[0],
+                  p->d_cpos[1],   p->d_levels,   p->d_colitems,   p->d_upditems,   p->d_chainitems,
                   p->d_chaincls,  p->d_ws,       p->d_status,     p->d_rY,         p->d_rX,
-                  p->d_rG,        p->d_rZ,       p->d_ovec,       p->d_bidx,       p->d_part};
+                  p->d_rG,        p->d_rZ,       p->d_ovec,       p->d_bidx,       p->d_part,
+                  p->d_srow,      p->d_scol,     p->d_scid,       p->d_sflat};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& r : p->recs) {
@@ -179,7 +180,7 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
     set_error("ndg_plan_create: at most 2 contacts are supported");
     return NDG_EINVAL;
   }
-  if (sy.max_cluster > kMaxCluster) {
+  if (sy.max_cluster > kMaxCluster) {  // (contacts larger than this span a chain)
     set_error("ndg_plan_create: a cluster exceeds 64 points");
     return NDG_EINVAL;
   }
@@ -196,12 +197,11 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   p->nclusters = sy.nclusters;
   p->max_height = sy.max_height;
   p->ncontacts = (int)sy.contact_cluster.size();
-  for (int c = 0; c < p->ncontacts; ++c) p->nc[c] = (int)sy.contact_local[c].size();
+  for (int c = 0; c < p->ncontacts; ++c) p->nc[c] = (int)sy.contact_pos[c].size();
   p->ops = oc;
   p->stride = layout(sy, p->hdesc);
   p->hbidx = sy.bidx;
-  for (int k = 0; k < (int)p->hdesc.size(); ++k)
-    if (p->hdesc[k].contact >= 0 && p->hdesc[k].contact < 2) p->contact_cl[p->hdesc[k].contact] = k;
+  for (int c = 0; c < p->ncontacts && c < 2; ++c) p->contact_cl[c] = sy.contact_cluster[c];
   const int nc = sy.nclusters, H = sy.max_height;
   // schedules per height
   std::vector<int32_t> levels;
@@ -315,7 +315,11 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   rc = rc ? rc : upload(&p->d_perm, sy.perm.data(), sy.perm.size());
   rc = rc ? rc : upload(&p->d_owner, sy.owner.data(), sy.owner.size());
   for (int c = 0; c < p->ncontacts && !rc; ++c)
-    rc = upload(&p->d_clocal[c], sy.contact_local[c].data(), sy.contact_local[c].size());
+    rc = upload(&p->d_cpos[c], sy.contact_pos[c].data(), sy.contact_pos[c].size());
+  rc = rc ? rc : upload(&p->d_srow, sy.srow.data(), sy.srow.size());
+  rc = rc ? rc : upload(&p->d_scol, sy.scol.data(), sy.scol.size());
+  rc = rc ? rc : upload(&p->d_scid, sy.scid.data(), sy.scid.size());
+  rc = rc ? rc : upload(&p->d_sflat, sy.sflat.data(), sy.sflat.size());
   rc = rc ? rc : upload(&p->d_levels, levels.data(), levels.size());
   rc = rc ? rc : upload(&p->d_colitems, cols.data(), cols.size());
   rc = rc ? rc : upload(&p->d_upditems, upds.data(), upds.size());
@@ -441,11 +445,15 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   c.hrow = p->d_hrow;
   c.hcol = p->d_hcol;
   c.hval = p->d_hval;
+  c.srow = p->d_srow;
+  c.scol = p->d_scol;
+  c.scid = p->d_scid;
+  c.sflat = p->d_sflat;
   c.perm = p->d_perm;
   c.owner = p->d_owner;
   c.ncontacts = p->ncontacts;
   for (int q = 0; q < 2; ++q) {
-    c.clocal[q] = p->d_clocal[q];
+    c.cpos[q] = p->d_cpos[q];
     c.nc[q] = p->nc[q];
     c.sig_r[q] = q < p->ncontacts ? reinterpret_cast<const double2*>(sig_r[q]) : nullptr;
     c.sig_l[q] = q < p->ncontacts ? reinterpret_cast<const double2*>(sig_less[q]) : nullptr;
@@ -479,7 +487,6 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   r.bidx = p->d_bidx;
   r.nbar = nbar;
   r.part = p->d_part;
-  for (int q = 0; q < 2; ++q) r.contact_cluster[q] = p->contact_cl[q];
   const int H = p->max_height;
   // profiling: an event pair around each launch, with its algorithmic work
   auto take_event = [&]() {
@@ -575,6 +582,10 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   if (hipGetLastError() != hipSuccess) { set_error("ndg_solve: kernel launch failed"); return NDG_EHIP; }
   return NDG_OK;
 }
+
+int plan_ncontacts(const ndg_plan* p) { return p->ncontacts; }
+int plan_device(const ndg_plan* p) { return p->device; }
+bool plan_profiling(const ndg_plan* p) { return p->profiling; }
 
 int plan_set_profiling(ndg_plan* p, bool enable) {
   p->profiling = enable;

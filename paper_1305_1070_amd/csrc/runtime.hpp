@@ -29,6 +29,9 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
              ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
              const double* nbar, double* vbar, int prec, void* stream);
 int plan_enable_adjoint(ndg_plan* plan);
+int plan_ncontacts(const ndg_plan* plan);
+int plan_device(const ndg_plan* plan);
+bool plan_profiling(const ndg_plan* plan);
 int plan_status(ndg_plan* plan, int32_t* code, int32_t* energy, int32_t* cluster);
 int plan_set_profiling(ndg_plan* plan, bool enable);
 int plan_profile(ndg_plan* plan, int capacity, ndg_kernel_stat* out, int32_t* count);

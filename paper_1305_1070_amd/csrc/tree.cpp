@@ -4,9 +4,11 @@
 //   1. clusters of one level do not interact, so they are processed
 //      independently;
 //   2. separators are small and leaves small enough to invert.
-// A contact's sites are coupled densely by its self-energy and Sigma^< is
-// block diagonal over clusters (Section 3.1), so each contact lies inside one
-// cluster.  With dense contact layers the tree keeps each contact as its own
+// A contact's sites are coupled densely by its self-energy; Section 3.1
+// takes Sigma^< block diagonal over clusters, so each contact lies inside one
+// cluster, or, when it is larger than the largest cluster, inside one
+// parent-child chain of clusters (the G^< source is then still formed along
+// that chain).  With dense contact layers the tree keeps each contact as its own
 // cluster below the separators (Section 3.2, Fig. 8 and the appendix, where
 // the dense blocks A_11 and A_44 are leaves); variant trees give the layer
 // chain of Fig. 6 (which reproduces RGF) and the contacts-in-root partition
@@ -14,6 +16,7 @@
 #include "tree.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -79,15 +82,6 @@ struct Builder {
   // points (top of the chain first).  Returns the bottom cluster.
   int add_chain(std::vector<int32_t> pts, int parent) {
     if (pts.empty()) return parent;
-    // contacts must not be split across clusters
-    if ((int)pts.size() > opt.max_cluster) {
-      for (int32_t v : pts)
-        if (contact_of[v] >= 0) {
-          err = "a contact larger than the maximum cluster size cannot stay in one cluster";
-          failed = true;
-          return parent;
-        }
-    }
     // order points along their longest extent so chain pieces are compact
     if (coords && pts.size() > 1) {
       double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -532,16 +526,48 @@ int build_symbolic(int64_t n, const int64_t* rowptr, const int32_t* col, const d
     sy.hptr[k + 1] = (int64_t)sy.hrow.size();
   }
   // ---- contacts -----------------------------------------------------------
+  // A contact lies in one cluster, or (when larger than max_cluster) in a
+  // parent-child chain of clusters; its self-energy entries are placed in the
+  // front of the lower cluster of each pair.
+  auto front_pos = [&](int k, int32_t nw) -> int32_t {
+    if (nw >= sy.cl_off[k] && nw < sy.cl_off[k + 1]) return nw - sy.cl_off[k];
+    auto b0 = sy.bidx.begin() + sy.bptr[k], b1 = sy.bidx.begin() + sy.bptr[k + 1];
+    auto it = std::lower_bound(b0, b1, nw);
+    if (it == b1 || *it != nw) return -1;
+    return sy.s(k) + (int32_t)(it - b0);
+  };
+  std::vector<std::vector<std::array<int32_t, 4>>> sent(nc);
   for (int c = 0; c < ncontacts; ++c) {
-    int own = sy.owner[sy.iperm[B.contacts[c][0]]];
-    std::vector<int32_t> loc;
-    for (int32_t v : B.contacts[c]) {
-      int32_t nw = sy.iperm[v];
-      if (sy.owner[nw] != own) { err = "contact split across clusters"; return TREE_ECONTACT; }
-      loc.push_back(nw - sy.cl_off[own]);
+    const auto& cs = B.contacts[c];
+    const int ncs = (int)cs.size();
+    std::vector<int32_t> pos(ncs), own(ncs);
+    int low = nc;
+    for (int a = 0; a < ncs; ++a) {
+      pos[a] = sy.iperm[cs[a]];
+      own[a] = sy.owner[pos[a]];
+      low = std::min(low, own[a]);
     }
-    sy.contact_cluster.push_back(own);
-    sy.contact_local.push_back(loc);
+    for (int a = 0; a < ncs; ++a)
+      if (own[a] != low && !is_ancestor(own[a], low)) { err = "contact split across unrelated clusters"; return TREE_ECONTACT; }
+    for (int a = 0; a < ncs; ++a)
+      for (int b = 0; b < ncs; ++b) {
+        const int k = std::min(own[a], own[b]);  // post-order: the lower cluster has the smaller id
+        const int32_t r = front_pos(k, pos[a]), q = front_pos(k, pos[b]);
+        if (r < 0 || q < 0) { err = "internal: contact coupling outside a front"; return TREE_EINVAL; }
+        sent[k].push_back({r, q, c, a * ncs + b});
+      }
+    sy.contact_cluster.push_back(low);
+    sy.contact_pos.push_back(pos);
+  }
+  sy.sptr.assign(nc + 1, 0);
+  for (int k = 0; k < nc; ++k) {
+    for (const auto& en : sent[k]) {
+      sy.srow.push_back(en[0]);
+      sy.scol.push_back(en[1]);
+      sy.scid.push_back(en[2]);
+      sy.sflat.push_back(en[3]);
+    }
+    sy.sptr[k + 1] = (int64_t)sy.srow.size();
   }
   // ---- levels ---------------------------------------------------------------
   sy.max_height = 0;
@@ -578,7 +604,7 @@ OpCounts count_ops(const Symbolic& sy, bool diag_only_leaves) {
     oc.gl_diag += d;
   }
   for (size_t c = 0; c < sy.contact_cluster.size(); ++c) {
-    double sc = (double)sy.contact_local[c].size();
+    double sc = (double)sy.contact_pos[c].size();
     for (int k = sy.contact_cluster[c]; k >= 0; k = sy.parent[k]) {
       double s = sy.s(k), b = sy.b(k);
       // forward substitution, D^{-1}, back substitution, W and initial P

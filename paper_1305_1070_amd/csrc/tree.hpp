@@ -43,10 +43,16 @@ struct Symbolic {
   std::vector<int32_t> bidx;    // new indices, ascending
   std::vector<int32_t> relmap;  // for each entry of bidx: position in the parent's front
   std::vector<int32_t> owner;   // owner[new index] = cluster id
-  // contacts: the cluster holding each contact, and each contact site's
-  // position inside that cluster (site order as given by the caller)
+  // contacts: the lowest cluster holding sites of each contact (a contact
+  // larger than max_cluster spans a parent-child chain of clusters), and each
+  // contact site's internal position (site order as given by the caller)
   std::vector<int32_t> contact_cluster;
-  std::vector<std::vector<int32_t>> contact_local;
+  std::vector<std::vector<int32_t>> contact_pos;
+  // contact self-energy entries per front: entry (a, b) of contact c goes to
+  // the front of the lower of the clusters owning sites a and b, at front
+  // positions (srow, scol); sflat = a * nc + b
+  std::vector<int64_t> sptr;
+  std::vector<int32_t> srow, scol, scid, sflat;
   // H in the new ordering, per cluster: entries of rows of cluster i whose
   // column lies in the front [i, B_i]: (local row, front column, value)
   std::vector<int64_t> hptr;

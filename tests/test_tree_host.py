@@ -83,7 +83,7 @@ def test_partition_rules_tube_and_graph_only():
     _check_partition(dev, sym.arrays())
 
 
-def test_rejects_nonsymmetric_h_and_oversized_contact():
+def test_rejects_nonsymmetric_h_and_overlapping_contacts():
     dev = devices.fd2d(6, 4)
     val = dev.val.copy()
     # break symmetry of one off-diagonal value
@@ -92,10 +92,6 @@ def test_rejects_nonsymmetric_h_and_oversized_contact():
     with pytest.raises(ndg.NdgError) as ei:
         ndg.analyze(dev.n, dev.rowptr, dev.col, val, dev.contacts, dev.coords)
     assert ei.value.code == -2
-    big = devices.fd2d(6, 80)
-    with pytest.raises(ndg.NdgError) as ei:
-        ndg.analyze(big.n, big.rowptr, big.col, big.val, big.contacts, big.coords)
-    assert ei.value.code == -3
     with pytest.raises(ndg.NdgError):
         ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, [dev.contacts[0], dev.contacts[0]], dev.coords)
 
@@ -133,3 +129,40 @@ def test_workspace_and_info_superlattice():
     assert info["n"] == 65536 and info["max_cluster"] <= 64
     assert info["ops_total"] < 0.2 * info["ops_rgf_equiv"]
     assert 0 < info["workspace_bytes_per_energy"] < 2e9
+
+
+@pytest.mark.parametrize("width", [96, 128])
+def test_wide_contact_spans_a_chain_of_clusters(width):
+    """A contact wider than the largest cluster (64) is split over a
+    parent-child chain of clusters; the partition rules still hold."""
+    dev = devices.fd2d(40, width)
+    sym, info, arr = _tree(dev, leaf_max=32)
+    _check_partition_chain(dev, arr)
+    assert info["max_cluster"] <= 64
+
+
+def _check_partition_chain(dev, arr):
+    perm, cl_off, parent = arr["perm"], arr["cl_off"], arr["parent"]
+    iperm = np.empty(dev.n, np.int64)
+    iperm[perm] = np.arange(dev.n)
+    owner = np.searchsorted(cl_off, np.arange(dev.n), side="right") - 1
+    for cs in dev.contacts:
+        owners = sorted(set(owner[iperm[cs]].tolist()))
+        low = owners[0]
+        anc = []
+        p = low
+        while p >= 0:
+            anc.append(p)
+            p = parent[p]
+        assert all(o in anc for o in owners)
+    h = dev.scipy_h().tocoo()
+    ancs = []
+    for c in range(len(cl_off) - 1):
+        a, p = set(), parent[c]
+        while p >= 0:
+            a.add(int(p))
+            p = parent[p]
+        ancs.append(a)
+    for i, j in zip(h.row, h.col):
+        ci, cj = owner[iperm[i]], owner[iperm[j]]
+        assert ci == cj or cj in ancs[ci] or ci in ancs[cj]
