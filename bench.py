@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false")
     ap.add_argument("--cpu-sample", type=int, default=32,
                     help="energies of the CPU oracle timing sample (0 disables it)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy, the reference kernel for scaling "
+                         "hardware byte counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -182,6 +185,19 @@ def main():
                "ms_per_step": ms_adj}
         del pa
 
+    copy_cal = None
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=cuda).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        dst.copy_(src)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        copy_cal = {"bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8,
+                    "ms": ev0.elapsed_time(ev1)}
+        del src, dst
+
     # dominant kernel and its roofline
     dom = max(stats, key=lambda r: r["ms"])
     t_dom = dom["ms"] / 1e3
@@ -245,6 +261,7 @@ def main():
         "parity_sample": parity,
         "kernels": kernels,
         "status": [status, status2],
+        "copy_calibration": copy_cal,
         "wall_s_timed": wall,
     }
     print(json.dumps(line), flush=True)

@@ -203,8 +203,10 @@ class Symbolic:
         return ndg_symbolic_arrays(self.handle)
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib._lib is not None:
-            _lib._lib.ndg_symbolic_destroy(self.handle)
+        # at interpreter exit the module globals may already be gone
+        lib = getattr(_lib, "_lib", None) if _lib is not None else None
+        if getattr(self, "handle", None) and lib is not None:
+            lib.ndg_symbolic_destroy(self.handle)
             self.handle = None
 
 
@@ -331,8 +333,9 @@ class Plan:
         return ndg_plan_export_block(self.handle, which, energy, cluster, cnt).reshape(shape)
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib._lib is not None:
-            _lib._lib.ndg_plan_destroy(self.handle)
+        lib = getattr(_lib, "_lib", None) if _lib is not None else None
+        if getattr(self, "handle", None) and lib is not None:
+            lib.ndg_plan_destroy(self.handle)
             self.handle = None
 
 
@@ -379,8 +382,9 @@ class Batch:
         return list(self._outs)
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib._lib is not None:
-            _lib._lib.ndg_batch_destroy(self.handle)
+        lib = getattr(_lib, "_lib", None) if _lib is not None else None
+        if getattr(self, "handle", None) and lib is not None:
+            lib.ndg_batch_destroy(self.handle)
             self.handle = None
 
 

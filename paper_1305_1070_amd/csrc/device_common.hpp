@@ -265,6 +265,139 @@ struct Gemm<false> {
   __device__ static void store(const Tile& t, FS fs) { ztile32_store_t<TM>(t, fs); }
 };
 
+// ---------------------------------------------------------------------------
+// Gauss-Jordan elimination with partial pivoting on a matrix held in
+// registers: thread (jt, i0) = (t % JS, t / JS) owns rows i0 + RS*m and
+// columns jt + JS*q.  Pivots are taken in place (no row interchanges): step
+// k sweeps column k with the largest unused row p_k among the first s rows,
+// so after s steps the entry in storage row p_k, column c < s is
+// (A^{-1})[k][p_c], rows and columns >= s keep their meaning, and
+//     [[A_ii, A_iB], [A_Bi, A_BB]]  ->  [[A_ii^{-1} (permuted), A_ii^{-1} A_iB (rows permuted)],
+//                                        [-A_Bi A_ii^{-1},      A_BB - A_Bi A_ii^{-1} A_iB]].
+// Only the pivot column and pivot row pass through LDS (double-buffered, so
+// each step needs two barriers).
+// ---------------------------------------------------------------------------
+template <int SF, int NT, int JS>
+struct RegGJ {
+  static constexpr int RS = NT / JS;
+  static constexpr int NR = (SF + RS - 1) / RS;
+  static constexpr int NC = (SF + JS - 1) / JS;
+  static_assert(NT % JS == 0, "thread grid");
+  static_assert(NR <= 32, "row mask");
+  struct Smem {
+    double2 col[2][NR * RS];
+    double2 row[2][NC * JS];
+    double2 val[2][RS];  // each row group's candidate pivot value
+    double mag[2][RS];
+    int who[2][RS];
+    int piv[SF], pinv[SF];
+  };
+  double re[NR][NC], im[NR][NC];
+  int jt, i0;
+
+  __device__ RegGJ(int t) : jt(t % JS), i0(t / JS) {}
+  __device__ int row(int m) const { return i0 + RS * m; }
+  __device__ int col(int q) const { return jt + JS * q; }
+
+  // s pivot steps; returns false if a pivot was exactly zero.  Per step:
+  // the owners of column k publish it with their best unused row; after a
+  // barrier every thread picks the pivot row p and its value, the owners of
+  // row p publish it; after a second barrier every thread reads the values
+  // it needs at once and updates its tile without branches.
+  __device__ bool run(Smem& sm, int s) {
+    const int t = i0 * JS + jt;
+    uint32_t used = 0;
+    bool ok = true;
+    for (int k = 0; k < s; ++k) {
+      const int buf = k & 1;
+      if (jt == k % JS) {
+        const int qk = k / JS;
+        double best = -1.0, br = 0.0, bi = 0.0;
+        int brow = 0x7fffffff;
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+          double vr = 0.0, vi = 0.0;
+#pragma unroll
+          for (int q = 0; q < NC; ++q)
+            if (q == qk) { vr = re[m][q]; vi = im[m][q]; }
+          const int i = row(m);
+          sm.col[buf][i] = make_double2(vr, vi);
+          // the first unused row is always taken, so a NaN column still
+          // names a valid row
+          const double a = fabs(vr) + fabs(vi);
+          const bool take = i < s && !((used >> m) & 1u) && (a > best || brow == 0x7fffffff);
+          best = take ? a : best;
+          brow = take ? i : brow;
+          br = take ? vr : br;
+          bi = take ? vi : bi;
+        }
+        sm.mag[buf][i0] = best;
+        sm.who[buf][i0] = brow;
+        sm.val[buf][i0] = make_double2(br, bi);
+      }
+      __syncthreads();
+      // groups whose rows are all used report 0x7fffffff; at least one
+      // group (k < s) reports a row below s
+      int p = 0x7fffffff, pg = 0;
+      double pm = -1.0;
+#pragma unroll
+      for (int r = 0; r < RS; ++r) {
+        const double om = sm.mag[buf][r];
+        const int orow = sm.who[buf][r];
+        const bool take = orow != 0x7fffffff && (p == 0x7fffffff || om > pm || (om == pm && orow < p));
+        pm = take ? om : pm;
+        p = take ? orow : p;
+        pg = take ? r : pg;
+      }
+      const double2 a = sm.val[buf][pg];
+      const int mp = p / RS;
+      const bool own_p = i0 == p % RS;
+      if (own_p) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          double vr = 0.0, vi = 0.0;
+#pragma unroll
+          for (int m = 0; m < NR; ++m)
+            if (m == mp) { vr = re[m][q]; vi = im[m][q]; }
+          sm.row[buf][col(q)] = make_double2(vr, vi);
+        }
+      }
+      if (t == 0) { sm.piv[k] = p; sm.pinv[p] = k; }
+      const double den = a.x * a.x + a.y * a.y;
+      double dr = 0.0, di = 0.0;
+      if (den > 0.0) { dr = a.x / den; di = -a.y / den; }
+      else ok = false;
+      __syncthreads();
+      double2 ck[NR], pr[NC];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) pr[q] = sm.row[buf][col(q)];
+#pragma unroll
+      for (int m = 0; m < NR; ++m) ck[m] = sm.col[buf][row(m)];
+      // row p:          M[p][j] <- M[p][j] d  (j != k),  d  (j == k)
+      // column k:       M[i][k] <- -M[i][k] d
+      // everything else M[i][j] <- M[i][j] - M[i][k] M[p][j] d
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const bool jk = col(q) == k;
+        const double xr = jk ? dr : pr[q].x * dr - pr[q].y * di;
+        const double xi = jk ? di : pr[q].x * di + pr[q].y * dr;
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+          const bool ip = row(m) == p;
+          const double cr = ip ? 0.0 : ck[m].x, ci = ip ? 0.0 : ck[m].y;
+          const double br = ip ? xr : (jk ? 0.0 : re[m][q]);
+          const double bi = ip ? xi : (jk ? 0.0 : im[m][q]);
+          re[m][q] = br - (cr * xr - ci * xi);
+          im[m][q] = bi - (cr * xi + ci * xr);
+        }
+      }
+      if (own_p) used |= 1u << mp;
+    }
+    __syncthreads();  // piv / pinv complete
+    return ok;
+  }
+};
+
 __device__ inline void raise_fault(int32_t* status, int code, int e, int cl) {
   if (atomicCAS(status, 0, code) == 0) {
     atomicExch(status + 1, e);

@@ -84,110 +84,60 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
 // ---------------------------------------------------------------------------
 template <int SM, int NT>
 __global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
-  __shared__ double Mr[SM][SM + 1], Mi[SM][SM + 1];
-  __shared__ double prr[SM], pri[SM], pcr[SM], pci[SM];
-  __shared__ int piv[SM];
-  __shared__ int sp;
+  using GJ = RegGJ<SM, NT, SM>;
+  __shared__ typename GJ::Smem sm;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
   const ClusterDesc d = c.cl[cl];
   double2* S = slab(c, e);
   const double2* F = S + d.o_fg;
   const int f = d.f, s = d.s;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int q = t; q < s * s; q += NT) {
-    const int i = q / s, j = q % s;
-    const double2 v = F[(int64_t)i * f + j];
-    Mr[i][j] = v.x;
-    Mi[i][j] = v.y;
-  }
-  __syncthreads();
-  bool singular = false;
-  for (int k = 0; k < s; ++k) {
-    if (w == 0) {
-      const int row = k + lane;
-      double mag = -1.0;
-      if (row < s) mag = fabs(Mr[row][k]) + fabs(Mi[row][k]);
-      int arg = row;
+  const int t = threadIdx.x;
+  GJ g(t);
+#pragma unroll
+  for (int m = 0; m < GJ::NR; ++m)
+#pragma unroll
+    for (int q = 0; q < GJ::NC; ++q) {
+      const int i = g.row(m), j = g.col(q);
+      const double2 v = (i < s && j < s) ? F[(int64_t)i * f + j] : cz();
+      g.re[m][q] = v.x;
+      g.im[m][q] = v.y;
+    }
+  const bool ok = g.run(sm, s);
+  if (!ok && t == 0) raise_fault(c.status, -4, c.e0 + e, cl);
+  double2* Ainv = S + d.o_ainv;
+#pragma unroll
+  for (int m = 0; m < GJ::NR; ++m)
+#pragma unroll
+    for (int q = 0; q < GJ::NC; ++q) {
+      const int i = g.row(m), j = g.col(q);
+      if (i < s && j < s)
+        Ainv[(int64_t)sm.pinv[i] * s + sm.piv[j]] = make_double2(g.re[m][q], g.im[m][q]);
+    }
+  if (c.growth && d.b > 0) {
+    // ||A_ii^{-1}||_inf ||A_iB||_inf from the stored inverse, one row per lane
+    __threadfence_block();
+    __syncthreads();
+    if (t < 64) {
+      double ru = 0.0, rb = 0.0;
+      if (t < s) {
+        for (int j = 0; j < s; ++j) {
+          const double2 v = Ainv[(int64_t)t * s + j];
+          ru += sqrt(v.x * v.x + v.y * v.y);
+        }
+        const double2* row = F + (int64_t)t * f + s;
+        for (int j = 0; j < d.b; ++j) rb += sqrt(row[j].x * row[j].x + row[j].y * row[j].y);
+      }
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
-        const double om = __shfl_xor(mag, off);
-        const int oa = __shfl_xor(arg, off);
-        if (om > mag || (om == mag && oa < arg)) { mag = om; arg = oa; }
+        ru = fmax(ru, __shfl_xor(ru, off));
+        rb = fmax(rb, __shfl_xor(rb, off));
       }
-      if (lane == 0) { sp = arg; piv[k] = arg; }
+      // non-negative doubles order like their bit patterns
+      if (t == 0)
+        atomicMax(reinterpret_cast<unsigned long long*>(c.growth + c.e0 + e),
+                  (unsigned long long)__double_as_longlong(ru * rb));
     }
-    __syncthreads();
-    const int p = sp;
-    if (p != k && t < s) {
-      double tr = Mr[k][t], ti = Mi[k][t];
-      Mr[k][t] = Mr[p][t]; Mi[k][t] = Mi[p][t];
-      Mr[p][t] = tr; Mi[p][t] = ti;
-    }
-    __syncthreads();
-    if (t < s) {
-      prr[t] = Mr[k][t]; pri[t] = Mi[k][t];
-      pcr[t] = Mr[t][k]; pci[t] = Mi[t][k];
-    }
-    __syncthreads();
-    const double ar = prr[k], ai = pri[k];
-    const double den = ar * ar + ai * ai;
-    double dr = 0.0, di = 0.0;
-    if (den > 0.0) { dr = ar / den; di = -ai / den; }
-    else singular = true;
-    for (int q = t; q < s * s; q += NT) {
-      const int i = q / s, j = q % s;
-      // row k scaled by d = 1 / a_kk
-      const double rr = prr[j] * dr - pri[j] * di, ri = prr[j] * di + pri[j] * dr;
-      if (i == k) {
-        if (j == k) { Mr[i][j] = dr; Mi[i][j] = di; }
-        else { Mr[i][j] = rr; Mi[i][j] = ri; }
-      } else {
-        const double fr = pcr[i], fi = pci[i];
-        if (j == k) {
-          Mr[i][j] = -(fr * dr - fi * di);
-          Mi[i][j] = -(fr * di + fi * dr);
-        } else {
-          Mr[i][j] -= fr * rr - fi * ri;
-          Mi[i][j] -= fr * ri + fi * rr;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // undo the row interchanges on the columns, last interchange first
-  for (int k = s - 1; k >= 0; --k) {
-    const int p = piv[k];
-    if (p != k && t < s) {
-      double tr = Mr[t][k], ti = Mi[t][k];
-      Mr[t][k] = Mr[t][p]; Mi[t][k] = Mi[t][p];
-      Mr[t][p] = tr; Mi[t][p] = ti;
-    }
-    __syncthreads();
-  }
-  if (singular && t == 0) raise_fault(c.status, -4, c.e0 + e, cl);
-  double2* Ainv = S + d.o_ainv;
-  for (int q = t; q < s * s; q += NT) {
-    const int i = q / s, j = q % s;
-    Ainv[q] = make_double2(Mr[i][j], Mi[i][j]);
-  }
-  if (c.growth && w == 0 && d.b > 0) {
-    // ||A_ii^{-1}||_inf ||A_iB||_inf, one row per lane, then wave maxima
-    double ru = 0.0, rb = 0.0;
-    if (lane < s) {
-      for (int j = 0; j < s; ++j) ru += sqrt(Mr[lane][j] * Mr[lane][j] + Mi[lane][j] * Mi[lane][j]);
-      const double2* row = F + (int64_t)lane * f + s;
-      for (int j = 0; j < d.b; ++j) rb += sqrt(row[j].x * row[j].x + row[j].y * row[j].y);
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      ru = fmax(ru, __shfl_xor(ru, off));
-      rb = fmax(rb, __shfl_xor(rb, off));
-    }
-    // non-negative doubles order like their bit patterns
-    if (lane == 0)
-      atomicMax(reinterpret_cast<unsigned long long*>(c.growth + c.e0 + e),
-                (unsigned long long)__double_as_longlong(ru * rb));
   }
 }
 
@@ -534,7 +484,7 @@ void launch_assemble(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStrea
 void launch_factor(const Ctx& c, const int32_t* cls, int ncl, int nb, int cls_size, hipStream_t st) {
   if (ncl <= 0) return;
   if (cls_size <= 16) hipLaunchKernelGGL((k_factor<16, 64>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
-  else if (cls_size <= 32) hipLaunchKernelGGL((k_factor<32, 64>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
+  else if (cls_size <= 32) hipLaunchKernelGGL((k_factor<32, 128>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
   else hipLaunchKernelGGL((k_factor<64, 256>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
 }
 void launch_psi(const Ctx& c, const ColItem* it, int nit, int nb, int cls_size, hipStream_t st) {

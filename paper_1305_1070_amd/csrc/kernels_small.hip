@@ -3,10 +3,10 @@
 // (leaves and the separators just above them), and tiling their products
 // into 64 x 64 matrix-core tiles would mostly multiply padding.
 //
-// Fold: the front [[F_ii, F_iB], [F_Bi, F_BB]] is assembled in LDS and
-// reduced by s steps of Gauss-Jordan elimination with partial pivoting among
-// the rows of cluster i, applied to the whole front.  Stored in place, the
-// result is
+// Fold: the front [[F_ii, F_iB], [F_Bi, F_BB]] is assembled in LDS, moved
+// to registers and reduced by s steps of Gauss-Jordan elimination with
+// partial pivoting among the rows of cluster i, applied to the whole front.
+// The result is
 //     [[ F_ii^{-1},          F_ii^{-1} F_iB           ],
 //      [ -F_Bi F_ii^{-1},    F_BB - F_Bi F_ii^{-1} F_iB ]]
 // i.e. the pivot inverse, -Psi_{i,B}, Psi^T and the Schur contribution to the
@@ -22,20 +22,19 @@
 
 namespace ndg {
 
-template <int SF, int NT>
+template <int SF, int NT, int JS>
 __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
   constexpr int SLD = SF + 1;  // padded row length in LDS
+  using GJ = RegGJ<SF, NT, JS>;
   __shared__ double Fr[SF * SLD], Fi[SF * SLD];
-  __shared__ double prr[SF], pri[SF], pcr[SF], pci[SF];
+  __shared__ typename GJ::Smem gsm;
   __shared__ double rowb[SF];
-  __shared__ int piv[SF];
-  __shared__ int sp;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
   const ClusterDesc d = c.cl[cl];
   double2* S = slab(c, e);
   const int f = d.f, s = d.s, b = d.b;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int t = threadIdx.x;
   for (int j = t & 31; j < f; j += 32)
     for (int i = t >> 5; i < f; i += NT / 32) {
       Fr[i * SLD + j] = 0.0;
@@ -85,107 +84,62 @@ __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
     for (int j = s; j < f; ++j) rb += sqrt(Fr[t * SLD + j] * Fr[t * SLD + j] + Fi[t * SLD + j] * Fi[t * SLD + j]);
     rowb[t] = rb;
   }
-  bool singular = false;
-  for (int k = 0; k < s; ++k) {
-    if (w == 0) {
-      const int row = k + lane;
-      double mag = -1.0;
-      if (row < s) mag = fabs(Fr[row * SLD + k]) + fabs(Fi[row * SLD + k]);
-      int arg = row;
+  // the front into registers, s elimination steps there
+  GJ g(t);
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double om = __shfl_xor(mag, off);
-        const int oa = __shfl_xor(arg, off);
-        if (om > mag || (om == mag && oa < arg)) { mag = om; arg = oa; }
-      }
-      if (lane == 0) { sp = arg; piv[k] = arg; }
+  for (int m = 0; m < GJ::NR; ++m)
+#pragma unroll
+    for (int q = 0; q < GJ::NC; ++q) {
+      const int i = g.row(m), j = g.col(q);
+      const bool in = i < f && j < f;
+      g.re[m][q] = in ? Fr[i * SLD + j] : 0.0;
+      g.im[m][q] = in ? Fi[i * SLD + j] : 0.0;
     }
-    __syncthreads();
-    const int p = sp;
-    if (p != k && t < f) {
-      const double tr = Fr[k * SLD + t], ti = Fi[k * SLD + t];
-      Fr[k * SLD + t] = Fr[p * SLD + t];
-      Fi[k * SLD + t] = Fi[p * SLD + t];
-      Fr[p * SLD + t] = tr;
-      Fi[p * SLD + t] = ti;
-    }
-    __syncthreads();
-    if (t < f) {
-      prr[t] = Fr[k * SLD + t]; pri[t] = Fi[k * SLD + t];
-      pcr[t] = Fr[t * SLD + k]; pci[t] = Fi[t * SLD + k];
-    }
-    __syncthreads();
-    const double ar = prr[k], ai = pri[k];
-    const double den = ar * ar + ai * ai;
-    double dr = 0.0, di = 0.0;
-    if (den > 0.0) { dr = ar / den; di = -ai / den; }
-    else singular = true;
-    // rank-one update of the whole front: column j = lane mod 32 (+32),
-    // rows strided by NT / 32
-    for (int j = t & 31; j < f; j += 32) {
-      const double rr = prr[j] * dr - pri[j] * di, ri = prr[j] * di + pri[j] * dr;
-      for (int i = t >> 5; i < f; i += NT / 32) {
-        const int pos = i * SLD + j;
-        if (i == k) {
-          if (j == k) { Fr[pos] = dr; Fi[pos] = di; }
-          else { Fr[pos] = rr; Fi[pos] = ri; }
-        } else {
-          const double fr = pcr[i], fi = pci[i];
-          if (j == k) {
-            Fr[pos] = -(fr * dr - fi * di);
-            Fi[pos] = -(fr * di + fi * dr);
-          } else {
-            Fr[pos] -= fr * rr - fi * ri;
-            Fi[pos] -= fr * ri + fi * rr;
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // undo the row interchanges on the eliminated columns, last one first
-  for (int k = s - 1; k >= 0; --k) {
-    const int p = piv[k];
-    if (p != k && t < f) {
-      const double tr = Fr[t * SLD + k], ti = Fi[t * SLD + k];
-      Fr[t * SLD + k] = Fr[t * SLD + p];
-      Fi[t * SLD + k] = Fi[t * SLD + p];
-      Fr[t * SLD + p] = tr;
-      Fi[t * SLD + p] = ti;
-    }
-    __syncthreads();
-  }
-  if (singular && t == 0) raise_fault(c.status, -4, c.e0 + e, cl);
+  const bool ok = g.run(gsm, s);
+  if (!ok && t == 0) raise_fault(c.status, -4, c.e0 + e, cl);
   double2* Ainv = S + d.o_ainv;
   double2* Psi = S + d.o_psi;
   double2* Upd = S + d.o_upd;
-  for (int q = t; q < s * s; q += NT) {
-    const int i = q / s, j = q - i * s;
-    Ainv[q] = make_double2(Fr[i * SLD + j], Fi[i * SLD + j]);
-  }
-  for (int q = t; q < s * b; q += NT) {
-    const int i = q / b, j = q - i * b;
-    Psi[q] = make_double2(-Fr[i * SLD + s + j], -Fi[i * SLD + s + j]);
-  }
-  for (int q = t; q < b * b; q += NT) {
-    const int i = q / b, j = q - i * b;
-    Upd[q] = make_double2(Fr[(s + i) * SLD + s + j], Fi[(s + i) * SLD + s + j]);
-  }
-  if (c.growth && w == 0 && b > 0) {
-    double ru = 0.0, rb = 0.0;
-    if (lane < s) {
-      for (int j = 0; j < s; ++j)
-        ru += sqrt(Fr[lane * SLD + j] * Fr[lane * SLD + j] + Fi[lane * SLD + j] * Fi[lane * SLD + j]);
-      rb = rowb[lane];
-    }
+  // storage row p_k holds row k of [A_ii^{-1}, A_ii^{-1} A_iB]; columns
+  // below s are permuted the same way
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      ru = fmax(ru, __shfl_xor(ru, off));
-      rb = fmax(rb, __shfl_xor(rb, off));
+  for (int m = 0; m < GJ::NR; ++m)
+#pragma unroll
+    for (int q = 0; q < GJ::NC; ++q) {
+      const int i = g.row(m), j = g.col(q);
+      const double vr = g.re[m][q], vi = g.im[m][q];
+      if (i < s) {
+        if (j < s) Ainv[gsm.pinv[i] * s + gsm.piv[j]] = make_double2(vr, vi);
+        else if (j < f) Psi[gsm.pinv[i] * b + (j - s)] = make_double2(-vr, -vi);
+      } else if (i < f && j >= s && j < f) {
+        Upd[(i - s) * b + (j - s)] = make_double2(vr, vi);
+      }
     }
-    if (lane == 0)
-      atomicMax(reinterpret_cast<unsigned long long*>(c.growth + c.e0 + e),
-                (unsigned long long)__double_as_longlong(ru * rb));
+  if (c.growth && b > 0) {
+    // ||A_ii^{-1}||_inf from the register tiles, via the (now free) LDS front
+#pragma unroll
+    for (int m = 0; m < GJ::NR; ++m)
+#pragma unroll
+      for (int q = 0; q < GJ::NC; ++q) {
+        const int i = g.row(m), j = g.col(q);
+        if (i < s && j < s) Fr[i * SLD + j] = sqrt(g.re[m][q] * g.re[m][q] + g.im[m][q] * g.im[m][q]);
+      }
+    __syncthreads();
+    if (t < 64) {
+      double ru = 0.0, rb = 0.0;
+      if (t < s) {
+        for (int j = 0; j < s; ++j) ru += Fr[t * SLD + j];
+        rb = rowb[t];
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        ru = fmax(ru, __shfl_xor(ru, off));
+        rb = fmax(rb, __shfl_xor(rb, off));
+      }
+      if (t == 0)
+        atomicMax(reinterpret_cast<unsigned long long*>(c.growth + c.e0 + e),
+                  (unsigned long long)__double_as_longlong(ru * rb));
+    }
   }
 }
 
@@ -266,9 +220,9 @@ __global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls)
 
 void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int front_size, hipStream_t st) {
   if (ncl <= 0) return;
-  if (front_size <= 32) hipLaunchKernelGGL((k_fold_small<32, 64>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
-  else if (front_size <= 48) hipLaunchKernelGGL((k_fold_small<48, 128>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
-  else hipLaunchKernelGGL((k_fold_small<64, 256>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+  if (front_size <= 32) hipLaunchKernelGGL((k_fold_small<32, 64, 32>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
+  else if (front_size <= 48) hipLaunchKernelGGL((k_fold_small<48, 128, 16>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
+  else hipLaunchKernelGGL((k_fold_small<64, 256, 64>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
 }
 
 void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, size_t lds_bytes,
