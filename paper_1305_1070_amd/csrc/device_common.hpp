@@ -274,22 +274,26 @@ struct Gemm<false> {
 // (A^{-1})[k][p_c], rows and columns >= s keep their meaning, and
 //     [[A_ii, A_iB], [A_Bi, A_BB]]  ->  [[A_ii^{-1} (permuted), A_ii^{-1} A_iB (rows permuted)],
 //                                        [-A_Bi A_ii^{-1},      A_BB - A_Bi A_ii^{-1} A_iB]].
-// Only the pivot column and pivot row pass through LDS (double-buffered, so
-// each step needs two barriers).
 // ---------------------------------------------------------------------------
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 template <int SF, int NT, int JS>
 struct RegGJ {
   static constexpr int RS = NT / JS;
   static constexpr int NR = (SF + RS - 1) / RS;
   static constexpr int NC = (SF + JS - 1) / JS;
   static_assert(NT % JS == 0, "thread grid");
-  static_assert(NR <= 32, "row mask");
+  static_assert(SF <= 64, "pivot rows are searched by one wavefront");
   struct Smem {
     double2 col[2][NR * RS];
     double2 row[2][NC * JS];
-    double2 val[2][RS];  // each row group's candidate pivot value
-    double mag[2][RS];
-    int who[2][RS];
     int piv[SF], pinv[SF];
   };
   double re[NR][NC], im[NR][NC];
@@ -300,56 +304,49 @@ struct RegGJ {
   __device__ int col(int q) const { return jt + JS * q; }
 
   // s pivot steps; returns false if a pivot was exactly zero.  Per step:
-  // the owners of column k publish it with their best unused row; after a
-  // barrier every thread picks the pivot row p and its value, the owners of
-  // row p publish it; after a second barrier every thread reads the values
-  // it needs at once and updates its tile without branches.
+  // the owners of column k publish it and clear it (its new value is
+  // -M[i][k] d); after a barrier every wavefront finds the pivot row p by a
+  // wave-wide maximum of packed (magnitude, row) keys and the owners of row
+  // p publish it; after a second barrier every thread applies
+  // M[i][j] -= M[i][k] x_j (x_j = M[p][j] d, x_k = d) to its whole tile
+  // without branches, and the owners of row p then overwrite it with x.
   __device__ bool run(Smem& sm, int s) {
-    const int t = i0 * JS + jt;
-    uint32_t used = 0;
+    const int t = i0 * JS + jt, lane = t & 63;
+    unsigned long long used = 0;
     bool ok = true;
     for (int k = 0; k < s; ++k) {
       const int buf = k & 1;
+      const int qk = k / JS;
       if (jt == k % JS) {
-        const int qk = k / JS;
-        double best = -1.0, br = 0.0, bi = 0.0;
-        int brow = 0x7fffffff;
 #pragma unroll
         for (int m = 0; m < NR; ++m) {
           double vr = 0.0, vi = 0.0;
 #pragma unroll
           for (int q = 0; q < NC; ++q)
-            if (q == qk) { vr = re[m][q]; vi = im[m][q]; }
-          const int i = row(m);
-          sm.col[buf][i] = make_double2(vr, vi);
-          // the first unused row is always taken, so a NaN column still
-          // names a valid row
-          const double a = fabs(vr) + fabs(vi);
-          const bool take = i < s && !((used >> m) & 1u) && (a > best || brow == 0x7fffffff);
-          best = take ? a : best;
-          brow = take ? i : brow;
-          br = take ? vr : br;
-          bi = take ? vi : bi;
+            if (q == qk) {
+              vr = re[m][q];
+              vi = im[m][q];
+              re[m][q] = 0.0;
+              im[m][q] = 0.0;
+            }
+          sm.col[buf][row(m)] = make_double2(vr, vi);
         }
-        sm.mag[buf][i0] = best;
-        sm.who[buf][i0] = brow;
-        sm.val[buf][i0] = make_double2(br, bi);
       }
       __syncthreads();
-      // groups whose rows are all used report 0x7fffffff; at least one
-      // group (k < s) reports a row below s
-      int p = 0x7fffffff, pg = 0;
-      double pm = -1.0;
-#pragma unroll
-      for (int r = 0; r < RS; ++r) {
-        const double om = sm.mag[buf][r];
-        const int orow = sm.who[buf][r];
-        const bool take = orow != 0x7fffffff && (p == 0x7fffffff || om > pm || (om == pm && orow < p));
-        pm = take ? om : pm;
-        p = take ? orow : p;
-        pg = take ? r : pg;
+      // key = magnitude bits (7 low bits cleared) | 64 | (63 - row): the
+      // largest |Re| + |Im| wins, ties go to the lower row; every unused row
+      // below s has a key >= 64, so p is always a valid row (a NaN column
+      // picks a NaN row)
+      unsigned long long key = 0;
+      if (lane < s && !((used >> lane) & 1ull)) {
+        const double2 v = sm.col[buf][lane];
+        const double mg = fabs(v.x) + fabs(v.y);
+        key = ((unsigned long long)__double_as_longlong(mg) & ~127ull) | 64ull |
+              (unsigned long long)(63 - lane);
       }
-      const double2 a = sm.val[buf][pg];
+      key = wave_max_u64(key);
+      const int p = 63 - (int)(key & 63ull);
+      const double2 a = sm.col[buf][p];
       const int mp = p / RS;
       const bool own_p = i0 == p % RS;
       if (own_p) {
@@ -363,6 +360,7 @@ struct RegGJ {
         }
       }
       if (t == 0) { sm.piv[k] = p; sm.pinv[p] = k; }
+      used |= 1ull << p;
       const double den = a.x * a.x + a.y * a.y;
       double dr = 0.0, di = 0.0;
       if (den > 0.0) { dr = a.x / den; di = -a.y / den; }
@@ -373,25 +371,29 @@ struct RegGJ {
       for (int q = 0; q < NC; ++q) pr[q] = sm.row[buf][col(q)];
 #pragma unroll
       for (int m = 0; m < NR; ++m) ck[m] = sm.col[buf][row(m)];
-      // row p:          M[p][j] <- M[p][j] d  (j != k),  d  (j == k)
-      // column k:       M[i][k] <- -M[i][k] d
-      // everything else M[i][j] <- M[i][j] - M[i][k] M[p][j] d
+      double xr[NC], xi[NC];
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
         const bool jk = col(q) == k;
-        const double xr = jk ? dr : pr[q].x * dr - pr[q].y * di;
-        const double xi = jk ? di : pr[q].x * di + pr[q].y * dr;
+        xr[q] = jk ? dr : pr[q].x * dr - pr[q].y * di;
+        xi[q] = jk ? di : pr[q].x * di + pr[q].y * dr;
 #pragma unroll
         for (int m = 0; m < NR; ++m) {
-          const bool ip = row(m) == p;
-          const double cr = ip ? 0.0 : ck[m].x, ci = ip ? 0.0 : ck[m].y;
-          const double br = ip ? xr : (jk ? 0.0 : re[m][q]);
-          const double bi = ip ? xi : (jk ? 0.0 : im[m][q]);
-          re[m][q] = br - (cr * xr - ci * xi);
-          im[m][q] = bi - (cr * xi + ci * xr);
+          re[m][q] -= ck[m].x * xr[q] - ck[m].y * xi[q];
+          im[m][q] -= ck[m].x * xi[q] + ck[m].y * xr[q];
         }
       }
-      if (own_p) used |= 1u << mp;
+      if (own_p) {
+#pragma unroll
+        for (int m = 0; m < NR; ++m)
+          if (m == mp) {
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+              re[m][q] = xr[q];
+              im[m][q] = xi[q];
+            }
+          }
+      }
     }
     __syncthreads();  // piv / pinv complete
     return ok;
