@@ -145,6 +145,8 @@ __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
 
 // Extraction of G^r and then G^< for one small front.  Dynamic LDS holds
 // Psi (s x b), the gathered B x B block of the parent's front and X_{i,B}.
+// A leaf's blocks are read by nobody but the epilogue, so a leaf forms and
+// stores only the diagonal of X_ii.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls) {
   extern __shared__ double2 sm[];
@@ -188,32 +190,44 @@ __global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls)
       XIB[q] = acc;
     }
     __syncthreads();
-    // X_ii = (A_ii^{-1} | P_init) + Psi X_{B,i}
-    for (int q = t; q < s * s; q += NT) {
-      const int r = q / s, j = q - r * s;
-      double2 acc;
-      if (lesser) acc = src ? X[(int64_t)r * f + j] : cz();
-      else acc = Ainv[q];
-      for (int k = 0; k < b; ++k) {
-        const double2 a = Psl[r * b + k];
-        double2 x = XIB[j * b + k];  // X_{B,i}[k][j] from X_{i,B}[j][k]
-        if (lesser) x = make_double2(-x.x, x.y);
-        acc.x += a.x * x.x - a.y * x.y;
-        acc.y += a.x * x.y + a.y * x.x;
+    // X_ii = (A_ii^{-1} | P_init) + Psi X_{B,i};  X_{B,i}[k][j] = X_{i,B}[j][k]
+    // for G^r, -conj(X_{i,B}[j][k]) for G^<
+    if (!inner) {
+      for (int r = t; r < s; r += NT) {
+        double2 acc = lesser ? (src ? X[(int64_t)r * f + r] : cz()) : Ainv[r * s + r];
+        for (int k = 0; k < b; ++k) {
+          const double2 a = Psl[r * b + k];
+          double2 x = XIB[r * b + k];
+          if (lesser) x = make_double2(-x.x, x.y);
+          acc.x += a.x * x.x - a.y * x.y;
+          acc.y += a.x * x.y + a.y * x.x;
+        }
+        X[(int64_t)r * f + r] = acc;
       }
-      X[(int64_t)r * f + j] = acc;
-    }
-    for (int q = t; q < s * b; q += NT) {
-      const int r = q / b, j = q - r * b;
-      const double2 v = XIB[q];
-      X[(int64_t)r * f + s + j] = v;
-      if (inner) X[(int64_t)(s + j) * f + r] = lesser ? make_double2(-v.x, v.y) : v;
-    }
-    if (inner)
+    } else {
+      for (int q = t; q < s * s; q += NT) {
+        const int r = q / s, j = q - r * s;
+        double2 acc = lesser ? (src ? X[(int64_t)r * f + j] : cz()) : Ainv[q];
+        for (int k = 0; k < b; ++k) {
+          const double2 a = Psl[r * b + k];
+          double2 x = XIB[j * b + k];
+          if (lesser) x = make_double2(-x.x, x.y);
+          acc.x += a.x * x.x - a.y * x.y;
+          acc.y += a.x * x.y + a.y * x.x;
+        }
+        X[(int64_t)r * f + j] = acc;
+      }
+      for (int q = t; q < s * b; q += NT) {
+        const int r = q / b, j = q - r * b;
+        const double2 v = XIB[q];
+        X[(int64_t)r * f + s + j] = v;
+        X[(int64_t)(s + j) * f + r] = lesser ? make_double2(-v.x, v.y) : v;
+      }
       for (int q = t; q < b * b; q += NT) {
         const int k = q / b, j = q - k * b;
         X[(int64_t)(s + k) * f + s + j] = XBB[q];
       }
+    }
     __syncthreads();
   }
 }
