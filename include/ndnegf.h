@@ -216,11 +216,14 @@ ndg_status ndg_density_vjp(ndg_plan* plan, int32_t nE, const double* E, double e
 /* ---------------------------------------------------------------------------
  * Batched solve of several devices (plans) of uneven sizes in one launch.
  *
- * ndg_batch_solve captures, on its first call with a given argument set, the
- * solves of all plans into one HIP graph -- one branch per device, so the
- * devices' level-by-level kernels run concurrently -- and launches it with a
- * single hipGraphLaunch on `stream`; later calls with identical arguments
- * replay the instantiated graph.  Each args[i] holds the arguments ndg_solve
+ * ndg_batch_solve captures, on its first call with a given argument set, one
+ * batch of energies (each plan's max_batch) of every plan into one HIP graph
+ * -- one branch per device, so the devices' level-by-level kernels run
+ * concurrently -- whose first energies live in device memory and are
+ * advanced by the graph's last node; the graph is then launched on `stream`
+ * as many times as the longest energy range needs (each plan's workspace
+ * stays that of one batch).  Later calls with identical arguments replay the
+ * instantiated graph.  Each args[i] holds the arguments ndg_solve
  * takes for plans[i] (device pointers; the growth pointer may be NULL).  The
  * plans must be distinct, on one device, and have profiling switched off.
  * The graph is re-captured whenever a pointer, nE, eta or the precision

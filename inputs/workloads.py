@@ -64,16 +64,20 @@ def uneven_devices(n_devices=64, n_energies=128, eta=1e-6, mu=(0.10, 0.05), kt=0
                    widths=(32, 48, 64, 96, 128), lmin=256, lmax=2048, base_seed=3000):
     """Batch of 2-D FD devices of uneven widths and lengths with random
     barrier profiles, 128 energies each in [0, 0.5] eV."""
-    out = []
-    for d in range(n_devices):
-        rng = np.random.default_rng(base_seed + d)
-        w = int(rng.choice(widths))
-        l = int(rng.integers(lmin, lmax + 1))
-        v = devices.barrier_potential(l, w, rng)
-        dev = devices.fd2d(l, w, 0.25, 0.067, potential=v, name="device%d" % d)
-        out.append(Workload("uneven%d_%dx%d" % (d, l, w), dev,
-                            np.linspace(0.0, 0.5, n_energies), eta, mu, kt))
-    return out
+    return [uneven_device(d, n_energies, eta, mu, kt, widths, lmin, lmax, base_seed)
+            for d in range(n_devices)]
+
+
+def uneven_device(d, n_energies=128, eta=1e-6, mu=(0.10, 0.05), kt=0.025,
+                  widths=(32, 48, 64, 96, 128), lmin=256, lmax=2048, base_seed=3000) -> Workload:
+    """Device d of the uneven batch (seed base_seed + d)."""
+    rng = np.random.default_rng(base_seed + d)
+    w = int(rng.choice(widths))
+    l = int(rng.integers(lmin, lmax + 1))
+    v = devices.barrier_potential(l, w, rng)
+    dev = devices.fd2d(l, w, 0.25, 0.067, potential=v, name="device%d" % d)
+    return Workload("uneven%d_%dx%d" % (d, l, w), dev, np.linspace(0.0, 0.5, n_energies), eta,
+                    mu, kt)
 
 
 def nanotube(n_cells=2000, n_energies=256, eta=1e-6, mu=(0.05, -0.05), kt=0.025,

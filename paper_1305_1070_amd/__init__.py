@@ -353,7 +353,9 @@ class Batch:
         self._outs = None
         self._stream = None
 
-    def solve(self, inputs, prec=NDG_FP64):
+    def solve(self, inputs, prec=NDG_FP64, growth=None):
+        """growth: optional list (one per plan) of float64 [nE] tensors that
+        receive the per-energy growth indicator, as in Plan.solve."""
         import torch
         if len(inputs) != len(self.plans):
             raise ValueError("one input tuple per plan")
@@ -370,13 +372,15 @@ class Batch:
         cur = torch.cuda.current_stream(shapes[0][2])
         self._stream.wait_stream(cur)
         args = []
-        for (E, eta, sig_r, sig_less, V), (gr, gl, gg) in zip(inputs, self._outs):
+        growth = growth if growth is not None else [None] * len(self.plans)
+        for (E, eta, sig_r, sig_less, V), (gr, gl, gg), g in zip(inputs, self._outs, growth):
             args.append({"nE": int(E.shape[0]), "E": E.data_ptr(), "eta": float(eta),
                          "V": V.data_ptr() if V is not None else None,
                          "sig_r": [t.data_ptr() for t in sig_r],
                          "sig_less": [t.data_ptr() for t in sig_less],
                          "diag_gr": gr.data_ptr(), "diag_gless": gl.data_ptr(),
-                         "diag_ggreater": gg.data_ptr(), "growth": None})
+                         "diag_ggreater": gg.data_ptr(),
+                         "growth": g.data_ptr() if g is not None else None})
         ndg_batch_solve(self.handle, args, prec, C.c_void_p(self._stream.cuda_stream))
         cur.wait_stream(self._stream)
         return list(self._outs)

@@ -1,18 +1,23 @@
-// Batched solve of several devices in one graph launch.
+// Batched solve of several devices in one captured graph.
 //
 // Energies and devices are independent problems (Section 3.2 processes one
 // energy at a time), so a batch of uneven devices is a set of independent
-// level-by-level launch sequences.  They are captured once into one HIP
-// graph with a branch per device (fork/join through events on per-device
-// capture streams) and replayed with a single hipGraphLaunch.
+// level-by-level launch sequences.  One batch of energies per device (the
+// plan's max_batch) is captured into one HIP graph with a branch per device
+// (fork/join through events on per-device capture streams); the first
+// energy of each device's batch lives in device memory and a final node
+// advances it, so replaying the same graph sweeps the whole energy range
+// with each plan's workspace bounded by its batch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "../../include/ndnegf.h"
+#include "kernels.hpp"
 #include "runtime.hpp"
 
 struct ndg_batch {
@@ -20,6 +25,9 @@ struct ndg_batch {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> done;
   hipEvent_t fork = nullptr;
+  int32_t* d_e0 = nullptr;   // per plan: first energy of the current replay
+  int32_t* d_inc = nullptr;  // per plan: its batch size
+  int replays = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // the argument set the cached graph was captured with
@@ -70,11 +78,27 @@ ndg_status ndg_batch_create(int32_t nplans, ndg_plan* const* plans, ndg_batch** 
   auto* b = new (std::nothrow) ndg_batch;
   if (!b) { ndg::set_error("ndg_batch_create: out of host memory"); return NDG_ENOMEM; }
   b->plans.assign(plans, plans + nplans);
-  if (hipSetDevice(ndg::plan_device(plans[0])) != hipSuccess ||
+  const int dev = ndg::plan_device(plans[0]);
+  for (int i = 1; i < nplans; ++i)
+    if (ndg::plan_device(plans[i]) != dev) {
+      delete b;
+      ndg::set_error("ndg_batch_create: the plans must live on one device");
+      return NDG_EINVAL;
+    }
+  if (hipSetDevice(dev) != hipSuccess ||
       hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
     delete b;
     ndg::set_error("ndg_batch_create: HIP event creation failed");
     return NDG_EHIP;
+  }
+  std::vector<int32_t> inc(nplans);
+  for (int i = 0; i < nplans; ++i) inc[i] = ndg::plan_max_batch(plans[i]);
+  if (hipMalloc((void**)&b->d_e0, sizeof(int32_t) * nplans) != hipSuccess ||
+      hipMalloc((void**)&b->d_inc, sizeof(int32_t) * nplans) != hipSuccess ||
+      hipMemcpy(b->d_inc, inc.data(), sizeof(int32_t) * nplans, hipMemcpyHostToDevice) != hipSuccess) {
+    ndg_batch_destroy(b);
+    ndg::set_error("ndg_batch_create: device allocation failed");
+    return NDG_ENOMEM;
   }
   for (int i = 0; i < nplans; ++i) {
     hipStream_t s = nullptr;
@@ -99,6 +123,8 @@ ndg_status ndg_batch_destroy(ndg_batch* b) {
   for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
   for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
   if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->d_e0) (void)hipFree(b->d_e0);
+  if (b->d_inc) (void)hipFree(b->d_inc);
   delete b;
   return NDG_OK;
 }
@@ -138,11 +164,13 @@ ndg_status ndg_batch_solve(ndg_batch* b, const ndg_solve_args* args, ndg_precisi
     for (int i = 0; i < np && rc == NDG_OK; ++i) {
       (void)hipStreamWaitEvent(b->streams[i], b->fork, 0);
       const ndg_solve_args& a = args[i];
-      rc = ndg::plan_solve(b->plans[i], a.nE, a.E, a.eta, a.V, a.sig_r, a.sig_less, a.diag_gr,
-                           a.diag_gless, a.diag_ggreater, a.growth, (int)prec, b->streams[i]);
+      rc = ndg::plan_solve_chunk(b->plans[i], a.nE, a.E, a.eta, a.V, a.sig_r, a.sig_less,
+                                 a.diag_gr, a.diag_gless, a.diag_ggreater, a.growth, (int)prec,
+                                 b->streams[i], b->d_e0 + i);
       (void)hipEventRecord(b->done[i], b->streams[i]);
       (void)hipStreamWaitEvent(st, b->done[i], 0);
     }
+    if (rc == NDG_OK) ndg::launch_advance(b->d_e0, b->d_inc, np, st);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(st, &g);
     if (rc != NDG_OK) {
@@ -172,10 +200,22 @@ ndg_status ndg_batch_solve(ndg_batch* b, const ndg_solve_args* args, ndg_precisi
     }
     b->key_prec = (int)prec;
   }
-  if (hipGraphLaunch(b->exec, st) != hipSuccess) {
-    ndg::set_error("ndg_batch_solve: hipGraphLaunch failed");
-    return NDG_EHIP;
+  // replays needed for the longest energy range; the counters and the
+  // growth outputs are cleared by kernels outside the graph
+  int replays = 0;
+  for (int i = 0; i < np; ++i) {
+    const int mb = ndg::plan_max_batch(b->plans[i]);
+    replays = std::max(replays, (args[i].nE + mb - 1) / mb);
   }
+  ndg::launch_fill_zero_i32(b->d_e0, np, st);
+  for (int i = 0; i < np; ++i)
+    if (args[i].growth) ndg::launch_fill_zero(args[i].growth, args[i].nE, st);
+  for (int r = 0; r < replays; ++r)
+    if (hipGraphLaunch(b->exec, st) != hipSuccess) {
+      ndg::set_error("ndg_batch_solve: hipGraphLaunch failed");
+      return NDG_EHIP;
+    }
+  b->replays = replays;
   return NDG_OK;
 }
 

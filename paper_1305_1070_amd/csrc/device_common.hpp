@@ -409,4 +409,7 @@ __device__ inline void raise_fault(int32_t* status, int code, int e, int cl) {
 
 __device__ inline double2* slab(const Ctx& c, int e) { return c.ws + (int64_t)e * c.stride; }
 
+// First energy of the batch this launch processes.
+__device__ inline int ebase(const Ctx& c) { return c.e0p ? c.e0 + *c.e0p : c.e0; }
+
 }  // namespace ndg

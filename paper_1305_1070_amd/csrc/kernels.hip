@@ -25,6 +25,8 @@ namespace ndg {
 __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[cl];
   double2* S = slab(c, e);
   double2* F = S + d.o_fg;
@@ -57,7 +59,7 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
     if (fc >= s) F[(int64_t)fc * f + r].x -= hv;
   }
   __syncthreads();
-  const double ez = c.E[c.e0 + e];
+  const double ez = c.E[eb + e];
   for (int r = t; r < s; r += 256) {
     const double v = c.V ? c.V[c.perm[d.pt_off + r]] : 0.0;
     double2 a = F[(int64_t)r * f + r];
@@ -69,7 +71,7 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
   // contact self-energies: each entry of the front is listed once
   for (int q = d.sptr0 + t; q < d.sptr1; q += 256) {
     const int cc = c.scid[q], nc = c.nc[cc];
-    const double2 sv = c.sig_r[cc][(int64_t)(c.e0 + e) * nc * nc + c.sflat[q]];
+    const double2 sv = c.sig_r[cc][(int64_t)(eb + e) * nc * nc + c.sflat[q]];
     const int64_t pos = (int64_t)c.srow[q] * f + c.scol[q];
     double2 v = F[pos];
     v.x -= sv.x;
@@ -88,6 +90,8 @@ __global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
   __shared__ typename GJ::Smem sm;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[cl];
   double2* S = slab(c, e);
   const double2* F = S + d.o_fg;
@@ -104,7 +108,7 @@ __global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
       g.im[m][q] = v.y;
     }
   const bool ok = g.run(sm, s);
-  if (!ok && t == 0) raise_fault(c.status, -4, c.e0 + e, cl);
+  if (!ok && t == 0) raise_fault(c.status, -4, eb + e, cl);
   double2* Ainv = S + d.o_ainv;
 #pragma unroll
   for (int m = 0; m < GJ::NR; ++m)
@@ -135,7 +139,7 @@ __global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
       }
       // non-negative doubles order like their bit patterns
       if (t == 0)
-        atomicMax(reinterpret_cast<unsigned long long*>(c.growth + c.e0 + e),
+        atomicMax(reinterpret_cast<unsigned long long*>(c.growth + eb + e),
                   (unsigned long long)__double_as_longlong(ru * rb));
     }
   }
@@ -147,6 +151,8 @@ __global__ void __launch_bounds__(256) k_psi(Ctx c, const ColItem* items) {
   __shared__ GemmSmem sm;
   const ColItem it = items[blockIdx.x];
   const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
   double2* S = slab(c, e);
   const double2* Ainv = S + d.o_ainv;
@@ -172,6 +178,8 @@ __global__ void __launch_bounds__(256) k_update(Ctx c, const UpdItem* items) {
   __shared__ typename GM::Smem sm;
   const UpdItem it = items[blockIdx.x];
   const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
   double2* S = slab(c, e);
   const double2* F = S + d.o_fg;
@@ -204,6 +212,8 @@ __global__ void __launch_bounds__(256) k_chain_fwd(Ctx c, const ChainItem* items
   __shared__ GemmSmem sm;
   const ChainItem it = items[blockIdx.x];
   const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
   const int cc = it.c, sc = c.nc[cc];
   double2* S = slab(c, e);
@@ -276,6 +286,8 @@ __global__ void __launch_bounds__(256) k_chain_back(Ctx c, const int32_t* cls) {
   __shared__ GemmSmem sm;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[cl];
   double2* S = slab(c, e);
   const double2* Psi = S + d.o_psi;
@@ -315,7 +327,7 @@ __global__ void __launch_bounds__(256) k_chain_back(Ctx c, const int32_t* cls) {
     }
     __syncthreads();
     {
-      const double2* sl = c.sig_l[cc] + (int64_t)(c.e0 + e) * sc * sc;
+      const double2* sl = c.sig_l[cc] + (int64_t)(eb + e) * sc * sc;
       for (int j0 = 0; j0 < sc; j0 += 64) {
         const int nj = min(64, sc - j0);
         ZTile acc;
@@ -368,6 +380,8 @@ __global__ void __launch_bounds__(256) k_down_off(Ctx c, const ColItem* items, i
   __shared__ typename GM::Smem sm;
   const ColItem it = items[blockIdx.x];
   const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
   const ClusterDesc dp = c.cl[d.parent];
   double2* S = slab(c, e);
@@ -411,6 +425,8 @@ __global__ void __launch_bounds__(256) k_down_diag(Ctx c, const int32_t* cls, in
   __shared__ typename GM::Smem sm;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[cl];
   double2* S = slab(c, e);
   const double2* Psi = S + d.o_psi;
@@ -454,6 +470,8 @@ __global__ void __launch_bounds__(256) k_down_diag(Ctx c, const int32_t* cls, in
 __global__ void __launch_bounds__(256) k_epilogue(Ctx c, double2* dgr, double2* dgl, double2* dgg) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
   if (p >= c.n) return;
   const int cl = c.owner[p];
   const ClusterDesc d = c.cl[cl];
@@ -461,12 +479,24 @@ __global__ void __launch_bounds__(256) k_epilogue(Ctx c, double2* dgr, double2* 
   const double2* S = slab(c, e);
   const double2 gr = S[d.o_fg + (int64_t)r * d.f + r];
   const double2 gl = S[d.o_fp + (int64_t)r * d.f + r];
-  const int64_t o = (int64_t)(c.e0 + e) * c.n + c.perm[p];
+  const int64_t o = (int64_t)(eb + e) * c.n + c.perm[p];
   dgr[o] = gr;
   dgl[o] = gl;
   if (dgg) dgg[o] = make_double2(gl.x, gl.y + 2.0 * gr.y);
   if (!isfinite(gr.x) || !isfinite(gr.y) || !isfinite(gl.x) || !isfinite(gl.y))
-    raise_fault(c.status, -7, c.e0 + e, cl);
+    raise_fault(c.status, -7, eb + e, cl);
+}
+
+// Graph replays over an energy range: each plan's first energy advances by
+// its batch size.
+__global__ void k_advance(int32_t* e0, const int32_t* inc, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) e0[i] += inc[i];
+}
+
+__global__ void k_fill_zero_i32(int32_t* p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) p[i] = 0;
 }
 
 __global__ void k_fill_zero(double* p, int64_t count) {
@@ -475,6 +505,13 @@ __global__ void k_fill_zero(double* p, int64_t count) {
 }
 
 // ---------------------------------------------------------------------------
+void launch_advance(int32_t* e0, const int32_t* inc, int n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_advance, dim3((n + 255) / 256), dim3(256), 0, st, e0, inc, n);
+}
+void launch_fill_zero_i32(int32_t* p, int64_t count, hipStream_t st) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_fill_zero_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count);
+}
 void launch_fill_zero(double* p, int64_t count, hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count);
 }

@@ -53,6 +53,8 @@ struct Ctx {
   int64_t stride;            // complex elements per energy slab
   const double* E;
   int32_t e0;                // first energy of the batch
+  const int32_t* e0p;        // if set, the batch starts at e0 + *e0p (advanced between graph replays)
+  int32_t nE;                // energies in E: batch slots at or beyond it are skipped
   double eta;
   const double* V;           // may be null
   const double2* sig_r[2];
@@ -94,6 +96,8 @@ void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, siz
                           int front_size, hipStream_t st);
 constexpr int kSmallFront = 64;  // fronts up to this size are handled whole on chip
 void launch_fill_zero(double* p, int64_t count, hipStream_t st);
+void launch_fill_zero_i32(int32_t* p, int64_t count, hipStream_t st);
+void launch_advance(int32_t* e0, const int32_t* inc, int n, hipStream_t st);
 void launch_rhs_contact(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st);
 void launch_rhs_lambda(const Ctx& c, const RhsCtx& r, int nb, hipStream_t st);
 void launch_rhs_fwd(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, hipStream_t st);

@@ -31,6 +31,8 @@ __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
   __shared__ double rowb[SF];
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[cl];
   double2* S = slab(c, e);
   const int f = d.f, s = d.s, b = d.b;
@@ -64,7 +66,7 @@ __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
     if (fc >= s) Fr[fc * SLD + r] -= hv;
   }
   __syncthreads();
-  const double ez = c.E[c.e0 + e];
+  const double ez = c.E[eb + e];
   for (int r = t; r < s; r += NT) {
     const double v = c.V ? c.V[c.perm[d.pt_off + r]] : 0.0;
     Fr[r * SLD + r] += ez - v;
@@ -74,7 +76,7 @@ __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
   // contact self-energies: each entry of the front is listed once
   for (int q = d.sptr0 + t; q < d.sptr1; q += NT) {
     const int cc = c.scid[q], nc = c.nc[cc];
-    const double2 sv = c.sig_r[cc][(int64_t)(c.e0 + e) * nc * nc + c.sflat[q]];
+    const double2 sv = c.sig_r[cc][(int64_t)(eb + e) * nc * nc + c.sflat[q]];
     Fr[c.srow[q] * SLD + c.scol[q]] -= sv.x;
     Fi[c.srow[q] * SLD + c.scol[q]] -= sv.y;
   }
@@ -96,7 +98,7 @@ __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
       g.im[m][q] = in ? Fi[i * SLD + j] : 0.0;
     }
   const bool ok = g.run(gsm, s);
-  if (!ok && t == 0) raise_fault(c.status, -4, c.e0 + e, cl);
+  if (!ok && t == 0) raise_fault(c.status, -4, eb + e, cl);
   double2* Ainv = S + d.o_ainv;
   double2* Psi = S + d.o_psi;
   double2* Upd = S + d.o_upd;
@@ -137,7 +139,7 @@ __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
         rb = fmax(rb, __shfl_xor(rb, off));
       }
       if (t == 0)
-        atomicMax(reinterpret_cast<unsigned long long*>(c.growth + c.e0 + e),
+        atomicMax(reinterpret_cast<unsigned long long*>(c.growth + eb + e),
                   (unsigned long long)__double_as_longlong(ru * rb));
     }
   }
@@ -152,6 +154,8 @@ __global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls)
   extern __shared__ double2 sm[];
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[cl];
   double2* S = slab(c, e);
   const int f = d.f, s = d.s, b = d.b;

@@ -418,10 +418,24 @@ int plan_solve(ndg_plan* p, int nE, const double* E, double eta, const double* V
                   nullptr, nullptr, nullptr, prec, stream);
 }
 
+int plan_solve_chunk(ndg_plan* p, int nE, const double* E, double eta, const double* V,
+                     const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
+                     ndg_c128* dgr, ndg_c128* dgl, ndg_c128* dgg, double* growth, int prec,
+                     void* stream, const int32_t* e0p) {
+  return plan_run(p, kRunSolve, nE, E, eta, V, sig_r, sig_less, dgr, dgl, dgg, growth, nullptr,
+                  nullptr, nullptr, nullptr, prec, stream, e0p);
+}
+
+int plan_max_batch(const ndg_plan* p) { return p->max_batch; }
+
 int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const double* V,
              const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
              ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
-             const double* nbar, double* vbar, int prec, void* stream) {
+             const double* nbar, double* vbar, int prec, void* stream, const int32_t* e0p) {
+  if (e0p && mode != kRunSolve) {
+    set_error("internal: device-resident energy offsets are for solves only");
+    return NDG_EINVAL;
+  }
   if (prec != NDG_FP64 && prec != NDG_MIXED) {
     set_error("ndg_solve: unknown precision");
     return NDG_EINVAL;
@@ -462,12 +476,15 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   c.ws = p->d_ws;
   c.stride = p->stride;
   c.E = E;
+  c.e0p = e0p;
+  c.nE = nE;
   c.eta = eta;
   c.V = V;
   c.status = p->d_status;
   c.growth = growth;
   c.mixed = prec == NDG_MIXED ? 1 : 0;
-  if (growth) launch_fill_zero(growth, nE, st);  // a kernel, so graph capture stays valid
+  // a kernel, so graph capture stays valid; a chunk leaves it to the caller
+  if (growth && !e0p) launch_fill_zero(growth, nE, st);
   if (mode == kRunDensity) launch_zero(density, p->n, st);
   if (mode == kRunVjp) {
     if (!p->d_rY) {
@@ -504,8 +521,10 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
     (void)hipEventRecord(r.b, st);
     p->recs.push_back(r);
   };
-  for (int e0 = 0; e0 < nE; e0 += p->max_batch) {
-    const int nb = std::min(p->max_batch, nE - e0);
+  // with e0p: exactly one batch, its first energy read on the device
+  const int e_end = e0p ? std::min(nE, 1) : nE;
+  for (int e0 = 0; e0 < e_end; e0 += p->max_batch) {
+    const int nb = std::min(p->max_batch, e0p ? nE : nE - e0);
     c.e0 = e0;
     for (int h = 1; h <= H; ++h) {
       const ChainItem* chi = p->d_chainitems + p->chain_ptr[h - 1];

@@ -27,7 +27,16 @@ enum RunMode { kRunSolve = 0, kRunDensity = 1, kRunVjp = 2 };
 int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const double* V,
              const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
              ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
-             const double* nbar, double* vbar, int prec, void* stream);
+             const double* nbar, double* vbar, int prec, void* stream,
+             const int32_t* e0p = nullptr);
+// One batch of energies starting at the device-resident index *e0p (for a
+// graph replayed over the energy range): the launches of a single batch of
+// max_batch energies, slots at or beyond nE skipped; growth is not cleared.
+int plan_solve_chunk(ndg_plan* plan, int nE, const double* E, double eta, const double* V,
+                     const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
+                     ndg_c128* dgr, ndg_c128* dgl, ndg_c128* dgg, double* growth, int prec,
+                     void* stream, const int32_t* e0p);
+int plan_max_batch(const ndg_plan* plan);
 int plan_enable_adjoint(ndg_plan* plan);
 int plan_ncontacts(const ndg_plan* plan);
 int plan_device(const ndg_plan* plan);

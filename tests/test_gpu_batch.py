@@ -12,12 +12,9 @@ import pytest
 
 from inputs import workloads
 
-from .helpers import gpu_solve, oracle_dense, oracle_rgf, rel_err
+from .helpers import gpu_solve, oracle_dense, oracle_rgf, rel_err, tolerance
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-10
-GATE = 30.0
-LOOSE = 1e-4
 
 
 def _say(msg):
@@ -44,7 +41,7 @@ def test_wide_contact_spans_a_chain(lib, length, width):
     err = _errs(out, oracle_dense(wl))
     for k in range(len(err)):
         _say("  energy %d growth %.3e err %.2e" % (k, out[3][k], err[k]))
-        assert err[k] < (TOL if out[3][k] < GATE else LOOSE)
+        assert err[k] < tolerance(out[3][k])
 
 
 def _batch_inputs(wls, cuda):
