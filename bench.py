@@ -67,15 +67,85 @@ def _noop(_):
     return 0
 
 
+def bench_batch(ndg, workloads, torch, cuda, n_devices=64, per_plan=4):
+    """64 uneven devices x 128 energies, leaf size per width class from the
+    autotuner, one captured graph replayed over the energy range."""
+    from paper_1305_1070_amd import autotune
+    wls = [workloads.uneven_device(d) for d in range(n_devices)]
+    by_dev = {id(w.device): w for w in wls}
+
+    def sample(dev):
+        w = by_dev[id(dev)]
+        idx = np.linspace(0, len(w.energies) - 1, 8).round().astype(int)
+        sl, sr, ll, lr = w.self_energies(w.energies[idx])
+        return (torch.tensor(w.energies[idx], device=cuda),
+                [torch.from_numpy(a).to(cuda) for a in (sl, sr)],
+                [torch.from_numpy(a).to(cuda) for a in (ll, lr)])
+
+    leaf = autotune.tune_classes([w.device for w in wls], sample, wls[0].eta)
+    plans, ins = [], []
+    gflop = 0.0
+    for w in wls:
+        d = w.device
+        sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords,
+                          leaf_max=leaf[len(d.contacts[0])])
+        gflop += sym.info()["ops_total"] * 8 / 1e9 * len(w.energies)
+        plans.append(ndg.Plan(sym, max_batch=per_plan))
+        sl, sr, ll, lr = w.self_energies()
+        ins.append((torch.tensor(w.energies, device=cuda), w.eta,
+                    [torch.from_numpy(a).to(cuda) for a in (sl, sr)],
+                    [torch.from_numpy(a).to(cuda) for a in (ll, lr)], None))
+    batch = ndg.Batch(plans)
+    batch.solve(ins)  # capture and first pass
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.solve(ins)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_pts = sum(len(w.energies) for w in wls)
+    del batch, plans, ins
+    torch.cuda.empty_cache()
+    return {"workload": "%d 2-D FD devices, widths 32..128, lengths 256..2048, 128 energies each"
+                        % n_devices,
+            "device_energy_points_per_s": n_pts / dt, "s_per_pass": dt,
+            "algorithmic_tflop_per_s": gflop / dt / 1e3, "energies_per_plan_batch": per_plan,
+            "leaf_per_width": {str(k): v for k, v in leaf.items()}}
+
+
+def bench_tube(ndg, workloads, torch, cuda):
+    """(10,0) tube, 2000 cells (80 000 orbitals), 256 energies."""
+    w = workloads.nanotube()
+    d = w.device
+    sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, leaf_max=24)
+    plan = ndg.Plan(sym, max_batch=128)
+    sl, sr, ll, lr = w.self_energies()
+    E = torch.tensor(w.energies, device=cuda)
+    srt = [torch.from_numpy(a).to(cuda) for a in (sl, sr)]
+    slt = [torch.from_numpy(a).to(cuda) for a in (ll, lr)]
+    out = plan.solve(E, w.eta, srt, slt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        plan.solve(E, w.eta, srt, slt, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    return {"workload": "(10,0) zigzag tube, 2000 cells x 40 atoms, 256 energies",
+            "energy_points_per_s": len(w.energies) / dt,
+            "algorithmic_gflop_per_energy": sym.info()["ops_total"] * 8 / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=128, help="energies in flight per batch")
-    ap.add_argument("--leaf", type=int, default=16, help="leaf size of the separator tree")
+    ap.add_argument("--leaf", type=int, default=0,
+                    help="leaf size of the separator tree (0: picked by the autotuner)")
     ap.add_argument("--energies", type=int, default=512)
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false")
+    ap.add_argument("--no-extra", dest="extra", action="store_false",
+                    help="skip the batched uneven-device and nanotube throughput figures")
     ap.add_argument("--cpu-sample", type=int, default=32,
                     help="energies of the CPU oracle timing sample (0 disables it)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -95,15 +165,22 @@ def main():
     n_transport, n_transverse = 1024, 64
     wl = workloads.superlattice(n_transport, n_transverse, n_energies=args.energies)
     dev = wl.device
-    sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords,
-                      leaf_max=args.leaf)
-    info = sym.info()
-    plan = ndg.Plan(sym, max_batch=min(args.batch, args.energies))
     cuda = torch.device("cuda:0")
     sl, sr, ll, lr = wl.self_energies()
     E = torch.tensor(wl.energies, dtype=torch.float64, device=cuda)
     sig_r = [torch.from_numpy(a).to(cuda) for a in (sl, sr)]
     sig_l = [torch.from_numpy(a).to(cuda) for a in (ll, lr)]
+    tuned = None
+    if args.leaf <= 0:
+        from paper_1305_1070_amd import autotune
+        pick = np.linspace(0, args.energies - 1, 64).round().astype(int)
+        args.leaf, tuned = autotune.tune_leaf(
+            dev, E[pick].contiguous(), wl.eta, [t[pick].contiguous() for t in sig_r],
+            [t[pick].contiguous() for t in sig_l], candidates=(12, 16, 20, 24))
+    sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords,
+                      leaf_max=args.leaf)
+    info = sym.info()
+    plan = ndg.Plan(sym, max_batch=min(args.batch, args.energies))
     ne, n = args.energies, dev.n
     out = tuple(torch.empty((ne, n), dtype=torch.complex128, device=cuda) for _ in range(3))
     stream = torch.cuda.current_stream(cuda)
@@ -185,6 +262,11 @@ def main():
                "ms_per_step": ms_adj}
         del pa
 
+    extra = None
+    if args.extra:
+        extra = {"batch": bench_batch(ndg, workloads, torch, cuda),
+                 "nanotube": bench_tube(ndg, workloads, torch, cuda)}
+
     copy_cal = None
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device=cuda).fill_(1.0)
@@ -250,6 +332,7 @@ def main():
         "config": {"workload": "superlattice 1024x64 FD grid, n=65536, dense 64x64 contact "
                                "self-energies, %d energies in [0,0.5] eV, eta=1e-6" % ne,
                    "energies": ne, "batch": plan.max_batch, "leaf_max": args.leaf,
+                   "leaf_autotune_ms_per_energy": tuned,
                    "clusters": info["nclusters"], "tree_levels": info["max_height"],
                    "algorithmic_gflop_per_energy": info["ops_total"] * 8 / 1e9,
                    "rgf_gflop_per_energy": info["ops_rgf_equiv"] * 8 / 1e9},
@@ -261,6 +344,7 @@ def main():
         "parity_sample": parity,
         "kernels": kernels,
         "status": [status, status2],
+        "extra": extra,
         "copy_calibration": copy_cal,
         "wall_s_timed": wall,
     }

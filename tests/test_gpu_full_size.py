@@ -3,7 +3,8 @@ energies against the RGF oracle (swept in both directions; the smaller
 error counts, as one direction can itself lose digits at a resonance).
 
 - 64 uneven 2-D devices (widths 32..128, lengths 256..2048, barriers), 128
-  energies each, solved by one graph launch (ndg_batch_solve);
+  energies each, leaf size per width class picked by the autotuner, solved
+  by one captured graph (ndg_batch_solve);
 - the (10,0) tube of 2000 cells (80 000 orbitals), 256 energies.
 
 Tolerance: helpers.tolerance(growth) -- 1e-10 where the growth indicator is
@@ -39,13 +40,27 @@ def test_batch_of_64_uneven_devices_full_size(lib):
     import torch
     cuda = torch.device("cuda:0")
     nd = 64
+    from paper_1305_1070_amd import autotune
     t0 = time.time()
+    wls = [workloads.uneven_device(d) for d in range(nd)]
+    by_dev = {id(w.device): w for w in wls}
+
+    def sample(dev):
+        wl = by_dev[id(dev)]
+        idx = np.linspace(0, len(wl.energies) - 1, 8).round().astype(int)
+        sl, sr, ll, lr = wl.self_energies(wl.energies[idx])
+        return (torch.tensor(wl.energies[idx], device=cuda),
+                [torch.from_numpy(a).to(cuda) for a in (sl, sr)],
+                [torch.from_numpy(a).to(cuda) for a in (ll, lr)])
+
+    leaf = autotune.tune_classes([w.device for w in wls], sample, wls[0].eta, verbose=True)
+    _say("  autotuned leaf size per width: %s (%.1fs)" % (leaf, time.time() - t0))
     plans, ins, grow = [], [], []
     for d in range(nd):
-        wl = workloads.uneven_device(d)
+        wl = wls[d]
         dev = wl.device
         sym = lib.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords,
-                          leaf_max=16)
+                          leaf_max=leaf[len(dev.contacts[0])])
         plans.append(lib.Plan(sym, max_batch=4))  # 32 graph replays cover 128 energies
         sl, sr, ll, lr = wl.self_energies()
         ins.append((torch.tensor(wl.energies, device=cuda), wl.eta,
