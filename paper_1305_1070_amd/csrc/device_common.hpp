@@ -275,13 +275,36 @@ struct Gemm<false> {
 //     [[A_ii, A_iB], [A_Bi, A_BB]]  ->  [[A_ii^{-1} (permuted), A_ii^{-1} A_iB (rows permuted)],
 //                                        [-A_Bi A_ii^{-1},      A_BB - A_Bi A_ii^{-1} A_iB]].
 // ---------------------------------------------------------------------------
-__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const unsigned long long o = __shfl_xor(v, off);
-    v = o > v ? o : v;
-  }
-  return v;
+// Maximum of a 32-bit key over the 64 lanes of a wavefront, returned to
+// every lane: a butterfly inside each row of 16 lanes through DPP (quad
+// permutations, then row rotations by 4 and 8), then the four row maxima
+// read as scalars.
+__device__ inline unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false));  // row_ror 4
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false));  // row_ror 8
+  const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+  const unsigned r1 = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+  const unsigned r3 = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+
+// 1 / x for x > 0: the hardware estimate refined by two Newton-Raphson steps
+// r <- r (2 - x r) (each doubles the number of correct bits).
+__device__ inline double recip_pos(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+__device__ inline double lane_read(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 template <int SF, int NT, int JS>
@@ -291,6 +314,7 @@ struct RegGJ {
   static constexpr int NC = (SF + JS - 1) / JS;
   static_assert(NT % JS == 0, "thread grid");
   static_assert(SF <= 64, "pivot rows are searched by one wavefront");
+  static_assert(NT % 64 == 0, "whole wavefronts");
   struct Smem {
     double2 col[2][NR * RS];
     double2 row[2][NC * JS];
@@ -333,20 +357,20 @@ struct RegGJ {
         }
       }
       __syncthreads();
-      // key = magnitude bits (7 low bits cleared) | 64 | (63 - row): the
-      // largest |Re| + |Im| wins, ties go to the lower row; every unused row
-      // below s has a key >= 64, so p is always a valid row (a NaN column
+      // key = valid bit | magnitude |Re| + |Im| as a float (its bits order
+      // like the values; 16 mantissa bits kept) | (63 - row): the largest
+      // magnitude wins, near-ties go to the lower row; every unused row
+      // below s has the valid bit, so p is always a valid row (a NaN column
       // picks a NaN row)
-      unsigned long long key = 0;
+      const double2 v = lane < s ? sm.col[buf][lane] : make_double2(0.0, 0.0);
+      unsigned key = 0;
       if (lane < s && !((used >> lane) & 1ull)) {
-        const double2 v = sm.col[buf][lane];
-        const double mg = fabs(v.x) + fabs(v.y);
-        key = ((unsigned long long)__double_as_longlong(mg) & ~127ull) | 64ull |
-              (unsigned long long)(63 - lane);
+        const float mg = (float)(fabs(v.x) + fabs(v.y));
+        key = 0x80000000u | ((__float_as_uint(mg) >> 1) & 0x7FFFFFC0u) | (unsigned)(63 - lane);
       }
-      key = wave_max_u64(key);
-      const int p = 63 - (int)(key & 63ull);
-      const double2 a = sm.col[buf][p];
+      key = wave_max_u32(key);
+      const int p = 63 - (int)(key & 63u);
+      const double2 a = make_double2(lane_read(v.x, p), lane_read(v.y, p));
       const int mp = p / RS;
       const bool own_p = i0 == p % RS;
       if (own_p) {
@@ -363,8 +387,13 @@ struct RegGJ {
       used |= 1ull << p;
       const double den = a.x * a.x + a.y * a.y;
       double dr = 0.0, di = 0.0;
-      if (den > 0.0) { dr = a.x / den; di = -a.y / den; }
-      else ok = false;
+      if (den > 0.0) {
+        const double r = recip_pos(den);
+        dr = a.x * r;
+        di = -a.y * r;
+      } else {
+        ok = false;
+      }
       __syncthreads();
       double2 ck[NR], pr[NC];
 #pragma unroll
