@@ -33,6 +33,11 @@ __device__ inline void ztile_zero(ZTile& a) {
 }
 
 __device__ inline double2 cz() { return make_double2(0.0, 0.0); }
+
+// Element cc (0 or 1) of a per-contact pair without dynamic indexing (which
+// would move the enclosing struct to scratch memory).
+template <class T>
+__device__ inline T sel2(const T (&a)[2], int cc) { return cc ? a[1] : a[0]; }
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -53,33 +58,67 @@ struct TileShape {
 // operand (and 0 outside the live range); A_IFAST / B_KFAST select which index
 // runs fastest across threads while staging, to match the memory layout.
 // Every thread of the 256-thread block must call this.
-template <int TM, bool A_IFAST, bool B_KFAST, class FA, class FB>
+// With PF, the operands of chunk k0 + KC are loaded into registers while the
+// matrix cores work on chunk k0 (the global-load latency hides behind the
+// MFMAs); kernels that inline several products turn it off to stay within
+// the register file.
+template <int TM, bool A_IFAST, bool B_KFAST, bool PF = true, class FA, class FB>
 __device__ void zgemm_acc_t(int K, FA fa, FB fb, ZTile& acc, GemmSmem& sm) {
   using T = TileShape<TM>;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
+  // staging index of operand element q of this thread
+  auto a_idx = [&](int q, int& i, int& kk) {
+    const int idx = t + 256 * q;
+    if (A_IFAST) { i = idx % TM; kk = idx / TM; }
+    else { kk = idx & (KC - 1); i = idx / KC; }
+  };
+  auto b_idx = [&](int q, int& kk, int& j) {
+    const int idx = t + 256 * q;
+    if (B_KFAST) { kk = idx & (KC - 1); j = idx / KC; }
+    else { j = idx & 63; kk = idx >> 6; }
+  };
+  double2 pa[PF ? TM / 16 : 1], pb[PF ? 4 : 1];
+  auto load = [&](int k0) {
+    if constexpr (PF) {
+#pragma unroll
+      for (int q = 0; q < TM / 16; ++q) {
+        int i, kk;
+        a_idx(q, i, kk);
+        pa[q] = (k0 + kk < K) ? fa(i, k0 + kk) : cz();
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int kk, j;
+        b_idx(q, kk, j);
+        pb[q] = (k0 + kk < K) ? fb(k0 + kk, j) : cz();
+      }
+    }
+  };
+  if (K > 0) load(0);
   for (int k0 = 0; k0 < K; k0 += KC) {
 #pragma unroll
     for (int q = 0; q < TM / 16; ++q) {
-      const int idx = t + 256 * q;
       int i, kk;
-      if (A_IFAST) { i = idx % TM; kk = idx / TM; }
-      else { kk = idx & (KC - 1); i = idx / KC; }
-      const double2 v = (k0 + kk < K) ? fa(i, k0 + kk) : cz();
+      a_idx(q, i, kk);
+      double2 v;
+      if constexpr (PF) v = pa[q];
+      else v = (k0 + kk < K) ? fa(i, k0 + kk) : cz();
       sm.ar[i][kk] = v.x;
       sm.ai[i][kk] = v.y;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int idx = t + 256 * q;
       int kk, j;
-      if (B_KFAST) { kk = idx & (KC - 1); j = idx / KC; }
-      else { j = idx & 63; kk = idx >> 6; }
-      const double2 v = (k0 + kk < K) ? fb(k0 + kk, j) : cz();
+      b_idx(q, kk, j);
+      double2 v;
+      if constexpr (PF) v = pb[q];
+      else v = (k0 + kk < K) ? fb(k0 + kk, j) : cz();
       sm.br[kk][j] = v.x;
       sm.bi[kk][j] = v.y;
     }
     __syncthreads();
+    if (k0 + KC < K) load(k0 + KC);
 #pragma unroll
     for (int k4 = 0; k4 < KC; k4 += 4) {
       const int kq = k4 + (lane >> 4);
@@ -112,7 +151,7 @@ __device__ void zgemm_acc_t(int K, FA fa, FB fb, ZTile& acc, GemmSmem& sm) {
 
 template <bool A_IFAST, bool B_KFAST, class FA, class FB>
 __device__ void zgemm_acc(int K, FA fa, FB fb, ZTile& acc, GemmSmem& sm) {
-  zgemm_acc_t<64, A_IFAST, B_KFAST>(K, fa, fb, acc, sm);
+  zgemm_acc_t<64, A_IFAST, B_KFAST, false>(K, fa, fb, acc, sm);
 }
 
 // Calls fs(i, j, re, im) for every tile element this thread holds
@@ -172,16 +211,15 @@ __device__ void zgemm32_acc_t(int K, FA fa, FB fb, ZTile32& acc, GemmSmem32& sm)
   using T = TileShape<TM>;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
-  for (int k0 = 0; k0 < K; k0 += KC) {
+  double2 pa[TM / 16], pb[4];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < TM / 16; ++q) {
       const int idx = t + 256 * q;
       int i, kk;
       if (A_IFAST) { i = idx % TM; kk = idx / TM; }
       else { kk = idx & (KC - 1); i = idx / KC; }
-      const double2 v = (k0 + kk < K) ? fa(i, k0 + kk) : cz();
-      sm.ar[i][kk] = (float)v.x;
-      sm.ai[i][kk] = (float)v.y;
+      pa[q] = (k0 + kk < K) ? fa(i, k0 + kk) : cz();
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -189,11 +227,31 @@ __device__ void zgemm32_acc_t(int K, FA fa, FB fb, ZTile32& acc, GemmSmem32& sm)
       int kk, j;
       if (B_KFAST) { kk = idx & (KC - 1); j = idx / KC; }
       else { j = idx & 63; kk = idx >> 6; }
-      const double2 v = (k0 + kk < K) ? fb(k0 + kk, j) : cz();
-      sm.br[kk][j] = (float)v.x;
-      sm.bi[kk][j] = (float)v.y;
+      pb[q] = (k0 + kk < K) ? fb(k0 + kk, j) : cz();
+    }
+  };
+  if (K > 0) load(0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+    for (int q = 0; q < TM / 16; ++q) {
+      const int idx = t + 256 * q;
+      int i, kk;
+      if (A_IFAST) { i = idx % TM; kk = idx / TM; }
+      else { kk = idx & (KC - 1); i = idx / KC; }
+      sm.ar[i][kk] = (float)pa[q].x;
+      sm.ai[i][kk] = (float)pa[q].y;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = t + 256 * q;
+      int kk, j;
+      if (B_KFAST) { kk = idx & (KC - 1); j = idx / KC; }
+      else { j = idx & 63; kk = idx >> 6; }
+      sm.br[kk][j] = (float)pb[q].x;
+      sm.bi[kk][j] = (float)pb[q].y;
     }
     __syncthreads();
+    if (k0 + KC < K) load(k0 + KC);
 #pragma unroll
     for (int k4 = 0; k4 < KC; k4 += 4) {
       const int kq = k4 + (lane >> 4);

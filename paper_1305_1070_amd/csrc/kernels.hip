@@ -215,19 +215,19 @@ __global__ void __launch_bounds__(256) k_chain_fwd(Ctx c, const ChainItem* items
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
-  const int cc = it.c, sc = c.nc[cc];
+  const int cc = it.c, sc = sel2(c.nc, cc);
   double2* S = slab(c, e);
-  double2* Zf = S + d.o_zf[cc];
+  double2* Zf = S + sel2(d.o_zf, cc);
   const double2* Psi = S + d.o_psi;
   const double2* Ainv = S + d.o_ainv;
   const int s = d.s, b = d.b, f = d.f;
   const int t = threadIdx.x;
   for (int q = t; q < f * sc; q += 256) Zf[q] = cz();
   __syncthreads();
-  const int ch = d.chain_child[cc];
+  const int ch = sel2(d.chain_child, cc);
   if (ch >= 0) {
     const ClusterDesc dc = c.cl[ch];
-    const double2* Zc = S + dc.o_zf[cc];
+    const double2* Zc = S + sel2(dc.o_zf, cc);
     const int32_t* rel = c.relmap + dc.bptr;
     for (int q = t; q < dc.b * sc; q += 256) {
       const int r = q / sc, a = q % sc;
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(256) k_chain_fwd(Ctx c, const ChainItem* items
   __syncthreads();
   // the contact's own columns: ones at its sites held by this cluster
   {
-    const int32_t* pos = c.cpos[cc];
+    const int32_t* pos = sel2(c.cpos, cc);
     for (int a = t; a < sc; a += 256) {
       const int r = pos[a] - d.pt_off;
       if (r >= 0 && r < s) Zf[(int64_t)r * sc + a] = make_double2(1.0, 0.0);
@@ -297,13 +297,13 @@ __global__ void __launch_bounds__(256) k_chain_back(Ctx c, const int32_t* cls) {
   bool first = true;
   for (int cc = 0; cc < c.ncontacts; ++cc) {
     if (!((d.chain_mask >> cc) & 1)) continue;
-    const int sc = c.nc[cc];
-    double2* Xf = S + d.o_xf[cc];
-    const double2* Zf = S + d.o_zf[cc];
-    double2* T = S + d.o_t[cc];
+    const int sc = sel2(c.nc, cc);
+    double2* Xf = S + sel2(d.o_xf, cc);
+    const double2* Zf = S + sel2(d.o_zf, cc);
+    double2* T = S + sel2(d.o_t, cc);
     if (d.parent >= 0) {
       const ClusterDesc dp = c.cl[d.parent];
-      const double2* Xp = S + dp.o_xf[cc];
+      const double2* Xp = S + sel2(dp.o_xf, cc);
       const int32_t* rel = c.relmap + d.bptr;
       for (int q = t; q < b * sc; q += 256) {
         const int r = q / sc, a = q % sc;
@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(256) k_chain_back(Ctx c, const int32_t* cls) {
     }
     __syncthreads();
     {
-      const double2* sl = c.sig_l[cc] + (int64_t)(eb + e) * sc * sc;
+      const double2* sl = sel2(c.sig_l, cc) + (int64_t)(eb + e) * sc * sc;
       for (int j0 = 0; j0 < sc; j0 += 64) {
         const int nj = min(64, sc - j0);
         ZTile acc;

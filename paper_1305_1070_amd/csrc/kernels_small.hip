@@ -159,15 +159,19 @@ __global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls)
   const ClusterDesc d = c.cl[cl];
   double2* S = slab(c, e);
   const int f = d.f, s = d.s, b = d.b;
+  const int lb = b | 1;           // odd row stride: lanes reading down a column hit distinct banks
   const int t = threadIdx.x;
   const bool inner = c.kids_ptr[cl + 1] > c.kids_ptr[cl];
   const bool chain = d.chain_mask != 0;
   const double2* Ainv = S + d.o_ainv;
-  double2* Psl = sm;              // s x b
-  double2* XBB = sm + s * b;      // b x b
-  double2* XIB = XBB + b * b;     // s x b
+  double2* Psl = sm;              // s x b, stride lb
+  double2* XBB = sm + s * lb;     // b x b
+  double2* XIB = XBB + b * b;     // s x b, stride lb
   const double2* Psi = S + d.o_psi;
-  for (int q = t; q < s * b; q += NT) Psl[q] = Psi[q];
+  for (int q = t; q < s * b; q += NT) {
+    const int r = q / b, k = q - r * b;
+    Psl[r * lb + k] = Psi[q];
+  }
   const int32_t* rel = c.relmap + d.bptr;
   for (int lesser = 0; lesser < 2; ++lesser) {
     double2* X = S + (lesser ? d.o_fp : d.o_fg);
@@ -182,48 +186,60 @@ __global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls)
       }
     }
     __syncthreads();
-    // X_{i,B} = P_init + Psi X_{B,B}
+    // X_{i,B} = P_init + Psi X_{B,B}   (two accumulators: even and odd k)
     for (int q = t; q < s * b; q += NT) {
       const int r = q / b, j = q - r * b;
-      double2 acc = src ? X[(int64_t)r * f + s + j] : cz();
-      for (int k = 0; k < b; ++k) {
-        const double2 a = Psl[r * b + k], x = XBB[k * b + j];
-        acc.x += a.x * x.x - a.y * x.y;
-        acc.y += a.x * x.y + a.y * x.x;
+      double2 a0 = src ? X[(int64_t)r * f + s + j] : cz(), a1 = cz();
+      const double2* pr = Psl + r * lb;
+      int k = 0;
+      for (; k + 1 < b; k += 2) {
+        const double2 p0 = pr[k], x0 = XBB[k * b + j];
+        const double2 p1 = pr[k + 1], x1 = XBB[(k + 1) * b + j];
+        a0.x += p0.x * x0.x - p0.y * x0.y;
+        a0.y += p0.x * x0.y + p0.y * x0.x;
+        a1.x += p1.x * x1.x - p1.y * x1.y;
+        a1.y += p1.x * x1.y + p1.y * x1.x;
       }
-      XIB[q] = acc;
+      if (k < b) {
+        const double2 p0 = pr[k], x0 = XBB[k * b + j];
+        a0.x += p0.x * x0.x - p0.y * x0.y;
+        a0.y += p0.x * x0.y + p0.y * x0.x;
+      }
+      XIB[r * lb + j] = make_double2(a0.x + a1.x, a0.y + a1.y);
     }
     __syncthreads();
     // X_ii = (A_ii^{-1} | P_init) + Psi X_{B,i};  X_{B,i}[k][j] = X_{i,B}[j][k]
-    // for G^r, -conj(X_{i,B}[j][k]) for G^<
-    if (!inner) {
-      for (int r = t; r < s; r += NT) {
-        double2 acc = lesser ? (src ? X[(int64_t)r * f + r] : cz()) : Ainv[r * s + r];
-        for (int k = 0; k < b; ++k) {
-          const double2 a = Psl[r * b + k];
-          double2 x = XIB[r * b + k];
-          if (lesser) x = make_double2(-x.x, x.y);
-          acc.x += a.x * x.x - a.y * x.y;
-          acc.y += a.x * x.y + a.y * x.x;
-        }
-        X[(int64_t)r * f + r] = acc;
+    // for G^r, -conj(X_{i,B}[j][k]) for G^<.  A leaf's blocks are read by
+    // nobody but the epilogue: it forms the diagonal only.
+    const double sg = lesser ? -1.0 : 1.0;
+    const int nout = inner ? s * s : s;
+    for (int q = t; q < nout; q += NT) {
+      const int r = inner ? q / s : q, j = inner ? q - r * s : q;
+      double2 a0 = lesser ? (src ? X[(int64_t)r * f + j] : cz()) : Ainv[r * s + j], a1 = cz();
+      const double2* pr = Psl + r * lb;
+      const double2* xr = XIB + j * lb;
+      int k = 0;
+      for (; k + 1 < b; k += 2) {
+        const double2 p0 = pr[k], p1 = pr[k + 1];
+        const double2 x0 = make_double2(sg * xr[k].x, xr[k].y);
+        const double2 x1 = make_double2(sg * xr[k + 1].x, xr[k + 1].y);
+        a0.x += p0.x * x0.x - p0.y * x0.y;
+        a0.y += p0.x * x0.y + p0.y * x0.x;
+        a1.x += p1.x * x1.x - p1.y * x1.y;
+        a1.y += p1.x * x1.y + p1.y * x1.x;
       }
-    } else {
-      for (int q = t; q < s * s; q += NT) {
-        const int r = q / s, j = q - r * s;
-        double2 acc = lesser ? (src ? X[(int64_t)r * f + j] : cz()) : Ainv[q];
-        for (int k = 0; k < b; ++k) {
-          const double2 a = Psl[r * b + k];
-          double2 x = XIB[j * b + k];
-          if (lesser) x = make_double2(-x.x, x.y);
-          acc.x += a.x * x.x - a.y * x.y;
-          acc.y += a.x * x.y + a.y * x.x;
-        }
-        X[(int64_t)r * f + j] = acc;
+      if (k < b) {
+        const double2 p0 = pr[k];
+        const double2 x0 = make_double2(sg * xr[k].x, xr[k].y);
+        a0.x += p0.x * x0.x - p0.y * x0.y;
+        a0.y += p0.x * x0.y + p0.y * x0.x;
       }
+      X[(int64_t)r * f + j] = make_double2(a0.x + a1.x, a0.y + a1.y);
+    }
+    if (inner) {
       for (int q = t; q < s * b; q += NT) {
         const int r = q / b, j = q - r * b;
-        const double2 v = XIB[q];
+        const double2 v = XIB[r * lb + j];
         X[(int64_t)r * f + s + j] = v;
         X[(int64_t)(s + j) * f + r] = lesser ? make_double2(-v.x, v.y) : v;
       }

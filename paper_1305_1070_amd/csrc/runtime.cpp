@@ -238,7 +238,8 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
         g.ncl++;
         if (q <= 2) {
           g.size = std::max(g.size, s_ + b);
-          g.lds = std::max(g.lds, (size_t)(2 * s_ * b + b * b) * 16);
+          // Psi and X_{i,B} rows padded to an odd stride (bank spread)
+          g.lds = std::max(g.lds, (size_t)(2 * s_ * (b | 1) + b * b) * 16);
         } else {
           g.size = std::max(g.size, s_);
           const int nt = (b + 63) / 64;
