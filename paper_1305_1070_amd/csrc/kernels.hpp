@@ -93,7 +93,7 @@ void launch_chain_back(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStr
 // small fronts: f <= 32 (one wave per front) or f <= 64 (four waves)
 void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int front_size, hipStream_t st);
 void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, size_t lds_bytes,
-                          int front_size, hipStream_t st);
+                          int front_size, bool lesser, hipStream_t st);
 constexpr int kSmallFront = 64;  // fronts up to this size are handled whole on chip
 void launch_fill_zero(double* p, int64_t count, hipStream_t st);
 void launch_fill_zero_i32(int32_t* p, int64_t count, hipStream_t st);

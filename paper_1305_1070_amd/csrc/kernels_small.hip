@@ -145,12 +145,13 @@ __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
   }
 }
 
-// Extraction of G^r and then G^< for one small front.  Dynamic LDS holds
+// Extraction of G^r (which = 0) or G^< (which = 1) for one small front; the
+// two run as separate launches on two streams.  Dynamic LDS holds
 // Psi (s x b), the gathered B x B block of the parent's front and X_{i,B}.
 // A leaf's blocks are read by nobody but the epilogue, so a leaf forms and
 // stores only the diagonal of X_ii.
 template <int NT>
-__global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls) {
+__global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls, int which) {
   extern __shared__ double2 sm[];
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
@@ -173,7 +174,8 @@ __global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls)
     Psl[r * lb + k] = Psi[q];
   }
   const int32_t* rel = c.relmap + d.bptr;
-  for (int lesser = 0; lesser < 2; ++lesser) {
+  {
+    const int lesser = which;
     double2* X = S + (lesser ? d.o_fp : d.o_fg);
     const bool src = lesser && chain;
     if (b > 0) {
@@ -260,7 +262,7 @@ void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int fr
 }
 
 void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, size_t lds_bytes,
-                          int front_size, hipStream_t st) {
+                          int front_size, bool lesser, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
     // the gathered B x B block can exceed 64 KB; gfx950 gives a block up to 160 KB
@@ -271,12 +273,13 @@ void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, siz
     attr_set = true;
   }
   if (ncl <= 0) return;
+  const int w = lesser ? 1 : 0;
   if (front_size <= 32)
-    hipLaunchKernelGGL((k_extract_small<64>), dim3(ncl, nb), dim3(64), lds_bytes, st, c, cls);
+    hipLaunchKernelGGL((k_extract_small<64>), dim3(ncl, nb), dim3(64), lds_bytes, st, c, cls, w);
   else if (front_size <= 48)
-    hipLaunchKernelGGL((k_extract_small<128>), dim3(ncl, nb), dim3(128), lds_bytes, st, c, cls);
+    hipLaunchKernelGGL((k_extract_small<128>), dim3(ncl, nb), dim3(128), lds_bytes, st, c, cls, w);
   else
-    hipLaunchKernelGGL((k_extract_small<256>), dim3(ncl, nb), dim3(256), lds_bytes, st, c, cls);
+    hipLaunchKernelGGL((k_extract_small<256>), dim3(ncl, nb), dim3(256), lds_bytes, st, c, cls, w);
 }
 
 }  // namespace ndg

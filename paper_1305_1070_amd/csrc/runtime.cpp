@@ -75,6 +75,10 @@ struct ndg_plan {
   struct Rec { int kid, h; hipEvent_t a, b; double flops, bytes; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
+  // the G^< extraction (with the chain back substitution it needs) runs on a
+  // second stream, concurrent with the G^r extraction
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace ndg {
@@ -84,12 +88,13 @@ namespace {
 enum KernelId {
   K_ASSEMBLE, K_FACTOR, K_PSI, K_UPDATE, K_CHAIN_FWD, K_DOWN_OFF_G, K_DOWN_DIAG_G, K_CHAIN_BACK,
   K_DOWN_OFF_P, K_DOWN_DIAG_P, K_EPILOGUE, K_FOLD_SMALL, K_EXTRACT_SMALL, K_RHS_FWD, K_RHS_BACK,
-  K_VJP, kKernels
+  K_VJP, K_EXTRACT_SMALL_P, kKernels
 };
 const char* const kKernelNames[kKernels] = {
     "k_assemble", "k_factor", "k_psi", "k_update", "k_chain_fwd", "k_down_off(G)",
     "k_down_diag(G)", "k_chain_back", "k_down_off(P)", "k_down_diag(P)", "k_epilogue",
-    "k_fold_small", "k_extract_small", "k_rhs_fwd", "k_rhs_back", "k_vjp_accum"};
+    "k_fold_small", "k_extract_small(G)", "k_rhs_fwd", "k_rhs_back", "k_vjp_accum",
+    "k_extract_small(P)"};
 
 int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
@@ -165,6 +170,9 @@ void free_plan(ndg_plan* p) {
     (void)hipEventDestroy(r.b);
   }
   for (hipEvent_t ev : p->event_pool) (void)hipEventDestroy(ev);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  if (p->side) (void)hipStreamDestroy(p->side);
   delete p;
 }
 
@@ -280,8 +288,9 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
     if (s + b <= kSmallFront) {
       // whole-front elimination: s steps over the f x f front
       addc(K_FOLD_SMALL, h, 8.0 * s * f * f, 16.0 * (kidb + s * s + s * b + b * b));
-      addc(K_EXTRACT_SMALL, h, 2 * 8.0 * (s * b * b + s * s * b),
-           2 * 16.0 * (b * b + s * s + s * b + (inner ? s * b + b * b : 0.0)) + 16.0 * (s * b + s * s));
+      for (int q : {K_EXTRACT_SMALL, K_EXTRACT_SMALL_P})
+        addc(q, h, 8.0 * (s * b * b + s * s * b),
+             16.0 * (b * b + s * s + s * b + (inner ? s * b + b * b : 0.0)) + 16.0 * (s * b + s * s));
     } else {
       addc(K_ASSEMBLE, h, 0.0, 16.0 * (f * f + kidb));
       addc(K_FACTOR, h, 8.0 * s * s * s, 16.0 * 2 * s * s);
@@ -333,6 +342,13 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   if (!rc) {
     if (hipMalloc((void**)&p->d_status, 4 * sizeof(int32_t)) != hipSuccess) rc = NDG_ENOMEM;
     else if (hipMemset(p->d_status, 0, 4 * sizeof(int32_t)) != hipSuccess) rc = NDG_EHIP;
+  }
+  if (!rc) {
+    // default priority, like every stream of the library
+    if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)
+      rc = NDG_EHIP;
   }
   if (rc) {
     (void)hipGetLastError();
@@ -513,15 +529,16 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
     else (void)hipEventCreate(&ev);
     return ev;
   };
-  auto timed = [&](int kid, int h, int nb, auto&& launch) {
+  auto timed_on = [&](hipStream_t on, int kid, int h, int nb, auto&& launch) {
     if (!p->profiling) { launch(); return; }
     ndg_plan::Rec r{kid, h, take_event(), take_event(), p->cost_flops[kid * (H + 1) + h] * nb,
                     p->cost_bytes[kid * (H + 1) + h] * nb};
-    (void)hipEventRecord(r.a, st);
+    (void)hipEventRecord(r.a, on);
     launch();
-    (void)hipEventRecord(r.b, st);
+    (void)hipEventRecord(r.b, on);
     p->recs.push_back(r);
   };
+  auto timed = [&](int kid, int h, int nb, auto&& launch) { timed_on(st, kid, h, nb, launch); };
   // with e0p: exactly one batch, its first energy read on the device
   const int e_end = e0p ? std::min(nE, 1) : nE;
   for (int e0 = 0; e0 < e_end; e0 += p->max_batch) {
@@ -571,24 +588,42 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
       p->last_batch = nb;
       continue;
     }
+    // G^r extraction on st; chain back substitution and G^< extraction on
+    // the side stream (they write disjoint buffers and read the fold's
+    // factors only), joined before the epilogue.  Under stream capture (the
+    // batch graph) everything stays on st: forking the plan's own stream
+    // inside a capture crashed the HIP runtime.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess) cap = hipStreamCaptureStatusActive;
+    const bool fork = cap == hipStreamCaptureStatusNone;
+    hipStream_t sp = fork ? p->side : st;
+    if (fork) {
+      (void)hipEventRecord(p->ev_fork, st);
+      (void)hipStreamWaitEvent(sp, p->ev_fork, 0);
+    }
     for (int h = H; h >= 1; --h) {
       const int k0 = p->chaincl_ptr[h - 1], nck = p->chaincl_ptr[h] - k0;
       // the G^< source on chain clusters first: the extraction of P reads it
-      if (nck) timed(K_CHAIN_BACK, h, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, st); });
+      if (nck) timed_on(sp, K_CHAIN_BACK, h, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, sp); });
       for (int q = 0; q < ndg_plan::kClasses; ++q) {
         const ndg_plan::Group& g = p->groups[h * ndg_plan::kClasses + q];
         if (!g.ncl) continue;
         const int32_t* cl = p->d_levels + g.cl0;
         if (q <= 2) {
-          timed(K_EXTRACT_SMALL, h, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, st); });
+          timed_on(sp, K_EXTRACT_SMALL_P, h, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, true, sp); });
+          timed(K_EXTRACT_SMALL, h, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, false, st); });
           continue;
         }
         const ColItem* ci = p->d_colitems + g.col0;
+        if (g.ncol) timed_on(sp, K_DOWN_OFF_P, h, nb, [&] { launch_down_off(c, ci, g.ncol, nb, true, g.size, sp); });
+        timed_on(sp, K_DOWN_DIAG_P, h, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, true, g.size, sp); });
         if (g.ncol) timed(K_DOWN_OFF_G, h, nb, [&] { launch_down_off(c, ci, g.ncol, nb, false, g.size, st); });
         timed(K_DOWN_DIAG_G, h, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, false, g.size, st); });
-        if (g.ncol) timed(K_DOWN_OFF_P, h, nb, [&] { launch_down_off(c, ci, g.ncol, nb, true, g.size, st); });
-        timed(K_DOWN_DIAG_P, h, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, true, g.size, st); });
       }
+    }
+    if (fork) {
+      (void)hipEventRecord(p->ev_join, sp);
+      (void)hipStreamWaitEvent(st, p->ev_join, 0);
     }
     if (mode == kRunSolve)
       timed(K_EPILOGUE, 0, nb, [&] {
