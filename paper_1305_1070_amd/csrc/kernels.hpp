@@ -25,6 +25,13 @@ struct ClusterDesc {
   int32_t sptr0, sptr1;   // contact self-energy entries of this front
   int32_t chain_child[2]; // per contact: child on the contact's chain, -1 if none
   int32_t chain_mask;     // bit c: the cluster is on contact c's chain
+  // fronts of at most 64 points (assembled in registers): the cluster's rows
+  // of -H over the front (s x f, mirrored for the B rows), the contact
+  // self-energy index map (f x f, (contact << 24) | flat index, -1 where
+  // none; -1 offset if the front has no entries), and for a cluster whose
+  // parent is such a front, the parent's front positions -> index in this
+  // cluster's B (f_parent entries, -1 where absent)
+  int64_t o_hf, o_smap, o_pinv;
 };
 
 struct UpdItem { int32_t cl, tr, tc, pad; };   // Schur update tile (rows tr*64.., cols tc*64..)
@@ -46,6 +53,9 @@ struct Ctx {
   const int32_t* scol;
   const int32_t* scid;
   const int32_t* sflat;
+  const double* hfront;      // see ClusterDesc::o_hf
+  const int32_t* smap;       // see ClusterDesc::o_smap
+  const int32_t* pinv;       // see ClusterDesc::o_pinv
   int32_t nc[2];
   int32_t ncontacts;
   int32_t n;

@@ -3,10 +3,11 @@
 // (leaves and the separators just above them), and tiling their products
 // into 64 x 64 matrix-core tiles would mostly multiply padding.
 //
-// Fold: the front [[F_ii, F_iB], [F_Bi, F_BB]] is assembled in LDS, moved
-// to registers and reduced by s steps of Gauss-Jordan elimination with
-// partial pivoting among the rows of cluster i, applied to the whole front.
-// The result is
+// Fold: the front [[F_ii, F_iB], [F_Bi, F_BB]] is assembled directly in
+// registers (the cluster's rows of A from a precomputed -H template, the
+// children's contributions gathered through their index maps) and reduced by
+// s steps of Gauss-Jordan elimination with partial pivoting among the rows of
+// cluster i, applied to the whole front.  The result is
 //     [[ F_ii^{-1},          F_ii^{-1} F_iB           ],
 //      [ -F_Bi F_ii^{-1},    F_BB - F_Bi F_ii^{-1} F_iB ]]
 // i.e. the pivot inverse, -Psi_{i,B}, Psi^T and the Schur contribution to the
@@ -23,12 +24,10 @@
 namespace ndg {
 
 template <int SF, int NT, int JS>
-__global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
-  constexpr int SLD = SF + 1;  // padded row length in LDS
+__device__ __forceinline__ void fold_small_body(const Ctx& c, const int32_t* cls) {
   using GJ = RegGJ<SF, NT, JS>;
-  __shared__ double Fr[SF * SLD], Fi[SF * SLD];
   __shared__ typename GJ::Smem gsm;
-  __shared__ double rowb[SF];
+  __shared__ double rsum[2][SF];  // growth indicator: row sums of |F_iB| and |F_ii^{-1}|
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
   const int eb = ebase(c);
@@ -37,66 +36,79 @@ __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
   double2* S = slab(c, e);
   const int f = d.f, s = d.s, b = d.b;
   const int t = threadIdx.x;
-  for (int j = t & 31; j < f; j += 32)
-    for (int i = t >> 5; i < f; i += NT / 32) {
-      Fr[i * SLD + j] = 0.0;
-      Fi[i * SLD + j] = 0.0;
-    }
-  __syncthreads();
-  // children's Schur contributions, one child at a time
-  for (int kp = c.kids_ptr[cl]; kp < c.kids_ptr[cl + 1]; ++kp) {
-    const ClusterDesc dc = c.cl[c.kids[kp]];
-    const int bc = dc.b;
-    const int32_t* rel = c.relmap + dc.bptr;
-    const double2* U = S + dc.o_upd;
-    for (int q = t; q < bc * bc; q += NT) {
-      const int r = q / bc, cc = q - r * bc;
-      const int pos = rel[r] * SLD + rel[cc];
-      const double2 u = U[q];
-      Fr[pos] += u.x;
-      Fi[pos] += u.y;
-    }
-    __syncthreads();
-  }
-  // rows of cluster i of -H, mirrored into the B rows
-  for (int p = d.hptr0 + t; p < d.hptr1; p += NT) {
-    const int r = c.hrow[p], fc = c.hcol[p];
-    const double hv = c.hval[p];
-    Fr[r * SLD + fc] -= hv;
-    if (fc >= s) Fr[fc * SLD + r] -= hv;
-  }
-  __syncthreads();
-  const double ez = c.E[eb + e];
-  for (int r = t; r < s; r += NT) {
-    const double v = c.V ? c.V[c.perm[d.pt_off + r]] : 0.0;
-    Fr[r * SLD + r] += ez - v;
-    Fi[r * SLD + r] += c.eta;
-  }
-  __syncthreads();
-  // contact self-energies: each entry of the front is listed once
-  for (int q = d.sptr0 + t; q < d.sptr1; q += NT) {
-    const int cc = c.scid[q], nc = c.nc[cc];
-    const double2 sv = c.sig_r[cc][(int64_t)(eb + e) * nc * nc + c.sflat[q]];
-    Fr[c.srow[q] * SLD + c.scol[q]] -= sv.x;
-    Fi[c.srow[q] * SLD + c.scol[q]] -= sv.y;
-  }
-  __syncthreads();
-  if (c.growth && t < s) {
-    double rb = 0.0;
-    for (int j = s; j < f; ++j) rb += sqrt(Fr[t * SLD + j] * Fr[t * SLD + j] + Fi[t * SLD + j] * Fi[t * SLD + j]);
-    rowb[t] = rb;
-  }
-  // the front into registers, s elimination steps there
   GJ g(t);
+  // the cluster's rows of A = zI - H - V - Sigma over the front (B rows by
+  // symmetry), straight into the register tiles
+  const double* hf = c.hfront + d.o_hf;
+  const double ez = c.E[eb + e];
 #pragma unroll
   for (int m = 0; m < GJ::NR; ++m)
 #pragma unroll
     for (int q = 0; q < GJ::NC; ++q) {
       const int i = g.row(m), j = g.col(q);
-      const bool in = i < f && j < f;
-      g.re[m][q] = in ? Fr[i * SLD + j] : 0.0;
-      g.im[m][q] = in ? Fi[i * SLD + j] : 0.0;
+      double re = 0.0, im = 0.0;
+      if (i < f && j < f) {
+        if (i < s) re = hf[i * f + j];
+        else if (j < s) re = hf[j * f + i];
+        if (i == j && i < s) {
+          re += ez - (c.V ? c.V[c.perm[d.pt_off + i]] : 0.0);
+          im += c.eta;
+        }
+      }
+      g.re[m][q] = re;
+      g.im[m][q] = im;
     }
+  if (d.o_smap >= 0) {
+    const int32_t* smp = c.smap + d.o_smap;
+#pragma unroll
+    for (int m = 0; m < GJ::NR; ++m)
+#pragma unroll
+      for (int q = 0; q < GJ::NC; ++q) {
+        const int i = g.row(m), j = g.col(q);
+        const int code = (i < f && j < f) ? smp[i * f + j] : -1;
+        if (code >= 0) {
+          const int cc = code >> 24, nc = sel2(c.nc, cc);
+          const double2 sv = sel2(c.sig_r, cc)[(int64_t)(eb + e) * nc * nc + (code & 0xFFFFFF)];
+          g.re[m][q] -= sv.x;
+          g.im[m][q] -= sv.y;
+        }
+      }
+  }
+  // children's Schur contributions, gathered through their index maps
+  for (int kp = c.kids_ptr[cl]; kp < c.kids_ptr[cl + 1]; ++kp) {
+    const ClusterDesc dc = c.cl[c.kids[kp]];
+    const int32_t* inv = c.pinv + dc.o_pinv;
+    const double2* U = S + dc.o_upd;
+    int ri[GJ::NR], cj[GJ::NC];
+#pragma unroll
+    for (int m = 0; m < GJ::NR; ++m) ri[m] = g.row(m) < f ? inv[g.row(m)] : -1;
+#pragma unroll
+    for (int q = 0; q < GJ::NC; ++q) cj[q] = g.col(q) < f ? inv[g.col(q)] : -1;
+#pragma unroll
+    for (int m = 0; m < GJ::NR; ++m)
+#pragma unroll
+      for (int q = 0; q < GJ::NC; ++q)
+        if (ri[m] >= 0 && cj[q] >= 0) {
+          const double2 u = U[ri[m] * dc.b + cj[q]];
+          g.re[m][q] += u.x;
+          g.im[m][q] += u.y;
+        }
+  }
+  if (c.growth) {
+    for (int r = t; r < 2 * SF; r += NT) rsum[r / SF][r % SF] = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < GJ::NR; ++m) {
+      const int i = g.row(m);
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < GJ::NC; ++q) {
+        const int j = g.col(q);
+        if (i < s && j >= s && j < f) acc += sqrt(g.re[m][q] * g.re[m][q] + g.im[m][q] * g.im[m][q]);
+      }
+      if (i < s && acc != 0.0) atomicAdd(&rsum[0][i], acc);
+    }
+  }
   const bool ok = g.run(gsm, s);
   if (!ok && t == 0) raise_fault(c.status, -4, eb + e, cl);
   double2* Ainv = S + d.o_ainv;
@@ -118,20 +130,22 @@ __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
       }
     }
   if (c.growth && b > 0) {
-    // ||A_ii^{-1}||_inf from the register tiles, via the (now free) LDS front
+    // ||A_ii^{-1}||_inf ||A_iB||_inf (row sums are permutation invariant)
 #pragma unroll
-    for (int m = 0; m < GJ::NR; ++m)
+    for (int m = 0; m < GJ::NR; ++m) {
+      const int i = g.row(m);
+      double acc = 0.0;
 #pragma unroll
-      for (int q = 0; q < GJ::NC; ++q) {
-        const int i = g.row(m), j = g.col(q);
-        if (i < s && j < s) Fr[i * SLD + j] = sqrt(g.re[m][q] * g.re[m][q] + g.im[m][q] * g.im[m][q]);
-      }
+      for (int q = 0; q < GJ::NC; ++q)
+        if (i < s && g.col(q) < s) acc += sqrt(g.re[m][q] * g.re[m][q] + g.im[m][q] * g.im[m][q]);
+      if (i < s && acc != 0.0) atomicAdd(&rsum[1][i], acc);
+    }
     __syncthreads();
     if (t < 64) {
       double ru = 0.0, rb = 0.0;
       if (t < s) {
-        for (int j = 0; j < s; ++j) ru += Fr[t * SLD + j];
-        rb = rowb[t];
+        ru = rsum[1][t];
+        rb = rsum[0][t];
       }
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
@@ -143,6 +157,18 @@ __global__ void __launch_bounds__(NT) k_fold_small(Ctx c, const int32_t* cls) {
                   (unsigned long long)__double_as_longlong(ru * rb));
     }
   }
+}
+
+// Entry points: the 32- and 64-point classes fit 128 registers, so four
+// wavefronts per SIMD; the 48-point class (three columns per thread) does not.
+template <int SF, int NT, int JS>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+k_fold_small(Ctx c, const int32_t* cls) {
+  fold_small_body<SF, NT, JS>(c, cls);
+}
+template <int SF, int NT, int JS>
+__global__ void __launch_bounds__(NT) k_fold_small_wide(Ctx c, const int32_t* cls) {
+  fold_small_body<SF, NT, JS>(c, cls);
 }
 
 // Extraction of G^r (which = 0) or G^< (which = 1) for one small front; the
@@ -257,7 +283,7 @@ __global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls,
 void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int front_size, hipStream_t st) {
   if (ncl <= 0) return;
   if (front_size <= 32) hipLaunchKernelGGL((k_fold_small<32, 64, 32>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
-  else if (front_size <= 48) hipLaunchKernelGGL((k_fold_small<48, 128, 16>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
+  else if (front_size <= 48) hipLaunchKernelGGL((k_fold_small_wide<48, 128, 16>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
   else hipLaunchKernelGGL((k_fold_small<64, 256, 64>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
 }
 

@@ -44,6 +44,8 @@ struct ndg_plan {
   int32_t *d_perm = nullptr, *d_owner = nullptr;
   int32_t* d_cpos[2] = {nullptr, nullptr};
   int32_t *d_srow = nullptr, *d_scol = nullptr, *d_scid = nullptr, *d_sflat = nullptr;
+  double* d_hfront = nullptr;
+  int32_t *d_smap = nullptr, *d_pinv = nullptr;
   int32_t* d_levels = nullptr;       // clusters by height
   ndg::ColItem* d_colitems = nullptr;
   ndg::UpdItem* d_upditems = nullptr;
@@ -162,7 +164,8 @@ void free_plan(ndg_plan* p) {
                   p->d_cpos[1],   p->d_levels,   p->d_colitems,   p->d_upditems,   p->d_chainitems,
                   p->d_chaincls,  p->d_ws,       p->d_status,     p->d_rY,         p->d_rX,
                   p->d_rG,        p->d_rZ,       p->d_ovec,       p->d_bidx,       p->d_part,
-                  p->d_srow,      p->d_scol,     p->d_scid,       p->d_sflat};
+                  p->d_srow,      p->d_scol,     p->d_scid,       p->d_sflat,      p->d_hfront,
+                  p->d_smap,      p->d_pinv};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& r : p->recs) {
@@ -314,11 +317,49 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
     for (int32_t ch : sy.children[k]) kids.push_back(ch);
     kids_ptr[k + 1] = (int32_t)kids.size();
   }
+  // register-assembled small fronts: -H rows, self-energy maps, child maps
+  std::vector<double> hfront;
+  std::vector<int32_t> smap, pinv;
+  for (int k = 0; k < nc; ++k) {
+    ClusterDesc& d = p->hdesc[k];
+    d.o_hf = d.o_smap = d.o_pinv = -1;
+    const int s_ = d.s, f = d.f;
+    if (f <= kSmallFront) {
+      d.o_hf = (int64_t)hfront.size();
+      hfront.resize(hfront.size() + (size_t)s_ * f, 0.0);
+      double* hf = hfront.data() + d.o_hf;
+      for (int64_t q = sy.hptr[k]; q < sy.hptr[k + 1]; ++q) hf[(int64_t)sy.hrow[q] * f + sy.hcol[q]] -= sy.hval[q];
+      if (sy.sptr[k] < sy.sptr[k + 1]) {
+        d.o_smap = (int64_t)smap.size();
+        smap.resize(smap.size() + (size_t)f * f, -1);
+        int32_t* sm = smap.data() + d.o_smap;
+        for (int64_t q = sy.sptr[k]; q < sy.sptr[k + 1]; ++q)
+          sm[(int64_t)sy.srow[q] * f + sy.scol[q]] = (sy.scid[q] << 24) | sy.sflat[q];
+      }
+    }
+    const int par = sy.parent[k];
+    if (par >= 0 && sy.s(par) + sy.b(par) <= kSmallFront) {
+      const int fp = sy.s(par) + sy.b(par);
+      d.o_pinv = (int64_t)pinv.size();
+      pinv.resize(pinv.size() + fp, -1);
+      for (int r = 0; r < d.b; ++r) pinv[d.o_pinv + sy.relmap[sy.bptr[k] + r]] = r;
+    }
+  }
+  for (int k = 0; k < nc; ++k)
+    for (int64_t q = sy.sptr[k]; q < sy.sptr[k + 1]; ++q)
+      if (sy.sflat[q] >= (1 << 24)) {
+        set_error("ndg_plan_create: contact too large for the self-energy index map");
+        free_plan(p);
+        return NDG_EINVAL;
+      }
   int rc = 0;
   rc = rc ? rc : upload(&p->d_cl, p->hdesc.data(), p->hdesc.size());
   rc = rc ? rc : upload(&p->d_relmap, sy.relmap.data(), sy.relmap.size());
   rc = rc ? rc : upload(&p->d_kids_ptr, kids_ptr.data(), kids_ptr.size());
   rc = rc ? rc : upload(&p->d_kids, kids.data(), kids.size());
+  rc = rc ? rc : upload(&p->d_hfront, hfront.data(), hfront.size());
+  rc = rc ? rc : upload(&p->d_smap, smap.data(), smap.size());
+  rc = rc ? rc : upload(&p->d_pinv, pinv.data(), pinv.size());
   rc = rc ? rc : upload(&p->d_hrow, sy.hrow.data(), sy.hrow.size());
   rc = rc ? rc : upload(&p->d_hcol, sy.hcol.data(), sy.hcol.size());
   rc = rc ? rc : upload(&p->d_hval, sy.hval.data(), sy.hval.size());
@@ -480,6 +521,9 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   c.scol = p->d_scol;
   c.scid = p->d_scid;
   c.sflat = p->d_sflat;
+  c.hfront = p->d_hfront;
+  c.smap = p->d_smap;
+  c.pinv = p->d_pinv;
   c.perm = p->d_perm;
   c.owner = p->d_owner;
   c.ncontacts = p->ncontacts;
