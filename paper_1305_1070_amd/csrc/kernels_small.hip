@@ -214,55 +214,77 @@ __global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls,
       }
     }
     __syncthreads();
-    // X_{i,B} = P_init + Psi X_{B,B}   (two accumulators: even and odd k)
-    for (int q = t; q < s * b; q += NT) {
-      const int r = q / b, j = q - r * b;
-      double2 a0 = src ? X[(int64_t)r * f + s + j] : cz(), a1 = cz();
-      const double2* pr = Psl + r * lb;
-      int k = 0;
-      for (; k + 1 < b; k += 2) {
-        const double2 p0 = pr[k], x0 = XBB[k * b + j];
-        const double2 p1 = pr[k + 1], x1 = XBB[(k + 1) * b + j];
-        a0.x += p0.x * x0.x - p0.y * x0.y;
-        a0.y += p0.x * x0.y + p0.y * x0.x;
-        a1.x += p1.x * x1.x - p1.y * x1.y;
-        a1.y += p1.x * x1.y + p1.y * x1.x;
+    // X_{i,B} = P_init + Psi X_{B,B}: two rows per thread share each X_{B,B}
+    // operand (rows r0 and r0 + 1, one column)
+    const int sp2 = (s + 1) >> 1;
+    for (int q = t; q < sp2 * b; q += NT) {
+      const int r0 = (q / b) << 1, j = q - (q / b) * b;
+      const bool two = r0 + 1 < s;
+      double2 a0 = src ? X[(int64_t)r0 * f + s + j] : cz();
+      double2 a1 = (src && two) ? X[(int64_t)(r0 + 1) * f + s + j] : cz();
+      const double2* p0r = Psl + r0 * lb;
+      const double2* p1r = Psl + (two ? r0 + 1 : r0) * lb;
+      for (int k = 0; k < b; ++k) {
+        const double2 x = XBB[k * b + j];
+        const double2 p0 = p0r[k], p1 = p1r[k];
+        a0.x += p0.x * x.x - p0.y * x.y;
+        a0.y += p0.x * x.y + p0.y * x.x;
+        a1.x += p1.x * x.x - p1.y * x.y;
+        a1.y += p1.x * x.y + p1.y * x.x;
       }
-      if (k < b) {
-        const double2 p0 = pr[k], x0 = XBB[k * b + j];
-        a0.x += p0.x * x0.x - p0.y * x0.y;
-        a0.y += p0.x * x0.y + p0.y * x0.x;
-      }
-      XIB[r * lb + j] = make_double2(a0.x + a1.x, a0.y + a1.y);
+      XIB[r0 * lb + j] = a0;
+      if (two) XIB[(r0 + 1) * lb + j] = a1;
     }
     __syncthreads();
     // X_ii = (A_ii^{-1} | P_init) + Psi X_{B,i};  X_{B,i}[k][j] = X_{i,B}[j][k]
     // for G^r, -conj(X_{i,B}[j][k]) for G^<.  A leaf's blocks are read by
     // nobody but the epilogue: it forms the diagonal only.
     const double sg = lesser ? -1.0 : 1.0;
-    const int nout = inner ? s * s : s;
-    for (int q = t; q < nout; q += NT) {
-      const int r = inner ? q / s : q, j = inner ? q - r * s : q;
-      double2 a0 = lesser ? (src ? X[(int64_t)r * f + j] : cz()) : Ainv[r * s + j], a1 = cz();
-      const double2* pr = Psl + r * lb;
-      const double2* xr = XIB + j * lb;
-      int k = 0;
-      for (; k + 1 < b; k += 2) {
-        const double2 p0 = pr[k], p1 = pr[k + 1];
-        const double2 x0 = make_double2(sg * xr[k].x, xr[k].y);
-        const double2 x1 = make_double2(sg * xr[k + 1].x, xr[k + 1].y);
-        a0.x += p0.x * x0.x - p0.y * x0.y;
-        a0.y += p0.x * x0.y + p0.y * x0.x;
-        a1.x += p1.x * x1.x - p1.y * x1.y;
-        a1.y += p1.x * x1.y + p1.y * x1.x;
+    if (!inner) {
+      for (int r = t; r < s; r += NT) {
+        double2 a0 = lesser ? (src ? X[(int64_t)r * f + r] : cz()) : Ainv[r * s + r], a1 = cz();
+        const double2* pr = Psl + r * lb;
+        const double2* xr = XIB + r * lb;
+        int k = 0;
+        for (; k + 1 < b; k += 2) {
+          const double2 p0 = pr[k], p1 = pr[k + 1];
+          const double2 x0 = make_double2(sg * xr[k].x, xr[k].y);
+          const double2 x1 = make_double2(sg * xr[k + 1].x, xr[k + 1].y);
+          a0.x += p0.x * x0.x - p0.y * x0.y;
+          a0.y += p0.x * x0.y + p0.y * x0.x;
+          a1.x += p1.x * x1.x - p1.y * x1.y;
+          a1.y += p1.x * x1.y + p1.y * x1.x;
+        }
+        if (k < b) {
+          const double2 p0 = pr[k];
+          const double2 x0 = make_double2(sg * xr[k].x, xr[k].y);
+          a0.x += p0.x * x0.x - p0.y * x0.y;
+          a0.y += p0.x * x0.y + p0.y * x0.x;
+        }
+        X[(int64_t)r * f + r] = make_double2(a0.x + a1.x, a0.y + a1.y);
       }
-      if (k < b) {
-        const double2 p0 = pr[k];
-        const double2 x0 = make_double2(sg * xr[k].x, xr[k].y);
-        a0.x += p0.x * x0.x - p0.y * x0.y;
-        a0.y += p0.x * x0.y + p0.y * x0.x;
+    } else {
+      // two rows per thread share each X_{B,i} operand
+      for (int q = t; q < sp2 * s; q += NT) {
+        const int r0 = (q / s) << 1, j = q - (q / s) * s;
+        const bool two = r0 + 1 < s;
+        const int r1 = two ? r0 + 1 : r0;
+        double2 a0 = lesser ? (src ? X[(int64_t)r0 * f + j] : cz()) : Ainv[r0 * s + j];
+        double2 a1 = lesser ? (src ? X[(int64_t)r1 * f + j] : cz()) : Ainv[r1 * s + j];
+        const double2* p0r = Psl + r0 * lb;
+        const double2* p1r = Psl + r1 * lb;
+        const double2* xr = XIB + j * lb;
+        for (int k = 0; k < b; ++k) {
+          const double2 x = make_double2(sg * xr[k].x, xr[k].y);
+          const double2 p0 = p0r[k], p1 = p1r[k];
+          a0.x += p0.x * x.x - p0.y * x.y;
+          a0.y += p0.x * x.y + p0.y * x.x;
+          a1.x += p1.x * x.x - p1.y * x.y;
+          a1.y += p1.x * x.y + p1.y * x.x;
+        }
+        X[(int64_t)r0 * f + j] = a0;
+        if (two) X[(int64_t)r1 * f + j] = a1;
       }
-      X[(int64_t)r * f + j] = make_double2(a0.x + a1.x, a0.y + a1.y);
     }
     if (inner) {
       for (int q = t; q < s * b; q += NT) {
