@@ -16,11 +16,11 @@
 namespace ndg {
 
 // ---------------------------------------------------------------------------
-// Fold: assemble the front [i, B_i] of A^(l) for cluster i.  The front holds
-// the rows of cluster i of A (its entries towards i and B_i, mirrored to the
-// B_i rows) plus the Schur contributions of its children, placed by the
-// children's relative index maps (extend-add, one child at a time so no two
-// threads write one entry at once).
+// Fold: assemble the rows of cluster i of the front [i, B_i] of A^(l): its
+// rows of A (entries towards i and B_i) plus the children's Schur
+// contributions that land in those rows (extend-add, one child at a time so
+// no two threads write one entry at once).  The B x B block of the front is
+// not formed: the Schur update gathers it from the children directly.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
   const int cl = cls[blockIdx.x];
@@ -32,51 +32,49 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
   double2* F = S + d.o_fg;
   const int f = d.f, s = d.s;
   const int t = threadIdx.x;
-  for (int64_t q = t; q < (int64_t)f * f; q += 256) F[q] = cz();
+  const double* hf = c.hfront + d.o_hf;
+  const int32_t* smp = d.o_smap >= 0 ? c.smap + d.o_smap : nullptr;
+  const double ez = c.E[eb + e];
+  // -H, z - V on the diagonal, -Sigma: every entry of the rows written once
+  for (int i = 0; i < s; ++i) {
+    const double vi = ez - (c.V ? c.V[c.perm[d.pt_off + i]] : 0.0);
+    for (int j = t; j < f; j += 256) {
+      double re = hf[i * f + j], im = 0.0;
+      if (j == i) {
+        re += vi;
+        im = c.eta;
+      }
+      if (smp) {
+        const int code = smp[i * f + j];
+        if (code >= 0) {
+          const int cc = code >> 24, nc = sel2(c.nc, cc);
+          const double2 sv = sel2(c.sig_r, cc)[(int64_t)(eb + e) * nc * nc + (code & 0xFFFFFF)];
+          re -= sv.x;
+          im -= sv.y;
+        }
+      }
+      F[(int64_t)i * f + j] = make_double2(re, im);
+    }
+  }
   __syncthreads();
+  // children's contributions to these rows
   for (int kp = c.kids_ptr[cl]; kp < c.kids_ptr[cl + 1]; ++kp) {
-    const int ch = c.kids[kp];
-    const ClusterDesc dc = c.cl[ch];
+    const ClusterDesc dc = c.cl[c.kids[kp]];
     const int bc = dc.b;
     const int32_t* rel = c.relmap + dc.bptr;
     const double2* U = S + dc.o_upd;
-    for (int64_t q = t; q < (int64_t)bc * bc; q += 256) {
-      const int r = (int)(q / bc), cc = (int)(q % bc);
-      const int64_t pos = (int64_t)rel[r] * f + rel[cc];
+    for (int q = t; q < bc * bc; q += 256) {
+      const int r = q / bc;
+      const int pr = rel[r];
+      if (pr >= s) continue;
+      const int cc = q - r * bc;
       const double2 u = U[q];
-      double2 v = F[pos];
+      double2 v = F[(int64_t)pr * f + rel[cc]];
       v.x += u.x;
       v.y += u.y;
-      F[pos] = v;
+      F[(int64_t)pr * f + rel[cc]] = v;
     }
     __syncthreads();
-  }
-  // rows of cluster i of -H (mirrored into the B_i rows: A is symmetric)
-  for (int p = d.hptr0 + t; p < d.hptr1; p += 256) {
-    const int r = c.hrow[p], fc = c.hcol[p];
-    const double hv = c.hval[p];
-    F[(int64_t)r * f + fc].x -= hv;
-    if (fc >= s) F[(int64_t)fc * f + r].x -= hv;
-  }
-  __syncthreads();
-  const double ez = c.E[eb + e];
-  for (int r = t; r < s; r += 256) {
-    const double v = c.V ? c.V[c.perm[d.pt_off + r]] : 0.0;
-    double2 a = F[(int64_t)r * f + r];
-    a.x += ez - v;
-    a.y += c.eta;
-    F[(int64_t)r * f + r] = a;
-  }
-  __syncthreads();
-  // contact self-energies: each entry of the front is listed once
-  for (int q = d.sptr0 + t; q < d.sptr1; q += 256) {
-    const int cc = c.scid[q], nc = c.nc[cc];
-    const double2 sv = c.sig_r[cc][(int64_t)(eb + e) * nc * nc + c.sflat[q]];
-    const int64_t pos = (int64_t)c.srow[q] * f + c.scol[q];
-    double2 v = F[pos];
-    v.x -= sv.x;
-    v.y -= sv.y;
-    F[pos] = v;
   }
 }
 
@@ -188,17 +186,77 @@ __global__ void __launch_bounds__(256) k_update(Ctx c, const UpdItem* items) {
   const int s = d.s, b = d.b, f = d.f;
   const int i0 = it.tr * 64, j0 = it.tc * 64;
   const int ni = min(64, b - i0), nj = min(64, b - j0);
+  // the children's index maps and contribution blocks (F_BB is gathered)
+  __shared__ int64_t kid_inv[kMaxKids], kid_upd[kMaxKids];
+  __shared__ int kid_b[kMaxKids];
+  const int k0 = c.kids_ptr[it.cl], nk = c.kids_ptr[it.cl + 1] - k0;
+  for (int q = threadIdx.x; q < nk; q += 256) {
+    const ClusterDesc& dc = c.cl[c.kids[k0 + q]];
+    kid_inv[q] = dc.o_pinv;
+    kid_upd[q] = dc.o_upd;
+    kid_b[q] = dc.b;
+  }
   typename GM::Tile acc;
   GM::zero(acc);
   GM::template acc<64, true, false>(
       s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
       [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm);
-  GM::template store<64>(acc, [&](int i, int j, double re, double im) {
-    if (i < ni && j < nj) {
-      const double2 fb = F[(int64_t)(s + i0 + i) * f + s + j0 + j];
-      U[(int64_t)(i0 + i) * b + j0 + j] = make_double2(fb.x + re, fb.y + im);
+  // F_BB gathered from the children: each lane holds fixed tile rows and
+  // columns (lane l, register r -> column l%16 of each 16 x 16 block and row
+  // l/16 + 4r for the FP64 matrix-core layout, 4(l/16) + r for the FP32
+  // one), so their map entries are loaded once per child; the sum is kept in
+  // FP64 and added when the tile is stored
+  using T = TileShape<64>;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = (w / T::WN) * (64 / T::WM), wc = (w % T::WN) * (64 / T::WN);
+  double cr[T::MB][T::NB][4], ci[T::MB][T::NB][4];
+#pragma unroll
+  for (int m = 0; m < T::MB; ++m)
+#pragma unroll
+    for (int n = 0; n < T::NB; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cr[m][n][r] = ci[m][n][r] = 0.0;
+  for (int q = 0; q < nk; ++q) {
+    const int32_t* inv = c.pinv + kid_inv[q];
+    const double2* Uq = S + kid_upd[q];
+    const int bq = kid_b[q];
+    int cj[T::NB], ri[T::MB][4];
+#pragma unroll
+    for (int n = 0; n < T::NB; ++n) {
+      const int j = wc + n * 16 + (lane & 15);
+      cj[n] = j < nj ? inv[s + j0 + j] : -1;
     }
-  });
+#pragma unroll
+    for (int m = 0; m < T::MB; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = wr + m * 16 + (P64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
+        ri[m][r] = i < ni ? inv[s + i0 + i] : -1;
+      }
+#pragma unroll
+    for (int m = 0; m < T::MB; ++m)
+#pragma unroll
+      for (int n = 0; n < T::NB; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (ri[m][r] >= 0 && cj[n] >= 0) {
+            const double2 u = Uq[(int64_t)ri[m][r] * bq + cj[n]];
+            cr[m][n][r] += u.x;
+            ci[m][n][r] += u.y;
+          }
+  }
+#pragma unroll
+  for (int m = 0; m < T::MB; ++m)
+#pragma unroll
+    for (int n = 0; n < T::NB; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = wr + m * 16 + (P64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
+        const int j = wc + n * 16 + (lane & 15);
+        if (i < ni && j < nj)
+          U[(int64_t)(i0 + i) * b + j0 + j] =
+              make_double2(cr[m][n][r] + (double)acc.re[m][n][r], ci[m][n][r] + (double)acc.im[m][n][r]);
+      }
 }
 
 // ---------------------------------------------------------------------------

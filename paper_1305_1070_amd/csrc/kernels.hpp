@@ -25,12 +25,11 @@ struct ClusterDesc {
   int32_t sptr0, sptr1;   // contact self-energy entries of this front
   int32_t chain_child[2]; // per contact: child on the contact's chain, -1 if none
   int32_t chain_mask;     // bit c: the cluster is on contact c's chain
-  // fronts of at most 64 points (assembled in registers): the cluster's rows
-  // of -H over the front (s x f, mirrored for the B rows), the contact
-  // self-energy index map (f x f, (contact << 24) | flat index, -1 where
-  // none; -1 offset if the front has no entries), and for a cluster whose
-  // parent is such a front, the parent's front positions -> index in this
-  // cluster's B (f_parent entries, -1 where absent)
+  // front assembly: the cluster's rows of -H over the front (s x f,
+  // mirrored for the B rows), the contact self-energy index map (f x f,
+  // (contact << 24) | flat index, -1 where none; -1 offset if the front has
+  // no entries), and the parent's front positions -> index in this
+  // cluster's B (f_parent entries, -1 where absent; -1 offset for a root)
   int64_t o_hf, o_smap, o_pinv;
 };
 
@@ -104,7 +103,8 @@ void launch_chain_back(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStr
 void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int front_size, hipStream_t st);
 void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, size_t lds_bytes,
                           int front_size, bool lesser, hipStream_t st);
-constexpr int kSmallFront = 64;  // fronts up to this size are handled whole on chip
+constexpr int kSmallFront = 64;
+constexpr int kMaxKids = 64;  // children per cluster (front assembly tables)  // fronts up to this size are handled whole on chip
 void launch_fill_zero(double* p, int64_t count, hipStream_t st);
 void launch_fill_zero_i32(int32_t* p, int64_t count, hipStream_t st);
 void launch_advance(int32_t* e0, const int32_t* inc, int n, hipStream_t st);

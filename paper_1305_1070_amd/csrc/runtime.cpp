@@ -317,14 +317,14 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
     for (int32_t ch : sy.children[k]) kids.push_back(ch);
     kids_ptr[k + 1] = (int32_t)kids.size();
   }
-  // register-assembled small fronts: -H rows, self-energy maps, child maps
+  // front assembly: -H rows, self-energy maps, children's index maps
   std::vector<double> hfront;
   std::vector<int32_t> smap, pinv;
   for (int k = 0; k < nc; ++k) {
     ClusterDesc& d = p->hdesc[k];
     d.o_hf = d.o_smap = d.o_pinv = -1;
     const int s_ = d.s, f = d.f;
-    if (f <= kSmallFront) {
+    {
       d.o_hf = (int64_t)hfront.size();
       hfront.resize(hfront.size() + (size_t)s_ * f, 0.0);
       double* hf = hfront.data() + d.o_hf;
@@ -338,13 +338,19 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
       }
     }
     const int par = sy.parent[k];
-    if (par >= 0 && sy.s(par) + sy.b(par) <= kSmallFront) {
+    if (par >= 0) {
       const int fp = sy.s(par) + sy.b(par);
       d.o_pinv = (int64_t)pinv.size();
       pinv.resize(pinv.size() + fp, -1);
       for (int r = 0; r < d.b; ++r) pinv[d.o_pinv + sy.relmap[sy.bptr[k] + r]] = r;
     }
   }
+  for (int k = 0; k < nc; ++k)
+    if ((int)sy.children[k].size() > kMaxKids) {
+      set_error("ndg_plan_create: a cluster has more than 64 children");
+      free_plan(p);
+      return NDG_EINVAL;
+    }
   for (int k = 0; k < nc; ++k)
     for (int64_t q = sy.sptr[k]; q < sy.sptr[k + 1]; ++q)
       if (sy.sflat[q] >= (1 << 24)) {
