@@ -259,12 +259,11 @@ ndg_status ndg_plan_status(ndg_plan* plan, int32_t* code, int32_t* energy, int32
 
 /* Test access: copies one stored block of the most recent batch of energies
  * to host memory.  which: 0 = pivot inverse (s x s), 1 = Psi (s x b),
- * 2 = front of G^r over [i, B_i] (f x f), 3 = front of G^< (f x f);
- * energy indexes the last batch (0 .. batch-1).  Row-major, host `out` of
- * s*s / s*b / f*f entries.  In fronts 2 and 3 the rows [0, s) hold the
- * cluster's final blocks G_ii, G_{i,B}; for a leaf cluster (no children)
- * with f <= 64 only the diagonal of G_ii is stored (nothing reads the rest).
- * Synchronises the device. */
+ * 2 = the cluster's rows of the G^r front over [i, B_i], i.e. [G_ii, G_{i,B}]
+ * (s x f), 3 = the same for G^< (s x f); energy indexes the last batch
+ * (0 .. batch-1).  Row-major, host `out` of s*s / s*b / s*f entries.  For a
+ * leaf cluster (no children) with f <= 64 only the diagonal of G_ii is
+ * stored (nothing reads the rest).  Synchronises the device. */
 ndg_status ndg_plan_export_block(ndg_plan* plan, int32_t which, int32_t energy, int32_t cluster,
                                  ndg_c128* out);
 

@@ -496,6 +496,21 @@ __device__ inline void raise_fault(int32_t* status, int code, int e, int cl) {
 
 __device__ inline double2* slab(const Ctx& c, int e) { return c.ws + (int64_t)e * c.stride; }
 
+// Entry (u, v) of X_{B,B} for a cluster with boundary B (X = G^r, or G^<
+// when lesser): read from the stored rows of the lower owning cluster, using
+// G^r_{yx} = G^r_{xy} and G^<_{yx} = -conj(G^<_{xy}) for the other order.
+__device__ inline double2 gather_bb(const Ctx& c, const double2* S, const ClusterDesc& d, int u,
+                                    int v, bool lesser) {
+  const int ru = c.grow[d.bptr + u], rv = c.grow[d.bptr + v];
+  const bool direct = (ru >> 16) <= (rv >> 16);
+  const int g = (direct ? ru : rv) >> 16;
+  const int row = (direct ? ru : rv) & 0xFFFF;
+  const int col = c.gcol[d.o_gcol + (int64_t)g * d.b + (direct ? v : u)];
+  const OwnerFront of = c.gown[d.o_gown + g];
+  const double2 x = S[(lesser ? of.ofp : of.ofg) + (int64_t)row * of.f + col];
+  return (direct || !lesser) ? x : make_double2(-x.x, x.y);
+}
+
 // First energy of the batch this launch processes.
 __device__ inline int ebase(const Ctx& c) { return c.e0p ? c.e0 + *c.e0p : c.e0; }
 

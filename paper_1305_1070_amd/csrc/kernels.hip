@@ -425,12 +425,11 @@ __global__ void __launch_bounds__(256) k_chain_back(Ctx c, const int32_t* cls) {
 }
 
 // ---------------------------------------------------------------------------
-// Extraction (top-down).  For cluster i with parent p:
-//   G_{i,B} = Psi_i G_{B,B},        G_{B,B} gathered from p's front,
-//   P_{i,B} = P_init + Psi_i P_{B,B},
-// one 64-column tile per block; the front of i also receives G_{B,i} =
-// G_{i,B}^T (P_{B,i} = -P_{i,B}^+) and the gathered B x B block, which i's
-// children read.
+// Extraction (top-down).  For cluster i:
+//   G_{i,B} = Psi_i G_{B,B},        P_{i,B} = P_init + Psi_i P_{B,B},
+// one 64-column tile per block.  G_{B,B} (P_{B,B}) is gathered from the
+// stored rows of the clusters owning B (gather_bb): every cluster keeps only
+// its own rows [G_ii, G_{i,B}], which its descendants read.
 // ---------------------------------------------------------------------------
 template <int TM, bool P64>
 __global__ void __launch_bounds__(256) k_down_off(Ctx c, const ColItem* items, int lesser) {
@@ -441,36 +440,24 @@ __global__ void __launch_bounds__(256) k_down_off(Ctx c, const ColItem* items, i
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
-  const ClusterDesc dp = c.cl[d.parent];
   double2* S = slab(c, e);
   const double2* Psi = S + d.o_psi;
   double2* X = S + (lesser ? d.o_fp : d.o_fg);
-  const double2* Xp = S + (lesser ? dp.o_fp : dp.o_fg);
-  const int32_t* rel = c.relmap + d.bptr;
-  const int s = d.s, b = d.b, f = d.f, fp = dp.f, j0 = it.tc * 64;
+  const int s = d.s, b = d.b, f = d.f, j0 = it.tc * 64;
   const int nj = min(64, b - j0);
-  const bool inner = c.kids_ptr[it.cl + 1] > c.kids_ptr[it.cl];
   const bool has_src = lesser && d.chain_mask;
-  const int t = threadIdx.x;
-  if (inner) {
-    for (int q = t; q < b * nj; q += 256) {
-      const int k = q / nj, j = q % nj;
-      X[(int64_t)(s + k) * f + s + j0 + j] = Xp[(int64_t)rel[k] * fp + rel[j0 + j]];
-    }
-  }
+  const bool ls = lesser != 0;
   typename GM::Tile acc;
   GM::zero(acc);
   GM::template acc<TM, false, false>(
       b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
-      [&](int k, int j) { return j < nj ? Xp[(int64_t)rel[k] * fp + rel[j0 + j]] : cz(); }, acc,
-      sm);
+      [&](int k, int j) { return j < nj ? gather_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm);
   GM::template store<TM>(acc, [&](int i, int j, double re, double im) {
     if (i < s && j < nj) {
       double2 v = make_double2(re, im);
       const int64_t pos = (int64_t)i * f + s + j0 + j;
       if (has_src) { const double2 p0 = X[pos]; v.x += p0.x; v.y += p0.y; }
       X[pos] = v;
-      if (inner) X[(int64_t)(s + j0 + j) * f + i] = lesser ? make_double2(-v.x, v.y) : v;
     }
   });
 }

@@ -13,8 +13,9 @@ struct ClusterDesc {
   int64_t o_ainv;   // s x s   pivot-block inverse (A_ii^(fold))^{-1}
   int64_t o_psi;    // s x b   Psi_{i,B_i} = -A_ii^{-1} A_{i,B_i}
   int64_t o_upd;    // b x b   Schur contribution passed to the parent front
-  int64_t o_fg;     // f x f   front of G^r over [i, B_i] (assembled front during the fold)
-  int64_t o_fp;     // f x f   front of G^< (rows i hold the source term before extraction)
+  int64_t o_fg;     // s x f   rows of cluster i of the front [i, B_i]: the assembled rows of A
+                    //         during the fold, then [G_ii, G_{i,B}] after the extraction
+  int64_t o_fp;     // s x f   [G^<_ii, G^<_{i,B}] (the source term before the extraction)
   int64_t o_zf[2];  // f x sc  per contact on whose chain the cluster lies: forward solve
   int64_t o_xf[2];  // f x sc  per contact: rows of the contact's column of G^r over the front
   int64_t o_t[2];   // s x sc  per contact: scratch
@@ -31,7 +32,14 @@ struct ClusterDesc {
   // no entries), and the parent's front positions -> index in this
   // cluster's B (f_parent entries, -1 where absent; -1 offset for a root)
   int64_t o_hf, o_smap, o_pinv;
+  // extraction gather: entry (u, v) of X_{B,B} lives in the stored rows of
+  // the lower of the clusters owning B[u] and B[v].  B is split into groups
+  // by owner (ascending); per group the owner's front (OwnerFront) and the
+  // column of every later-or-equal B entry in that front (b per group)
+  int64_t o_gown, o_gcol;
 };
+
+struct OwnerFront { int64_t ofg, ofp; int32_t f, pad; };
 
 struct UpdItem { int32_t cl, tr, tc, pad; };   // Schur update tile (rows tr*64.., cols tc*64..)
 struct ColItem { int32_t cl, tc; };            // column tile of an s x b panel
@@ -55,6 +63,9 @@ struct Ctx {
   const double* hfront;      // see ClusterDesc::o_hf
   const int32_t* smap;       // see ClusterDesc::o_smap
   const int32_t* pinv;       // see ClusterDesc::o_pinv
+  const int32_t* grow;       // per B entry: (owner group << 16) | row in the owner's front
+  const int32_t* gcol;       // see ClusterDesc::o_gcol
+  const OwnerFront* gown;    // see ClusterDesc::o_gown
   int32_t nc[2];
   int32_t ncontacts;
   int32_t n;

@@ -172,7 +172,8 @@ __global__ void __launch_bounds__(NT) k_fold_small_wide(Ctx c, const int32_t* cl
 }
 
 // Extraction of G^r (which = 0) or G^< (which = 1) for one small front; the
-// two run as separate launches on two streams.  Dynamic LDS holds
+// two run as separate launches on two streams.  X_{B,B} is gathered from the
+// stored rows of the clusters owning B (gather_bb).  Dynamic LDS holds
 // Psi (s x b), the gathered B x B block of the parent's front and X_{i,B}.
 // A leaf's blocks are read by nobody but the epilogue, so a leaf forms and
 // stores only the diagonal of X_ii.
@@ -199,19 +200,13 @@ __global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls,
     const int r = q / b, k = q - r * b;
     Psl[r * lb + k] = Psi[q];
   }
-  const int32_t* rel = c.relmap + d.bptr;
   {
     const int lesser = which;
     double2* X = S + (lesser ? d.o_fp : d.o_fg);
     const bool src = lesser && chain;
-    if (b > 0) {
-      const ClusterDesc dp = c.cl[d.parent];
-      const double2* Xp = S + (lesser ? dp.o_fp : dp.o_fg);
-      const int fp = dp.f;
-      for (int q = t; q < b * b; q += NT) {
-        const int k = q / b, j = q - k * b;
-        XBB[q] = Xp[(int64_t)rel[k] * fp + rel[j]];
-      }
+    for (int q = t; q < b * b; q += NT) {
+      const int k = q / b, j = q - k * b;
+      XBB[q] = gather_bb(c, S, d, k, j, lesser != 0);
     }
     __syncthreads();
     // X_{i,B} = P_init + Psi X_{B,B}: two rows per thread share each X_{B,B}
@@ -287,15 +282,10 @@ __global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls,
       }
     }
     if (inner) {
+      // the cluster's rows [X_ii, X_{i,B}] are what its descendants gather
       for (int q = t; q < s * b; q += NT) {
         const int r = q / b, j = q - r * b;
-        const double2 v = XIB[r * lb + j];
-        X[(int64_t)r * f + s + j] = v;
-        X[(int64_t)(s + j) * f + r] = lesser ? make_double2(-v.x, v.y) : v;
-      }
-      for (int q = t; q < b * b; q += NT) {
-        const int k = q / b, j = q - k * b;
-        X[(int64_t)(s + k) * f + s + j] = XBB[q];
+        X[(int64_t)r * f + s + j] = XIB[r * lb + j];
       }
     }
     __syncthreads();

@@ -46,6 +46,8 @@ struct ndg_plan {
   int32_t *d_srow = nullptr, *d_scol = nullptr, *d_scid = nullptr, *d_sflat = nullptr;
   double* d_hfront = nullptr;
   int32_t *d_smap = nullptr, *d_pinv = nullptr;
+  int32_t *d_grow = nullptr, *d_gcol = nullptr;
+  ndg::OwnerFront* d_gown = nullptr;
   int32_t* d_levels = nullptr;       // clusters by height
   ndg::ColItem* d_colitems = nullptr;
   ndg::UpdItem* d_upditems = nullptr;
@@ -132,8 +134,8 @@ int64_t layout(const Symbolic& sy, std::vector<ClusterDesc>& desc) {
     d.o_ainv = off; off = align8(off + s * s);
     d.o_psi = off;  off = align8(off + s * b);
     d.o_upd = off;  off = align8(off + b * b);
-    d.o_fg = off;   off = align8(off + f * f);
-    d.o_fp = off;   off = align8(off + f * f);
+    d.o_fg = off;   off = align8(off + s * f);   // rows [0, s) of the fronts
+    d.o_fp = off;   off = align8(off + s * f);
     for (int c = 0; c < 2; ++c) {
       d.chain_child[c] = chain_child[2 * k + c];
       d.o_zf[c] = d.o_xf[c] = d.o_t[c] = -1;
@@ -165,7 +167,7 @@ void free_plan(ndg_plan* p) {
                   p->d_chaincls,  p->d_ws,       p->d_status,     p->d_rY,         p->d_rX,
                   p->d_rG,        p->d_rZ,       p->d_ovec,       p->d_bidx,       p->d_part,
                   p->d_srow,      p->d_scol,     p->d_scid,       p->d_sflat,      p->d_hfront,
-                  p->d_smap,      p->d_pinv};
+                  p->d_smap,      p->d_pinv,     p->d_grow,       p->d_gcol,       p->d_gown};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& r : p->recs) {
@@ -293,14 +295,14 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
       addc(K_FOLD_SMALL, h, 8.0 * s * f * f, 16.0 * (kidb + s * s + s * b + b * b));
       for (int q : {K_EXTRACT_SMALL, K_EXTRACT_SMALL_P})
         addc(q, h, 8.0 * (s * b * b + s * s * b),
-             16.0 * (b * b + s * s + s * b + (inner ? s * b + b * b : 0.0)) + 16.0 * (s * b + s * s));
+             16.0 * (b * b + s * s + s * b) + 16.0 * (inner ? s * b + s * s : s));
     } else {
       addc(K_ASSEMBLE, h, 0.0, 16.0 * (f * f + kidb));
       addc(K_FACTOR, h, 8.0 * s * s * s, 16.0 * 2 * s * s);
       addc(K_PSI, h, 8.0 * s * s * b, 16.0 * (s * s + 2 * s * b));
       addc(K_UPDATE, h, 8.0 * s * b * b, 16.0 * (2 * s * b + 2 * b * b));
       for (int q : {K_DOWN_OFF_G, K_DOWN_OFF_P})
-        addc(q, h, 8.0 * s * b * b, 16.0 * (s * b + b * b + s * b + (inner ? s * b + b * b : 0.0)));
+        addc(q, h, 8.0 * s * b * b, 16.0 * (s * b + b * b + s * b));
       for (int q : {K_DOWN_DIAG_G, K_DOWN_DIAG_P}) addc(q, h, 8.0 * s * s * b, 16.0 * (2 * s * b + 2 * s * s));
     }
     for (int c = 0; c < p->ncontacts; ++c) {
@@ -345,6 +347,51 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
       for (int r = 0; r < d.b; ++r) pinv[d.o_pinv + sy.relmap[sy.bptr[k] + r]] = r;
     }
   }
+  // extraction gather tables (see ClusterDesc::o_gown)
+  std::vector<int32_t> grow(sy.bidx.size(), 0), gcol;
+  std::vector<OwnerFront> gown;
+  for (int k = 0; k < nc; ++k) {
+    ClusterDesc& d = p->hdesc[k];
+    d.o_gown = (int64_t)gown.size();
+    d.o_gcol = (int64_t)gcol.size();
+    const int b = d.b;
+    if (b == 0) continue;
+    const int32_t* B = sy.bidx.data() + sy.bptr[k];
+    std::vector<int> grp(b), own_of_grp;
+    for (int u = 0; u < b; ++u) {
+      const int a = sy.owner[B[u]];
+      if (u == 0 || a != own_of_grp.back()) {
+        own_of_grp.push_back(a);
+        const ClusterDesc& da = p->hdesc[a];
+        gown.push_back(OwnerFront{da.o_fg, da.o_fp, da.f, 0});
+      }
+      grp[u] = (int)own_of_grp.size() - 1;
+      grow[sy.bptr[k] + u] = (grp[u] << 16) | (B[u] - sy.cl_off[a]);
+    }
+    const int ng = (int)own_of_grp.size();
+    gcol.resize(gcol.size() + (size_t)ng * b, -1);
+    int32_t* gc = gcol.data() + d.o_gcol;
+    for (int g = 0; g < ng; ++g) {
+      const int a = own_of_grp[g];
+      const int32_t* Ba0 = sy.bidx.data() + sy.bptr[a];
+      const int32_t* Ba1 = sy.bidx.data() + sy.bptr[a + 1];
+      for (int v = 0; v < b; ++v) {
+        if (grp[v] < g) continue;
+        int pos;
+        if (sy.owner[B[v]] == a) pos = B[v] - sy.cl_off[a];
+        else {
+          const int32_t* it = std::lower_bound(Ba0, Ba1, B[v]);
+          if (it == Ba1 || *it != B[v]) {
+            set_error("internal: boundary entry missing from an ancestor's front");
+            free_plan(p);
+            return NDG_EINVAL;
+          }
+          pos = sy.s(a) + (int)(it - Ba0);
+        }
+        gc[(int64_t)g * b + v] = pos;
+      }
+    }
+  }
   for (int k = 0; k < nc; ++k)
     if ((int)sy.children[k].size() > kMaxKids) {
       set_error("ndg_plan_create: a cluster has more than 64 children");
@@ -366,6 +413,9 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   rc = rc ? rc : upload(&p->d_hfront, hfront.data(), hfront.size());
   rc = rc ? rc : upload(&p->d_smap, smap.data(), smap.size());
   rc = rc ? rc : upload(&p->d_pinv, pinv.data(), pinv.size());
+  rc = rc ? rc : upload(&p->d_grow, grow.data(), grow.size());
+  rc = rc ? rc : upload(&p->d_gcol, gcol.data(), gcol.size());
+  rc = rc ? rc : upload(&p->d_gown, gown.data(), gown.size());
   rc = rc ? rc : upload(&p->d_hrow, sy.hrow.data(), sy.hrow.size());
   rc = rc ? rc : upload(&p->d_hcol, sy.hcol.data(), sy.hcol.size());
   rc = rc ? rc : upload(&p->d_hval, sy.hval.data(), sy.hval.size());
@@ -530,6 +580,9 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   c.hfront = p->d_hfront;
   c.smap = p->d_smap;
   c.pinv = p->d_pinv;
+  c.grow = p->d_grow;
+  c.gcol = p->d_gcol;
+  c.gown = p->d_gown;
   c.perm = p->d_perm;
   c.owner = p->d_owner;
   c.ncontacts = p->ncontacts;
@@ -754,8 +807,8 @@ int plan_export_block(ndg_plan* p, int which, int energy, int cluster, ndg_c128*
   switch (which) {
     case 0: off = d.o_ainv; count = (int64_t)d.s * d.s; break;
     case 1: off = d.o_psi; count = (int64_t)d.s * d.b; break;
-    case 2: off = d.o_fg; count = (int64_t)d.f * d.f; break;
-    default: off = d.o_fp; count = (int64_t)d.f * d.f; break;
+    case 2: off = d.o_fg; count = (int64_t)d.s * d.f; break;
+    default: off = d.o_fp; count = (int64_t)d.s * d.f; break;
   }
   if (count == 0) return NDG_OK;
   if (hipSetDevice(p->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||

@@ -105,8 +105,8 @@ def test_stored_blocks_match_dense(lib):
             orig = perm[pts]
             f = len(pts)
             s = cl_off[c + 1] - cl_off[c]
-            fg = plan.export_block(2, k, c, (f, f))
-            fp = plan.export_block(3, k, c, (f, f))
+            fg = plan.export_block(2, k, c, (s, f))
+            fp = plan.export_block(3, k, c, (s, f))
             ref_g = g[np.ix_(orig, orig)]
             ref_p = gl[np.ix_(orig, orig)]
             if not has_kids[c] and f <= 64:
