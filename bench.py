@@ -139,7 +139,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=256, help="energies in flight per batch")
+    ap.add_argument("--batch", type=int, default=512, help="energies in flight per batch")
     ap.add_argument("--leaf", type=int, default=0,
                     help="leaf size of the separator tree (0: picked by the autotuner)")
     ap.add_argument("--energies", type=int, default=512)
