@@ -67,6 +67,30 @@ def _noop(_):
     return 0
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter profile
+    (profiles/traffic.json: FETCH_SIZE + WRITE_SIZE, scaled by a plain copy),
+    or None if that profile is of another kernel or of other library sources."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(here, "profiles", "traffic.json")) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    srcs = sorted(glob.glob(os.path.join(here, "paper_1305_1070_amd", "csrc", "*.hip")) +
+                  glob.glob(os.path.join(here, "paper_1305_1070_amd", "csrc", "*.hpp")) +
+                  glob.glob(os.path.join(here, "paper_1305_1070_amd", "csrc", "*.cpp")))
+    h = hashlib.sha256()
+    for p in srcs:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    if rec.get("kernel") != kernel or rec.get("sources_sha256") != h.hexdigest():
+        return None
+    return rec["bytes_per_launch"]
+
+
 def bench_batch(ndg, workloads, torch, cuda, n_devices=64, per_plan=4):
     """64 uneven devices x 128 energies, leaf size per width class from the
     autotuner, one captured graph replayed over the energy range."""
@@ -296,7 +320,7 @@ def main():
         roof = {"bound": "hbm", "achieved": dom["bytes"] / t_dom / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom["name"])
     roof["kernel"] = dom["name"]
     roof["launches"] = dom["launches"] // args.steps
     roof["avg_launch_us"] = dom["ms"] / dom["launches"] * 1e3
