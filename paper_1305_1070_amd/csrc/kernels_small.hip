@@ -304,20 +304,22 @@ void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, siz
   static bool attr_set = false;
   if (!attr_set) {
     // the gathered B x B block can exceed 64 KB; gfx950 gives a block up to 160 KB
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_extract_small<256>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_extract_small<512>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_extract_small<128>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_extract_small<256>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
   if (ncl <= 0) return;
   const int w = lesser ? 1 : 0;
+  // the larger classes hold few blocks per CU (LDS), so each block runs more
+  // threads: more independent outputs in flight per front
   if (front_size <= 32)
     hipLaunchKernelGGL((k_extract_small<64>), dim3(ncl, nb), dim3(64), lds_bytes, st, c, cls, w);
   else if (front_size <= 48)
-    hipLaunchKernelGGL((k_extract_small<128>), dim3(ncl, nb), dim3(128), lds_bytes, st, c, cls, w);
-  else
     hipLaunchKernelGGL((k_extract_small<256>), dim3(ncl, nb), dim3(256), lds_bytes, st, c, cls, w);
+  else
+    hipLaunchKernelGGL((k_extract_small<512>), dim3(ncl, nb), dim3(512), lds_bytes, st, c, cls, w);
 }
 
 }  // namespace ndg
