@@ -91,7 +91,7 @@ def measured_traffic(kernel):
     return rec["bytes_per_launch"]
 
 
-def bench_batch(ndg, workloads, torch, cuda, n_devices=64, per_plan=4):
+def bench_batch(ndg, workloads, torch, cuda, n_devices=64, per_plan=8):
     """64 uneven devices x 128 energies, leaf size per width class from the
     autotuner, one captured graph replayed over the energy range."""
     from paper_1305_1070_amd import autotune

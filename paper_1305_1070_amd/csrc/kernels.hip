@@ -513,23 +513,21 @@ __global__ void __launch_bounds__(256) k_down_diag(Ctx c, const int32_t* cls, in
 
 // diag G^r, G^<, G^> in the caller's site order; G^> = G^< + G^r - (G^r)^*.
 __global__ void __launch_bounds__(256) k_epilogue(Ctx c, double2* dgr, double2* dgl, double2* dgg) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int q = blockIdx.x * 256 + threadIdx.x;  // site in the caller's order
   const int e = blockIdx.y;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
-  if (p >= c.n) return;
-  const int cl = c.owner[p];
-  const ClusterDesc d = c.cl[cl];
-  const int r = p - d.pt_off;
+  if (q >= c.n) return;
+  const SiteDiag sd = c.sdiag[q];
   const double2* S = slab(c, e);
-  const double2 gr = S[d.o_fg + (int64_t)r * d.f + r];
-  const double2 gl = S[d.o_fp + (int64_t)r * d.f + r];
-  const int64_t o = (int64_t)(eb + e) * c.n + c.perm[p];
+  const double2 gr = S[sd.og];
+  const double2 gl = S[sd.ol];
+  const int64_t o = (int64_t)(eb + e) * c.n + q;
   dgr[o] = gr;
   dgl[o] = gl;
   if (dgg) dgg[o] = make_double2(gl.x, gl.y + 2.0 * gr.y);
   if (!isfinite(gr.x) || !isfinite(gr.y) || !isfinite(gl.x) || !isfinite(gl.y))
-    raise_fault(c.status, -7, eb + e, cl);
+    raise_fault(c.status, -7, eb + e, sd.cl);
 }
 
 // Graph replays over an energy range: each plan's first energy advances by

@@ -41,6 +41,10 @@ struct ClusterDesc {
 
 struct OwnerFront { int64_t ofg, ofp; int32_t f, pad; };
 
+// Per site in the caller's order: slab offsets of its diagonal entries in
+// the G^r and G^< fronts, and its cluster.
+struct SiteDiag { int64_t og, ol; int32_t cl, pad; };
+
 struct UpdItem { int32_t cl, tr, tc, pad; };   // Schur update tile (rows tr*64.., cols tc*64..)
 struct ColItem { int32_t cl, tc; };            // column tile of an s x b panel
 struct ChainItem { int32_t cl, c; };           // chain cluster and contact
@@ -66,6 +70,7 @@ struct Ctx {
   const int32_t* grow;       // per B entry: (owner group << 16) | row in the owner's front
   const int32_t* gcol;       // see ClusterDesc::o_gcol
   const OwnerFront* gown;    // see ClusterDesc::o_gown
+  const SiteDiag* sdiag;     // [n], caller's site order
   int32_t nc[2];
   int32_t ncontacts;
   int32_t n;

@@ -207,17 +207,15 @@ __global__ void k_vjp_reduce(Ctx c, RhsCtx r, int nb, const double* cE, double* 
 
 // density[perm[row]] += sum_e cE[e] Re(-i G^<_rr), energies in order.
 __global__ void k_density(Ctx c, int nb, const double* cE, double* dens) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= c.n) return;
-  const int cl = c.owner[p];
-  const ClusterDesc d = c.cl[cl];
-  const int rr = p - d.pt_off;
+  const int q = blockIdx.x * 256 + threadIdx.x;  // site in the caller's order
+  if (q >= c.n) return;
+  const int64_t ol = c.sdiag[q].ol;
   double acc = 0.0;
   for (int e = 0; e < nb; ++e) {
-    const double2 gl = (c.ws + (int64_t)e * c.stride)[d.o_fp + (int64_t)rr * d.f + rr];
+    const double2 gl = (c.ws + (int64_t)e * c.stride)[ol];
     acc += cE[c.e0 + e] * gl.y;  // Re(-i (x + i y)) = y
   }
-  dens[c.perm[p]] += acc;
+  dens[q] += acc;
 }
 
 void launch_rhs_contact(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st) {

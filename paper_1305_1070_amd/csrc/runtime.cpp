@@ -48,6 +48,7 @@ struct ndg_plan {
   int32_t *d_smap = nullptr, *d_pinv = nullptr;
   int32_t *d_grow = nullptr, *d_gcol = nullptr;
   ndg::OwnerFront* d_gown = nullptr;
+  ndg::SiteDiag* d_sdiag = nullptr;
   int32_t* d_levels = nullptr;       // clusters by height
   ndg::ColItem* d_colitems = nullptr;
   ndg::UpdItem* d_upditems = nullptr;
@@ -167,7 +168,8 @@ void free_plan(ndg_plan* p) {
                   p->d_chaincls,  p->d_ws,       p->d_status,     p->d_rY,         p->d_rX,
                   p->d_rG,        p->d_rZ,       p->d_ovec,       p->d_bidx,       p->d_part,
                   p->d_srow,      p->d_scol,     p->d_scid,       p->d_sflat,      p->d_hfront,
-                  p->d_smap,      p->d_pinv,     p->d_grow,       p->d_gcol,       p->d_gown};
+                  p->d_smap,      p->d_pinv,     p->d_grow,       p->d_gcol,       p->d_gown,
+                  p->d_sdiag};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& r : p->recs) {
@@ -392,6 +394,13 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
       }
     }
   }
+  std::vector<SiteDiag> sdiag(sy.n);
+  for (int64_t pn = 0; pn < sy.n; ++pn) {
+    const int k = sy.owner[pn];
+    const ClusterDesc& d = p->hdesc[k];
+    const int64_t r = pn - sy.cl_off[k];
+    sdiag[sy.perm[pn]] = SiteDiag{d.o_fg + r * d.f + r, d.o_fp + r * d.f + r, k, 0};
+  }
   for (int k = 0; k < nc; ++k)
     if ((int)sy.children[k].size() > kMaxKids) {
       set_error("ndg_plan_create: a cluster has more than 64 children");
@@ -416,6 +425,7 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   rc = rc ? rc : upload(&p->d_grow, grow.data(), grow.size());
   rc = rc ? rc : upload(&p->d_gcol, gcol.data(), gcol.size());
   rc = rc ? rc : upload(&p->d_gown, gown.data(), gown.size());
+  rc = rc ? rc : upload(&p->d_sdiag, sdiag.data(), sdiag.size());
   rc = rc ? rc : upload(&p->d_hrow, sy.hrow.data(), sy.hrow.size());
   rc = rc ? rc : upload(&p->d_hcol, sy.hcol.data(), sy.hcol.size());
   rc = rc ? rc : upload(&p->d_hval, sy.hval.data(), sy.hval.size());
@@ -583,6 +593,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   c.grow = p->d_grow;
   c.gcol = p->d_gcol;
   c.gown = p->d_gown;
+  c.sdiag = p->d_sdiag;
   c.perm = p->d_perm;
   c.owner = p->d_owner;
   c.ncontacts = p->ncontacts;
