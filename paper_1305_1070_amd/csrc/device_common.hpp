@@ -501,14 +501,9 @@ __device__ inline double2* slab(const Ctx& c, int e) { return c.ws + (int64_t)e 
 // G^r_{yx} = G^r_{xy} and G^<_{yx} = -conj(G^<_{xy}) for the other order.
 __device__ inline double2 gather_bb(const Ctx& c, const double2* S, const ClusterDesc& d, int u,
                                     int v, bool lesser) {
-  const int ru = c.grow[d.bptr + u], rv = c.grow[d.bptr + v];
-  const bool direct = (ru >> 16) <= (rv >> 16);
-  const int g = (direct ? ru : rv) >> 16;
-  const int row = (direct ? ru : rv) & 0xFFFF;
-  const int col = c.gcol[d.o_gcol + (int64_t)g * d.b + (direct ? v : u)];
-  const OwnerFront of = c.gown[d.o_gown + g];
-  const double2 x = S[(lesser ? of.ofp : of.ofg) + (int64_t)row * of.f + col];
-  return (direct || !lesser) ? x : make_double2(-x.x, x.y);
+  const int32_t m = c.gaddr[d.o_gaddr + (int64_t)u * d.b + v];
+  const double2 x = S[(int64_t)(m & 0x7FFFFFFF) + (lesser ? c.pdelta : 0)];
+  return (m < 0 && lesser) ? make_double2(-x.x, x.y) : x;
 }
 
 // First energy of the batch this launch processes.

@@ -32,14 +32,10 @@ struct ClusterDesc {
   // no entries), and the parent's front positions -> index in this
   // cluster's B (f_parent entries, -1 where absent; -1 offset for a root)
   int64_t o_hf, o_smap, o_pinv;
-  // extraction gather: entry (u, v) of X_{B,B} lives in the stored rows of
-  // the lower of the clusters owning B[u] and B[v].  B is split into groups
-  // by owner (ascending); per group the owner's front (OwnerFront) and the
-  // column of every later-or-equal B entry in that front (b per group)
-  int64_t o_gown, o_gcol;
+  // extraction gather: slab offsets of the entries of X_{B,B} (b x b int32,
+  // see Ctx::gaddr)
+  int64_t o_gaddr;
 };
-
-struct OwnerFront { int64_t ofg, ofp; int32_t f, pad; };
 
 // Per site in the caller's order: slab offsets of its diagonal entries in
 // the G^r and G^< fronts, and its cluster.
@@ -67,9 +63,12 @@ struct Ctx {
   const double* hfront;      // see ClusterDesc::o_hf
   const int32_t* smap;       // see ClusterDesc::o_smap
   const int32_t* pinv;       // see ClusterDesc::o_pinv
-  const int32_t* grow;       // per B entry: (owner group << 16) | row in the owner's front
-  const int32_t* gcol;       // see ClusterDesc::o_gcol
-  const OwnerFront* gown;    // see ClusterDesc::o_gown
+  // per cluster (ClusterDesc::o_gaddr), entry (u, v) of X_{B,B}: the slab
+  // offset of G^r(B[u], B[v]) in the stored rows of the lower owning
+  // cluster, bit 31 set when it is stored as G^r(B[v], B[u]); the G^< fronts
+  // lie pdelta entries after the G^r fronts
+  const int32_t* gaddr;
+  int64_t pdelta;
   const SiteDiag* sdiag;     // [n], caller's site order
   int32_t nc[2];
   int32_t ncontacts;

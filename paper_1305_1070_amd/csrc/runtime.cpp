@@ -46,8 +46,7 @@ struct ndg_plan {
   int32_t *d_srow = nullptr, *d_scol = nullptr, *d_scid = nullptr, *d_sflat = nullptr;
   double* d_hfront = nullptr;
   int32_t *d_smap = nullptr, *d_pinv = nullptr;
-  int32_t *d_grow = nullptr, *d_gcol = nullptr;
-  ndg::OwnerFront* d_gown = nullptr;
+  int32_t* d_gaddr = nullptr;
   ndg::SiteDiag* d_sdiag = nullptr;
   int32_t* d_levels = nullptr;       // clusters by height
   ndg::ColItem* d_colitems = nullptr;
@@ -117,7 +116,17 @@ int64_t layout(const Symbolic& sy, std::vector<ClusterDesc>& desc) {
       prev = k;
     }
   }
+  // the rows of the G^r fronts of all clusters first, then those of the G^<
+  // fronts in the same arrangement: a G^< entry sits a fixed distance after
+  // its G^r counterpart (one gather table serves both)
   int64_t off = 0;
+  for (int k = 0; k < nc; ++k) {
+    desc[k].o_fg = off;
+    off = align8(off + (int64_t)sy.s(k) * (sy.s(k) + sy.b(k)));
+  }
+  const int64_t pdelta = off;
+  for (int k = 0; k < nc; ++k) desc[k].o_fp = desc[k].o_fg + pdelta;
+  off = 2 * pdelta;
   for (int k = 0; k < nc; ++k) {
     ClusterDesc& d = desc[k];
     d.s = sy.s(k);
@@ -135,8 +144,6 @@ int64_t layout(const Symbolic& sy, std::vector<ClusterDesc>& desc) {
     d.o_ainv = off; off = align8(off + s * s);
     d.o_psi = off;  off = align8(off + s * b);
     d.o_upd = off;  off = align8(off + b * b);
-    d.o_fg = off;   off = align8(off + s * f);   // rows [0, s) of the fronts
-    d.o_fp = off;   off = align8(off + s * f);
     for (int c = 0; c < 2; ++c) {
       d.chain_child[c] = chain_child[2 * k + c];
       d.o_zf[c] = d.o_xf[c] = d.o_t[c] = -1;
@@ -168,8 +175,7 @@ void free_plan(ndg_plan* p) {
                   p->d_chaincls,  p->d_ws,       p->d_status,     p->d_rY,         p->d_rX,
                   p->d_rG,        p->d_rZ,       p->d_ovec,       p->d_bidx,       p->d_part,
                   p->d_srow,      p->d_scol,     p->d_scid,       p->d_sflat,      p->d_hfront,
-                  p->d_smap,      p->d_pinv,     p->d_grow,       p->d_gcol,       p->d_gown,
-                  p->d_sdiag};
+                  p->d_smap,      p->d_pinv,     p->d_gaddr,      p->d_sdiag};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& r : p->recs) {
@@ -349,50 +355,48 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
       for (int r = 0; r < d.b; ++r) pinv[d.o_pinv + sy.relmap[sy.bptr[k] + r]] = r;
     }
   }
-  // extraction gather tables (see ClusterDesc::o_gown)
-  std::vector<int32_t> grow(sy.bidx.size(), 0), gcol;
-  std::vector<OwnerFront> gown;
+  // extraction gather tables (see ClusterDesc::o_gaddr): entry (u, v) of
+  // X_{B,B} sits in the stored rows of the lower of the clusters owning B[u]
+  // and B[v] (B[u], B[v] are coupled after fill, so the other point is in
+  // that cluster's front)
+  std::vector<int32_t> gaddr;
+  const int64_t pdelta = p->hdesc.empty() ? 0 : p->hdesc[0].o_fp - p->hdesc[0].o_fg;
+  if (2 * pdelta >= (int64_t)1 << 31) {
+    set_error("ndg_plan_create: fronts exceed the 2^31-entry gather range");
+    free_plan(p);
+    return NDG_EINVAL;
+  }
   for (int k = 0; k < nc; ++k) {
     ClusterDesc& d = p->hdesc[k];
-    d.o_gown = (int64_t)gown.size();
-    d.o_gcol = (int64_t)gcol.size();
+    d.o_gaddr = (int64_t)gaddr.size();
     const int b = d.b;
     if (b == 0) continue;
     const int32_t* B = sy.bidx.data() + sy.bptr[k];
-    std::vector<int> grp(b), own_of_grp;
-    for (int u = 0; u < b; ++u) {
-      const int a = sy.owner[B[u]];
-      if (u == 0 || a != own_of_grp.back()) {
-        own_of_grp.push_back(a);
-        const ClusterDesc& da = p->hdesc[a];
-        gown.push_back(OwnerFront{da.o_fg, da.o_fp, da.f, 0});
-      }
-      grp[u] = (int)own_of_grp.size() - 1;
-      grow[sy.bptr[k] + u] = (grp[u] << 16) | (B[u] - sy.cl_off[a]);
-    }
-    const int ng = (int)own_of_grp.size();
-    gcol.resize(gcol.size() + (size_t)ng * b, -1);
-    int32_t* gc = gcol.data() + d.o_gcol;
-    for (int g = 0; g < ng; ++g) {
-      const int a = own_of_grp[g];
-      const int32_t* Ba0 = sy.bidx.data() + sy.bptr[a];
-      const int32_t* Ba1 = sy.bidx.data() + sy.bptr[a + 1];
+    gaddr.resize(gaddr.size() + (size_t)b * b);
+    int32_t* ga = gaddr.data() + d.o_gaddr;
+    for (int u = 0; u < b; ++u)
       for (int v = 0; v < b; ++v) {
-        if (grp[v] < g) continue;
+        const int ou = sy.owner[B[u]], ov = sy.owner[B[v]];
+        const bool direct = ou <= ov;  // post-order: the lower cluster has the smaller id
+        const int a = direct ? ou : ov;
+        const int32_t x = direct ? B[u] : B[v], y = direct ? B[v] : B[u];
         int pos;
-        if (sy.owner[B[v]] == a) pos = B[v] - sy.cl_off[a];
+        if (sy.owner[y] == a) pos = y - sy.cl_off[a];
         else {
-          const int32_t* it = std::lower_bound(Ba0, Ba1, B[v]);
-          if (it == Ba1 || *it != B[v]) {
+          const int32_t* Ba0 = sy.bidx.data() + sy.bptr[a];
+          const int32_t* Ba1 = sy.bidx.data() + sy.bptr[a + 1];
+          const int32_t* it = std::lower_bound(Ba0, Ba1, y);
+          if (it == Ba1 || *it != y) {
             set_error("internal: boundary entry missing from an ancestor's front");
             free_plan(p);
             return NDG_EINVAL;
           }
           pos = sy.s(a) + (int)(it - Ba0);
         }
-        gc[(int64_t)g * b + v] = pos;
+        const ClusterDesc& da = p->hdesc[a];
+        const int64_t o = da.o_fg + (int64_t)(x - sy.cl_off[a]) * da.f + pos;
+        ga[(int64_t)u * b + v] = (int32_t)o | (direct ? 0 : (int32_t)0x80000000);
       }
-    }
   }
   std::vector<SiteDiag> sdiag(sy.n);
   for (int64_t pn = 0; pn < sy.n; ++pn) {
@@ -422,9 +426,7 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   rc = rc ? rc : upload(&p->d_hfront, hfront.data(), hfront.size());
   rc = rc ? rc : upload(&p->d_smap, smap.data(), smap.size());
   rc = rc ? rc : upload(&p->d_pinv, pinv.data(), pinv.size());
-  rc = rc ? rc : upload(&p->d_grow, grow.data(), grow.size());
-  rc = rc ? rc : upload(&p->d_gcol, gcol.data(), gcol.size());
-  rc = rc ? rc : upload(&p->d_gown, gown.data(), gown.size());
+  rc = rc ? rc : upload(&p->d_gaddr, gaddr.data(), gaddr.size());
   rc = rc ? rc : upload(&p->d_sdiag, sdiag.data(), sdiag.size());
   rc = rc ? rc : upload(&p->d_hrow, sy.hrow.data(), sy.hrow.size());
   rc = rc ? rc : upload(&p->d_hcol, sy.hcol.data(), sy.hcol.size());
@@ -590,9 +592,8 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   c.hfront = p->d_hfront;
   c.smap = p->d_smap;
   c.pinv = p->d_pinv;
-  c.grow = p->d_grow;
-  c.gcol = p->d_gcol;
-  c.gown = p->d_gown;
+  c.gaddr = p->d_gaddr;
+  c.pdelta = p->hdesc.empty() ? 0 : p->hdesc[0].o_fp - p->hdesc[0].o_fg;
   c.sdiag = p->d_sdiag;
   c.perm = p->d_perm;
   c.owner = p->d_owner;
