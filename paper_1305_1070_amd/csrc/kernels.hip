@@ -63,10 +63,10 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
     const int bc = dc.b;
     const int32_t* rel = c.relmap + dc.bptr;
     const double2* U = S + dc.o_upd;
-    for (int q = t; q < bc * bc; q += 256) {
+    // only the leading dc.nself rows land in this cluster's rows
+    for (int q = t; q < dc.nself * bc; q += 256) {
       const int r = q / bc;
       const int pr = rel[r];
-      if (pr >= s) continue;
       const int cc = q - r * bc;
       const double2 u = U[q];
       double2 v = F[(int64_t)pr * f + rel[cc]];

@@ -35,6 +35,10 @@ struct ClusterDesc {
   // extraction gather: slab offsets of the entries of X_{B,B} (b x b int32,
   // see Ctx::gaddr)
   int64_t o_gaddr;
+  // leading entries of B owned by the parent (B is sorted and the parent's
+  // points precede its ancestors'): the rows of the contribution that land in
+  // the parent's own rows
+  int32_t nself, pad2;
 };
 
 // Per site in the caller's order: slab offsets of its diagonal entries in

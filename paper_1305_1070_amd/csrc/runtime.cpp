@@ -140,6 +140,9 @@ int64_t layout(const Symbolic& sy, std::vector<ClusterDesc>& desc) {
     d.sptr0 = (int32_t)sy.sptr[k];
     d.sptr1 = (int32_t)sy.sptr[k + 1];
     d.chain_mask = mask[k];
+    d.nself = 0;
+    if (d.parent >= 0)
+      for (int64_t q = sy.bptr[k]; q < sy.bptr[k + 1] && sy.owner[sy.bidx[q]] == d.parent; ++q) d.nself++;
     const int64_t s = d.s, b = d.b, f = d.f;
     d.o_ainv = off; off = align8(off + s * s);
     d.o_psi = off;  off = align8(off + s * b);
@@ -396,6 +399,16 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
         const ClusterDesc& da = p->hdesc[a];
         const int64_t o = da.o_fg + (int64_t)(x - sy.cl_off[a]) * da.f + pos;
         ga[(int64_t)u * b + v] = (int32_t)o | (direct ? 0 : (int32_t)0x80000000);
+      }
+  }
+  // the assembly relies on the parent's points leading each sorted B
+  for (int k = 0; k < nc; ++k) {
+    const ClusterDesc& d = p->hdesc[k];
+    for (int64_t q = sy.bptr[k] + d.nself; q < sy.bptr[k + 1]; ++q)
+      if (sy.owner[sy.bidx[q]] == d.parent) {
+        set_error("internal: parent's points do not lead a boundary set");
+        free_plan(p);
+        return NDG_EINVAL;
       }
   }
   std::vector<SiteDiag> sdiag(sy.n);
