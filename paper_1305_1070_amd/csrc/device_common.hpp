@@ -391,95 +391,117 @@ struct RegGJ {
   // wave-wide maximum of packed (magnitude, row) keys and the owners of row
   // p publish it; after a second barrier every thread applies
   // M[i][j] -= M[i][k] x_j (x_j = M[p][j] d, x_k = d) to its whole tile
-  // without branches, and the owners of row p then overwrite it with x.
+  // and the owners of row p then overwrite it with x.  The steps run in
+  // groups of JS (one register column q_k per group, unrolled), so the
+  // pivot column's register index is a constant; the pivot row's register
+  // slot m_p = p / RS is uniform over the block, and with several columns
+  // per thread the row is published from a branch per slot rather than
+  // through selects over all slots.
   __device__ bool run(Smem& sm, int s) {
     const int t = i0 * JS + jt, lane = t & 63;
     unsigned long long used = 0;
     bool ok = true;
-    for (int k = 0; k < s; ++k) {
-      const int buf = k & 1;
-      const int qk = k / JS;
-      if (jt == k % JS) {
 #pragma unroll
-        for (int m = 0; m < NR; ++m) {
-          double vr = 0.0, vi = 0.0;
+    for (int qk = 0; qk < NC; ++qk) {
+      for (int kj = 0; kj < JS; ++kj) {
+        const int k = qk * JS + kj;
+        if (k >= s) break;
+        const int buf = k & 1;
+        if (jt == kj) {
 #pragma unroll
-          for (int q = 0; q < NC; ++q)
-            if (q == qk) {
-              vr = re[m][q];
-              vi = im[m][q];
-              re[m][q] = 0.0;
-              im[m][q] = 0.0;
-            }
-          sm.col[buf][row(m)] = make_double2(vr, vi);
+          for (int m = 0; m < NR; ++m) {
+            sm.col[buf][row(m)] = make_double2(re[m][qk], im[m][qk]);
+            re[m][qk] = 0.0;
+            im[m][qk] = 0.0;
+          }
         }
-      }
-      __syncthreads();
-      // key = valid bit | magnitude |Re| + |Im| as a float (its bits order
-      // like the values; 16 mantissa bits kept) | (63 - row): the largest
-      // magnitude wins, near-ties go to the lower row; every unused row
-      // below s has the valid bit, so p is always a valid row (a NaN column
-      // picks a NaN row)
-      const double2 v = lane < s ? sm.col[buf][lane] : make_double2(0.0, 0.0);
-      unsigned key = 0;
-      if (lane < s && !((used >> lane) & 1ull)) {
-        const float mg = (float)(fabs(v.x) + fabs(v.y));
-        key = 0x80000000u | ((__float_as_uint(mg) >> 1) & 0x7FFFFFC0u) | (unsigned)(63 - lane);
-      }
-      key = wave_max_u32(key);
-      const int p = 63 - (int)(key & 63u);
-      const double2 a = make_double2(lane_read(v.x, p), lane_read(v.y, p));
-      const int mp = p / RS;
-      const bool own_p = i0 == p % RS;
-      if (own_p) {
+        __syncthreads();
+        // key = valid bit | magnitude |Re| + |Im| as a float (its bits
+        // order like the values; 16 mantissa bits kept) | (63 - row): the
+        // largest magnitude wins, near-ties go to the lower row; every
+        // unused row below s has the valid bit, so p is always a valid row
+        // (a NaN column picks a NaN row)
+        const double2 v = lane < s ? sm.col[buf][lane] : make_double2(0.0, 0.0);
+        unsigned key = 0;
+        if (lane < s && !((used >> lane) & 1ull)) {
+          const float mg = (float)(fabs(v.x) + fabs(v.y));
+          key = 0x80000000u | ((__float_as_uint(mg) >> 1) & 0x7FFFFFC0u) | (unsigned)(63 - lane);
+        }
+        key = wave_max_u32(key);
+        const int p = 63 - (int)(key & 63u);
+        const double2 a = make_double2(lane_read(v.x, p), lane_read(v.y, p));
+        const int mp = p / RS;
+        const bool own_p = i0 == p % RS;
+        if constexpr (NC > 1) {
 #pragma unroll
-        for (int q = 0; q < NC; ++q) {
+          for (int m = 0; m < NR; ++m) {
+            if (m == mp) {
+              // distinct per slot, so the branches are not merged into selects
+              asm volatile("; pivot row slot %0" ::"i"(m));
+              if (own_p) {
+#pragma unroll
+                for (int q = 0; q < NC; ++q) sm.row[buf][col(q)] = make_double2(re[m][q], im[m][q]);
+              }
+            }
+          }
+        } else if (own_p) {
           double vr = 0.0, vi = 0.0;
 #pragma unroll
           for (int m = 0; m < NR; ++m)
-            if (m == mp) { vr = re[m][q]; vi = im[m][q]; }
-          sm.row[buf][col(q)] = make_double2(vr, vi);
-        }
-      }
-      if (t == 0) { sm.piv[k] = p; sm.pinv[p] = k; }
-      used |= 1ull << p;
-      const double den = a.x * a.x + a.y * a.y;
-      double dr = 0.0, di = 0.0;
-      if (den > 0.0) {
-        const double r = recip_pos(den);
-        dr = a.x * r;
-        di = -a.y * r;
-      } else {
-        ok = false;
-      }
-      __syncthreads();
-      double2 ck[NR], pr[NC];
-#pragma unroll
-      for (int q = 0; q < NC; ++q) pr[q] = sm.row[buf][col(q)];
-#pragma unroll
-      for (int m = 0; m < NR; ++m) ck[m] = sm.col[buf][row(m)];
-      double xr[NC], xi[NC];
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const bool jk = col(q) == k;
-        xr[q] = jk ? dr : pr[q].x * dr - pr[q].y * di;
-        xi[q] = jk ? di : pr[q].x * di + pr[q].y * dr;
-#pragma unroll
-        for (int m = 0; m < NR; ++m) {
-          re[m][q] -= ck[m].x * xr[q] - ck[m].y * xi[q];
-          im[m][q] -= ck[m].x * xi[q] + ck[m].y * xr[q];
-        }
-      }
-      if (own_p) {
-#pragma unroll
-        for (int m = 0; m < NR; ++m)
-          if (m == mp) {
-#pragma unroll
-            for (int q = 0; q < NC; ++q) {
-              re[m][q] = xr[q];
-              im[m][q] = xi[q];
+            if (m == mp) {
+              vr = re[m][0];
+              vi = im[m][0];
             }
+          sm.row[buf][col(0)] = make_double2(vr, vi);
+        }
+        if (t == 0) {
+          sm.piv[k] = p;
+          sm.pinv[p] = k;
+        }
+        used |= 1ull << p;
+        const double den = a.x * a.x + a.y * a.y;
+        double dr = 0.0, di = 0.0;
+        if (den > 0.0) {
+          const double r = recip_pos(den);
+          dr = a.x * r;
+          di = -a.y * r;
+        } else {
+          ok = false;
+        }
+        __syncthreads();
+        double2 ck[NR], pr[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) pr[q] = sm.row[buf][col(q)];
+#pragma unroll
+        for (int m = 0; m < NR; ++m) ck[m] = sm.col[buf][row(m)];
+        double xr[NC], xi[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          xr[q] = fma(pr[q].x, dr, -pr[q].y * di);
+          xi[q] = fma(pr[q].x, di, pr[q].y * dr);
+          if (q == qk) {
+            xr[q] = jt == kj ? dr : xr[q];
+            xi[q] = jt == kj ? di : xi[q];
           }
+#pragma unroll
+          for (int m = 0; m < NR; ++m) {
+            re[m][q] = fma(-ck[m].x, xr[q], re[m][q]);
+            re[m][q] = fma(ck[m].y, xi[q], re[m][q]);
+            im[m][q] = fma(-ck[m].x, xi[q], im[m][q]);
+            im[m][q] = fma(-ck[m].y, xr[q], im[m][q]);
+          }
+        }
+        if (own_p) {
+#pragma unroll
+          for (int m = 0; m < NR; ++m)
+            if (m == mp) {
+#pragma unroll
+              for (int q = 0; q < NC; ++q) {
+                re[m][q] = xr[q];
+                im[m][q] = xi[q];
+              }
+            }
+        }
       }
     }
     __syncthreads();  // piv / pinv complete
