@@ -307,8 +307,8 @@ struct Gemm<true> {
   using Tile = ZTile;
   using Smem = GemmSmem;
   __device__ static void zero(Tile& a) { ztile_zero(a); }
-  template <int TM, bool AI, bool BK, class FA, class FB>
-  __device__ static void acc(int K, FA fa, FB fb, Tile& t, Smem& sm) { zgemm_acc_t<TM, AI, BK>(K, fa, fb, t, sm); }
+  template <int TM, bool AI, bool BK, bool PF = true, class FA, class FB>
+  __device__ static void acc(int K, FA fa, FB fb, Tile& t, Smem& sm) { zgemm_acc_t<TM, AI, BK, PF>(K, fa, fb, t, sm); }
   template <int TM, class FS>
   __device__ static void store(const Tile& t, FS fs) { ztile_store_t<TM>(t, fs); }
 };
@@ -317,7 +317,7 @@ struct Gemm<false> {
   using Tile = ZTile32;
   using Smem = GemmSmem32;
   __device__ static void zero(Tile& a) { ztile32_zero(a); }
-  template <int TM, bool AI, bool BK, class FA, class FB>
+  template <int TM, bool AI, bool BK, bool PF = true, class FA, class FB>
   __device__ static void acc(int K, FA fa, FB fb, Tile& t, Smem& sm) { zgemm32_acc_t<TM, AI, BK>(K, fa, fb, t, sm); }
   template <int TM, class FS>
   __device__ static void store(const Tile& t, FS fs) { ztile32_store_t<TM>(t, fs); }

@@ -79,10 +79,12 @@ struct ndg_plan {
   struct Rec { int kid, h; hipEvent_t a, b; double flops, bytes; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
-  // the G^< extraction (with the chain back substitution it needs) runs on a
-  // second stream, concurrent with the G^r extraction
-  hipStream_t side = nullptr;
+  // the G^< extraction runs on a second stream, concurrent with the G^r
+  // extraction; the chain back substitution it needs runs ahead of it on a
+  // third, which marks each finished height with an event
+  hipStream_t side = nullptr, chain = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::vector<hipEvent_t> ev_chain;  // [H + 1]
 };
 
 namespace ndg {
@@ -188,7 +190,10 @@ void free_plan(ndg_plan* p) {
   for (hipEvent_t ev : p->event_pool) (void)hipEventDestroy(ev);
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  for (hipEvent_t ev : p->ev_chain)
+    if (ev) (void)hipEventDestroy(ev);
   if (p->side) (void)hipStreamDestroy(p->side);
+  if (p->chain) (void)hipStreamDestroy(p->chain);
   delete p;
 }
 
@@ -468,9 +473,15 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   if (!rc) {
     // default priority, like every stream of the library
     if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&p->chain, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)
       rc = NDG_EHIP;
+    p->ev_chain.assign(p->max_height + 1, nullptr);
+    for (int h = 1; h <= p->max_height && !rc; ++h)
+      if (p->chaincl_ptr[h] > p->chaincl_ptr[h - 1] &&
+          hipEventCreateWithFlags(&p->ev_chain[h], hipEventDisableTiming) != hipSuccess)
+        rc = NDG_EHIP;
   }
   if (rc) {
     (void)hipGetLastError();
@@ -716,11 +727,13 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
       p->last_batch = nb;
       continue;
     }
-    // G^r extraction on st; chain back substitution and G^< extraction on
-    // the side stream (they write disjoint buffers and read the fold's
-    // factors only), joined before the epilogue.  Under stream capture (the
-    // batch graph) everything stays on st: forking the plan's own stream
-    // inside a capture crashed the HIP runtime.
+    // G^r extraction on st, G^< extraction on the side stream (they write
+    // disjoint buffers and read the fold's factors only), joined before the
+    // epilogue.  The chain back substitution reads only the fold's factors
+    // and its parent's panels, so it runs top-down on a third stream; the
+    // G^< extraction of a height waits for that height's chain clusters.
+    // Under stream capture (the batch graph) everything stays on st: forking
+    // the plan's own stream inside a capture crashed the HIP runtime.
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cap) != hipSuccess) cap = hipStreamCaptureStatusActive;
     const bool fork = cap == hipStreamCaptureStatusNone;
@@ -728,11 +741,21 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
     if (fork) {
       (void)hipEventRecord(p->ev_fork, st);
       (void)hipStreamWaitEvent(sp, p->ev_fork, 0);
+      (void)hipStreamWaitEvent(p->chain, p->ev_fork, 0);
+      for (int h = H; h >= 1; --h) {
+        const int k0 = p->chaincl_ptr[h - 1], nck = p->chaincl_ptr[h] - k0;
+        if (!nck) continue;
+        timed_on(p->chain, K_CHAIN_BACK, h, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, p->chain); });
+        (void)hipEventRecord(p->ev_chain[h], p->chain);
+      }
     }
     for (int h = H; h >= 1; --h) {
       const int k0 = p->chaincl_ptr[h - 1], nck = p->chaincl_ptr[h] - k0;
       // the G^< source on chain clusters first: the extraction of P reads it
-      if (nck) timed_on(sp, K_CHAIN_BACK, h, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, sp); });
+      if (nck) {
+        if (fork) (void)hipStreamWaitEvent(sp, p->ev_chain[h], 0);
+        else timed_on(sp, K_CHAIN_BACK, h, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, sp); });
+      }
       for (int q = 0; q < ndg_plan::kClasses; ++q) {
         const ndg_plan::Group& g = p->groups[h * ndg_plan::kClasses + q];
         if (!g.ncl) continue;
