@@ -167,6 +167,11 @@ k_fold_small(Ctx c, const int32_t* cls) {
   fold_small_body<SF, NT, JS>(c, cls);
 }
 template <int SF, int NT, int JS>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6)))
+k_fold_small_narrow(Ctx c, const int32_t* cls) {
+  fold_small_body<SF, NT, JS>(c, cls);
+}
+template <int SF, int NT, int JS>
 __global__ void __launch_bounds__(NT) k_fold_small_wide(Ctx c, const int32_t* cls) {
   fold_small_body<SF, NT, JS>(c, cls);
 }
@@ -178,7 +183,8 @@ __global__ void __launch_bounds__(NT) k_fold_small_wide(Ctx c, const int32_t* cl
 // A leaf's blocks are read by nobody but the epilogue, so a leaf forms and
 // stores only the diagonal of X_ii.
 template <int NT>
-__global__ void __launch_bounds__(NT) k_extract_small(Ctx c, const int32_t* cls, int which) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8)))
+k_extract_small(Ctx c, const int32_t* cls, int which) {
   extern __shared__ double2 sm[];
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
@@ -296,7 +302,7 @@ void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int fr
   if (ncl <= 0) return;
   // the variant follows the largest front of the group (padding costs work
   // in every elimination step)
-  if (front_size <= 24) hipLaunchKernelGGL((k_fold_small<24, 64, 8>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
+  if (front_size <= 24) hipLaunchKernelGGL((k_fold_small_narrow<24, 64, 8>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
   else if (front_size <= 32) hipLaunchKernelGGL((k_fold_small<32, 64, 32>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
   else if (front_size <= 40) hipLaunchKernelGGL((k_fold_small<40, 128, 8>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
   else if (front_size <= 48) hipLaunchKernelGGL((k_fold_small_wide<48, 128, 16>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
