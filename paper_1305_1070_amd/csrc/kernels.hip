@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
 
 // Psi_{i,B_i} = -A_ii^{-1} A_{i,B_i}: one 64-column tile per block.
 template <int TM>
-__global__ void __launch_bounds__(256) k_psi(Ctx c, const ColItem* items) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_psi(Ctx c, const ColItem* items) {
   __shared__ GemmSmem sm;
   const ColItem it = items[blockIdx.x];
   const int e = blockIdx.y;
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(256) k_psi(Ctx c, const ColItem* items) {
 // Schur contribution of cluster i to its parent front:
 // U = F_BB + Psi^T F_{i,B} (b x b), one 64 x 64 tile per block.
 template <bool P64>
-__global__ void __launch_bounds__(256) k_update(Ctx c, const UpdItem* items) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_update(Ctx c, const UpdItem* items) {
   using GM = Gemm<P64>;
   __shared__ typename GM::Smem sm;
   const UpdItem it = items[blockIdx.x];
@@ -198,13 +198,14 @@ __global__ void __launch_bounds__(256) k_update(Ctx c, const UpdItem* items) {
   }
   typename GM::Tile acc;
   GM::zero(acc);
-  GM::template acc<64, true, false>(
+  GM::template acc<64, true, false, false>(
       s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
       [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm);
   // F_BB gathered from the children: each lane holds fixed tile rows and
   // columns (lane l, register r -> column l%16 of each 16 x 16 block and row
   // l/16 + 4r for the FP64 matrix-core layout, 4(l/16) + r for the FP32
-  // one), so their map entries are loaded once per child; the sum is kept in
+  // one), so their map entries are loaded once per child.  FP64 tiles take
+  // the sum straight into the accumulators; with FP32 tiles it is kept in
   // FP64 and added when the tile is stored
   using T = TileShape<64>;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -241,8 +242,13 @@ __global__ void __launch_bounds__(256) k_update(Ctx c, const UpdItem* items) {
         for (int r = 0; r < 4; ++r)
           if (ri[m][r] >= 0 && cj[n] >= 0) {
             const double2 u = Uq[(int64_t)ri[m][r] * bq + cj[n]];
-            cr[m][n][r] += u.x;
-            ci[m][n][r] += u.y;
+            if constexpr (P64) {
+              acc.re[m][n][r] += u.x;
+              acc.im[m][n][r] += u.y;
+            } else {
+              cr[m][n][r] += u.x;
+              ci[m][n][r] += u.y;
+            }
           }
   }
 #pragma unroll
@@ -266,7 +272,7 @@ __global__ void __launch_bounds__(256) k_update(Ctx c, const UpdItem* items) {
 // (passed up as V_d = Psi_d^T Z_d over B_d), then Zd_i = A_ii^{-1} Z_i.
 // Zf rows [0, s) end up holding Zd_i, rows [s, f) the contribution V_i.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_chain_fwd(Ctx c, const ChainItem* items) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_chain_fwd(Ctx c, const ChainItem* items) {
   __shared__ GemmSmem sm;
   const ChainItem it = items[blockIdx.x];
   const int e = blockIdx.y;
@@ -340,7 +346,7 @@ __global__ void __launch_bounds__(256) k_chain_fwd(Ctx c, const ChainItem* items
 // P_init = sum_c Zd_i Sigma^<_c (X_front)^+ (s x f), written into rows [0, s)
 // of the G^< front.  This is D^{-1} L^{-1} Sigma^< (G^r)^+ restricted to the
 // front, evaluated as (L^{-1} Sigma^<)(G^r)^+ so only s x sc panels are folded.
-__global__ void __launch_bounds__(256) k_chain_back(Ctx c, const int32_t* cls) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_chain_back(Ctx c, const int32_t* cls) {
   __shared__ GemmSmem sm;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
@@ -432,7 +438,7 @@ __global__ void __launch_bounds__(256) k_chain_back(Ctx c, const int32_t* cls) {
 // its own rows [G_ii, G_{i,B}], which its descendants read.
 // ---------------------------------------------------------------------------
 template <int TM, bool P64>
-__global__ void __launch_bounds__(256) k_down_off(Ctx c, const ColItem* items, int lesser) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_down_off(Ctx c, const ColItem* items, int lesser) {
   using GM = Gemm<P64>;
   __shared__ typename GM::Smem sm;
   const ColItem it = items[blockIdx.x];
@@ -465,7 +471,7 @@ __global__ void __launch_bounds__(256) k_down_off(Ctx c, const ColItem* items, i
 //   G_ii = A_ii^{-1} + Psi_i G_{B,i},  G_{B,i} = G_{i,B}^T
 //   P_ii = P_init + Psi_i P_{B,i},     P_{B,i} = -P_{i,B}^+
 template <int TM, bool P64>
-__global__ void __launch_bounds__(256) k_down_diag(Ctx c, const int32_t* cls, int lesser) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_down_diag(Ctx c, const int32_t* cls, int lesser) {
   using GM = Gemm<P64>;
   __shared__ typename GM::Smem sm;
   const int cl = cls[blockIdx.x];
