@@ -12,10 +12,14 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int KC = 16;  // K chunk staged in LDS per step
 
-struct GemmSmem {
-  double ar[64][KC + 1], ai[64][KC + 1];
+// A staged for R rows (R >= the tile's TM: smaller tiles take less LDS, so
+// more blocks fit on a CU), B for 64 columns
+template <int R>
+struct GemmSmemR {
+  double ar[R][KC + 1], ai[R][KC + 1];
   double br[KC][64 + 1], bi[KC][64 + 1];
 };
+using GemmSmem = GemmSmemR<64>;
 
 struct ZTile {
   v4d re[2][2];
@@ -62,8 +66,9 @@ struct TileShape {
 // matrix cores work on chunk k0 (the global-load latency hides behind the
 // MFMAs); kernels that inline several products turn it off to stay within
 // the register file.
-template <int TM, bool A_IFAST, bool B_KFAST, bool PF = true, class FA, class FB>
-__device__ void zgemm_acc_t(int K, FA fa, FB fb, ZTile& acc, GemmSmem& sm) {
+template <int TM, bool A_IFAST, bool B_KFAST, bool PF = true, int R = 64, class FA, class FB>
+__device__ void zgemm_acc_t(int K, FA fa, FB fb, ZTile& acc, GemmSmemR<R>& sm) {
+  static_assert(R >= TM, "staging rows");
   using T = TileShape<TM>;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
@@ -186,10 +191,12 @@ __device__ inline void ztile_store(const ZTile& acc, FS fs) {
 // row 4 (l / 16) + r, column l % 16.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-struct GemmSmem32 {
-  float ar[64][KC + 1], ai[64][KC + 1];
+template <int R>
+struct GemmSmem32R {
+  float ar[R][KC + 1], ai[R][KC + 1];
   float br[KC][64 + 1], bi[KC][64 + 1];
 };
+using GemmSmem32 = GemmSmem32R<64>;
 
 struct ZTile32 {
   v4f re[2][2];
@@ -206,8 +213,9 @@ __device__ inline void ztile32_zero(ZTile32& a) {
     }
 }
 
-template <int TM, bool A_IFAST, bool B_KFAST, class FA, class FB>
-__device__ void zgemm32_acc_t(int K, FA fa, FB fb, ZTile32& acc, GemmSmem32& sm) {
+template <int TM, bool A_IFAST, bool B_KFAST, int R = 64, class FA, class FB>
+__device__ void zgemm32_acc_t(int K, FA fa, FB fb, ZTile32& acc, GemmSmem32R<R>& sm) {
+  static_assert(R >= TM, "staging rows");
   using T = TileShape<TM>;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
@@ -306,9 +314,11 @@ template <>
 struct Gemm<true> {
   using Tile = ZTile;
   using Smem = GemmSmem;
+  template <int R>
+  using SmemT = GemmSmemR<R>;
   __device__ static void zero(Tile& a) { ztile_zero(a); }
-  template <int TM, bool AI, bool BK, bool PF = true, class FA, class FB>
-  __device__ static void acc(int K, FA fa, FB fb, Tile& t, Smem& sm) { zgemm_acc_t<TM, AI, BK, PF>(K, fa, fb, t, sm); }
+  template <int TM, bool AI, bool BK, bool PF = true, int R, class FA, class FB>
+  __device__ static void acc(int K, FA fa, FB fb, Tile& t, SmemT<R>& sm) { zgemm_acc_t<TM, AI, BK, PF>(K, fa, fb, t, sm); }
   template <int TM, class FS>
   __device__ static void store(const Tile& t, FS fs) { ztile_store_t<TM>(t, fs); }
 };
@@ -316,9 +326,11 @@ template <>
 struct Gemm<false> {
   using Tile = ZTile32;
   using Smem = GemmSmem32;
+  template <int R>
+  using SmemT = GemmSmem32R<R>;
   __device__ static void zero(Tile& a) { ztile32_zero(a); }
-  template <int TM, bool AI, bool BK, bool PF = true, class FA, class FB>
-  __device__ static void acc(int K, FA fa, FB fb, Tile& t, Smem& sm) { zgemm32_acc_t<TM, AI, BK>(K, fa, fb, t, sm); }
+  template <int TM, bool AI, bool BK, bool PF = true, int R, class FA, class FB>
+  __device__ static void acc(int K, FA fa, FB fb, Tile& t, SmemT<R>& sm) { zgemm32_acc_t<TM, AI, BK>(K, fa, fb, t, sm); }
   template <int TM, class FS>
   __device__ static void store(const Tile& t, FS fs) { ztile32_store_t<TM>(t, fs); }
 };

@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
 // Psi_{i,B_i} = -A_ii^{-1} A_{i,B_i}: one 64-column tile per block.
 template <int TM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_psi(Ctx c, const ColItem* items) {
-  __shared__ GemmSmem sm;
+  __shared__ GemmSmemR<TM> sm;
   const ColItem it = items[blockIdx.x];
   const int e = blockIdx.y;
   const int eb = ebase(c);
@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 template <int TM, bool P64>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_down_off(Ctx c, const ColItem* items, int lesser) {
   using GM = Gemm<P64>;
-  __shared__ typename GM::Smem sm;
+  __shared__ typename GM::template SmemT<TM> sm;
   const ColItem it = items[blockIdx.x];
   const int e = blockIdx.y;
   const int eb = ebase(c);
@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 template <int TM, bool P64>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_down_diag(Ctx c, const int32_t* cls, int lesser) {
   using GM = Gemm<P64>;
-  __shared__ typename GM::Smem sm;
+  __shared__ typename GM::template SmemT<TM> sm;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
   const int eb = ebase(c);
