@@ -210,9 +210,21 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
     const int lesser = which;
     double2* X = S + (lesser ? d.o_fp : d.o_fg);
     const bool src = lesser && chain;
-    for (int q = t; q < b * b; q += NT) {
-      const int k = q / b, j = q - k * b;
-      XBB[q] = gather_bb(c, S, d, k, j, lesser != 0);
+    // X_{B,B} is complex symmetric for G^r and anti-Hermitian for G^<
+    // (X_vu = -conj(X_uv)): the upper triangle is gathered and mirrored.
+    // Entry q of the triangle is (k, j), k <= j, rows of length b - k
+    // starting at k b - k (k - 1) / 2.
+    const int ntri = b * (b + 1) / 2;
+    const float bh = (float)b + 0.5f;
+    for (int q = t; q < ntri; q += NT) {
+      int k = (int)(bh - sqrtf(bh * bh - 2.0f * (float)q));
+      k = min(max(k, 0), b - 1);
+      if (k * b - (k * (k - 1) >> 1) > q) --k;
+      else if (k + 1 < b && (k + 1) * b - ((k + 1) * k >> 1) <= q) ++k;
+      const int j = k + q - (k * b - (k * (k - 1) >> 1));
+      const double2 x = gather_bb(c, S, d, k, j, lesser != 0);
+      XBB[k * b + j] = x;
+      if (j != k) XBB[j * b + k] = lesser ? make_double2(-x.x, x.y) : x;
     }
     __syncthreads();
     // X_{i,B} = P_init + Psi X_{B,B}: two rows per thread share each X_{B,B}
