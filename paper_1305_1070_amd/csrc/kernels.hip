@@ -36,25 +36,24 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
   const int32_t* smp = d.o_smap >= 0 ? c.smap + d.o_smap : nullptr;
   const double ez = c.E[eb + e];
   // -H, z - V on the diagonal, -Sigma: every entry of the rows written once
-  for (int i = 0; i < s; ++i) {
-    const double vi = ez - (c.V ? c.V[c.perm[d.pt_off + i]] : 0.0);
-    for (int j = t; j < f; j += 256) {
-      double re = hf[i * f + j], im = 0.0;
-      if (j == i) {
-        re += vi;
-        im = c.eta;
-      }
-      if (smp) {
-        const int code = smp[i * f + j];
-        if (code >= 0) {
-          const int cc = code >> 24, nc = sel2(c.nc, cc);
-          const double2 sv = sel2(c.sig_r, cc)[(int64_t)(eb + e) * nc * nc + (code & 0xFFFFFF)];
-          re -= sv.x;
-          im -= sv.y;
-        }
-      }
-      F[(int64_t)i * f + j] = make_double2(re, im);
+  // (one pass over all s f entries, so short rows do not idle threads)
+  for (int q = t; q < s * f; q += 256) {
+    const int i = q / f, j = q - i * f;
+    double re = hf[q], im = 0.0;
+    if (j == i) {
+      re += ez - (c.V ? c.V[c.perm[d.pt_off + i]] : 0.0);
+      im = c.eta;
     }
+    if (smp) {
+      const int code = smp[q];
+      if (code >= 0) {
+        const int cc = code >> 24, nc = sel2(c.nc, cc);
+        const double2 sv = sel2(c.sig_r, cc)[(int64_t)(eb + e) * nc * nc + (code & 0xFFFFFF)];
+        re -= sv.x;
+        im -= sv.y;
+      }
+    }
+    F[q] = make_double2(re, im);
   }
   __syncthreads();
   // children's contributions to these rows
