@@ -69,8 +69,9 @@ def _noop(_):
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter profile
-    (profiles/traffic.json: FETCH_SIZE + WRITE_SIZE, scaled by a plain copy),
-    or None if that profile is of another kernel or of other library sources."""
+    (profiles/traffic.json: FETCH_SIZE + WRITE_SIZE per kernel, scaled by a
+    plain copy), or None if the profile lacks that kernel or is of other
+    library sources."""
     import glob
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
@@ -86,9 +87,10 @@ def measured_traffic(kernel):
     for p in srcs:
         with open(p, "rb") as f:
             h.update(f.read())
-    if rec.get("kernel") != kernel or rec.get("sources_sha256") != h.hexdigest():
+    if rec.get("sources_sha256") != h.hexdigest():
         return None
-    return rec["bytes_per_launch"]
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["bytes_per_launch"]
 
 
 def bench_batch(ndg, workloads, torch, cuda, n_devices=64, per_plan=8):
