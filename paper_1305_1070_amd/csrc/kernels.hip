@@ -83,7 +83,9 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
 // ---------------------------------------------------------------------------
 template <int SM, int NT>
 __global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
-  using GJ = RegGJ<SM, NT, SM>;
+  // column groups of 16 (8 for the 16-point class): several columns per
+  // thread, so the pivot row is published from a branch per register slot
+  using GJ = RegGJ<SM, NT, (SM == 16 ? 8 : 16)>;
   __shared__ typename GJ::Smem sm;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
