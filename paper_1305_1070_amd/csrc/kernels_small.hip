@@ -316,7 +316,7 @@ void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int fr
   // in every elimination step)
   if (front_size <= 24) hipLaunchKernelGGL((k_fold_small_narrow<24, 64, 8>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
   else if (front_size <= 32) hipLaunchKernelGGL((k_fold_small<32, 64, 8>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
-  else if (front_size <= 40) hipLaunchKernelGGL((k_fold_small<40, 128, 8>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
+  else if (front_size <= 40) hipLaunchKernelGGL((k_fold_small<40, 128, 16>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
   else if (front_size <= 48) hipLaunchKernelGGL((k_fold_small_wide<48, 128, 16>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
   else hipLaunchKernelGGL((k_fold_small<64, 256, 16>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
 }
