@@ -45,6 +45,13 @@ __device__ inline T sel2(const T (&a)[2], int cc) { return cc ? a[1] : a[0]; }
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+// acc += p x as four FMAs
+__device__ inline void cmac(double2& acc, double2 p, double2 x) {
+  acc.x = fma(p.x, x.x, acc.x);
+  acc.x = fma(-p.y, x.y, acc.x);
+  acc.y = fma(p.x, x.y, acc.y);
+  acc.y = fma(p.y, x.x, acc.y);
+}
 
 // Tile shapes: a 256-thread block computes a TM x 64 complex tile, TM in
 // {64, 32, 16} (TM follows the cluster size so small clusters do not fill

@@ -240,10 +240,8 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
       for (int k = 0; k < b; ++k) {
         const double2 x = XBB[k * b + j];
         const double2 p0 = p0r[k], p1 = p1r[k];
-        a0.x += p0.x * x.x - p0.y * x.y;
-        a0.y += p0.x * x.y + p0.y * x.x;
-        a1.x += p1.x * x.x - p1.y * x.y;
-        a1.y += p1.x * x.y + p1.y * x.x;
+        cmac(a0, p0, x);
+        cmac(a1, p1, x);
       }
       XIB[r0 * lb + j] = a0;
       if (two) XIB[(r0 + 1) * lb + j] = a1;
@@ -261,19 +259,10 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
         int k = 0;
         for (; k + 1 < b; k += 2) {
           const double2 p0 = pr[k], p1 = pr[k + 1];
-          const double2 x0 = make_double2(sg * xr[k].x, xr[k].y);
-          const double2 x1 = make_double2(sg * xr[k + 1].x, xr[k + 1].y);
-          a0.x += p0.x * x0.x - p0.y * x0.y;
-          a0.y += p0.x * x0.y + p0.y * x0.x;
-          a1.x += p1.x * x1.x - p1.y * x1.y;
-          a1.y += p1.x * x1.y + p1.y * x1.x;
+          cmac(a0, p0, make_double2(sg * xr[k].x, xr[k].y));
+          cmac(a1, p1, make_double2(sg * xr[k + 1].x, xr[k + 1].y));
         }
-        if (k < b) {
-          const double2 p0 = pr[k];
-          const double2 x0 = make_double2(sg * xr[k].x, xr[k].y);
-          a0.x += p0.x * x0.x - p0.y * x0.y;
-          a0.y += p0.x * x0.y + p0.y * x0.x;
-        }
+        if (k < b) cmac(a0, pr[k], make_double2(sg * xr[k].x, xr[k].y));
         X[(int64_t)r * f + r] = make_double2(a0.x + a1.x, a0.y + a1.y);
       }
     } else {
@@ -289,11 +278,8 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
         const double2* xr = XIB + j * lb;
         for (int k = 0; k < b; ++k) {
           const double2 x = make_double2(sg * xr[k].x, xr[k].y);
-          const double2 p0 = p0r[k], p1 = p1r[k];
-          a0.x += p0.x * x.x - p0.y * x.y;
-          a0.y += p0.x * x.y + p0.y * x.x;
-          a1.x += p1.x * x.x - p1.y * x.y;
-          a1.y += p1.x * x.y + p1.y * x.x;
+          cmac(a0, p0r[k], x);
+          cmac(a1, p1r[k], x);
         }
         X[(int64_t)r0 * f + j] = a0;
         if (two) X[(int64_t)r1 * f + j] = a1;
