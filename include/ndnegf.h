@@ -141,6 +141,8 @@ ndg_status ndg_symbolic_arrays(const ndg_symbolic* sy, int32_t* perm, int32_t* c
  */
 ndg_status ndg_plan_create(const ndg_symbolic* sy, int32_t max_batch, int32_t device,
                            ndg_plan** out);
+/* Waits for all work on the plan's device (solves still in flight use its
+ * memory), then frees the plan.  NULL is a no-op. */
 ndg_status ndg_plan_destroy(ndg_plan* plan);
 ndg_status ndg_plan_info(const ndg_plan* plan, ndg_info* out);
 
@@ -247,6 +249,8 @@ typedef struct {
 } ndg_solve_args;
 
 ndg_status ndg_batch_create(int32_t nplans, ndg_plan* const* plans, ndg_batch** out);
+/* Waits for all work on the batch's device (graph replays still in flight),
+ * then frees the batch; the plans are the caller's and stay.  NULL is a no-op. */
 ndg_status ndg_batch_destroy(ndg_batch* batch);
 ndg_status ndg_batch_solve(ndg_batch* batch, const ndg_solve_args* args, ndg_precision prec,
                            void* stream);

@@ -21,6 +21,7 @@
 #include "runtime.hpp"
 
 struct ndg_batch {
+  int device = -1;
   std::vector<ndg_plan*> plans;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> done;
@@ -85,6 +86,7 @@ ndg_status ndg_batch_create(int32_t nplans, ndg_plan* const* plans, ndg_batch** 
       ndg::set_error("ndg_batch_create: the plans must live on one device");
       return NDG_EINVAL;
     }
+  b->device = dev;
   if (hipSetDevice(dev) != hipSuccess ||
       hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
     delete b;
@@ -119,6 +121,8 @@ ndg_status ndg_batch_create(int32_t nplans, ndg_plan* const* plans, ndg_batch** 
 
 ndg_status ndg_batch_destroy(ndg_batch* b) {
   if (!b) return NDG_OK;
+  // replays still in flight read the graph and the offsets freed below
+  if (b->device >= 0 && hipSetDevice(b->device) == hipSuccess) (void)hipDeviceSynchronize();
   release_graph(b);
   for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
   for (hipEvent_t e : b->done) (void)hipEventDestroy(e);

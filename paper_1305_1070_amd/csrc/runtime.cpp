@@ -513,7 +513,9 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
 
 int plan_destroy(ndg_plan* plan) {
   if (!plan) return NDG_OK;
-  (void)hipSetDevice(plan->device);
+  // solves still in flight (on the caller's stream or the plan's own) use
+  // the workspace and tables freed below
+  if (hipSetDevice(plan->device) == hipSuccess) (void)hipDeviceSynchronize();
   free_plan(plan);
   return NDG_OK;
 }
