@@ -180,8 +180,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU; runs on more than one GPU are not part of this build "
-              "(the method shards over energies; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: multi-GPU runs are not implemented (energies are "
+              "independent, so N GPUs would each solve a contiguous energy range and all-reduce "
+              "the density)", file=sys.stderr)
         sys.exit(2)
 
     import torch
