@@ -55,11 +55,112 @@ __global__ void k_rhs_lambda(Ctx c, RhsCtx r) {
   }
 }
 
-// Forward substitution and D^{-1} for one cluster (bottom-up by levels):
-// the front vector Zf (f x m) gathers the children's contributions, adds the
-// cluster's rows of Y, passes V = Zf_B + Psi^T Z_I up, and stores
-// D^{-1} Z_I = A_ii^{-1} Z_I in the cluster's rows of X.
+// Lane layout of a 64 x 64 FP64 matrix-core tile (TileShape<64>): lane l,
+// block (mm, n), register rr hold row wr + 16 mm + l/16 + 4 rr and column
+// wc + 16 n + l%16 of the tile.
+struct TileLanes {
+  using T = TileShape<64>;
+  int lane, wr, wc;
+  __device__ TileLanes(int t) : lane(t & 63) {
+    const int w = t >> 6;
+    wr = (w / T::WN) * (64 / T::WM);
+    wc = (w % T::WN) * (64 / T::WN);
+  }
+  __device__ int row(int mm, int rr) const { return wr + mm * 16 + (lane >> 4) + 4 * rr; }
+  __device__ int col(int n) const { return wc + n * 16 + (lane & 15); }
+};
+
+// Forward substitution for one cluster (bottom-up by levels).  The cluster's
+// rows of its front vector, Z_I = Y_I + the children's contributions to I,
+// are gathered in one pass; the rows passed up to the parent,
+// Z_B = the children's contributions to B + Psi^T Z_I, are formed in the
+// matrix-core tile (children gathered through their index maps into the
+// accumulators, then the product on top).  Every row is written once; the
+// block diagonal D^{-1} is applied by the back substitution.
 __global__ void __launch_bounds__(256) k_rhs_fwd(Ctx c, RhsCtx r, const int32_t* cls) {
+  __shared__ GemmSmem sm;
+  __shared__ int64_t kid_inv[kMaxKids], kid_z[kMaxKids];
+  const int cl = cls[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[cl];
+  double2* S = slab(c, e);
+  const double2* Psi = S + d.o_psi;
+  const int m = r.m, s = d.s, b = d.b;
+  const double2* Zsl = r.Z + (int64_t)e * r.zstride;
+  double2* Zf = r.Z + (int64_t)e * r.zstride + r.o_vec[cl];
+  const double2* Y = r.Y + (int64_t)e * r.n * m;
+  const int t = threadIdx.x;
+  const int k0 = c.kids_ptr[cl], nk = c.kids_ptr[cl + 1] - k0;
+  for (int q = t; q < nk; q += 256) {
+    const int ch = c.kids[k0 + q];
+    const ClusterDesc& dc = c.cl[ch];
+    kid_inv[q] = dc.o_pinv;                             // parent front position -> child B index
+    kid_z[q] = r.o_vec[ch] + (int64_t)dc.s * m;         // the child's B rows
+  }
+  __syncthreads();
+  for (int q = t; q < s * m; q += 256) {
+    const int x = q / m, a = q - x * m;
+    double2 v = Y[(int64_t)(d.pt_off + x) * m + a];
+    for (int kq = 0; kq < nk; ++kq) {
+      const int ci = c.pinv[kid_inv[kq] + x];
+      if (ci >= 0) {
+        const double2 u = Zsl[kid_z[kq] + (int64_t)ci * m + a];
+        v.x += u.x;
+        v.y += u.y;
+      }
+    }
+    Zf[q] = v;
+  }
+  if (b == 0) return;  // the root passes nothing up
+  __threadfence_block();
+  __syncthreads();  // Z_I complete: the product below reads it
+  using T = TileShape<64>;
+  const TileLanes L(t);
+  for (int i0 = 0; i0 < b; i0 += 64) {
+    const int ni = min(64, b - i0);
+    for (int j0 = 0; j0 < m; j0 += 64) {
+      const int nj = min(64, m - j0);
+      ZTile acc;
+      ztile_zero(acc);
+      for (int kq = 0; kq < nk; ++kq) {
+        const int32_t* inv = c.pinv + kid_inv[kq];
+        const double2* Zc = Zsl + kid_z[kq];
+        int ri[T::MB][4];
+#pragma unroll
+        for (int mm = 0; mm < T::MB; ++mm)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int i = L.row(mm, rr);
+            ri[mm][rr] = i < ni ? inv[s + i0 + i] : -1;
+          }
+#pragma unroll
+        for (int mm = 0; mm < T::MB; ++mm)
+#pragma unroll
+          for (int n = 0; n < T::NB; ++n)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+              const int j = L.col(n);
+              if (ri[mm][rr] >= 0 && j < nj) {
+                const double2 u = Zc[(int64_t)ri[mm][rr] * m + j0 + j];
+                acc.re[mm][n][rr] += u.x;
+                acc.im[mm][n][rr] += u.y;
+              }
+            }
+      }
+      zgemm_acc_t<64, true, false, false>(
+          s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
+          [&](int k, int j) { return j < nj ? Zf[(int64_t)k * m + j0 + j] : cz(); }, acc, sm);
+      ztile_store_t<64>(acc, [&](int i, int j, double re, double im) {
+        if (i < ni && j < nj) Zf[(int64_t)(s + i0 + i) * m + j0 + j] = make_double2(re, im);
+      });
+    }
+  }
+}
+
+// Back substitution (top-down by levels): X_I = A_ii^{-1} Z_I + Psi_i X_{B_i},
+// both products into one tile, the B_i rows gathered from the ancestors'
+// final rows of X; the cluster's rows of X are written once.
+__global__ void __launch_bounds__(256) k_rhs_back(Ctx c, RhsCtx r, const int32_t* cls) {
   __shared__ GemmSmem sm;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
@@ -67,128 +168,88 @@ __global__ void __launch_bounds__(256) k_rhs_fwd(Ctx c, RhsCtx r, const int32_t*
   double2* S = slab(c, e);
   const double2* Psi = S + d.o_psi;
   const double2* Ainv = S + d.o_ainv;
-  const int m = r.m, s = d.s, b = d.b, f = d.f;
-  double2* Zsl = r.Z + (int64_t)e * r.zstride;
-  double2* Zf = Zsl + r.o_vec[cl];
-  const double2* Y = r.Y + (int64_t)e * r.n * m;
-  double2* X = r.X + (int64_t)e * r.n * m;
-  const int t = threadIdx.x;
-  for (int q = t; q < f * m; q += 256) Zf[q] = q < s * m ? Y[(int64_t)d.pt_off * m + q] : cz();
-  __syncthreads();
-  for (int kp = c.kids_ptr[cl]; kp < c.kids_ptr[cl + 1]; ++kp) {
-    const int ch = c.kids[kp];
-    const ClusterDesc dc = c.cl[ch];
-    const double2* Zc = Zsl + r.o_vec[ch];
-    const int32_t* rel = c.relmap + dc.bptr;
-    for (int q = t; q < dc.b * m; q += 256) {
-      const int rr = q / m, a = q - rr * m;
-      double2 v = Zf[(int64_t)rel[rr] * m + a];
-      const double2 u = Zc[(int64_t)(dc.s + rr) * m + a];
-      v.x += u.x;
-      v.y += u.y;
-      Zf[(int64_t)rel[rr] * m + a] = v;
-    }
-    __syncthreads();
-  }
-  for (int i0 = 0; i0 < b; i0 += 64) {
-    const int ni = min(64, b - i0);
-    for (int j0 = 0; j0 < m; j0 += 64) {
-      const int nj = min(64, m - j0);
-      ZTile acc;
-      ztile_zero(acc);
-      zgemm_acc<true, false>(
-          s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
-          [&](int k, int j) { return j < nj ? Zf[(int64_t)k * m + j0 + j] : cz(); }, acc, sm);
-      ztile_store(acc, [&](int i, int j, double re, double im) {
-        if (i < ni && j < nj) {
-          double2 v = Zf[(int64_t)(s + i0 + i) * m + j0 + j];
-          v.x += re;
-          v.y += im;
-          Zf[(int64_t)(s + i0 + i) * m + j0 + j] = v;
-        }
-      });
-    }
-  }
-  for (int j0 = 0; j0 < m; j0 += 64) {
-    const int nj = min(64, m - j0);
-    ZTile acc;
-    ztile_zero(acc);
-    zgemm_acc<false, false>(
-        s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
-        [&](int k, int j) { return j < nj ? Zf[(int64_t)k * m + j0 + j] : cz(); }, acc, sm);
-    ztile_store(acc, [&](int i, int j, double re, double im) {
-      if (i < s && j < nj) X[(int64_t)(d.pt_off + i) * m + j0 + j] = make_double2(re, im);
-    });
-  }
-}
-
-// Back substitution (top-down by levels): X_I = X_I + Psi_i X_{B_i}, the
-// B_i rows gathered from the ancestors' final rows of X.
-__global__ void __launch_bounds__(256) k_rhs_back(Ctx c, RhsCtx r, const int32_t* cls) {
-  __shared__ GemmSmem sm;
-  const int cl = cls[blockIdx.x];
-  const int e = blockIdx.y;
-  const ClusterDesc d = c.cl[cl];
-  if (d.b == 0) return;
-  double2* S = slab(c, e);
-  const double2* Psi = S + d.o_psi;
   const int m = r.m, s = d.s, b = d.b;
+  const double2* Zf = r.Z + (int64_t)e * r.zstride + r.o_vec[cl];
   double2* X = r.X + (int64_t)e * r.n * m;
   const int32_t* bidx = r.bidx + d.bptr;
   for (int j0 = 0; j0 < m; j0 += 64) {
     const int nj = min(64, m - j0);
     ZTile acc;
     ztile_zero(acc);
-    zgemm_acc<false, false>(
-        b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
-        [&](int k, int j) { return j < nj ? X[(int64_t)bidx[k] * m + j0 + j] : cz(); }, acc, sm);
-    ztile_store(acc, [&](int i, int j, double re, double im) {
-      if (i < s && j < nj) {
-        double2 v = X[(int64_t)(d.pt_off + i) * m + j0 + j];
-        v.x += re;
-        v.y += im;
-        X[(int64_t)(d.pt_off + i) * m + j0 + j] = v;
-      }
+    zgemm_acc_t<64, false, false, false>(
+        s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
+        [&](int k, int j) { return j < nj ? Zf[(int64_t)k * m + j0 + j] : cz(); }, acc, sm);
+    if (b > 0)
+      zgemm_acc_t<64, false, false, false>(
+          b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
+          [&](int k, int j) { return j < nj ? X[(int64_t)bidx[k] * m + j0 + j] : cz(); }, acc, sm);
+    ztile_store_t<64>(acc, [&](int i, int j, double re, double im) {
+      if (i < s && j < nj) X[(int64_t)(d.pt_off + i) * m + j0 + j] = make_double2(re, im);
     });
   }
 }
 
-// T = G_{:,c} Sigma^<_c (n x m, written over Y, which is free by now):
-// 64 x 64 tiles on the FP64 matrix cores, grid = (row tiles * col tiles, nb).
-__global__ void __launch_bounds__(256) k_vjp_gemm(Ctx c, RhsCtx r, int cc) {
+// part[e][row] += 2 Im[ sum_a T[row][a] X[row][a] ],  T = G_{:,c} Sigma^<_c.
+// One block per 64 rows: each 64-column tile of T is formed on the matrix
+// cores and consumed in registers (never stored); the row sums are reduced
+// across the lanes of a row and the two column halves of the tile, column
+// tiles in order (deterministic).
+__global__ void __launch_bounds__(256) k_vjp(Ctx c, RhsCtx r, int cc) {
   __shared__ GemmSmem sm;
+  using T = TileShape<64>;
+  __shared__ double rowsum[T::WN][64];
   const int e = blockIdx.y;
   const int m = r.m;
-  const int ntc = (m + 63) / 64;
-  const int i0 = (blockIdx.x / ntc) * 64, j0 = (blockIdx.x % ntc) * 64;
-  const int ni = min(64, r.n - i0), nj = min(64, m - j0);
+  const int i0 = blockIdx.x * 64;
+  const int ni = min(64, r.n - i0);
   const double2* G = r.Gc + (int64_t)e * r.n * m;
-  const double2* sg = c.sig_l[cc] + (int64_t)(c.e0 + e) * m * m;
-  double2* T = r.Y + (int64_t)e * r.n * m;
-  ZTile acc;
-  ztile_zero(acc);
-  zgemm_acc<false, false>(
-      m, [&](int i, int k) { return i < ni ? G[(int64_t)(i0 + i) * m + k] : cz(); },
-      [&](int k, int j) { return j < nj ? sg[(int64_t)k * m + j0 + j] : cz(); }, acc, sm);
-  ztile_store(acc, [&](int i, int j, double re, double im) {
-    if (i < ni && j < nj) T[(int64_t)(i0 + i) * m + j0 + j] = make_double2(re, im);
-  });
-}
-
-// part[e][row] += 2 Im[ sum_b T[row,b] X[row,b] ]
-__global__ void __launch_bounds__(256) k_vjp_accum(Ctx c, RhsCtx r, int cc) {
-  const int e = blockIdx.y;
-  const int row = blockIdx.x * 256 + threadIdx.x;
-  if (row >= r.n) return;
-  const int m = r.m;
-  const double2* T = r.Y + ((int64_t)e * r.n + row) * m;
-  const double2* X = r.X + ((int64_t)e * r.n + row) * m;
-  double acc = 0.0;
-  for (int bb = 0; bb < m; ++bb) {
-    const double2 t = T[bb], x = X[bb];
-    acc += t.x * x.y + t.y * x.x;  // Im[(t.x + i t.y)(x.x + i x.y)]
+  const double2* sg = sel2(c.sig_l, cc) + (int64_t)(c.e0 + e) * m * m;
+  const double2* X = r.X + (int64_t)e * r.n * m;
+  const int t = threadIdx.x;
+  const TileLanes L(t);
+  double rs[T::MB][4];
+#pragma unroll
+  for (int mm = 0; mm < T::MB; ++mm)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) rs[mm][rr] = 0.0;
+  for (int j0 = 0; j0 < m; j0 += 64) {
+    const int nj = min(64, m - j0);
+    ZTile acc;
+    ztile_zero(acc);
+    zgemm_acc_t<64, false, false, false>(
+        m, [&](int i, int k) { return i < ni ? G[(int64_t)(i0 + i) * m + k] : cz(); },
+        [&](int k, int j) { return j < nj ? sg[(int64_t)k * m + j0 + j] : cz(); }, acc, sm);
+#pragma unroll
+    for (int mm = 0; mm < T::MB; ++mm)
+#pragma unroll
+      for (int n = 0; n < T::NB; ++n)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int i = L.row(mm, rr), j = L.col(n);
+          if (i < ni && j < nj) {
+            const double2 x = X[(int64_t)(i0 + i) * m + j0 + j];
+            // Im[(t.x + i t.y)(x.x + i x.y)]
+            rs[mm][rr] += (double)acc.re[mm][n][rr] * x.y + (double)acc.im[mm][n][rr] * x.x;
+          }
+        }
   }
-  r.part[(int64_t)e * r.n + row] += 2.0 * acc;
+  // the 16 lanes of a row (same lane / 16) hold its columns
+#pragma unroll
+  for (int mm = 0; mm < T::MB; ++mm)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      double v = rs[mm][rr];
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off);
+      if ((L.lane & 15) == 0) rowsum[(t >> 6) % T::WN][L.row(mm, rr)] = v;
+    }
+  __syncthreads();
+  if (t < ni) {
+    double v = 0.0;
+#pragma unroll
+    for (int h = 0; h < T::WN; ++h) v += rowsum[h][t];
+    r.part[(int64_t)e * r.n + i0 + t] += 2.0 * v;
+  }
 }
 
 __global__ void k_zero(double* p, int64_t count) {
@@ -232,9 +293,7 @@ void launch_rhs_back(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl,
   if (ncl > 0) hipLaunchKernelGGL(k_rhs_back, dim3(ncl, nb), dim3(256), 0, st, c, r, cls);
 }
 void launch_vjp_accum(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st) {
-  const int tiles = ((r.n + 63) / 64) * ((r.m + 63) / 64);
-  hipLaunchKernelGGL(k_vjp_gemm, dim3(tiles, nb), dim3(256), 0, st, c, r, cc);
-  hipLaunchKernelGGL(k_vjp_accum, dim3((r.n + 255) / 256, nb), dim3(256), 0, st, c, r, cc);
+  hipLaunchKernelGGL(k_vjp, dim3((r.n + 63) / 64, nb), dim3(256), 0, st, c, r, cc);
 }
 void launch_zero(double* p, int64_t count, hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count);
