@@ -70,6 +70,116 @@ struct TileLanes {
   __device__ int col(int n) const { return wc + n * 16 + (lane & 15); }
 };
 
+// Clusters with s <= kRhsS and b <= kRhsB (the leaves and the separators
+// just above them, most clusters) are solved by one wavefront each: lane =
+// right-hand-side column (a row of 64 columns is 1 KB contiguous), Psi and
+// A_ii^{-1} staged in LDS, the short products on the vector units.  Matrix
+// tiles of 64 x 64 would be mostly padding there.
+constexpr int kRhsS = 16, kRhsB = 32;
+__device__ inline bool rhs_small(const ClusterDesc& d) { return d.s <= kRhsS && d.b <= kRhsB; }
+
+__global__ void __launch_bounds__(64) k_rhs_fwd_small(Ctx c, RhsCtx r, const int32_t* cls) {
+  __shared__ double2 psi[kRhsS * kRhsB];
+  __shared__ int64_t kid_inv[kMaxKids], kid_z[kMaxKids];
+  const int cl = cls[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[cl];
+  if (!rhs_small(d)) return;  // k_rhs_fwd
+  const double2* Psi = slab(c, e) + d.o_psi;
+  const int m = r.m, s = d.s, b = d.b;
+  const double2* Zsl = r.Z + (int64_t)e * r.zstride;
+  double2* Zf = r.Z + (int64_t)e * r.zstride + r.o_vec[cl];
+  const double2* Y = r.Y + (int64_t)e * r.n * m;
+  const int t = threadIdx.x;
+  const int k0 = c.kids_ptr[cl], nk = c.kids_ptr[cl + 1] - k0;
+  for (int q = t; q < nk; q += 64) {
+    const int ch = c.kids[k0 + q];
+    const ClusterDesc& dc = c.cl[ch];
+    kid_inv[q] = dc.o_pinv;
+    kid_z[q] = r.o_vec[ch] + (int64_t)dc.s * m;
+  }
+  for (int q = t; q < s * b; q += 64) psi[q] = Psi[q];  // row k = I index, column i = B index
+  __syncthreads();
+  for (int a0 = 0; a0 < m; a0 += 64) {
+    const int a = a0 + t;
+    const bool on = a < m;
+    double2 zi[kRhsS];
+#pragma unroll
+    for (int x = 0; x < kRhsS; ++x) {
+      zi[x] = cz();
+      if (x < s) {
+        double2 v = on ? Y[(int64_t)(d.pt_off + x) * m + a] : cz();
+        for (int kq = 0; kq < nk; ++kq) {
+          const int ci = c.pinv[kid_inv[kq] + x];
+          if (ci >= 0 && on) {
+            const double2 u = Zsl[kid_z[kq] + (int64_t)ci * m + a];
+            v.x += u.x;
+            v.y += u.y;
+          }
+        }
+        zi[x] = v;
+        if (on) Zf[(int64_t)x * m + a] = v;
+      }
+    }
+    for (int i = 0; i < b; ++i) {
+      double2 v = cz();
+      for (int kq = 0; kq < nk; ++kq) {
+        const int ci = c.pinv[kid_inv[kq] + s + i];
+        if (ci >= 0 && on) {
+          const double2 u = Zsl[kid_z[kq] + (int64_t)ci * m + a];
+          v.x += u.x;
+          v.y += u.y;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kRhsS; ++k)
+        if (k < s) cmac(v, psi[k * b + i], zi[k]);  // (Psi^T Z_I)_i = sum_k Psi[k][i] Z_I[k]
+      if (on) Zf[(int64_t)(s + i) * m + a] = v;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(64) k_rhs_back_small(Ctx c, RhsCtx r, const int32_t* cls) {
+  __shared__ double2 psi[kRhsS * kRhsB], ainv[kRhsS * kRhsS];
+  __shared__ int32_t bix[kRhsB];
+  const int cl = cls[blockIdx.x];
+  const int e = blockIdx.y;
+  const ClusterDesc d = c.cl[cl];
+  if (!rhs_small(d)) return;  // k_rhs_back
+  double2* S = slab(c, e);
+  const int m = r.m, s = d.s, b = d.b;
+  const double2* Zf = r.Z + (int64_t)e * r.zstride + r.o_vec[cl];
+  double2* X = r.X + (int64_t)e * r.n * m;
+  const int t = threadIdx.x;
+  for (int q = t; q < s * b; q += 64) psi[q] = S[d.o_psi + q];
+  for (int q = t; q < s * s; q += 64) ainv[q] = S[d.o_ainv + q];
+  for (int q = t; q < b; q += 64) bix[q] = r.bidx[d.bptr + q];
+  __syncthreads();
+  for (int a0 = 0; a0 < m; a0 += 64) {
+    const int a = a0 + t;
+    const bool on = a < m;
+    double2 xo[kRhsS];
+#pragma unroll
+    for (int i = 0; i < kRhsS; ++i) xo[i] = cz();
+    // one input row at a time: only the outputs stay in registers
+    for (int k = 0; k < s; ++k) {
+      const double2 z = on ? Zf[(int64_t)k * m + a] : cz();
+#pragma unroll
+      for (int i = 0; i < kRhsS; ++i)
+        if (i < s) cmac(xo[i], ainv[i * s + k], z);
+    }
+    for (int k = 0; k < b; ++k) {
+      const double2 xb = on ? X[(int64_t)bix[k] * m + a] : cz();
+#pragma unroll
+      for (int i = 0; i < kRhsS; ++i)
+        if (i < s) cmac(xo[i], psi[i * b + k], xb);
+    }
+#pragma unroll
+    for (int i = 0; i < kRhsS; ++i)
+      if (i < s && on) X[(int64_t)(d.pt_off + i) * m + a] = xo[i];
+  }
+}
+
 // Forward substitution for one cluster (bottom-up by levels).  The cluster's
 // rows of its front vector, Z_I = Y_I + the children's contributions to I,
 // are gathered in one pass; the rows passed up to the parent,
@@ -83,6 +193,7 @@ __global__ void __launch_bounds__(256) k_rhs_fwd(Ctx c, RhsCtx r, const int32_t*
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
   const ClusterDesc d = c.cl[cl];
+  if (rhs_small(d)) return;  // k_rhs_fwd_small
   double2* S = slab(c, e);
   const double2* Psi = S + d.o_psi;
   const int m = r.m, s = d.s, b = d.b;
@@ -165,6 +276,7 @@ __global__ void __launch_bounds__(256) k_rhs_back(Ctx c, RhsCtx r, const int32_t
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
   const ClusterDesc d = c.cl[cl];
+  if (rhs_small(d)) return;  // k_rhs_back_small
   double2* S = slab(c, e);
   const double2* Psi = S + d.o_psi;
   const double2* Ainv = S + d.o_ainv;
@@ -286,11 +398,16 @@ void launch_rhs_contact(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream
 void launch_rhs_lambda(const Ctx& c, const RhsCtx& r, int nb, hipStream_t st) {
   hipLaunchKernelGGL(k_rhs_lambda, dim3(256, nb), dim3(256), 0, st, c, r);
 }
+// Both variants over all clusters of a height; each skips the other's.
 void launch_rhs_fwd(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, hipStream_t st) {
-  if (ncl > 0) hipLaunchKernelGGL(k_rhs_fwd, dim3(ncl, nb), dim3(256), 0, st, c, r, cls);
+  if (ncl <= 0) return;
+  hipLaunchKernelGGL(k_rhs_fwd_small, dim3(ncl, nb), dim3(64), 0, st, c, r, cls);
+  hipLaunchKernelGGL(k_rhs_fwd, dim3(ncl, nb), dim3(256), 0, st, c, r, cls);
 }
 void launch_rhs_back(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, hipStream_t st) {
-  if (ncl > 0) hipLaunchKernelGGL(k_rhs_back, dim3(ncl, nb), dim3(256), 0, st, c, r, cls);
+  if (ncl <= 0) return;
+  hipLaunchKernelGGL(k_rhs_back_small, dim3(ncl, nb), dim3(64), 0, st, c, r, cls);
+  hipLaunchKernelGGL(k_rhs_back, dim3(ncl, nb), dim3(256), 0, st, c, r, cls);
 }
 void launch_vjp_accum(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st) {
   hipLaunchKernelGGL(k_vjp, dim3((r.n + 63) / 64, nb), dim3(256), 0, st, c, r, cc);
