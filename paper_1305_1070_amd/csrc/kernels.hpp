@@ -129,8 +129,17 @@ void launch_fill_zero_i32(int32_t* p, int64_t count, hipStream_t st);
 void launch_advance(int32_t* e0, const int32_t* inc, int n, hipStream_t st);
 void launch_rhs_contact(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st);
 void launch_rhs_lambda(const Ctx& c, const RhsCtx& r, int nb, hipStream_t st);
-void launch_rhs_fwd(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, hipStream_t st);
-void launch_rhs_back(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, hipStream_t st);
+// adjoint solves: clusters with s <= kRhsSmallS, b <= kRhsSmallB and
+// s b <= kRhsSmallSB run one wavefront each (dynamic LDS rhs_small_lds_*),
+// the others as 64 x 64 tiles (faster once the products grow)
+constexpr int kRhsSmallS = 16, kRhsSmallB = 64, kRhsSmallSB = 512;
+inline bool rhs_small_host(int s, int b) { return s <= kRhsSmallS && b <= kRhsSmallB && s * b <= kRhsSmallSB; }
+inline size_t rhs_small_lds_fwd(int s, int b) { return (size_t)s * b * 16; }
+inline size_t rhs_small_lds_back(int s, int b) { return (size_t)(s * b + s * s) * 16 + (size_t)b * 4; }
+void launch_rhs_fwd(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, size_t small_lds,
+                    bool big, hipStream_t st);
+void launch_rhs_back(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, size_t small_lds,
+                     bool big, hipStream_t st);
 void launch_vjp_accum(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st);
 void launch_zero(double* p, int64_t count, hipStream_t st);
 void launch_vjp_reduce(const Ctx& c, const RhsCtx& r, int nb, const double* cE, double* vbar, hipStream_t st);

@@ -70,16 +70,19 @@ struct TileLanes {
   __device__ int col(int n) const { return wc + n * 16 + (lane & 15); }
 };
 
-// Clusters with s <= kRhsS and b <= kRhsB (the leaves and the separators
-// just above them, most clusters) are solved by one wavefront each: lane =
-// right-hand-side column (a row of 64 columns is 1 KB contiguous), Psi and
-// A_ii^{-1} staged in LDS, the short products on the vector units.  Matrix
-// tiles of 64 x 64 would be mostly padding there.
-constexpr int kRhsS = 16, kRhsB = 32;
-__device__ inline bool rhs_small(const ClusterDesc& d) { return d.s <= kRhsS && d.b <= kRhsB; }
+// Clusters with s <= kRhsSmallS, b <= kRhsSmallB and s b <= kRhsSmallSB (the
+// leaves and the separators of the lower heights, most clusters) are solved by one
+// wavefront each: lane = right-hand-side column (a row of 64 columns is 1 KB
+// contiguous), Psi and A_ii^{-1} staged in LDS sized per height by the
+// launch, the short products on the vector units.  Matrix tiles of 64 x 64
+// would be mostly padding there.
+constexpr int kRhsS = kRhsSmallS;
+__device__ inline bool rhs_small(const ClusterDesc& d) {
+  return d.s <= kRhsSmallS && d.b <= kRhsSmallB && d.s * d.b <= kRhsSmallSB;
+}
 
 __global__ void __launch_bounds__(64) k_rhs_fwd_small(Ctx c, RhsCtx r, const int32_t* cls) {
-  __shared__ double2 psi[kRhsS * kRhsB];
+  extern __shared__ double2 psi[];  // s x b
   __shared__ int64_t kid_inv[kMaxKids], kid_z[kMaxKids];
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
@@ -140,14 +143,16 @@ __global__ void __launch_bounds__(64) k_rhs_fwd_small(Ctx c, RhsCtx r, const int
 }
 
 __global__ void __launch_bounds__(64) k_rhs_back_small(Ctx c, RhsCtx r, const int32_t* cls) {
-  __shared__ double2 psi[kRhsS * kRhsB], ainv[kRhsS * kRhsS];
-  __shared__ int32_t bix[kRhsB];
+  extern __shared__ double2 dsm[];  // Psi (s x b), A_ii^{-1} (s x s), B_i positions (b)
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
   const ClusterDesc d = c.cl[cl];
   if (!rhs_small(d)) return;  // k_rhs_back
   double2* S = slab(c, e);
   const int m = r.m, s = d.s, b = d.b;
+  double2* psi = dsm;
+  double2* ainv = dsm + s * b;
+  int32_t* bix = reinterpret_cast<int32_t*>(ainv + s * s);
   const double2* Zf = r.Z + (int64_t)e * r.zstride + r.o_vec[cl];
   double2* X = r.X + (int64_t)e * r.n * m;
   const int t = threadIdx.x;
@@ -399,15 +404,19 @@ void launch_rhs_lambda(const Ctx& c, const RhsCtx& r, int nb, hipStream_t st) {
   hipLaunchKernelGGL(k_rhs_lambda, dim3(256, nb), dim3(256), 0, st, c, r);
 }
 // Both variants over all clusters of a height; each skips the other's.
-void launch_rhs_fwd(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, hipStream_t st) {
+// small_lds: the small variant's dynamic LDS for this height (0: no small
+// cluster), big: whether the height has a cluster for the tiled variant.
+void launch_rhs_fwd(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, size_t small_lds,
+                    bool big, hipStream_t st) {
   if (ncl <= 0) return;
-  hipLaunchKernelGGL(k_rhs_fwd_small, dim3(ncl, nb), dim3(64), 0, st, c, r, cls);
-  hipLaunchKernelGGL(k_rhs_fwd, dim3(ncl, nb), dim3(256), 0, st, c, r, cls);
+  if (small_lds) hipLaunchKernelGGL(k_rhs_fwd_small, dim3(ncl, nb), dim3(64), small_lds, st, c, r, cls);
+  if (big) hipLaunchKernelGGL(k_rhs_fwd, dim3(ncl, nb), dim3(256), 0, st, c, r, cls);
 }
-void launch_rhs_back(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, hipStream_t st) {
+void launch_rhs_back(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, size_t small_lds,
+                     bool big, hipStream_t st) {
   if (ncl <= 0) return;
-  hipLaunchKernelGGL(k_rhs_back_small, dim3(ncl, nb), dim3(64), 0, st, c, r, cls);
-  hipLaunchKernelGGL(k_rhs_back, dim3(ncl, nb), dim3(256), 0, st, c, r, cls);
+  if (small_lds) hipLaunchKernelGGL(k_rhs_back_small, dim3(ncl, nb), dim3(64), small_lds, st, c, r, cls);
+  if (big) hipLaunchKernelGGL(k_rhs_back, dim3(ncl, nb), dim3(256), 0, st, c, r, cls);
 }
 void launch_vjp_accum(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st) {
   hipLaunchKernelGGL(k_vjp, dim3((r.n + 63) / 64, nb), dim3(256), 0, st, c, r, cc);

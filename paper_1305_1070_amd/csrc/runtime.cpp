@@ -54,6 +54,10 @@ struct ndg_plan {
   ndg::ChainItem* d_chainitems = nullptr;
   int32_t* d_chaincls = nullptr;
   std::vector<int> lvl_ptr, col_ptr, upd_ptr, chain_ptr, chaincl_ptr;  // per height (1-based)
+  // adjoint solves per height: dynamic LDS of the one-wavefront variant (0:
+  // no such cluster) and whether a cluster needs the tiled one
+  std::vector<size_t> rhs_lds_fwd, rhs_lds_back;
+  std::vector<char> rhs_big;
   // per height, the clusters split into size classes: fronts f <= 32, f <= 64
   // (whole on chip), then larger fronts with s <= 16, s <= 32, s <= 64
   // (separate kernels, tile height following s)
@@ -243,6 +247,9 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   p->upd_ptr.assign(H + 1, 0);
   p->chain_ptr.assign(H + 1, 0);
   p->chaincl_ptr.assign(H + 1, 0);
+  p->rhs_lds_fwd.assign(H + 1, 0);
+  p->rhs_lds_back.assign(H + 1, 0);
+  p->rhs_big.assign(H + 1, 0);
   p->groups.assign((H + 1) * ndg_plan::kClasses, ndg_plan::Group{});
   auto class_of = [&](int k) {
     const int s_ = sy.s(k), f = s_ + sy.b(k);
@@ -279,6 +286,15 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
       }
       g.ncol = (int)cols.size() - g.col0;
       g.nupd = (int)upds.size() - g.upd0;
+    }
+    for (int32_t k : lv) {
+      const int s_ = sy.s(k), b = sy.b(k);
+      if (rhs_small_host(s_, b)) {
+        p->rhs_lds_fwd[h] = std::max(p->rhs_lds_fwd[h], std::max<size_t>(16, rhs_small_lds_fwd(s_, b)));
+        p->rhs_lds_back[h] = std::max(p->rhs_lds_back[h], rhs_small_lds_back(s_, b));
+      } else {
+        p->rhs_big[h] = 1;
+      }
     }
     for (int32_t k : lv)
       if (p->hdesc[k].chain_mask) {
@@ -716,11 +732,13 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
           rr.X = pass == 0 ? r.Gc : r.X;
           for (int h = 1; h <= H; ++h)
             timed(K_RHS_FWD, h, nb, [&] {
-              launch_rhs_fwd(c, rr, p->d_levels + p->lvl_ptr[h - 1], p->lvl_ptr[h] - p->lvl_ptr[h - 1], nb, st);
+              launch_rhs_fwd(c, rr, p->d_levels + p->lvl_ptr[h - 1], p->lvl_ptr[h] - p->lvl_ptr[h - 1], nb,
+                             p->rhs_lds_fwd[h], p->rhs_big[h], st);
             });
           for (int h = H; h >= 1; --h)
             timed(K_RHS_BACK, h, nb, [&] {
-              launch_rhs_back(c, rr, p->d_levels + p->lvl_ptr[h - 1], p->lvl_ptr[h] - p->lvl_ptr[h - 1], nb, st);
+              launch_rhs_back(c, rr, p->d_levels + p->lvl_ptr[h - 1], p->lvl_ptr[h] - p->lvl_ptr[h - 1], nb,
+                              p->rhs_lds_back[h], p->rhs_big[h], st);
             });
         }
         timed(K_VJP, 0, nb, [&] { launch_vjp_accum(c, r, cc, nb, st); });
