@@ -94,7 +94,11 @@ struct Ctx {
 
 // Multi-right-hand-side solves with the factors of the fold (adjoint).
 struct RhsCtx {
-  double2* Y;         // [nb][n][m] right-hand sides, internal row order
+  // right-hand side, formed where the forward substitution reads it:
+  // ymode 0 the contact's unit columns E_c (cinv[row] = its column or -1),
+  // ymode 1 Lambda conj(G_{:,c}) from Gc and nbar
+  int32_t ymode;
+  const int32_t* cinv;
   double2* X;         // [nb][n][m] solutions
   double2* Gc;        // [nb][n][m] contact columns of G^r
   double2* Z;         // [nb][zstride] per-cluster front vectors (f x m)
@@ -127,8 +131,6 @@ constexpr int kMaxKids = 64;  // children per cluster (front assembly tables)  /
 void launch_fill_zero(double* p, int64_t count, hipStream_t st);
 void launch_fill_zero_i32(int32_t* p, int64_t count, hipStream_t st);
 void launch_advance(int32_t* e0, const int32_t* inc, int n, hipStream_t st);
-void launch_rhs_contact(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st);
-void launch_rhs_lambda(const Ctx& c, const RhsCtx& r, int nb, hipStream_t st);
 // adjoint solves: clusters with s <= kRhsSmallS, b <= kRhsSmallB and
 // s b <= kRhsSmallSB run one wavefront each (dynamic LDS rhs_small_lds_*),
 // the others as 64 x 64 tiles (faster once the products grow)

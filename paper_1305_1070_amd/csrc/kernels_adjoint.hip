@@ -23,36 +23,15 @@
 
 namespace ndg {
 
-// Y = E_c: ones at (contact site a, column a) in the internal ordering.
-__global__ void k_rhs_contact(Ctx c, RhsCtx r, int cc) {
-  const int e = blockIdx.y;
-  double2* Y = r.Y + (int64_t)e * r.n * r.m;
-  const int64_t total = (int64_t)r.n * r.m;
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (int64_t)gridDim.x * 256)
-    Y[q] = cz();
-  // (the ones are placed by k_rhs_contact_ones after this kernel)
-}
-
-__global__ void k_rhs_contact_ones(Ctx c, RhsCtx r, int cc) {
-  const int e = blockIdx.y;
-  double2* Y = r.Y + (int64_t)e * r.n * r.m;
-  const int a = blockIdx.x * 256 + threadIdx.x;
-  if (a >= c.nc[cc]) return;
-  Y[(int64_t)c.cpos[cc][a] * r.m + a] = make_double2(1.0, 0.0);
-}
-
-// Y = Lambda conj(G_{:,c}) with Lambda = diag(nbar) in the caller's order.
-__global__ void k_rhs_lambda(Ctx c, RhsCtx r) {
-  const int e = blockIdx.y;
-  const double2* G = r.Gc + (int64_t)e * r.n * r.m;
-  double2* Y = r.Y + (int64_t)e * r.n * r.m;
-  const int64_t total = (int64_t)r.n * r.m;
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (int64_t)gridDim.x * 256) {
-    const int row = (int)(q / r.m);
-    const double w = r.nbar[c.perm[row]];
-    const double2 g = G[q];
-    Y[q] = make_double2(w * g.x, -w * g.y);
-  }
+// Right-hand side entry Y[row][a] (internal row order): the contact's unit
+// columns E_c in the first solve, Lambda conj(G_{:,c}) with Lambda = diag(nbar)
+// (caller's order) in the second; formed where the forward substitution
+// reads it, never stored.
+__device__ inline double2 rhs_y(const Ctx& c, const RhsCtx& r, int e, int row, int a) {
+  if (r.ymode == 0) return make_double2(r.cinv[row] == a ? 1.0 : 0.0, 0.0);
+  const double w = r.nbar[c.perm[row]];
+  const double2 g = r.Gc[((int64_t)e * r.n + row) * r.m + a];
+  return make_double2(w * g.x, -w * g.y);
 }
 
 // Lane layout of a 64 x 64 FP64 matrix-core tile (TileShape<64>): lane l,
@@ -92,7 +71,6 @@ __global__ void __launch_bounds__(64) k_rhs_fwd_small(Ctx c, RhsCtx r, const int
   const int m = r.m, s = d.s, b = d.b;
   const double2* Zsl = r.Z + (int64_t)e * r.zstride;
   double2* Zf = r.Z + (int64_t)e * r.zstride + r.o_vec[cl];
-  const double2* Y = r.Y + (int64_t)e * r.n * m;
   const int t = threadIdx.x;
   const int k0 = c.kids_ptr[cl], nk = c.kids_ptr[cl + 1] - k0;
   for (int q = t; q < nk; q += 64) {
@@ -111,7 +89,7 @@ __global__ void __launch_bounds__(64) k_rhs_fwd_small(Ctx c, RhsCtx r, const int
     for (int x = 0; x < kRhsS; ++x) {
       zi[x] = cz();
       if (x < s) {
-        double2 v = on ? Y[(int64_t)(d.pt_off + x) * m + a] : cz();
+        double2 v = on ? rhs_y(c, r, e, d.pt_off + x, a) : cz();
         for (int kq = 0; kq < nk; ++kq) {
           const int ci = c.pinv[kid_inv[kq] + x];
           if (ci >= 0 && on) {
@@ -204,7 +182,6 @@ __global__ void __launch_bounds__(256) k_rhs_fwd(Ctx c, RhsCtx r, const int32_t*
   const int m = r.m, s = d.s, b = d.b;
   const double2* Zsl = r.Z + (int64_t)e * r.zstride;
   double2* Zf = r.Z + (int64_t)e * r.zstride + r.o_vec[cl];
-  const double2* Y = r.Y + (int64_t)e * r.n * m;
   const int t = threadIdx.x;
   const int k0 = c.kids_ptr[cl], nk = c.kids_ptr[cl + 1] - k0;
   for (int q = t; q < nk; q += 256) {
@@ -216,7 +193,7 @@ __global__ void __launch_bounds__(256) k_rhs_fwd(Ctx c, RhsCtx r, const int32_t*
   __syncthreads();
   for (int q = t; q < s * m; q += 256) {
     const int x = q / m, a = q - x * m;
-    double2 v = Y[(int64_t)(d.pt_off + x) * m + a];
+    double2 v = rhs_y(c, r, e, d.pt_off + x, a);
     for (int kq = 0; kq < nk; ++kq) {
       const int ci = c.pinv[kid_inv[kq] + x];
       if (ci >= 0) {
@@ -396,13 +373,6 @@ __global__ void k_density(Ctx c, int nb, const double* cE, double* dens) {
   dens[q] += acc;
 }
 
-void launch_rhs_contact(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_rhs_contact, dim3(256, nb), dim3(256), 0, st, c, r, cc);
-  hipLaunchKernelGGL(k_rhs_contact_ones, dim3((c.nc[cc] + 255) / 256, nb), dim3(256), 0, st, c, r, cc);
-}
-void launch_rhs_lambda(const Ctx& c, const RhsCtx& r, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_rhs_lambda, dim3(256, nb), dim3(256), 0, st, c, r);
-}
 // Both variants over all clusters of a height; each skips the other's.
 // small_lds: the small variant's dynamic LDS for this height (0: no small
 // cluster), big: whether the height has a cluster for the tiled variant.

@@ -68,7 +68,8 @@ struct ndg_plan {
   int32_t* d_status = nullptr;
   // adjoint workspace (ndg_plan_enable_adjoint): right-hand sides Y, solutions
   // X, contact columns of G, per-cluster front vectors, per-energy partials
-  double2 *d_rY = nullptr, *d_rX = nullptr, *d_rG = nullptr, *d_rZ = nullptr;
+  double2 *d_rX = nullptr, *d_rG = nullptr, *d_rZ = nullptr;
+  int32_t* d_cinv[2] = {nullptr, nullptr};  // per contact: internal position -> contact column, or -1
   int64_t* d_ovec = nullptr;
   int32_t* d_bidx = nullptr;
   double* d_part = nullptr;
@@ -181,10 +182,10 @@ void free_plan(ndg_plan* p) {
   void* ptrs[] = {p->d_cl,        p->d_relmap,   p->d_kids_ptr,   p->d_kids,       p->d_hrow,
                   p->d_hcol,      p->d_hval,     p->d_perm,       p->d_owner,      p->d_cpos[0],
                   p->d_cpos[1],   p->d_levels,   p->d_colitems,   p->d_upditems,   p->d_chainitems,
-                  p->d_chaincls,  p->d_ws,       p->d_status,     p->d_rY,         p->d_rX,
+                  p->d_chaincls,  p->d_ws,       p->d_status,     p->d_cinv[0],    p->d_rX,
                   p->d_rG,        p->d_rZ,       p->d_ovec,       p->d_bidx,       p->d_part,
                   p->d_srow,      p->d_scol,     p->d_scid,       p->d_sflat,      p->d_hfront,
-                  p->d_smap,      p->d_pinv,     p->d_gaddr,      p->d_sdiag};
+                  p->d_smap,      p->d_pinv,     p->d_gaddr,      p->d_sdiag,      p->d_cinv[1]};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& r : p->recs) {
@@ -467,8 +468,12 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   rc = rc ? rc : upload(&p->d_hval, sy.hval.data(), sy.hval.size());
   rc = rc ? rc : upload(&p->d_perm, sy.perm.data(), sy.perm.size());
   rc = rc ? rc : upload(&p->d_owner, sy.owner.data(), sy.owner.size());
-  for (int c = 0; c < p->ncontacts && !rc; ++c)
+  for (int c = 0; c < p->ncontacts && !rc; ++c) {
     rc = upload(&p->d_cpos[c], sy.contact_pos[c].data(), sy.contact_pos[c].size());
+    std::vector<int32_t> cinv(p->n, -1);
+    for (size_t a = 0; a < sy.contact_pos[c].size(); ++a) cinv[sy.contact_pos[c][a]] = (int32_t)a;
+    rc = rc ? rc : upload(&p->d_cinv[c], cinv.data(), cinv.size());
+  }
   rc = rc ? rc : upload(&p->d_srow, sy.srow.data(), sy.srow.size());
   rc = rc ? rc : upload(&p->d_scol, sy.scol.data(), sy.scol.size());
   rc = rc ? rc : upload(&p->d_scid, sy.scid.data(), sy.scid.size());
@@ -542,7 +547,7 @@ int plan_info(const ndg_plan* plan, ndg_info* out) {
 }
 
 int plan_enable_adjoint(ndg_plan* p) {
-  if (p->d_rY) return NDG_OK;
+  if (p->d_rX) return NDG_OK;
   if (hipSetDevice(p->device) != hipSuccess) { set_error("ndg_plan_enable_adjoint: hipSetDevice failed"); return NDG_EHIP; }
   int mmax = 1;
   for (int c = 0; c < p->ncontacts; ++c) mmax = std::max(mmax, p->nc[c]);
@@ -556,8 +561,7 @@ int plan_enable_adjoint(ndg_plan* p) {
   p->mmax = mmax;
   const size_t nb = (size_t)p->max_batch, nm = (size_t)p->n * mmax;
   int rc = 0;
-  if (hipMalloc((void**)&p->d_rY, nb * nm * 16) != hipSuccess ||
-      hipMalloc((void**)&p->d_rX, nb * nm * 16) != hipSuccess ||
+  if (hipMalloc((void**)&p->d_rX, nb * nm * 16) != hipSuccess ||
       hipMalloc((void**)&p->d_rG, nb * nm * 16) != hipSuccess ||
       hipMalloc((void**)&p->d_rZ, nb * (size_t)p->zstride * 16) != hipSuccess ||
       hipMalloc((void**)&p->d_part, nb * (size_t)p->n * 8) != hipSuccess)
@@ -566,10 +570,10 @@ int plan_enable_adjoint(ndg_plan* p) {
   if (!rc) rc = upload(&p->d_bidx, p->hbidx.data(), p->hbidx.size());
   if (rc) {
     (void)hipGetLastError();
-    void* ptrs[] = {p->d_rY, p->d_rX, p->d_rG, p->d_rZ, p->d_part, p->d_ovec, p->d_bidx};
+    void* ptrs[] = {p->d_rX, p->d_rG, p->d_rZ, p->d_part, p->d_ovec, p->d_bidx};
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
-    p->d_rY = p->d_rX = p->d_rG = p->d_rZ = nullptr;
+    p->d_rX = p->d_rG = p->d_rZ = nullptr;
     p->d_part = nullptr;
     p->d_ovec = nullptr;
     p->d_bidx = nullptr;
@@ -661,14 +665,13 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   if (growth && !e0p) launch_fill_zero(growth, nE, st);
   if (mode == kRunDensity) launch_zero(density, p->n, st);
   if (mode == kRunVjp) {
-    if (!p->d_rY) {
+    if (!p->d_rX) {
       set_error("ndg_density_vjp: call ndg_plan_enable_adjoint first");
       return NDG_EINVAL;
     }
     launch_zero(vbar, p->n, st);
   }
   RhsCtx r{};
-  r.Y = p->d_rY;
   r.X = p->d_rX;
   r.Gc = p->d_rG;
   r.Z = p->d_rZ;
@@ -726,9 +729,9 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         // two solves with the factors: G_{:,c} = A^{-1} E_c, then
         // X_c = A^{-1} (Lambda conj(G_{:,c}))
         for (int pass = 0; pass < 2; ++pass) {
-          if (pass == 0) launch_rhs_contact(c, r, cc, nb, st);
-          else launch_rhs_lambda(c, r, nb, st);
           RhsCtx rr = r;
+          rr.ymode = pass;
+          rr.cinv = p->d_cinv[cc];
           rr.X = pass == 0 ? r.Gc : r.X;
           for (int h = 1; h <= H; ++h)
             timed(K_RHS_FWD, h, nb, [&] {
