@@ -99,7 +99,8 @@ __global__ void __launch_bounds__(64) k_rhs_fwd_small(Ctx c, RhsCtx r, const int
           }
         }
         zi[x] = v;
-        if (on) Zf[(int64_t)x * m + a] = v;
+        // a leaf's Z_I is its right-hand side: the back substitution forms it again
+        if (on && nk > 0) Zf[(int64_t)x * m + a] = v;
       }
     }
     for (int i = 0; i < b; ++i) {
@@ -131,6 +132,7 @@ __global__ void __launch_bounds__(64) k_rhs_back_small(Ctx c, RhsCtx r, const in
   double2* psi = dsm;
   double2* ainv = dsm + s * b;
   int32_t* bix = reinterpret_cast<int32_t*>(ainv + s * s);
+  const bool leaf = c.kids_ptr[cl + 1] == c.kids_ptr[cl];  // Z_I not stored (k_rhs_fwd_small)
   const double2* Zf = r.Z + (int64_t)e * r.zstride + r.o_vec[cl];
   double2* X = r.X + (int64_t)e * r.n * m;
   const int t = threadIdx.x;
@@ -146,7 +148,7 @@ __global__ void __launch_bounds__(64) k_rhs_back_small(Ctx c, RhsCtx r, const in
     for (int i = 0; i < kRhsS; ++i) xo[i] = cz();
     // one input row at a time: only the outputs stay in registers
     for (int k = 0; k < s; ++k) {
-      const double2 z = on ? Zf[(int64_t)k * m + a] : cz();
+      const double2 z = !on ? cz() : leaf ? rhs_y(c, r, e, d.pt_off + k, a) : Zf[(int64_t)k * m + a];
 #pragma unroll
       for (int i = 0; i < kRhsS; ++i)
         if (i < s) cmac(xo[i], ainv[i * s + k], z);
