@@ -783,16 +783,19 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         const ndg_plan::Group& g = p->groups[h * ndg_plan::kClasses + q];
         if (!g.ncl) continue;
         const int32_t* cl = p->d_levels + g.cl0;
+        // the density needs only G^<, whose extraction reads none of G^r's
+        // rows (its source comes from the chain kernels)
+        const bool gr = mode != kRunDensity;
         if (q <= 2) {
           timed_on(sp, K_EXTRACT_SMALL_P, h, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, true, sp); });
-          timed(K_EXTRACT_SMALL, h, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, false, st); });
+          if (gr) timed(K_EXTRACT_SMALL, h, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, false, st); });
           continue;
         }
         const ColItem* ci = p->d_colitems + g.col0;
         if (g.ncol) timed_on(sp, K_DOWN_OFF_P, h, nb, [&] { launch_down_off(c, ci, g.ncol, nb, true, g.size, sp); });
         timed_on(sp, K_DOWN_DIAG_P, h, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, true, g.size, sp); });
-        if (g.ncol) timed(K_DOWN_OFF_G, h, nb, [&] { launch_down_off(c, ci, g.ncol, nb, false, g.size, st); });
-        timed(K_DOWN_DIAG_G, h, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, false, g.size, st); });
+        if (gr && g.ncol) timed(K_DOWN_OFF_G, h, nb, [&] { launch_down_off(c, ci, g.ncol, nb, false, g.size, st); });
+        if (gr) timed(K_DOWN_DIAG_G, h, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, false, g.size, st); });
       }
     }
     if (fork) {
