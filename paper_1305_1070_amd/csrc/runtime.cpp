@@ -720,7 +720,8 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         if (g.ncol) timed(K_PSI, h, nb, [&] { launch_psi(c, p->d_colitems + g.col0, g.ncol, nb, g.size, st); });
         if (g.nupd) timed(K_UPDATE, h, nb, [&] { launch_update(c, p->d_upditems + g.upd0, g.nupd, nb, st); });
       }
-      if (nch) timed(K_CHAIN_FWD, h, nb, [&] { launch_chain_fwd(c, chi, nch, nb, st); });
+      // the G^< source; the gradient's solves need only the factors
+      if (nch && mode != kRunVjp) timed(K_CHAIN_FWD, h, nb, [&] { launch_chain_fwd(c, chi, nch, nb, st); });
     }
     if (mode == kRunVjp) {
       launch_zero(r.part, (int64_t)nb * p->n, st);
