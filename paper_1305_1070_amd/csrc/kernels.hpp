@@ -94,9 +94,10 @@ struct Ctx {
 
 // Multi-right-hand-side solves with the factors of the fold (adjoint).
 struct RhsCtx {
-  // right-hand side, formed where the forward substitution reads it:
-  // ymode 0 the contact's unit columns E_c (cinv[row] = its column or -1),
-  // ymode 1 Lambda conj(G_{:,c}) from Gc and nbar
+  // right-hand side (the columns of all contacts side by side), formed where
+  // the forward substitution reads it: ymode 0 the unit columns E_c
+  // (cinv[row] = the column of a contact site, or -1), ymode 1
+  // Lambda conj(G_{:,c}) from Gc and nbar
   int32_t ymode;
   const int32_t* cinv;
   double2* X;         // [nb][n][m] solutions
@@ -142,7 +143,7 @@ void launch_rhs_fwd(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, 
                     bool big, hipStream_t st);
 void launch_rhs_back(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl, int nb, size_t small_lds,
                      bool big, hipStream_t st);
-void launch_vjp_accum(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st);
+void launch_vjp_accum(const Ctx& c, const RhsCtx& r, int cc, int off, int nb, hipStream_t st);
 void launch_zero(double* p, int64_t count, hipStream_t st);
 void launch_vjp_reduce(const Ctx& c, const RhsCtx& r, int nb, const double* cE, double* vbar, hipStream_t st);
 void launch_density(const Ctx& c, int nb, const double* cE, double* dens, hipStream_t st);

@@ -23,10 +23,10 @@
 
 namespace ndg {
 
-// Right-hand side entry Y[row][a] (internal row order): the contact's unit
-// columns E_c in the first solve, Lambda conj(G_{:,c}) with Lambda = diag(nbar)
-// (caller's order) in the second; formed where the forward substitution
-// reads it, never stored.
+// Right-hand side entry Y[row][a] (internal row order; the columns of all
+// contacts side by side): the unit columns E_c in the first solve,
+// Lambda conj(G_{:,c}) with Lambda = diag(nbar) (caller's order) in the
+// second; formed where the forward substitution reads it, never stored.
 __device__ inline double2 rhs_y(const Ctx& c, const RhsCtx& r, int e, int row, int a) {
   if (r.ymode == 0) return make_double2(r.cinv[row] == a ? 1.0 : 0.0, 0.0);
   const double w = r.nbar[c.perm[row]];
@@ -285,22 +285,24 @@ __global__ void __launch_bounds__(256) k_rhs_back(Ctx c, RhsCtx r, const int32_t
   }
 }
 
-// part[e][row] += 2 Im[ sum_a T[row][a] X[row][a] ],  T = G_{:,c} Sigma^<_c.
+// part[e][row] += 2 Im[ sum_a T[row][a] X[row][a] ],  T = G_{:,c} Sigma^<_c,
+// over contact c's block of columns [off, off + n_c) of G and X.
 // One block per 64 rows: each 64-column tile of T is formed on the matrix
 // cores and consumed in registers (never stored); the row sums are reduced
 // across the lanes of a row and the two column halves of the tile, column
 // tiles in order (deterministic).
-__global__ void __launch_bounds__(256) k_vjp(Ctx c, RhsCtx r, int cc) {
+__global__ void __launch_bounds__(256) k_vjp(Ctx c, RhsCtx r, int cc, int off) {
   __shared__ GemmSmem sm;
   using T = TileShape<64>;
   __shared__ double rowsum[T::WN][64];
   const int e = blockIdx.y;
-  const int m = r.m;
+  const int m = r.m;             // row stride: all contacts' columns
+  const int mc = sel2(c.nc, cc);  // this contact's columns [off, off + mc)
   const int i0 = blockIdx.x * 64;
   const int ni = min(64, r.n - i0);
-  const double2* G = r.Gc + (int64_t)e * r.n * m;
-  const double2* sg = sel2(c.sig_l, cc) + (int64_t)(c.e0 + e) * m * m;
-  const double2* X = r.X + (int64_t)e * r.n * m;
+  const double2* G = r.Gc + (int64_t)e * r.n * m + off;
+  const double2* sg = sel2(c.sig_l, cc) + (int64_t)(c.e0 + e) * mc * mc;
+  const double2* X = r.X + (int64_t)e * r.n * m + off;
   const int t = threadIdx.x;
   const TileLanes L(t);
   double rs[T::MB][4];
@@ -308,13 +310,13 @@ __global__ void __launch_bounds__(256) k_vjp(Ctx c, RhsCtx r, int cc) {
   for (int mm = 0; mm < T::MB; ++mm)
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) rs[mm][rr] = 0.0;
-  for (int j0 = 0; j0 < m; j0 += 64) {
-    const int nj = min(64, m - j0);
+  for (int j0 = 0; j0 < mc; j0 += 64) {
+    const int nj = min(64, mc - j0);
     ZTile acc;
     ztile_zero(acc);
     zgemm_acc_t<64, false, false, false>(
-        m, [&](int i, int k) { return i < ni ? G[(int64_t)(i0 + i) * m + k] : cz(); },
-        [&](int k, int j) { return j < nj ? sg[(int64_t)k * m + j0 + j] : cz(); }, acc, sm);
+        mc, [&](int i, int k) { return i < ni ? G[(int64_t)(i0 + i) * m + k] : cz(); },
+        [&](int k, int j) { return j < nj ? sg[(int64_t)k * mc + j0 + j] : cz(); }, acc, sm);
 #pragma unroll
     for (int mm = 0; mm < T::MB; ++mm)
 #pragma unroll
@@ -390,8 +392,8 @@ void launch_rhs_back(const Ctx& c, const RhsCtx& r, const int32_t* cls, int ncl,
   if (small_lds) hipLaunchKernelGGL(k_rhs_back_small, dim3(ncl, nb), dim3(64), small_lds, st, c, r, cls);
   if (big) hipLaunchKernelGGL(k_rhs_back, dim3(ncl, nb), dim3(256), 0, st, c, r, cls);
 }
-void launch_vjp_accum(const Ctx& c, const RhsCtx& r, int cc, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_vjp, dim3((r.n + 63) / 64, nb), dim3(256), 0, st, c, r, cc);
+void launch_vjp_accum(const Ctx& c, const RhsCtx& r, int cc, int off, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_vjp, dim3((r.n + 63) / 64, nb), dim3(256), 0, st, c, r, cc, off);
 }
 void launch_zero(double* p, int64_t count, hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count);

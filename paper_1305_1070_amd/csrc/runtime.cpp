@@ -69,7 +69,7 @@ struct ndg_plan {
   // adjoint workspace (ndg_plan_enable_adjoint): right-hand sides Y, solutions
   // X, contact columns of G, per-cluster front vectors, per-energy partials
   double2 *d_rX = nullptr, *d_rG = nullptr, *d_rZ = nullptr;
-  int32_t* d_cinv[2] = {nullptr, nullptr};  // per contact: internal position -> contact column, or -1
+  int32_t* d_cinv = nullptr;  // internal position -> column among all contacts' columns, or -1
   int64_t* d_ovec = nullptr;
   int32_t* d_bidx = nullptr;
   double* d_part = nullptr;
@@ -182,10 +182,10 @@ void free_plan(ndg_plan* p) {
   void* ptrs[] = {p->d_cl,        p->d_relmap,   p->d_kids_ptr,   p->d_kids,       p->d_hrow,
                   p->d_hcol,      p->d_hval,     p->d_perm,       p->d_owner,      p->d_cpos[0],
                   p->d_cpos[1],   p->d_levels,   p->d_colitems,   p->d_upditems,   p->d_chainitems,
-                  p->d_chaincls,  p->d_ws,       p->d_status,     p->d_cinv[0],    p->d_rX,
+                  p->d_chaincls,  p->d_ws,       p->d_status,     p->d_cinv,       p->d_rX,
                   p->d_rG,        p->d_rZ,       p->d_ovec,       p->d_bidx,       p->d_part,
                   p->d_srow,      p->d_scol,     p->d_scid,       p->d_sflat,      p->d_hfront,
-                  p->d_smap,      p->d_pinv,     p->d_gaddr,      p->d_sdiag,      p->d_cinv[1]};
+                  p->d_smap,      p->d_pinv,     p->d_gaddr,      p->d_sdiag};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& r : p->recs) {
@@ -468,11 +468,14 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   rc = rc ? rc : upload(&p->d_hval, sy.hval.data(), sy.hval.size());
   rc = rc ? rc : upload(&p->d_perm, sy.perm.data(), sy.perm.size());
   rc = rc ? rc : upload(&p->d_owner, sy.owner.data(), sy.owner.size());
-  for (int c = 0; c < p->ncontacts && !rc; ++c) {
-    rc = upload(&p->d_cpos[c], sy.contact_pos[c].data(), sy.contact_pos[c].size());
+  {
     std::vector<int32_t> cinv(p->n, -1);
-    for (size_t a = 0; a < sy.contact_pos[c].size(); ++a) cinv[sy.contact_pos[c][a]] = (int32_t)a;
-    rc = rc ? rc : upload(&p->d_cinv[c], cinv.data(), cinv.size());
+    int32_t col = 0;
+    for (int c = 0; c < p->ncontacts && !rc; ++c) {
+      rc = upload(&p->d_cpos[c], sy.contact_pos[c].data(), sy.contact_pos[c].size());
+      for (size_t a = 0; a < sy.contact_pos[c].size(); ++a) cinv[sy.contact_pos[c][a]] = col++;
+    }
+    rc = rc ? rc : upload(&p->d_cinv, cinv.data(), cinv.size());
   }
   rc = rc ? rc : upload(&p->d_srow, sy.srow.data(), sy.srow.size());
   rc = rc ? rc : upload(&p->d_scol, sy.scol.data(), sy.scol.size());
@@ -549,8 +552,10 @@ int plan_info(const ndg_plan* plan, ndg_info* out) {
 int plan_enable_adjoint(ndg_plan* p) {
   if (p->d_rX) return NDG_OK;
   if (hipSetDevice(p->device) != hipSuccess) { set_error("ndg_plan_enable_adjoint: hipSetDevice failed"); return NDG_EHIP; }
-  int mmax = 1;
-  for (int c = 0; c < p->ncontacts; ++c) mmax = std::max(mmax, p->nc[c]);
+  // one right-hand side with the columns of all contacts side by side
+  int mmax = 0;
+  for (int c = 0; c < p->ncontacts; ++c) mmax += p->nc[c];
+  mmax = std::max(mmax, 1);
   std::vector<int64_t> ovec(p->nclusters);
   int64_t off = 0;
   for (int k = 0; k < p->nclusters; ++k) {
@@ -725,14 +730,15 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
     }
     if (mode == kRunVjp) {
       launch_zero(r.part, (int64_t)nb * p->n, st);
-      for (int cc = 0; cc < p->ncontacts; ++cc) {
-        r.m = p->nc[cc];
-        // two solves with the factors: G_{:,c} = A^{-1} E_c, then
-        // X_c = A^{-1} (Lambda conj(G_{:,c}))
+      r.m = 0;
+      for (int cc = 0; cc < p->ncontacts; ++cc) r.m += p->nc[cc];
+      if (r.m > 0) {
+        // two solves with the factors, all contacts' columns at once:
+        // G_{:,c} = A^{-1} E_c, then X_c = A^{-1} (Lambda conj(G_{:,c}))
         for (int pass = 0; pass < 2; ++pass) {
           RhsCtx rr = r;
           rr.ymode = pass;
-          rr.cinv = p->d_cinv[cc];
+          rr.cinv = p->d_cinv;
           rr.X = pass == 0 ? r.Gc : r.X;
           for (int h = 1; h <= H; ++h)
             timed(K_RHS_FWD, h, nb, [&] {
@@ -745,7 +751,8 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
                               p->rhs_lds_back[h], p->rhs_big[h], st);
             });
         }
-        timed(K_VJP, 0, nb, [&] { launch_vjp_accum(c, r, cc, nb, st); });
+        for (int cc = 0, off = 0; cc < p->ncontacts; off += p->nc[cc], ++cc)
+          timed(K_VJP, 0, nb, [&] { launch_vjp_accum(c, r, cc, off, nb, st); });
       }
       launch_vjp_reduce(c, r, nb, cE, vbar, st);
       p->last_batch = nb;
