@@ -326,16 +326,18 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
     if (s + b <= kSmallFront) {
       // whole-front elimination: s steps over the f x f front
       addc(K_FOLD_SMALL, h, 8.0 * s * f * f, 16.0 * (kidb + s * s + s * b + b * b));
+      // X_BB counted by its distinct entries (symmetric for G^r,
+      // anti-Hermitian for G^<): b (b + 1) / 2
       for (int q : {K_EXTRACT_SMALL, K_EXTRACT_SMALL_P})
         addc(q, h, 8.0 * (s * b * b + s * s * b),
-             16.0 * (b * b + s * s + s * b) + 16.0 * (inner ? s * b + s * s : s));
+             16.0 * (b * (b + 1) / 2 + s * s + s * b) + 16.0 * (inner ? s * b + s * s : s));
     } else {
       addc(K_ASSEMBLE, h, 0.0, 16.0 * (f * f + kidb));
       addc(K_FACTOR, h, 8.0 * s * s * s, 16.0 * 2 * s * s);
       addc(K_PSI, h, 8.0 * s * s * b, 16.0 * (s * s + 2 * s * b));
       addc(K_UPDATE, h, 8.0 * s * b * b, 16.0 * (2 * s * b + 2 * b * b));
       for (int q : {K_DOWN_OFF_G, K_DOWN_OFF_P})
-        addc(q, h, 8.0 * s * b * b, 16.0 * (s * b + b * b + s * b));
+        addc(q, h, 8.0 * s * b * b, 16.0 * (s * b + b * (b + 1) / 2 + s * b));
       for (int q : {K_DOWN_DIAG_G, K_DOWN_DIAG_P}) addc(q, h, 8.0 * s * s * b, 16.0 * (2 * s * b + 2 * s * s));
     }
     for (int c = 0; c < p->ncontacts; ++c) {
