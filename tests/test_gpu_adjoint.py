@@ -49,15 +49,19 @@ def _vjp(plan, wl, t, v, nbar):
     return g.cpu().numpy()
 
 
-def test_density_and_vjp_match_dense_oracle(lib):
+@pytest.mark.parametrize("ny,nx,leaf", [(14, 8, 8), (20, 40, 16)])
+def test_density_and_vjp_match_dense_oracle(lib, ny, nx, leaf):
+    """(20, 40): both contacts' 80 columns form one right-hand side (a full and
+    a ragged 64-column chunk), and the 40-point separators take the tiled
+    solve kernels while the leaves take the one-wavefront ones."""
     from oracle import gradient
-    wl = workloads.small_grid(14, 8, n_energies=4, emin=0.02, emax=0.3, eta=1e-3)
+    wl = workloads.small_grid(ny, nx, n_energies=4, emin=0.02, emax=0.3, eta=1e-3)
     dev = wl.device
     rng = np.random.default_rng(31)
     v = rng.uniform(-0.03, 0.03, dev.n)
     nbar = rng.uniform(0.5, 1.5, dev.n)
-    _say("density / vjp 14x8 vs dense oracle")
-    plan, t, (sl, sr, ll, lr) = _setup(lib, wl, leaf_max=8, max_batch=3)
+    _say("density / vjp %dx%d vs dense oracle" % (ny, nx))
+    plan, t, (sl, sr, ll, lr) = _setup(lib, wl, leaf_max=leaf, max_batch=3)
     n_gpu = _density(plan, wl, t, v)
     n_ref = gradient.density(dev.scipy_h(), v, wl.energies, wl.eta, dev.contacts, [sl, sr],
                              [ll, lr], wl.quad_weights())
