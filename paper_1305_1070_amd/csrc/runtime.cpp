@@ -332,7 +332,11 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
         addc(q, h, 8.0 * (s * b * b + s * s * b),
              16.0 * (b * (b + 1) / 2 + s * s + s * b) + 16.0 * (inner ? s * b + s * s : s));
     } else {
-      addc(K_ASSEMBLE, h, 0.0, 16.0 * (f * f + kidb));
+      // the cluster's rows written once, each child's contribution to them
+      // (its first nself boundary rows) read once
+      double kidrows = 0;
+      for (int32_t ch : sy.children[k]) kidrows += (double)p->hdesc[ch].nself * sy.b(ch);
+      addc(K_ASSEMBLE, h, 0.0, 16.0 * (s * f + kidrows));
       addc(K_FACTOR, h, 8.0 * s * s * s, 16.0 * 2 * s * s);
       addc(K_PSI, h, 8.0 * s * s * b, 16.0 * (s * s + 2 * s * b));
       addc(K_UPDATE, h, 8.0 * s * b * b, 16.0 * (2 * s * b + 2 * b * b));
