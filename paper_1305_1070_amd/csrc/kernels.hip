@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // its own rows [G_ii, G_{i,B}], which its descendants read.
 // ---------------------------------------------------------------------------
 template <int TM, bool P64>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_down_off(Ctx c, const ColItem* items, int lesser) {
+__device__ __forceinline__ void down_off_body(const Ctx& c, const ColItem* items, int lesser) {
   using GM = Gemm<P64>;
   __shared__ typename GM::template SmemT<TM> sm;
   const ColItem it = items[blockIdx.x];
@@ -469,10 +469,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   });
 }
 
+// 32- and 64-row tiles: three waves per SIMD; 16-row tiles (bound by the
+// gather of X_{B,B}, not the matrix cores) hold fewer registers and run six
+// to keep more gathers in flight.
+template <int TM, bool P64>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_down_off(Ctx c, const ColItem* items, int lesser) {
+  down_off_body<TM, P64>(c, items, lesser);
+}
+template <bool P64>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+k_down_off_narrow(Ctx c, const ColItem* items, int lesser) {
+  down_off_body<16, P64>(c, items, lesser);
+}
+
 //   G_ii = A_ii^{-1} + Psi_i G_{B,i},  G_{B,i} = G_{i,B}^T
 //   P_ii = P_init + Psi_i P_{B,i},     P_{B,i} = -P_{i,B}^+
 template <int TM, bool P64>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_down_diag(Ctx c, const int32_t* cls, int lesser) {
+__device__ __forceinline__ void down_diag_body(const Ctx& c, const int32_t* cls, int lesser) {
   using GM = Gemm<P64>;
   __shared__ typename GM::template SmemT<TM> sm;
   const int cl = cls[blockIdx.x];
@@ -516,6 +530,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
       X[pos] = v;
     }
   });
+}
+
+// Entry points as for k_down_off: 16-row tiles at six waves per SIMD.
+template <int TM, bool P64>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_down_diag(Ctx c, const int32_t* cls, int lesser) {
+  down_diag_body<TM, P64>(c, cls, lesser);
+}
+template <bool P64>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+k_down_diag_narrow(Ctx c, const int32_t* cls, int lesser) {
+  down_diag_body<16, P64>(c, cls, lesser);
 }
 
 // diag G^r, G^<, G^> in the caller's site order; G^> = G^< + G^r - (G^r)^*.
@@ -591,7 +617,7 @@ void launch_chain_fwd(const Ctx& c, const ChainItem* it, int nit, int nb, hipStr
 template <bool P64>
 static void down_off_t(const Ctx& c, const ColItem* it, int nit, int nb, bool lesser, int cls_size,
                        hipStream_t st) {
-  if (cls_size <= 16) hipLaunchKernelGGL((k_down_off<16, P64>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
+  if (cls_size <= 16) hipLaunchKernelGGL((k_down_off_narrow<P64>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
   else if (cls_size <= 32) hipLaunchKernelGGL((k_down_off<32, P64>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
   else hipLaunchKernelGGL((k_down_off<64, P64>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
 }
@@ -604,7 +630,7 @@ void launch_down_off(const Ctx& c, const ColItem* it, int nit, int nb, bool less
 template <bool P64>
 static void down_diag_t(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, int cls_size,
                         hipStream_t st) {
-  if (cls_size <= 16) hipLaunchKernelGGL((k_down_diag<16, P64>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
+  if (cls_size <= 16) hipLaunchKernelGGL((k_down_diag_narrow<P64>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
   else if (cls_size <= 32) hipLaunchKernelGGL((k_down_diag<32, P64>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
   else hipLaunchKernelGGL((k_down_diag<64, P64>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
 }
