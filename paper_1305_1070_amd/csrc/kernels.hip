@@ -170,11 +170,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 }
 
 // Schur contribution of cluster i to its parent front:
-// U = F_BB + Psi^T F_{i,B} (b x b), one 64 x 64 tile per block.
-template <bool P64>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_update(Ctx c, const UpdItem* items) {
+// U = F_BB + Psi^T F_{i,B} (b x b), one TM x 64 tile per block.  Clusters
+// with s <= 16 (K = s: the tile is all gather and store) take 32-row tiles:
+// half the accumulators, more blocks in flight, less padding on ragged edges.
+template <int TM, bool P64>
+__device__ __forceinline__ void update_body(const Ctx& c, const UpdItem* items) {
   using GM = Gemm<P64>;
-  __shared__ typename GM::Smem sm;
+  __shared__ typename GM::template SmemT<TM> sm;
   const UpdItem it = items[blockIdx.x];
   const int e = blockIdx.y;
   const int eb = ebase(c);
@@ -185,8 +187,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   const double2* Psi = S + d.o_psi;
   double2* U = S + d.o_upd;
   const int s = d.s, b = d.b, f = d.f;
-  const int i0 = it.tr * 64, j0 = it.tc * 64;
-  const int ni = min(64, b - i0), nj = min(64, b - j0);
+  const int i0 = it.tr * TM, j0 = it.tc * 64;
+  const int ni = min(TM, b - i0), nj = min(64, b - j0);
   // the children's index maps and contribution blocks (F_BB is gathered)
   __shared__ int64_t kid_inv[kMaxKids], kid_upd[kMaxKids];
   __shared__ int kid_b[kMaxKids];
@@ -199,7 +201,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   }
   typename GM::Tile acc;
   GM::zero(acc);
-  GM::template acc<64, true, false, false>(
+  GM::template acc<TM, true, false, false>(
       s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
       [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm);
   // F_BB gathered from the children: each lane holds fixed tile rows and
@@ -208,9 +210,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   // one), so their map entries are loaded once per child.  FP64 tiles take
   // the sum straight into the accumulators; with FP32 tiles it is kept in
   // FP64 and added when the tile is stored
-  using T = TileShape<64>;
+  using T = TileShape<TM>;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = (w / T::WN) * (64 / T::WM), wc = (w % T::WN) * (64 / T::WN);
+  const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
   double cr[T::MB][T::NB][4], ci[T::MB][T::NB][4];
 #pragma unroll
   for (int m = 0; m < T::MB; ++m)
@@ -264,6 +266,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
           U[(int64_t)(i0 + i) * b + j0 + j] =
               make_double2(cr[m][n][r] + (double)acc.re[m][n][r], ci[m][n][r] + (double)acc.im[m][n][r]);
       }
+}
+
+template <bool P64>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_update(Ctx c, const UpdItem* items) {
+  update_body<64, P64>(c, items);
+}
+template <bool P64>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+k_update_narrow(Ctx c, const UpdItem* items) {
+  update_body<32, P64>(c, items);
 }
 
 // ---------------------------------------------------------------------------
@@ -606,10 +619,15 @@ void launch_psi(const Ctx& c, const ColItem* it, int nit, int nb, int cls_size, 
   else if (cls_size <= 32) hipLaunchKernelGGL((k_psi<32>), dim3(nit, nb), dim3(256), 0, st, c, it);
   else hipLaunchKernelGGL((k_psi<64>), dim3(nit, nb), dim3(256), 0, st, c, it);
 }
-void launch_update(const Ctx& c, const UpdItem* it, int nit, int nb, hipStream_t st) {
+void launch_update(const Ctx& c, const UpdItem* it, int nit, int nb, int tile_rows, hipStream_t st) {
   if (nit <= 0) return;
-  if (c.mixed) hipLaunchKernelGGL((k_update<false>), dim3(nit, nb), dim3(256), 0, st, c, it);
-  else hipLaunchKernelGGL((k_update<true>), dim3(nit, nb), dim3(256), 0, st, c, it);
+  if (tile_rows == 32) {
+    if (c.mixed) hipLaunchKernelGGL((k_update_narrow<false>), dim3(nit, nb), dim3(256), 0, st, c, it);
+    else hipLaunchKernelGGL((k_update_narrow<true>), dim3(nit, nb), dim3(256), 0, st, c, it);
+  } else {
+    if (c.mixed) hipLaunchKernelGGL((k_update<false>), dim3(nit, nb), dim3(256), 0, st, c, it);
+    else hipLaunchKernelGGL((k_update<true>), dim3(nit, nb), dim3(256), 0, st, c, it);
+  }
 }
 void launch_chain_fwd(const Ctx& c, const ChainItem* it, int nit, int nb, hipStream_t st) {
   if (nit > 0) hipLaunchKernelGGL(k_chain_fwd, dim3(nit, nb), dim3(256), 0, st, c, it);

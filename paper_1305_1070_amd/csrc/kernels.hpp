@@ -45,7 +45,7 @@ struct ClusterDesc {
 // the G^r and G^< fronts, and its cluster.
 struct SiteDiag { int64_t og, ol; int32_t cl, pad; };
 
-struct UpdItem { int32_t cl, tr, tc, pad; };   // Schur update tile (rows tr*64.., cols tc*64..)
+struct UpdItem { int32_t cl, tr, tc, pad; };   // Schur update tile (rows tr*TM.., cols tc*64..)
 struct ColItem { int32_t cl, tc; };            // column tile of an s x b panel
 struct ChainItem { int32_t cl, c; };           // chain cluster and contact
 
@@ -116,7 +116,9 @@ void launch_assemble(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStrea
 // cls_size: the largest cluster size s of the launch (selects the tile shape)
 void launch_factor(const Ctx& c, const int32_t* cls, int ncl, int nb, int cls_size, hipStream_t st);
 void launch_psi(const Ctx& c, const ColItem* it, int nit, int nb, int cls_size, hipStream_t st);
-void launch_update(const Ctx& c, const UpdItem* it, int nit, int nb, hipStream_t st);
+// tile_rows: 64, or 32 for clusters with s <= kUpdNarrowS (items of that height)
+constexpr int kUpdNarrowS = 16;
+void launch_update(const Ctx& c, const UpdItem* it, int nit, int nb, int tile_rows, hipStream_t st);
 void launch_chain_fwd(const Ctx& c, const ChainItem* it, int nit, int nb, hipStream_t st);
 void launch_down_off(const Ctx& c, const ColItem* it, int nit, int nb, bool lesser, int cls_size,
                      hipStream_t st);

@@ -281,7 +281,9 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
           g.size = std::max(g.size, s_);
           const int nt = (b + 63) / 64;
           for (int tc = 0; tc < nt; ++tc) cols.push_back(ColItem{k, tc});
-          for (int tr = 0; tr < nt; ++tr)
+          // class 3 (s <= 16) updates in 32-row tiles
+          const int ntr = q == 3 ? (b + 31) / 32 : nt;
+          for (int tr = 0; tr < ntr; ++tr)
             for (int tc = 0; tc < nt; ++tc) upds.push_back(UpdItem{k, tr, tc, 0});
         }
       }
@@ -729,7 +731,8 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         timed(K_ASSEMBLE, h, nb, [&] { launch_assemble(c, cl, g.ncl, nb, st); });
         timed(K_FACTOR, h, nb, [&] { launch_factor(c, cl, g.ncl, nb, g.size, st); });
         if (g.ncol) timed(K_PSI, h, nb, [&] { launch_psi(c, p->d_colitems + g.col0, g.ncol, nb, g.size, st); });
-        if (g.nupd) timed(K_UPDATE, h, nb, [&] { launch_update(c, p->d_upditems + g.upd0, g.nupd, nb, st); });
+        if (g.nupd)
+          timed(K_UPDATE, h, nb, [&] { launch_update(c, p->d_upditems + g.upd0, g.nupd, nb, q == 3 ? 32 : 64, st); });
       }
       // the G^< source; the gradient's solves need only the factors
       if (nch && mode != kRunVjp) timed(K_CHAIN_FWD, h, nb, [&] { launch_chain_fwd(c, chi, nch, nb, st); });
