@@ -9,8 +9,9 @@ arithmetic.
 
 What it computes (all complex128 / float64):
   * definition.py -- the problem statement itself (Section 1, equations
-    defineGless1 and defineA): A = zI - H - diag(V) - Sigma_L - Sigma_R,
-    G^r = A^{-1} by dense LU, G^< = G^r Sigma^< G^r+, and
+    defineGless1 and defineA): A = zI - H - diag(V) - Sigma_L - Sigma_R
+    - diag(Sigma_Phonon) (the phonon term optional and diagonal, its lesser
+    part added to Sigma^<), G^r = A^{-1} by dense LU, G^< = G^r Sigma^< G^r+, and
     G^> := G^< + G^r - G^r+ on the diagonal.  The nested-dissection method is
     exact (Sections 1 and 3: every stored entry of G^(0) and P^(0) equals the
     corresponding entry of G^r and G^<), so this definition is the oracle.
@@ -27,5 +28,8 @@ and lesser, exact at complex energy), unit transmission per open mode, the
 anti-Hermiticity of G^<, the identity G^r - G^r+ = -i G^r Gamma G^r+ with
 Gamma including the 2 eta broadening, equilibrium G^< = -f (G^r - G^r+) up to
 the eta term, the paper's printed 3-cluster and 3-level block formulas, and
-central finite differences for the gradient.
+central finite differences for the gradient.  With phonons: the 50-digit brute
+force, the waveguide closed form at z = E + i(eta + gamma/2) for a uniform
+Sigma^r_ph = -i gamma/2, and the fluctuation-dissipation identity
+G^< = -f (G^r - G^r+) at eta = 0 in equilibrium.
 """

@@ -1,10 +1,12 @@
 """The problem statement written out densely (Section 1).
 
-A(E) = E I - H - Sigma^r_L - Sigma^r_R (equation defineA; no phonon term),
+A(E) = E I - H - Sigma^r_L - Sigma^r_R - Sigma^r_Phonon (equation defineA),
 with E replaced by z = E + i eta and the on-site potential V added to H.
-G^r solves A G^r = I and G^< solves A G^< = Sigma^< (G^r)+ (equation
-defineGless1), so G^< = G^r Sigma^< G^r+.  G^> on the diagonal is taken from
-G^> - G^< = G^r - G^r+.
+The phonon self-energy is optional and diagonal (one complex value per site
+and energy, the case Section 1 assumes), and its lesser part adds to the
+contacts' Sigma^<.  G^r solves A G^r = I and G^< solves
+A G^< = Sigma^< (G^r)+ (equation defineGless1), so G^< = G^r Sigma^< G^r+.
+G^> on the diagonal is taken from G^> - G^< = G^r - G^r+.
 
 Everything is a plain dense computation: assemble A, LU-factor it with
 partial pivoting (scipy/LAPACK), solve for the needed columns.
@@ -25,8 +27,9 @@ def dense_h(h) -> np.ndarray:
     return np.asarray(h, dtype=np.float64)
 
 
-def assemble_a(h: np.ndarray, v, z: complex, contacts, sig_r) -> np.ndarray:
-    """A = z I - H - diag(V) - sum_c Sigma^r_c placed on contact c's sites."""
+def assemble_a(h: np.ndarray, v, z: complex, contacts, sig_r, sig_r_ph=None) -> np.ndarray:
+    """A = z I - H - diag(V) - sum_c Sigma^r_c placed on contact c's sites
+    - diag(Sigma^r_Phonon) (sig_r_ph: [n] complex, or None)."""
     n = h.shape[0]
     a = -h.astype(np.complex128)
     a[np.diag_indices(n)] += z
@@ -34,29 +37,37 @@ def assemble_a(h: np.ndarray, v, z: complex, contacts, sig_r) -> np.ndarray:
         a[np.diag_indices(n)] -= np.asarray(v, dtype=np.float64)
     for sites, s in zip(contacts, sig_r):
         a[np.ix_(sites, sites)] -= s
+    if sig_r_ph is not None:
+        a[np.diag_indices(n)] -= np.asarray(sig_r_ph, dtype=np.complex128)
     return a
 
 
-def full_greens(h, v, e: float, eta: float, contacts, sig_r, sig_less):
+def full_greens(h, v, e: float, eta: float, contacts, sig_r, sig_less, sig_r_ph=None,
+                sig_less_ph=None):
     """Full matrices (G^r, G^<) at one energy; sig_r / sig_less are lists of
-    dense contact blocks in the site order of `contacts`."""
+    dense contact blocks in the site order of `contacts`; sig_r_ph /
+    sig_less_ph the phonon self-energies' diagonals ([n] each) or None."""
     hd = dense_h(h)
-    a = assemble_a(hd, v, complex(e, eta), contacts, sig_r)
+    a = assemble_a(hd, v, complex(e, eta), contacts, sig_r, sig_r_ph)
     lu = sla.lu_factor(a)
     g = sla.lu_solve(lu, np.eye(a.shape[0], dtype=np.complex128))
     n = a.shape[0]
     sl = np.zeros((n, n), np.complex128)
     for sites, s in zip(contacts, sig_less):
         sl[np.ix_(sites, sites)] += s
+    if sig_less_ph is not None:
+        sl[np.diag_indices(n)] += np.asarray(sig_less_ph, dtype=np.complex128)
     gl = g @ sl @ g.conj().T
     return g, gl
 
 
-def diag_greens(h, v, energies, eta: float, contacts, sig_r, sig_less):
+def diag_greens(h, v, energies, eta: float, contacts, sig_r, sig_less, sig_r_ph=None,
+                sig_less_ph=None):
     """diag G^r, diag G^<, diag G^> for every energy.
 
-    sig_r[c] and sig_less[c] are [nE, nc, nc] arrays for contact c.
-    Returns three complex128 arrays [nE, n]."""
+    sig_r[c] and sig_less[c] are [nE, nc, nc] arrays for contact c;
+    sig_r_ph / sig_less_ph are [nE, n] diagonals of the phonon self-energies
+    (site order of H) or None.  Returns three complex128 arrays [nE, n]."""
     hd = dense_h(h)
     n = hd.shape[0]
     energies = np.atleast_1d(np.asarray(energies, dtype=np.float64))
@@ -65,7 +76,8 @@ def diag_greens(h, v, energies, eta: float, contacts, sig_r, sig_less):
     dgl = np.zeros((ne, n), np.complex128)
     eye = np.eye(n, dtype=np.complex128)
     for k, e in enumerate(energies):
-        a = assemble_a(hd, v, complex(e, eta), contacts, [s[k] for s in sig_r])
+        a = assemble_a(hd, v, complex(e, eta), contacts, [s[k] for s in sig_r],
+                       None if sig_r_ph is None else sig_r_ph[k])
         lu = sla.lu_factor(a)
         g = sla.lu_solve(lu, eye)
         dgr[k] = np.diag(g)
@@ -74,6 +86,9 @@ def diag_greens(h, v, energies, eta: float, contacts, sig_r, sig_less):
             gc = g[:, sites]                       # columns of G^r on the contact
             # (G Sigma^< G+)_jj = sum_ab G_ja S_ab conj(G_jb)
             acc += np.einsum("ja,ab,jb->j", gc, s[k], gc.conj())
+        if sig_less_ph is not None:
+            # diagonal Sigma^<: (G diag(sigma) G+)_jj = sum_m |G_jm|^2 sigma_m
+            acc += (np.abs(g) ** 2) @ np.asarray(sig_less_ph[k], dtype=np.complex128)
         dgl[k] = acc
     dgg = dgl + dgr - dgr.conj()
     return dgr, dgl, dgg

@@ -11,7 +11,7 @@ finite differences.
 import numpy as np
 import pytest
 
-from inputs import devices, leads, workloads
+from inputs import devices, leads, phonons, workloads
 from oracle import brute, definition, gradient, rgf
 
 pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
@@ -204,6 +204,73 @@ def test_equilibrium_lesser():
         f = leads.fermi(e[k], 0.1, 0.025)
         rhs = -f * (g - g.conj().T) - 2j * wl.eta * f * g @ g.conj().T
         assert _rel(gl, rhs) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# diagonal phonon self-energies (Sigma^r_Phonon of equation defineA, diagonal
+# as Section 1 takes it; its lesser part adds to Sigma^<)
+# ---------------------------------------------------------------------------
+
+def test_phonon_dense_matches_mpmath_bruteforce():
+    wl = workloads.small_grid(5, 4, n_energies=2, emin=0.05, emax=0.25, eta=1e-3, noise=0.05, seed=12)
+    e, sr, sl = _problem(wl)
+    pr, pl = phonons.diagonal_self_energies(wl.device, e, gamma0=2e-2, seed=3)
+    h = wl.device.dense_h()
+    dgr, dgl, _ = definition.diag_greens(h, None, e, wl.eta, wl.device.contacts, sr, sl, pr, pl)
+    for k in range(len(e)):
+        bgr, bgl = brute.diag_greens(h, None, e[k], wl.eta, wl.device.contacts,
+                                     [s[k] for s in sr], [s[k] for s in sl],
+                                     sig_r_ph=pr[k], sig_less_ph=pl[k])
+        assert _rel(dgr[k], bgr) < 1e-11
+        assert _rel(dgl[k], bgl) < 1e-10
+    # the phonon terms are not negligible at this size
+    dgr0, dgl0, _ = definition.diag_greens(h, None, e, wl.eta, wl.device.contacts, sr, sl)
+    assert _rel(dgr0, dgr) > 1e-3 and _rel(dgl0, dgl) > 1e-3
+
+
+@pytest.mark.parametrize("gamma", [1e-3, 2e-2])
+def test_phonon_uniform_broadening_matches_waveguide_closed_form(gamma):
+    """Sigma^r_ph = -i gamma / 2 on every site (Sigma^<_ph = 0) turns the
+    device's z = E + i eta into E + i (eta + gamma / 2); with the leads taken
+    at that z too, the closed form of the infinite waveguide holds there."""
+    ny, nx, eta = 16, 8, 1e-6
+    wl = workloads.uniform_waveguide(ny, nx, n_energies=4, emax=0.6, eta=eta)
+    e = wl.energies
+    eta2 = eta + 0.5 * gamma
+    sl_, sr_, ll_, lr_ = leads.contact_self_energies(wl.device, e, eta2, wl.mu, wl.kt)
+    n = wl.device.n
+    pr = np.full((len(e), n), -0.5j * gamma)
+    pl = np.zeros((len(e), n), np.complex128)
+    dgr, dgl, _ = definition.diag_greens(wl.device.scipy_h(), None, e, eta, wl.device.contacts,
+                                         [sl_, sr_], [ll_, lr_], pr, pl)
+    t0 = wl.device.lead["t0"]
+    for k in range(len(e)):
+        f_l = leads.fermi(e[k], wl.mu[0], wl.kt)
+        f_r = leads.fermi(e[k], wl.mu[1], wl.kt)
+        cgr, cgl = _waveguide_closed_form(ny, nx, t0, complex(e[k], eta2), f_l, f_r)
+        assert _rel(dgr[k], cgr) < 1e-10
+        assert _rel(dgl[k], cgl) < 1e-9
+
+
+def test_phonon_equilibrium_fluctuation_dissipation():
+    """One chemical potential for the leads and every phonon site, eta = 0
+    in the device: Sigma^< = -f (Sigma^r - Sigma^r+) for every source, so
+    G^< = -f (G^r - G^r+) exactly (A+ - A = Sigma^r - Sigma^r+)."""
+    dev = devices.fd2d(8, 4)
+    e = np.array([0.05, 0.2])
+    mu = (0.1, 0.1)
+    sl_, sr_, ll_, lr_ = leads.contact_self_energies(dev, e, 1e-6, mu, 0.025)
+    pr, pl = phonons.diagonal_self_energies(dev, e, gamma0=1e-2, mu=mu, seed=7, equilibrium=True)
+    for k in range(len(e)):
+        g, gl = definition.full_greens(dev.scipy_h(), None, e[k], 0.0, dev.contacts,
+                                       [sl_[k], sr_[k]], [ll_[k], lr_[k]], pr[k], pl[k])
+        f = leads.fermi(e[k], 0.1, 0.025)
+        assert _rel(gl, -f * (g - g.conj().T)) < 1e-11
+        # and the diagonal path of the oracle agrees with the full matrices
+        dgr, dgl, _ = definition.diag_greens(dev.scipy_h(), None, e[k:k + 1], 0.0, dev.contacts,
+                                             [sl_[k:k + 1], sr_[k:k + 1]], [ll_[k:k + 1], lr_[k:k + 1]],
+                                             pr[k:k + 1], pl[k:k + 1])
+        assert _rel(dgl[0], np.diag(gl)) < 1e-12 and _rel(dgr[0], np.diag(g)) < 1e-12
 
 
 # ---------------------------------------------------------------------------

@@ -180,3 +180,110 @@ def test_appendix_three_level_gless(appendix, sigma_on):
         pr3 = air @ N[(r, 3)] - air @ B(r, 3) @ p33_1 + air @ B(r, 5) @ p35_1.conj().T
         prr = air @ N[(r, r)] + air @ B(r, 3) @ pr3.conj().T + air @ B(r, 5) @ pr5.conj().T
         assert _close(pr5, GL(r, 5)) and _close(pr3, GL(r, 3)) and _close(prr, GL(r, r))
+
+
+# ---------------------------------------------------------------------------
+# Section 3.2's multilevel algorithms on a tree where a cluster has an
+# ancestor it is not coupled to, with Sigma^< on every cluster (the diagonal
+# phonon case): P_i is the set of ALL ancestors of i (the paper's
+# definition), and the N fold needs every (cluster, ancestor) block of
+# G^(0).  Restricting P_i to the ancestors coupled to i after fill (which is
+# exact for G^r, where Psi_ij = 0 for the others) loses terms of N.
+# ---------------------------------------------------------------------------
+
+def _chain7():
+    """Seven clusters in a line, 1-2-3-4-5-6-7 (0-based 0..6): leaves 1, 3,
+    5, 7 (level 1), separators 2 and 6 (level 2), root 4 (level 3).  Cluster
+    1 couples to 2 only: its ancestors are {2, 4}, but only 2 is coupled to
+    it, before or after fill."""
+    sizes = [4, 3, 4, 3, 4, 3, 4]
+    a, sig, sl = _make(sizes, [(k, k + 1) for k in range(6)])
+    parent = [1, 3, 1, -1, 5, 3, 5]
+    level = [1, 2, 1, 3, 1, 2, 1]
+    return a, sig, sl, parent, level
+
+
+def _ancestors(parent, i):
+    out = []
+    while parent[i] >= 0:
+        i = parent[i]
+        out.append(i)
+    return out
+
+
+def _multilevel(a, sig, sl, parent, level, ancestor_sets):
+    """G^r and G^< blocks by the four steps of Section 3.2, with the given
+    ancestor set per cluster standing for P_i.  Returns dicts of blocks."""
+    inv = np.linalg.inv
+    nl = max(level)
+    A = {(i, j): a[sl[i], sl[j]].copy() for i in range(len(sl)) for j in range(len(sl))}
+    on = lambda l: [i for i in range(len(sl)) if level[i] == l]
+    P = ancestor_sets
+    # fold: A_jk += Psi_ij^T A_ik for j, k in P_i
+    psi = {}
+    for l in range(1, nl):
+        for i in on(l):
+            ainv = inv(A[(i, i)])
+            for j in P[i]:
+                psi[(i, j)] = -ainv @ A[(i, j)]
+            for j in P[i]:
+                for k in P[i]:
+                    A[(j, k)] = A[(j, k)] + psi[(i, j)].T @ A[(i, k)]
+    root = on(nl)[0]
+    # G^r extraction
+    G = {(root, root): inv(A[(root, root)])}
+    for l in range(nl - 1, 0, -1):
+        for i in on(l):
+            for j in P[i]:
+                G[(i, j)] = sum(psi[(i, k)] @ G[(k, j)] for k in P[i])
+            for j in P[i]:
+                G[(j, i)] = G[(i, j)].T
+            G[(i, i)] = inv(A[(i, i)]) + sum(psi[(i, j)] @ G[(j, i)] for j in P[i])
+    # step 1: N = Sigma^< (G^(0))+ on the blocks (i, k), k in {i} and P_i
+    S = lambda i: sig[sl[i], sl[i]]
+    N = {}
+    for i in range(len(sl)):
+        for k in [i] + list(P[i]):
+            N[(i, k)] = S(i) @ G[(k, i)].conj().T
+    # step 2: N_jk += Psi_ij^T N_ik for j, k in P_i
+    for l in range(1, nl):
+        for i in on(l):
+            for j in P[i]:
+                for k in P[i]:
+                    N[(j, k)] = N.get((j, k), 0) + psi[(i, j)].T @ N[(i, k)]
+    # step 3: P = D^{-1} N on the same blocks
+    Pl = {(i, k): inv(A[(i, i)]) @ N[(i, k)] for (i, k) in N
+          if k == i or k in P[i]}
+    # step 4: extraction
+    for l in range(nl - 1, 0, -1):
+        for i in on(l):
+            for j in P[i]:
+                Pl[(i, j)] = Pl[(i, j)] + sum(psi[(i, k)] @ Pl[(k, j)] for k in P[i])
+            for j in P[i]:
+                Pl[(j, i)] = -Pl[(i, j)].conj().T
+            Pl[(i, i)] = Pl[(i, i)] + sum(psi[(i, j)] @ Pl[(j, i)] for j in P[i])
+    return G, Pl
+
+
+@pytest.mark.parametrize("sigma_on", ["ends", "all"])
+def test_multilevel_needs_all_ancestors_for_gless(sigma_on):
+    a, sig, sl, parent, level = _chain7()
+    if sigma_on == "ends":
+        for i in range(1, 6):  # Sigma^< on the two end clusters only (contacts)
+            sig[sl[i], sl[i]] = 0
+    g = np.linalg.inv(a)
+    gl = g @ sig @ g.conj().T
+    anc = [_ancestors(parent, i) for i in range(7)]
+    G, Pl = _multilevel(a, sig, sl, parent, level, anc)
+    for i in range(7):
+        assert _close(G[(i, i)], g[sl[i], sl[i]])
+        assert _close(Pl[(i, i)], gl[sl[i], sl[i]])
+    # the coupled ancestors only: cluster 1 (index 0) loses ancestor 4 (3),
+    # cluster 7 (index 6) likewise; G^r is unchanged, G^< is not
+    coupled = [a_ for a_ in anc]
+    coupled[0] = [1]
+    coupled[6] = [5]
+    G2, Pl2 = _multilevel(a, sig, sl, parent, level, coupled)
+    for i in range(7):
+        assert _close(G2[(i, i)], g[sl[i], sl[i]])
+    assert not all(_close(Pl2[(i, i)], gl[sl[i], sl[i]]) for i in range(7))
