@@ -85,6 +85,8 @@ typedef struct {
   double ops_total;
   double ops_rgf_equiv;   /* RGF count for a layered device of the same size (0 if unknown) */
   int64_t workspace_bytes_per_energy; /* device workspace a plan needs per energy in flight */
+  int64_t scatter_bytes_per_energy;   /* extra workspace per energy once phonon scattering is
+                                         enabled (0 before): the all-ancestor row blocks    */
 } ndg_info;
 
 /* ---------------------------------------------------------------------------
@@ -183,6 +185,43 @@ ndg_status ndg_solve(ndg_plan* plan, int32_t nE, const double* E, double eta, co
                      const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
                      ndg_c128* diag_gr, ndg_c128* diag_gless, ndg_c128* diag_ggreater,
                      double* growth, ndg_precision prec, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Solve with diagonal phonon self-energies (scattering).
+ *
+ * Equation defineA includes a phonon self-energy, which Section 1 takes
+ * diagonal: A = zI - H - diag(V) - Sigma^r_L - Sigma^r_R - diag(Sigma^r_ph),
+ * and Sigma^< = Sigma^<_L + Sigma^<_R + diag(Sigma^<_ph).  With Sigma^< on
+ * every cluster, the G^< source is formed by the four steps of Section 3.2
+ * "Computation of blocks for G^<" with P_i = all ancestors of cluster i:
+ * the rows of G^(0) over every (cluster, ancestor) pair, N = Sigma^<
+ * (G^(0))+, the fold of N, and D^{-1} N (the paper's most time-consuming
+ * step); the contacts' part of the source comes from their chains as in
+ * ndg_solve.  G^r, its extraction and the G^< extraction are those of
+ * ndg_solve.
+ *
+ * ndg_plan_enable_scattering allocates, once per plan, max_batch times
+ * ndg_info.scatter_bytes_per_energy of device memory (the all-ancestor
+ * rows: sum over clusters of s_i (s_i + ancestor points)) and the launch
+ * tables.  Errors: NDG_ENOMEM, NDG_EINVAL (a tree deeper than 63 levels).
+ *
+ * ndg_solve_scattering: the arguments of ndg_solve, FP64 only, plus
+ *   sig_r_ph[nE][n]     device, Sigma^r_ph per energy and site (caller's
+ *                       site order), or NULL for none
+ *   sig_less_ph[nE][n]  device, Sigma^<_ph (anti-Hermitian: purely imaginary
+ *                       for a physical model, any complex value accepted),
+ *                       or NULL for none.  Non-NULL needs
+ *                       ndg_plan_enable_scattering first.
+ * With both NULL it equals ndg_solve in FP64.  Runs on `stream` alone (no
+ * side streams).  Errors: as ndg_solve; NDG_EINVAL if sig_less_ph is given
+ * and scattering was not enabled.
+ */
+ndg_status ndg_plan_enable_scattering(ndg_plan* plan);
+ndg_status ndg_solve_scattering(ndg_plan* plan, int32_t nE, const double* E, double eta,
+                                const double* V, const ndg_c128* const* sig_r,
+                                const ndg_c128* const* sig_less, const ndg_c128* sig_r_ph,
+                                const ndg_c128* sig_less_ph, ndg_c128* diag_gr, ndg_c128* diag_gless,
+                                ndg_c128* diag_ggreater, double* growth, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Electron density and its gradient with respect to the on-site potential.

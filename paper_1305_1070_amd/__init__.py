@@ -23,6 +23,7 @@ __all__ = ["analyze", "Symbolic", "Plan", "load", "NdgError", "NDG_FP64", "NDG_M
            "ndg_plan_export_block", "ndg_plan_set_profiling", "ndg_plan_profile",
            "ndg_density", "ndg_plan_enable_adjoint", "ndg_density_vjp", "NDDensity",
            "ndg_batch_create", "ndg_batch_destroy", "ndg_batch_solve", "Batch",
+           "ndg_plan_enable_scattering", "ndg_solve_scattering",
            "ndg_status_string", "ndg_last_error"]
 
 
@@ -98,6 +99,19 @@ def ndg_solve(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, dgr_ptr, d
     sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
     _lib.check(load().ndg_solve(plan, ne, e_ptr, eta, v_ptr, sr, sl, dgr_ptr, dgl_ptr, dgg_ptr,
                                 growth_ptr, prec, stream_ptr))
+
+
+def ndg_plan_enable_scattering(plan):
+    _lib.check(load().ndg_plan_enable_scattering(plan))
+
+
+def ndg_solve_scattering(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, sr_ph_ptr,
+                         sl_ph_ptr, dgr_ptr, dgl_ptr, dgg_ptr, growth_ptr, stream_ptr):
+    nc = len(sig_r_ptrs)
+    sr = (C.c_void_p * max(1, nc))(*sig_r_ptrs)
+    sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
+    _lib.check(load().ndg_solve_scattering(plan, ne, e_ptr, eta, v_ptr, sr, sl, sr_ph_ptr, sl_ph_ptr,
+                                           dgr_ptr, dgl_ptr, dgg_ptr, growth_ptr, stream_ptr))
 
 
 def ndg_density(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, ce_ptr, dens_ptr, prec,
@@ -302,6 +316,36 @@ class Plan:
 
     def enable_adjoint(self):
         ndg_plan_enable_adjoint(self.handle)
+
+    def enable_scattering(self):
+        ndg_plan_enable_scattering(self.handle)
+        self._info = ndg_plan_info(self.handle)
+
+    def solve_scattering(self, E, eta, sig_r, sig_less, sig_r_ph=None, sig_less_ph=None, V=None,
+                         out=None, stream=None, growth=None):
+        """solve() in FP64 with diagonal phonon self-energies sig_r_ph,
+        sig_less_ph: complex128 [nE, n] tensors on the plan's GPU (caller's
+        site order) or None.  sig_less_ph needs enable_scattering() first."""
+        import torch
+        n, ne, dev = self._check_inputs(E, sig_r, sig_less, V)
+        for t in (sig_r_ph, sig_less_ph):
+            if t is not None and (t.dtype != torch.complex128 or tuple(t.shape) != (ne, n)
+                                  or t.device != dev or not t.is_contiguous()):
+                raise ValueError("phonon self-energies must be contiguous complex128 [nE, n] "
+                                 "tensors on the plan's device")
+        if out is None:
+            out = tuple(torch.empty((ne, n), dtype=torch.complex128, device=dev) for _ in range(3))
+        gr, gl, gg = out
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        ndg_solve_scattering(self.handle, ne, E.data_ptr(), float(eta),
+                             V.data_ptr() if V is not None else None,
+                             [t.data_ptr() for t in sig_r], [t.data_ptr() for t in sig_less],
+                             sig_r_ph.data_ptr() if sig_r_ph is not None else None,
+                             sig_less_ph.data_ptr() if sig_less_ph is not None else None,
+                             gr.data_ptr(), gl.data_ptr(), gg.data_ptr() if gg is not None else None,
+                             growth.data_ptr() if growth is not None else None,
+                             C.c_void_p(st.cuda_stream))
+        return gr, gl, gg
 
     def density_vjp(self, E, eta, sig_r, sig_less, cE, nbar, V=None, out=None, prec=NDG_FP64,
                     stream=None):

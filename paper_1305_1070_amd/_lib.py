@@ -38,7 +38,8 @@ class Info(C.Structure):
                 ("ops_gr_diag", C.c_double), ("ops_gl_chain", C.c_double),
                 ("ops_gl_off", C.c_double), ("ops_gl_diag", C.c_double),
                 ("ops_total", C.c_double), ("ops_rgf_equiv", C.c_double),
-                ("workspace_bytes_per_energy", C.c_int64)]
+                ("workspace_bytes_per_energy", C.c_int64),
+                ("scatter_bytes_per_energy", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -83,6 +84,9 @@ SIGNATURES = {
     "ndg_plan_enable_adjoint": (C.c_int, [P]),
     "ndg_density_vjp": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P), P,
                                   P, P, C.c_int, P]),
+    "ndg_plan_enable_scattering": (C.c_int, [P]),
+    "ndg_solve_scattering": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P),
+                                       P, P, P, P, P, P, P]),
     "ndg_plan_set_profiling": (C.c_int, [P, C.c_int32]),
     "ndg_plan_profile": (C.c_int, [P, C.c_int32, C.POINTER(KernelStat), C.POINTER(C.c_int32)]),
     "ndg_batch_create": (C.c_int, [C.c_int32, C.POINTER(P), C.POINTER(P)]),

@@ -147,6 +147,28 @@ ndg_status ndg_solve(ndg_plan* plan, int32_t nE, const double* E, double eta, co
                                      diag_ggreater, growth, (int)prec, stream);
 }
 
+ndg_status ndg_plan_enable_scattering(ndg_plan* plan) {
+  if (!plan) { set_error("ndg_plan_enable_scattering: NULL plan"); return NDG_EINVAL; }
+  return (ndg_status)ndg::plan_enable_scattering(plan);
+}
+
+ndg_status ndg_solve_scattering(ndg_plan* plan, int32_t nE, const double* E, double eta,
+                                const double* V, const ndg_c128* const* sig_r,
+                                const ndg_c128* const* sig_less, const ndg_c128* sig_r_ph,
+                                const ndg_c128* sig_less_ph, ndg_c128* diag_gr, ndg_c128* diag_gless,
+                                ndg_c128* diag_ggreater, double* growth, void* stream) {
+  if (!plan) { set_error("ndg_solve_scattering: NULL plan"); return NDG_EINVAL; }
+  if (nE < 0 || !(eta >= 0)) { set_error("ndg_solve_scattering: nE < 0 or eta < 0"); return NDG_EINVAL; }
+  if (nE == 0) return NDG_OK;
+  if (!E || !diag_gr || !diag_gless) {
+    set_error("ndg_solve_scattering: NULL energy or output pointer");
+    return NDG_EINVAL;
+  }
+  return (ndg_status)ndg::plan_run(plan, ndg::kRunSolve, nE, E, eta, V, sig_r, sig_less, diag_gr,
+                                   diag_gless, diag_ggreater, growth, nullptr, nullptr, nullptr, nullptr,
+                                   (int)NDG_FP64, stream, nullptr, sig_r_ph, sig_less_ph);
+}
+
 static ndg_status check_common(const char* who, ndg_plan* plan, int32_t nE, const double* E, double eta,
                                ndg_precision prec) {
   if (!plan) { set_error(std::string(who) + ": NULL plan"); return NDG_EINVAL; }

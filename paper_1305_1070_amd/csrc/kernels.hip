@@ -41,8 +41,14 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
     const int i = q / f, j = q - i * f;
     double re = hf[q], im = 0.0;
     if (j == i) {
-      re += ez - (c.V ? c.V[c.perm[d.pt_off + i]] : 0.0);
+      const int site = c.perm[d.pt_off + i];
+      re += ez - (c.V ? c.V[site] : 0.0);
       im = c.eta;
+      if (c.sig_r_ph) {
+        const double2 sp = c.sig_r_ph[(int64_t)(eb + e) * c.n + site];
+        re -= sp.x;
+        im -= sp.y;
+      }
     }
     if (smp) {
       const int code = smp[q];
@@ -465,7 +471,7 @@ __device__ __forceinline__ void down_off_body(const Ctx& c, const ColItem* items
   double2* X = S + (lesser ? d.o_fp : d.o_fg);
   const int s = d.s, b = d.b, f = d.f, j0 = it.tc * 64;
   const int nj = min(64, b - j0);
-  const bool has_src = lesser && d.chain_mask;
+  const bool has_src = lesser && (d.chain_mask || c.scat);
   const bool ls = lesser != 0;
   typename GM::Tile acc;
   GM::zero(acc);
@@ -512,7 +518,7 @@ __device__ __forceinline__ void down_diag_body(const Ctx& c, const int32_t* cls,
   const double2* Ainv = S + d.o_ainv;
   double2* X = S + (lesser ? d.o_fp : d.o_fg);
   const int s = d.s, b = d.b, f = d.f;
-  const bool has_src = lesser && d.chain_mask;
+  const bool has_src = lesser && (d.chain_mask || c.scat);
   typename GM::Tile acc;
   GM::zero(acc);
   if (lesser) {

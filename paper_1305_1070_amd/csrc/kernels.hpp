@@ -87,6 +87,13 @@ struct Ctx {
   const double* V;           // may be null
   const double2* sig_r[2];
   const double2* sig_l[2];
+  // diagonal phonon self-energies, [nE][n] in the caller's site order, or
+  // null: Sigma^r_ph enters A's diagonal; with scat set, every cluster's
+  // G^< source comes from the all-ancestor N fold (Sigma^<_ph) and the
+  // contact chains
+  const double2* sig_r_ph;
+  const double2* sig_l_ph;
+  int32_t scat;
   int32_t* status;           // [code, energy, cluster]
   double* growth;            // [nE] or null: max over clusters of ||A_ii^{-1}|| ||A_iB||
   int32_t mixed;             // 1: Schur updates and extraction products on FP32 matrix cores
@@ -110,6 +117,48 @@ struct RhsCtx {
   const double* nbar;    // cotangent of the density (caller order)
   double* part;          // [nb][n] per-energy partial gradients
 };
+
+// All-ancestor rows for a Sigma^< on every cluster (diagonal phonon
+// self-energy).  Cluster i's frame lists its own points, then those of its
+// ancestors, parent first (ascending internal positions); its width is
+// g_i = s_i + W_i with W_i the number of ancestor points.  The ancestors'
+// frames are tails of this one: ancestor a's frame starts at column
+// ao_i[a] of i's.
+struct ScatDesc {
+  int64_t o_g;     // s x g block of the scattering slab: the rows [G_ii, G_{i,Anc}]
+                   // of the paper's G^(0), overwritten in place by N_i
+  int32_t g;       // frame width s + W
+  int32_t D;       // number of ancestors
+  int32_t tab;     // into ScatCtx::atab: D + 1 cluster ids (the cluster, its
+                   // ancestors parent first), then the D + 2 frame offsets ao
+  int32_t lk0, lk1;  // descendants whose B meets this cluster: ScatCtx::lk[lk0 .. lk1)
+  int32_t pad;
+};
+// descendant d whose B contains points of the cluster: umap[map .. map + s)
+// gives, per point of the cluster, its index in B_d (or -1); col is the
+// column of the cluster's frame inside d's frame
+struct LkItem { int32_t d, map, col, pad; };
+// per entry of B_i (indexed like relmap): its column in i's frame and the
+// index in i's chain of the cluster that owns it
+struct BPos { int32_t col, a; };
+
+struct ScatCtx {
+  const ScatDesc* sd;
+  const int32_t* atab;
+  const BPos* bpos;
+  const LkItem* lk;
+  const int32_t* umap;
+  double2* ws;       // [nb][stride]
+  int64_t stride;
+};
+constexpr int kMaxAncestors = 63;
+// tile_rows 16, 32 or 64 (at least the largest cluster of the launch)
+void launch_anc_g(const Ctx& c, const ScatCtx& x, const ColItem* it, int nit, int nb, int tile_rows,
+                  hipStream_t st);
+void launch_anc_n(const Ctx& c, const ScatCtx& x, const ColItem* it, int nit, int nb, int tile_rows,
+                  hipStream_t st);
+void launch_anc_p0(const Ctx& c, const ScatCtx& x, const int32_t* cls, int ncl, int nb, int tile_rows,
+                   hipStream_t st);
 
 // Launchers (kernels.hip).  nb = energies in the batch.
 void launch_assemble(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st);

@@ -1,0 +1,223 @@
+// G^< source for a Sigma^< on every cluster (diagonal phonon self-energy),
+// Section 3.2 "Computation of blocks for G^<", steps 1-3, with P_i the set of
+// ALL ancestors of cluster i as the paper defines it.
+//
+// Without phonons Sigma^< sits on the contacts and the source is formed on
+// the contacts' ancestor chains only.  With a diagonal Sigma^<_ph every row
+// of N = Sigma^< (G^(0))+ is nonzero, and the fold of N carries each
+// cluster's row block across all of its ancestors' points, not only the
+// coupled ones B_i (a cluster's source reaches an ancestor it is not coupled
+// to through the ancestors in between).  Three passes, each over one height
+// per launch:
+//   k_anc_g   top-down:  G_{i,Anc} = Psi_i G_{B_i,Anc}   (the paper's G^(0)
+//             over every (cluster, ancestor) pair; G_{B,Anc} is read from
+//             the ancestors' rows of this pass, directly or transposed,
+//             G^r being complex symmetric), G_ii copied from the G^r
+//             extraction;
+//   k_anc_n   bottom-up: N_i = Sigma^<_ph,i conj(G_{i,frame})
+//             + sum over descendants d with B_d meeting i of
+//               Psi_{d,i}^T N_{d, frame of i}
+//             (the fold N_jk += Psi_ij^T N_ik, gathered by the receiving
+//             cluster: no contribution blocks are stored, no atomics);
+//   k_anc_p0  P_init = A_ii^{-1} N_{i, [i, B_i]}, written into the G^< front
+//             (added to the contact chains' part where the cluster lies on
+//             one, since the source is linear in Sigma^<).
+// The extraction of G^< then runs unchanged with a source on every cluster.
+#include "device_common.hpp"
+
+namespace ndg {
+
+namespace {
+
+// Frame tables of one cluster in LDS: per chain index a (0 = the cluster),
+// the owner's row block offset and row length, and the frame offsets ao.
+struct FrameLds {
+  int64_t og[kMaxAncestors + 1];
+  int32_t gg[kMaxAncestors + 1];
+  int32_t ao[kMaxAncestors + 2];
+};
+
+__device__ inline void load_frame(const ScatCtx& x, const ScatDesc& sd, FrameLds& fr) {
+  const int32_t* tab = x.atab + sd.tab;
+  for (int q = threadIdx.x; q <= sd.D; q += blockDim.x) {
+    const ScatDesc a = x.sd[tab[q]];
+    fr.og[q] = a.o_g;
+    fr.gg[q] = a.g;
+  }
+  for (int q = threadIdx.x; q < sd.D + 2; q += blockDim.x) fr.ao[q] = tab[sd.D + 1 + q];
+}
+
+}  // namespace
+
+// G_{i, Anc_i} = Psi_i G_{B_i, Anc_i}, one 64-column tile of the frame per
+// block; the tile's columns inside the cluster's own points take G_ii from
+// the G^r extraction.  Entry (x, y) of G_{B,Anc}, x in the frame's cluster
+// a_x and y in a_y: the rows of the lower of the two (G(x, y) in a_x's rows
+// when a_y >= a_x, else G(y, x) in a_y's rows).
+template <int TM>
+__global__ void __launch_bounds__(256) k_anc_g(Ctx c, ScatCtx x, const ColItem* items) {
+  __shared__ GemmSmemR<TM> sm;
+  __shared__ FrameLds fr;
+  __shared__ int32_t col_a[64];
+  const ColItem it = items[blockIdx.x];
+  const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
+  const ClusterDesc d = c.cl[it.cl];
+  const ScatDesc sd = x.sd[it.cl];
+  double2* S = slab(c, e);
+  double2* X = x.ws + (int64_t)e * x.stride;
+  const int s = d.s, b = d.b, f = d.f, g = sd.g, D = sd.D;
+  const int j0 = it.tc * 64, nj = min(64, g - j0);
+  load_frame(x, sd, fr);
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int y = j0 + threadIdx.x;
+    int a = 0;
+    while (a < D && fr.ao[a + 1] <= y) ++a;
+    col_a[threadIdx.x] = a;
+  }
+  __syncthreads();
+  const double2* Psi = S + d.o_psi;
+  const double2* Gf = S + d.o_fg;
+  const BPos* bp = x.bpos + d.bptr;
+  double2* Gi = X + sd.o_g;
+  ZTile acc;
+  ztile_zero(acc);
+  if (j0 + nj > s)
+    zgemm_acc_t<TM, false, false, true, TM>(
+        b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
+        [&](int k, int j) {
+          const int y = j0 + j;
+          if (j >= nj || y < s) return cz();
+          const BPos u = bp[k];
+          const int ay = col_a[j];
+          int64_t addr;
+          if (ay >= u.a) addr = fr.og[u.a] + (int64_t)(u.col - fr.ao[u.a]) * fr.gg[u.a] + (y - fr.ao[u.a]);
+          else addr = fr.og[ay] + (int64_t)(y - fr.ao[ay]) * fr.gg[ay] + (u.col - fr.ao[ay]);
+          return X[addr];
+        },
+        acc, sm);
+  ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
+    const int y = j0 + j;
+    if (i < s && j < nj) Gi[(int64_t)i * g + y] = y < s ? Gf[(int64_t)i * f + y] : make_double2(re, im);
+  });
+}
+
+// N_i over one 64-column tile of the frame.  The own term Sigma^<_ph conj(G)
+// reads the G^(0) entry that N_i replaces (same element, same thread).
+template <int TM>
+__global__ void __launch_bounds__(256) k_anc_n(Ctx c, ScatCtx x, const ColItem* items) {
+  __shared__ GemmSmemR<TM> sm;
+  const ColItem it = items[blockIdx.x];
+  const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
+  const ClusterDesc d = c.cl[it.cl];
+  const ScatDesc sd = x.sd[it.cl];
+  const double2* S = slab(c, e);
+  double2* X = x.ws + (int64_t)e * x.stride;
+  const int s = d.s, g = sd.g;
+  const int j0 = it.tc * 64, nj = min(64, g - j0);
+  ZTile acc;
+  ztile_zero(acc);
+  for (int q = sd.lk0; q < sd.lk1; ++q) {
+    const LkItem L = x.lk[q];
+    const ClusterDesc dd = c.cl[L.d];
+    const ScatDesc sdd = x.sd[L.d];
+    const double2* Psd = S + dd.o_psi;
+    const double2* Nd = X + sdd.o_g;
+    const int bd = dd.b, gd = sdd.g, coff = L.col + j0;
+    const int32_t* um = x.umap + L.map;
+    // A(i, k) = Psi_d[k][u(i)]: row k of d, the B_d column of point i
+    zgemm_acc_t<TM, true, false, true, TM>(
+        dd.s,
+        [&](int i, int k) {
+          const int u = i < s ? um[i] : -1;
+          return u >= 0 ? Psd[(int64_t)k * bd + u] : cz();
+        },
+        [&](int k, int j) { return j < nj ? Nd[(int64_t)k * gd + coff + j] : cz(); }, acc, sm);
+  }
+  const double2* sl = c.sig_l_ph + (int64_t)(eb + e) * c.n;
+  double2* Ni = X + sd.o_g;
+  ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
+    if (i < s && j < nj) {
+      const int64_t pos = (int64_t)i * g + j0 + j;
+      const double2 gv = Ni[pos];
+      const double2 sg = sl[c.perm[d.pt_off + i]];
+      re += sg.x * gv.x + sg.y * gv.y;   // sigma conj(G)
+      im += sg.y * gv.x - sg.x * gv.y;
+      Ni[pos] = make_double2(re, im);
+    }
+  });
+}
+
+// P_init = A_ii^{-1} N_{i,[i, B_i]} into the cluster's rows of the G^< front.
+template <int TM>
+__global__ void __launch_bounds__(256) k_anc_p0(Ctx c, ScatCtx x, const int32_t* cls) {
+  __shared__ GemmSmemR<TM> sm;
+  const int cl = cls[blockIdx.x];
+  const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
+  const ClusterDesc d = c.cl[cl];
+  const ScatDesc sd = x.sd[cl];
+  double2* S = slab(c, e);
+  const double2* Ni = x.ws + (int64_t)e * x.stride + sd.o_g;
+  const double2* Ainv = S + d.o_ainv;
+  double2* FP = S + d.o_fp;
+  const BPos* bp = x.bpos + d.bptr;
+  const int s = d.s, f = d.f, g = sd.g;
+  const bool add = d.chain_mask != 0;
+  for (int j0 = 0; j0 < f; j0 += 64) {
+    const int nj = min(64, f - j0);
+    ZTile acc;
+    ztile_zero(acc);
+    zgemm_acc_t<TM, false, false, true, TM>(
+        s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
+        [&](int k, int j) {
+          if (j >= nj) return cz();
+          const int cc = j0 + j;
+          const int col = cc < s ? cc : bp[cc - s].col;
+          return Ni[(int64_t)k * g + col];
+        },
+        acc, sm);
+    ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
+      if (i < s && j < nj) {
+        double2* p = FP + (int64_t)i * f + j0 + j;
+        if (add) {
+          const double2 v = *p;
+          re += v.x;
+          im += v.y;
+        }
+        *p = make_double2(re, im);
+      }
+    });
+  }
+}
+
+void launch_anc_g(const Ctx& c, const ScatCtx& x, const ColItem* it, int nit, int nb, int tile_rows,
+                  hipStream_t st) {
+  if (nit <= 0) return;
+  if (tile_rows <= 16) hipLaunchKernelGGL(k_anc_g<16>, dim3(nit, nb), dim3(256), 0, st, c, x, it);
+  else if (tile_rows <= 32) hipLaunchKernelGGL(k_anc_g<32>, dim3(nit, nb), dim3(256), 0, st, c, x, it);
+  else hipLaunchKernelGGL(k_anc_g<64>, dim3(nit, nb), dim3(256), 0, st, c, x, it);
+}
+
+void launch_anc_n(const Ctx& c, const ScatCtx& x, const ColItem* it, int nit, int nb, int tile_rows,
+                  hipStream_t st) {
+  if (nit <= 0) return;
+  if (tile_rows <= 16) hipLaunchKernelGGL(k_anc_n<16>, dim3(nit, nb), dim3(256), 0, st, c, x, it);
+  else if (tile_rows <= 32) hipLaunchKernelGGL(k_anc_n<32>, dim3(nit, nb), dim3(256), 0, st, c, x, it);
+  else hipLaunchKernelGGL(k_anc_n<64>, dim3(nit, nb), dim3(256), 0, st, c, x, it);
+}
+
+void launch_anc_p0(const Ctx& c, const ScatCtx& x, const int32_t* cls, int ncl, int nb, int tile_rows,
+                   hipStream_t st) {
+  if (ncl <= 0) return;
+  if (tile_rows <= 16) hipLaunchKernelGGL(k_anc_p0<16>, dim3(ncl, nb), dim3(256), 0, st, c, x, cls);
+  else if (tile_rows <= 32) hipLaunchKernelGGL(k_anc_p0<32>, dim3(ncl, nb), dim3(256), 0, st, c, x, cls);
+  else hipLaunchKernelGGL(k_anc_p0<64>, dim3(ncl, nb), dim3(256), 0, st, c, x, cls);
+}
+
+}  // namespace ndg

@@ -51,8 +51,14 @@ __device__ __forceinline__ void fold_small_body(const Ctx& c, const int32_t* cls
         if (i < s) re = hf[i * f + j];
         else if (j < s) re = hf[j * f + i];
         if (i == j && i < s) {
-          re += ez - (c.V ? c.V[c.perm[d.pt_off + i]] : 0.0);
+          const int site = c.perm[d.pt_off + i];
+          re += ez - (c.V ? c.V[site] : 0.0);
           im += c.eta;
+          if (c.sig_r_ph) {
+            const double2 sp = c.sig_r_ph[(int64_t)(eb + e) * c.n + site];
+            re -= sp.x;
+            im -= sp.y;
+          }
         }
       }
       g.re[m][q] = re;
@@ -195,8 +201,10 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
   const int f = d.f, s = d.s, b = d.b;
   const int lb = b | 1;           // odd row stride: lanes reading down a column hit distinct banks
   const int t = threadIdx.x;
-  const bool inner = c.kids_ptr[cl + 1] > c.kids_ptr[cl];
-  const bool chain = d.chain_mask != 0;
+  // with phonon sources every cluster's full rows [X_ii, X_{i,B}] are read
+  // (by the all-ancestor extraction) and every cluster has a G^< source
+  const bool inner = c.scat || c.kids_ptr[cl + 1] > c.kids_ptr[cl];
+  const bool chain = c.scat || d.chain_mask != 0;
   const double2* Ainv = S + d.o_ainv;
   double2* Psl = sm;              // s x b, stride lb
   double2* XBB = sm + s * lb;     // b x b

@@ -36,6 +36,7 @@ struct ndg_plan {
   std::vector<ndg::ClusterDesc> hdesc;
   std::vector<int32_t> hbidx;
   std::vector<int32_t> hdeg;   // children count (host)
+  std::vector<int32_t> hheight;
   // device arrays
   ndg::ClusterDesc* d_cl = nullptr;
   int32_t *d_relmap = nullptr, *d_kids_ptr = nullptr, *d_kids = nullptr;
@@ -76,6 +77,20 @@ struct ndg_plan {
   int64_t zstride = 0;
   int mmax = 0;
   int contact_cl[2] = {-1, -1};
+  // phonon G^< source (ndg_plan_enable_scattering): all-ancestor rows, per
+  // height and tile class (clusters s <= 16, <= 32, <= 64) the column tiles
+  // of the frames and the clusters
+  ndg::ScatDesc* d_sd = nullptr;
+  int32_t* d_atab = nullptr;
+  ndg::BPos* d_bpos = nullptr;
+  ndg::LkItem* d_lk = nullptr;
+  int32_t* d_umap = nullptr;
+  ndg::ColItem* d_ancitems = nullptr;
+  int32_t* d_anccls = nullptr;
+  double2* d_sws = nullptr;
+  int64_t sstride = 0;
+  struct AncGroup { int it0 = 0, nit = 0, cl0 = 0, ncl = 0; };
+  std::vector<AncGroup> anc_groups;  // [(H + 1) * 3]
   int last_batch = 0;
   // algorithmic cost per energy of each kernel class at each height
   std::vector<double> cost_flops, cost_bytes;  // [kKernels * (H + 1)]
@@ -99,13 +114,13 @@ namespace {
 enum KernelId {
   K_ASSEMBLE, K_FACTOR, K_PSI, K_UPDATE, K_CHAIN_FWD, K_DOWN_OFF_G, K_DOWN_DIAG_G, K_CHAIN_BACK,
   K_DOWN_OFF_P, K_DOWN_DIAG_P, K_EPILOGUE, K_FOLD_SMALL, K_EXTRACT_SMALL, K_RHS_FWD, K_RHS_BACK,
-  K_VJP, K_EXTRACT_SMALL_P, kKernels
+  K_VJP, K_EXTRACT_SMALL_P, K_ANC_G, K_ANC_N, K_ANC_P0, kKernels
 };
 const char* const kKernelNames[kKernels] = {
     "k_assemble", "k_factor", "k_psi", "k_update", "k_chain_fwd", "k_down_off(G)",
     "k_down_diag(G)", "k_chain_back", "k_down_off(P)", "k_down_diag(P)", "k_epilogue",
-    "k_fold_small", "k_extract_small(G)", "k_rhs_fwd", "k_rhs_back", "k_vjp_accum",
-    "k_extract_small(P)"};
+    "k_fold_small", "k_extract_small(G)", "k_rhs_fwd", "k_rhs_back", "k_vjp",
+    "k_extract_small(P)", "k_anc_g", "k_anc_n", "k_anc_p0"};
 
 int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
@@ -185,7 +200,9 @@ void free_plan(ndg_plan* p) {
                   p->d_chaincls,  p->d_ws,       p->d_status,     p->d_cinv,       p->d_rX,
                   p->d_rG,        p->d_rZ,       p->d_ovec,       p->d_bidx,       p->d_part,
                   p->d_srow,      p->d_scol,     p->d_scid,       p->d_sflat,      p->d_hfront,
-                  p->d_smap,      p->d_pinv,     p->d_gaddr,      p->d_sdiag};
+                  p->d_smap,      p->d_pinv,     p->d_gaddr,      p->d_sdiag,      p->d_sd,
+                  p->d_atab,      p->d_bpos,     p->d_lk,         p->d_umap,       p->d_ancitems,
+                  p->d_anccls,    p->d_sws};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& r : p->recs) {
@@ -235,6 +252,7 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   p->ops = oc;
   p->stride = layout(sy, p->hdesc);
   p->hbidx = sy.bidx;
+  p->hheight = sy.height;
   for (int c = 0; c < p->ncontacts && c < 2; ++c) p->contact_cl[c] = sy.contact_cluster[c];
   const int nc = sy.nclusters, H = sy.max_height;
   // schedules per height
@@ -596,6 +614,137 @@ int plan_enable_adjoint(ndg_plan* p) {
   return NDG_OK;
 }
 
+int plan_enable_scattering(ndg_plan* p) {
+  if (p->d_sws) return NDG_OK;
+  if (hipSetDevice(p->device) != hipSuccess) {
+    set_error("ndg_plan_enable_scattering: hipSetDevice failed");
+    return NDG_EHIP;
+  }
+  const int nc = p->nclusters, H = p->max_height;
+  const auto& hd = p->hdesc;
+  // frames: the cluster, then its ancestors parent first
+  std::vector<ScatDesc> sd(nc);
+  std::vector<int32_t> atab;
+  std::vector<std::vector<int32_t>> chain(nc), ao(nc);
+  int64_t off = 0;
+  for (int i = 0; i < nc; ++i) {
+    for (int k = i; k >= 0; k = hd[k].parent) chain[i].push_back(k);
+    const int D = (int)chain[i].size() - 1;
+    if (D > kMaxAncestors) {
+      set_error("ndg_plan_enable_scattering: tree deeper than 63 ancestors");
+      return NDG_EINVAL;
+    }
+    ao[i].assign(D + 2, 0);
+    for (int t = 0; t <= D; ++t) ao[i][t + 1] = ao[i][t] + hd[chain[i][t]].s;
+    sd[i] = ScatDesc{off, ao[i][D + 1], D, (int32_t)atab.size(), 0, 0, 0};
+    atab.insert(atab.end(), chain[i].begin(), chain[i].end());
+    atab.insert(atab.end(), ao[i].begin(), ao[i].end());
+    off += align8((int64_t)hd[i].s * sd[i].g);
+  }
+  std::vector<int32_t> owner(p->n);
+  for (int i = 0; i < nc; ++i)
+    for (int r = 0; r < hd[i].s; ++r) owner[hd[i].pt_off + r] = i;
+  // B entries in the frame; descendants feeding each cluster's N rows
+  std::vector<BPos> bpos(p->hbidx.size());
+  std::vector<std::vector<LkItem>> lkj(nc);
+  std::vector<int32_t> umap;
+  for (int i = 0; i < nc; ++i) {
+    const int b = hd[i].b;
+    for (int u = 0; u < b; ++u) {
+      const int xpt = p->hbidx[hd[i].bptr + u], o = owner[xpt];
+      int t = 1;
+      while (t < (int)chain[i].size() && chain[i][t] != o) ++t;
+      if (t >= (int)chain[i].size()) {
+        set_error("ndg_plan_enable_scattering: boundary point outside the ancestors");
+        return NDG_EINVAL;
+      }
+      bpos[hd[i].bptr + u] = BPos{ao[i][t] + xpt - hd[o].pt_off, t};
+    }
+    // B is ascending and every cluster's points are contiguous: one run per owner
+    for (int u0 = 0; u0 < b;) {
+      const int a = bpos[hd[i].bptr + u0].a, j = chain[i][a];
+      int u1 = u0;
+      const int moff = (int)umap.size();
+      umap.resize(moff + hd[j].s, -1);
+      while (u1 < b && bpos[hd[i].bptr + u1].a == a) {
+        umap[moff + p->hbidx[hd[i].bptr + u1] - hd[j].pt_off] = u1;
+        ++u1;
+      }
+      lkj[j].push_back(LkItem{i, moff, ao[i][a], 0});
+      u0 = u1;
+    }
+  }
+  std::vector<LkItem> lk;
+  for (int j = 0; j < nc; ++j) {
+    sd[j].lk0 = (int32_t)lk.size();
+    lk.insert(lk.end(), lkj[j].begin(), lkj[j].end());
+    sd[j].lk1 = (int32_t)lk.size();
+  }
+  // launch lists per height and tile class; the algorithmic work per energy
+  std::vector<ColItem> items;
+  std::vector<int32_t> cls;
+  p->anc_groups.assign((H + 1) * 3, ndg_plan::AncGroup{});
+  for (int h = 1; h <= H; ++h)
+    for (int q = 0; q < 3; ++q) {
+      ndg_plan::AncGroup& g = p->anc_groups[h * 3 + q];
+      g.it0 = (int)items.size();
+      g.cl0 = (int)cls.size();
+      for (int i = 0; i < nc; ++i) {
+        const int si = hd[i].s, qi = si <= 16 ? 0 : si <= 32 ? 1 : 2;
+        if (p->hheight[i] != h || qi != q) continue;
+        cls.push_back(i);
+        for (int tc = 0; tc * 64 < sd[i].g; ++tc) items.push_back(ColItem{i, tc});
+      }
+      g.nit = (int)items.size() - g.it0;
+      g.ncl = (int)cls.size() - g.cl0;
+    }
+  for (int i = 0; i < nc; ++i) {
+    const int h = p->hheight[i];
+    const double s = hd[i].s, b = hd[i].b, f = hd[i].f, g = sd[i].g, W = g - s;
+    p->cost_flops[K_ANC_G * (H + 1) + h] += 8.0 * s * b * W;
+    p->cost_bytes[K_ANC_G * (H + 1) + h] += 16.0 * (s * b + b * W + s * g);
+    double nf = 0, nby = 32.0 * s * g;
+    for (const LkItem& L : lkj[i]) {
+      nf += 8.0 * s * hd[L.d].s * g;
+      nby += 16.0 * hd[L.d].s * g;
+    }
+    p->cost_flops[K_ANC_N * (H + 1) + h] += nf;
+    p->cost_bytes[K_ANC_N * (H + 1) + h] += nby + 16.0 * b * s;
+    p->cost_flops[K_ANC_P0 * (H + 1) + h] += 8.0 * s * s * f;
+    p->cost_bytes[K_ANC_P0 * (H + 1) + h] += 16.0 * (s * s + 2.0 * s * f);
+  }
+  p->sstride = off;
+  int rc = 0;
+  if (hipMalloc((void**)&p->d_sws, (size_t)p->max_batch * (size_t)off * 16) != hipSuccess) rc = NDG_ENOMEM;
+  if (!rc) rc = upload(&p->d_sd, sd.data(), sd.size());
+  if (!rc) rc = upload(&p->d_atab, atab.data(), atab.size());
+  if (!rc && !bpos.empty()) rc = upload(&p->d_bpos, bpos.data(), bpos.size());
+  if (!rc && !lk.empty()) rc = upload(&p->d_lk, lk.data(), lk.size());
+  if (!rc && !umap.empty()) rc = upload(&p->d_umap, umap.data(), umap.size());
+  if (!rc) rc = upload(&p->d_ancitems, items.data(), items.size());
+  if (!rc) rc = upload(&p->d_anccls, cls.data(), cls.size());
+  if (rc) {
+    (void)hipGetLastError();
+    void* ptrs[] = {p->d_sws, p->d_sd, p->d_atab, p->d_bpos, p->d_lk, p->d_umap, p->d_ancitems, p->d_anccls};
+    for (void* q : ptrs)
+      if (q) (void)hipFree(q);
+    p->d_sws = nullptr;
+    p->d_sd = nullptr;
+    p->d_atab = nullptr;
+    p->d_bpos = nullptr;
+    p->d_lk = nullptr;
+    p->d_umap = nullptr;
+    p->d_ancitems = nullptr;
+    p->d_anccls = nullptr;
+    for (int k = K_ANC_G; k <= K_ANC_P0; ++k)
+      for (int h = 0; h <= H; ++h) p->cost_flops[k * (H + 1) + h] = p->cost_bytes[k * (H + 1) + h] = 0;
+    set_error("ndg_plan_enable_scattering: device allocation failed");
+    return rc == NDG_ENOMEM ? NDG_ENOMEM : rc;
+  }
+  p->info.scatter_bytes_per_energy = off * 16;
+  return NDG_OK;
+}
+
 int plan_solve(ndg_plan* p, int nE, const double* E, double eta, const double* V,
                const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
                ndg_c128* dgl, ndg_c128* dgg, double* growth, int prec, void* stream) {
@@ -616,7 +765,17 @@ int plan_max_batch(const ndg_plan* p) { return p->max_batch; }
 int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const double* V,
              const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
              ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
-             const double* nbar, double* vbar, int prec, void* stream, const int32_t* e0p) {
+             const double* nbar, double* vbar, int prec, void* stream, const int32_t* e0p,
+             const ndg_c128* sig_r_ph, const ndg_c128* sig_less_ph) {
+  const bool scat = sig_less_ph != nullptr;
+  if ((scat || sig_r_ph) && (mode != kRunSolve || e0p || prec != NDG_FP64)) {
+    set_error("internal: phonon self-energies are for FP64 solves only");
+    return NDG_EINVAL;
+  }
+  if (scat && !p->d_sws) {
+    set_error("ndg_solve_scattering: call ndg_plan_enable_scattering first");
+    return NDG_EINVAL;
+  }
   if (e0p && mode != kRunSolve) {
     set_error("internal: device-resident energy offsets are for solves only");
     return NDG_EINVAL;
@@ -674,6 +833,10 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   c.status = p->d_status;
   c.growth = growth;
   c.mixed = prec == NDG_MIXED ? 1 : 0;
+  c.sig_r_ph = reinterpret_cast<const double2*>(sig_r_ph);
+  c.sig_l_ph = reinterpret_cast<const double2*>(sig_less_ph);
+  c.scat = scat ? 1 : 0;
+  ScatCtx x{p->d_sd, p->d_atab, p->d_bpos, p->d_lk, p->d_umap, p->d_sws, p->sstride};
   // a kernel, so graph capture stays valid; a chunk leaves it to the caller
   if (growth && !e0p) launch_fill_zero(growth, nE, st);
   if (mode == kRunDensity) launch_zero(density, p->n, st);
@@ -764,6 +927,58 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
           timed(K_VJP, 0, nb, [&] { launch_vjp_accum(c, r, cc, off, nb, st); });
       }
       launch_vjp_reduce(c, r, nb, cE, vbar, st);
+      p->last_batch = nb;
+      continue;
+    }
+    // extraction of one height, G^r (lesser = false) or G^< (true)
+    auto extract = [&](int h, bool lesser, hipStream_t on) {
+      for (int q = 0; q < ndg_plan::kClasses; ++q) {
+        const ndg_plan::Group& g = p->groups[h * ndg_plan::kClasses + q];
+        if (!g.ncl) continue;
+        const int32_t* cl = p->d_levels + g.cl0;
+        if (q <= 2) {
+          timed_on(on, lesser ? K_EXTRACT_SMALL_P : K_EXTRACT_SMALL, h, nb,
+                   [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, lesser, on); });
+          continue;
+        }
+        const ColItem* ci = p->d_colitems + g.col0;
+        if (g.ncol)
+          timed_on(on, lesser ? K_DOWN_OFF_P : K_DOWN_OFF_G, h, nb,
+                   [&] { launch_down_off(c, ci, g.ncol, nb, lesser, g.size, on); });
+        timed_on(on, lesser ? K_DOWN_DIAG_P : K_DOWN_DIAG_G, h, nb,
+                 [&] { launch_down_diag(c, cl, g.ncl, nb, lesser, g.size, on); });
+      }
+    };
+    if (scat) {
+      // phonon sources on every cluster, all on the caller's stream: G^r
+      // extraction, the contact chains' part of the source, the rows of
+      // G^(0) over all ancestors (top-down), the N fold and P_init
+      // (bottom-up), then the G^< extraction
+      for (int h = H; h >= 1; --h) extract(h, false, st);
+      for (int h = H; h >= 1; --h) {
+        const int k0 = p->chaincl_ptr[h - 1], nck = p->chaincl_ptr[h] - k0;
+        if (nck) timed(K_CHAIN_BACK, h, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, st); });
+      }
+      static const int kTile[3] = {16, 32, 64};
+      for (int h = H; h >= 1; --h)
+        for (int q = 0; q < 3; ++q) {
+          const ndg_plan::AncGroup& g = p->anc_groups[h * 3 + q];
+          if (g.nit)
+            timed(K_ANC_G, h, nb, [&] { launch_anc_g(c, x, p->d_ancitems + g.it0, g.nit, nb, kTile[q], st); });
+        }
+      for (int h = 1; h <= H; ++h)
+        for (int q = 0; q < 3; ++q) {
+          const ndg_plan::AncGroup& g = p->anc_groups[h * 3 + q];
+          if (g.nit)
+            timed(K_ANC_N, h, nb, [&] { launch_anc_n(c, x, p->d_ancitems + g.it0, g.nit, nb, kTile[q], st); });
+          if (g.ncl)
+            timed(K_ANC_P0, h, nb, [&] { launch_anc_p0(c, x, p->d_anccls + g.cl0, g.ncl, nb, kTile[q], st); });
+        }
+      for (int h = H; h >= 1; --h) extract(h, true, st);
+      timed(K_EPILOGUE, 0, nb, [&] {
+        launch_epilogue(c, nb, reinterpret_cast<double2*>(dgr), reinterpret_cast<double2*>(dgl),
+                        reinterpret_cast<double2*>(dgg), st);
+      });
       p->last_batch = nb;
       continue;
     }

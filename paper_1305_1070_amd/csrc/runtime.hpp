@@ -28,7 +28,8 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
              const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
              ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
              const double* nbar, double* vbar, int prec, void* stream,
-             const int32_t* e0p = nullptr);
+             const int32_t* e0p = nullptr, const ndg_c128* sig_r_ph = nullptr,
+             const ndg_c128* sig_less_ph = nullptr);
 // One batch of energies starting at the device-resident index *e0p (for a
 // graph replayed over the energy range): the launches of a single batch of
 // max_batch energies, slots at or beyond nE skipped; growth is not cleared.
@@ -38,6 +39,7 @@ int plan_solve_chunk(ndg_plan* plan, int nE, const double* E, double eta, const 
                      void* stream, const int32_t* e0p);
 int plan_max_batch(const ndg_plan* plan);
 int plan_enable_adjoint(ndg_plan* plan);
+int plan_enable_scattering(ndg_plan* plan);
 int plan_ncontacts(const ndg_plan* plan);
 int plan_device(const ndg_plan* plan);
 bool plan_profiling(const ndg_plan* plan);

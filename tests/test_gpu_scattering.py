@@ -1,0 +1,168 @@
+"""Parity of the phonon-scattering solve (diagonal Sigma^r_ph, Sigma^<_ph)
+through the C ABI with the dense definition of the oracle.
+
+The library forms the G^< source of every cluster by the four steps of
+Section 3.2 with P_i = all ancestors (the rows of G^(0) over every
+(cluster, ancestor) pair, the fold of N = Sigma^< (G^(0))+, D^{-1} N), then
+extracts G^< as without phonons.  Tolerance: 1e-10 normwise relative per
+energy (FP64) where the fold is well conditioned, as for ndg_solve.  At the
+superlattice's size, where the dense oracle is out of reach, the
+fluctuation-dissipation identity G^< = -f (G^r - G^r*) checks the path on
+every diagonal entry (equilibrium, eta = 0 in the device).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from inputs import devices, leads, phonons, workloads
+
+from .helpers import GATE, TOL, rel_err, tolerance
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(ndg, dev, e, eta, sig, pr, pl, max_batch=64, tree_kind=0, leaf_max=0, enable=True):
+    import torch
+    sl_, sr_, ll_, lr_ = sig
+    sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords,
+                      leaf_max=leaf_max, tree_kind=tree_kind)
+    plan = ndg.Plan(sym, max_batch=max_batch)
+    if enable:
+        plan.enable_scattering()
+    cuda = torch.device("cuda:0")
+    E = torch.tensor(np.asarray(e, np.float64), device=cuda)
+    sr = [torch.from_numpy(np.ascontiguousarray(a)).to(cuda) for a in (sl_, sr_)]
+    sl = [torch.from_numpy(np.ascontiguousarray(a)).to(cuda) for a in (ll_, lr_)]
+    prt = None if pr is None else torch.from_numpy(np.ascontiguousarray(pr)).to(cuda)
+    plt = None if pl is None else torch.from_numpy(np.ascontiguousarray(pl)).to(cuda)
+    growth = torch.zeros(len(e), dtype=torch.float64, device=cuda)
+    gr, gl, gg = plan.solve_scattering(E, eta, sr, sl, prt, plt, growth=growth)
+    torch.cuda.synchronize()
+    code, energy, cluster = plan.status()
+    assert code == 0, (code, energy, cluster)
+    return gr.cpu().numpy(), gl.cpu().numpy(), gg.cpu().numpy(), growth.cpu().numpy(), plan
+
+
+def _oracle(dev, e, eta, sig, pr, pl):
+    from oracle import definition
+    sl_, sr_, ll_, lr_ = sig
+    return definition.diag_greens(dev.scipy_h(), None, e, eta, dev.contacts, [sl_, sr_], [ll_, lr_],
+                                  pr, pl)
+
+
+def _check(out, ref, what):
+    growth = out[3]
+    er = rel_err(out[0], ref[0])
+    el = rel_err(out[1], ref[1])
+    scale = np.maximum(np.max(np.abs(ref[0]), axis=-1), np.max(np.abs(ref[1]), axis=-1))
+    eg = np.max(np.abs(out[2] - ref[2]), axis=-1) / scale
+    bad = []
+    for k in range(len(growth)):
+        _say("  %s energy %d growth %.3e errs %.2e %.2e %.2e" % (what, k, growth[k], er[k], el[k], eg[k]))
+        if not max(er[k], el[k], eg[k]) < tolerance(growth[k]):
+            bad.append(k)
+    assert not bad, bad
+    assert np.sum(growth < GATE) >= len(growth) // 2, "most energies must be held to 1e-10"
+
+
+@pytest.mark.parametrize("tree_kind,leaf_max", [(0, 0), (0, 8), (1, 0), (2, 0)])
+def test_scattering_small_grid_matches_definition(lib, tree_kind, leaf_max):
+    wl = workloads.small_grid(20, 12, n_energies=5, emin=0.02, emax=0.4, eta=1e-3, noise=0.05, seed=4)
+    e = wl.energies
+    sig = wl.self_energies(e)
+    pr, pl = phonons.diagonal_self_energies(wl.device, e, gamma0=1e-2, seed=2)
+    _say("scattering 20x12 tree_kind=%d leaf_max=%d" % (tree_kind, leaf_max))
+    out = _run(lib, wl.device, e, wl.eta, sig, pr, pl, tree_kind=tree_kind, leaf_max=leaf_max)
+    ref = _oracle(wl.device, e, wl.eta, sig, pr, pl)
+    _check(out, ref, "tree %d leaf %d" % (tree_kind, leaf_max))
+    # the phonon source is not negligible here
+    ref0 = _oracle(wl.device, e, wl.eta, sig, pr, None)
+    assert np.max(rel_err(ref0[1], ref[1])) > 1e-3
+
+
+def test_scattering_batches_and_ragged_tail(lib):
+    """7 energies through a plan of 3 (batches 3, 3, 1); larger fronts
+    (32 x 16, default leaves) that take the tiled kernels."""
+    wl = workloads.small_grid(32, 16, n_energies=7, emin=0.05, emax=0.35, eta=1e-3, noise=0.03, seed=8)
+    e = wl.energies
+    sig = wl.self_energies(e)
+    pr, pl = phonons.diagonal_self_energies(wl.device, e, gamma0=5e-3, seed=5)
+    _say("scattering 32x16 max_batch=3")
+    out = _run(lib, wl.device, e, wl.eta, sig, pr, pl, max_batch=3)
+    ref = _oracle(wl.device, e, wl.eta, sig, pr, pl)
+    _check(out, ref, "32x16")
+
+
+def test_scattering_wide_contacts(lib):
+    """Contacts of 80 sites span a parent-child chain of clusters: their part
+    of the source comes from the chains and is added to the phonon part."""
+    wl = workloads.small_grid(10, 80, n_energies=3, emin=0.05, emax=0.3, eta=1e-3, noise=0.03, seed=9)
+    e = wl.energies
+    sig = wl.self_energies(e)
+    pr, pl = phonons.diagonal_self_energies(wl.device, e, gamma0=1e-2, seed=6)
+    _say("scattering 10x80 (wide contacts)")
+    out = _run(lib, wl.device, e, wl.eta, sig, pr, pl)
+    ref = _oracle(wl.device, e, wl.eta, sig, pr, pl)
+    _check(out, ref, "10x80")
+
+
+def test_scattering_retarded_only_and_none(lib):
+    """Sigma^r_ph alone needs no scattering workspace (the contacts' chains
+    carry the whole source); with neither it equals ndg_solve."""
+    import torch
+    from .helpers import gpu_solve
+    wl = workloads.small_grid(16, 10, n_energies=3, emin=0.05, emax=0.3, eta=1e-3, noise=0.05, seed=6)
+    e = wl.energies
+    sig = wl.self_energies(e)
+    pr, _ = phonons.diagonal_self_energies(wl.device, e, gamma0=1e-2, seed=3)
+    _say("scattering Sigma^r_ph only")
+    out = _run(lib, wl.device, e, wl.eta, sig, pr, None, enable=False)
+    ref = _oracle(wl.device, e, wl.eta, sig, pr, None)
+    _check(out, ref, "r only")
+    _say("scattering without phonon terms vs ndg_solve")
+    out0 = _run(lib, wl.device, e, wl.eta, sig, None, None, enable=False)
+    plain, _ = gpu_solve(lib, wl)
+    for a, b in zip(out0[:3], plain[:3]):
+        assert np.array_equal(a, b)
+    torch.cuda.synchronize()
+
+
+def test_scattering_needs_enable(lib):
+    import torch
+    wl = workloads.small_grid(8, 6, n_energies=2, eta=1e-3)
+    e = wl.energies
+    sig = wl.self_energies(e)
+    pr, pl = phonons.diagonal_self_energies(wl.device, e, seed=1)
+    with pytest.raises(lib.NdgError):
+        _run(lib, wl.device, e, wl.eta, sig, pr, pl, enable=False)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("nt", [256, 1024])
+def test_scattering_superlattice_equilibrium_identity(lib, nt):
+    """Superlattice nt x 64 (the full-size geometry at nt = 1024), one
+    chemical potential for the leads and every phonon site, eta = 0 in the
+    device: diag G^< = -f (G^r - conj(G^r)) on all sites."""
+    wl = workloads.superlattice(n_transport=nt, n_energies=4)
+    dev = wl.device
+    e = np.array([0.03, 0.08, 0.12, 0.21])
+    mu = (0.1, 0.1)
+    sig = leads.contact_self_energies(dev, e, 1e-6, mu, wl.kt)
+    pr, pl = phonons.diagonal_self_energies(dev, e, gamma0=5e-3, mu=mu, seed=11, equilibrium=True)
+    _say("scattering superlattice %dx64 equilibrium" % nt)
+    gr, gl, gg, growth, plan = _run(lib, dev, e, 0.0, sig, pr, pl, max_batch=4, leaf_max=20)
+    _say("  scatter workspace %.1f MB per energy" % (plan.info()["scatter_bytes_per_energy"] / 1e6))
+    f = leads.fermi(e, mu[0], wl.kt)[:, None]
+    rhs = -f * (gr - gr.conj())
+    err = np.max(np.abs(gl - rhs), axis=1) / np.max(np.abs(rhs), axis=1)
+    for k in range(len(e)):
+        _say("  E=%.3f growth %.3e err %.2e" % (e[k], growth[k], err[k]))
+        assert err[k] < tolerance(growth[k])
+    # G^> = G^< + G^r - G^r* = (1 - f)(G^r - G^r*) in equilibrium
+    assert np.max(np.abs(gg - (1 - f) * (gr - gr.conj()))) <= 1e-9 * np.max(np.abs(gr))
