@@ -160,6 +160,63 @@ def bench_tube(ndg, workloads, torch, cuda):
             "algorithmic_gflop_per_energy": sym.info()["ops_total"] * 8 / 1e9}
 
 
+def bench_scattering(ndg, workloads, torch, cuda, leaf, n_energies=64, batch=32):
+    """Superlattice 1024x64 with diagonal phonon self-energies on every site
+    (local dephasing, gamma0 = 5 meV): every eighth energy of the 512-point
+    grid, FP64, through ndg_solve_scattering; per-kernel times from the
+    library's profile of one further solve."""
+    from inputs import phonons
+    w = workloads.superlattice(n_energies=512)
+    d = w.device
+    e = w.energies[::512 // n_energies][:n_energies]
+    sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, leaf_max=leaf)
+    plan = ndg.Plan(sym, max_batch=batch)
+    plan.enable_scattering()
+    sl, sr, ll, lr = w.self_energies(e)
+    pr, pl = phonons.diagonal_self_energies(d, e, gamma0=5e-3, mu=w.mu, kt=w.kt, seed=2)
+    E = torch.tensor(e, device=cuda)
+    srt = [torch.from_numpy(a).to(cuda) for a in (sl, sr)]
+    slt = [torch.from_numpy(a).to(cuda) for a in (ll, lr)]
+    prt = torch.from_numpy(pr).to(cuda)
+    plt = torch.from_numpy(pl).to(cuda)
+    stream = torch.cuda.current_stream(cuda)
+    out = plan.solve_scattering(E, w.eta, srt, slt, prt, plt)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    reps = 3
+    ev0.record(stream)
+    for _ in range(reps):
+        plan.solve_scattering(E, w.eta, srt, slt, prt, plt, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    plan.set_profiling(True)
+    plan.solve_scattering(E, w.eta, srt, slt, prt, plt, out=out)
+    prof = plan.profile()
+    plan.set_profiling(False)
+    kern = {}
+    for r in prof:
+        k = kern.setdefault(r["name"], {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
+        k["ms"] += r["ms"]
+        k["launches"] += r["launches"]
+        k["flops"] += r["flops"]
+        k["bytes"] += r["bytes"]
+    kernels = {name: {"ms_per_solve": k["ms"], "launches": k["launches"],
+                      "gbs": k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0,
+                      "tflops": k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0}
+               for name, k in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}
+    status = plan.status()
+    info = plan.info()
+    del plan
+    torch.cuda.empty_cache()
+    return {"workload": "superlattice 1024x64 FD grid, n=65536, diagonal phonon self-energies on "
+                        "every site (gamma0 5 meV), %d energies in [0,0.5] eV, FP64" % len(e),
+            "energy_points_per_s": len(e) / (ms * 1e-3), "ms_per_energy": ms / len(e),
+            "batch": batch, "scatter_bytes_per_energy": info["scatter_bytes_per_energy"],
+            "kernels": kernels, "status": list(status)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +227,8 @@ def main():
                     help="leaf size of the separator tree (0: picked by the autotuner)")
     ap.add_argument("--energies", type=int, default=512)
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false")
+    ap.add_argument("--no-scattering", dest="scattering", action="store_false",
+                    help="skip the phonon-scattering throughput figure")
     ap.add_argument("--no-extra", dest="extra", action="store_false",
                     help="skip the batched uneven-device and nanotube throughput figures")
     ap.add_argument("--cpu-sample", type=int, default=32,
@@ -294,6 +353,8 @@ def main():
                "ms_per_step": ms_adj}
         del pa
 
+    scat = bench_scattering(ndg, workloads, torch, cuda, args.leaf) if args.scattering else None
+
     extra = None
     if args.extra:
         extra = {"batch": bench_batch(ndg, workloads, torch, cuda),
@@ -371,6 +432,7 @@ def main():
         "mixed": {"value": ne / (ms_mixed / 1e3), "ms_per_step": ms_mixed,
                   "speedup_vs_fp64": ms_per_step / ms_mixed},
         "adjoint": adj,
+        "scattering": scat,
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity_sample": parity,

@@ -72,8 +72,11 @@ struct TileShape {
 // With PF, the operands of chunk k0 + KC are loaded into registers while the
 // matrix cores work on chunk k0 (the global-load latency hides behind the
 // MFMAs); kernels that inline several products turn it off to stay within
-// the register file.
-template <int TM, bool A_IFAST, bool B_KFAST, bool PF = true, int R = 64, class FA, class FB>
+// the register file.  With RAGGED the last chunk runs only the 4-deep MFMA
+// steps that hold live K (products with short K, where a full 16-deep chunk
+// would mostly multiply zeros).
+template <int TM, bool A_IFAST, bool B_KFAST, bool PF = true, int R = 64, bool RAGGED = false, class FA,
+          class FB>
 __device__ void zgemm_acc_t(int K, FA fa, FB fb, ZTile& acc, GemmSmemR<R>& sm) {
   static_assert(R >= TM, "staging rows");
   using T = TileShape<TM>;
@@ -131,8 +134,10 @@ __device__ void zgemm_acc_t(int K, FA fa, FB fb, ZTile& acc, GemmSmemR<R>& sm) {
     }
     __syncthreads();
     if (k0 + KC < K) load(k0 + KC);
+    const int kend = RAGGED ? min(KC, K - k0) : KC;
 #pragma unroll
     for (int k4 = 0; k4 < KC; k4 += 4) {
+      if (RAGGED && k4 >= kend) break;
       const int kq = k4 + (lane >> 4);
       double are[2], aim[2], bre[2], bim[2];
 #pragma unroll

@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) k_anc_g(Ctx c, ScatCtx x, const ColItem* 
   ZTile acc;
   ztile_zero(acc);
   if (j0 + nj > s)
-    zgemm_acc_t<TM, false, false, true, TM>(
+    zgemm_acc_t<TM, false, false, true, TM, true>(
         b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
         [&](int k, int j) {
           const int y = j0 + j;
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(256) k_anc_n(Ctx c, ScatCtx x, const ColItem* 
     const int bd = dd.b, gd = sdd.g, coff = L.col + j0;
     const int32_t* um = x.umap + L.map;
     // A(i, k) = Psi_d[k][u(i)]: row k of d, the B_d column of point i
-    zgemm_acc_t<TM, true, false, true, TM>(
+    zgemm_acc_t<TM, true, false, true, TM, true>(
         dd.s,
         [&](int i, int k) {
           const int u = i < s ? um[i] : -1;
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(256) k_anc_p0(Ctx c, ScatCtx x, const int32_t*
     const int nj = min(64, f - j0);
     ZTile acc;
     ztile_zero(acc);
-    zgemm_acc_t<TM, false, false, true, TM>(
+    zgemm_acc_t<TM, false, false, true, TM, true>(
         s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
         [&](int k, int j) {
           if (j >= nj) return cz();
