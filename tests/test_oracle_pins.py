@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from inputs import devices, leads, phonons, workloads
-from oracle import brute, definition, gradient, rgf
+from oracle import brute, definition, gradient, rgf, scba
 
 pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
 
@@ -271,6 +271,43 @@ def test_phonon_equilibrium_fluctuation_dissipation():
                                              [sl_[k:k + 1], sr_[k:k + 1]], [ll_[k:k + 1], lr_[k:k + 1]],
                                              pr[k:k + 1], pl[k:k + 1])
         assert _rel(dgl[0], np.diag(gl)) < 1e-12 and _rel(dgr[0], np.diag(g)) < 1e-12
+
+
+def test_scba_without_coupling_is_the_phonon_free_definition():
+    wl = workloads.small_grid(6, 4, n_energies=3, emin=0.05, emax=0.25, eta=1e-3, noise=0.05, seed=2)
+    e, sr, sl = _problem(wl)
+    h = wl.device.scipy_h()
+    out = scba.scba(h, None, e, wl.eta, wl.device.contacts, sr, sl, 0.0, 0.5, 1e-12, 10)
+    ref = definition.diag_greens(h, None, e, wl.eta, wl.device.contacts, sr, sl)
+    assert out[5] == 1 and out[6] == 0.0
+    assert _rel(out[0], ref[0]) < 1e-14 and _rel(out[1], ref[1]) < 1e-14
+    assert not np.any(out[3]) and not np.any(out[4])
+
+
+def test_scba_preserves_equilibrium_and_converges_to_a_fixed_point():
+    """Leads at one chemical potential, eta = 0 in the device: every iterate
+    keeps Sigma^<_ph = -f (Sigma^r_ph - Sigma^r_ph*) (it is D0 times a
+    G^< that obeys G^< = -f (G^r - G^r*)), so the converged diagonals obey
+    both identities; and the returned self-energies reproduce themselves
+    when the definition is evaluated once more with them."""
+    dev = devices.fd2d(8, 4)
+    e = np.array([3.8, 4.2, 4.6])        # in the first transverse band (edge near 3.5 eV)
+    mu = (4.2, 4.2)
+    sl_, sr_, ll_, lr_ = leads.contact_self_energies(dev, e, 1e-6, mu, 0.025)
+    d0 = 0.2
+    dgr, dgl, _, spr, spl, it, res = scba.scba(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_],
+                                               [ll_, lr_], d0, 0.7, 1e-12, 200)
+    assert res < 1e-12 and 2 < it < 200
+    f = leads.fermi(e, 4.2, 0.025)[:, None]
+    assert _rel(dgl, -f * (dgr - dgr.conj())) < 1e-11
+    assert _rel(spl, -f * (spr - spr.conj())) < 1e-11
+    # fixed point: one more evaluation at the returned self-energies
+    gr2, gl2, _ = definition.diag_greens(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_],
+                                         [ll_, lr_], spr, spl)
+    assert _rel(d0 * gr2, spr) < 1e-10 and _rel(d0 * gl2, spl) < 1e-10
+    # the scattering is not negligible at this coupling
+    gr0, _, _ = definition.diag_greens(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_], [ll_, lr_])
+    assert _rel(gr2, gr0) > 1e-2
 
 
 # ---------------------------------------------------------------------------
