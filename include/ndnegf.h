@@ -224,6 +224,35 @@ ndg_status ndg_solve_scattering(ndg_plan* plan, int32_t nE, const double* E, dou
                                 ndg_c128* diag_ggreater, double* growth, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Self-consistent Born loop for local elastic phonon scattering.
+ *
+ * The phonon self-energy of equation defineA depends on the Green's
+ * functions; for local elastic (deformation-potential) scattering,
+ *   Sigma^r_ph,k(E) = d0 G^r_kk(E),   Sigma^<_ph,k(E) = d0 G^<_kk(E).
+ * ndg_scba iterates: solve with the current self-energies
+ * (ndg_solve_scattering), S' = d0 diag G, residual = max|S' - S| / max|S'|
+ * over both self-energies, all sites and energies, S <- (1 - mix) S + mix S';
+ * it stops after the update once residual < tol, or after max_iter solves.
+ *
+ *   d0                coupling (energy^2), >= 0;  mix in (0, 1];  tol >= 0
+ *   sig_r_ph, sig_less_ph   device [nE][n] (caller's site order): the
+ *                     starting self-energies on entry (zero for a cold
+ *                     start), the last update on return
+ *   diag_*            device outputs of the last solve (diag_ggreater may
+ *                     be NULL)
+ *   iterations, residual   host outputs (may be NULL): solves run, last
+ *                     residual
+ * Needs ndg_plan_enable_scattering.  Synchronizes `stream` once per
+ * iteration to read the residual, so it cannot be captured into a graph.  The other arguments are those of ndg_solve.
+ * Errors: NDG_EINVAL (arguments, scattering not enabled), NDG_EHIP.
+ */
+ndg_status ndg_scba(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
+                    const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, double d0, double mix,
+                    double tol, int32_t max_iter, ndg_c128* sig_r_ph, ndg_c128* sig_less_ph,
+                    ndg_c128* diag_gr, ndg_c128* diag_gless, ndg_c128* diag_ggreater, int32_t* iterations,
+                    double* residual, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Electron density and its gradient with respect to the on-site potential.
  *
  * ndg_density: density[i] = sum_E cE[E] (-i G^<_ii(E)), the G^< of ndg_solve

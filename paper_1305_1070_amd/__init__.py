@@ -23,7 +23,7 @@ __all__ = ["analyze", "Symbolic", "Plan", "load", "NdgError", "NDG_FP64", "NDG_M
            "ndg_plan_export_block", "ndg_plan_set_profiling", "ndg_plan_profile",
            "ndg_density", "ndg_plan_enable_adjoint", "ndg_density_vjp", "NDDensity",
            "ndg_batch_create", "ndg_batch_destroy", "ndg_batch_solve", "Batch",
-           "ndg_plan_enable_scattering", "ndg_solve_scattering",
+           "ndg_plan_enable_scattering", "ndg_solve_scattering", "ndg_scba",
            "ndg_status_string", "ndg_last_error"]
 
 
@@ -112,6 +112,20 @@ def ndg_solve_scattering(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs,
     sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
     _lib.check(load().ndg_solve_scattering(plan, ne, e_ptr, eta, v_ptr, sr, sl, sr_ph_ptr, sl_ph_ptr,
                                            dgr_ptr, dgl_ptr, dgg_ptr, growth_ptr, stream_ptr))
+
+
+def ndg_scba(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, d0, mix, tol, max_iter,
+             sr_ph_ptr, sl_ph_ptr, dgr_ptr, dgl_ptr, dgg_ptr, stream_ptr):
+    """Returns (iterations, residual)."""
+    nc = len(sig_r_ptrs)
+    sr = (C.c_void_p * max(1, nc))(*sig_r_ptrs)
+    sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
+    it = C.c_int32()
+    res = C.c_double()
+    _lib.check(load().ndg_scba(plan, ne, e_ptr, eta, v_ptr, sr, sl, d0, mix, tol, max_iter, sr_ph_ptr,
+                               sl_ph_ptr, dgr_ptr, dgl_ptr, dgg_ptr, C.byref(it), C.byref(res),
+                               stream_ptr))
+    return it.value, res.value
 
 
 def ndg_density(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, ce_ptr, dens_ptr, prec,
@@ -320,6 +334,35 @@ class Plan:
     def enable_scattering(self):
         ndg_plan_enable_scattering(self.handle)
         self._info = ndg_plan_info(self.handle)
+
+    def scba(self, E, eta, sig_r, sig_less, d0, mix=0.7, tol=1e-10, max_iter=100, sig_r_ph=None,
+             sig_less_ph=None, V=None, out=None, stream=None):
+        """Self-consistent Born loop (local elastic scattering, ndg_scba).
+        sig_r_ph / sig_less_ph: starting complex128 [nE, n] tensors, updated
+        in place (zeros when None).  Returns (diag G^r, diag G^<, diag G^>,
+        sig_r_ph, sig_less_ph, iterations, residual)."""
+        import torch
+        n, ne, dev = self._check_inputs(E, sig_r, sig_less, V)
+        ph = []
+        for t in (sig_r_ph, sig_less_ph):
+            if t is None:
+                t = torch.zeros((ne, n), dtype=torch.complex128, device=dev)
+            elif (t.dtype != torch.complex128 or tuple(t.shape) != (ne, n) or t.device != dev
+                  or not t.is_contiguous()):
+                raise ValueError("phonon self-energies must be contiguous complex128 [nE, n] "
+                                 "tensors on the plan's device")
+            ph.append(t)
+        if out is None:
+            out = tuple(torch.empty((ne, n), dtype=torch.complex128, device=dev) for _ in range(3))
+        gr, gl, gg = out
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        it, res = ndg_scba(self.handle, ne, E.data_ptr(), float(eta),
+                           V.data_ptr() if V is not None else None,
+                           [t.data_ptr() for t in sig_r], [t.data_ptr() for t in sig_less],
+                           float(d0), float(mix), float(tol), int(max_iter), ph[0].data_ptr(),
+                           ph[1].data_ptr(), gr.data_ptr(), gl.data_ptr(),
+                           gg.data_ptr() if gg is not None else None, C.c_void_p(st.cuda_stream))
+        return gr, gl, gg, ph[0], ph[1], it, res
 
     def solve_scattering(self, E, eta, sig_r, sig_less, sig_r_ph=None, sig_less_ph=None, V=None,
                          out=None, stream=None, growth=None):

@@ -159,6 +159,12 @@ void launch_anc_n(const Ctx& c, const ScatCtx& x, const ColItem* it, int nit, in
                   hipStream_t st);
 void launch_anc_p0(const Ctx& c, const ScatCtx& x, const int32_t* cls, int ncl, int nb, int tile_rows,
                    hipStream_t st);
+// self-consistent Born update over count = nE n entries: S' = d0 diag G,
+// S <- (1 - mix) S + mix S' for Sigma^r_ph and Sigma^<_ph; out[0] = max
+// |S' - S|, out[1] = max |S'| (part: kScbaBlocks x 2 doubles of scratch)
+constexpr int kScbaBlocks = 1024;
+void launch_scba_mix(const double2* dgr, const double2* dgl, double2* sr, double2* sl, int64_t count,
+                     double d0, double mix, double* part, double* out, hipStream_t st);
 
 // Launchers (kernels.hip).  nb = energies in the batch.
 void launch_assemble(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st);

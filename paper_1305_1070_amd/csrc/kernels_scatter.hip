@@ -25,6 +25,8 @@
 // The extraction of G^< then runs unchanged with a source on every cluster.
 #include "device_common.hpp"
 
+#include <algorithm>
+
 namespace ndg {
 
 namespace {
@@ -194,6 +196,68 @@ __global__ void __launch_bounds__(256) k_anc_p0(Ctx c, ScatCtx x, const int32_t*
       }
     });
   }
+}
+
+// Self-consistent Born update (local elastic scattering): per (energy, site)
+// S' = d0 G_kk for the retarded and lesser self-energies, S mixed towards S',
+// and per block the largest change and the largest new value; the maxima
+// are combined by k_scba_max (order-independent, so deterministic).
+__global__ void __launch_bounds__(256) k_scba_mix(const double2* dgr, const double2* dgl, double2* sr, double2* sl,
+                                                  int64_t count, double d0, double mix, double* part) {
+  __shared__ double rd[256], rs[256];
+  double dmax = 0.0, smax = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < count; q += (int64_t)gridDim.x * 256) {
+    const double2 gr = dgr[q], gl = dgl[q], o_r = sr[q], o_l = sl[q];
+    const double2 nr = make_double2(d0 * gr.x, d0 * gr.y), nl = make_double2(d0 * gl.x, d0 * gl.y);
+    dmax = fmax(dmax, fmax(hypot(nr.x - o_r.x, nr.y - o_r.y), hypot(nl.x - o_l.x, nl.y - o_l.y)));
+    smax = fmax(smax, fmax(hypot(nr.x, nr.y), hypot(nl.x, nl.y)));
+    sr[q] = make_double2((1.0 - mix) * o_r.x + mix * nr.x, (1.0 - mix) * o_r.y + mix * nr.y);
+    sl[q] = make_double2((1.0 - mix) * o_l.x + mix * nl.x, (1.0 - mix) * o_l.y + mix * nl.y);
+  }
+  rd[threadIdx.x] = dmax;
+  rs[threadIdx.x] = smax;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rd[threadIdx.x] = fmax(rd[threadIdx.x], rd[threadIdx.x + w]);
+      rs[threadIdx.x] = fmax(rs[threadIdx.x], rs[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = rd[0];
+    part[2 * blockIdx.x + 1] = rs[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_scba_max(const double* part, int nblk, double* out) {
+  __shared__ double rd[256], rs[256];
+  double dmax = 0.0, smax = 0.0;
+  for (int q = threadIdx.x; q < nblk; q += 256) {
+    dmax = fmax(dmax, part[2 * q]);
+    smax = fmax(smax, part[2 * q + 1]);
+  }
+  rd[threadIdx.x] = dmax;
+  rs[threadIdx.x] = smax;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rd[threadIdx.x] = fmax(rd[threadIdx.x], rd[threadIdx.x + w]);
+      rs[threadIdx.x] = fmax(rs[threadIdx.x], rs[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = rd[0];
+    out[1] = rs[0];
+  }
+}
+
+void launch_scba_mix(const double2* dgr, const double2* dgl, double2* sr, double2* sl, int64_t count,
+                     double d0, double mix, double* part, double* out, hipStream_t st) {
+  const int nblk = (int)std::min<int64_t>(kScbaBlocks, std::max<int64_t>(1, (count + 255) / 256));
+  hipLaunchKernelGGL(k_scba_mix, dim3(nblk), dim3(256), 0, st, dgr, dgl, sr, sl, count, d0, mix, part);
+  hipLaunchKernelGGL(k_scba_max, dim3(1), dim3(256), 0, st, part, nblk, out);
 }
 
 void launch_anc_g(const Ctx& c, const ScatCtx& x, const ColItem* it, int nit, int nb, int tile_rows,

@@ -88,6 +88,7 @@ struct ndg_plan {
   ndg::ColItem* d_ancitems = nullptr;
   int32_t* d_anccls = nullptr;
   double2* d_sws = nullptr;
+  double* d_scba = nullptr;  // Born loop reduction scratch: kScbaBlocks x 2 partials, then 2 maxima
   int64_t sstride = 0;
   struct AncGroup { int it0 = 0, nit = 0, cl0 = 0, ncl = 0; };
   std::vector<AncGroup> anc_groups;  // [(H + 1) * 3]
@@ -202,7 +203,7 @@ void free_plan(ndg_plan* p) {
                   p->d_srow,      p->d_scol,     p->d_scid,       p->d_sflat,      p->d_hfront,
                   p->d_smap,      p->d_pinv,     p->d_gaddr,      p->d_sdiag,      p->d_sd,
                   p->d_atab,      p->d_bpos,     p->d_lk,         p->d_umap,       p->d_ancitems,
-                  p->d_anccls,    p->d_sws};
+                  p->d_anccls,    p->d_sws,      p->d_scba};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& r : p->recs) {
@@ -723,9 +724,11 @@ int plan_enable_scattering(ndg_plan* p) {
   if (!rc && !umap.empty()) rc = upload(&p->d_umap, umap.data(), umap.size());
   if (!rc) rc = upload(&p->d_ancitems, items.data(), items.size());
   if (!rc) rc = upload(&p->d_anccls, cls.data(), cls.size());
+  if (!rc && hipMalloc((void**)&p->d_scba, (2 * kScbaBlocks + 2) * sizeof(double)) != hipSuccess) rc = NDG_ENOMEM;
   if (rc) {
     (void)hipGetLastError();
-    void* ptrs[] = {p->d_sws, p->d_sd, p->d_atab, p->d_bpos, p->d_lk, p->d_umap, p->d_ancitems, p->d_anccls};
+    void* ptrs[] = {p->d_sws, p->d_sd, p->d_atab, p->d_bpos, p->d_lk, p->d_umap, p->d_ancitems, p->d_anccls,
+                    p->d_scba};
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
     p->d_sws = nullptr;
@@ -736,6 +739,7 @@ int plan_enable_scattering(ndg_plan* p) {
     p->d_umap = nullptr;
     p->d_ancitems = nullptr;
     p->d_anccls = nullptr;
+    p->d_scba = nullptr;
     for (int k = K_ANC_G; k <= K_ANC_P0; ++k)
       for (int h = 0; h <= H; ++h) p->cost_flops[k * (H + 1) + h] = p->cost_bytes[k * (H + 1) + h] = 0;
     set_error("ndg_plan_enable_scattering: device allocation failed");
@@ -750,6 +754,38 @@ int plan_solve(ndg_plan* p, int nE, const double* E, double eta, const double* V
                ndg_c128* dgl, ndg_c128* dgg, double* growth, int prec, void* stream) {
   return plan_run(p, kRunSolve, nE, E, eta, V, sig_r, sig_less, dgr, dgl, dgg, growth, nullptr,
                   nullptr, nullptr, nullptr, prec, stream);
+}
+
+int plan_scba(ndg_plan* p, int nE, const double* E, double eta, const double* V,
+              const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, double d0, double mix,
+              double tol, int max_iter, ndg_c128* sig_r_ph, ndg_c128* sig_less_ph, ndg_c128* dgr,
+              ndg_c128* dgl, ndg_c128* dgg, int32_t* iterations, double* residual, void* stream) {
+  if (!p->d_sws) {
+    set_error("ndg_scba: call ndg_plan_enable_scattering first");
+    return NDG_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int it = 0;
+  double res = 0.0, hm[2] = {0.0, 0.0};
+  while (it < max_iter) {
+    int rc = plan_run(p, kRunSolve, nE, E, eta, V, sig_r, sig_less, dgr, dgl, dgg, nullptr, nullptr, nullptr,
+                      nullptr, nullptr, NDG_FP64, stream, nullptr, sig_r_ph, sig_less_ph);
+    if (rc) return rc;
+    ++it;
+    launch_scba_mix(reinterpret_cast<const double2*>(dgr), reinterpret_cast<const double2*>(dgl),
+                    reinterpret_cast<double2*>(sig_r_ph), reinterpret_cast<double2*>(sig_less_ph),
+                    (int64_t)nE * p->n, d0, mix, p->d_scba, p->d_scba + 2 * kScbaBlocks, st);
+    if (hipMemcpyAsync(hm, p->d_scba + 2 * kScbaBlocks, sizeof(hm), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("ndg_scba: reading the residual failed");
+      return NDG_EHIP;
+    }
+    res = hm[1] > 0.0 ? hm[0] / hm[1] : 0.0;
+    if (res < tol) break;
+  }
+  if (iterations) *iterations = it;
+  if (residual) *residual = res;
+  return NDG_OK;
 }
 
 int plan_solve_chunk(ndg_plan* p, int nE, const double* E, double eta, const double* V,

@@ -40,6 +40,10 @@ int plan_solve_chunk(ndg_plan* plan, int nE, const double* E, double eta, const 
 int plan_max_batch(const ndg_plan* plan);
 int plan_enable_adjoint(ndg_plan* plan);
 int plan_enable_scattering(ndg_plan* plan);
+int plan_scba(ndg_plan* p, int nE, const double* E, double eta, const double* V,
+              const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, double d0, double mix,
+              double tol, int max_iter, ndg_c128* sig_r_ph, ndg_c128* sig_less_ph, ndg_c128* dgr,
+              ndg_c128* dgl, ndg_c128* dgg, int32_t* iterations, double* residual, void* stream);
 int plan_ncontacts(const ndg_plan* plan);
 int plan_device(const ndg_plan* plan);
 bool plan_profiling(const ndg_plan* plan);

@@ -166,3 +166,61 @@ def test_scattering_superlattice_equilibrium_identity(lib, nt):
         assert err[k] < tolerance(growth[k])
     # G^> = G^< + G^r - G^r* = (1 - f)(G^r - G^r*) in equilibrium
     assert np.max(np.abs(gg - (1 - f) * (gr - gr.conj()))) <= 1e-9 * np.max(np.abs(gr))
+
+
+def _scba_gpu(ndg, dev, e, eta, sig, d0, mix, tol, max_iter, leaf_max=0, max_batch=64):
+    import torch
+    sl_, sr_, ll_, lr_ = sig
+    sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, leaf_max=leaf_max)
+    plan = ndg.Plan(sym, max_batch=max_batch)
+    plan.enable_scattering()
+    cuda = torch.device("cuda:0")
+    E = torch.tensor(np.asarray(e, np.float64), device=cuda)
+    sr = [torch.from_numpy(np.ascontiguousarray(a)).to(cuda) for a in (sl_, sr_)]
+    sl = [torch.from_numpy(np.ascontiguousarray(a)).to(cuda) for a in (ll_, lr_)]
+    gr, gl, gg, spr, spl, it, res = plan.scba(E, eta, sr, sl, d0, mix, tol, max_iter)
+    torch.cuda.synchronize()
+    assert plan.status()[0] == 0
+    return (gr.cpu().numpy(), gl.cpu().numpy(), gg.cpu().numpy(), spr.cpu().numpy(), spl.cpu().numpy(),
+            it, res)
+
+
+def test_scba_matches_oracle_loop(lib):
+    """The Born loop on the GPU against the oracle's loop: same iterations,
+    the same self-energies and Green's functions (both iterate the same
+    contraction from zero; FP64 differences of one solve stay at 1e-15)."""
+    from oracle import scba
+    dev = devices.fd2d(16, 8)
+    e = np.linspace(1.2, 1.8, 5)              # first transverse band of the 8-wide lead
+    mu = (1.5, 1.4)
+    sig = leads.contact_self_energies(dev, e, 1e-6, mu, 0.025)
+    sl_, sr_, ll_, lr_ = sig
+    _say("scba 16x8 d0=0.1")
+    out = _scba_gpu(lib, dev, e, 1e-6, sig, 0.1, 0.7, 1e-10, 60, leaf_max=8)
+    ref = scba.scba(dev.scipy_h(), None, e, 1e-6, dev.contacts, [sl_, sr_], [ll_, lr_], 0.1, 0.7, 1e-10, 60)
+    _say("  iterations gpu %d oracle %d, residual gpu %.2e oracle %.2e" % (out[5], ref[5], out[6], ref[6]))
+    assert out[5] == ref[5] and out[6] < 1e-10
+    for k, name in ((0, "Gr"), (1, "Gless"), (3, "Sigma^r_ph"), (4, "Sigma^<_ph")):
+        err = np.max(rel_err(out[k], ref[k]))
+        _say("  %s max rel err %.2e" % (name, err))
+        assert err < 1e-10, name
+
+
+def test_scba_superlattice_equilibrium(lib):
+    """Superlattice 256 x 64, leads at one chemical potential, eta = 0 in
+    the device: every Born iterate keeps the fluctuation-dissipation pairs,
+    so the converged G^< = -f (G^r - G^r*) and
+    Sigma^<_ph = -f (Sigma^r_ph - Sigma^r_ph*) on every site."""
+    wl = workloads.superlattice(n_transport=256, n_energies=4)
+    dev = wl.device
+    e = np.array([0.04, 0.09, 0.15, 0.22])
+    mu = (0.1, 0.1)
+    sig = leads.contact_self_energies(dev, e, 1e-6, mu, wl.kt)
+    _say("scba superlattice 256x64 equilibrium")
+    gr, gl, gg, spr, spl, it, res = _scba_gpu(lib, dev, e, 0.0, sig, 0.05, 0.8, 1e-9, 80, leaf_max=20,
+                                              max_batch=4)
+    _say("  iterations %d residual %.2e max |Sigma^r_ph| %.3e" % (it, res, np.abs(spr).max()))
+    assert res < 1e-9 and it > 2
+    f = leads.fermi(e, mu[0], wl.kt)[:, None]
+    assert np.max(rel_err(gl, -f * (gr - gr.conj()))) < 1e-9
+    assert np.max(rel_err(spl, -f * (spr - spr.conj()))) < 1e-9
