@@ -152,9 +152,11 @@ struct ScatCtx {
   int64_t stride;
 };
 constexpr int kMaxAncestors = 63;
-// tile_rows 16, 32 or 64 (at least the largest cluster of the launch)
+constexpr int kClusterRows = 64;  // largest cluster the kernels hold per block
+// tile_rows 16, 32 or 64 (at least the largest cluster of the launch);
+// leaves: the launch holds only leaves (height 1), which store their N
 void launch_anc_g(const Ctx& c, const ScatCtx& x, const ColItem* it, int nit, int nb, int tile_rows,
-                  hipStream_t st);
+                  bool leaves, hipStream_t st);
 void launch_anc_n(const Ctx& c, const ScatCtx& x, const ColItem* it, int nit, int nb, int tile_rows,
                   hipStream_t st);
 void launch_anc_p0(const Ctx& c, const ScatCtx& x, const int32_t* cls, int ncl, int nb, int tile_rows,

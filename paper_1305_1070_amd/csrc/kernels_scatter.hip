@@ -55,12 +55,16 @@ __device__ inline void load_frame(const ScatCtx& x, const ScatDesc& sd, FrameLds
 // block; the tile's columns inside the cluster's own points take G_ii from
 // the G^r extraction.  Entry (x, y) of G_{B,Anc}, x in the frame's cluster
 // a_x and y in a_y: the rows of the lower of the two (G(x, y) in a_x's rows
-// when a_y >= a_x, else G(y, x) in a_y's rows).
-template <int TM>
-__global__ void __launch_bounds__(256) k_anc_g(Ctx c, ScatCtx x, const ColItem* items) {
+// when a_y >= a_x, else G(y, x) in a_y's rows).  A leaf's rows are gathered
+// by nobody and its N has no descendants' part, so a leaf stores
+// N_i = Sigma^<_ph,i conj(G) at once (k_anc_n skips the leaves); LEAF
+// launches (height 1) hold only leaves.
+template <int TM, bool LEAF>
+__device__ __forceinline__ void anc_g_body(const Ctx& c, const ScatCtx& x, const ColItem* items) {
   __shared__ GemmSmemR<TM> sm;
   __shared__ FrameLds fr;
   __shared__ int32_t col_a[64];
+  __shared__ double2 sig_row[kClusterRows];
   const ColItem it = items[blockIdx.x];
   const int e = blockIdx.y;
   const int eb = ebase(c);
@@ -72,6 +76,7 @@ __global__ void __launch_bounds__(256) k_anc_g(Ctx c, ScatCtx x, const ColItem* 
   const int s = d.s, b = d.b, f = d.f, g = sd.g, D = sd.D;
   const int j0 = it.tc * 64, nj = min(64, g - j0);
   load_frame(x, sd, fr);
+  if (LEAF && threadIdx.x < s) sig_row[threadIdx.x] = c.sig_l_ph[(int64_t)(eb + e) * c.n + c.perm[d.pt_off + threadIdx.x]];
   __syncthreads();
   if (threadIdx.x < 64) {
     const int y = j0 + threadIdx.x;
@@ -102,8 +107,27 @@ __global__ void __launch_bounds__(256) k_anc_g(Ctx c, ScatCtx x, const ColItem* 
         acc, sm);
   ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
     const int y = j0 + j;
-    if (i < s && j < nj) Gi[(int64_t)i * g + y] = y < s ? Gf[(int64_t)i * f + y] : make_double2(re, im);
+    if (i < s && j < nj) {
+      double2 v = y < s ? Gf[(int64_t)i * f + y] : make_double2(re, im);
+      if constexpr (LEAF) {
+        const double2 sg = sig_row[i];
+        v = make_double2(sg.x * v.x + sg.y * v.y, sg.y * v.x - sg.x * v.y);   // sigma conj(G)
+      }
+      Gi[(int64_t)i * g + y] = v;
+    }
   });
+}
+
+template <int TM>
+__global__ void __launch_bounds__(256) k_anc_g(Ctx c, ScatCtx x, const ColItem* items) {
+  anc_g_body<TM, false>(c, x, items);
+}
+// the leaves' epilogue holds more registers: the hint keeps the 16-row
+// tiles (most leaves) at seven waves per SIMD
+template <int TM, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_anc_g_leaf(Ctx c, ScatCtx x, const ColItem* items) {
+  anc_g_body<TM, true>(c, x, items);
 }
 
 // N_i over one 64-column tile of the frame.  The own term Sigma^<_ph conj(G)
@@ -111,6 +135,7 @@ __global__ void __launch_bounds__(256) k_anc_g(Ctx c, ScatCtx x, const ColItem* 
 template <int TM>
 __global__ void __launch_bounds__(256) k_anc_n(Ctx c, ScatCtx x, const ColItem* items) {
   __shared__ GemmSmemR<TM> sm;
+  __shared__ double2 sig_row[kClusterRows];
   const ColItem it = items[blockIdx.x];
   const int e = blockIdx.y;
   const int eb = ebase(c);
@@ -121,6 +146,8 @@ __global__ void __launch_bounds__(256) k_anc_n(Ctx c, ScatCtx x, const ColItem* 
   double2* X = x.ws + (int64_t)e * x.stride;
   const int s = d.s, g = sd.g;
   const int j0 = it.tc * 64, nj = min(64, g - j0);
+  if (threadIdx.x < s) sig_row[threadIdx.x] = c.sig_l_ph[(int64_t)(eb + e) * c.n + c.perm[d.pt_off + threadIdx.x]];
+  __syncthreads();
   ZTile acc;
   ztile_zero(acc);
   for (int q = sd.lk0; q < sd.lk1; ++q) {
@@ -140,13 +167,12 @@ __global__ void __launch_bounds__(256) k_anc_n(Ctx c, ScatCtx x, const ColItem* 
         },
         [&](int k, int j) { return j < nj ? Nd[(int64_t)k * gd + coff + j] : cz(); }, acc, sm);
   }
-  const double2* sl = c.sig_l_ph + (int64_t)(eb + e) * c.n;
   double2* Ni = X + sd.o_g;
   ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
     if (i < s && j < nj) {
       const int64_t pos = (int64_t)i * g + j0 + j;
       const double2 gv = Ni[pos];
-      const double2 sg = sl[c.perm[d.pt_off + i]];
+      const double2 sg = sig_row[i];
       re += sg.x * gv.x + sg.y * gv.y;   // sigma conj(G)
       im += sg.y * gv.x - sg.x * gv.y;
       Ni[pos] = make_double2(re, im);
@@ -261,11 +287,18 @@ void launch_scba_mix(const double2* dgr, const double2* dgl, double2* sr, double
 }
 
 void launch_anc_g(const Ctx& c, const ScatCtx& x, const ColItem* it, int nit, int nb, int tile_rows,
-                  hipStream_t st) {
+                  bool leaves, hipStream_t st) {
   if (nit <= 0) return;
-  if (tile_rows <= 16) hipLaunchKernelGGL(k_anc_g<16>, dim3(nit, nb), dim3(256), 0, st, c, x, it);
-  else if (tile_rows <= 32) hipLaunchKernelGGL(k_anc_g<32>, dim3(nit, nb), dim3(256), 0, st, c, x, it);
-  else hipLaunchKernelGGL(k_anc_g<64>, dim3(nit, nb), dim3(256), 0, st, c, x, it);
+  const dim3 grid(nit, nb), blk(256);
+  if (leaves) {
+    if (tile_rows <= 16) hipLaunchKernelGGL((k_anc_g_leaf<16, 7>), grid, blk, 0, st, c, x, it);
+    else if (tile_rows <= 32) hipLaunchKernelGGL((k_anc_g_leaf<32, 4>), grid, blk, 0, st, c, x, it);
+    else hipLaunchKernelGGL((k_anc_g_leaf<64, 3>), grid, blk, 0, st, c, x, it);
+  } else {
+    if (tile_rows <= 16) hipLaunchKernelGGL(k_anc_g<16>, grid, blk, 0, st, c, x, it);
+    else if (tile_rows <= 32) hipLaunchKernelGGL(k_anc_g<32>, grid, blk, 0, st, c, x, it);
+    else hipLaunchKernelGGL(k_anc_g<64>, grid, blk, 0, st, c, x, it);
+  }
 }
 
 void launch_anc_n(const Ctx& c, const ScatCtx& x, const ColItem* it, int nit, int nb, int tile_rows,

@@ -616,6 +616,7 @@ int plan_enable_adjoint(ndg_plan* p) {
 }
 
 int plan_enable_scattering(ndg_plan* p) {
+  static_assert(kClusterRows >= kMaxCluster, "scattering kernels stage one value per cluster row");
   if (p->d_sws) return NDG_OK;
   if (hipSetDevice(p->device) != hipSuccess) {
     set_error("ndg_plan_enable_scattering: hipSetDevice failed");
@@ -704,13 +705,18 @@ int plan_enable_scattering(ndg_plan* p) {
     const double s = hd[i].s, b = hd[i].b, f = hd[i].f, g = sd[i].g, W = g - s;
     p->cost_flops[K_ANC_G * (H + 1) + h] += 8.0 * s * b * W;
     p->cost_bytes[K_ANC_G * (H + 1) + h] += 16.0 * (s * b + b * W + s * g);
-    double nf = 0, nby = 32.0 * s * g;
-    for (const LkItem& L : lkj[i]) {
-      nf += 8.0 * s * hd[L.d].s * g;
-      nby += 16.0 * hd[L.d].s * g;
+    // the N fold of an inner cluster: read G^(0) rows, write N, and per
+    // feeding descendant its N rows over this frame and its Psi entries
+    // (leaves are formed inside k_anc_g: no launch, no cost here)
+    if (h > 1) {
+      double nf = 0, nby = 32.0 * s * g;
+      for (const LkItem& L : lkj[i]) {
+        nf += 8.0 * s * hd[L.d].s * g;
+        nby += 16.0 * hd[L.d].s * (g + s);
+      }
+      p->cost_flops[K_ANC_N * (H + 1) + h] += nf;
+      p->cost_bytes[K_ANC_N * (H + 1) + h] += nby;
     }
-    p->cost_flops[K_ANC_N * (H + 1) + h] += nf;
-    p->cost_bytes[K_ANC_N * (H + 1) + h] += nby + 16.0 * b * s;
     p->cost_flops[K_ANC_P0 * (H + 1) + h] += 8.0 * s * s * f;
     p->cost_bytes[K_ANC_P0 * (H + 1) + h] += 16.0 * (s * s + 2.0 * s * f);
   }
@@ -1000,12 +1006,14 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         for (int q = 0; q < 3; ++q) {
           const ndg_plan::AncGroup& g = p->anc_groups[h * 3 + q];
           if (g.nit)
-            timed(K_ANC_G, h, nb, [&] { launch_anc_g(c, x, p->d_ancitems + g.it0, g.nit, nb, kTile[q], st); });
+            timed(K_ANC_G, h, nb,
+                  [&] { launch_anc_g(c, x, p->d_ancitems + g.it0, g.nit, nb, kTile[q], h == 1, st); });
         }
+      // leaves (height 1) stored their N in k_anc_g
       for (int h = 1; h <= H; ++h)
         for (int q = 0; q < 3; ++q) {
           const ndg_plan::AncGroup& g = p->anc_groups[h * 3 + q];
-          if (g.nit)
+          if (g.nit && h > 1)
             timed(K_ANC_N, h, nb, [&] { launch_anc_n(c, x, p->d_ancitems + g.it0, g.nit, nb, kTile[q], st); });
           if (g.ncl)
             timed(K_ANC_P0, h, nb, [&] { launch_anc_p0(c, x, p->d_anccls + g.cl0, g.ncl, nb, kTile[q], st); });
