@@ -40,6 +40,11 @@ def _rgf_energy(args):
     return idx, time.perf_counter() - t, gr[0], gl[0]
 
 
+def _progress(msg):
+    """One line per finished leg on stderr (the JSON line stays alone on stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def cpu_baseline(idxs, wl_args):
     """Times the RGF oracle on the host cores: one process per core, one BLAS
     thread each, energies distributed over the pool."""
@@ -67,16 +72,17 @@ def _noop(_):
     return 0
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter profile
-    (profiles/traffic.json: FETCH_SIZE + WRITE_SIZE per kernel, scaled by a
-    plain copy), or None if the profile lacks that kernel or is of other
-    library sources."""
+def measured_traffic(kernel, profile="traffic.json"):
+    """HBM bytes per launch of `kernel` from a committed counter profile
+    (profiles/traffic.json for the superlattice solve,
+    profiles/traffic_scattering.json for the phonon solve: FETCH_SIZE +
+    WRITE_SIZE per kernel, scaled by a plain copy), or None if the profile
+    lacks that kernel or is of other library sources."""
     import glob
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     try:
-        with open(os.path.join(here, "profiles", "traffic.json")) as f:
+        with open(os.path.join(here, "profiles", profile)) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
@@ -210,11 +216,24 @@ def bench_scattering(ndg, workloads, torch, cuda, leaf, n_energies=64, batch=32)
     info = plan.info()
     del plan
     torch.cuda.empty_cache()
+    # the dominant kernel against its roof (the N fold and the G^(0) rows sit
+    # below the 9.8 flop/B ridge: HBM)
+    dname = max(kern, key=lambda k: kern[k]["ms"])
+    dk = kern[dname]
+    t = dk["ms"] * 1e-3
+    if dk["flops"] / max(dk["bytes"], 1.0) >= PEAK_FP64 / PEAK_HBM:
+        roof = {"bound": "mfma", "achieved": dk["flops"] / t / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": dk["bytes"] / t / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof.update({"kernel": dname, "launches": dk["launches"], "avg_launch_us": dk["ms"] * 1e3 / dk["launches"],
+                 "algorithmic_bytes_per_launch": dk["bytes"] / dk["launches"],
+                 "traffic": measured_traffic(dname, "traffic_scattering.json")})
     return {"workload": "superlattice 1024x64 FD grid, n=65536, diagonal phonon self-energies on "
                         "every site (gamma0 5 meV), %d energies in [0,0.5] eV, FP64" % len(e),
             "energy_points_per_s": len(e) / (ms * 1e-3), "ms_per_energy": ms / len(e),
             "batch": batch, "scatter_bytes_per_energy": info["scatter_bytes_per_energy"],
-            "kernels": kernels, "status": list(status)}
+            "kernels": kernels, "roofline": roof, "status": list(status)}
 
 
 def main():
@@ -229,6 +248,9 @@ def main():
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false")
     ap.add_argument("--no-scattering", dest="scattering", action="store_false",
                     help="skip the phonon-scattering throughput figure")
+    ap.add_argument("--only-scattering", action="store_true",
+                    help="run only the phonon-scattering figure (leaf 20 unless --leaf) and print it "
+                         "as the JSON line (for profiling its kernels)")
     ap.add_argument("--no-extra", dest="extra", action="store_false",
                     help="skip the batched uneven-device and nanotube throughput figures")
     ap.add_argument("--cpu-sample", type=int, default=32,
@@ -247,6 +269,12 @@ def main():
     import torch
     import paper_1305_1070_amd as ndg
     from inputs import workloads
+
+    if args.only_scattering:
+        ndg.load()
+        print(json.dumps(bench_scattering(ndg, workloads, torch, torch.device("cuda:0"),
+                                          args.leaf if args.leaf > 0 else 20)), flush=True)
+        return
 
     n_transport, n_transverse = 1024, 64
     wl = workloads.superlattice(n_transport, n_transverse, n_energies=args.energies)
@@ -300,6 +328,7 @@ def main():
             a[k] += r[k]
     stats = list(stats.values())
     ms_per_step = ms_total / args.steps
+    _progress("fp64 superlattice: %.1f ms per step" % ms_per_step)
     value = ne / (ms_per_step / 1e3)
 
     # mixed-precision path on the same inputs (timed the same way, no profiling)
@@ -312,6 +341,7 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_mixed = ev0.elapsed_time(ev1) / args.steps
+    _progress("mixed superlattice: %.1f ms per step" % ms_mixed)
     growth = torch.zeros(ne, dtype=torch.float64, device=cuda)
     plan.solve(E, wl.eta, sig_r, sig_l, out=out, stream=stream, growth=growth)
     torch.cuda.synchronize()
@@ -348,12 +378,15 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         ms_adj = ev0.elapsed_time(ev1) / args.steps
+        _progress("forward + adjoint: %.1f ms per step" % ms_adj)
         adj = {"workload": "512x64 FD grid, smooth +-50 meV V, %d energies" % wa.energies.size,
                "fwd_plus_adjoint_ms_per_energy": ms_adj / wa.energies.size,
                "ms_per_step": ms_adj}
         del pa
 
     scat = bench_scattering(ndg, workloads, torch, cuda, args.leaf) if args.scattering else None
+    if scat:
+        _progress("scattering: %.0f energies/s" % scat["energy_points_per_s"])
 
     extra = None
     if args.extra:
@@ -395,6 +428,8 @@ def main():
     # CPU oracle on a bounded sample of the same workload, and parity there
     cpu = None
     parity = None
+    if args.extra:
+        _progress("batch and tube done")
     if args.cpu_sample > 0:
         idxs = list(np.linspace(0, ne - 1, args.cpu_sample).round().astype(int))
         rate, cores, cwall, res = cpu_baseline(idxs, (n_transport, n_transverse, ne))
