@@ -98,3 +98,30 @@ def density(dgl: np.ndarray, cweights: np.ndarray) -> np.ndarray:
     """n_i = sum_E c_E (-i G^<_ii(E)) (real part kept; the imaginary part is
     zero up to rounding because G^< is skew-Hermitian)."""
     return np.real(-1j * (np.asarray(cweights)[:, None] * dgl).sum(axis=0))
+
+
+def terminal_currents(h, v, energies, eta: float, contacts, sig_r, sig_less, sig_r_ph=None,
+                      sig_less_ph=None):
+    """Current spectral density into the device from each contact, per energy:
+
+      i_c(E) = Tr[Sigma^<_c G^>_cc - Sigma^>_c G^<_cc]
+
+    over contact c's block, with Sigma^> = Sigma^< + Sigma^r - Sigma^r+ and
+    G^> = G^< + G^r - G^r+ (in-scattering times empty states minus
+    out-scattering times filled states; the terminal current is
+    (e/h) times its energy integral).  Returns a real array [nE, ncontacts]."""
+    hd = dense_h(h)
+    energies = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+    out = np.zeros((energies.size, len(contacts)))
+    for k, e in enumerate(energies):
+        g, gl = full_greens(hd, v, e, eta, contacts, [s[k] for s in sig_r], [s[k] for s in sig_less],
+                            None if sig_r_ph is None else sig_r_ph[k],
+                            None if sig_less_ph is None else sig_less_ph[k])
+        gg = gl + g - g.conj().T
+        for c, sites in enumerate(contacts):
+            ix = np.ix_(sites, sites)
+            sl = sig_less[c][k]
+            sg = sl + sig_r[c][k] - sig_r[c][k].conj().T
+            val = np.trace(sl @ gg[ix] - sg @ gl[ix])
+            out[k, c] = val.real
+    return out

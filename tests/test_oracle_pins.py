@@ -311,6 +311,58 @@ def test_scba_preserves_equilibrium_and_converges_to_a_fixed_point():
 
 
 # ---------------------------------------------------------------------------
+# terminal currents
+# ---------------------------------------------------------------------------
+
+def test_terminal_current_is_landauer_and_conserved():
+    """Phonon-free, eta = 0 in the device: i_L(E) = T(E) (f_L - f_R) with
+    T = Tr[Gamma_L G_LR Gamma_R G_LR+] (the transmission, a different block
+    of G than the contact block the current formula reads), and i_L = -i_R."""
+    wl = workloads.small_grid(10, 8, n_energies=3, emin=1.2, emax=1.8, eta=0.0, mu=(1.5, 1.4), noise=0.05,
+                              seed=21)
+    dev = wl.device
+    e = wl.energies
+    sl_, sr_, ll_, lr_ = leads.contact_self_energies(dev, e, 1e-6, wl.mu, wl.kt)
+    cur = definition.terminal_currents(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_], [ll_, lr_])
+    L, R = dev.contacts
+    for k in range(len(e)):
+        g, _ = definition.full_greens(dev.scipy_h(), None, e[k], 0.0, dev.contacts, [sl_[k], sr_[k]],
+                                      [ll_[k], lr_[k]])
+        gam_l = 1j * (sl_[k] - sl_[k].conj().T)
+        gam_r = 1j * (sr_[k] - sr_[k].conj().T)
+        glr = g[np.ix_(L, R)]
+        t = np.trace(gam_l @ glr @ gam_r @ glr.conj().T).real
+        df = leads.fermi(e[k], wl.mu[0], wl.kt) - leads.fermi(e[k], wl.mu[1], wl.kt)
+        assert abs(cur[k, 0] - t * df) <= 1e-11 * abs(t * df)
+        assert abs(cur[k, 0] + cur[k, 1]) <= 1e-11 * abs(cur[k, 0])
+        assert t > 0.1   # energies in the first band: an open channel
+
+
+def test_terminal_current_conserved_by_converged_elastic_scattering():
+    """Local elastic scattering at the Born fixed point exchanges no current
+    with the phonons at any energy (i D (G^<_kk G^>_kk - G^>_kk G^<_kk) = 0
+    per site), so i_L + i_R = 0 still holds at eta = 0, while the current
+    itself differs from the ballistic one."""
+    dev = devices.fd2d(10, 8)
+    e = np.array([1.3, 1.5, 1.7])
+    mu = (1.5, 1.4)
+    sl_, sr_, ll_, lr_ = leads.contact_self_energies(dev, e, 1e-6, mu, 0.025)
+    *_, spr, spl, it, res = scba.scba(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_], [ll_, lr_],
+                                      0.2, 0.7, 1e-13, 300)
+    assert res < 1e-13
+    cur = definition.terminal_currents(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_], [ll_, lr_],
+                                       spr, spl)
+    bal = definition.terminal_currents(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_], [ll_, lr_])
+    assert np.all(np.abs(cur[:, 0] + cur[:, 1]) <= 1e-9 * np.abs(cur[:, 0]))
+    assert np.max(np.abs(cur[:, 0] - bal[:, 0]) / np.abs(bal[:, 0])) > 1e-2
+    # a fixed, non-self-consistent phonon self-energy does exchange current
+    pr, pl = phonons.diagonal_self_energies(dev, e, gamma0=2e-2, mu=(1.6, 1.3), seed=4)
+    cur2 = definition.terminal_currents(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_], [ll_, lr_],
+                                        pr, pl)
+    assert np.max(np.abs(cur2[:, 0] + cur2[:, 1]) / np.abs(cur2[:, 0])) > 1e-3
+
+
+# ---------------------------------------------------------------------------
 # lead self-energies (inputs): two independent constructions must agree
 # ---------------------------------------------------------------------------
 
