@@ -212,8 +212,17 @@ ndg_status ndg_solve(ndg_plan* plan, int32_t nE, const double* E, double eta, co
  *                       for a physical model, any complex value accepted),
  *                       or NULL for none.  Non-NULL needs
  *                       ndg_plan_enable_scattering first.
- * With both NULL it equals ndg_solve in FP64.  Runs on `stream` alone (no
- * side streams).  Errors: as ndg_solve; NDG_EINVAL if sig_less_ph is given
+ *   current[nE][ncontacts]   device output or NULL: per energy and contact the
+ *                       current spectral density into the device,
+ *                       i_c(E) = Tr[Sigma^<_c G^>_cc - Sigma^>_c G^<_cc] over the
+ *                       contact block (Sigma^> = Sigma^< + Sigma^r - Sigma^r+,
+ *                       G^> = G^< + G^r - G^r+); the terminal current is e/h
+ *                       times its energy integral.  The contact block of G^r
+ *                       and G^< is read from the clusters' stored rows, which
+ *                       hold every pair of sites of one contact (its dense
+ *                       self-energy couples them).
+ * With both phonon pointers NULL it equals ndg_solve in FP64 (plus the
+ * currents).  Runs on `stream` alone (no side streams).  Errors: as ndg_solve; NDG_EINVAL if sig_less_ph is given
  * and scattering was not enabled.
  */
 ndg_status ndg_plan_enable_scattering(ndg_plan* plan);
@@ -221,7 +230,7 @@ ndg_status ndg_solve_scattering(ndg_plan* plan, int32_t nE, const double* E, dou
                                 const double* V, const ndg_c128* const* sig_r,
                                 const ndg_c128* const* sig_less, const ndg_c128* sig_r_ph,
                                 const ndg_c128* sig_less_ph, ndg_c128* diag_gr, ndg_c128* diag_gless,
-                                ndg_c128* diag_ggreater, double* growth, void* stream);
+                                ndg_c128* diag_ggreater, double* growth, double* current, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Self-consistent Born loop for local elastic phonon scattering.
@@ -238,8 +247,8 @@ ndg_status ndg_solve_scattering(ndg_plan* plan, int32_t nE, const double* E, dou
  *   sig_r_ph, sig_less_ph   device [nE][n] (caller's site order): the
  *                     starting self-energies on entry (zero for a cold
  *                     start), the last update on return
- *   diag_*            device outputs of the last solve (diag_ggreater may
- *                     be NULL)
+ *   diag_*, current   device outputs of the last solve (diag_ggreater and
+ *                     current may be NULL; current as in ndg_solve_scattering)
  *   iterations, residual   host outputs (may be NULL): solves run, last
  *                     residual
  * Needs ndg_plan_enable_scattering.  Synchronizes `stream` once per
@@ -249,8 +258,8 @@ ndg_status ndg_solve_scattering(ndg_plan* plan, int32_t nE, const double* E, dou
 ndg_status ndg_scba(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
                     const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, double d0, double mix,
                     double tol, int32_t max_iter, ndg_c128* sig_r_ph, ndg_c128* sig_less_ph,
-                    ndg_c128* diag_gr, ndg_c128* diag_gless, ndg_c128* diag_ggreater, int32_t* iterations,
-                    double* residual, void* stream);
+                    ndg_c128* diag_gr, ndg_c128* diag_gless, ndg_c128* diag_ggreater, double* current,
+                    int32_t* iterations, double* residual, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Electron density and its gradient with respect to the on-site potential.

@@ -106,16 +106,17 @@ def ndg_plan_enable_scattering(plan):
 
 
 def ndg_solve_scattering(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, sr_ph_ptr,
-                         sl_ph_ptr, dgr_ptr, dgl_ptr, dgg_ptr, growth_ptr, stream_ptr):
+                         sl_ph_ptr, dgr_ptr, dgl_ptr, dgg_ptr, growth_ptr, current_ptr, stream_ptr):
     nc = len(sig_r_ptrs)
     sr = (C.c_void_p * max(1, nc))(*sig_r_ptrs)
     sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
     _lib.check(load().ndg_solve_scattering(plan, ne, e_ptr, eta, v_ptr, sr, sl, sr_ph_ptr, sl_ph_ptr,
-                                           dgr_ptr, dgl_ptr, dgg_ptr, growth_ptr, stream_ptr))
+                                           dgr_ptr, dgl_ptr, dgg_ptr, growth_ptr, current_ptr,
+                                           stream_ptr))
 
 
 def ndg_scba(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, d0, mix, tol, max_iter,
-             sr_ph_ptr, sl_ph_ptr, dgr_ptr, dgl_ptr, dgg_ptr, stream_ptr):
+             sr_ph_ptr, sl_ph_ptr, dgr_ptr, dgl_ptr, dgg_ptr, current_ptr, stream_ptr):
     """Returns (iterations, residual)."""
     nc = len(sig_r_ptrs)
     sr = (C.c_void_p * max(1, nc))(*sig_r_ptrs)
@@ -123,8 +124,8 @@ def ndg_scba(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, d0, mix, to
     it = C.c_int32()
     res = C.c_double()
     _lib.check(load().ndg_scba(plan, ne, e_ptr, eta, v_ptr, sr, sl, d0, mix, tol, max_iter, sr_ph_ptr,
-                               sl_ph_ptr, dgr_ptr, dgl_ptr, dgg_ptr, C.byref(it), C.byref(res),
-                               stream_ptr))
+                               sl_ph_ptr, dgr_ptr, dgl_ptr, dgg_ptr, current_ptr, C.byref(it),
+                               C.byref(res), stream_ptr))
     return it.value, res.value
 
 
@@ -336,10 +337,12 @@ class Plan:
         self._info = ndg_plan_info(self.handle)
 
     def scba(self, E, eta, sig_r, sig_less, d0, mix=0.7, tol=1e-10, max_iter=100, sig_r_ph=None,
-             sig_less_ph=None, V=None, out=None, stream=None):
+             sig_less_ph=None, V=None, out=None, stream=None, current=None):
         """Self-consistent Born loop (local elastic scattering, ndg_scba).
         sig_r_ph / sig_less_ph: starting complex128 [nE, n] tensors, updated
-        in place (zeros when None).  Returns (diag G^r, diag G^<, diag G^>,
+        in place (zeros when None).  current: optional float64
+        [nE, ncontacts] tensor receiving the terminal current spectral
+        density of the last solve.  Returns (diag G^r, diag G^<, diag G^>,
         sig_r_ph, sig_less_ph, iterations, residual)."""
         import torch
         n, ne, dev = self._check_inputs(E, sig_r, sig_less, V)
@@ -361,14 +364,28 @@ class Plan:
                            [t.data_ptr() for t in sig_r], [t.data_ptr() for t in sig_less],
                            float(d0), float(mix), float(tol), int(max_iter), ph[0].data_ptr(),
                            ph[1].data_ptr(), gr.data_ptr(), gl.data_ptr(),
-                           gg.data_ptr() if gg is not None else None, C.c_void_p(st.cuda_stream))
+                           gg.data_ptr() if gg is not None else None,
+                           self._current_ptr(current, ne, dev), C.c_void_p(st.cuda_stream))
         return gr, gl, gg, ph[0], ph[1], it, res
 
+    def _current_ptr(self, current, ne, dev):
+        import torch
+        if current is None:
+            return None
+        nc = len(self.sym.contact_sizes)
+        if (current.dtype != torch.float64 or tuple(current.shape) != (ne, nc) or current.device != dev
+                or not current.is_contiguous()):
+            raise ValueError("current must be a contiguous float64 [nE, ncontacts] tensor on the "
+                             "plan's device")
+        return current.data_ptr()
+
     def solve_scattering(self, E, eta, sig_r, sig_less, sig_r_ph=None, sig_less_ph=None, V=None,
-                         out=None, stream=None, growth=None):
+                         out=None, stream=None, growth=None, current=None):
         """solve() in FP64 with diagonal phonon self-energies sig_r_ph,
         sig_less_ph: complex128 [nE, n] tensors on the plan's GPU (caller's
-        site order) or None.  sig_less_ph needs enable_scattering() first."""
+        site order) or None.  sig_less_ph needs enable_scattering() first.
+        current: optional float64 [nE, ncontacts] tensor receiving the
+        terminal current spectral density Tr[S^<_c G^>_cc - S^>_c G^<_cc]."""
         import torch
         n, ne, dev = self._check_inputs(E, sig_r, sig_less, V)
         for t in (sig_r_ph, sig_less_ph):
@@ -387,7 +404,7 @@ class Plan:
                              sig_less_ph.data_ptr() if sig_less_ph is not None else None,
                              gr.data_ptr(), gl.data_ptr(), gg.data_ptr() if gg is not None else None,
                              growth.data_ptr() if growth is not None else None,
-                             C.c_void_p(st.cuda_stream))
+                             self._current_ptr(current, ne, dev), C.c_void_p(st.cuda_stream))
         return gr, gl, gg
 
     def density_vjp(self, E, eta, sig_r, sig_less, cE, nbar, V=None, out=None, prec=NDG_FP64,

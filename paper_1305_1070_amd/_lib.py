@@ -86,9 +86,9 @@ SIGNATURES = {
                                   P, P, C.c_int, P]),
     "ndg_plan_enable_scattering": (C.c_int, [P]),
     "ndg_solve_scattering": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P),
-                                       P, P, P, P, P, P, P]),
+                                       P, P, P, P, P, P, P, P]),
     "ndg_scba": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P), C.c_double,
-                           C.c_double, C.c_double, C.c_int32, P, P, P, P, P, I32P, F64P, P]),
+                           C.c_double, C.c_double, C.c_int32, P, P, P, P, P, P, I32P, F64P, P]),
     "ndg_plan_set_profiling": (C.c_int, [P, C.c_int32]),
     "ndg_plan_profile": (C.c_int, [P, C.c_int32, C.POINTER(KernelStat), C.POINTER(C.c_int32)]),
     "ndg_batch_create": (C.c_int, [C.c_int32, C.POINTER(P), C.POINTER(P)]),

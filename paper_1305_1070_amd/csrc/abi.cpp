@@ -156,7 +156,7 @@ ndg_status ndg_solve_scattering(ndg_plan* plan, int32_t nE, const double* E, dou
                                 const double* V, const ndg_c128* const* sig_r,
                                 const ndg_c128* const* sig_less, const ndg_c128* sig_r_ph,
                                 const ndg_c128* sig_less_ph, ndg_c128* diag_gr, ndg_c128* diag_gless,
-                                ndg_c128* diag_ggreater, double* growth, void* stream) {
+                                ndg_c128* diag_ggreater, double* growth, double* current, void* stream) {
   if (!plan) { set_error("ndg_solve_scattering: NULL plan"); return NDG_EINVAL; }
   if (nE < 0 || !(eta >= 0)) { set_error("ndg_solve_scattering: nE < 0 or eta < 0"); return NDG_EINVAL; }
   if (nE == 0) return NDG_OK;
@@ -166,14 +166,14 @@ ndg_status ndg_solve_scattering(ndg_plan* plan, int32_t nE, const double* E, dou
   }
   return (ndg_status)ndg::plan_run(plan, ndg::kRunSolve, nE, E, eta, V, sig_r, sig_less, diag_gr,
                                    diag_gless, diag_ggreater, growth, nullptr, nullptr, nullptr, nullptr,
-                                   (int)NDG_FP64, stream, nullptr, sig_r_ph, sig_less_ph);
+                                   (int)NDG_FP64, stream, nullptr, sig_r_ph, sig_less_ph, current);
 }
 
 ndg_status ndg_scba(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
                     const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, double d0, double mix,
                     double tol, int32_t max_iter, ndg_c128* sig_r_ph, ndg_c128* sig_less_ph,
-                    ndg_c128* diag_gr, ndg_c128* diag_gless, ndg_c128* diag_ggreater, int32_t* iterations,
-                    double* residual, void* stream) {
+                    ndg_c128* diag_gr, ndg_c128* diag_gless, ndg_c128* diag_ggreater, double* current,
+                    int32_t* iterations, double* residual, void* stream) {
   if (!plan) { set_error("ndg_scba: NULL plan"); return NDG_EINVAL; }
   if (nE < 0 || !(eta >= 0) || !(d0 >= 0) || !(mix > 0 && mix <= 1) || !(tol >= 0) || max_iter < 1) {
     set_error("ndg_scba: nE < 0, eta < 0, d0 < 0, mix outside (0, 1], tol < 0 or max_iter < 1");
@@ -189,8 +189,8 @@ ndg_status ndg_scba(ndg_plan* plan, int32_t nE, const double* E, double eta, con
     return NDG_EINVAL;
   }
   return (ndg_status)ndg::plan_scba(plan, nE, E, eta, V, sig_r, sig_less, d0, mix, tol, max_iter, sig_r_ph,
-                                    sig_less_ph, diag_gr, diag_gless, diag_ggreater, iterations, residual,
-                                    stream);
+                                    sig_less_ph, diag_gr, diag_gless, diag_ggreater, current, iterations,
+                                    residual, stream);
 }
 
 static ndg_status check_common(const char* who, ndg_plan* plan, int32_t nE, const double* E, double eta,

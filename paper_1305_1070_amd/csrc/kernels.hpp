@@ -165,6 +165,9 @@ void launch_anc_p0(const Ctx& c, const ScatCtx& x, const int32_t* cls, int ncl, 
 // S <- (1 - mix) S + mix S' for Sigma^r_ph and Sigma^<_ph; out[0] = max
 // |S' - S|, out[1] = max |S'| (part: kScbaBlocks x 2 doubles of scratch)
 constexpr int kScbaBlocks = 1024;
+// terminal current spectral density per contact and energy of the batch,
+// cur[(e0 + e) * ncontacts + c] (caddr: see the plan's contact tables)
+void launch_current(const Ctx& c, const int32_t* caddr, int nb, double* cur, hipStream_t st);
 void launch_scba_mix(const double2* dgr, const double2* dgl, double2* sr, double2* sl, int64_t count,
                      double d0, double mix, double* part, double* out, hipStream_t st);
 

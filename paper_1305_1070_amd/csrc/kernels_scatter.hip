@@ -279,6 +279,49 @@ __global__ void __launch_bounds__(256) k_scba_max(const double* part, int nblk, 
   }
 }
 
+// Terminal current spectral density, one block per (contact, energy):
+// i_c = Tr[Sigma^<_c G^>_cc - Sigma^>_c G^<_cc] = sum_ab Sigma^<(a,b) G^>(b,a)
+// - Sigma^>(a,b) G^<(b,a).  G^r(b,a) and G^<(b,a) come from the stored rows
+// (caddr entry (b, a); bit 31: stored as the transposed entry, G^r
+// symmetric, G^< anti-Hermitian); G^> = G^< + G^r - G^r+ with G^r+(b,a) =
+// conj(G^r(a,b)) = conj(G^r(b,a)).  Block sum in a fixed order.
+__global__ void __launch_bounds__(256) k_current(Ctx c, const int32_t* caddr, double* cur) {
+  __shared__ double red[256];
+  const int cc = blockIdx.x, e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
+  const int nc = sel2(c.nc, cc);
+  const int32_t* ca = caddr + (cc ? c.nc[0] * c.nc[0] : 0);
+  const double2* S = slab(c, e);
+  const double2* sl = sel2(c.sig_l, cc) + (int64_t)(eb + e) * nc * nc;
+  const double2* sr = sel2(c.sig_r, cc) + (int64_t)(eb + e) * nc * nc;
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < nc * nc; q += 256) {
+    const int a = q / nc, b = q - a * nc;
+    const int32_t code = ca[b * nc + a];
+    const int64_t off = code & 0x7fffffff;
+    const double2 gr = S[off];
+    double2 gl = S[off + c.pdelta];
+    if (code < 0) gl = make_double2(-gl.x, gl.y);
+    const double2 gg = make_double2(gl.x, gl.y + 2.0 * gr.y);           // G^< + G^r - conj(G^r)
+    const double2 s_l = sl[q], s_r = sr[q], s_rt = sr[b * nc + a];
+    const double2 s_g = make_double2(s_l.x + s_r.x - s_rt.x, s_l.y + s_r.y + s_rt.y);  // Sigma^>(a,b)
+    acc += (s_l.x * gg.x - s_l.y * gg.y) - (s_g.x * gl.x - s_g.y * gl.y);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cur[(int64_t)(eb + e) * c.ncontacts + cc] = red[0];
+}
+
+void launch_current(const Ctx& c, const int32_t* caddr, int nb, double* cur, hipStream_t st) {
+  if (c.ncontacts <= 0 || nb <= 0) return;
+  hipLaunchKernelGGL(k_current, dim3(c.ncontacts, nb), dim3(256), 0, st, c, caddr, cur);
+}
+
 void launch_scba_mix(const double2* dgr, const double2* dgl, double2* sr, double2* sl, int64_t count,
                      double d0, double mix, double* part, double* out, hipStream_t st) {
   const int nblk = (int)std::min<int64_t>(kScbaBlocks, std::max<int64_t>(1, (count + 255) / 256));

@@ -202,8 +202,9 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
   const int lb = b | 1;           // odd row stride: lanes reading down a column hit distinct banks
   const int t = threadIdx.x;
   // with phonon sources every cluster's full rows [X_ii, X_{i,B}] are read
-  // (by the all-ancestor extraction) and every cluster has a G^< source
-  const bool inner = c.scat || c.kids_ptr[cl + 1] > c.kids_ptr[cl];
+  // (by the all-ancestor extraction) and every cluster has a G^< source; a
+  // contact's clusters keep full rows for the terminal currents
+  const bool inner = c.scat || d.chain_mask != 0 || c.kids_ptr[cl + 1] > c.kids_ptr[cl];
   const bool chain = c.scat || d.chain_mask != 0;
   const double2* Ainv = S + d.o_ainv;
   double2* Psl = sm;              // s x b, stride lb

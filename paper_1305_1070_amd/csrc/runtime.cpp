@@ -48,6 +48,7 @@ struct ndg_plan {
   double* d_hfront = nullptr;
   int32_t *d_smap = nullptr, *d_pinv = nullptr;
   int32_t* d_gaddr = nullptr;
+  int32_t* d_caddr = nullptr;  // contact blocks' stored-entry offsets (terminal currents)
   ndg::SiteDiag* d_sdiag = nullptr;
   int32_t* d_levels = nullptr;       // clusters by height
   ndg::ColItem* d_colitems = nullptr;
@@ -203,7 +204,7 @@ void free_plan(ndg_plan* p) {
                   p->d_srow,      p->d_scol,     p->d_scid,       p->d_sflat,      p->d_hfront,
                   p->d_smap,      p->d_pinv,     p->d_gaddr,      p->d_sdiag,      p->d_sd,
                   p->d_atab,      p->d_bpos,     p->d_lk,         p->d_umap,       p->d_ancitems,
-                  p->d_anccls,    p->d_sws,      p->d_scba};
+                  p->d_anccls,    p->d_sws,      p->d_scba,       p->d_caddr};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& r : p->recs) {
@@ -418,6 +419,28 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
     free_plan(p);
     return NDG_EINVAL;
   }
+  // slab offset of G^r(x, y) for coupled points x, y: the stored rows of the
+  // lower owning cluster, bit 31 set when stored as G^r(y, x); false if y is
+  // missing from that cluster's front
+  auto stored_addr = [&](int32_t x0, int32_t y0, int32_t& out) {
+    const int ou = sy.owner[x0], ov = sy.owner[y0];
+    const bool direct = ou <= ov;  // post-order: the lower cluster has the smaller id
+    const int a = direct ? ou : ov;
+    const int32_t x = direct ? x0 : y0, y = direct ? y0 : x0;
+    int pos;
+    if (sy.owner[y] == a) pos = y - sy.cl_off[a];
+    else {
+      const int32_t* Ba0 = sy.bidx.data() + sy.bptr[a];
+      const int32_t* Ba1 = sy.bidx.data() + sy.bptr[a + 1];
+      const int32_t* it = std::lower_bound(Ba0, Ba1, y);
+      if (it == Ba1 || *it != y) return false;
+      pos = sy.s(a) + (int)(it - Ba0);
+    }
+    const ClusterDesc& da = p->hdesc[a];
+    const int64_t o = da.o_fg + (int64_t)(x - sy.cl_off[a]) * da.f + pos;
+    out = (int32_t)o | (direct ? 0 : (int32_t)0x80000000);
+    return true;
+  };
   for (int k = 0; k < nc; ++k) {
     ClusterDesc& d = p->hdesc[k];
     d.o_gaddr = (int64_t)gaddr.size();
@@ -427,28 +450,28 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
     gaddr.resize(gaddr.size() + (size_t)b * b);
     int32_t* ga = gaddr.data() + d.o_gaddr;
     for (int u = 0; u < b; ++u)
-      for (int v = 0; v < b; ++v) {
-        const int ou = sy.owner[B[u]], ov = sy.owner[B[v]];
-        const bool direct = ou <= ov;  // post-order: the lower cluster has the smaller id
-        const int a = direct ? ou : ov;
-        const int32_t x = direct ? B[u] : B[v], y = direct ? B[v] : B[u];
-        int pos;
-        if (sy.owner[y] == a) pos = y - sy.cl_off[a];
-        else {
-          const int32_t* Ba0 = sy.bidx.data() + sy.bptr[a];
-          const int32_t* Ba1 = sy.bidx.data() + sy.bptr[a + 1];
-          const int32_t* it = std::lower_bound(Ba0, Ba1, y);
-          if (it == Ba1 || *it != y) {
-            set_error("internal: boundary entry missing from an ancestor's front");
-            free_plan(p);
-            return NDG_EINVAL;
-          }
-          pos = sy.s(a) + (int)(it - Ba0);
+      for (int v = 0; v < b; ++v)
+        if (!stored_addr(B[u], B[v], ga[(int64_t)u * b + v])) {
+          set_error("internal: boundary entry missing from an ancestor's front");
+          free_plan(p);
+          return NDG_EINVAL;
         }
-        const ClusterDesc& da = p->hdesc[a];
-        const int64_t o = da.o_fg + (int64_t)(x - sy.cl_off[a]) * da.f + pos;
-        ga[(int64_t)u * b + v] = (int32_t)o | (direct ? 0 : (int32_t)0x80000000);
-      }
+  }
+  // the contact blocks (terminal currents): entry (a, b) of contact c at
+  // caddr[off_c + a nc + b], contact sites in the caller's order (every pair
+  // of sites of one contact is coupled through its dense self-energy)
+  std::vector<int32_t> caddr;
+  for (int cc = 0; cc < p->ncontacts; ++cc) {
+    const std::vector<int32_t>& cp = sy.contact_pos[cc];
+    const size_t m = cp.size(), o0 = caddr.size();
+    caddr.resize(o0 + m * m);
+    for (size_t a = 0; a < m; ++a)
+      for (size_t b = 0; b < m; ++b)
+        if (!stored_addr(cp[a], cp[b], caddr[o0 + a * m + b])) {
+          set_error("internal: contact entry missing from its clusters' fronts");
+          free_plan(p);
+          return NDG_EINVAL;
+        }
   }
   // the assembly relies on the parent's points leading each sorted B
   for (int k = 0; k < nc; ++k) {
@@ -489,6 +512,7 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   rc = rc ? rc : upload(&p->d_smap, smap.data(), smap.size());
   rc = rc ? rc : upload(&p->d_pinv, pinv.data(), pinv.size());
   rc = rc ? rc : upload(&p->d_gaddr, gaddr.data(), gaddr.size());
+  rc = rc ? rc : upload(&p->d_caddr, caddr.data(), caddr.size());
   rc = rc ? rc : upload(&p->d_sdiag, sdiag.data(), sdiag.size());
   rc = rc ? rc : upload(&p->d_hrow, sy.hrow.data(), sy.hrow.size());
   rc = rc ? rc : upload(&p->d_hcol, sy.hcol.data(), sy.hcol.size());
@@ -765,7 +789,8 @@ int plan_solve(ndg_plan* p, int nE, const double* E, double eta, const double* V
 int plan_scba(ndg_plan* p, int nE, const double* E, double eta, const double* V,
               const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, double d0, double mix,
               double tol, int max_iter, ndg_c128* sig_r_ph, ndg_c128* sig_less_ph, ndg_c128* dgr,
-              ndg_c128* dgl, ndg_c128* dgg, int32_t* iterations, double* residual, void* stream) {
+              ndg_c128* dgl, ndg_c128* dgg, double* current, int32_t* iterations, double* residual,
+              void* stream) {
   if (!p->d_sws) {
     set_error("ndg_scba: call ndg_plan_enable_scattering first");
     return NDG_EINVAL;
@@ -775,7 +800,7 @@ int plan_scba(ndg_plan* p, int nE, const double* E, double eta, const double* V,
   double res = 0.0, hm[2] = {0.0, 0.0};
   while (it < max_iter) {
     int rc = plan_run(p, kRunSolve, nE, E, eta, V, sig_r, sig_less, dgr, dgl, dgg, nullptr, nullptr, nullptr,
-                      nullptr, nullptr, NDG_FP64, stream, nullptr, sig_r_ph, sig_less_ph);
+                      nullptr, nullptr, NDG_FP64, stream, nullptr, sig_r_ph, sig_less_ph, current);
     if (rc) return rc;
     ++it;
     launch_scba_mix(reinterpret_cast<const double2*>(dgr), reinterpret_cast<const double2*>(dgl),
@@ -808,7 +833,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
              const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
              ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
              const double* nbar, double* vbar, int prec, void* stream, const int32_t* e0p,
-             const ndg_c128* sig_r_ph, const ndg_c128* sig_less_ph) {
+             const ndg_c128* sig_r_ph, const ndg_c128* sig_less_ph, double* current) {
   const bool scat = sig_less_ph != nullptr;
   if ((scat || sig_r_ph) && (mode != kRunSolve || e0p || prec != NDG_FP64)) {
     set_error("internal: phonon self-energies are for FP64 solves only");
@@ -1023,6 +1048,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         launch_epilogue(c, nb, reinterpret_cast<double2*>(dgr), reinterpret_cast<double2*>(dgl),
                         reinterpret_cast<double2*>(dgg), st);
       });
+      if (current) launch_current(c, p->d_caddr, nb, current, st);
       p->last_batch = nb;
       continue;
     }
@@ -1078,12 +1104,13 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
       (void)hipEventRecord(p->ev_join, sp);
       (void)hipStreamWaitEvent(st, p->ev_join, 0);
     }
-    if (mode == kRunSolve)
+    if (mode == kRunSolve) {
       timed(K_EPILOGUE, 0, nb, [&] {
         launch_epilogue(c, nb, reinterpret_cast<double2*>(dgr), reinterpret_cast<double2*>(dgl),
                         reinterpret_cast<double2*>(dgg), st);
       });
-    else
+      if (current) launch_current(c, p->d_caddr, nb, current, st);
+    } else
       launch_density(c, nb, cE, density, st);
     p->last_batch = nb;
   }

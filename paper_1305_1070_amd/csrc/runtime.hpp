@@ -29,7 +29,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
              ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
              const double* nbar, double* vbar, int prec, void* stream,
              const int32_t* e0p = nullptr, const ndg_c128* sig_r_ph = nullptr,
-             const ndg_c128* sig_less_ph = nullptr);
+             const ndg_c128* sig_less_ph = nullptr, double* current = nullptr);
 // One batch of energies starting at the device-resident index *e0p (for a
 // graph replayed over the energy range): the launches of a single batch of
 // max_batch energies, slots at or beyond nE skipped; growth is not cleared.
@@ -43,7 +43,8 @@ int plan_enable_scattering(ndg_plan* plan);
 int plan_scba(ndg_plan* p, int nE, const double* E, double eta, const double* V,
               const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, double d0, double mix,
               double tol, int max_iter, ndg_c128* sig_r_ph, ndg_c128* sig_less_ph, ndg_c128* dgr,
-              ndg_c128* dgl, ndg_c128* dgg, int32_t* iterations, double* residual, void* stream);
+              ndg_c128* dgl, ndg_c128* dgg, double* current, int32_t* iterations, double* residual,
+              void* stream);
 int plan_ncontacts(const ndg_plan* plan);
 int plan_device(const ndg_plan* plan);
 bool plan_profiling(const ndg_plan* plan);

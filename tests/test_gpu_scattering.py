@@ -224,3 +224,97 @@ def test_scba_superlattice_equilibrium(lib):
     f = leads.fermi(e, mu[0], wl.kt)[:, None]
     assert np.max(rel_err(gl, -f * (gr - gr.conj()))) < 1e-9
     assert np.max(rel_err(spl, -f * (spr - spr.conj()))) < 1e-9
+
+
+def _currents(ndg, dev, e, eta, sig, pr, pl, leaf_max=0, enable=True):
+    import torch
+    sl_, sr_, ll_, lr_ = sig
+    sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, leaf_max=leaf_max)
+    plan = ndg.Plan(sym, max_batch=64)
+    if enable:
+        plan.enable_scattering()
+    cuda = torch.device("cuda:0")
+    E = torch.tensor(np.asarray(e, np.float64), device=cuda)
+    sr = [torch.from_numpy(np.ascontiguousarray(a)).to(cuda) for a in (sl_, sr_)]
+    sl = [torch.from_numpy(np.ascontiguousarray(a)).to(cuda) for a in (ll_, lr_)]
+    prt = None if pr is None else torch.from_numpy(np.ascontiguousarray(pr)).to(cuda)
+    plt = None if pl is None else torch.from_numpy(np.ascontiguousarray(pl)).to(cuda)
+    cur = torch.full((len(e), 2), float("nan"), dtype=torch.float64, device=cuda)
+    plan.solve_scattering(E, eta, sr, sl, prt, plt, current=cur)
+    torch.cuda.synchronize()
+    assert plan.status()[0] == 0
+    return cur.cpu().numpy()
+
+
+@pytest.mark.parametrize("phonon", [False, True])
+def test_terminal_currents_match_oracle(lib, phonon):
+    """Current spectral density per contact against the oracle's trace
+    formula, ballistic (where it is the Landauer current) and with fixed
+    phonon self-energies on every site."""
+    from oracle import definition
+    dev = devices.fd2d(16, 8)
+    e = np.linspace(1.2, 1.8, 6)
+    mu = (1.55, 1.35)
+    sig = leads.contact_self_energies(dev, e, 1e-6, mu, 0.025)
+    sl_, sr_, ll_, lr_ = sig
+    pr, pl = (phonons.diagonal_self_energies(dev, e, gamma0=2e-2, mu=mu, seed=8) if phonon
+              else (None, None))
+    _say("currents 16x8 phonon=%s" % phonon)
+    cur = _currents(lib, dev, e, 1e-6, sig, pr, pl, leaf_max=8, enable=phonon)
+    ref = definition.terminal_currents(dev.scipy_h(), None, e, 1e-6, dev.contacts, [sl_, sr_], [ll_, lr_],
+                                       pr, pl)
+    err = np.max(np.abs(cur - ref), axis=1) / np.max(np.abs(ref), axis=1)
+    _say("  currents %s\n  max rel err %.2e" % (np.array2string(cur[:, 0], precision=4), err.max()))
+    assert np.all(err < 1e-10)
+
+
+def test_terminal_currents_wide_contacts(lib):
+    """80-site contacts span a parent-child chain of clusters: the contact
+    block is read across the chain's stored rows."""
+    from oracle import definition
+    wl = workloads.small_grid(10, 80, n_energies=3, emin=0.05, emax=0.3, eta=1e-3, noise=0.03, seed=9)
+    e = wl.energies
+    sig = wl.self_energies(e)
+    sl_, sr_, ll_, lr_ = sig
+    _say("currents 10x80 (wide contacts)")
+    cur = _currents(lib, wl.device, e, wl.eta, sig, None, None, enable=False)
+    ref = definition.terminal_currents(wl.device.scipy_h(), None, e, wl.eta, wl.device.contacts,
+                                       [sl_, sr_], [ll_, lr_])
+    err = np.max(np.abs(cur - ref), axis=1) / np.max(np.abs(ref), axis=1)
+    _say("  max rel err %.2e" % err.max())
+    assert np.all(err < 1e-10)
+
+
+def test_scba_conserves_current_superlattice(lib):
+    """Superlattice 256 x 64 under bias, eta = 0 in the device: at the Born
+    fixed point of local elastic scattering no current goes into the
+    phonons, so i_L + i_R = 0 per energy, while the current differs from the
+    ballistic one."""
+    import torch
+    wl = workloads.superlattice(n_transport=256, n_energies=4)
+    dev = wl.device
+    e = np.array([0.06, 0.09, 0.12, 0.15])
+    sig = leads.contact_self_energies(dev, e, 1e-6, wl.mu, wl.kt)
+    sl_, sr_, ll_, lr_ = sig
+    sym = lib.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, leaf_max=20)
+    plan = lib.Plan(sym, max_batch=4)
+    plan.enable_scattering()
+    cuda = torch.device("cuda:0")
+    E = torch.tensor(e, device=cuda)
+    sr = [torch.from_numpy(np.ascontiguousarray(a)).to(cuda) for a in (sl_, sr_)]
+    sl = [torch.from_numpy(np.ascontiguousarray(a)).to(cuda) for a in (ll_, lr_)]
+    cur = torch.zeros((len(e), 2), dtype=torch.float64, device=cuda)
+    _say("scba superlattice 256x64 under bias")
+    *_, it, res = plan.scba(E, 0.0, sr, sl, 0.05, 0.8, 1e-9, 100, current=cur)
+    bal = torch.zeros_like(cur)
+    plan.solve_scattering(E, 0.0, sr, sl, current=bal)
+    torch.cuda.synchronize()
+    c, b = cur.cpu().numpy(), bal.cpu().numpy()
+    _say("  iterations %d residual %.2e\n  i_L %s\n  i_R %s\n  ballistic %s" % (
+        it, res, np.array2string(c[:, 0], precision=5), np.array2string(c[:, 1], precision=5),
+        np.array2string(b[:, 0], precision=5)))
+    assert res < 1e-9
+    # against the largest current (at 0.06 eV the current sits in a minigap)
+    assert np.max(np.abs(c[:, 0] + c[:, 1])) <= 1e-7 * np.max(np.abs(c[:, 0]))
+    assert np.max(np.abs(b[:, 0] + b[:, 1])) <= 1e-7 * np.max(np.abs(b[:, 0]))
+    assert np.max(np.abs(c[:, 0] - b[:, 0])) > 1e-2 * np.max(np.abs(b[:, 0]))
