@@ -201,6 +201,81 @@ def zigzag_tube(n_cells: int, n: int = 10, t: float = -2.7, disorder: float = 0.
 
 
 # ---------------------------------------------------------------------------
+# armchair graphene nanoribbon, nearest-neighbour tight binding (the
+# honeycomb stencil: each atom and its three neighbours)
+# ---------------------------------------------------------------------------
+
+def _armchair_cells(n_cells: int, n_lines: int):
+    """Atom positions (nm) of an armchair ribbon of n_lines dimer lines,
+    n_cells translational cells of length 3 a_cc along x (transport), and
+    its bonds (pairs at distance a_cc).  Dimer line m sits at y = m sqrt(3)/2
+    a_cc; even lines hold atoms at x = 0 and a_cc of each cell, odd lines at
+    1.5 and 2.5 a_cc.  Cell c, line m, atom q -> c * 2 n_lines + 2 m + q."""
+    a = A_CC_NM
+    pos = []
+    for c in range(n_cells):
+        for m in range(n_lines):
+            x0 = 3 * a * c + (0.0 if m % 2 == 0 else 1.5 * a)
+            for q in range(2):
+                pos.append((x0 + q * a, m * np.sqrt(3.0) / 2 * a, 0.0))
+    pos = np.array(pos)
+    per = 2 * n_lines
+    bonds = []
+    for i in range(len(pos)):
+        c = i // per
+        for j in range(i + 1, min(len(pos), (c + 2) * per)):
+            if abs(np.linalg.norm(pos[i] - pos[j]) - a) < 1e-6:
+                bonds.append((i, j))
+    return bonds, pos
+
+
+def armchair_ribbon_blocks(n_lines: int = 7, t: float = -2.7):
+    """Pristine cell blocks (H00, H01) of the armchair ribbon; H01 couples
+    cell c (rows) to cell c + 1 (columns)."""
+    bonds, _ = _armchair_cells(3, n_lines)
+    m = 2 * n_lines
+    h00 = np.zeros((m, m))
+    h01 = np.zeros((m, m))
+    for a_, b_ in bonds:
+        ca, cb = a_ // m, b_ // m
+        if ca == 1 and cb == 1:
+            h00[a_ - m, b_ - m] = h00[b_ - m, a_ - m] = t
+        elif ca == 1 and cb == 2:
+            h01[a_ - m, b_ - 2 * m] = t
+    return h00, h01
+
+
+def armchair_ribbon(n_cells: int, n_lines: int = 7, t: float = -2.7, disorder: float = 0.0,
+                    vacancies: float = 0.0, seed: int = 6, name: str = "armchair_ribbon") -> Device:
+    """Armchair graphene nanoribbon of n_lines dimer lines and n_cells cells
+    (2 n_lines atoms each), Anderson on-site disorder uniform in
+    [-disorder, disorder] eV, and a fraction `vacancies` of the atoms of the
+    inner cells removed (seeded): an irregular honeycomb graph.  The first
+    and last cells are the contacts; the leads are pristine ribbons."""
+    rng = np.random.default_rng(seed)
+    bonds, pos = _armchair_cells(n_cells, n_lines)
+    per = 2 * n_lines
+    keep = np.ones(len(pos), bool)
+    if vacancies > 0:
+        inner = np.arange(per, len(pos) - per)
+        keep[rng.choice(inner, int(round(vacancies * inner.size)), replace=False)] = False
+    new = -np.ones(len(pos), np.int64)
+    new[keep] = np.arange(int(keep.sum()))
+    natom = int(keep.sum())
+    b = np.array([(new[i], new[j]) for i, j in bonds if keep[i] and keep[j]], dtype=np.int64)
+    eps = rng.uniform(-disorder, disorder, natom) if disorder > 0 else np.zeros(natom)
+    rowptr, col, val = _csr_from_triplets(natom, np.concatenate([np.arange(natom), b[:, 0], b[:, 1]]),
+                                          np.concatenate([np.arange(natom), b[:, 1], b[:, 0]]),
+                                          np.concatenate([eps, np.full(2 * len(b), t)]))
+    cell = np.arange(len(pos)) // per
+    layers = [new[(cell == c) & keep] for c in range(n_cells)]
+    contacts = [layers[0].astype(np.int32).copy(), layers[-1].astype(np.int32).copy()]
+    h00, h01 = armchair_ribbon_blocks(n_lines, t)
+    lead = {"kind": "sancho_rubio", "h00": h00, "h01": h01}
+    return Device(name, natom, rowptr, col, val, pos[keep], layers, contacts, lead)
+
+
+# ---------------------------------------------------------------------------
 # potentials
 # ---------------------------------------------------------------------------
 

@@ -90,6 +90,16 @@ def nanotube(n_cells=2000, n_energies=256, eta=1e-6, mu=(0.05, -0.05), kt=0.025,
                     eta, mu, kt)
 
 
+def armchair_ribbon(n_cells=60, n_lines=7, n_energies=6, emin=-1.2, emax=1.2, eta=1e-6,
+                    mu=(0.05, -0.05), kt=0.025, disorder=0.2, vacancies=0.03, seed=6) -> Workload:
+    """Armchair graphene nanoribbon (7 dimer lines, 14 atoms per cell),
+    t = -2.7 eV, Anderson disorder and seeded vacancies: the honeycomb
+    stencil on an irregular graph."""
+    dev = devices.armchair_ribbon(n_cells, n_lines, -2.7, disorder, vacancies, seed)
+    return Workload("agnr%d_%dcells" % (n_lines, n_cells), dev, np.linspace(emin, emax, n_energies),
+                    eta, mu, kt)
+
+
 def adjoint_device(n_transport=512, n_transverse=64, n_energies=256, eta=1e-6, mu=(0.10, 0.05),
                    kt=0.025, seed=5) -> Workload:
     """512 x 64 grid with a seeded smooth random potential (max |V| = 50 meV)

@@ -406,6 +406,30 @@ def test_tube_transmission_counts_bloch_bands():
         assert abs(t - n_ch) < 1e-4, (e, t, n_ch)
 
 
+def test_armchair_ribbon_transmission_counts_bloch_bands():
+    """Pristine armchair ribbon (7 dimer lines): the Caroli transmission
+    equals the number of right-moving Bloch channels at E (0 in the gap of
+    this semiconducting ribbon), which pins the generator's cell blocks and
+    the device's honeycomb graph together."""
+    h00, h01 = devices.armchair_ribbon_blocks(7, -2.7)
+    ks = np.linspace(0, 2 * np.pi, 2001)
+    bands = np.array([np.linalg.eigvalsh(h00 + h01 * np.exp(1j * k) + h01.T * np.exp(-1j * k))
+                      for k in ks])
+    gap = np.min(np.abs(bands))
+    assert 0.3 < gap < 1.2            # N = 7 armchair ribbons are semiconducting
+    dev = devices.armchair_ribbon(4, 7, -2.7)
+    for e in [0.0, 0.9, 1.5, 2.2]:
+        crossings = np.sum(np.diff(np.sign(bands - e), axis=0) != 0)
+        n_ch = crossings // 2
+        z = complex(e, 1e-8)
+        s_l, s_r = leads.tube_lead_sigmas(z, h00, h01)
+        g, _ = definition.full_greens(dev.scipy_h(), None, e, 1e-8, dev.contacts, [s_l, s_r],
+                                      [0 * s_l, 0 * s_r])
+        g1n = g[np.ix_(dev.contacts[0], dev.contacts[1])]
+        t = np.trace(leads.gamma(s_l) @ g1n @ leads.gamma(s_r) @ g1n.conj().T).real
+        assert abs(t - n_ch) < 1e-4, (e, t, n_ch)
+
+
 # ---------------------------------------------------------------------------
 # gradient
 # ---------------------------------------------------------------------------

@@ -83,6 +83,16 @@ def test_partition_rules_tube_and_graph_only():
     _check_partition(dev, sym.arrays())
 
 
+def test_partition_rules_armchair_ribbon_with_vacancies():
+    """The honeycomb stencil with seeded vacancies (an irregular graph), cut
+    geometrically and, without coordinates, by level-set separators."""
+    dev = devices.armchair_ribbon(40, 7, -2.7, disorder=0.1, vacancies=0.05)
+    _, _, arr = _tree(dev, leaf_max=16)
+    _check_partition(dev, arr)
+    sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, None, leaf_max=16)
+    _check_partition(dev, sym.arrays())
+
+
 def test_rejects_nonsymmetric_h_and_overlapping_contacts():
     dev = devices.fd2d(6, 4)
     val = dev.val.copy()
