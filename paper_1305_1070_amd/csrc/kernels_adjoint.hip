@@ -11,11 +11,13 @@
 //   (G^< Lambda G)_kk = sum_c [G_{k,c} Sigma^<_c X_c(k,:)^T],
 //   X_c = A^{-1} (Lambda conj(G_{:,c})).
 // Both G_{:,c} = A^{-1} E_c and X_c are multi-right-hand-side solves with the
-// factors of the fold (Section 3.2): forward substitution up the tree
-// (Z_i = Y_i + sum of the children's contributions Psi_d^T Z_d), the block
-// diagonal D^{-1} (the pivot inverses), and back substitution down the tree
-// (X_i = D^{-1}Z_i + Psi_i X_{B_i}).  The factors are recomputed by a fresh
-// fold rather than kept from the forward pass.
+// factors of the fold (Section 3.2), the columns of all contacts forming one
+// right-hand side: forward substitution up the tree (Z_i = Y_i + sum of the
+// children's contributions Psi_d^T Z_d), then back substitution down the tree
+// with the pivot inverses applied in the same step (X_i = A_ii^{-1} Z_i +
+// Psi_i X_{B_i}).  The right-hand sides Y are formed where the forward
+// substitution reads them (rhs_y) and never stored.  The factors are
+// recomputed by a fresh fold rather than kept from the forward pass.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"

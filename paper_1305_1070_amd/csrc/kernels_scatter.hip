@@ -130,6 +130,114 @@ k_anc_g_leaf(Ctx c, ScatCtx x, const ColItem* items) {
   anc_g_body<TM, true>(c, x, items);
 }
 
+// The N fold's product for one tile: the sum over the feeding descendants d
+// of A_d (TM x s_d) times B_d (s_d x 64), A_d(i, r) = Psi_d[r][u(i)] (the
+// B_d column of point i, 0 where i is not in B_d), B_d(r, j) = the entry of
+// N_d's row r at column j of the tile.  The descendants' rows run as one
+// stream of 16-deep K chunks (the last chunk of each descendant cut to its
+// live 4-deep steps), and the operands of the next chunk, which may be the
+// next descendant's first, are loaded into registers while the matrix
+// cores work on the current one: most descendants hold a single chunk, so
+// a product per descendant would wait on every first load.
+struct Feed {
+  const double2* psi;
+  const double2* n;
+  const int32_t* um;
+  int bd, gd, sd;
+  int64_t coff;
+};
+
+template <int TM>
+__device__ __forceinline__ void anc_n_product(const Ctx& c, const ScatCtx& x, const ScatDesc& sd,
+                                              const double2* S, const double2* X, int s, int j0, int nj,
+                                              ZTile& acc, GemmSmemR<TM>& sm) {
+  using T = TileShape<TM>;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
+  auto feed = [&](int q) {
+    const LkItem L = x.lk[q];
+    const ClusterDesc dd = c.cl[L.d];
+    const ScatDesc sdd = x.sd[L.d];
+    return Feed{S + dd.o_psi, X + sdd.o_g, x.umap + L.map, dd.b, sdd.g, dd.s, (int64_t)L.col + j0};
+  };
+  double2 pa[TM / 16], pb[4];
+  auto load = [&](const Feed& f, int r0) {
+#pragma unroll
+    for (int q = 0; q < TM / 16; ++q) {
+      const int idx = t + 256 * q, i = idx % TM, kk = idx / TM;
+      const int u = (i < s && r0 + kk < f.sd) ? f.um[i] : -1;
+      pa[q] = u >= 0 ? f.psi[(int64_t)(r0 + kk) * f.bd + u] : cz();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = t + 256 * q, j = idx & 63, kk = idx >> 6;
+      pb[q] = (j < nj && r0 + kk < f.sd) ? f.n[(int64_t)(r0 + kk) * f.gd + f.coff + j] : cz();
+    }
+  };
+  int q = sd.lk0;
+  if (q >= sd.lk1) return;
+  Feed cur = feed(q);
+  int r0 = 0;
+  load(cur, 0);
+  while (true) {
+#pragma unroll
+    for (int qq = 0; qq < TM / 16; ++qq) {
+      const int idx = t + 256 * qq, i = idx % TM, kk = idx / TM;
+      sm.ar[i][kk] = pa[qq].x;
+      sm.ai[i][kk] = pa[qq].y;
+    }
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int idx = t + 256 * qq, j = idx & 63, kk = idx >> 6;
+      sm.br[kk][j] = pb[qq].x;
+      sm.bi[kk][j] = pb[qq].y;
+    }
+    __syncthreads();
+    const int kend = min(KC, cur.sd - r0);
+    int nr0 = r0 + KC, nq = q;
+    Feed nxt = cur;
+    if (nr0 >= cur.sd) {
+      nq = q + 1;
+      nr0 = 0;
+      if (nq < sd.lk1) nxt = feed(nq);
+    }
+    const bool more = nq < sd.lk1;
+    if (more) load(nxt, nr0);
+#pragma unroll
+    for (int k4 = 0; k4 < KC; k4 += 4) {
+      if (k4 >= kend) break;
+      const int kq = k4 + (lane >> 4);
+      double are[2], aim[2], bre[2], bim[2];
+#pragma unroll
+      for (int m = 0; m < T::MB; ++m) {
+        const int i = wr + m * 16 + (lane & 15);
+        are[m] = sm.ar[i][kq];
+        aim[m] = sm.ai[i][kq];
+      }
+#pragma unroll
+      for (int n = 0; n < T::NB; ++n) {
+        const int j = wc + n * 16 + (lane & 15);
+        bre[n] = sm.br[kq][j];
+        bim[n] = sm.bi[kq][j];
+      }
+#pragma unroll
+      for (int m = 0; m < T::MB; ++m)
+#pragma unroll
+        for (int n = 0; n < T::NB; ++n) {
+          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bre[n], acc.re[m][n], 0, 0, 0);
+          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim[m], bim[n], acc.re[m][n], 0, 0, 0);
+          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bim[n], acc.im[m][n], 0, 0, 0);
+          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[m], bre[n], acc.im[m][n], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+    if (!more) break;
+    cur = nxt;
+    r0 = nr0;
+    q = nq;
+  }
+}
+
 // N_i over one 64-column tile of the frame.  The own term Sigma^<_ph conj(G)
 // reads the G^(0) entry that N_i replaces (same element, same thread).
 template <int TM>
@@ -150,23 +258,7 @@ __global__ void __launch_bounds__(256) k_anc_n(Ctx c, ScatCtx x, const ColItem* 
   __syncthreads();
   ZTile acc;
   ztile_zero(acc);
-  for (int q = sd.lk0; q < sd.lk1; ++q) {
-    const LkItem L = x.lk[q];
-    const ClusterDesc dd = c.cl[L.d];
-    const ScatDesc sdd = x.sd[L.d];
-    const double2* Psd = S + dd.o_psi;
-    const double2* Nd = X + sdd.o_g;
-    const int bd = dd.b, gd = sdd.g, coff = L.col + j0;
-    const int32_t* um = x.umap + L.map;
-    // A(i, k) = Psi_d[k][u(i)]: row k of d, the B_d column of point i
-    zgemm_acc_t<TM, true, false, true, TM, true>(
-        dd.s,
-        [&](int i, int k) {
-          const int u = i < s ? um[i] : -1;
-          return u >= 0 ? Psd[(int64_t)k * bd + u] : cz();
-        },
-        [&](int k, int j) { return j < nj ? Nd[(int64_t)k * gd + coff + j] : cz(); }, acc, sm);
-  }
+  anc_n_product<TM>(c, x, sd, S, X, s, j0, nj, acc, sm);
   double2* Ni = X + sd.o_g;
   ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
     if (i < s && j < nj) {
