@@ -166,11 +166,12 @@ def bench_tube(ndg, workloads, torch, cuda):
             "algorithmic_gflop_per_energy": sym.info()["ops_total"] * 8 / 1e9}
 
 
-def bench_scattering(ndg, workloads, torch, cuda, leaf, n_energies=64, batch=32):
+def bench_scattering(ndg, workloads, torch, cuda, leaf, n_energies=512, batch=256):
     """Superlattice 1024x64 with diagonal phonon self-energies on every site
-    (local dephasing, gamma0 = 5 meV): every eighth energy of the 512-point
-    grid, FP64, through ndg_solve_scattering; per-kernel times from the
-    library's profile of one further solve."""
+    (local dephasing, gamma0 = 5 meV): the 512-point energy grid (or every
+    (512 / n_energies)-th energy of it), FP64, through ndg_solve_scattering
+    in batches of `batch` energies (677 MB each in flight: 173 GB at 256);
+    per-kernel times from the library's profile of one further solve."""
     from inputs import phonons
     w = workloads.superlattice(n_energies=512)
     d = w.device
