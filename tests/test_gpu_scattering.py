@@ -318,3 +318,49 @@ def test_scba_conserves_current_superlattice(lib):
     assert np.max(np.abs(c[:, 0] + c[:, 1])) <= 1e-7 * np.max(np.abs(c[:, 0]))
     assert np.max(np.abs(b[:, 0] + b[:, 1])) <= 1e-7 * np.max(np.abs(b[:, 0]))
     assert np.max(np.abs(c[:, 0] - b[:, 0])) > 1e-2 * np.max(np.abs(b[:, 0]))
+
+
+def test_scattering_deep_tree_refused_and_empty_calls(lib):
+    """A layer chain of 80 layers (tree depth 80) would need every later
+    layer in each frame: enable_scattering refuses it (NDG_EINVAL) before
+    allocating.  nE = 0 returns at once."""
+    import torch
+    dev = devices.fd2d(80, 4)
+    sym = lib.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, tree_kind=1)
+    plan = lib.Plan(sym, max_batch=2)
+    with pytest.raises(lib.NdgError) as ei:
+        plan.enable_scattering()
+    assert ei.value.code == -1
+    assert plan.info()["scatter_bytes_per_energy"] == 0
+    wl = workloads.small_grid(8, 6, n_energies=2, eta=1e-3)
+    sym2 = lib.analyze(wl.device.n, wl.device.rowptr, wl.device.col, wl.device.val, wl.device.contacts,
+                       wl.device.coords)
+    plan2 = lib.Plan(sym2, max_batch=2)
+    plan2.enable_scattering()
+    cuda = torch.device("cuda:0")
+    n = wl.device.n
+    E = torch.zeros(0, dtype=torch.float64, device=cuda)
+    z = [torch.zeros((0, 6, 6), dtype=torch.complex128, device=cuda) for _ in range(2)]
+    ph = torch.zeros((0, n), dtype=torch.complex128, device=cuda)
+    gr, gl, gg = plan2.solve_scattering(E, 1e-3, z, z, ph, ph)
+    assert gr.shape == (0, n)
+    *_, it, res = plan2.scba(E, 1e-3, z, z, 0.1)
+    assert it == 0 and res == 0.0
+    torch.cuda.synchronize()
+
+
+def test_scba_ragged_batches_match_oracle(lib):
+    """The Born loop over 5 energies in batches of 2 (2, 2, 1): every
+    iteration solves all energies before the mixing step."""
+    from oracle import scba
+    dev = devices.fd2d(12, 8)
+    e = np.linspace(1.25, 1.75, 5)
+    sig = leads.contact_self_energies(dev, e, 1e-6, (1.5, 1.4), 0.025)
+    sl_, sr_, ll_, lr_ = sig
+    _say("scba 12x8 batches of 2")
+    out = _scba_gpu(lib, dev, e, 1e-6, sig, 0.1, 0.7, 1e-10, 60, leaf_max=8, max_batch=2)
+    ref = scba.scba(dev.scipy_h(), None, e, 1e-6, dev.contacts, [sl_, sr_], [ll_, lr_], 0.1, 0.7, 1e-10, 60)
+    _say("  iterations gpu %d oracle %d" % (out[5], ref[5]))
+    assert out[5] == ref[5]
+    for k in (0, 1, 3, 4):
+        assert np.max(rel_err(out[k], ref[k])) < 1e-10
