@@ -23,6 +23,10 @@
 //             (added to the contact chains' part where the cluster lies on
 //             one, since the source is linear in Sigma^<).
 // The extraction of G^< then runs unchanged with a source on every cluster.
+//
+// Also here: the self-consistent Born update of local elastic scattering
+// (k_scba_mix, k_scba_max) and the terminal current spectral density per
+// contact (k_current), which read the outputs and stored rows of a solve.
 #include "device_common.hpp"
 
 #include <algorithm>

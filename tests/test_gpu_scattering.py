@@ -364,3 +364,23 @@ def test_scba_ragged_batches_match_oracle(lib):
     assert out[5] == ref[5]
     for k in (0, 1, 3, 4):
         assert np.max(rel_err(out[k], ref[k])) < 1e-10
+
+
+def test_scattering_tiny_device(lib):
+    """A 3 x 4 device (12 sites, the root possibly a leaf with no
+    ancestors): phonon solve and currents against the definition."""
+    from oracle import definition
+    wl = workloads.small_grid(3, 4, n_energies=3, emin=0.05, emax=0.3, eta=1e-3, noise=0.05, seed=13)
+    dev = wl.device
+    e = wl.energies
+    sig = wl.self_energies(e)
+    sl_, sr_, ll_, lr_ = sig
+    pr, pl = phonons.diagonal_self_energies(dev, e, gamma0=2e-2, seed=9)
+    info = lib.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords).info()
+    _say("tiny device: %d clusters, %d levels" % (info["nclusters"], info["max_height"]))
+    out = _run(lib, dev, e, wl.eta, sig, pr, pl)
+    _check(out, _oracle(dev, e, wl.eta, sig, pr, pl), "3x4")
+    cur = _currents(lib, dev, e, wl.eta, sig, pr, pl)
+    ref = definition.terminal_currents(dev.scipy_h(), None, e, wl.eta, dev.contacts, [sl_, sr_], [ll_, lr_],
+                                       pr, pl)
+    assert np.max(np.abs(cur - ref)) <= 1e-10 * np.max(np.abs(ref))
