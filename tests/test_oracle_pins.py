@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from inputs import devices, leads, phonons, workloads
-from oracle import brute, definition, gradient, rgf, scba
+from oracle import brute, definition, gradient, poisson, rgf, scba
 
 pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
 
@@ -360,6 +360,78 @@ def test_terminal_current_conserved_by_converged_elastic_scattering():
     cur2 = definition.terminal_currents(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_], [ll_, lr_],
                                         pr, pl)
     assert np.max(np.abs(cur2[:, 0] + cur2[:, 1]) / np.abs(cur2[:, 0])) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Schroedinger-Poisson Newton step
+# ---------------------------------------------------------------------------
+
+def _sp_problem(mu=(2.2, 2.2)):
+    """8 x 6 grid (first transverse band from 1.8 eV), 31 energies over the
+    occupied band, eta = 0 in the device; K = 0.05 (graph Laplacian + 0.5 I),
+    beta = 1, background density 1.3 n(0)."""
+    dev = devices.fd2d(8, 6)
+    e = np.linspace(1.7, 2.6, 31)
+    w = np.full(e.size, e[1] - e[0])
+    w[0] *= 0.5
+    w[-1] *= 0.5
+    cE = w / (2 * np.pi)
+    sl_, sr_, ll_, lr_ = leads.contact_self_energies(dev, e, 1e-7, mu, 0.025)
+    h = dev.scipy_h()
+    a = (h != 0).astype(float).toarray()
+    np.fill_diagonal(a, 0.0)
+    K = 0.05 * (np.diag(a.sum(1)) - a + 0.5 * np.eye(dev.n))
+    args = (h, None, e, 0.0, dev.contacts, [sl_, sr_], [ll_, lr_], cE)
+    n0 = gradient.density(*args)
+    return dev, args, K, 1.0, 1.3 * n0
+
+
+def test_density_response_symmetric_only_in_equilibrium():
+    """chi = dn/dV is the Hessian of the grand potential in equilibrium
+    (symmetric; exactly so at eta = 0), and not symmetric under bias."""
+    dev, args, *_ = _sp_problem()
+    h, _, e, eta, contacts, sr, sl, cE = args
+    chi = poisson.response(h, np.zeros(dev.n), e, eta, contacts, sr, sl, cE)
+    for k in (0, 17, 40):       # rows are the density's vector-Jacobian products
+        e_k = np.zeros(dev.n)
+        e_k[k] = 1.0
+        row = gradient.density_vjp(h, np.zeros(dev.n), e, eta, contacts, sr, sl, cE, e_k)
+        assert np.max(np.abs(chi[k] - row)) <= 1e-12 * np.abs(chi).max()
+    assert np.abs(chi - chi.T).max() <= 1e-10 * np.abs(chi).max()
+    assert np.all(np.diag(chi) < 0)          # raising V on a site lowers its density
+    dev_b, args_b, *_ = _sp_problem(mu=(2.3, 2.1))
+    hb, _, eb, etab, cb, srb, slb, cEb = args_b
+    chib = poisson.response(hb, np.zeros(dev_b.n), eb, etab, cb, srb, slb, cEb)
+    assert np.abs(chib - chib.T).max() > 1e-2 * np.abs(chib).max()
+
+
+def test_newton_jacobian_matches_finite_differences_of_the_residual():
+    dev, args, K, beta, nd = _sp_problem()
+    h, _, e, eta, contacts, sr, sl, cE = args
+    rng = np.random.default_rng(3)
+    v = rng.uniform(-0.05, 0.05, dev.n)
+    dv = rng.standard_normal(dev.n)
+    J = K - beta * poisson.response(h, v, e, eta, contacts, sr, sl, cE)
+    step = 1e-6
+    fp = poisson.residual(h, v + step * dv, e, eta, contacts, sr, sl, cE, K, beta, nd)
+    fm = poisson.residual(h, v - step * dv, e, eta, contacts, sr, sl, cE, K, beta, nd)
+    fd = (fp - fm) / (2 * step)
+    assert np.max(np.abs(J @ dv - fd)) <= 1e-6 * np.max(np.abs(fd))
+
+
+def test_newton_converges_quadratically():
+    dev, args, K, beta, nd = _sp_problem()
+    h, _, e, eta, contacts, sr, sl, cE = args
+    v = np.zeros(dev.n)
+    norms = []
+    for _ in range(6):
+        d, F = poisson.newton_step(h, v, e, eta, contacts, sr, sl, cE, K, beta, nd)
+        norms.append(np.linalg.norm(F))
+        v = v + d
+    assert norms[-1] < 1e-10 * norms[0]
+    # the last contracting steps square the residual (up to a modest constant)
+    k = next(i for i in range(1, 6) if norms[i] < 1e-3 * norms[0])
+    assert norms[k + 1] <= 10.0 * norms[k] ** 2 / norms[0] + 1e-14 * norms[0]
 
 
 # ---------------------------------------------------------------------------
