@@ -52,7 +52,9 @@ typedef enum {
   NDG_ESINGULAR = -4,  /* a zero pivot was met while inverting a cluster block          */
   NDG_ENOMEM = -5,     /* device allocation failed                                      */
   NDG_EHIP = -6,       /* a HIP runtime call failed                                     */
-  NDG_ENONFINITE = -7  /* a non-finite value reached an output                          */
+  NDG_ENONFINITE = -7, /* a non-finite value reached an output                          */
+  NDG_ENOTSPD = -8     /* the Newton step's Jacobian was not positive definite along a
+                          search direction (out of equilibrium, or a non-convex point)   */
 } ndg_status;
 
 typedef enum { NDG_FP64 = 0, NDG_MIXED = 1 } ndg_precision;
@@ -291,6 +293,43 @@ ndg_status ndg_density_vjp(ndg_plan* plan, int32_t nE, const double* E, double e
                            const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
                            const double* cE, const double* nbar, double* vbar, ndg_precision prec,
                            void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Newton step of the Schroedinger-Poisson problem (self-consistency of the
+ * potential with the density, the motivation for repeated solves in
+ * Section 1), using the density's vector-Jacobian product.
+ *
+ * With a symmetric positive definite discrete Poisson operator K on the
+ * sites, a coupling beta and a background density n_D:
+ *   F(V) = K V - beta (n(V) - n_D),  J = dF/dV = K - beta chi,  chi = dn/dV,
+ * ndg_poisson_newton_step returns delta with J delta = -F(V) by conjugate
+ * gradients; each iteration applies chi through ndg_density_vjp's solves,
+ * which is exact when chi is symmetric: in equilibrium (one chemical
+ * potential for all contacts; exactly at eta = 0), where chi is the Hessian
+ * of the grand potential and J is positive definite.  Out of equilibrium it
+ * is a Newton-like step with the symmetrized response.
+ *   E, eta, V, sig_r, sig_less, cE   as ndg_density (V: the current
+ *                                      potential, device [n], not NULL)
+ *   k_rowptr[n+1] (int64), k_col[k_nnz] (int32), k_val[k_nnz]   device CSR
+ *                     of K in the caller's site order (row ranges outside
+ *                     [0, k_nnz) and columns outside [0, n) are ignored)
+ *   beta, nd[n]       coupling and device background density
+ *   cg_tol, cg_max_iter   stop when ||r|| <= cg_tol ||F|| or after
+ *                     cg_max_iter iterations (each one density VJP)
+ *   delta[n]          device output (the caller updates V += delta)
+ *   res_norm          host output or NULL: ||F(V)||_2
+ *   cg_iterations, cg_residual   host outputs or NULL: iterations run,
+ *                     final ||r|| / ||F||
+ * Needs ndg_plan_enable_adjoint (its workspace holds the vectors).  Runs on
+ * `stream` and synchronizes it once per iteration (dot products).
+ * Errors: NDG_EINVAL, NDG_EHIP, NDG_ENOTSPD (see above).
+ */
+ndg_status ndg_poisson_newton_step(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
+                                   const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
+                                   const double* cE, const int64_t* k_rowptr, const int32_t* k_col,
+                                   const double* k_val, int64_t k_nnz, double beta, const double* nd,
+                                   double cg_tol, int32_t cg_max_iter, double* delta, double* res_norm,
+                                   int32_t* cg_iterations, double* cg_residual, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched solve of several devices (plans) of uneven sizes in one launch.

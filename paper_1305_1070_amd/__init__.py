@@ -23,7 +23,7 @@ __all__ = ["analyze", "Symbolic", "Plan", "load", "NdgError", "NDG_FP64", "NDG_M
            "ndg_plan_export_block", "ndg_plan_set_profiling", "ndg_plan_profile",
            "ndg_density", "ndg_plan_enable_adjoint", "ndg_density_vjp", "NDDensity",
            "ndg_batch_create", "ndg_batch_destroy", "ndg_batch_solve", "Batch",
-           "ndg_plan_enable_scattering", "ndg_solve_scattering", "ndg_scba",
+           "ndg_plan_enable_scattering", "ndg_solve_scattering", "ndg_scba", "ndg_poisson_newton_step",
            "ndg_status_string", "ndg_last_error"]
 
 
@@ -127,6 +127,23 @@ def ndg_scba(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, d0, mix, to
                                sl_ph_ptr, dgr_ptr, dgl_ptr, dgg_ptr, current_ptr, C.byref(it),
                                C.byref(res), stream_ptr))
     return it.value, res.value
+
+
+def ndg_poisson_newton_step(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, ce_ptr, k_rowptr_ptr,
+                            k_col_ptr, k_val_ptr, k_nnz, beta, nd_ptr, cg_tol, cg_max_iter, delta_ptr,
+                            stream_ptr):
+    """Returns (||F||, cg iterations, final relative residual)."""
+    nc = len(sig_r_ptrs)
+    sr = (C.c_void_p * max(1, nc))(*sig_r_ptrs)
+    sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
+    fn = C.c_double()
+    it = C.c_int32()
+    res = C.c_double()
+    _lib.check(load().ndg_poisson_newton_step(plan, ne, e_ptr, eta, v_ptr, sr, sl, ce_ptr, k_rowptr_ptr,
+                                              k_col_ptr, k_val_ptr, k_nnz, beta, nd_ptr, cg_tol, cg_max_iter,
+                                              delta_ptr, C.byref(fn), C.byref(it), C.byref(res),
+                                              stream_ptr))
+    return fn.value, it.value, res.value
 
 
 def ndg_density(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, ce_ptr, dens_ptr, prec,
@@ -331,6 +348,33 @@ class Plan:
 
     def enable_adjoint(self):
         ndg_plan_enable_adjoint(self.handle)
+
+    def poisson_newton_step(self, E, eta, sig_r, sig_less, cE, V, k_rowptr, k_col, k_val, beta, nd,
+                            cg_tol=1e-10, cg_max_iter=200, out=None, stream=None):
+        """Newton step of the Schroedinger-Poisson problem (ndg_poisson_newton_step):
+        K given as a CSR (int64 rowptr, int32 col, float64 val tensors on
+        the GPU), nd float64 [n].  Returns (delta, ||F||, cg iterations,
+        final relative residual); enable_adjoint() first."""
+        import torch
+        n, ne, dev = self._check_inputs(E, sig_r, sig_less, V)
+        if V is None:
+            raise ValueError("V is required")
+        for t, dt in ((cE, torch.float64), (k_rowptr, torch.int64), (k_col, torch.int32),
+                      (k_val, torch.float64), (nd, torch.float64)):
+            if t.dtype != dt or t.device != dev or not t.is_contiguous():
+                raise ValueError("cE, K and nd must be contiguous tensors on the plan's device "
+                                 "(float64 / int64 / int32 / float64 / float64)")
+        if k_rowptr.numel() != n + 1 or nd.numel() != n or cE.numel() != ne:
+            raise ValueError("K must be n x n CSR, nd [n], cE [nE]")
+        out = torch.empty(n, dtype=torch.float64, device=dev) if out is None else out
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        fn, it, res = ndg_poisson_newton_step(
+            self.handle, ne, E.data_ptr(), float(eta), V.data_ptr(), [t.data_ptr() for t in sig_r],
+            [t.data_ptr() for t in sig_less], cE.data_ptr(), k_rowptr.data_ptr(), k_col.data_ptr(),
+            k_val.data_ptr(), int(k_col.numel()), float(beta), nd.data_ptr(), float(cg_tol), int(cg_max_iter),
+            out.data_ptr(),
+            C.c_void_p(st.cuda_stream))
+        return out, fn, it, res
 
     def enable_scattering(self):
         ndg_plan_enable_scattering(self.handle)

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(HERE, "libndnegf.so")
 
 NDG_OK = 0
 STATUS = {0: "NDG_OK", -1: "NDG_EINVAL", -2: "NDG_ENOTSYM", -3: "NDG_ECONTACT",
-          -4: "NDG_ESINGULAR", -5: "NDG_ENOMEM", -6: "NDG_EHIP", -7: "NDG_ENONFINITE"}
+          -4: "NDG_ESINGULAR", -5: "NDG_ENOMEM", -6: "NDG_EHIP", -7: "NDG_ENONFINITE",
+          -8: "NDG_ENOTSPD"}
 NDG_FP64, NDG_MIXED = 0, 1
 
 
@@ -89,6 +90,9 @@ SIGNATURES = {
                                        P, P, P, P, P, P, P, P]),
     "ndg_scba": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P), C.c_double,
                            C.c_double, C.c_double, C.c_int32, P, P, P, P, P, P, I32P, F64P, P]),
+    "ndg_poisson_newton_step": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P), P,
+                                          P, P, P, C.c_int64, C.c_double, P, C.c_double, C.c_int32, P,
+                                          F64P, I32P, F64P, P]),
     "ndg_plan_set_profiling": (C.c_int, [P, C.c_int32]),
     "ndg_plan_profile": (C.c_int, [P, C.c_int32, C.POINTER(KernelStat), C.POINTER(C.c_int32)]),
     "ndg_batch_create": (C.c_int, [C.c_int32, C.POINTER(P), C.POINTER(P)]),

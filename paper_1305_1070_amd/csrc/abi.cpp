@@ -193,6 +193,26 @@ ndg_status ndg_scba(ndg_plan* plan, int32_t nE, const double* E, double eta, con
                                     residual, stream);
 }
 
+ndg_status ndg_poisson_newton_step(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
+                                   const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
+                                   const double* cE, const int64_t* k_rowptr, const int32_t* k_col,
+                                   const double* k_val, int64_t k_nnz, double beta, const double* nd,
+                                   double cg_tol, int32_t cg_max_iter, double* delta, double* res_norm,
+                                   int32_t* cg_iterations, double* cg_residual, void* stream) {
+  if (!plan) { set_error("ndg_poisson_newton_step: NULL plan"); return NDG_EINVAL; }
+  if (nE < 0 || !(eta >= 0) || !(cg_tol >= 0) || cg_max_iter < 0 || k_nnz < 0) {
+    set_error("ndg_poisson_newton_step: nE < 0, eta < 0, cg_tol < 0 or cg_max_iter < 0");
+    return NDG_EINVAL;
+  }
+  if (!E || !V || !cE || !k_rowptr || !k_col || !k_val || !nd || !delta) {
+    set_error("ndg_poisson_newton_step: NULL argument");
+    return NDG_EINVAL;
+  }
+  return (ndg_status)ndg::plan_poisson_newton(plan, nE, E, eta, V, sig_r, sig_less, cE, k_rowptr, k_col, k_val,
+                                              k_nnz, beta, nd, cg_tol, cg_max_iter, delta, res_norm, cg_iterations,
+                                              cg_residual, stream);
+}
+
 static ndg_status check_common(const char* who, ndg_plan* plan, int32_t nE, const double* E, double eta,
                                ndg_precision prec) {
   if (!plan) { set_error(std::string(who) + ": NULL plan"); return NDG_EINVAL; }
@@ -265,6 +285,7 @@ const char* ndg_status_string(int32_t s) {
     case NDG_ENOMEM: return "out of device memory";
     case NDG_EHIP: return "HIP runtime error";
     case NDG_ENONFINITE: return "non-finite value";
+    case NDG_ENOTSPD: return "Newton Jacobian not positive definite";
     default: return "unknown status";
   }
 }

@@ -168,6 +168,15 @@ constexpr int kScbaBlocks = 1024;
 // terminal current spectral density per contact and energy of the batch,
 // cur[(e0 + e) * ncontacts + c] (caddr: see the plan's contact tables)
 void launch_current(const Ctx& c, const int32_t* caddr, int nb, double* cur, hipStream_t st);
+
+// Vector kernels of the Schroedinger-Poisson Newton step (kernels_poisson.hip):
+// y = K x for a CSR matrix, out = a x + b y, *out = x . y (part: kVecBlocks
+// doubles of scratch; fixed reduction order)
+constexpr int kVecBlocks = 1024;
+void launch_spmv(int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
+                 const double* x, double* y, hipStream_t st);
+void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out, hipStream_t st);
+void launch_dot(int64_t n, const double* x, const double* y, double* part, double* out, hipStream_t st);
 void launch_scba_mix(const double2* dgr, const double2* dgl, double2* sr, double2* sl, int64_t count,
                      double d0, double mix, double* part, double* out, hipStream_t st);
 

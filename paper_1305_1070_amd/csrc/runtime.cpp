@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -77,6 +78,11 @@ struct ndg_plan {
   double* d_part = nullptr;
   int64_t zstride = 0;
   int mmax = 0;
+  // Newton step of the Schroedinger-Poisson problem (allocated with the
+  // adjoint workspace): kPoissonVecs vectors of n doubles, dot-product scratch
+  static constexpr int kPoissonVecs = 7;
+  double* d_pvec = nullptr;
+  double* d_pdot = nullptr;
   int contact_cl[2] = {-1, -1};
   // phonon G^< source (ndg_plan_enable_scattering): all-ancestor rows, per
   // height and tile class (clusters s <= 16, <= 32, <= 64) the column tiles
@@ -204,7 +210,8 @@ void free_plan(ndg_plan* p) {
                   p->d_srow,      p->d_scol,     p->d_scid,       p->d_sflat,      p->d_hfront,
                   p->d_smap,      p->d_pinv,     p->d_gaddr,      p->d_sdiag,      p->d_sd,
                   p->d_atab,      p->d_bpos,     p->d_lk,         p->d_umap,       p->d_ancitems,
-                  p->d_anccls,    p->d_sws,      p->d_scba,       p->d_caddr};
+                  p->d_anccls,    p->d_sws,      p->d_scba,       p->d_caddr,      p->d_pvec,
+                  p->d_pdot};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& r : p->recs) {
@@ -620,17 +627,20 @@ int plan_enable_adjoint(ndg_plan* p) {
   if (hipMalloc((void**)&p->d_rX, nb * nm * 16) != hipSuccess ||
       hipMalloc((void**)&p->d_rG, nb * nm * 16) != hipSuccess ||
       hipMalloc((void**)&p->d_rZ, nb * (size_t)p->zstride * 16) != hipSuccess ||
-      hipMalloc((void**)&p->d_part, nb * (size_t)p->n * 8) != hipSuccess)
+      hipMalloc((void**)&p->d_part, nb * (size_t)p->n * 8) != hipSuccess ||
+      hipMalloc((void**)&p->d_pvec, (size_t)ndg_plan::kPoissonVecs * (size_t)p->n * 8) != hipSuccess ||
+      hipMalloc((void**)&p->d_pdot, (size_t)(kVecBlocks + 2) * 8) != hipSuccess)
     rc = NDG_ENOMEM;
   if (!rc) rc = upload(&p->d_ovec, ovec.data(), ovec.size());
   if (!rc) rc = upload(&p->d_bidx, p->hbidx.data(), p->hbidx.size());
   if (rc) {
     (void)hipGetLastError();
-    void* ptrs[] = {p->d_rX, p->d_rG, p->d_rZ, p->d_part, p->d_ovec, p->d_bidx};
+    void* ptrs[] = {p->d_rX, p->d_rG, p->d_rZ, p->d_part, p->d_ovec, p->d_bidx, p->d_pvec, p->d_pdot};
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
     p->d_rX = p->d_rG = p->d_rZ = nullptr;
     p->d_part = nullptr;
+    p->d_pvec = p->d_pdot = nullptr;
     p->d_ovec = nullptr;
     p->d_bidx = nullptr;
     set_error("ndg_plan_enable_adjoint: device allocation failed");
@@ -816,6 +826,84 @@ int plan_scba(ndg_plan* p, int nE, const double* E, double eta, const double* V,
   }
   if (iterations) *iterations = it;
   if (residual) *residual = res;
+  return NDG_OK;
+}
+
+int plan_poisson_newton(ndg_plan* p, int nE, const double* E, double eta, const double* V,
+                        const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, const double* cE,
+                        const int64_t* k_rowptr, const int32_t* k_col, const double* k_val, int64_t k_nnz,
+                        double beta, const double* nd, double cg_tol, int cg_max_iter, double* delta,
+                        double* res_norm, int32_t* cg_iterations, double* cg_residual, void* stream) {
+  if (!p->d_pvec) {
+    set_error("ndg_poisson_newton_step: call ndg_plan_enable_adjoint first");
+    return NDG_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = p->n;
+  double* nv = p->d_pvec;       // n(V), then K p
+  double* F = nv + n;           // residual
+  double* r = F + n;
+  double* pv = r + n;
+  double* chip = pv + n;        // chi p (the density's vector-Jacobian product with p)
+  double* Ap = chip + n;
+  double* kv = Ap + n;
+  double* part = p->d_pdot;
+  double* dot = part + kVecBlocks;
+  auto dot_host = [&](const double* a, const double* b, double& out) {
+    launch_dot(n, a, b, part, dot, st);
+    if (hipMemcpyAsync(&out, dot, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("ndg_poisson_newton_step: reading a dot product failed");
+      return false;
+    }
+    return true;
+  };
+  // F = K V - beta (n(V) - n_D)
+  int rc = plan_run(p, kRunDensity, nE, E, eta, V, sig_r, sig_less, nullptr, nullptr, nullptr, nullptr, cE, nv,
+                    nullptr, nullptr, NDG_FP64, stream);
+  if (rc) return rc;
+  launch_spmv(n, k_nnz, k_rowptr, k_col, k_val, V, kv, st);
+  launch_axpby(n, 1.0, nv, -1.0, nd, nv, st);
+  launch_axpby(n, 1.0, kv, -beta, nv, F, st);
+  // conjugate gradients on J delta = -F, J = K - beta chi (chi symmetric in
+  // equilibrium, so chi p is the vector-Jacobian product with p)
+  launch_axpby(n, -1.0, F, 0.0, F, r, st);
+  launch_axpby(n, 1.0, r, 0.0, r, pv, st);
+  launch_axpby(n, 0.0, r, 0.0, r, delta, st);
+  double rr = 0.0;
+  if (!dot_host(r, r, rr)) return NDG_EHIP;
+  const double f0 = std::sqrt(rr);
+  if (res_norm) *res_norm = f0;
+  int it = 0;
+  double rel = f0 > 0.0 ? 1.0 : 0.0;
+  while (it < cg_max_iter && rel > cg_tol) {
+    rc = plan_run(p, kRunVjp, nE, E, eta, V, sig_r, sig_less, nullptr, nullptr, nullptr, nullptr, cE, nullptr,
+                  pv, chip, NDG_FP64, stream);
+    if (rc) return rc;
+    launch_spmv(n, k_nnz, k_rowptr, k_col, k_val, pv, kv, st);
+    launch_axpby(n, 1.0, kv, -beta, chip, Ap, st);
+    double pap = 0.0;
+    if (!dot_host(pv, Ap, pap)) return NDG_EHIP;
+    if (!(pap > 0.0)) {
+      set_error("ndg_poisson_newton_step: the Jacobian is not positive definite along a search direction");
+      return NDG_ENOTSPD;
+    }
+    const double alpha = rr / pap;
+    launch_axpby(n, 1.0, delta, alpha, pv, delta, st);
+    launch_axpby(n, 1.0, r, -alpha, Ap, r, st);
+    double rr_new = 0.0;
+    if (!dot_host(r, r, rr_new)) return NDG_EHIP;
+    ++it;
+    rel = std::sqrt(rr_new) / f0;
+    launch_axpby(n, 1.0, r, rr_new / rr, pv, pv, st);
+    rr = rr_new;
+  }
+  if (cg_iterations) *cg_iterations = it;
+  if (cg_residual) *cg_residual = rel;
+  if (hipGetLastError() != hipSuccess) {
+    set_error("ndg_poisson_newton_step: kernel launch failed");
+    return NDG_EHIP;
+  }
   return NDG_OK;
 }
 

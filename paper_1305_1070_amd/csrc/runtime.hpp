@@ -40,6 +40,11 @@ int plan_solve_chunk(ndg_plan* plan, int nE, const double* E, double eta, const 
 int plan_max_batch(const ndg_plan* plan);
 int plan_enable_adjoint(ndg_plan* plan);
 int plan_enable_scattering(ndg_plan* plan);
+int plan_poisson_newton(ndg_plan* p, int nE, const double* E, double eta, const double* V,
+                        const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, const double* cE,
+                        const int64_t* k_rowptr, const int32_t* k_col, const double* k_val, int64_t k_nnz,
+                        double beta, const double* nd, double cg_tol, int cg_max_iter, double* delta,
+                        double* res_norm, int32_t* cg_iterations, double* cg_residual, void* stream);
 int plan_scba(ndg_plan* p, int nE, const double* E, double eta, const double* V,
               const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, double d0, double mix,
               double tol, int max_iter, ndg_c128* sig_r_ph, ndg_c128* sig_less_ph, ndg_c128* dgr,
