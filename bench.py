@@ -166,6 +166,69 @@ def bench_tube(ndg, workloads, torch, cuda):
             "algorithmic_gflop_per_energy": sym.info()["ops_total"] * 8 / 1e9}
 
 
+def bench_ribbon(ndg, workloads, torch, cuda):
+    """Armchair graphene nanoribbon, 7 dimer lines x 2000 cells (about 27 000
+    atoms after 3 % vacancies), Anderson disorder, 256 energies in
+    [-1.2, 1.2] eV, on the level-set (graph-only, no coordinates) tree."""
+    w = workloads.armchair_ribbon(n_cells=2000, n_energies=256)
+    d = w.device
+    sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, None, leaf_max=16)
+    plan = ndg.Plan(sym, max_batch=128)
+    sl, sr, ll, lr = w.self_energies()
+    E = torch.tensor(w.energies, device=cuda)
+    srt = [torch.from_numpy(a).to(cuda) for a in (sl, sr)]
+    slt = [torch.from_numpy(a).to(cuda) for a in (ll, lr)]
+    out = plan.solve(E, w.eta, srt, slt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        plan.solve(E, w.eta, srt, slt, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    info = sym.info()
+    return {"workload": "armchair ribbon 7 x 2000 cells, %d atoms (3%% vacancies), 256 energies, level-set "
+                        "tree" % d.n, "energy_points_per_s": len(w.energies) / dt,
+            "clusters": info["nclusters"], "tree_levels": info["max_height"]}
+
+
+def bench_newton(ndg, workloads, torch, cuda, leaf, cg_iter=8):
+    """One Schroedinger-Poisson Newton step on the 512 x 64 grid (256
+    energies, both contacts at 0.10 eV): the density, then cg_iter conjugate
+    gradient iterations (each one density vector-Jacobian product) with
+    K = graph Laplacian + 0.5 I, beta = 1, n_D = 0."""
+    import scipy.sparse as sp
+    w = workloads.adjoint_device(mu=(0.10, 0.10))
+    d = w.device
+    sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, leaf_max=leaf)
+    plan = ndg.Plan(sym, max_batch=128)
+    plan.enable_adjoint()
+    h = sp.csr_matrix((d.val, d.col, d.rowptr), shape=(d.n, d.n))
+    a = (h != 0).astype(np.float64)
+    a.setdiag(0.0)
+    a.eliminate_zeros()
+    K = (sp.diags(np.asarray(a.sum(axis=1)).ravel() + 0.5) - a).tocsr()
+    sl, sr, ll, lr = w.self_energies()
+    E = torch.tensor(w.energies, device=cuda)
+    srt = [torch.from_numpy(x).to(cuda) for x in (sl, sr)]
+    slt = [torch.from_numpy(x).to(cuda) for x in (ll, lr)]
+    cE = torch.tensor(w.quad_weights(), device=cuda)
+    V = torch.tensor(w.potential, device=cuda)
+    rp = torch.tensor(K.indptr.astype(np.int64), device=cuda)
+    col = torch.tensor(K.indices.astype(np.int32), device=cuda)
+    val = torch.tensor(K.data.astype(np.float64), device=cuda)
+    nd = torch.zeros(d.n, dtype=torch.float64, device=cuda)
+    plan.poisson_newton_step(E, w.eta, srt, slt, cE, V, rp, col, val, 1.0, nd, cg_tol=0.0, cg_max_iter=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, fn, it, res = plan.poisson_newton_step(E, w.eta, srt, slt, cE, V, rp, col, val, 1.0, nd, cg_tol=0.0,
+                                              cg_max_iter=cg_iter)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": "512x64 FD grid, 256 energies, equilibrium, K = graph Laplacian + 0.5 I",
+            "ms_per_newton_step": dt * 1e3, "cg_iterations": it, "ms_per_cg_iteration": dt * 1e3 / (it + 1),
+            "cg_relative_residual": res}
+
+
 def bench_scattering(ndg, workloads, torch, cuda, leaf, n_energies=512, batch=256):
     """Superlattice 1024x64 with diagonal phonon self-energies on every site
     (local dephasing, gamma0 = 5 meV): the 512-point energy grid (or every
@@ -392,7 +455,9 @@ def main():
     extra = None
     if args.extra:
         extra = {"batch": bench_batch(ndg, workloads, torch, cuda),
-                 "nanotube": bench_tube(ndg, workloads, torch, cuda)}
+                 "nanotube": bench_tube(ndg, workloads, torch, cuda),
+                 "ribbon_graph_tree": bench_ribbon(ndg, workloads, torch, cuda),
+                 "newton_step": bench_newton(ndg, workloads, torch, cuda, args.leaf)}
 
     copy_cal = None
     if args.copy_calibration:
@@ -430,7 +495,7 @@ def main():
     cpu = None
     parity = None
     if args.extra:
-        _progress("batch and tube done")
+        _progress("extra legs done")
     if args.cpu_sample > 0:
         idxs = list(np.linspace(0, ne - 1, args.cpu_sample).round().astype(int))
         rate, cores, cwall, res = cpu_baseline(idxs, (n_transport, n_transverse, ne))
