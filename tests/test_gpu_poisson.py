@@ -97,3 +97,20 @@ def test_newton_iterations_converge(lib):
         v = v + d
     _say("newton |F|: " + " ".join("%.2e" % x for x in norms))
     assert norms[-1] < 1e-10 * norms[0]
+
+
+def test_newton_step_reports_indefinite_jacobian(lib):
+    """K = 0 and beta = -1 make J = dn/dV, negative definite: the first
+    conjugate-gradient step finds p^T J p <= 0 and returns NDG_ENOTSPD (a
+    condition set from the host; every kernel exits normally)."""
+    import scipy.sparse as sp
+    dev, e, cE, sig, K, Kcsr, beta, nd = _problem()
+    # one explicit zero entry (an empty CSR would pass null index arrays)
+    zero = sp.csr_matrix((np.zeros(1), np.zeros(1, np.int32), np.r_[0, np.ones(dev.n, np.int64)]),
+                         shape=(dev.n, dev.n))
+    assert zero.nnz == 1
+    step = _gpu(lib, dev, e, cE, sig, zero, -1.0, nd)
+    with pytest.raises(lib.NdgError) as ei:
+        step(np.zeros(dev.n))
+    assert ei.value.code == -8
+    _say("indefinite Jacobian reported: %s" % ei.value)
