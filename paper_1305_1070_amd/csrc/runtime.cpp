@@ -876,9 +876,14 @@ int plan_poisson_newton(ndg_plan* p, int nE, const double* E, double eta, const 
   if (res_norm) *res_norm = f0;
   int it = 0;
   double rel = f0 > 0.0 ? 1.0 : 0.0;
+  // V and the energies stay fixed during the step: when they fit one batch,
+  // the density solve's factors serve every vector-Jacobian product (its
+  // extraction writes only the fronts' rows, the solves read only Psi and the
+  // pivot inverses)
+  const bool reuse = nE <= p->max_batch;
   while (it < cg_max_iter && rel > cg_tol) {
     rc = plan_run(p, kRunVjp, nE, E, eta, V, sig_r, sig_less, nullptr, nullptr, nullptr, nullptr, cE, nullptr,
-                  pv, chip, NDG_FP64, stream);
+                  pv, chip, NDG_FP64, stream, nullptr, nullptr, nullptr, nullptr, reuse);
     if (rc) return rc;
     launch_spmv(n, k_nnz, k_rowptr, k_col, k_val, pv, kv, st);
     launch_axpby(n, 1.0, kv, -beta, chip, Ap, st);
@@ -921,7 +926,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
              const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
              ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
              const double* nbar, double* vbar, int prec, void* stream, const int32_t* e0p,
-             const ndg_c128* sig_r_ph, const ndg_c128* sig_less_ph, double* current) {
+             const ndg_c128* sig_r_ph, const ndg_c128* sig_less_ph, double* current, bool reuse_fold) {
   const bool scat = sig_less_ph != nullptr;
   if ((scat || sig_r_ph) && (mode != kRunSolve || e0p || prec != NDG_FP64)) {
     set_error("internal: phonon self-energies are for FP64 solves only");
@@ -1035,7 +1040,9 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   for (int e0 = 0; e0 < e_end; e0 += p->max_batch) {
     const int nb = std::min(p->max_batch, e0p ? nE : nE - e0);
     c.e0 = e0;
-    for (int h = 1; h <= H; ++h) {
+    // reuse_fold: the factors (Psi, pivot inverses) of this single batch are
+    // still in the workspace from a previous call with the same energies and V
+    for (int h = 1; h <= H && !reuse_fold; ++h) {
       const ChainItem* chi = p->d_chainitems + p->chain_ptr[h - 1];
       const int nch = p->chain_ptr[h] - p->chain_ptr[h - 1];
       for (int q = 0; q < ndg_plan::kClasses; ++q) {

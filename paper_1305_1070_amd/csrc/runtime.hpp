@@ -29,7 +29,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
              ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
              const double* nbar, double* vbar, int prec, void* stream,
              const int32_t* e0p = nullptr, const ndg_c128* sig_r_ph = nullptr,
-             const ndg_c128* sig_less_ph = nullptr, double* current = nullptr);
+             const ndg_c128* sig_less_ph = nullptr, double* current = nullptr, bool reuse_fold = false);
 // One batch of energies starting at the device-resident index *e0p (for a
 // graph replayed over the energy range): the launches of a single batch of
 // max_batch energies, slots at or beyond nE skipped; growth is not cleared.
