@@ -200,7 +200,9 @@ def bench_newton(ndg, workloads, torch, cuda, leaf, cg_iter=8):
     w = workloads.adjoint_device(mu=(0.10, 0.10))
     d = w.device
     sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, leaf_max=leaf)
-    plan = ndg.Plan(sym, max_batch=128)
+    # all 256 energies in one batch: the conjugate-gradient iterations then
+    # reuse the density solve's factors
+    plan = ndg.Plan(sym, max_batch=256)
     plan.enable_adjoint()
     h = sp.csr_matrix((d.val, d.col, d.rowptr), shape=(d.n, d.n))
     a = (h != 0).astype(np.float64)
