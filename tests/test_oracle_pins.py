@@ -211,6 +211,23 @@ def test_equilibrium_lesser():
 # as Section 1 takes it; its lesser part adds to Sigma^<)
 # ---------------------------------------------------------------------------
 
+def test_phonon_inputs_are_physical_self_energies():
+    """The generator's Sigma^<_ph is anti-Hermitian on the diagonal (purely
+    imaginary, Im >= 0: in-scattering), Im Sigma^r_ph < 0 (retarded), and in
+    equilibrium mode Sigma^<_ph = -f (Sigma^r_ph - conj(Sigma^r_ph))
+    exactly; the same seed gives the same arrays."""
+    dev = devices.fd2d(10, 6)
+    e = np.linspace(0.0, 0.5, 7)
+    pr, pl = phonons.diagonal_self_energies(dev, e, gamma0=1e-2, seed=4)
+    assert np.all(pl.real == 0) and np.all(pl.imag >= 0)
+    assert np.all(pr.imag < 0)
+    pr2, pl2 = phonons.diagonal_self_energies(dev, e, gamma0=1e-2, seed=4)
+    assert np.array_equal(pr, pr2) and np.array_equal(pl, pl2)
+    qr, ql = phonons.diagonal_self_energies(dev, e, gamma0=1e-2, mu=(0.2, 0.2), seed=4, equilibrium=True)
+    f = leads.fermi(e, 0.2, 0.025)[:, None]
+    assert np.max(np.abs(ql + f * (qr - qr.conj()))) <= 1e-15 * np.max(np.abs(ql))
+
+
 def test_phonon_dense_matches_mpmath_bruteforce():
     wl = workloads.small_grid(5, 4, n_energies=2, emin=0.05, emax=0.25, eta=1e-3, noise=0.05, seed=12)
     e, sr, sl = _problem(wl)
