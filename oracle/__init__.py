@@ -21,6 +21,12 @@ What it computes (all complex128 / float64):
   * brute.py -- the definition again in 50-digit arithmetic (mpmath), no
     LAPACK, for tiny grids.
   * gradient.py -- d(density)/d(on-site potential) from the dense definition.
+  * scba.py -- the self-consistent Born loop of local elastic phonon
+    scattering (Sigma_ph = d0 diag G) over the dense definition.
+  * poisson.py -- the Newton step of the Schroedinger-Poisson problem,
+    F = K V - beta (n(V) - n_D), with dn/dV assembled from gradient.py.
+  * definition.terminal_currents -- the current spectral density per contact,
+    Tr[Sigma^< G^> - Sigma^> G^<] over the contact block.
 
 Pins (tests/test_oracle_*.py, marked "not gpu"): mpmath brute force, the
 closed-form Green's function of the uniform hard-wall waveguide (retarded
@@ -31,5 +37,9 @@ the eta term, the paper's printed 3-cluster and 3-level block formulas, and
 central finite differences for the gradient.  With phonons: the 50-digit brute
 force, the waveguide closed form at z = E + i(eta + gamma/2) for a uniform
 Sigma^r_ph = -i gamma/2, and the fluctuation-dissipation identity
-G^< = -f (G^r - G^r+) at eta = 0 in equilibrium.
+G^< = -f (G^r - G^r+) at eta = 0 in equilibrium.  Born loop: D0 = 0, the
+fluctuation-dissipation pairs of every iterate, the fixed point.  Currents:
+Landauer's Tr[Gamma_L G_LR Gamma_R G_LR+] (f_L - f_R) and conservation.
+Newton step: dn/dV symmetric in equilibrium, central differences of F,
+quadratic convergence.
 """
