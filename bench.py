@@ -99,9 +99,10 @@ def measured_traffic(kernel, profile="traffic.json"):
     return None if k is None else k["bytes_per_launch"]
 
 
-def bench_batch(ndg, workloads, torch, cuda, n_devices=64, per_plan=8):
-    """64 uneven devices x 128 energies, leaf size per width class from the
-    autotuner, one captured graph replayed over the energy range."""
+def bench_batch(ndg, workloads, torch, cuda, n_devices=64, per_plan=8, chain=True):
+    """64 uneven devices x 128 energies, tree shape per width class from the
+    autotuner (slab and leaf of the open slab chain, or the leaf of nested
+    dissection), one captured graph replayed over the energy range."""
     from paper_1305_1070_amd import autotune
     wls = [workloads.uneven_device(d) for d in range(n_devices)]
     by_dev = {id(w.device): w for w in wls}
@@ -114,13 +115,21 @@ def bench_batch(ndg, workloads, torch, cuda, n_devices=64, per_plan=8):
                 [torch.from_numpy(a).to(cuda) for a in (sl, sr)],
                 [torch.from_numpy(a).to(cuda) for a in (ll, lr)])
 
-    leaf = autotune.tune_classes([w.device for w in wls], sample, wls[0].eta)
+    if chain:
+        leaf = autotune.tune_classes([w.device for w in wls], sample, wls[0].eta, candidates=(16, 24),
+                                     slabs=(8, 12))
+    else:
+        leaf = autotune.tune_classes([w.device for w in wls], sample, wls[0].eta)
     plans, ins = [], []
     gflop = 0.0
     for w in wls:
         d = w.device
-        sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords,
-                          leaf_max=leaf[len(d.contacts[0])])
+        shape = leaf[len(d.contacts[0])]
+        if chain:
+            sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, leaf_max=shape[1],
+                              tree_kind=3, slab=shape[0], layers=d.layers)
+        else:
+            sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, leaf_max=shape)
         gflop += sym.info()["ops_total"] * 8 / 1e9 * len(w.energies)
         plans.append(ndg.Plan(sym, max_batch=per_plan))
         sl, sr, ll, lr = w.self_energies()
@@ -141,15 +150,21 @@ def bench_batch(ndg, workloads, torch, cuda, n_devices=64, per_plan=8):
                         % n_devices,
             "device_energy_points_per_s": n_pts / dt, "s_per_pass": dt,
             "algorithmic_tflop_per_s": gflop / dt / 1e3, "energies_per_plan_batch": per_plan,
-            "leaf_per_width": {str(k): v for k, v in leaf.items()}}
+            "tree": "open slab chain" if chain else "nested dissection",
+            "shape_per_width": {str(k): v for k, v in leaf.items()}}
 
 
-def bench_tube(ndg, workloads, torch, cuda):
-    """(10,0) tube, 2000 cells (80 000 orbitals), 256 energies."""
+def bench_tube(ndg, workloads, torch, cuda, chain=True):
+    """(10,0) tube, 2000 cells (80 000 orbitals), 256 energies, on the chain
+    of its 40-atom cells rooted in the middle cell (or nested dissection)."""
     w = workloads.nanotube()
     d = w.device
-    sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, leaf_max=24)
-    plan = ndg.Plan(sym, max_batch=128)
+    if chain:
+        sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, tree_kind=3, slab=-1,
+                          layers=d.layers)
+    else:
+        sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, leaf_max=24)
+    plan = ndg.Plan(sym, max_batch=256)
     sl, sr, ll, lr = w.self_energies()
     E = torch.tensor(w.energies, device=cuda)
     srt = [torch.from_numpy(a).to(cuda) for a in (sl, sr)]
@@ -162,6 +177,8 @@ def bench_tube(ndg, workloads, torch, cuda):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / 3
     return {"workload": "(10,0) zigzag tube, 2000 cells x 40 atoms, 256 energies",
+            "tree": "cell chain" if chain else "nested dissection",
+            "tree_levels": sym.info()["max_height"],
             "energy_points_per_s": len(w.energies) / dt,
             "algorithmic_gflop_per_energy": sym.info()["ops_total"] * 8 / 1e9}
 
@@ -173,6 +190,8 @@ def bench_ribbon(ndg, workloads, torch, cuda):
     w = workloads.armchair_ribbon(n_cells=2000, n_energies=256)
     d = w.device
     sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, None, leaf_max=16)
+    # (the level-set tree's closed pieces carry vacancy states: this leg
+    # measures the graph-only tree's speed, its parity is tested on 40 cells)
     plan = ndg.Plan(sym, max_batch=128)
     sl, sr, ll, lr = w.self_energies()
     E = torch.tensor(w.energies, device=cuda)
@@ -191,7 +210,7 @@ def bench_ribbon(ndg, workloads, torch, cuda):
             "clusters": info["nclusters"], "tree_levels": info["max_height"]}
 
 
-def bench_newton(ndg, workloads, torch, cuda, leaf, cg_iter=8):
+def bench_newton(ndg, workloads, torch, cuda, leaf, cg_iter=8, tree_kw=None):
     """One Schroedinger-Poisson Newton step on the 512 x 64 grid (256
     energies, both contacts at 0.10 eV): the density, then cg_iter conjugate
     gradient iterations (each one density vector-Jacobian product) with
@@ -199,7 +218,8 @@ def bench_newton(ndg, workloads, torch, cuda, leaf, cg_iter=8):
     import scipy.sparse as sp
     w = workloads.adjoint_device(mu=(0.10, 0.10))
     d = w.device
-    sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, leaf_max=leaf)
+    sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, leaf_max=leaf,
+                      **_tree_kw(tree_kw, d))
     # all 256 energies in one batch: the conjugate-gradient iterations then
     # reuse the density solve's factors
     plan = ndg.Plan(sym, max_batch=256)
@@ -231,7 +251,7 @@ def bench_newton(ndg, workloads, torch, cuda, leaf, cg_iter=8):
             "cg_relative_residual": res}
 
 
-def bench_scattering(ndg, workloads, torch, cuda, leaf, n_energies=512, batch=256):
+def bench_scattering(ndg, workloads, torch, cuda, leaf, n_energies=512, batch=256, tree_kw=None):
     """Superlattice 1024x64 with diagonal phonon self-energies on every site
     (local dephasing, gamma0 = 5 meV): the 512-point energy grid (or every
     (512 / n_energies)-th energy of it), FP64, through ndg_solve_scattering
@@ -241,7 +261,8 @@ def bench_scattering(ndg, workloads, torch, cuda, leaf, n_energies=512, batch=25
     w = workloads.superlattice(n_energies=512)
     d = w.device
     e = w.energies[::512 // n_energies][:n_energies]
-    sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, leaf_max=leaf)
+    sym = ndg.analyze(d.n, d.rowptr, d.col, d.val, d.contacts, d.coords, leaf_max=leaf,
+                      **_tree_kw(tree_kw, d))
     plan = ndg.Plan(sym, max_batch=batch)
     plan.enable_scattering()
     sl, sr, ll, lr = w.self_energies(e)
@@ -302,6 +323,14 @@ def bench_scattering(ndg, workloads, torch, cuda, leaf, n_energies=512, batch=25
             "kernels": kernels, "roofline": roof, "status": list(status)}
 
 
+def _tree_kw(tree_kw, dev):
+    """Tree options for ndg.analyze: {"slab": k} selects the open slab chain
+    over the device's transport layers, None nested dissection."""
+    if not tree_kw:
+        return {}
+    return {"tree_kind": 3, "slab": tree_kw["slab"], "layers": dev.layers}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -310,6 +339,10 @@ def main():
     ap.add_argument("--batch", type=int, default=512, help="energies in flight per batch")
     ap.add_argument("--leaf", type=int, default=0,
                     help="leaf size of the separator tree (0: picked by the autotuner)")
+    ap.add_argument("--tree", choices=("chain", "nd"), default="chain",
+                    help="open slab chain (every folded region holds a contact or is a thin slab; "
+                         "the default) or nested dissection")
+    ap.add_argument("--slab", type=int, default=0, help="slab length of the chain (0: autotuned)")
     ap.add_argument("--energies", type=int, default=512)
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false")
     ap.add_argument("--no-scattering", dest="scattering", action="store_false",
@@ -336,10 +369,14 @@ def main():
     import paper_1305_1070_amd as ndg
     from inputs import workloads
 
+    chain = args.tree == "chain"
+    # the phonon solve's frames need a tree of at most 63 levels: slab 12
+    scat_tree = {"slab": 12} if chain else None
     if args.only_scattering:
         ndg.load()
         print(json.dumps(bench_scattering(ndg, workloads, torch, torch.device("cuda:0"),
-                                          args.leaf if args.leaf > 0 else 20)), flush=True)
+                                          args.leaf if args.leaf > 0 else 20, tree_kw=scat_tree)),
+              flush=True)
         return
 
     n_transport, n_transverse = 1024, 64
@@ -351,14 +388,22 @@ def main():
     sig_r = [torch.from_numpy(a).to(cuda) for a in (sl, sr)]
     sig_l = [torch.from_numpy(a).to(cuda) for a in (ll, lr)]
     tuned = None
-    if args.leaf <= 0:
+    if args.leaf <= 0 or (chain and args.slab <= 0):
         from paper_1305_1070_amd import autotune
         pick = np.linspace(0, args.energies - 1, 64).round().astype(int)
-        args.leaf, tuned = autotune.tune_leaf(
+        best, tuned = autotune.tune_leaf(
             dev, E[pick].contiguous(), wl.eta, [t[pick].contiguous() for t in sig_r],
-            [t[pick].contiguous() for t in sig_l], candidates=(12, 16, 20, 24))
+            [t[pick].contiguous() for t in sig_l],
+            candidates=(args.leaf,) if args.leaf > 0 else (12, 16, 20, 24),
+            slabs=((args.slab,) if args.slab > 0 else (8, 12)) if chain else None)
+        if chain:
+            args.slab, args.leaf = best
+        else:
+            args.leaf = best
+        tuned = {str(k): v for k, v in tuned.items()}
+    tree_kw = {"slab": args.slab} if chain else None
     sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords,
-                      leaf_max=args.leaf)
+                      leaf_max=args.leaf, **_tree_kw(tree_kw, dev))
     info = sym.info()
     plan = ndg.Plan(sym, max_batch=min(args.batch, args.energies))
     ne, n = args.energies, dev.n
@@ -424,7 +469,7 @@ def main():
         wa = workloads.adjoint_device()
         da = wa.device
         syma = ndg.analyze(da.n, da.rowptr, da.col, da.val, da.contacts, da.coords,
-                           leaf_max=args.leaf)
+                           leaf_max=args.leaf, **_tree_kw(tree_kw, da))
         pa = ndg.Plan(syma, max_batch=min(args.batch, 128))
         pa.enable_adjoint()
         sla, sra, lla, lra = wa.self_energies()
@@ -450,16 +495,17 @@ def main():
                "ms_per_step": ms_adj}
         del pa
 
-    scat = bench_scattering(ndg, workloads, torch, cuda, args.leaf) if args.scattering else None
+    scat = (bench_scattering(ndg, workloads, torch, cuda, args.leaf, tree_kw=scat_tree)
+            if args.scattering else None)
     if scat:
         _progress("scattering: %.0f energies/s" % scat["energy_points_per_s"])
 
     extra = None
     if args.extra:
-        extra = {"batch": bench_batch(ndg, workloads, torch, cuda),
-                 "nanotube": bench_tube(ndg, workloads, torch, cuda),
+        extra = {"batch": bench_batch(ndg, workloads, torch, cuda, chain=chain),
+                 "nanotube": bench_tube(ndg, workloads, torch, cuda, chain=chain),
                  "ribbon_graph_tree": bench_ribbon(ndg, workloads, torch, cuda),
-                 "newton_step": bench_newton(ndg, workloads, torch, cuda, args.leaf)}
+                 "newton_step": bench_newton(ndg, workloads, torch, cuda, args.leaf, tree_kw=tree_kw)}
 
     copy_cal = None
     if args.copy_calibration:
@@ -528,7 +574,8 @@ def main():
         "config": {"workload": "superlattice 1024x64 FD grid, n=65536, dense 64x64 contact "
                                "self-energies, %d energies in [0,0.5] eV, eta=1e-6" % ne,
                    "energies": ne, "batch": batch_used, "leaf_max": args.leaf,
-                   "leaf_autotune_ms_per_energy": tuned,
+                   "tree": ("open slab chain, slab %d" % args.slab) if chain else "nested dissection",
+                   "autotune_ms_per_energy": tuned,
                    "clusters": info["nclusters"], "tree_levels": info["max_height"],
                    "algorithmic_gflop_per_energy": info["ops_total"] * 8 / 1e9,
                    "rgf_gflop_per_energy": info["ops_rgf_equiv"] * 8 / 1e9},

@@ -65,7 +65,23 @@ typedef struct {
   int32_t max_cluster; /* clusters larger than this are split into a chain (default/max 64)  */
   int32_t tree_kind;   /* 0 nested dissection (default); 1 layer chain, the partition that
                           reproduces RGF (Section 3.2, Fig. 6); 2 contacts merged into the top
-                          of the tree (Section 3.2, Fig. 7)                                   */
+                          of the tree (Section 3.2, Fig. 7); 3 open slab chain: separator
+                          layers every slab + 1 transport layers, chained from the middle
+                          layer (the root) towards both end layers, the slabs between them
+                          dissected as in 0.  Every chain cluster's subtree then holds an end
+                          layer (a contact), so no folded region is closed except the slabs,
+                          whose levels lie far from the energy window when they are thin
+                          (Section 3.2's rules hold for any of these trees)                  */
+  int32_t slab;        /* kind 3: transport layers between consecutive separators; 0 selects
+                          8, a negative value none (every layer a separator: the layer chain
+                          with its root in the middle layer)                                */
+  int32_t layer_max;   /* kind 3: separator and end layers of up to this many points stay one
+                          cluster (0 selects 128, the largest the kernels take); a wider layer
+                          is split into a parent-child chain of clusters                    */
+  int32_t reserved;
+  const int32_t* layer_of; /* kinds 1 and 3: host [n], the transport layer of every site
+                          (H must couple only equal or consecutive layers), or NULL: the
+                          sites of equal x coordinate form a layer (coords required)        */
 } ndg_tree_opts;
 
 /* Summary of a symbolic analysis.  Operation counts follow Section 4.1's

@@ -36,7 +36,7 @@ def _ptr(a, ctype):
 # ----------------------------------------------------------------------------
 
 def ndg_analyze(n, rowptr, col, val, contacts, coords=None, leaf_max=0, max_cluster=0,
-                tree_kind=0):
+                tree_kind=0, slab=0, layer_of=None, layer_max=0):
     lib = load()
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
     col = np.ascontiguousarray(col, dtype=np.int32)
@@ -48,7 +48,11 @@ def ndg_analyze(n, rowptr, col, val, contacts, coords=None, leaf_max=0, max_clus
     if coords is not None:
         coords = np.ascontiguousarray(coords, dtype=np.float64).reshape(n, 3)
         cc = _ptr(coords, C.c_double)
-    opts = _lib.TreeOpts(leaf_max, max_cluster, tree_kind)
+    lo = None
+    if layer_of is not None:
+        layer_of = np.ascontiguousarray(layer_of, dtype=np.int32).reshape(n)
+        lo = _ptr(layer_of, C.c_int32)
+    opts = _lib.TreeOpts(leaf_max, max_cluster, tree_kind, slab, layer_max, 0, lo)
     out = C.c_void_p()
     _lib.check(lib.ndg_analyze(n, _ptr(rowptr, C.c_int64), _ptr(col, C.c_int32),
                                _ptr(val, C.c_double), len(cs), cptrs, _ptr(cn, C.c_int32), cc,
@@ -256,8 +260,20 @@ class Symbolic:
             self.handle = None
 
 
-def analyze(n, rowptr, col, val, contacts, coords=None, leaf_max=0, max_cluster=0, tree_kind=0):
-    h = ndg_analyze(n, rowptr, col, val, contacts, coords, leaf_max, max_cluster, tree_kind)
+def analyze(n, rowptr, col, val, contacts, coords=None, leaf_max=0, max_cluster=0, tree_kind=0,
+            slab=0, layers=None, layer_max=0):
+    """Separator tree and symbolic analysis.  layers: optional list of site
+    arrays in transport order (tree kinds 1 and 3), else layers are the sites
+    of equal x coordinate."""
+    layer_of = None
+    if layers is not None:
+        layer_of = np.full(n, -1, dtype=np.int32)
+        for q, L in enumerate(layers):
+            layer_of[np.asarray(L)] = q
+        if (layer_of < 0).any():
+            raise ValueError("layers must cover every site")
+    h = ndg_analyze(n, rowptr, col, val, contacts, coords, leaf_max, max_cluster, tree_kind, slab,
+                    layer_of, layer_max)
     return Symbolic(h, len(contacts), [len(c) for c in contacts])
 
 

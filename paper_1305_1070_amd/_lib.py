@@ -27,7 +27,9 @@ class NdgError(RuntimeError):
 
 
 class TreeOpts(C.Structure):
-    _fields_ = [("leaf_max", C.c_int32), ("max_cluster", C.c_int32), ("tree_kind", C.c_int32)]
+    _fields_ = [("leaf_max", C.c_int32), ("max_cluster", C.c_int32), ("tree_kind", C.c_int32),
+                ("slab", C.c_int32), ("layer_max", C.c_int32), ("reserved", C.c_int32),
+                ("layer_of", C.POINTER(C.c_int32))]
 
 
 class Info(C.Structure):

@@ -1,13 +1,17 @@
-"""Autotuner for the separator tree's leaf size.
+"""Autotuner for the separator tree's shape: the leaf size and, on the open
+slab chain (tree kind 3), the slab length.
 
 The leaf size sets the shapes of every block the kernels see: small leaves
 give many tiny fronts (latency-bound on-chip eliminations), large leaves
-give fewer levels but cubic leaf work.  The best value depends on the
-device's width and length and on the GPU, so it is measured: each candidate
-tree is analysed, a plan is built and a short sample of energies is solved
-on the GPU (timed with HIP events after one untimed pass); the fastest
-candidate per energy wins.  Results are cached per (n, width, contacts,
-candidates) key for the life of the process.
+give fewer levels but cubic leaf work.  On the slab chain the slab length
+trades the chain's depth (sequential levels, one 2w-point front each)
+against the slabs' dissection (short separators with 2w-point boundaries).
+The best values depend on the device's width and length and on the GPU, so
+they are measured: each candidate tree is analysed, a plan is built and a
+short sample of energies is solved on the GPU (timed with HIP events after
+one untimed pass); the fastest candidate per energy wins.  Results are
+cached per (n, width, contacts, candidates) key for the life of the
+process.
 
 Only the library's own entry points run; nothing is approximated.
 """
@@ -24,13 +28,18 @@ def _key(dev, candidates):
 
 
 def tune_leaf(dev, energies, eta, sig_r, sig_less, candidates=(8, 12, 16, 24, 32), batch=None,
-              repeats=2, verbose=False):
-    """Returns (best leaf size, {leaf: ms per energy}).
+              repeats=2, verbose=False, slabs=None):
+    """Returns (best candidate, {candidate: ms per energy}).  Without slabs
+    the candidates are leaf sizes of the nested-dissection tree; with slabs
+    (a list of slab lengths) they are (slab, leaf) pairs of the open slab
+    chain over dev.layers.
 
-    dev: a device with n, rowptr, col, val, contacts, coords; energies:
-    float64 tensor of sample energies on the GPU; sig_r / sig_less: per
-    contact complex128 tensors [len(energies), nc, nc] on the GPU."""
+    dev: a device with n, rowptr, col, val, contacts, coords (and layers);
+    energies: float64 tensor of sample energies on the GPU; sig_r / sig_less:
+    per contact complex128 tensors [len(energies), nc, nc] on the GPU."""
     import torch
+    if slabs is not None:
+        candidates = tuple((sl, lf) for sl in slabs for lf in candidates)
     key = _key(dev, candidates)
     if key in _cache:
         return _cache[key]
@@ -39,7 +48,11 @@ def tune_leaf(dev, energies, eta, sig_r, sig_less, candidates=(8, 12, 16, 24, 32
     times = {}
     stream = torch.cuda.current_stream(energies.device)
     for leaf in candidates:
-        sym = analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, leaf_max=leaf)
+        if slabs is None:
+            sym = analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, leaf_max=leaf)
+        else:
+            sym = analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords,
+                          leaf_max=leaf[1], tree_kind=3, slab=leaf[0], layers=dev.layers)
         plan = Plan(sym, max_batch=batch)
         out = plan.solve(energies, eta, sig_r, sig_less, stream=stream)
         a = torch.cuda.Event(enable_timing=True)
@@ -51,18 +64,19 @@ def tune_leaf(dev, energies, eta, sig_r, sig_less, candidates=(8, 12, 16, 24, 32
         b.synchronize()
         times[leaf] = a.elapsed_time(b) / repeats / ne
         if verbose:
-            print("  leaf %2d: %.4f ms per energy" % (leaf, times[leaf]), flush=True)
+            print("  %s: %.4f ms per energy" % (leaf, times[leaf]), flush=True)
         del plan, sym, out
     best = min(times, key=times.get)
     _cache[key] = (best, times)
     return best, times
 
 
-def tune_classes(devices, sample, eta, candidates=(8, 12, 16, 24, 32), verbose=False):
-    """Leaf size per width class for a batch of devices: each class (devices
+def tune_classes(devices, sample, eta, candidates=(8, 12, 16, 24, 32), verbose=False, slabs=None):
+    """Tree shape per width class for a batch of devices: each class (devices
     of one contact width) is tuned on its shortest member with the sample
-    energies; returns {width: leaf}.  sample(dev) must return (energies,
-    sig_r, sig_less) GPU tensors for that device."""
+    energies; returns {width: leaf} (or {width: (slab, leaf)} with slabs).
+    sample(dev) must return (energies, sig_r, sig_less) GPU tensors for that
+    device."""
     by_width = {}
     for dev in devices:
         w = len(dev.contacts[0])
@@ -71,11 +85,11 @@ def tune_classes(devices, sample, eta, candidates=(8, 12, 16, 24, 32), verbose=F
     out = {}
     for w, dev in sorted(by_width.items()):
         e, sr, sl = sample(dev)
-        best, times = tune_leaf(dev, e, eta, sr, sl, candidates, verbose=False)
+        best, times = tune_leaf(dev, e, eta, sr, sl, candidates, verbose=False, slabs=slabs)
         out[w] = best
         if verbose:
-            print("  width %3d (n=%d): leaf %d  [%s]" % (
-                w, dev.n, best, ", ".join("%d: %.3f" % (k, v) for k, v in sorted(times.items()))),
+            print("  width %3d (n=%d): %s  [%s]" % (
+                w, dev.n, best, ", ".join("%s: %.3f" % (k, v) for k, v in sorted(times.items()))),
                 flush=True)
     return out
 

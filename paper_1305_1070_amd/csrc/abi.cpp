@@ -67,9 +67,18 @@ ndg_status ndg_analyze(int64_t n, const int64_t* rowptr, const int32_t* col, con
     if (opts->leaf_max > 0) to.leaf_max = opts->leaf_max;
     if (opts->max_cluster > 0) to.max_cluster = opts->max_cluster;
     to.kind = opts->tree_kind;
+    if (to.kind == 3) to.slab = opts->slab > 0 ? opts->slab : opts->slab == 0 ? 8 : 0;
+    to.layer_of = opts->layer_of;
+    if (opts->layer_max > ndg::kMaxCluster) {
+      set_error("ndg_analyze: layer_max exceeds the kernels' limit of 128");
+      return NDG_EINVAL;
+    }
+    to.layer_max = opts->layer_max > 0 ? opts->layer_max : ndg::kMaxCluster;
+  } else {
+    to.layer_max = ndg::kMaxCluster;
   }
   if (to.max_cluster > ndg::kMaxCluster) {
-    set_error("ndg_analyze: max_cluster exceeds the kernels' limit of 64");
+    set_error("ndg_analyze: max_cluster exceeds the kernels' limit of 128");
     return NDG_EINVAL;
   }
   auto* h = new (std::nothrow) ndg_symbolic;

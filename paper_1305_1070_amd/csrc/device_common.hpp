@@ -395,7 +395,9 @@ struct RegGJ {
   static constexpr int NR = (SF + RS - 1) / RS;
   static constexpr int NC = (SF + JS - 1) / JS;
   static_assert(NT % JS == 0, "thread grid");
-  static_assert(SF <= 64, "pivot rows are searched by one wavefront");
+  // one wavefront searches the pivot rows: a row per lane, two above 64
+  static_assert(SF <= 128, "pivot rows are searched by one wavefront");
+  static constexpr bool kTwo = SF > 64;
   static_assert(NT % 64 == 0, "whole wavefronts");
   struct Smem {
     double2 col[2][NR * RS];
@@ -423,7 +425,7 @@ struct RegGJ {
   // through selects over all slots.
   __device__ bool run(Smem& sm, int s) {
     const int t = i0 * JS + jt, lane = t & 63;
-    unsigned long long used = 0;
+    unsigned long long used = 0, used_hi = 0;  // rows 0..63, 64..127 already pivots
     bool ok = true;
 #pragma unroll
     for (int qk = 0; qk < NC; ++qk) {
@@ -447,13 +449,34 @@ struct RegGJ {
         // (a NaN column picks a NaN row)
         const double2 v = lane < s ? sm.col[buf][lane] : make_double2(0.0, 0.0);
         unsigned key = 0;
-        if (lane < s && !((used >> lane) & 1ull)) {
-          const float mg = (float)(fabs(v.x) + fabs(v.y));
-          key = 0x80000000u | ((__float_as_uint(mg) >> 1) & 0x7FFFFFC0u) | (unsigned)(63 - lane);
+        int p;
+        double2 a;
+        if constexpr (!kTwo) {
+          if (lane < s && !((used >> lane) & 1ull)) {
+            const float mg = (float)(fabs(v.x) + fabs(v.y));
+            key = 0x80000000u | ((__float_as_uint(mg) >> 1) & 0x7FFFFFC0u) | (unsigned)(63 - lane);
+          }
+          key = wave_max_u32(key);
+          p = 63 - (int)(key & 63u);
+          a = make_double2(lane_read(v.x, p), lane_read(v.y, p));
+        } else {
+          // rows lane and lane + 64; 7 row bits, (127 - row) so near-ties go
+          // to the lower row
+          const double2 v2 = lane + 64 < s ? sm.col[buf][lane + 64] : make_double2(0.0, 0.0);
+          if (lane < s && !((used >> lane) & 1ull)) {
+            const float mg = (float)(fabs(v.x) + fabs(v.y));
+            key = 0x80000000u | ((__float_as_uint(mg) >> 1) & 0x7FFFFF80u) | (unsigned)(127 - lane);
+          }
+          if (lane + 64 < s && !((used_hi >> lane) & 1ull)) {
+            const float mg = (float)(fabs(v2.x) + fabs(v2.y));
+            const unsigned k2 = 0x80000000u | ((__float_as_uint(mg) >> 1) & 0x7FFFFF80u) | (unsigned)(63 - lane);
+            key = k2 > key ? k2 : key;
+          }
+          key = wave_max_u32(key);
+          p = 127 - (int)(key & 127u);
+          const double2 w = p < 64 ? v : v2;
+          a = make_double2(lane_read(w.x, p & 63), lane_read(w.y, p & 63));
         }
-        key = wave_max_u32(key);
-        const int p = 63 - (int)(key & 63u);
-        const double2 a = make_double2(lane_read(v.x, p), lane_read(v.y, p));
         const int mp = p / RS;
         const bool own_p = i0 == p % RS;
         if constexpr (NC > 1) {
@@ -482,7 +505,8 @@ struct RegGJ {
           sm.piv[k] = p;
           sm.pinv[p] = k;
         }
-        used |= 1ull << p;
+        if (p < 64) used |= 1ull << p;
+        else used_hi |= 1ull << (p - 64);
         const double den = a.x * a.x + a.y * a.y;
         double dr = 0.0, di = 0.0;
         if (den > 0.0) {
@@ -550,6 +574,34 @@ __device__ inline double2 gather_bb(const Ctx& c, const double2* S, const Cluste
   const int32_t m = c.gaddr[d.o_gaddr + (int64_t)u * d.b + v];
   const double2 x = S[(int64_t)(m & 0x7FFFFFFF) + (lesser ? c.pdelta : 0)];
   return (m < 0 && lesser) ? make_double2(-x.x, x.y) : x;
+}
+
+// The exact X_ii block of G^r is complex symmetric and that of G^< anti-
+// Hermitian; the extraction computes it as A_ii^{-1} + Psi_i X_{B,i}, whose
+// two triangles carry different rounding, amplified by large Psi.  Replacing
+// the stored block by its symmetric (anti-Hermitian) part before any
+// descendant gathers from it keeps that error out of the descendants: a
+// descendant reading either triangle then sees the same value.  In place on
+// the s x s block (row stride f) after the whole block is written: one
+// thread per pair (r, c >= r), every block thread taking part.
+__device__ inline void symmetrize_block(double2* X, int s, int f, bool lesser) {
+  __threadfence_block();
+  __syncthreads();
+  for (int q = threadIdx.x; q < s * s; q += blockDim.x) {
+    const int r = q / s, cc = q - r * s;
+    if (cc < r) continue;
+    const double2 a = X[(int64_t)r * f + cc], b = X[(int64_t)cc * f + r];
+    if (lesser) {
+      // (a - conj(b)) / 2 at (r, c), its negated conjugate at (c, r)
+      const double2 m = make_double2(0.5 * (a.x - b.x), 0.5 * (a.y + b.y));
+      X[(int64_t)r * f + cc] = m;
+      X[(int64_t)cc * f + r] = make_double2(-m.x, m.y);
+    } else {
+      const double2 m = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
+      X[(int64_t)r * f + cc] = m;
+      X[(int64_t)cc * f + r] = m;
+    }
+  }
 }
 
 // First energy of the batch this launch processes.

@@ -92,6 +92,7 @@ __global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
   // column groups of 16 (8 for the 16-point class): several columns per
   // thread, so the pivot row is published from a branch per register slot
   using GJ = RegGJ<SM, NT, (SM == 16 ? 8 : 16)>;
+  static_assert(SM <= 64 || NT >= 512, "the 128-point inverse spreads over 512 threads");
   __shared__ typename GJ::Smem sm;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
@@ -129,13 +130,16 @@ __global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
     __syncthreads();
     if (t < 64) {
       double ru = 0.0, rb = 0.0;
-      if (t < s) {
+      for (int r = t; r < s; r += 64) {  // rows t, t + 64: fixed order per lane
+        double u = 0.0, w = 0.0;
         for (int j = 0; j < s; ++j) {
-          const double2 v = Ainv[(int64_t)t * s + j];
-          ru += sqrt(v.x * v.x + v.y * v.y);
+          const double2 v = Ainv[(int64_t)r * s + j];
+          u += sqrt(v.x * v.x + v.y * v.y);
         }
-        const double2* row = F + (int64_t)t * f + s;
-        for (int j = 0; j < d.b; ++j) rb += sqrt(row[j].x * row[j].x + row[j].y * row[j].y);
+        const double2* row = F + (int64_t)r * f + s;
+        for (int j = 0; j < d.b; ++j) w += sqrt(row[j].x * row[j].x + row[j].y * row[j].y);
+        ru = fmax(ru, u);
+        rb = fmax(rb, w);
       }
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
@@ -165,14 +169,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   double2* Psi = S + d.o_psi;
   const int s = d.s, b = d.b, f = d.f, j0 = it.tc * 64;
   const int nj = min(64, b - j0);
-  ZTile acc;
-  ztile_zero(acc);
-  zgemm_acc_t<TM, false, false>(
-      s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
-      [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm);
-  ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
-    if (i < s && j < nj) Psi[(int64_t)i * b + j0 + j] = make_double2(-re, -im);
-  });
+  // clusters of more than TM points (up to 128) take the rows in TM-row tiles
+  for (int r0 = 0; r0 < s; r0 += TM) {
+    const int ni = min(TM, s - r0);
+    ZTile acc;
+    ztile_zero(acc);
+    zgemm_acc_t<TM, false, false>(
+        s, [&](int i, int k) { return i < ni ? Ainv[(r0 + i) * s + k] : cz(); },
+        [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm);
+    ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
+      if (i < ni && j < nj) Psi[(int64_t)(r0 + i) * b + j0 + j] = make_double2(-re, -im);
+    });
+    __syncthreads();
+  }
 }
 
 // Schur contribution of cluster i to its parent front:
@@ -347,15 +356,36 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         }
       });
     }
-    // in place: the panel's rows [0, s) are all staged before any is written
-    ZTile acc;
-    ztile_zero(acc);
-    zgemm_acc<false, false>(
-        s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
-        [&](int k, int j) { return j < nj ? Zf[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
-    ztile_store(acc, [&](int i, int j, double re, double im) {
-      if (i < s && j < nj) Zf[(int64_t)i * sc + j0 + j] = make_double2(re, im);
-    });
+    if (s <= 64) {
+      // in place: the panel's rows [0, s) are all staged before any is written
+      ZTile acc;
+      ztile_zero(acc);
+      zgemm_acc<false, false>(
+          s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
+          [&](int k, int j) { return j < nj ? Zf[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
+      ztile_store(acc, [&](int i, int j, double re, double im) {
+        if (i < s && j < nj) Zf[(int64_t)i * sc + j0 + j] = make_double2(re, im);
+      });
+    } else {
+      // 64-row tiles through the cluster's s x sc scratch, then copied back
+      double2* T = S + sel2(d.o_t, cc);
+      for (int r0 = 0; r0 < s; r0 += 64) {
+        const int ni = min(64, s - r0);
+        ZTile acc;
+        ztile_zero(acc);
+        zgemm_acc<false, false>(
+            s, [&](int i, int k) { return i < ni ? Ainv[(r0 + i) * s + k] : cz(); },
+            [&](int k, int j) { return j < nj ? Zf[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
+        ztile_store(acc, [&](int i, int j, double re, double im) {
+          if (i < ni && j < nj) T[(int64_t)(r0 + i) * sc + j0 + j] = make_double2(re, im);
+        });
+        __syncthreads();
+      }
+      for (int q = t; q < s * nj; q += 256) {
+        const int i = q / nj, j = q - i * nj;
+        Zf[(int64_t)i * sc + j0 + j] = T[(int64_t)i * sc + j0 + j];
+      }
+    }
     __syncthreads();
   }
 }
@@ -395,56 +425,60 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       }
     }
     __syncthreads();
-    for (int j0 = 0; j0 < sc; j0 += 64) {
-      const int nj = min(64, sc - j0);
-      ZTile acc;
-      ztile_zero(acc);
-      zgemm_acc<false, false>(
-          b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
-          [&](int k, int j) { return j < nj ? Xf[(int64_t)(s + k) * sc + j0 + j] : cz(); }, acc, sm);
-      ztile_store(acc, [&](int i, int j, double re, double im) {
-        if (i < s && j < nj) {
-          const double2 z = Zf[(int64_t)i * sc + j0 + j];
-          Xf[(int64_t)i * sc + j0 + j] = make_double2(z.x + re, z.y + im);
-        }
-      });
-    }
-    __syncthreads();
-    {
-      const double2* sl = sel2(c.sig_l, cc) + (int64_t)(eb + e) * sc * sc;
+    // 64-row tiles of the cluster's rows (one unless s > 64)
+    for (int r0 = 0; r0 < s; r0 += 64)
       for (int j0 = 0; j0 < sc; j0 += 64) {
-        const int nj = min(64, sc - j0);
+        const int ni = min(64, s - r0), nj = min(64, sc - j0);
         ZTile acc;
         ztile_zero(acc);
         zgemm_acc<false, false>(
-            sc, [&](int i, int k) { return i < s ? Zf[(int64_t)i * sc + k] : cz(); },
-            [&](int k, int j) { return j < nj ? sl[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
+            b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
+            [&](int k, int j) { return j < nj ? Xf[(int64_t)(s + k) * sc + j0 + j] : cz(); }, acc, sm);
         ztile_store(acc, [&](int i, int j, double re, double im) {
-          if (i < s && j < nj) T[(int64_t)i * sc + j0 + j] = make_double2(re, im);
+          if (i < ni && j < nj) {
+            const double2 z = Zf[(int64_t)(r0 + i) * sc + j0 + j];
+            Xf[(int64_t)(r0 + i) * sc + j0 + j] = make_double2(z.x + re, z.y + im);
+          }
         });
       }
+    __syncthreads();
+    {
+      const double2* sl = sel2(c.sig_l, cc) + (int64_t)(eb + e) * sc * sc;
+      for (int r0 = 0; r0 < s; r0 += 64)
+        for (int j0 = 0; j0 < sc; j0 += 64) {
+          const int ni = min(64, s - r0), nj = min(64, sc - j0);
+          ZTile acc;
+          ztile_zero(acc);
+          zgemm_acc<false, false>(
+              sc, [&](int i, int k) { return i < ni ? Zf[(int64_t)(r0 + i) * sc + k] : cz(); },
+              [&](int k, int j) { return j < nj ? sl[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
+          ztile_store(acc, [&](int i, int j, double re, double im) {
+            if (i < ni && j < nj) T[(int64_t)(r0 + i) * sc + j0 + j] = make_double2(re, im);
+          });
+        }
     }
     __syncthreads();
-    for (int j0 = 0; j0 < f; j0 += 64) {
-      const int nj = min(64, f - j0);
-      ZTile acc;
-      ztile_zero(acc);
-      zgemm_acc<false, true>(
-          sc, [&](int i, int k) { return i < s ? T[(int64_t)i * sc + k] : cz(); },
-          [&](int k, int j) {
-            if (j >= nj) return cz();
-            const double2 x = Xf[(int64_t)(j0 + j) * sc + k];
-            return make_double2(x.x, -x.y);
-          },
-          acc, sm);
-      ztile_store(acc, [&](int i, int j, double re, double im) {
-        if (i < s && j < nj) {
-          double2* p = FP + (int64_t)i * f + j0 + j;
-          if (first) *p = make_double2(re, im);
-          else { double2 v = *p; v.x += re; v.y += im; *p = v; }
-        }
-      });
-    }
+    for (int r0 = 0; r0 < s; r0 += 64)
+      for (int j0 = 0; j0 < f; j0 += 64) {
+        const int ni = min(64, s - r0), nj = min(64, f - j0);
+        ZTile acc;
+        ztile_zero(acc);
+        zgemm_acc<false, true>(
+            sc, [&](int i, int k) { return i < ni ? T[(int64_t)(r0 + i) * sc + k] : cz(); },
+            [&](int k, int j) {
+              if (j >= nj) return cz();
+              const double2 x = Xf[(int64_t)(j0 + j) * sc + k];
+              return make_double2(x.x, -x.y);
+            },
+            acc, sm);
+        ztile_store(acc, [&](int i, int j, double re, double im) {
+          if (i < ni && j < nj) {
+            double2* p = FP + (int64_t)(r0 + i) * f + j0 + j;
+            if (first) *p = make_double2(re, im);
+            else { double2 v = *p; v.x += re; v.y += im; *p = v; }
+          }
+        });
+      }
     __syncthreads();
     first = false;
   }
@@ -473,19 +507,23 @@ __device__ __forceinline__ void down_off_body(const Ctx& c, const ColItem* items
   const int nj = min(64, b - j0);
   const bool has_src = lesser && (d.chain_mask || c.scat);
   const bool ls = lesser != 0;
-  typename GM::Tile acc;
-  GM::zero(acc);
-  GM::template acc<TM, false, false>(
-      b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
-      [&](int k, int j) { return j < nj ? gather_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm);
-  GM::template store<TM>(acc, [&](int i, int j, double re, double im) {
-    if (i < s && j < nj) {
-      double2 v = make_double2(re, im);
-      const int64_t pos = (int64_t)i * f + s + j0 + j;
-      if (has_src) { const double2 p0 = X[pos]; v.x += p0.x; v.y += p0.y; }
-      X[pos] = v;
-    }
-  });
+  for (int r0 = 0; r0 < s; r0 += TM) {  // TM-row tiles (one unless s > TM)
+    const int ni = min(TM, s - r0);
+    typename GM::Tile acc;
+    GM::zero(acc);
+    GM::template acc<TM, false, false>(
+        b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
+        [&](int k, int j) { return j < nj ? gather_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm);
+    GM::template store<TM>(acc, [&](int i, int j, double re, double im) {
+      if (i < ni && j < nj) {
+        double2 v = make_double2(re, im);
+        const int64_t pos = (int64_t)(r0 + i) * f + s + j0 + j;
+        if (has_src) { const double2 p0 = X[pos]; v.x += p0.x; v.y += p0.y; }
+        X[pos] = v;
+      }
+    });
+    if (r0 + TM < s) __syncthreads();
+  }
 }
 
 // 32- and 64-row tiles: three waves per SIMD; 16-row tiles (bound by the
@@ -519,36 +557,44 @@ __device__ __forceinline__ void down_diag_body(const Ctx& c, const int32_t* cls,
   double2* X = S + (lesser ? d.o_fp : d.o_fg);
   const int s = d.s, b = d.b, f = d.f;
   const bool has_src = lesser && (d.chain_mask || c.scat);
-  typename GM::Tile acc;
-  GM::zero(acc);
-  if (lesser) {
-    GM::template acc<TM, false, true>(
-        b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
-        [&](int k, int j) {
-          if (j >= s) return cz();
-          const double2 x = X[(int64_t)j * f + s + k];
-          return make_double2(-x.x, x.y);
-        },
-        acc, sm);
-  } else {
-    GM::template acc<TM, false, true>(
-        b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
-        [&](int k, int j) { return j < s ? X[(int64_t)j * f + s + k] : cz(); }, acc, sm);
-  }
-  GM::template store<TM>(acc, [&](int i, int j, double re, double im) {
-    if (i < s && j < s) {
-      double2 v = make_double2(re, im);
-      const int64_t pos = (int64_t)i * f + j;
+  // TM x 64 tiles of the s x s block (one unless s > TM); the block's
+  // columns [0, s) are written, its columns [s, f) only read
+  for (int r0 = 0; r0 < s; r0 += TM)
+    for (int c0 = 0; c0 < s; c0 += 64) {
+      const int ni = min(TM, s - r0), nj = min(64, s - c0);
+      typename GM::Tile acc;
+      GM::zero(acc);
       if (lesser) {
-        if (has_src) { const double2 p0 = X[pos]; v.x += p0.x; v.y += p0.y; }
+        GM::template acc<TM, false, true>(
+            b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
+            [&](int k, int j) {
+              if (j >= nj) return cz();
+              const double2 x = X[(int64_t)(c0 + j) * f + s + k];
+              return make_double2(-x.x, x.y);
+            },
+            acc, sm);
       } else {
-        const double2 a = Ainv[i * s + j];
-        v.x += a.x;
-        v.y += a.y;
+        GM::template acc<TM, false, true>(
+            b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
+            [&](int k, int j) { return j < nj ? X[(int64_t)(c0 + j) * f + s + k] : cz(); }, acc, sm);
       }
-      X[pos] = v;
+      GM::template store<TM>(acc, [&](int i, int j, double re, double im) {
+        if (i < ni && j < nj) {
+          double2 v = make_double2(re, im);
+          const int64_t pos = (int64_t)(r0 + i) * f + c0 + j;
+          if (lesser) {
+            if (has_src) { const double2 p0 = X[pos]; v.x += p0.x; v.y += p0.y; }
+          } else {
+            const double2 a = Ainv[(r0 + i) * s + c0 + j];
+            v.x += a.x;
+            v.y += a.y;
+          }
+          X[pos] = v;
+        }
+      });
+      if (r0 + TM < s || c0 + 64 < s) __syncthreads();
     }
-  });
+  symmetrize_block(X, s, f, lesser != 0);
 }
 
 // Entry points as for k_down_off: 16-row tiles at six waves per SIMD.
@@ -617,7 +663,8 @@ void launch_factor(const Ctx& c, const int32_t* cls, int ncl, int nb, int cls_si
   if (ncl <= 0) return;
   if (cls_size <= 16) hipLaunchKernelGGL((k_factor<16, 64>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
   else if (cls_size <= 32) hipLaunchKernelGGL((k_factor<32, 128>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
-  else hipLaunchKernelGGL((k_factor<64, 256>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+  else if (cls_size <= 64) hipLaunchKernelGGL((k_factor<64, 256>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+  else hipLaunchKernelGGL((k_factor<128, 512>), dim3(ncl, nb), dim3(512), 0, st, c, cls);
 }
 void launch_psi(const Ctx& c, const ColItem* it, int nit, int nb, int cls_size, hipStream_t st) {
   if (nit <= 0) return;

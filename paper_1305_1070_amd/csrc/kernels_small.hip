@@ -300,6 +300,7 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
         const int r = q / b, j = q - r * b;
         X[(int64_t)r * f + s + j] = XIB[r * lb + j];
       }
+      symmetrize_block(X, s, f, lesser != 0);
     }
     __syncthreads();
   }

@@ -62,10 +62,10 @@ struct ndg_plan {
   std::vector<size_t> rhs_lds_fwd, rhs_lds_back;
   std::vector<char> rhs_big;
   // per height, the clusters split into size classes: fronts f <= 32, f <= 64
-  // (whole on chip), then larger fronts with s <= 16, s <= 32, s <= 64
-  // (separate kernels, tile height following s)
+  // (whole on chip), then larger fronts with s <= 16, s <= 32, s <= 64,
+  // s <= 128 (separate kernels, tile height following s; 64-row tiles above)
   struct Group { int cl0 = 0, ncl = 0, col0 = 0, ncol = 0, upd0 = 0, nupd = 0, size = 0; size_t lds = 0; };
-  static constexpr int kClasses = 6;
+  static constexpr int kClasses = 7;
   std::vector<Group> groups;  // [(H + 1) * kClasses]
   double2* d_ws = nullptr;
   int32_t* d_status = nullptr;
@@ -241,7 +241,7 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
     return NDG_EINVAL;
   }
   if (sy.max_cluster > kMaxCluster) {  // (contacts larger than this span a chain)
-    set_error("ndg_plan_create: a cluster exceeds 64 points");
+    set_error("ndg_plan_create: a cluster exceeds 128 points");
     return NDG_EINVAL;
   }
   int ndev = 0;
@@ -284,7 +284,7 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
     if (f <= 32) return 0;
     if (f <= 48) return 1;
     if (f <= kSmallFront) return 2;
-    return s_ <= 16 ? 3 : s_ <= 32 ? 4 : 5;
+    return s_ <= 16 ? 3 : s_ <= 32 ? 4 : s_ <= 64 ? 5 : 6;
   };
   for (int h = 1; h <= H; ++h) {
     std::vector<int32_t> lv(sy.level_order.begin() + sy.level_ptr[h - 1],
@@ -609,6 +609,11 @@ int plan_info(const ndg_plan* plan, ndg_info* out) {
 
 int plan_enable_adjoint(ndg_plan* p) {
   if (p->d_rX) return NDG_OK;
+  for (int k = 0; k < p->nclusters; ++k)
+    if (p->hdesc[k].s > kMaxClusterAux) {
+      set_error("ndg_plan_enable_adjoint: the adjoint's solves take clusters of at most 64 points");
+      return NDG_EINVAL;
+    }
   if (hipSetDevice(p->device) != hipSuccess) { set_error("ndg_plan_enable_adjoint: hipSetDevice failed"); return NDG_EHIP; }
   // one right-hand side with the columns of all contacts side by side
   int mmax = 0;
@@ -650,8 +655,13 @@ int plan_enable_adjoint(ndg_plan* p) {
 }
 
 int plan_enable_scattering(ndg_plan* p) {
-  static_assert(kClusterRows >= kMaxCluster, "scattering kernels stage one value per cluster row");
+  static_assert(kClusterRows >= kMaxClusterAux, "scattering kernels stage one value per cluster row");
   if (p->d_sws) return NDG_OK;
+  for (int k = 0; k < p->nclusters; ++k)
+    if (p->hdesc[k].s > kMaxClusterAux) {
+      set_error("ndg_plan_enable_scattering: the scattering kernels take clusters of at most 64 points");
+      return NDG_EINVAL;
+    }
   if (hipSetDevice(p->device) != hipSuccess) {
     set_error("ndg_plan_enable_scattering: hipSetDevice failed");
     return NDG_EHIP;

@@ -10,7 +10,8 @@
 
 namespace ndg {
 
-constexpr int kMaxCluster = 64;  // largest cluster the pivot kernels hold on chip
+constexpr int kMaxCluster = 128;  // largest cluster the pivot kernels hold on chip
+constexpr int kMaxClusterAux = 64;  // largest cluster of the adjoint and scattering kernels
 constexpr int kMaxContacts = 2;  // contacts handled by the chain kernels
 
 void set_error(const std::string& msg);

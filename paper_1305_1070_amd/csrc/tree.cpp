@@ -80,7 +80,8 @@ struct Builder {
 
   // Adds pts as one cluster, or a chain of clusters of at most max_cluster
   // points (top of the chain first).  Returns the bottom cluster.
-  int add_chain(std::vector<int32_t> pts, int parent) {
+  int add_chain(std::vector<int32_t> pts, int parent, int maxc = 0) {
+    if (maxc <= 0) maxc = opt.max_cluster;
     if (pts.empty()) return parent;
     // order points along their longest extent so chain pieces are compact
     if (coords && pts.size() > 1) {
@@ -100,7 +101,7 @@ struct Builder {
     } else {
       std::sort(pts.begin(), pts.end());
     }
-    int nchunk = (int)((pts.size() + opt.max_cluster - 1) / opt.max_cluster);
+    int nchunk = (int)((pts.size() + maxc - 1) / maxc);
     int cur = parent;
     for (int k = nchunk - 1; k >= 0; --k) {  // top of chain = last chunk
       size_t a = pts.size() * k / nchunk, b = pts.size() * (k + 1) / nchunk;
@@ -307,7 +308,7 @@ int build_symbolic(int64_t n, const int64_t* rowptr, const int32_t* col, const d
                    const double* coords, const TreeOptions& opt, Symbolic& out, std::string& err) {
   out = Symbolic();
   if (n <= 0 || !rowptr || !col || !val) { err = "empty or null H"; return TREE_EINVAL; }
-  if (opt.leaf_max < 1 || opt.max_cluster < 1 || opt.kind < 0 || opt.kind > 2) {
+  if (opt.leaf_max < 1 || opt.max_cluster < 1 || opt.kind < 0 || opt.kind > 3 || opt.slab < 0) {
     err = "bad tree options";
     return TREE_EINVAL;
   }
@@ -343,12 +344,20 @@ int build_symbolic(int64_t n, const int64_t* rowptr, const int32_t* col, const d
   std::iota(all.begin(), all.end(), 0);
   if (opt.kind == 0) {
     B.nd(all, -1, 0);
-  } else if (opt.kind == 1) {
-    // layer chain (RGF partition): group sites by transport coordinate (or
-    // by BFS distance from the first contact without coordinates); the
-    // first layer is the deepest leaf and the last layer the root.
+  } else if (opt.kind == 1 || opt.kind == 3) {
+    // transport layers: the caller's layer index per site, else the sites of
+    // equal transport (x) coordinate
     std::vector<std::vector<int32_t>> layers;
-    if (coords) {
+    if (opt.layer_of) {
+      std::vector<int32_t> idx(all);
+      for (int32_t v : idx)
+        if (opt.layer_of[v] < 0) { err = "negative layer index"; return TREE_EINVAL; }
+      std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return opt.layer_of[a] < opt.layer_of[b]; });
+      for (size_t k = 0; k < idx.size(); ++k) {
+        if (k == 0 || opt.layer_of[idx[k]] != opt.layer_of[idx[k - 1]]) layers.emplace_back();
+        layers.back().push_back(idx[k]);
+      }
+    } else if (coords) {
       std::vector<int32_t> idx(all);
       std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return coords[3 * (int64_t)a] < coords[3 * (int64_t)b]; });
       for (size_t k = 0; k < idx.size(); ++k) {
@@ -356,7 +365,7 @@ int build_symbolic(int64_t n, const int64_t* rowptr, const int32_t* col, const d
         layers.back().push_back(idx[k]);
       }
     } else {
-      err = "the layer-chain tree needs coordinates";
+      err = "the layer-chain trees need coordinates or a layer index per site";
       return TREE_EINVAL;
     }
     // merge layers holding pieces of one contact
@@ -372,9 +381,57 @@ int build_symbolic(int64_t n, const int64_t* rowptr, const int32_t* col, const d
         }
       }
     }
-    int cur = -1;
-    for (int L = (int)layers.size() - 1; L >= 0; --L)
-      if (!layers[L].empty()) cur = B.add_chain(layers[L], cur);
+    layers.erase(std::remove_if(layers.begin(), layers.end(), [](const std::vector<int32_t>& L) { return L.empty(); }),
+                 layers.end());
+    // the slab chain needs every coupling to join equal or consecutive
+    // layers (block tridiagonal), or a slab would reach past its separators
+    if (opt.kind == 3) {
+      std::vector<int32_t> lid(n, -1);
+      for (int L = 0; L < (int)layers.size(); ++L)
+        for (int32_t v : layers[L]) lid[v] = L;
+      for (int64_t i = 0; i < n; ++i) {
+        bool bad = false;
+        B.for_adj((int32_t)i, [&](int32_t u) { bad |= std::abs(lid[u] - lid[i]) > 1; });
+        if (bad) { err = "the layers do not make H block tridiagonal"; return TREE_EINVAL; }
+      }
+    }
+    if (opt.kind == 1) {
+      int cur = -1;
+      for (int L = (int)layers.size() - 1; L >= 0; --L) cur = B.add_chain(layers[L], cur);
+    } else {
+      // open slab chain: separator layers every slab + 1 layers, chained from
+      // the middle layer (the root) towards both end layers; the slabs of
+      // layers between two separators hang below the lower of the two and are
+      // dissected as above.  Every chain cluster's subtree then holds an end
+      // layer, so the region it folds is open through that end's contact.
+      const int m = (int)layers.size(), step = opt.slab + 1, r = m / 2;
+      auto interior = [&](int a, int b) {  // layers strictly between a and b
+        std::vector<int32_t> R;
+        for (int L = a + 1; L < b; ++L) R.insert(R.end(), layers[L].begin(), layers[L].end());
+        return R;
+      };
+      // a layer is kept whole up to layer_max points (one cluster per chain
+      // level: fewer levels and taller matrix-core tiles); a wider one is
+      // split into a parent-child chain of clusters
+      const int lmax = opt.layer_max;
+      const int root = B.add_chain(layers[r], -1, lmax);
+      for (int side = -1; side <= 1; side += 2) {
+        if ((side < 0 && r == 0) || (side > 0 && r == m - 1)) continue;
+        int up = r, up_cl = root;
+        while (true) {
+          int nxt = up + side * step;
+          const bool end = side < 0 ? nxt <= 0 : nxt >= m - 1;
+          if (end) nxt = side < 0 ? 0 : m - 1;
+          const int cl = B.add_chain(layers[nxt], up_cl, lmax);
+          // the slab between this separator and the one above it
+          B.nd(side < 0 ? interior(nxt, up) : interior(up, nxt), cl, 1);
+          if (end) break;
+          up = nxt;
+          up_cl = cl;
+        }
+        if (B.failed) break;
+      }
+    }
   } else {
     // contacts merged into the top of the tree, nested dissection below
     int cur = -1;

@@ -24,7 +24,12 @@ namespace ndg {
 struct TreeOptions {
   int leaf_max = 64;     // regions with at most this many points become leaves
   int max_cluster = 64;  // clusters larger than this are split into a chain
-  int kind = 0;          // 0: nested dissection, 1: layer chain, 2: contacts in the root
+  int kind = 0;          // 0: nested dissection, 1: layer chain, 2: contacts in the root,
+                         // 3: open slab chain
+  int slab = 8;          // kind 3: layers between consecutive chain separators
+  int layer_max = 128;   // kind 3: separator (and end) layers up to this size stay one cluster
+  const int32_t* layer_of = nullptr;  // kinds 1, 3: transport layer of every site, or null
+                                      // (then layers are the sites of equal x coordinate)
 };
 
 struct Symbolic {

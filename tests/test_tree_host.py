@@ -28,7 +28,7 @@ def _tree(dev, **kw):
     return sym, sym.info(), sym.arrays()
 
 
-def _check_partition(dev, arr):
+def _check_partition(dev, arr, max_s=64):
     perm, cl_off, parent, bptr, bidx = (arr[k] for k in ("perm", "cl_off", "parent", "bptr", "bidx"))
     n = dev.n
     nc = len(cl_off) - 1
@@ -38,7 +38,7 @@ def _check_partition(dev, arr):
     owner = np.empty(n, np.int64)
     for c in range(nc):
         owner[cl_off[c]:cl_off[c + 1]] = c
-        assert 0 < cl_off[c + 1] - cl_off[c] <= 64
+        assert 0 < cl_off[c + 1] - cl_off[c] <= max_s
     # ancestor sets
     anc = []
     for c in range(nc):
@@ -55,12 +55,33 @@ def _check_partition(dev, arr):
     # contacts whole
     for cs in dev.contacts:
         assert len(set(owner[iperm[cs]].tolist())) == 1
-    # boundary sets: ancestor points, ascending, and contain every direct coupling
+    # boundary sets: ancestor points, ascending
+    bset = []
     for c in range(nc):
         b = bidx[bptr[c]:bptr[c + 1]]
         assert np.all(np.diff(b) > 0)
         for q in b:
             assert owner[q] in anc[c]
+        bset.append(set(b.tolist()))
+    # and complete (Section 3.2: B_i holds the ancestor points coupled to i
+    # directly or through fill passed up from its children): every coupling
+    # of a point of cluster c to an ancestor's point lies in B_c ...
+    for i, j in zip(h.row, h.col):
+        ci, cj = owner[iperm[i]], owner[iperm[j]]
+        if cj in anc[ci]:
+            assert iperm[j] in bset[ci]
+    for cs in dev.contacts:  # (a contact's self-energy couples all its sites)
+        ic = iperm[np.asarray(cs)]
+        for x in ic:
+            for y in ic:
+                if owner[y] in anc[owner[x]]:
+                    assert y in bset[owner[x]]
+    # ... and a child's boundary points outside its parent lie in the parent's B
+    for c in range(nc):
+        p = parent[c]
+        if p >= 0:
+            for q in bset[c]:
+                assert owner[q] == p or q in bset[p]
     # post-order: parents after children
     for c in range(nc):
         if parent[c] >= 0:
@@ -176,3 +197,68 @@ def _check_partition_chain(dev, arr):
     for i, j in zip(h.row, h.col):
         ci, cj = owner[iperm[i]], owner[iperm[j]]
         assert ci == cj or cj in ancs[ci] or ci in ancs[cj]
+
+
+def _subtree_extent(dev, arr, layers):
+    """Per cluster: whether its subtree holds a contact site, and how many
+    transport layers its subtree's points span."""
+    perm, cl_off, parent = arr["perm"], arr["cl_off"], arr["parent"]
+    nc = len(parent)
+    layer_of = np.empty(dev.n, np.int64)
+    for q, L in enumerate(layers):
+        layer_of[L] = q
+    is_contact = np.zeros(dev.n, bool)
+    for cs in dev.contacts:
+        is_contact[cs] = True
+    lo = np.full(nc, 1 << 40)
+    hi = np.full(nc, -1)
+    has = np.zeros(nc, bool)
+    for c in range(nc):  # post-order: children first
+        sites = perm[cl_off[c]:cl_off[c + 1]]
+        lo[c] = min(lo[c], layer_of[sites].min())
+        hi[c] = max(hi[c], layer_of[sites].max())
+        has[c] |= is_contact[sites].any()
+        p = parent[c]
+        if p >= 0:
+            lo[p] = min(lo[p], lo[c])
+            hi[p] = max(hi[p], hi[c])
+            has[p] |= has[c]
+    return has, hi - lo + 1
+
+
+@pytest.mark.parametrize("width,slab", [(24, 4), (24, -1), (64, 8), (96, 8), (128, 12)])
+def test_open_slab_chain_tree(width, slab):
+    """Tree kind 3: every folded region either holds a contact (open) or is
+    a slab of at most `slab` layers; separator layers up to 128 points stay
+    one cluster; the partition rules hold."""
+    dev = devices.fd2d(60, width)
+    sym, info, arr = _tree(dev, tree_kind=3, slab=slab, leaf_max=16, layers=dev.layers)
+    _check_partition(dev, arr, max_s=128)
+    has, span = _subtree_extent(dev, arr, dev.layers)
+    assert np.all(has | (span <= max(slab, 0)))
+    assert info["max_cluster"] == width
+    # the root is a middle layer; both contacts' clusters are chain ends
+    root = int(np.nonzero(arr["parent"] < 0)[0][0])
+    sites = arr["perm"][arr["cl_off"][root]:arr["cl_off"][root + 1]]
+    assert set(sites.tolist()) == set(dev.layers[30].tolist())
+    if slab < 0:
+        assert info["nclusters"] == 60 and info["max_height"] == 31
+
+
+def test_open_slab_chain_tube_cells():
+    """The tube's 40-atom cells as layers: with no slabs (every cell a
+    separator) the tree is the layer chain of Section 3.2, Fig. 6, rooted in
+    the middle cell, so every folded region holds a contact."""
+    dev = devices.zigzag_tube(16, disorder=0.1)
+    sym, info, arr = _tree(dev, tree_kind=3, slab=-1, layers=dev.layers)
+    _check_partition(dev, arr)
+    has, _ = _subtree_extent(dev, arr, dev.layers)
+    assert has.all() and info["nclusters"] == 16
+
+
+def test_open_slab_chain_rejects_non_tridiagonal_layers():
+    dev = devices.fd2d(10, 6)
+    bad = [np.concatenate([dev.layers[0], dev.layers[2]]), dev.layers[1]] + list(dev.layers[3:])
+    with pytest.raises(ndg.NdgError):
+        ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, tree_kind=3,
+                    layers=bad)
