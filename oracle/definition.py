@@ -94,6 +94,47 @@ def diag_greens(h, v, energies, eta: float, contacts, sig_r, sig_less, sig_r_ph=
     return dgr, dgl, dgg
 
 
+def diag_greater(h, v, energies, eta: float, contacts, sig_r, sig_less) -> np.ndarray:
+    """diag G^> formed in its own step (Section 2): G^> = G^r Sigma^> G^r+
+    with Sigma^> = Sigma^< + Sigma^r - Sigma^r+ on each contact (the lesser
+    and greater self-energies differ by the retarded minus the advanced one).
+    With broadening eta > 0 in the device this differs from the identity
+    G^< + G^r - G^r+ by 2 i eta diag(G^r G^r+).  Returns complex128 [nE, n]."""
+    hd = dense_h(h)
+    n = hd.shape[0]
+    energies = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+    out = np.zeros((energies.size, n), np.complex128)
+    eye = np.eye(n, dtype=np.complex128)
+    for k, e in enumerate(energies):
+        a = assemble_a(hd, v, complex(e, eta), contacts, [s[k] for s in sig_r])
+        g = sla.lu_solve(sla.lu_factor(a), eye)
+        for sites, sr, sl in zip(contacts, sig_r, sig_less):
+            sg = sl[k] + sr[k] - sr[k].conj().T
+            gc = g[:, sites]
+            out[k] += np.einsum("ja,ab,jb->j", gc, sg, gc.conj())
+    return out
+
+
+def transmission(h, v, energies, eta: float, contacts, sig_r) -> np.ndarray:
+    """Transmission between the first two contacts, T(E) = Tr[Gamma_L G_LR
+    Gamma_R G_LR+] with Gamma = i (Sigma^r - Sigma^r+) and G_LR the block of
+    G^r between the contacts' sites.  Returns a real array [nE]."""
+    hd = dense_h(h)
+    n = hd.shape[0]
+    energies = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+    out = np.zeros(energies.size)
+    L, R = contacts[0], contacts[1]
+    for k, e in enumerate(energies):
+        a = assemble_a(hd, v, complex(e, eta), contacts, [s[k] for s in sig_r])
+        rhs = np.zeros((n, len(R)), np.complex128)
+        rhs[R, np.arange(len(R))] = 1.0
+        glr = sla.lu_solve(sla.lu_factor(a), rhs)[L]        # G^r[L, R]
+        gl_ = 1j * (sig_r[0][k] - sig_r[0][k].conj().T)
+        gr_ = 1j * (sig_r[1][k] - sig_r[1][k].conj().T)
+        out[k] = np.trace(gl_ @ glr @ gr_ @ glr.conj().T).real
+    return out
+
+
 def density(dgl: np.ndarray, cweights: np.ndarray) -> np.ndarray:
     """n_i = sum_E c_E (-i G^<_ii(E)) (real part kept; the imaginary part is
     zero up to rounding because G^< is skew-Hermitian)."""

@@ -569,3 +569,84 @@ def test_sparse_lu_rows_match_dense_definition():
     gr, gl = sparse.sampled_diag(dev.scipy_h(), v, e, wl.eta, dev.contacts, sr, sl, sites)
     assert _rel(gr, dgr[:, sites]) < 1e-12
     assert _rel(gl, dgl[:, sites]) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# G^> in its own step, and the transmission
+# ---------------------------------------------------------------------------
+
+def test_explicit_greater_differs_from_the_identity_by_the_broadening_term():
+    """G^r Sigma^> G^r+ = G^< + G^r - G^r+ + 2 i eta G^r G^r+ (the identity
+    holds exactly only at eta = 0): the explicit diagonal minus the
+    identity's equals 2 i eta sum_j |G_kj|^2, computed from the full G."""
+    wl = workloads.small_grid(9, 5, n_energies=3, eta=2e-2, noise=0.05, seed=31)
+    dev = wl.device
+    e, sr, sl = _problem(wl)
+    dgr, dgl, dgg = definition.diag_greens(dev.scipy_h(), None, e, wl.eta, dev.contacts, sr, sl)
+    exp_g = definition.diag_greater(dev.scipy_h(), None, e, wl.eta, dev.contacts, sr, sl)
+    for k in range(len(e)):
+        g, _ = definition.full_greens(dev.scipy_h(), None, e[k], wl.eta, dev.contacts,
+                                      [s[k] for s in sr], [s[k] for s in sl])
+        gg = np.sum(np.abs(g) ** 2, axis=1)
+        assert _rel(exp_g[k] - dgg[k], 2j * wl.eta * gg) < 1e-10
+        assert np.max(np.abs(gg)) * wl.eta > 1e-3 * np.max(np.abs(dgg[k]))  # the term is not negligible
+    # at eta = 0 in the device the two coincide
+    dgr0, dgl0, dgg0 = definition.diag_greens(dev.scipy_h(), None, e, 0.0, dev.contacts, sr, sl)
+    exp0 = definition.diag_greater(dev.scipy_h(), None, e, 0.0, dev.contacts, sr, sl)
+    assert _rel(exp0, dgg0) < 1e-11
+
+
+def test_explicit_greater_in_equilibrium():
+    """One chemical potential, eta = 0 in the device: G^< = -f A and
+    G^> = (1 - f) A with A = G^r - G^r+, so G^> = (f - 1) / f G^< site by
+    site."""
+    dev = devices.fd2d(8, 5)
+    e = np.array([0.05, 0.12, 0.3])
+    mu, kt = (0.1, 0.1), 0.025
+    sl_, sr_, ll_, lr_ = leads.contact_self_energies(dev, e, 1e-6, mu, kt)
+    _, dgl, _ = definition.diag_greens(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_], [ll_, lr_])
+    gg = definition.diag_greater(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_], [ll_, lr_])
+    f = leads.fermi(e, mu[0], kt)[:, None]
+    assert _rel(gg, (f - 1) / f * dgl) < 1e-10
+
+
+def test_transmission_counts_channels():
+    """Unit transmission per open mode of the uniform hard-wall waveguide,
+    and the number of right-moving Bloch channels of the pristine (10,0)
+    tube."""
+    ny, nx = 10, 6
+    wl = workloads.uniform_waveguide(ny, nx, n_energies=1, eta=1e-9)
+    t0 = wl.device.lead["t0"]
+    _, eps = leads.transverse_modes(nx, t0)
+    es = np.array([0.5, 2.0, 6.0, 15.0])
+    s = np.array([leads.fd_lead_sigma(complex(x, 1e-9), nx, t0) for x in es])
+    t = definition.transmission(wl.device.scipy_h(), None, es, 1e-9, wl.device.contacts, [s, s])
+    for x, tx in zip(es, t):
+        assert abs(tx - int(np.sum((x > eps) & (x < eps + 4 * t0)))) < 1e-6
+    h00, h01 = devices.zigzag_tube_blocks(10, -2.7)
+    ks = np.linspace(0, 2 * np.pi, 2001)
+    bands = np.array([np.linalg.eigvalsh(h00 + h01 * np.exp(1j * k) + h01.T * np.exp(-1j * k))
+                      for k in ks])
+    dev = devices.zigzag_tube(3, 10, -2.7, disorder=0.0)
+    es = np.array([0.2, 0.75, 1.6, 2.2])
+    sig = [leads.tube_lead_sigmas(complex(x, 1e-8), h00, h01) for x in es]
+    t = definition.transmission(dev.scipy_h(), None, es, 1e-8, dev.contacts,
+                                [np.array([a for a, _ in sig]), np.array([b for _, b in sig])])
+    for x, tx in zip(es, t):
+        n_ch = np.sum(np.diff(np.sign(bands - x), axis=0) != 0) // 2
+        assert abs(tx - n_ch) < 1e-4, (x, tx, n_ch)
+
+
+def test_transmission_is_the_landauer_current():
+    """Phonon-free, eta = 0: i_L(E) = T(E) (f_L - f_R) with the terminal
+    current formula (the contact block of G^< and G^>)."""
+    wl = workloads.small_grid(10, 8, n_energies=3, emin=1.2, emax=1.8, eta=0.0, mu=(1.5, 1.4),
+                              noise=0.05, seed=21)
+    dev = wl.device
+    e = wl.energies
+    sl_, sr_, ll_, lr_ = leads.contact_self_energies(dev, e, 1e-6, wl.mu, wl.kt)
+    cur = definition.terminal_currents(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_], [ll_, lr_])
+    t = definition.transmission(dev.scipy_h(), None, e, 0.0, dev.contacts, [sl_, sr_])
+    df = leads.fermi(e, wl.mu[0], wl.kt) - leads.fermi(e, wl.mu[1], wl.kt)
+    assert np.all(t > 0.1)
+    assert np.max(np.abs(cur[:, 0] - t * df) / np.abs(t * df)) < 1e-11
