@@ -205,6 +205,30 @@ ndg_status ndg_solve(ndg_plan* plan, int32_t nE, const double* E, double eta, co
                      double* growth, ndg_precision prec, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * G^> in its own step, and the transmission (Section 2 computes G^> in a
+ * separate step; Section 4.2 reports density and current).
+ *
+ * As ndg_solve in FP64 (diag_gr, diag_gless, growth as there), plus
+ *   diag_ggreater   device [nE][n] or NULL: diag of G^> = G^r Sigma^> G^r+
+ *                   with Sigma^> = Sigma^< + Sigma^r - Sigma^r+ on each
+ *                   contact, formed by a further G^< pass over the same
+ *                   factors with Sigma^> as its source (not the identity
+ *                   G^< + G^r - G^r+ of ndg_solve, from which it differs by
+ *                   2 i eta diag(G^r G^r+))
+ *   transmission    device [nE] or NULL (two contacts): T(E) = Tr[Gamma_0
+ *                   G_01 Gamma_1 G_01+], Gamma = i (Sigma^r - Sigma^r+), from
+ *                   one more pass with source -i Gamma_1 (X = G Gamma_1 G+ on
+ *                   contact 0's block, T = Tr[Gamma_0 X_00])
+ * Each requested output costs one G^< source-and-extraction pass.  Not for
+ * graph capture by ndg_batch_solve.  Errors: as ndg_solve; NDG_EINVAL for a
+ * transmission with other than two contacts.
+ */
+ndg_status ndg_solve_transport(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
+                               const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
+                               ndg_c128* diag_gr, ndg_c128* diag_gless, ndg_c128* diag_ggreater,
+                               double* transmission, double* growth, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Solve with diagonal phonon self-energies (scattering).
  *
  * Equation defineA includes a phonon self-energy, which Section 1 takes
@@ -404,22 +428,37 @@ ndg_status ndg_plan_export_block(ndg_plan* plan, int32_t which, int32_t energy, 
                                  ndg_c128* out);
 
 /* Per-kernel timing.  With profiling enabled the plan records a HIP event
- * pair around every kernel launch of ndg_solve on the solve's stream; the
- * statistics hold, per kernel, the number of launches, the summed event time
- * and the algorithmic work of those launches: flops (8 real flops per complex
- * multiply-add, Section 4.1's counts) and bytes (each input block read once,
- * each output block written once), one entry per kernel and tree level.
+ * pair around every kernel launch of ndg_solve on the launch's stream; the
+ * statistics hold, per launch group (kernel, tree level, size class), the
+ * number of launches, the summed event time and the algorithmic work of
+ * those launches: flops (8 real flops per complex multiply-add, Section
+ * 4.1's counts) and bytes (each input block read once, each output block
+ * written once).  Each launch is credited with its own group's work; the
+ * flops of all groups of one phonon-free solve sum to 8 ndg_info.ops_total
+ * per energy.  ndg_plan_set_profiling: mode 0 off, 1 on (the G^< extraction
+ * and the contact chains run on side streams, overlapping the G^r
+ * extraction, so event times include co-running kernels), 2 on with every
+ * launch on the caller's stream (each event time is the kernel's own).
  * ndg_plan_profile synchronises the device, copies at most `capacity`
  * entries, sets *count and clears the statistics. */
 typedef struct {
   char name[32];
-  int32_t height;   /* tree level of the launches (0 for the epilogue)   */
-  int32_t reserved;
+  int32_t height;     /* tree level of the launches (0 for the epilogue)                  */
+  int32_t size_class; /* 0-2: fronts of at most 32, 48, 64 points (whole on chip); 3-6:
+                         larger fronts with clusters of at most 16, 32, 64, 128 points; the
+                         phonon kernels' tile classes 0-2: clusters of at most 16, 32, 64 */
   int64_t launches;
   double ms;
   double flops;
   double bytes;
 } ndg_kernel_stat;
+
+/* Algorithmic work per energy of every launch group of a phonon-free solve
+ * on this tree (host only, no device): the entries of ndg_plan_profile with
+ * launches = 1, ms = 0, flops and bytes per energy.  Returns NDG_EINVAL (and
+ * the first `capacity` entries) if capacity is too small. */
+ndg_status ndg_symbolic_costs(const ndg_symbolic* sy, int32_t capacity, ndg_kernel_stat* out,
+                              int32_t* count);
 
 ndg_status ndg_plan_set_profiling(ndg_plan* plan, int32_t enable);
 ndg_status ndg_plan_profile(ndg_plan* plan, int32_t capacity, ndg_kernel_stat* out,

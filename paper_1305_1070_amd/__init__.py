@@ -20,10 +20,11 @@ from ._lib import NDG_FP64, NDG_MIXED, NdgError, load  # noqa: F401
 __all__ = ["analyze", "Symbolic", "Plan", "load", "NdgError", "NDG_FP64", "NDG_MIXED",
            "ndg_analyze", "ndg_symbolic_info", "ndg_symbolic_arrays", "ndg_plan_create",
            "ndg_plan_destroy", "ndg_plan_info", "ndg_solve", "ndg_plan_status",
-           "ndg_plan_export_block", "ndg_plan_set_profiling", "ndg_plan_profile",
+           "ndg_plan_export_block", "ndg_plan_set_profiling", "ndg_plan_profile", "ndg_symbolic_costs",
            "ndg_density", "ndg_plan_enable_adjoint", "ndg_density_vjp", "NDDensity",
            "ndg_batch_create", "ndg_batch_destroy", "ndg_batch_solve", "Batch",
            "ndg_plan_enable_scattering", "ndg_solve_scattering", "ndg_scba", "ndg_poisson_newton_step",
+           "ndg_solve_transport",
            "ndg_status_string", "ndg_last_error"]
 
 
@@ -105,6 +106,15 @@ def ndg_solve(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, dgr_ptr, d
                                 growth_ptr, prec, stream_ptr))
 
 
+def ndg_solve_transport(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, dgr_ptr, dgl_ptr,
+                        dgg_ptr, t_ptr, growth_ptr, stream_ptr):
+    nc = len(sig_r_ptrs)
+    sr = (C.c_void_p * max(1, nc))(*sig_r_ptrs)
+    sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
+    _lib.check(load().ndg_solve_transport(plan, ne, e_ptr, eta, v_ptr, sr, sl, dgr_ptr, dgl_ptr, dgg_ptr,
+                                          t_ptr, growth_ptr, stream_ptr))
+
+
 def ndg_plan_enable_scattering(plan):
     _lib.check(load().ndg_plan_enable_scattering(plan))
 
@@ -184,18 +194,32 @@ def ndg_plan_export_block(plan, which, energy, cluster, count):
     return out[:count]
 
 
-def ndg_plan_set_profiling(plan, enable: bool):
-    _lib.check(load().ndg_plan_set_profiling(plan, 1 if enable else 0))
+def ndg_plan_set_profiling(plan, enable):
+    """enable: False/0 off, True/1 on, 2 on with every launch on the caller's
+    stream (no overlap between the extractions)."""
+    _lib.check(load().ndg_plan_set_profiling(plan, int(enable)))
+
+
+def _stats(arr, cnt):
+    return [{"name": arr[i].name.decode(), "height": arr[i].height,
+             "size_class": arr[i].size_class, "launches": arr[i].launches, "ms": arr[i].ms,
+             "flops": arr[i].flops, "bytes": arr[i].bytes} for i in range(cnt)]
 
 
 def ndg_plan_profile(plan) -> list:
-    cap = 4096
+    cap = 1 << 16
     arr = (_lib.KernelStat * cap)()
     cnt = C.c_int32()
     _lib.check(load().ndg_plan_profile(plan, cap, arr, C.byref(cnt)))
-    return [{"name": arr[i].name.decode(), "height": arr[i].height,
-             "launches": arr[i].launches, "ms": arr[i].ms,
-             "flops": arr[i].flops, "bytes": arr[i].bytes} for i in range(cnt.value)]
+    return _stats(arr, cnt.value)
+
+
+def ndg_symbolic_costs(sy) -> list:
+    cap = 1 << 16
+    arr = (_lib.KernelStat * cap)()
+    cnt = C.c_int32()
+    _lib.check(load().ndg_symbolic_costs(sy, cap, arr, C.byref(cnt)))
+    return _stats(arr, cnt.value)
 
 
 def ndg_batch_create(plans):
@@ -251,6 +275,11 @@ class Symbolic:
 
     def arrays(self) -> dict:
         return ndg_symbolic_arrays(self.handle)
+
+    def costs(self) -> list:
+        """Algorithmic flops and bytes per energy of every launch group
+        (kernel, height, size class) of a phonon-free solve."""
+        return ndg_symbolic_costs(self.handle)
 
     def __del__(self):
         # at interpreter exit the module globals may already be gone
@@ -326,6 +355,25 @@ class Plan:
                   growth.data_ptr() if growth is not None else None,
                   prec, C.c_void_p(st.cuda_stream))
         return gr, gl, gg
+
+    def solve_transport(self, E, eta, sig_r, sig_less, V=None, greater=True, transmission=True,
+                        growth=None, stream=None):
+        """FP64 solve plus G^> in its own step (G^r Sigma^> G^r+) and the
+        transmission T(E) between the two contacts.  Returns (diag G^r,
+        diag G^<, diag G^> or None, T or None)."""
+        import torch
+        n, ne, dev = self._check_inputs(E, sig_r, sig_less, V)
+        gr, gl = (torch.empty((ne, n), dtype=torch.complex128, device=dev) for _ in range(2))
+        gg = torch.empty((ne, n), dtype=torch.complex128, device=dev) if greater else None
+        T = torch.empty(ne, dtype=torch.float64, device=dev) if transmission else None
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        ndg_solve_transport(self.handle, ne, E.data_ptr(), float(eta),
+                            V.data_ptr() if V is not None else None,
+                            [t.data_ptr() for t in sig_r], [t.data_ptr() for t in sig_less],
+                            gr.data_ptr(), gl.data_ptr(), gg.data_ptr() if greater else None,
+                            T.data_ptr() if transmission else None,
+                            growth.data_ptr() if growth is not None else None, C.c_void_p(st.cuda_stream))
+        return gr, gl, gg, T
 
     def _check_inputs(self, E, sig_r, sig_less, V):
         import torch
@@ -486,7 +534,7 @@ class Plan:
     def status(self):
         return ndg_plan_status(self.handle)
 
-    def set_profiling(self, enable: bool):
+    def set_profiling(self, enable):
         ndg_plan_set_profiling(self.handle, enable)
 
     def profile(self) -> list:

@@ -49,7 +49,7 @@ class Info(C.Structure):
 
 
 class KernelStat(C.Structure):
-    _fields_ = [("name", C.c_char * 32), ("height", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("name", C.c_char * 32), ("height", C.c_int32), ("size_class", C.c_int32),
                 ("launches", C.c_int64), ("ms", C.c_double),
                 ("flops", C.c_double), ("bytes", C.c_double)]
 
@@ -80,6 +80,8 @@ SIGNATURES = {
     "ndg_plan_info": (C.c_int, [P, C.POINTER(Info)]),
     "ndg_solve": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P), P, P, P,
                             P, C.c_int, P]),
+    "ndg_solve_transport": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P), P,
+                                      P, P, P, P, P]),
     "ndg_plan_status": (C.c_int, [P, I32P, I32P, I32P]),
     "ndg_plan_export_block": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, P]),
     "ndg_density": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P), P, P,
@@ -97,6 +99,7 @@ SIGNATURES = {
                                           F64P, I32P, F64P, P]),
     "ndg_plan_set_profiling": (C.c_int, [P, C.c_int32]),
     "ndg_plan_profile": (C.c_int, [P, C.c_int32, C.POINTER(KernelStat), C.POINTER(C.c_int32)]),
+    "ndg_symbolic_costs": (C.c_int, [P, C.c_int32, C.POINTER(KernelStat), C.POINTER(C.c_int32)]),
     "ndg_batch_create": (C.c_int, [C.c_int32, C.POINTER(P), C.POINTER(P)]),
     "ndg_batch_destroy": (C.c_int, [P]),
     "ndg_batch_solve": (C.c_int, [P, C.POINTER(SolveArgs), C.c_int, P]),

@@ -110,6 +110,14 @@ ndg_status ndg_analyze(int64_t n, const int64_t* rowptr, const int32_t* col, con
 
 void ndg_symbolic_destroy(ndg_symbolic* sy) { delete sy; }
 
+ndg_status ndg_symbolic_costs(const ndg_symbolic* sy, int32_t capacity, ndg_kernel_stat* out,
+                              int32_t* count) {
+  if (!sy || !out || !count || capacity < 0) { set_error("ndg_symbolic_costs: bad argument"); return NDG_EINVAL; }
+  const int rc = ndg::symbolic_costs(sy->sy, capacity, out, count);
+  if (rc) set_error("ndg_symbolic_costs: capacity too small");
+  return (ndg_status)rc;
+}
+
 ndg_status ndg_symbolic_info(const ndg_symbolic* sy, ndg_info* out) {
   if (!sy || !out) { set_error("ndg_symbolic_info: NULL argument"); return NDG_EINVAL; }
   fill_info(sy->sy, sy->ops, sy->rgf_equiv, ndg::workspace_bytes_per_energy(sy->sy), out);
@@ -154,6 +162,23 @@ ndg_status ndg_solve(ndg_plan* plan, int32_t nE, const double* E, double eta, co
   if (prec != NDG_FP64 && prec != NDG_MIXED) { set_error("ndg_solve: unknown precision"); return NDG_EINVAL; }
   return (ndg_status)ndg::plan_solve(plan, nE, E, eta, V, sig_r, sig_less, diag_gr, diag_gless,
                                      diag_ggreater, growth, (int)prec, stream);
+}
+
+ndg_status ndg_solve_transport(ndg_plan* plan, int32_t nE, const double* E, double eta, const double* V,
+                               const ndg_c128* const* sig_r, const ndg_c128* const* sig_less,
+                               ndg_c128* diag_gr, ndg_c128* diag_gless, ndg_c128* diag_ggreater,
+                               double* transmission, double* growth, void* stream) {
+  if (!plan) { set_error("ndg_solve_transport: NULL plan"); return NDG_EINVAL; }
+  if (nE < 0 || !(eta >= 0)) { set_error("ndg_solve_transport: nE < 0 or eta < 0"); return NDG_EINVAL; }
+  if (nE == 0) return NDG_OK;
+  if (!E || !diag_gr || !diag_gless) {
+    set_error("ndg_solve_transport: NULL energy or output pointer");
+    return NDG_EINVAL;
+  }
+  return (ndg_status)ndg::plan_run(plan, ndg::kRunSolve, nE, E, eta, V, sig_r, sig_less, diag_gr, diag_gless,
+                                   nullptr, growth, nullptr, nullptr, nullptr, nullptr, NDG_FP64, stream,
+                                   nullptr, nullptr, nullptr, nullptr, false, nullptr, 0, diag_ggreater,
+                                   transmission);
 }
 
 ndg_status ndg_plan_enable_scattering(ndg_plan* plan) {
@@ -272,7 +297,8 @@ ndg_status ndg_plan_export_block(ndg_plan* plan, int32_t which, int32_t energy, 
 
 ndg_status ndg_plan_set_profiling(ndg_plan* plan, int32_t enable) {
   if (!plan) { set_error("ndg_plan_set_profiling: NULL plan"); return NDG_EINVAL; }
-  return (ndg_status)ndg::plan_set_profiling(plan, enable != 0);
+  if (enable < 0 || enable > 2) { set_error("ndg_plan_set_profiling: mode must be 0, 1 or 2"); return NDG_EINVAL; }
+  return (ndg_status)ndg::plan_set_profiling(plan, enable);
 }
 
 ndg_status ndg_plan_profile(ndg_plan* plan, int32_t capacity, ndg_kernel_stat* out,

@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       }
     __syncthreads();
     {
-      const double2* sl = sel2(c.sig_l, cc) + (int64_t)(eb + e) * sc * sc;
+      const double2* sl = sel2(c.sig_l, cc) + (int64_t)(eb + e - c.sl_e0) * sc * sc;
       for (int r0 = 0; r0 < s; r0 += 64)
         for (int j0 = 0; j0 < sc; j0 += 64) {
           const int ni = min(64, s - r0), nj = min(64, sc - j0);

@@ -87,6 +87,8 @@ struct Ctx {
   const double* V;           // may be null
   const double2* sig_r[2];
   const double2* sig_l[2];
+  int32_t sl_e0;             // energy index of sig_l[c][0] (0: the caller's arrays; the batch
+                             // start when sig_l points at the library's per-batch sources)
   // diagonal phonon self-energies, [nE][n] in the caller's site order, or
   // null: Sigma^r_ph enters A's diagonal; with scat set, every cluster's
   // G^< source comes from the all-ancestor N fold (Sigma^<_ph) and the
@@ -168,6 +170,15 @@ constexpr int kScbaBlocks = 1024;
 // terminal current spectral density per contact and energy of the batch,
 // cur[(e0 + e) * ncontacts + c] (caddr: see the plan's contact tables)
 void launch_current(const Ctx& c, const int32_t* caddr, int nb, double* cur, hipStream_t st);
+// Sources of the extra G^< passes, per energy of the batch and contact
+// ([nb][nc][nc] each): which = 0, Sigma^> = Sigma^< + Sigma^r - Sigma^r+ on
+// every contact; which = 1, Sigma^r - Sigma^r+ = -i Gamma on contact 1 and
+// zero on contact 0 (the transmission).
+void launch_form_source(const Ctx& c, double2* src0, double2* src1, int which, int nb, hipStream_t st);
+// diag of the G^< fronts' rows in the caller's site order into out[nE][n]
+void launch_epilogue_lesser(const Ctx& c, int nb, double2* out, hipStream_t st);
+// T(E) = -Tr[(Sigma^r_0 - Sigma^r_0+) X_00] from the G^< fronts' contact-0 block
+void launch_transmission(const Ctx& c, const int32_t* caddr, int nb, double* T, hipStream_t st);
 
 // Vector kernels of the Schroedinger-Poisson Newton step (kernels_poisson.hip):
 // y = K x for a CSR matrix, out = a x + b y, *out = x . y (part: kVecBlocks

@@ -413,6 +413,84 @@ __global__ void __launch_bounds__(256) k_current(Ctx c, const int32_t* caddr, do
   if (threadIdx.x == 0) cur[(int64_t)(eb + e) * c.ncontacts + cc] = red[0];
 }
 
+// Sources of the separate G^> step (Section 2) and of the transmission, per
+// (entry, energy of the batch, contact); see launch_form_source.
+__global__ void __launch_bounds__(256) k_form_source(Ctx c, double2* src0, double2* src1, int which) {
+  const int cc = blockIdx.z, e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
+  const int nc = sel2(c.nc, cc);
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= nc * nc) return;
+  const int a = q / nc, b = q - a * nc;
+  const double2* sr = sel2(c.sig_r, cc) + (int64_t)(eb + e) * nc * nc;
+  const double2 r_ab = sr[q], r_ba = sr[b * nc + a];
+  double2 v = make_double2(r_ab.x - r_ba.x, r_ab.y + r_ba.y);   // Sigma^r - (Sigma^r)+
+  if (which == 0) {
+    const double2 l = sel2(c.sig_l, cc)[(int64_t)(eb + e) * nc * nc + q];
+    v.x += l.x;
+    v.y += l.y;
+  } else if (cc == 0) {
+    v = make_double2(0.0, 0.0);
+  }
+  (cc ? src1 : src0)[(int64_t)e * nc * nc + q] = v;
+}
+
+__global__ void __launch_bounds__(256) k_epilogue_lesser(Ctx c, double2* out) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE || q >= c.n) return;
+  const SiteDiag sd = c.sdiag[q];
+  const double2* S = slab(c, e);
+  out[(int64_t)(eb + e) * c.n + q] = S[sd.ol];
+}
+
+// T = Tr[Gamma_0 G_01 Gamma_1 G_01+] from X = G (Sigma^r_1 - Sigma^r_1+) G+
+// = -i G Gamma_1 G+ held in the G^< fronts: with Gamma_0 = i D_0,
+// D_0 = Sigma^r_0 - Sigma^r_0+, T = -Tr[D_0 X_00] = -sum_ab D_0(a,b) X(b,a).
+// X is anti-Hermitian like G^<: X(b,a) stored as the transposed entry is
+// -conj of it.  One block per energy, a fixed-order block sum.
+__global__ void __launch_bounds__(256) k_transmission(Ctx c, const int32_t* caddr, double* T) {
+  __shared__ double red[256];
+  const int e = blockIdx.x;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
+  const int nc = c.nc[0];
+  const double2* S = slab(c, e);
+  const double2* sr = c.sig_r[0] + (int64_t)(eb + e) * nc * nc;
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < nc * nc; q += 256) {
+    const int a = q / nc, b = q - a * nc;
+    const int32_t code = caddr[b * nc + a];
+    double2 x = S[(int64_t)(code & 0x7fffffff) + c.pdelta];
+    if (code < 0) x = make_double2(-x.x, x.y);
+    const double2 r_ab = sr[q], r_ba = sr[b * nc + a];
+    const double2 d = make_double2(r_ab.x - r_ba.x, r_ab.y + r_ba.y);
+    acc -= d.x * x.x - d.y * x.y;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) T[eb + e] = red[0];
+}
+
+void launch_form_source(const Ctx& c, double2* src0, double2* src1, int which, int nb, hipStream_t st) {
+  const int m = max(c.nc[0] * c.nc[0], c.ncontacts > 1 ? c.nc[1] * c.nc[1] : 0);
+  if (c.ncontacts <= 0 || nb <= 0 || m <= 0) return;
+  hipLaunchKernelGGL(k_form_source, dim3((m + 255) / 256, nb, c.ncontacts), dim3(256), 0, st, c, src0, src1,
+                     which);
+}
+void launch_epilogue_lesser(const Ctx& c, int nb, double2* out, hipStream_t st) {
+  if (nb > 0) hipLaunchKernelGGL(k_epilogue_lesser, dim3((c.n + 255) / 256, nb), dim3(256), 0, st, c, out);
+}
+void launch_transmission(const Ctx& c, const int32_t* caddr, int nb, double* T, hipStream_t st) {
+  if (nb > 0 && c.ncontacts >= 2) hipLaunchKernelGGL(k_transmission, dim3(nb), dim3(256), 0, st, c, caddr, T);
+}
+
 void launch_current(const Ctx& c, const int32_t* caddr, int nb, double* cur, hipStream_t st) {
   if (c.ncontacts <= 0 || nb <= 0) return;
   hipLaunchKernelGGL(k_current, dim3(c.ncontacts, nb), dim3(256), 0, st, c, caddr, cur);

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "../../include/ndnegf.h"
@@ -50,6 +51,7 @@ struct ndg_plan {
   int32_t *d_smap = nullptr, *d_pinv = nullptr;
   int32_t* d_gaddr = nullptr;
   int32_t* d_caddr = nullptr;  // contact blocks' stored-entry offsets (terminal currents)
+  double2* d_src[2] = {nullptr, nullptr};  // per-batch sources of the extra G^< passes
   ndg::SiteDiag* d_sdiag = nullptr;
   int32_t* d_levels = nullptr;       // clusters by height
   ndg::ColItem* d_colitems = nullptr;
@@ -100,11 +102,13 @@ struct ndg_plan {
   struct AncGroup { int it0 = 0, nit = 0, cl0 = 0, ncl = 0; };
   std::vector<AncGroup> anc_groups;  // [(H + 1) * 3]
   int last_batch = 0;
-  // algorithmic cost per energy of each kernel class at each height
-  std::vector<double> cost_flops, cost_bytes;  // [kKernels * (H + 1)]
+  // algorithmic work per energy of each launch group: kernel, height, size
+  // class (tile class for the scattering kernels); cost_index()
+  std::vector<double> cost_flops, cost_bytes;
+  int profiling_mode = 0;  // 2: every launch on the caller's stream (no overlap)
   // profiling
   bool profiling = false;
-  struct Rec { int kid, h; hipEvent_t a, b; double flops, bytes; };
+  struct Rec { int kid, h, q; hipEvent_t a, b; double flops, bytes; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
   // the G^< extraction runs on a second stream, concurrent with the G^r
@@ -211,6 +215,7 @@ void free_plan(ndg_plan* p) {
                   p->d_smap,      p->d_pinv,     p->d_gaddr,      p->d_sdiag,      p->d_sd,
                   p->d_atab,      p->d_bpos,     p->d_lk,         p->d_umap,       p->d_ancitems,
                   p->d_anccls,    p->d_sws,      p->d_scba,       p->d_caddr,      p->d_pvec,
+                  p->d_src[0],    p->d_src[1],
                   p->d_pdot};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -229,6 +234,75 @@ void free_plan(ndg_plan* p) {
 }
 
 }  // namespace
+
+// Size class of cluster k: fronts of at most 32, 48, 64 points (whole on
+// chip), then larger fronts by cluster size s <= 16, 32, 64, 128.
+int size_class(const Symbolic& sy, int k) {
+  const int s_ = sy.s(k), f = s_ + sy.b(k);
+  if (f <= 32) return 0;
+  if (f <= 48) return 1;
+  if (f <= kSmallFront) return 2;
+  return s_ <= 16 ? 3 : s_ <= 32 ? 4 : s_ <= 64 ? 5 : 6;
+}
+
+int cost_index(int kid, int h, int q, int H) { return (kid * (H + 1) + h) * kCostClasses + q; }
+
+// Algorithmic work per energy of every launch group of the phonon-free solve
+// (kernel, height, size class), in Section 4.1's convention: a product of
+// i x j by j x k counts ijk complex multiply-adds, an i x i inversion i^3,
+// 8 real flops each; bytes count each input block read once and each output
+// block written once (16 per complex entry).  The flops of all groups sum to
+// 8 times count_ops' total.
+void phonon_free_costs(const Symbolic& sy, const std::vector<ClusterDesc>& hd, const int* nc_contact,
+                       int ncontacts, std::vector<double>& fl, std::vector<double>& by) {
+  const int nc = sy.nclusters, H = sy.max_height;
+  fl.assign((size_t)kKernels * (H + 1) * kCostClasses, 0.0);
+  by.assign(fl.size(), 0.0);
+  auto addc = [&](int kid, int h, int q, double f_, double b_) {
+    fl[cost_index(kid, h, q, H)] += f_;
+    by[cost_index(kid, h, q, H)] += b_;
+  };
+  for (int k = 0; k < nc; ++k) {
+    const int h = sy.height[k], q = size_class(sy, k);
+    const double s = sy.s(k), b = sy.b(k), f = s + b;
+    const bool leaf = sy.children[k].empty();
+    double kidb = 0;
+    for (int32_t ch : sy.children[k]) kidb += (double)sy.b(ch) * sy.b(ch);
+    if (s + b <= kSmallFront) {
+      // pivot inverse, Psi and the Schur contribution of the whole front
+      addc(K_FOLD_SMALL, h, q, 8.0 * (s * s * s + s * s * b + s * b * b),
+           16.0 * (kidb + s * s + s * b + b * b));
+      // X_BB counted by its distinct entries (symmetric for G^r,
+      // anti-Hermitian for G^<): b (b + 1) / 2.  A leaf off the contact
+      // chains forms the diagonal of X_ii only.
+      const bool diag_only = leaf && hd[k].chain_mask == 0;
+      for (int kid : {K_EXTRACT_SMALL, K_EXTRACT_SMALL_P})
+        addc(kid, h, q, 8.0 * (s * b * b + (diag_only ? s * b : s * s * b)),
+             16.0 * (b * (b + 1) / 2 + s * s + s * b) + 16.0 * (diag_only ? s : s * b + s * s));
+    } else {
+      // the cluster's rows written once, each child's contribution to them
+      // (its first nself boundary rows) read once
+      double kidrows = 0;
+      for (int32_t ch : sy.children[k]) kidrows += (double)hd[ch].nself * sy.b(ch);
+      addc(K_ASSEMBLE, h, q, 0.0, 16.0 * (s * f + kidrows));
+      addc(K_FACTOR, h, q, 8.0 * s * s * s, 16.0 * 2 * s * s);
+      addc(K_PSI, h, q, 8.0 * s * s * b, 16.0 * (s * s + 2 * s * b));
+      addc(K_UPDATE, h, q, 8.0 * s * b * b, 16.0 * (2 * s * b + 2 * b * b));
+      for (int kid : {K_DOWN_OFF_G, K_DOWN_OFF_P})
+        addc(kid, h, q, 8.0 * s * b * b, 16.0 * (s * b + b * (b + 1) / 2 + s * b));
+      for (int kid : {K_DOWN_DIAG_G, K_DOWN_DIAG_P}) addc(kid, h, q, 8.0 * s * s * b, 16.0 * (2 * s * b + 2 * s * s));
+    }
+    // the contact chains launch once per height (class 0)
+    for (int c = 0; c < ncontacts; ++c) {
+      if (!((hd[k].chain_mask >> c) & 1)) continue;
+      const double sc = nc_contact[c];
+      addc(K_CHAIN_FWD, h, 0, 8.0 * (s * b * sc + s * s * sc), 16.0 * (s * b + s * s + 2 * f * sc));
+      addc(K_CHAIN_BACK, h, 0, 8.0 * (s * b * sc + s * sc * sc + s * sc * f),
+           16.0 * (s * b + 3 * f * sc + s * sc + sc * sc + s * f));
+    }
+  }
+  addc(K_EPILOGUE, 0, 0, 0.0, 16.0 * 5.0 * (double)sy.n);
+}
 
 int64_t workspace_bytes_per_energy(const Symbolic& sy) {
   std::vector<ClusterDesc> desc;
@@ -279,13 +353,7 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   p->rhs_lds_back.assign(H + 1, 0);
   p->rhs_big.assign(H + 1, 0);
   p->groups.assign((H + 1) * ndg_plan::kClasses, ndg_plan::Group{});
-  auto class_of = [&](int k) {
-    const int s_ = sy.s(k), f = s_ + sy.b(k);
-    if (f <= 32) return 0;
-    if (f <= 48) return 1;
-    if (f <= kSmallFront) return 2;
-    return s_ <= 16 ? 3 : s_ <= 32 ? 4 : s_ <= 64 ? 5 : 6;
-  };
+  auto class_of = [&](int k) { return size_class(sy, k); };
   for (int h = 1; h <= H; ++h) {
     std::vector<int32_t> lv(sy.level_order.begin() + sy.level_ptr[h - 1],
                             sy.level_order.begin() + sy.level_ptr[h]);
@@ -338,50 +406,7 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
     p->chain_ptr[h] = (int)chains.size();
     p->chaincl_ptr[h] = (int)chaincls.size();
   }
-  // algorithmic work per energy (complex multiply-add = 8 flops; bytes = 16 per
-  // complex element read or written once)
-  p->cost_flops.assign(kKernels * (H + 1), 0.0);
-  p->cost_bytes.assign(kKernels * (H + 1), 0.0);
-  auto addc = [&](int kid, int h, double fl, double by) {
-    p->cost_flops[kid * (H + 1) + h] += fl;
-    p->cost_bytes[kid * (H + 1) + h] += by;
-  };
-  for (int k = 0; k < nc; ++k) {
-    const int h = sy.height[k];
-    const double s = sy.s(k), b = sy.b(k), f = s + b;
-    const bool inner = !sy.children[k].empty();
-    double kidb = 0;
-    for (int32_t ch : sy.children[k]) kidb += (double)sy.b(ch) * sy.b(ch);
-    if (s + b <= kSmallFront) {
-      // whole-front elimination: s steps over the f x f front
-      addc(K_FOLD_SMALL, h, 8.0 * s * f * f, 16.0 * (kidb + s * s + s * b + b * b));
-      // X_BB counted by its distinct entries (symmetric for G^r,
-      // anti-Hermitian for G^<): b (b + 1) / 2
-      for (int q : {K_EXTRACT_SMALL, K_EXTRACT_SMALL_P})
-        addc(q, h, 8.0 * (s * b * b + s * s * b),
-             16.0 * (b * (b + 1) / 2 + s * s + s * b) + 16.0 * (inner ? s * b + s * s : s));
-    } else {
-      // the cluster's rows written once, each child's contribution to them
-      // (its first nself boundary rows) read once
-      double kidrows = 0;
-      for (int32_t ch : sy.children[k]) kidrows += (double)p->hdesc[ch].nself * sy.b(ch);
-      addc(K_ASSEMBLE, h, 0.0, 16.0 * (s * f + kidrows));
-      addc(K_FACTOR, h, 8.0 * s * s * s, 16.0 * 2 * s * s);
-      addc(K_PSI, h, 8.0 * s * s * b, 16.0 * (s * s + 2 * s * b));
-      addc(K_UPDATE, h, 8.0 * s * b * b, 16.0 * (2 * s * b + 2 * b * b));
-      for (int q : {K_DOWN_OFF_G, K_DOWN_OFF_P})
-        addc(q, h, 8.0 * s * b * b, 16.0 * (s * b + b * (b + 1) / 2 + s * b));
-      for (int q : {K_DOWN_DIAG_G, K_DOWN_DIAG_P}) addc(q, h, 8.0 * s * s * b, 16.0 * (2 * s * b + 2 * s * s));
-    }
-    for (int c = 0; c < p->ncontacts; ++c) {
-      if (!((p->hdesc[k].chain_mask >> c) & 1)) continue;
-      const double sc = p->nc[c];
-      addc(K_CHAIN_FWD, h, 8.0 * (s * b * sc + s * s * sc), 16.0 * (s * b + s * s + 2 * f * sc));
-      addc(K_CHAIN_BACK, h, 8.0 * (s * b * sc + s * sc * sc + s * sc * f),
-           16.0 * (s * b + 3 * f * sc + s * sc + sc * sc + s * f));
-    }
-  }
-  addc(K_EPILOGUE, 0, 0.0, 16.0 * 5.0 * (double)sy.n);
+  phonon_free_costs(sy, p->hdesc, p->nc, p->ncontacts, p->cost_flops, p->cost_bytes);
   std::vector<int32_t> kids_ptr(nc + 1, 0), kids;
   for (int k = 0; k < nc; ++k) {
     for (int32_t ch : sy.children[k]) kids.push_back(ch);
@@ -520,6 +545,9 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   rc = rc ? rc : upload(&p->d_pinv, pinv.data(), pinv.size());
   rc = rc ? rc : upload(&p->d_gaddr, gaddr.data(), gaddr.size());
   rc = rc ? rc : upload(&p->d_caddr, caddr.data(), caddr.size());
+  // sources of the separate G^> step and of the transmission, per batch
+  for (int c = 0; c < p->ncontacts && !rc; ++c)
+    if (hipMalloc((void**)&p->d_src[c], (size_t)max_batch * p->nc[c] * p->nc[c] * 16) != hipSuccess) rc = NDG_ENOMEM;
   rc = rc ? rc : upload(&p->d_sdiag, sdiag.data(), sdiag.size());
   rc = rc ? rc : upload(&p->d_hrow, sy.hrow.data(), sy.hrow.size());
   rc = rc ? rc : upload(&p->d_hcol, sy.hcol.data(), sy.hcol.size());
@@ -747,8 +775,9 @@ int plan_enable_scattering(ndg_plan* p) {
   for (int i = 0; i < nc; ++i) {
     const int h = p->hheight[i];
     const double s = hd[i].s, b = hd[i].b, f = hd[i].f, g = sd[i].g, W = g - s;
-    p->cost_flops[K_ANC_G * (H + 1) + h] += 8.0 * s * b * W;
-    p->cost_bytes[K_ANC_G * (H + 1) + h] += 16.0 * (s * b + b * W + s * g);
+    const int q = hd[i].s <= 16 ? 0 : hd[i].s <= 32 ? 1 : 2;  // the launch's tile class
+    p->cost_flops[cost_index(K_ANC_G, h, q, H)] += 8.0 * s * b * W;
+    p->cost_bytes[cost_index(K_ANC_G, h, q, H)] += 16.0 * (s * b + b * W + s * g);
     // the N fold of an inner cluster: read G^(0) rows, write N, and per
     // feeding descendant its N rows over this frame and its Psi entries
     // (leaves are formed inside k_anc_g: no launch, no cost here)
@@ -758,11 +787,11 @@ int plan_enable_scattering(ndg_plan* p) {
         nf += 8.0 * s * hd[L.d].s * g;
         nby += 16.0 * hd[L.d].s * (g + s);
       }
-      p->cost_flops[K_ANC_N * (H + 1) + h] += nf;
-      p->cost_bytes[K_ANC_N * (H + 1) + h] += nby;
+      p->cost_flops[cost_index(K_ANC_N, h, q, H)] += nf;
+      p->cost_bytes[cost_index(K_ANC_N, h, q, H)] += nby;
     }
-    p->cost_flops[K_ANC_P0 * (H + 1) + h] += 8.0 * s * s * f;
-    p->cost_bytes[K_ANC_P0 * (H + 1) + h] += 16.0 * (s * s + 2.0 * s * f);
+    p->cost_flops[cost_index(K_ANC_P0, h, q, H)] += 8.0 * s * s * f;
+    p->cost_bytes[cost_index(K_ANC_P0, h, q, H)] += 16.0 * (s * s + 2.0 * s * f);
   }
   p->sstride = off;
   int rc = 0;
@@ -791,7 +820,9 @@ int plan_enable_scattering(ndg_plan* p) {
     p->d_anccls = nullptr;
     p->d_scba = nullptr;
     for (int k = K_ANC_G; k <= K_ANC_P0; ++k)
-      for (int h = 0; h <= H; ++h) p->cost_flops[k * (H + 1) + h] = p->cost_bytes[k * (H + 1) + h] = 0;
+      for (int h = 0; h <= H; ++h)
+        for (int q = 0; q < kCostClasses; ++q)
+          p->cost_flops[cost_index(k, h, q, H)] = p->cost_bytes[cost_index(k, h, q, H)] = 0;
     set_error("ndg_plan_enable_scattering: device allocation failed");
     return rc == NDG_ENOMEM ? NDG_ENOMEM : rc;
   }
@@ -936,8 +967,17 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
              const ndg_c128* const* sig_r, const ndg_c128* const* sig_less, ndg_c128* dgr,
              ndg_c128* dgl, ndg_c128* dgg, double* growth, const double* cE, double* density,
              const double* nbar, double* vbar, int prec, void* stream, const int32_t* e0p,
-             const ndg_c128* sig_r_ph, const ndg_c128* sig_less_ph, double* current, bool reuse_fold) {
+             const ndg_c128* sig_r_ph, const ndg_c128* sig_less_ph, double* current, bool reuse_fold,
+             double* vjp_part, int64_t vjp_part_capacity, ndg_c128* dgg_explicit, double* transmission) {
   const bool scat = sig_less_ph != nullptr;
+  if ((dgg_explicit || transmission) && (mode != kRunSolve || scat || e0p)) {
+    set_error("internal: the separate G^> step and the transmission are for plain solves only");
+    return NDG_EINVAL;
+  }
+  if (transmission && p->ncontacts != 2) {
+    set_error("ndg_solve_transport: the transmission needs two contacts");
+    return NDG_EINVAL;
+  }
   if ((scat || sig_r_ph) && (mode != kRunSolve || e0p || prec != NDG_FP64)) {
     set_error("internal: phonon self-energies are for FP64 solves only");
     return NDG_EINVAL;
@@ -1015,6 +1055,14 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
       set_error("ndg_density_vjp: call ndg_plan_enable_adjoint first");
       return NDG_EINVAL;
     }
+    // the per-energy partials of one batch: the plan's buffer, or the
+    // caller-supplied (static) one, which must hold them
+    if (vjp_part && (int64_t)std::min(nE, p->max_batch) * p->n > vjp_part_capacity) {
+      set_error("ndg_density_vjp: n x min(nE, max_batch) = " +
+                std::to_string((int64_t)std::min(nE, p->max_batch) * p->n) +
+                " partials exceed the static buffer of " + std::to_string(vjp_part_capacity) + " doubles");
+      return NDG_EINVAL;
+    }
     launch_zero(vbar, p->n, st);
   }
   RhsCtx r{};
@@ -1026,7 +1074,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   r.n = (int32_t)p->n;
   r.bidx = p->d_bidx;
   r.nbar = nbar;
-  r.part = p->d_part;
+  r.part = vjp_part ? vjp_part : p->d_part;
   const int H = p->max_height;
   // profiling: an event pair around each launch, with its algorithmic work
   auto take_event = [&]() {
@@ -1035,16 +1083,17 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
     else (void)hipEventCreate(&ev);
     return ev;
   };
-  auto timed_on = [&](hipStream_t on, int kid, int h, int nb, auto&& launch) {
+  // each launch is credited with its own group's work (kernel, height, class)
+  auto timed_on = [&](hipStream_t on, int kid, int h, int q, int nb, auto&& launch) {
     if (!p->profiling) { launch(); return; }
-    ndg_plan::Rec r{kid, h, take_event(), take_event(), p->cost_flops[kid * (H + 1) + h] * nb,
-                    p->cost_bytes[kid * (H + 1) + h] * nb};
+    ndg_plan::Rec r{kid, h, q, take_event(), take_event(), p->cost_flops[cost_index(kid, h, q, H)] * nb,
+                    p->cost_bytes[cost_index(kid, h, q, H)] * nb};
     (void)hipEventRecord(r.a, on);
     launch();
     (void)hipEventRecord(r.b, on);
     p->recs.push_back(r);
   };
-  auto timed = [&](int kid, int h, int nb, auto&& launch) { timed_on(st, kid, h, nb, launch); };
+  auto timed = [&](int kid, int h, int q, int nb, auto&& launch) { timed_on(st, kid, h, q, nb, launch); };
   // with e0p: exactly one batch, its first energy read on the device
   const int e_end = e0p ? std::min(nE, 1) : nE;
   for (int e0 = 0; e0 < e_end; e0 += p->max_batch) {
@@ -1060,17 +1109,17 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         if (!g.ncl) continue;
         const int32_t* cl = p->d_levels + g.cl0;
         if (q <= 2) {
-          timed(K_FOLD_SMALL, h, nb, [&] { launch_fold_small(c, cl, g.ncl, nb, g.size, st); });
+          timed(K_FOLD_SMALL, h, q, nb, [&] { launch_fold_small(c, cl, g.ncl, nb, g.size, st); });
           continue;
         }
-        timed(K_ASSEMBLE, h, nb, [&] { launch_assemble(c, cl, g.ncl, nb, st); });
-        timed(K_FACTOR, h, nb, [&] { launch_factor(c, cl, g.ncl, nb, g.size, st); });
-        if (g.ncol) timed(K_PSI, h, nb, [&] { launch_psi(c, p->d_colitems + g.col0, g.ncol, nb, g.size, st); });
+        timed(K_ASSEMBLE, h, q, nb, [&] { launch_assemble(c, cl, g.ncl, nb, st); });
+        timed(K_FACTOR, h, q, nb, [&] { launch_factor(c, cl, g.ncl, nb, g.size, st); });
+        if (g.ncol) timed(K_PSI, h, q, nb, [&] { launch_psi(c, p->d_colitems + g.col0, g.ncol, nb, g.size, st); });
         if (g.nupd)
-          timed(K_UPDATE, h, nb, [&] { launch_update(c, p->d_upditems + g.upd0, g.nupd, nb, q == 3 ? 32 : 64, st); });
+          timed(K_UPDATE, h, q, nb, [&] { launch_update(c, p->d_upditems + g.upd0, g.nupd, nb, q == 3 ? 32 : 64, st); });
       }
       // the G^< source; the gradient's solves need only the factors
-      if (nch && mode != kRunVjp) timed(K_CHAIN_FWD, h, nb, [&] { launch_chain_fwd(c, chi, nch, nb, st); });
+      if (nch && mode != kRunVjp) timed(K_CHAIN_FWD, h, 0, nb, [&] { launch_chain_fwd(c, chi, nch, nb, st); });
     }
     if (mode == kRunVjp) {
       launch_zero(r.part, (int64_t)nb * p->n, st);
@@ -1085,18 +1134,18 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
           rr.cinv = p->d_cinv;
           rr.X = pass == 0 ? r.Gc : r.X;
           for (int h = 1; h <= H; ++h)
-            timed(K_RHS_FWD, h, nb, [&] {
+            timed(K_RHS_FWD, h, 0, nb, [&] {
               launch_rhs_fwd(c, rr, p->d_levels + p->lvl_ptr[h - 1], p->lvl_ptr[h] - p->lvl_ptr[h - 1], nb,
                              p->rhs_lds_fwd[h], p->rhs_big[h], st);
             });
           for (int h = H; h >= 1; --h)
-            timed(K_RHS_BACK, h, nb, [&] {
+            timed(K_RHS_BACK, h, 0, nb, [&] {
               launch_rhs_back(c, rr, p->d_levels + p->lvl_ptr[h - 1], p->lvl_ptr[h] - p->lvl_ptr[h - 1], nb,
                               p->rhs_lds_back[h], p->rhs_big[h], st);
             });
         }
         for (int cc = 0, off = 0; cc < p->ncontacts; off += p->nc[cc], ++cc)
-          timed(K_VJP, 0, nb, [&] { launch_vjp_accum(c, r, cc, off, nb, st); });
+          timed(K_VJP, 0, 0, nb, [&] { launch_vjp_accum(c, r, cc, off, nb, st); });
       }
       launch_vjp_reduce(c, r, nb, cE, vbar, st);
       p->last_batch = nb;
@@ -1109,15 +1158,15 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         if (!g.ncl) continue;
         const int32_t* cl = p->d_levels + g.cl0;
         if (q <= 2) {
-          timed_on(on, lesser ? K_EXTRACT_SMALL_P : K_EXTRACT_SMALL, h, nb,
+          timed_on(on, lesser ? K_EXTRACT_SMALL_P : K_EXTRACT_SMALL, h, q, nb,
                    [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, lesser, on); });
           continue;
         }
         const ColItem* ci = p->d_colitems + g.col0;
         if (g.ncol)
-          timed_on(on, lesser ? K_DOWN_OFF_P : K_DOWN_OFF_G, h, nb,
+          timed_on(on, lesser ? K_DOWN_OFF_P : K_DOWN_OFF_G, h, q, nb,
                    [&] { launch_down_off(c, ci, g.ncol, nb, lesser, g.size, on); });
-        timed_on(on, lesser ? K_DOWN_DIAG_P : K_DOWN_DIAG_G, h, nb,
+        timed_on(on, lesser ? K_DOWN_DIAG_P : K_DOWN_DIAG_G, h, q, nb,
                  [&] { launch_down_diag(c, cl, g.ncl, nb, lesser, g.size, on); });
       }
     };
@@ -1129,14 +1178,14 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
       for (int h = H; h >= 1; --h) extract(h, false, st);
       for (int h = H; h >= 1; --h) {
         const int k0 = p->chaincl_ptr[h - 1], nck = p->chaincl_ptr[h] - k0;
-        if (nck) timed(K_CHAIN_BACK, h, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, st); });
+        if (nck) timed(K_CHAIN_BACK, h, 0, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, st); });
       }
       static const int kTile[3] = {16, 32, 64};
       for (int h = H; h >= 1; --h)
         for (int q = 0; q < 3; ++q) {
           const ndg_plan::AncGroup& g = p->anc_groups[h * 3 + q];
           if (g.nit)
-            timed(K_ANC_G, h, nb,
+            timed(K_ANC_G, h, q, nb,
                   [&] { launch_anc_g(c, x, p->d_ancitems + g.it0, g.nit, nb, kTile[q], h == 1, st); });
         }
       // leaves (height 1) stored their N in k_anc_g
@@ -1144,12 +1193,12 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         for (int q = 0; q < 3; ++q) {
           const ndg_plan::AncGroup& g = p->anc_groups[h * 3 + q];
           if (g.nit && h > 1)
-            timed(K_ANC_N, h, nb, [&] { launch_anc_n(c, x, p->d_ancitems + g.it0, g.nit, nb, kTile[q], st); });
+            timed(K_ANC_N, h, q, nb, [&] { launch_anc_n(c, x, p->d_ancitems + g.it0, g.nit, nb, kTile[q], st); });
           if (g.ncl)
-            timed(K_ANC_P0, h, nb, [&] { launch_anc_p0(c, x, p->d_anccls + g.cl0, g.ncl, nb, kTile[q], st); });
+            timed(K_ANC_P0, h, q, nb, [&] { launch_anc_p0(c, x, p->d_anccls + g.cl0, g.ncl, nb, kTile[q], st); });
         }
       for (int h = H; h >= 1; --h) extract(h, true, st);
-      timed(K_EPILOGUE, 0, nb, [&] {
+      timed(K_EPILOGUE, 0, 0, nb, [&] {
         launch_epilogue(c, nb, reinterpret_cast<double2*>(dgr), reinterpret_cast<double2*>(dgl),
                         reinterpret_cast<double2*>(dgg), st);
       });
@@ -1166,7 +1215,9 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
     // the plan's own stream inside a capture crashed the HIP runtime.
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cap) != hipSuccess) cap = hipStreamCaptureStatusActive;
-    const bool fork = cap == hipStreamCaptureStatusNone;
+    // profiling mode 2 keeps everything on st too, so each kernel's event
+    // time is its own (no overlap with the other extraction's kernels)
+    const bool fork = cap == hipStreamCaptureStatusNone && !(p->profiling && p->profiling_mode == 2);
     hipStream_t sp = fork ? p->side : st;
     if (fork) {
       (void)hipEventRecord(p->ev_fork, st);
@@ -1175,7 +1226,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
       for (int h = H; h >= 1; --h) {
         const int k0 = p->chaincl_ptr[h - 1], nck = p->chaincl_ptr[h] - k0;
         if (!nck) continue;
-        timed_on(p->chain, K_CHAIN_BACK, h, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, p->chain); });
+        timed_on(p->chain, K_CHAIN_BACK, h, 0, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, p->chain); });
         (void)hipEventRecord(p->ev_chain[h], p->chain);
       }
     }
@@ -1184,7 +1235,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
       // the G^< source on chain clusters first: the extraction of P reads it
       if (nck) {
         if (fork) (void)hipStreamWaitEvent(sp, p->ev_chain[h], 0);
-        else timed_on(sp, K_CHAIN_BACK, h, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, sp); });
+        else timed_on(sp, K_CHAIN_BACK, h, 0, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, sp); });
       }
       for (int q = 0; q < ndg_plan::kClasses; ++q) {
         const ndg_plan::Group& g = p->groups[h * ndg_plan::kClasses + q];
@@ -1194,15 +1245,15 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         // rows (its source comes from the chain kernels)
         const bool gr = mode != kRunDensity;
         if (q <= 2) {
-          timed_on(sp, K_EXTRACT_SMALL_P, h, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, true, sp); });
-          if (gr) timed(K_EXTRACT_SMALL, h, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, false, st); });
+          timed_on(sp, K_EXTRACT_SMALL_P, h, q, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, true, sp); });
+          if (gr) timed(K_EXTRACT_SMALL, h, q, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, false, st); });
           continue;
         }
         const ColItem* ci = p->d_colitems + g.col0;
-        if (g.ncol) timed_on(sp, K_DOWN_OFF_P, h, nb, [&] { launch_down_off(c, ci, g.ncol, nb, true, g.size, sp); });
-        timed_on(sp, K_DOWN_DIAG_P, h, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, true, g.size, sp); });
-        if (gr && g.ncol) timed(K_DOWN_OFF_G, h, nb, [&] { launch_down_off(c, ci, g.ncol, nb, false, g.size, st); });
-        if (gr) timed(K_DOWN_DIAG_G, h, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, false, g.size, st); });
+        if (g.ncol) timed_on(sp, K_DOWN_OFF_P, h, q, nb, [&] { launch_down_off(c, ci, g.ncol, nb, true, g.size, sp); });
+        timed_on(sp, K_DOWN_DIAG_P, h, q, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, true, g.size, sp); });
+        if (gr && g.ncol) timed(K_DOWN_OFF_G, h, q, nb, [&] { launch_down_off(c, ci, g.ncol, nb, false, g.size, st); });
+        if (gr) timed(K_DOWN_DIAG_G, h, q, nb, [&] { launch_down_diag(c, cl, g.ncl, nb, false, g.size, st); });
       }
     }
     if (fork) {
@@ -1210,11 +1261,39 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
       (void)hipStreamWaitEvent(st, p->ev_join, 0);
     }
     if (mode == kRunSolve) {
-      timed(K_EPILOGUE, 0, nb, [&] {
+      timed(K_EPILOGUE, 0, 0, nb, [&] {
         launch_epilogue(c, nb, reinterpret_cast<double2*>(dgr), reinterpret_cast<double2*>(dgl),
                         reinterpret_cast<double2*>(dgg), st);
       });
       if (current) launch_current(c, p->d_caddr, nb, current, st);
+      // further G^< passes over the same factors with other sources (the
+      // G^< fronts are overwritten; the G^< diagonal was written above):
+      // Sigma^> for G^> in its own step, then -i Gamma_1 for the
+      // transmission.  All on st.
+      for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 0 ? !dgg_explicit : !transmission) continue;
+        launch_form_source(c, p->d_src[0], p->d_src[1], pass, nb, st);
+        Ctx c2 = c;
+        for (int q = 0; q < 2; ++q) c2.sig_l[q] = p->d_src[q];
+        c2.sl_e0 = e0;
+        for (int h = H; h >= 1; --h) {
+          const int k0 = p->chaincl_ptr[h - 1], nck = p->chaincl_ptr[h] - k0;
+          if (nck) launch_chain_back(c2, p->d_chaincls + k0, nck, nb, st);
+          for (int q = 0; q < ndg_plan::kClasses; ++q) {
+            const ndg_plan::Group& g = p->groups[h * ndg_plan::kClasses + q];
+            if (!g.ncl) continue;
+            const int32_t* cl = p->d_levels + g.cl0;
+            if (q <= 2) {
+              launch_extract_small(c2, cl, g.ncl, nb, g.lds, g.size, true, st);
+              continue;
+            }
+            if (g.ncol) launch_down_off(c2, p->d_colitems + g.col0, g.ncol, nb, true, g.size, st);
+            launch_down_diag(c2, cl, g.ncl, nb, true, g.size, st);
+          }
+        }
+        if (pass == 0) launch_epilogue_lesser(c2, nb, reinterpret_cast<double2*>(dgg_explicit), st);
+        else launch_transmission(c2, p->d_caddr, nb, transmission, st);
+      }
     } else
       launch_density(c, nb, cE, density, st);
     p->last_batch = nb;
@@ -1223,12 +1302,44 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
   return NDG_OK;
 }
 
+int symbolic_costs(const Symbolic& sy, int capacity, ndg_kernel_stat* out, int32_t* count) {
+  std::vector<ClusterDesc> hd;
+  layout(sy, hd);
+  int ncont[2] = {0, 0};
+  const int ncontacts = std::min((int)sy.contact_cluster.size(), kMaxContacts);
+  for (int c = 0; c < ncontacts; ++c) ncont[c] = (int)sy.contact_pos[c].size();
+  std::vector<double> fl, by;
+  phonon_free_costs(sy, hd, ncont, ncontacts, fl, by);
+  const int H = sy.max_height;
+  int m = 0;
+  for (int k = 0; k < kKernels; ++k)
+    for (int h = 0; h <= H; ++h)
+      for (int q = 0; q < kCostClasses; ++q) {
+        const int i = cost_index(k, h, q, H);
+        if (fl[i] == 0.0 && by[i] == 0.0) continue;
+        if (m < capacity) {
+          ndg_kernel_stat& a = out[m];
+          std::memset(&a, 0, sizeof(a));
+          std::snprintf(a.name, sizeof(a.name), "%s", kKernelNames[k]);
+          a.height = h;
+          a.size_class = q;
+          a.launches = 1;
+          a.flops = fl[i];
+          a.bytes = by[i];
+        }
+        ++m;
+      }
+  *count = std::min(m, capacity);
+  return m <= capacity ? NDG_OK : NDG_EINVAL;
+}
+
 int plan_ncontacts(const ndg_plan* p) { return p->ncontacts; }
 int plan_device(const ndg_plan* p) { return p->device; }
 bool plan_profiling(const ndg_plan* p) { return p->profiling; }
 
-int plan_set_profiling(ndg_plan* p, bool enable) {
-  p->profiling = enable;
+int plan_set_profiling(ndg_plan* p, int mode) {
+  p->profiling = mode != 0;
+  p->profiling_mode = mode;
   return NDG_OK;
 }
 
@@ -1238,18 +1349,20 @@ int plan_profile(ndg_plan* p, int capacity, ndg_kernel_stat* out, int32_t* count
     return NDG_EHIP;
   }
   const int H = p->max_height;
-  std::vector<ndg_kernel_stat> acc(kKernels * (H + 1));
+  std::vector<ndg_kernel_stat> acc((size_t)kKernels * (H + 1) * kCostClasses);
   std::memset(acc.data(), 0, sizeof(ndg_kernel_stat) * acc.size());
   for (int k = 0; k < kKernels; ++k)
-    for (int h = 0; h <= H; ++h) {
-      ndg_kernel_stat& a = acc[k * (H + 1) + h];
-      std::snprintf(a.name, sizeof(a.name), "%s", kKernelNames[k]);
-      a.height = h;
-    }
+    for (int h = 0; h <= H; ++h)
+      for (int q = 0; q < kCostClasses; ++q) {
+        ndg_kernel_stat& a = acc[cost_index(k, h, q, H)];
+        std::snprintf(a.name, sizeof(a.name), "%s", kKernelNames[k]);
+        a.height = h;
+        a.size_class = q;
+      }
   for (auto& r : p->recs) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, r.a, r.b);
-    ndg_kernel_stat& a = acc[r.kid * (H + 1) + r.h];
+    ndg_kernel_stat& a = acc[cost_index(r.kid, r.h, r.q, H)];
     a.launches += 1;
     a.ms += ms;
     a.flops += r.flops;

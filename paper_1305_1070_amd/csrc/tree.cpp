@@ -648,9 +648,15 @@ int build_symbolic(int64_t n, const int64_t* rowptr, const int32_t* col, const d
 
 OpCounts count_ops(const Symbolic& sy, bool diag_only_leaves) {
   OpCounts oc;
+  // a leaf forms only the diagonal of its own block when nobody reads the
+  // rest: its front fits one on-chip block (s + b <= 64) and it does not lie
+  // on a contact's chain (those keep their rows for the G^< source)
+  std::vector<char> on_chain(sy.nclusters, 0);
+  for (int32_t c0 : sy.contact_cluster)
+    for (int k = c0; k >= 0; k = sy.parent[k]) on_chain[k] = 1;
   for (int k = 0; k < sy.nclusters; ++k) {
     double s = sy.s(k), b = sy.b(k);
-    bool leaf = sy.children[k].empty();
+    bool leaf = sy.children[k].empty() && s + b <= 64 && !on_chain[k];
     oc.fold_inv += s * s * s;
     oc.fold_psi += s * s * b;
     oc.fold_update += s * b * b;

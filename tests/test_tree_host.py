@@ -262,3 +262,84 @@ def test_open_slab_chain_rejects_non_tridiagonal_layers():
     with pytest.raises(ndg.NdgError):
         ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, tree_kind=3,
                     layers=bad)
+
+
+def _recount(dev, arr):
+    """Flops per launch group recomputed from the tree arrays (Section 4.1's
+    convention, 8 flops per complex multiply-add)."""
+    perm, cl_off, parent, height, bptr = (arr[k] for k in ("perm", "cl_off", "parent", "height", "bptr"))
+    nc = len(parent)
+    s = np.diff(cl_off).astype(float)
+    b = np.diff(bptr).astype(float)
+    kids = np.zeros(nc, int)
+    for p in parent:
+        if p >= 0:
+            kids[p] += 1
+    iperm = np.empty(dev.n, int)
+    iperm[perm] = np.arange(dev.n)
+    owner = np.searchsorted(cl_off, np.arange(dev.n), side="right") - 1
+    chain_of = []
+    for cs in dev.contacts:
+        ch, k = set(), int(owner[iperm[cs]].min())
+        while k >= 0:
+            ch.add(k)
+            k = parent[k]
+        chain_of.append(ch)
+    out = {}
+
+    def add(name, h, q, v):
+        out[(name, h, q)] = out.get((name, h, q), 0.0) + v
+
+    for k in range(nc):
+        sk, bk, h = s[k], b[k], int(height[k])
+        f = sk + bk
+        q = (0 if f <= 32 else 1 if f <= 48 else 2) if f <= 64 else \
+            (3 if sk <= 16 else 4 if sk <= 32 else 5 if sk <= 64 else 6)
+        if f <= 64:
+            add("k_fold_small", h, q, 8 * (sk ** 3 + sk * sk * bk + sk * bk * bk))
+            diag = kids[k] == 0 and not any(k in c for c in chain_of)
+            for nm in ("k_extract_small(G)", "k_extract_small(P)"):
+                add(nm, h, q, 8 * (sk * bk * bk + (sk * bk if diag else sk * sk * bk)))
+        else:
+            add("k_factor", h, q, 8 * sk ** 3)
+            add("k_psi", h, q, 8 * sk * sk * bk)
+            add("k_update", h, q, 8 * sk * bk * bk)
+            for nm in ("k_down_off(G)", "k_down_off(P)"):
+                add(nm, h, q, 8 * sk * bk * bk)
+            for nm in ("k_down_diag(G)", "k_down_diag(P)"):
+                add(nm, h, q, 8 * sk * sk * bk)
+        for c, cs in zip(chain_of, dev.contacts):
+            if k in c:
+                sc = len(cs)
+                add("k_chain_fwd", h, 0, 8 * (sk * bk * sc + sk * sk * sc))
+                add("k_chain_back", h, 0, 8 * (sk * bk * sc + sk * sc * sc + sk * sc * f))
+    return out
+
+
+@pytest.mark.parametrize("case", ["nd", "slab_chain_wide", "tube_cells"])
+def test_cost_table_sums_to_op_count_and_recounts(case):
+    """The per-launch-group cost table the profiler credits each launch with
+    (one group per kernel, height and size class) sums to 8 x ops_total and
+    equals a recount from the tree arrays."""
+    if case == "nd":
+        dev = devices.fd2d(60, 40)
+        sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, leaf_max=16)
+    elif case == "slab_chain_wide":
+        dev = devices.fd2d(50, 96)
+        sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, leaf_max=16,
+                          tree_kind=3, slab=6, layers=dev.layers)
+    else:
+        dev = devices.zigzag_tube(20, disorder=0.1)
+        sym = ndg.analyze(dev.n, dev.rowptr, dev.col, dev.val, dev.contacts, dev.coords, tree_kind=3,
+                          slab=-1, layers=dev.layers)
+    costs = sym.costs()
+    info = sym.info()
+    total = sum(c["flops"] for c in costs)
+    assert total == pytest.approx(8 * info["ops_total"], rel=1e-12)
+    got = {(c["name"], c["height"], c["size_class"]): c["flops"] for c in costs if c["flops"] > 0}
+    ref = {k: v for k, v in _recount(dev, sym.arrays()).items() if v > 0}
+    assert set(got) == set(ref)
+    for key, v in ref.items():
+        assert got[key] == pytest.approx(v, rel=1e-12), key
+    # several size classes share a height (one launch each)
+    assert len({(n, h) for n, h, _ in got}) < len(got) or case == "tube_cells"
