@@ -334,6 +334,22 @@ ndg_status ndg_density_vjp(ndg_plan* plan, int32_t nE, const double* E, double e
                            const double* cE, const double* nbar, double* vbar, ndg_precision prec,
                            void* stream);
 
+/* ndg_density_vjp_noalloc: ndg_density_vjp for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, same kernels and same result; the
+ * per-energy partials of a batch live in a file-scope device buffer of 4 Mi
+ * doubles (32 MiB, one per GPU, held until the process ends) instead of the
+ * plan's adjoint workspace, and the call allocates nothing (the plan and its
+ * adjoint workspace, enabled beforehand, are inputs).  Calls that overlap on
+ * one GPU race on that buffer.  Errors: as ndg_density_vjp; NDG_EINVAL when
+ * n x min(nE, max_batch) exceeds 4 Mi, NDG_EHIP if the buffer's device
+ * address cannot be obtained. */
+ndg_status ndg_density_vjp_noalloc(ndg_plan* plan, int32_t nE, const double* E, double eta,
+                                   const double* V, const ndg_c128* const* sig_r,
+                                   const ndg_c128* const* sig_less, const double* cE,
+                                   const double* nbar, double* vbar, ndg_precision prec,
+                                   void* stream);
+
 /* ---------------------------------------------------------------------------
  * Newton step of the Schroedinger-Poisson problem (self-consistency of the
  * potential with the density, the motivation for repeated solves in

@@ -21,7 +21,8 @@ __all__ = ["analyze", "Symbolic", "Plan", "load", "NdgError", "NDG_FP64", "NDG_M
            "ndg_analyze", "ndg_symbolic_info", "ndg_symbolic_arrays", "ndg_plan_create",
            "ndg_plan_destroy", "ndg_plan_info", "ndg_solve", "ndg_plan_status",
            "ndg_plan_export_block", "ndg_plan_set_profiling", "ndg_plan_profile", "ndg_symbolic_costs",
-           "ndg_density", "ndg_plan_enable_adjoint", "ndg_density_vjp", "NDDensity",
+           "ndg_density", "ndg_plan_enable_adjoint", "ndg_density_vjp", "ndg_density_vjp_noalloc",
+           "NDDensity",
            "ndg_batch_create", "ndg_batch_destroy", "ndg_batch_solve", "Batch",
            "ndg_plan_enable_scattering", "ndg_solve_scattering", "ndg_scba", "ndg_poisson_newton_step",
            "ndg_solve_transport",
@@ -180,6 +181,15 @@ def ndg_density_vjp(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, ce_p
     sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
     _lib.check(load().ndg_density_vjp(plan, ne, e_ptr, eta, v_ptr, sr, sl, ce_ptr, nbar_ptr,
                                       vbar_ptr, prec, stream_ptr))
+
+
+def ndg_density_vjp_noalloc(plan, ne, e_ptr, eta, v_ptr, sig_r_ptrs, sig_less_ptrs, ce_ptr, nbar_ptr,
+                            vbar_ptr, prec, stream_ptr):
+    nc = len(sig_r_ptrs)
+    sr = (C.c_void_p * max(1, nc))(*sig_r_ptrs)
+    sl = (C.c_void_p * max(1, nc))(*sig_less_ptrs)
+    _lib.check(load().ndg_density_vjp_noalloc(plan, ne, e_ptr, eta, v_ptr, sr, sl, ce_ptr, nbar_ptr,
+                                              vbar_ptr, prec, stream_ptr))
 
 
 def ndg_plan_status(plan):
@@ -516,15 +526,18 @@ class Plan:
         return gr, gl, gg
 
     def density_vjp(self, E, eta, sig_r, sig_less, cE, nbar, V=None, out=None, prec=NDG_FP64,
-                    stream=None):
-        """(d n / d V)^T nbar; float64 [n] on the GPU."""
+                    stream=None, noalloc=False):
+        """(d n / d V)^T nbar; float64 [n] on the GPU.  noalloc: through
+        ndg_density_vjp_noalloc (the partials in the library's static device
+        buffer; out must then be given, so nothing is allocated)."""
         import torch
         n, ne, dev = self._check_inputs(E, sig_r, sig_less, V)
         if nbar.dtype != torch.float64 or nbar.numel() != n or not nbar.is_contiguous():
             raise ValueError("nbar must be a contiguous float64 [n] tensor")
         out = torch.empty(n, dtype=torch.float64, device=dev) if out is None else out
         st = stream if stream is not None else torch.cuda.current_stream(dev)
-        ndg_density_vjp(self.handle, ne, E.data_ptr(), float(eta),
+        fn = ndg_density_vjp_noalloc if noalloc else ndg_density_vjp
+        fn(self.handle, ne, E.data_ptr(), float(eta),
                         V.data_ptr() if V is not None else None,
                         [t.data_ptr() for t in sig_r], [t.data_ptr() for t in sig_less],
                         cE.data_ptr(), nbar.data_ptr(), out.data_ptr(), prec,

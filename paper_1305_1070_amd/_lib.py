@@ -89,6 +89,8 @@ SIGNATURES = {
     "ndg_plan_enable_adjoint": (C.c_int, [P]),
     "ndg_density_vjp": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P), P,
                                   P, P, C.c_int, P]),
+    "ndg_density_vjp_noalloc": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P),
+                                          P, P, P, C.c_int, P]),
     "ndg_plan_enable_scattering": (C.c_int, [P]),
     "ndg_solve_scattering": (C.c_int, [P, C.c_int32, P, C.c_double, P, C.POINTER(P), C.POINTER(P),
                                        P, P, P, P, P, P, P, P]),

@@ -284,6 +284,27 @@ ndg_status ndg_density_vjp(ndg_plan* plan, int32_t nE, const double* E, double e
                                    stream);
 }
 
+ndg_status ndg_density_vjp_noalloc(ndg_plan* plan, int32_t nE, const double* E, double eta,
+                                   const double* V, const ndg_c128* const* sig_r,
+                                   const ndg_c128* const* sig_less, const double* cE,
+                                   const double* nbar, double* vbar, ndg_precision prec, void* stream) {
+  ndg_status st = check_common("ndg_density_vjp_noalloc", plan, nE, E, eta, prec);
+  if (st != NDG_OK) return st;
+  if (!cE || !nbar || !vbar) {
+    set_error("ndg_density_vjp_noalloc: NULL weights, cotangent or output");
+    return NDG_EINVAL;
+  }
+  int64_t cap = 0;
+  double* part = ndg::noalloc_scratch(ndg::plan_device(plan), &cap);
+  if (!part) {
+    set_error("ndg_density_vjp_noalloc: the static buffer's device address is not available");
+    return NDG_EHIP;
+  }
+  return (ndg_status)ndg::plan_run(plan, ndg::kRunVjp, nE, E, eta, V, sig_r, sig_less, nullptr,
+                                   nullptr, nullptr, nullptr, cE, nullptr, nbar, vbar, (int)prec,
+                                   stream, nullptr, nullptr, nullptr, nullptr, false, part, cap);
+}
+
 ndg_status ndg_plan_status(ndg_plan* plan, int32_t* code, int32_t* energy, int32_t* cluster) {
   if (!plan || !code || !energy || !cluster) { set_error("ndg_plan_status: NULL argument"); return NDG_EINVAL; }
   return (ndg_status)ndg::plan_status(plan, code, energy, cluster);

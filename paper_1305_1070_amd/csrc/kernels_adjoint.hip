@@ -20,6 +20,8 @@
 // recomputed by a fresh fold rather than kept from the forward pass.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -405,6 +407,40 @@ void launch_vjp_reduce(const Ctx& c, const RhsCtx& r, int nb, const double* cE, 
 }
 void launch_density(const Ctx& c, int nb, const double* cE, double* dens, hipStream_t st) {
   hipLaunchKernelGGL(k_density, dim3((c.n + 255) / 256), dim3(256), 0, st, c, nb, cE, dens);
+}
+
+// ---------------------------------------------------------------------------
+// Static partials buffer of ndg_density_vjp_noalloc (for callers that cannot
+// allocate): 4 Mi doubles (32 MiB), one copy per GPU, held until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in for the symbol): its address on each device comes from
+// hipGetSymbolAddress, taken once per device with that device current.  Calls
+// that overlap on one GPU race on this buffer.
+constexpr int64_t kNoAllocDoubles = int64_t(4) << 20;
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+double* noalloc_scratch(int device, int64_t* capacity) {
+  static std::mutex mu;
+  static double* addr[kNoAllocDevices] = {};
+  *capacity = 0;
+  if (device < 0 || device >= kNoAllocDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != device && hipSetDevice(device) != hipSuccess) return nullptr;
+    void* ptr = nullptr;
+    const hipError_t rc = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (rc != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    addr[device] = static_cast<double*>(ptr);
+  }
+  *capacity = kNoAllocDoubles;
+  return addr[device];
 }
 
 }  // namespace ndg

@@ -1058,7 +1058,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
     // the per-energy partials of one batch: the plan's buffer, or the
     // caller-supplied (static) one, which must hold them
     if (vjp_part && (int64_t)std::min(nE, p->max_batch) * p->n > vjp_part_capacity) {
-      set_error("ndg_density_vjp: n x min(nE, max_batch) = " +
+      set_error("ndg_density_vjp_noalloc: n x min(nE, max_batch) = " +
                 std::to_string((int64_t)std::min(nE, p->max_batch) * p->n) +
                 " partials exceed the static buffer of " + std::to_string(vjp_part_capacity) + " doubles");
       return NDG_EINVAL;

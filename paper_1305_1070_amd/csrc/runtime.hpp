@@ -36,6 +36,9 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
              const ndg_c128* sig_less_ph = nullptr, double* current = nullptr, bool reuse_fold = false,
              double* vjp_part = nullptr, int64_t vjp_part_capacity = 0,
              ndg_c128* dgg_explicit = nullptr, double* transmission = nullptr);
+// The no-allocation density VJP's partials: a file-scope device array, its
+// address on `device` (looked up once per device) and its size in doubles.
+double* noalloc_scratch(int device, int64_t* capacity);
 // One batch of energies starting at the device-resident index *e0p (for a
 // graph replayed over the energy range): the launches of a single batch of
 // max_batch energies, slots at or beyond nE skipped; growth is not cleared.
