@@ -323,6 +323,122 @@ def bench_scattering(ndg, workloads, torch, cuda, leaf, n_energies=512, batch=25
             "kernels": kernels, "roofline": roof, "status": list(status)}
 
 
+def _kernel_family(name):
+    """Library kernel family of a rocprofv3 kernel name, as bench.py's
+    per-kernel statistics name it ("k_down_off", ...), with "(mixed)" for the
+    FP32 matrix-core variants (template flag false); None for other kernels."""
+    import re
+    m = re.match(r"\s*(?:void\s+)?ndg::(k_[a-z0-9_]+?)(?:_narrow|_wide)?(<[^(]*>)?\s*\(", name)
+    if not m:
+        return None
+    fam = m.group(1)
+    targs = m.group(2) or ""
+    if re.search(r"\bfalse\b", targs):
+        fam += "(mixed)"
+    return fam
+
+
+def summarize_profile(trace_dir, fetch_dir, write_dir, title, out_md, out_json):
+    """Summaries of rocprofv3 runs of bench.py (kernel trace with --stats, and
+    one --pmc run each for FETCH_SIZE and WRITE_SIZE): per kernel family the
+    dispatches, average duration, and HBM bytes per dispatch scaled by the
+    counters' reading for the plain device copy of known size that
+    --copy-calibration adds.  Writes a markdown table and the JSON the bench
+    reads for roofline.traffic (keyed to the sources' hash)."""
+    import csv
+    import glob
+    import hashlib
+
+    def rows(d, pat):
+        out = []
+        for f in sorted(glob.glob(os.path.join(d, "**", pat), recursive=True)):
+            with open(f) as fh:
+                out += list(csv.DictReader(fh))
+        return out
+
+    trace = rows(trace_dir, "*kernel_trace.csv")
+    dur = {}
+    for r in trace:
+        fam = _kernel_family(r["Kernel_Name"])
+        if fam is None:
+            continue
+        d = dur.setdefault(fam, [0, 0.0])
+        d[0] += 1
+        d[1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+    stats = rows(trace_dir, "*kernel_stats.csv")
+
+    def counters(d, counter):
+        per = {}
+        for r in rows(d, "*counter_collection.csv"):
+            if r.get("Counter_Name") != counter:
+                continue
+            per.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+        return per
+
+    fetch, write = counters(fetch_dir, "FETCH_SIZE"), counters(write_dir, "WRITE_SIZE")
+    copy_bytes = float(1 << 30)  # --copy-calibration: 2^27 doubles read and written
+
+    def calib(per):
+        # the copy is the dispatch outside the library with the largest reading
+        cand = [(v, k) for k, (n, v) in per.items() if _kernel_family(n) is None]
+        v, k = max(cand)
+        return copy_bytes / v, per[k][0]
+
+    f_scale, f_name = calib(fetch)
+    w_scale, w_name = calib(write)
+    traffic = {}
+    for per, scale, key in ((fetch, f_scale, "fetch"), (write, w_scale, "write")):
+        for _, (n, v) in per.items():
+            fam = _kernel_family(n)
+            if fam is None:
+                continue
+            t = traffic.setdefault(fam, {"fetch": [0, 0.0], "write": [0, 0.0]})
+            t[key][0] += 1
+            t[key][1] += v * scale
+    here = os.path.dirname(os.path.abspath(__file__))
+    srcs = sorted(glob.glob(os.path.join(here, "paper_1305_1070_amd", "csrc", "*.hip")) +
+                  glob.glob(os.path.join(here, "paper_1305_1070_amd", "csrc", "*.hpp")) +
+                  glob.glob(os.path.join(here, "paper_1305_1070_amd", "csrc", "*.cpp")))
+    h = hashlib.sha256()
+    for p in srcs:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    kern = {}
+    for fam, t in sorted(traffic.items()):
+        fb = t["fetch"][1] / max(t["fetch"][0], 1)
+        wb = t["write"][1] / max(t["write"][0], 1)
+        kern[fam] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
+                     "dispatches": t["fetch"][0]}
+    rec = {"sources_sha256": h.hexdigest(), "calibration": {
+        "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes, "fetch_scale": f_scale,
+        "write_scale": w_scale, "copy_kernel": f_name}, "kernels": kern}
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    lines = ["# " + title, ""]
+    lines += ["Per kernel family (G^r and G^< extractions and all size classes together; FP32 "
+              "matrix-core variants of the mixed path as \"(mixed)\"): dispatches and average "
+              "duration from the kernel trace, HBM bytes per dispatch from FETCH_SIZE and "
+              "WRITE_SIZE scaled by the same counters' reading for a plain 1 GiB device copy "
+              "(fetch x%.3f, write x%.3f)." % (f_scale, w_scale), "",
+              "| Kernel family | Dispatches | Avg us | Total ms | Fetch MB/dispatch | Write MB/dispatch |",
+              "|---|---|---|---|---|---|"]
+    for fam, (cnt, us) in sorted(dur.items(), key=lambda kv: -kv[1][1]):
+        k = kern.get(fam, {})
+        lines.append("| `%s` | %d | %.1f | %.1f | %s | %s |" % (
+            fam, cnt, us / cnt, us * 1e-3,
+            "%.1f" % (k["fetch_bytes_per_launch"] / 1e6) if k else "-",
+            "%.1f" % (k["write_bytes_per_launch"] / 1e6) if k else "-"))
+    lines += ["", "rocprofv3 --stats (top 30 by total time):", "",
+              "| Kernel | Calls | Total ms | Avg us |", "|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:30]:
+        nm = r["Name"].split("(")[0].strip()
+        lines.append("| `%s` | %s | %.1f | %.1f |" % (nm, r["Calls"], float(r["TotalDurationNs"]) * 1e-6,
+                                                   float(r["AverageNs"]) * 1e-3))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("wrote %s and %s" % (out_md, out_json))
+
+
 def _tree_kw(tree_kw, dev):
     """Tree options for ndg.analyze: {"slab": k} selects the open slab chain
     over the device's transport layers, None nested dissection."""
@@ -357,7 +473,17 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy, the reference kernel for scaling "
                          "hardware byte counters")
+    ap.add_argument("--summarize-profile", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="summarize rocprofv3 runs of this bench into profiles/ (no GPU work)")
+    ap.add_argument("--profile-name", default="superlattice_1024x64",
+                    help="file stem of the summaries under profiles/")
     args = ap.parse_args()
+    if args.summarize_profile:
+        here = os.path.dirname(os.path.abspath(__file__))
+        stem = os.path.join(here, "profiles", args.profile_name)
+        summarize_profile(*args.summarize_profile, title="%s: kernel time and HBM traffic" % args.profile_name,
+                          out_md=stem + "_kernels.md", out_json=os.path.join(here, "profiles", "traffic.json"))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: multi-GPU runs are not implemented (energies are "
