@@ -26,8 +26,9 @@ PEAK_HBM = 8.0e12        # MI355X HBM3E, bytes/s
 
 
 def _rgf_energy(args):
-    """One energy of the RGF oracle (cpu_baseline leg; runs in a worker)."""
-    idx, n_transport, n_transverse, n_energies = args
+    """One energy of the RGF oracle (cpu_baseline leg; runs in a worker);
+    reverse=True sweeps the layers from the other end (untimed parity use)."""
+    idx, n_transport, n_transverse, n_energies, reverse = args
     from inputs import workloads
     from oracle import rgf
     wl = workloads.superlattice(n_transport, n_transverse, n_energies=n_energies)
@@ -35,9 +36,30 @@ def _rgf_energy(args):
     sl, sr, ll, lr = wl.self_energies(e)
     d = wl.device
     t = time.perf_counter()
-    gr, gl, _ = rgf.diag_greens(d.scipy_h(), None, e, wl.eta, d.layers, d.contacts, [sl, sr],
-                                [ll, lr])
+    gr, gl, _ = rgf.diag_greens(d.scipy_h(), None, e, wl.eta, d.layers[::-1] if reverse else d.layers,
+                                d.contacts, [sl, sr], [ll, lr])
     return idx, time.perf_counter() - t, gr[0], gl[0]
+
+
+def _host_description():
+    """CPU model and the BLAS numpy links (reported with the CPU baseline)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = "unknown"
+    try:
+        cfg = np.show_config(mode="dicts")
+        b = cfg.get("Build Dependencies", {}).get("blas", {})
+        blas = "%s %s" % (b.get("name", "?"), b.get("version", ""))
+    except Exception:
+        pass
+    return model, blas.strip()
 
 
 def _progress(msg):
@@ -56,14 +78,18 @@ def cpu_baseline(idxs, wl_args):
     cores = max(1, min(cores, len(idxs)))
     t0 = time.perf_counter()
     res = {}
+    rev = {}
     with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
         # warm the workers (imports) before timing
         list(ex.map(_noop, range(cores)))
         t0 = time.perf_counter()
-        for idx, dt, gr, gl in ex.map(_rgf_energy, [(i,) + wl_args for i in idxs]):
+        for idx, dt, gr, gl in ex.map(_rgf_energy, [(i,) + wl_args + (False,) for i in idxs]):
             res[idx] = (gr, gl)
-    wall = time.perf_counter() - t0
-    return len(idxs) / wall, cores, wall, res
+        wall = time.perf_counter() - t0
+        # the sweeps from the other end (not timed): the oracle's own error
+        for idx, dt, gr, gl in ex.map(_rgf_energy, [(i,) + wl_args + (True,) for i in idxs]):
+            rev[idx] = (gr, gl)
+    return len(idxs) / wall, cores, wall, res, rev
 
 
 def _noop(_):
@@ -379,8 +405,11 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, title, out_md, out_json):
     copy_bytes = float(1 << 30)  # --copy-calibration: 2^27 doubles read and written
 
     def calib(per):
-        # the copy is the dispatch outside the library with the largest reading
-        cand = [(v, k) for k, (n, v) in per.items() if _kernel_family(n) is None]
+        # the calibration copy (torch's elementwise multiply of 2^27 doubles)
+        # is the elementwise dispatch outside the library with the largest
+        # reading
+        cand = [(v, k) for k, (n, v) in per.items()
+                if _kernel_family(n) is None and "elementwise" in n and "Mul" in n]
         v, k = max(cand)
         return copy_bytes / v, per[k][0]
 
@@ -470,6 +499,9 @@ def main():
                     help="skip the batched uneven-device and nanotube throughput figures")
     ap.add_argument("--cpu-sample", type=int, default=32,
                     help="energies of the CPU oracle timing sample (0 disables it)")
+    ap.add_argument("--serialize", action="store_true",
+                    help="every solve with per-launch events and all launches on one stream (profiling "
+                         "mode 2), so a kernel trace's per-kernel durations match the bench's own")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy, the reference kernel for scaling "
                          "hardware byte counters")
@@ -539,6 +571,8 @@ def main():
     out = tuple(torch.empty((ne, n), dtype=torch.complex128, device=cuda) for _ in range(3))
     stream = torch.cuda.current_stream(cuda)
 
+    if args.serialize:
+        plan.set_profiling(2)
     for _ in range(args.warmup):
         plan.solve(E, wl.eta, sig_r, sig_l, out=out, stream=stream)
     torch.cuda.synchronize()
@@ -558,13 +592,15 @@ def main():
     # the caller's stream (profiling mode 2: no overlap between the G^r and
     # G^< extractions, so each kernel's event time is its own), each launch
     # credited with its own launch group's algorithmic work
+    plan.profile()  # clear (with --serialize the timed steps were profiled too)
     plan.set_profiling(2)
     ev0.record(stream)
     for _ in range(args.steps):
         plan.solve(E, wl.eta, sig_r, sig_l, out=out, stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
-    plan.set_profiling(False)
+    if not args.serialize:
+        plan.set_profiling(False)
     ms_profiled = ev0.elapsed_time(ev1) / args.steps
     per_level = plan.profile()
     status2 = plan.status()
@@ -592,6 +628,16 @@ def main():
     torch.cuda.synchronize()
     ms_mixed = ev0.elapsed_time(ev1) / args.steps
     _progress("mixed superlattice: %.1f ms per step" % ms_mixed)
+    # the mixed path against the FP64 path at every energy (the FP64 result
+    # is far closer to the exact one than 1e-6, see parity_sample)
+    mixed_err = []
+    for k0 in range(0, ne, 64):
+        a = [t[k0:k0 + 64] for t in out[:2]]
+        b = [t[k0:k0 + 64] for t in out_m[:2]]
+        e_k = torch.maximum((b[0] - a[0]).abs().amax(1) / a[0].abs().amax(1),
+                            (b[1] - a[1]).abs().amax(1) / a[1].abs().amax(1))
+        mixed_err.append(e_k.cpu().numpy())
+    mixed_err = np.concatenate(mixed_err)
     growth = torch.zeros(ne, dtype=torch.float64, device=cuda)
     plan.solve(E, wl.eta, sig_r, sig_l, out=out, stream=stream, growth=growth)
     torch.cuda.synchronize()
@@ -648,11 +694,13 @@ def main():
 
     copy_cal = None
     if args.copy_calibration:
+        # a plain streaming kernel (torch's elementwise multiply, not the
+        # runtime's copy engine): reads 1 GiB and writes 1 GiB
         src = torch.empty(1 << 27, dtype=torch.float64, device=cuda).fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         ev0.record(stream)
-        dst.copy_(src)
+        torch.mul(src, 2.0, out=dst)
         ev1.record(stream)
         torch.cuda.synchronize()
         copy_cal = {"bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8,
@@ -688,24 +736,33 @@ def main():
         _progress("extra legs done")
     if args.cpu_sample > 0:
         idxs = list(np.linspace(0, ne - 1, args.cpu_sample).round().astype(int))
-        rate, cores, cwall, res = cpu_baseline(idxs, (n_transport, n_transverse, ne))
+        rate, cores, cwall, res, rev = cpu_baseline(idxs, (n_transport, n_transverse, ne))
+        model, blas = _host_description()
         cpu = {"value": rate, "unit": UNIT, "cores": cores, "kind": "oracle",
                "sample": "%d of the %d energies (evenly spaced), plain RGF oracle, complex128, "
-                         "one process per core, %.1f s wall" % (len(idxs), ne, cwall)}
-        parity = {"energies": len(idxs), "growth_below_30": int(np.sum(growth[idxs] < 30))}
+                         "one process per core, %.1f s wall" % (len(idxs), ne, cwall),
+               "cpu_model": model, "blas": blas}
+
+        def rel(x, r):
+            return np.max(np.abs(x - r)) / np.max(np.abs(r))
+
+        # the oracle's own uncertainty: its two sweep directions' disagreement
+        d_rgf = np.array([max(rel(res[i][0], rev[i][0]), rel(res[i][1], rev[i][1])) for i in idxs])
+        parity = {"energies": len(idxs), "reference": "RGF oracle, nearer of its two sweep directions",
+                  "oracle_disagreement_max": float(d_rgf.max()),
+                  "oracle_disagreement_above_1e-11": int(np.sum(d_rgf > 1e-11))}
         for tag, o in (("fp64", out), ("mixed", out_m)):
             gr = o[0][idxs].cpu().numpy()
             gl = o[1][idxs].cpu().numpy()
             errs = []
             for k, i in enumerate(idxs):
-                rgr, rgl = res[i]
-                errs.append(max(np.max(np.abs(gr[k] - rgr)) / np.max(np.abs(rgr)),
-                                np.max(np.abs(gl[k] - rgl)) / np.max(np.abs(rgl))))
+                errs.append(max(min(rel(gr[k], res[i][0]), rel(gr[k], rev[i][0])),
+                                min(rel(gl[k], res[i][1]), rel(gl[k], rev[i][1]))))
             errs = np.array(errs)
-            good = growth[idxs] < 30
+            bound = 1e-10 + 2 * d_rgf
             parity[tag] = {"max_rel_err": float(errs.max()), "median_rel_err": float(np.median(errs)),
-                           "max_rel_err_growth_below_30": float(errs[good].max()) if good.any() else None,
                            "above_1e-10": int(np.sum(errs > 1e-10)),
+                           "above_1e-10_plus_oracle": int(np.sum(errs > bound)),
                            "above_1e-6": int(np.sum(errs > 1e-6))}
 
     line = {
@@ -722,7 +779,11 @@ def main():
                    "algorithmic_gflop_per_energy": info["ops_total"] * 8 / 1e9,
                    "rgf_gflop_per_energy": info["ops_rgf_equiv"] * 8 / 1e9},
         "mixed": {"value": ne / (ms_mixed / 1e3), "ms_per_step": ms_mixed,
-                  "speedup_vs_fp64": ms_per_step / ms_mixed},
+                  "speedup_vs_fp64": ms_per_step / ms_mixed,
+                  "err_vs_fp64": {"median": float(np.median(mixed_err)), "max": float(mixed_err.max()),
+                                  "above_1e-6": int(np.sum(mixed_err > 1e-6)), "energies": int(ne)},
+                  # the metric counts the mixed figure only at <= 1e-6 per energy
+                  "counted_under_metric": bool(np.all(mixed_err <= 1e-6))},
         "adjoint": adj,
         "scattering": scat,
         "roofline": roof,
