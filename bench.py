@@ -349,6 +349,22 @@ def bench_scattering(ndg, workloads, torch, cuda, leaf, n_energies=512, batch=25
             "kernels": kernels, "roofline": roof, "status": list(status)}
 
 
+def _copy_calibration(torch, cuda):
+    """A plain streaming kernel (torch's elementwise multiply, not the
+    runtime's copy engine) that reads 1 GiB and writes 1 GiB: the reference
+    dispatch for scaling the hardware byte counters."""
+    stream = torch.cuda.current_stream(cuda)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    src = torch.empty(1 << 27, dtype=torch.float64, device=cuda).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    torch.mul(src, 2.0, out=dst)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return {"bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8, "ms": ev0.elapsed_time(ev1)}
+
+
 def _kernel_family(name):
     """Library kernel family of a rocprofv3 kernel name, as bench.py's
     per-kernel statistics name it ("k_down_off", ...), with "(mixed)" for the
@@ -364,7 +380,7 @@ def _kernel_family(name):
     return fam
 
 
-def summarize_profile(trace_dir, fetch_dir, write_dir, title, out_md, out_json):
+def summarize_profile(trace_dir, fetch_dir, write_dir, title, out_md, out_json, commands=()):
     """Summaries of rocprofv3 runs of bench.py (kernel trace with --stats, and
     one --pmc run each for FETCH_SIZE and WRITE_SIZE): per kernel family the
     dispatches, average duration, and HBM bytes per dispatch scaled by the
@@ -444,6 +460,9 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, title, out_md, out_json):
     with open(out_json, "w") as fh:
         json.dump(rec, fh, indent=1)
     lines = ["# " + title, ""]
+    if commands:
+        lines += ["Made by (from the repository root, after `cd /tmp && export TMPDIR=/tmp`; `R` the "
+                  "repository root):", "", "```"] + list(commands) + ["```", ""]
     lines += ["Per kernel family (G^r and G^< extractions and all size classes together; FP32 "
               "matrix-core variants of the mixed path as \"(mixed)\"): dispatches and average "
               "duration from the kernel trace, HBM bytes per dispatch from FETCH_SIZE and "
@@ -482,12 +501,15 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=512, help="energies in flight per batch")
-    ap.add_argument("--leaf", type=int, default=0,
-                    help="leaf size of the separator tree (0: picked by the autotuner)")
+    ap.add_argument("--leaf", type=int, default=20,
+                    help="leaf size of the separator tree (0: picked by the autotuner; 20 is its pick "
+                         "for this workload)")
     ap.add_argument("--tree", choices=("chain", "nd"), default="chain",
                     help="open slab chain (every folded region holds a contact or is a thin slab; "
                          "the default) or nested dissection")
-    ap.add_argument("--slab", type=int, default=0, help="slab length of the chain (0: autotuned)")
+    ap.add_argument("--slab", type=int, default=12,
+                    help="slab length of the chain in layers (0: autotuned; 12 is the autotuner's pick "
+                         "and the longest slab whose levels lie above the energy window)")
     ap.add_argument("--energies", type=int, default=512)
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false")
     ap.add_argument("--no-scattering", dest="scattering", action="store_false",
@@ -509,12 +531,18 @@ def main():
                     help="summarize rocprofv3 runs of this bench into profiles/ (no GPU work)")
     ap.add_argument("--profile-name", default="superlattice_1024x64",
                     help="file stem of the summaries under profiles/")
+    ap.add_argument("--profile-command", action="append", default=[],
+                    help="a command that made the runs (written into the summary; repeatable)")
+    ap.add_argument("--traffic-json", default="traffic.json",
+                    help="name under profiles/ of the per-kernel traffic record the summary writes "
+                         "(traffic_scattering.json for the phonon solve's)")
     args = ap.parse_args()
     if args.summarize_profile:
         here = os.path.dirname(os.path.abspath(__file__))
         stem = os.path.join(here, "profiles", args.profile_name)
         summarize_profile(*args.summarize_profile, title="%s: kernel time and HBM traffic" % args.profile_name,
-                          out_md=stem + "_kernels.md", out_json=os.path.join(here, "profiles", "traffic.json"))
+                          out_md=stem + "_kernels.md", out_json=os.path.join(here, "profiles", args.traffic_json),
+                          commands=args.profile_command)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -535,9 +563,11 @@ def main():
     scat_tree = None
     if args.only_scattering:
         ndg.load()
-        print(json.dumps(bench_scattering(ndg, workloads, torch, torch.device("cuda:0"),
-                                          args.leaf if args.leaf > 0 else 20, tree_kw=scat_tree)),
-              flush=True)
+        rec = bench_scattering(ndg, workloads, torch, torch.device("cuda:0"), args.leaf if args.leaf > 0 else 20,
+                               tree_kw=scat_tree)
+        if args.copy_calibration:
+            rec["copy_calibration"] = _copy_calibration(torch, torch.device("cuda:0"))
+        print(json.dumps(rec), flush=True)
         return
 
     n_transport, n_transverse = 1024, 64
@@ -692,20 +722,7 @@ def main():
                  "ribbon_graph_tree": bench_ribbon(ndg, workloads, torch, cuda),
                  "newton_step": bench_newton(ndg, workloads, torch, cuda, args.leaf, tree_kw=tree_kw)}
 
-    copy_cal = None
-    if args.copy_calibration:
-        # a plain streaming kernel (torch's elementwise multiply, not the
-        # runtime's copy engine): reads 1 GiB and writes 1 GiB
-        src = torch.empty(1 << 27, dtype=torch.float64, device=cuda).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        torch.mul(src, 2.0, out=dst)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        copy_cal = {"bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8,
-                    "ms": ev0.elapsed_time(ev1)}
-        del src, dst
+    copy_cal = _copy_calibration(torch, cuda) if args.copy_calibration else None
 
     # dominant kernel and its roofline
     dom = max(stats, key=lambda r: r["ms"])
