@@ -195,6 +195,28 @@ __device__ inline void ztile_store(const ZTile& acc, FS fs) {
   ztile_store_t<64>(acc, fs);
 }
 
+// Calls fs(i, j, re, im) with references to every tile element this thread
+// holds (same layout as ztile_store_t), to update the tile in place.
+template <int TM, class FS>
+__device__ inline void ztile_apply_t(ZTile& acc, FS fs) {
+  using T = TileShape<TM>;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
+#pragma unroll
+  for (int m = 0; m < T::MB; ++m)
+#pragma unroll
+    for (int n = 0; n < T::NB; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = wr + m * 16 + (lane >> 4) + 4 * r;
+        const int j = wc + n * 16 + (lane & 15);
+        double re = acc.re[m][n][r], im = acc.im[m][n][r];
+        fs(i, j, re, im);
+        acc.re[m][n][r] = re;
+        acc.im[m][n][r] = im;
+      }
+}
+
 
 // ---------------------------------------------------------------------------
 // Complex FP32 tiles on the FP32 matrix cores (mixed-precision path):
@@ -574,6 +596,14 @@ __device__ inline double2 gather_bb(const Ctx& c, const double2* S, const Cluste
   const int32_t m = c.gaddr[d.o_gaddr + (int64_t)u * d.b + v];
   const double2 x = S[(int64_t)(m & 0x7FFFFFFF) + (lesser ? c.pdelta : 0)];
   return (m < 0 && lesser) ? make_double2(-x.x, x.y) : x;
+}
+
+// Entry (u, v) of X_{B,B} where B is a run of one ancestor's points
+// (ClusterDesc::o_bbd): a dense block of that ancestor's stored rows, no
+// lookup.
+__device__ inline double2 direct_bb(const Ctx& c, const double2* S, const ClusterDesc& d, int u, int v,
+                                    bool lesser) {
+  return S[d.o_bbd + (int64_t)u * d.bbd_ld + v + (lesser ? c.pdelta : 0)];
 }
 
 // The exact X_ii block of G^r is complex symmetric and that of G^< anti-

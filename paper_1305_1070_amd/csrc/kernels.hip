@@ -18,9 +18,12 @@ namespace ndg {
 // ---------------------------------------------------------------------------
 // Fold: assemble the rows of cluster i of the front [i, B_i] of A^(l): its
 // rows of A (entries towards i and B_i) plus the children's Schur
-// contributions that land in those rows (extend-add, one child at a time so
-// no two threads write one entry at once).  The B x B block of the front is
-// not formed: the Schur update gathers it from the children directly.
+// contributions that land in those rows (extend-add).  Gathered: each entry
+// sums its terms in registers and is written once, each child's term found
+// through the child's map from this front's positions to its B indices
+// (only the leading rows of a child's contribution, its parent's points,
+// land in these rows).  The B x B block of the front is not formed: the
+// Schur update gathers it from the children directly.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
   const int cl = cls[blockIdx.x];
@@ -35,8 +38,18 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
   const double* hf = c.hfront + d.o_hf;
   const int32_t* smp = d.o_smap >= 0 ? c.smap + d.o_smap : nullptr;
   const double ez = c.E[eb + e];
-  // -H, z - V on the diagonal, -Sigma: every entry of the rows written once
-  // (one pass over all s f entries, so short rows do not idle threads)
+  __shared__ int64_t kid_inv[kMaxKids], kid_upd[kMaxKids];
+  __shared__ int kid_b[kMaxKids];
+  const int k0 = c.kids_ptr[cl], nk = c.kids_ptr[cl + 1] - k0;
+  for (int q = t; q < nk; q += 256) {
+    const ClusterDesc& dc = c.cl[c.kids[k0 + q]];
+    kid_inv[q] = dc.o_pinv;
+    kid_upd[q] = dc.o_upd;
+    kid_b[q] = dc.b;
+  }
+  __syncthreads();
+  // -H, z - V on the diagonal, -Sigma, then the children's terms: one pass
+  // over all s f entries, so short rows do not idle threads
   for (int q = t; q < s * f; q += 256) {
     const int i = q / f, j = q - i * f;
     double re = hf[q], im = 0.0;
@@ -59,27 +72,17 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
         im -= sv.y;
       }
     }
-    F[q] = make_double2(re, im);
-  }
-  __syncthreads();
-  // children's contributions to these rows
-  for (int kp = c.kids_ptr[cl]; kp < c.kids_ptr[cl + 1]; ++kp) {
-    const ClusterDesc dc = c.cl[c.kids[kp]];
-    const int bc = dc.b;
-    const int32_t* rel = c.relmap + dc.bptr;
-    const double2* U = S + dc.o_upd;
-    // only the leading dc.nself rows land in this cluster's rows
-    for (int q = t; q < dc.nself * bc; q += 256) {
-      const int r = q / bc;
-      const int pr = rel[r];
-      const int cc = q - r * bc;
-      const double2 u = U[q];
-      double2 v = F[(int64_t)pr * f + rel[cc]];
-      v.x += u.x;
-      v.y += u.y;
-      F[(int64_t)pr * f + rel[cc]] = v;
+    for (int kq = 0; kq < nk; ++kq) {
+      const int32_t* inv = c.pinv + kid_inv[kq];
+      const int ri = inv[i];
+      if (ri < 0) continue;
+      const int rj = inv[j];
+      if (rj < 0) continue;
+      const double2 u = S[kid_upd[kq] + (int64_t)ri * kid_b[kq] + rj];
+      re += u.x;
+      im += u.y;
     }
-    __syncthreads();
+    F[q] = make_double2(re, im);
   }
 }
 
@@ -156,7 +159,7 @@ __global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
 
 // Psi_{i,B_i} = -A_ii^{-1} A_{i,B_i}: one 64-column tile per block.
 template <int TM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_psi(Ctx c, const ColItem* items) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 64 ? 2 : 3))) k_psi(Ctx c, const ColItem* items) {
   __shared__ GemmSmemR<TM> sm;
   const ColItem it = items[blockIdx.x];
   const int e = blockIdx.y;
@@ -315,78 +318,57 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   const double2* Ainv = S + d.o_ainv;
   const int s = d.s, b = d.b, f = d.f;
   const int t = threadIdx.x;
-  for (int q = t; q < f * sc; q += 256) Zf[q] = cz();
-  __syncthreads();
+  // The right-hand side over the front before the solve, read where it
+  // lives: a one at each of the contact's sites held by this cluster (its
+  // own column), else the chain child's contribution V_d at the positions
+  // its B maps to, else zero.  Every entry of Zf is then written once.
   const int ch = sel2(d.chain_child, cc);
+  const double2* Zc = nullptr;
+  const int32_t* inv = nullptr;  // front position -> the child's B index, or -1
+  int cs = 0;
   if (ch >= 0) {
     const ClusterDesc dc = c.cl[ch];
-    const double2* Zc = S + sel2(dc.o_zf, cc);
-    const int32_t* rel = c.relmap + dc.bptr;
-    for (int q = t; q < dc.b * sc; q += 256) {
-      const int r = q / sc, a = q % sc;
-      Zf[(int64_t)rel[r] * sc + a] = Zc[(int64_t)(dc.s + r) * sc + a];
-    }
+    Zc = S + sel2(dc.o_zf, cc);
+    inv = c.pinv + dc.o_pinv;
+    cs = dc.s;
   }
-  __syncthreads();
-  // the contact's own columns: ones at its sites held by this cluster
-  {
-    const int32_t* pos = sel2(c.cpos, cc);
-    for (int a = t; a < sc; a += 256) {
-      const int r = pos[a] - d.pt_off;
-      if (r >= 0 && r < s) Zf[(int64_t)r * sc + a] = make_double2(1.0, 0.0);
-    }
-  }
-  __syncthreads();
+  const int32_t* pos = sel2(c.cpos, cc);
+  const int off = d.pt_off;
+  auto rhs = [&](int p, int a) {
+    if (p < s && pos[a] - off == p) return make_double2(1.0, 0.0);
+    const int r = inv ? inv[p] : -1;
+    return r >= 0 ? Zc[(int64_t)(cs + r) * sc + a] : cz();
+  };
   // contacts wider than one tile: 64-column panels of Zf, independent
   for (int j0 = 0; j0 < sc; j0 += 64) {
     const int nj = min(64, sc - j0);
+    // rows [s, f): V_i = rhs + Psi^T rhs_i
     for (int i0 = 0; i0 < b; i0 += 64) {
       const int ni = min(64, b - i0);
       ZTile acc;
       ztile_zero(acc);
       zgemm_acc<true, false>(
           s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
-          [&](int k, int j) { return j < nj ? Zf[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
+          [&](int k, int j) { return j < nj ? rhs(k, j0 + j) : cz(); }, acc, sm);
       ztile_store(acc, [&](int i, int j, double re, double im) {
         if (i < ni && j < nj) {
-          double2 v = Zf[(int64_t)(s + i0 + i) * sc + j0 + j];
-          v.x += re;
-          v.y += im;
-          Zf[(int64_t)(s + i0 + i) * sc + j0 + j] = v;
+          const double2 v = rhs(s + i0 + i, j0 + j);
+          Zf[(int64_t)(s + i0 + i) * sc + j0 + j] = make_double2(v.x + re, v.y + im);
         }
       });
     }
-    if (s <= 64) {
-      // in place: the panel's rows [0, s) are all staged before any is written
+    // rows [0, s): Zd_i = A_ii^{-1} rhs_i, in 64-row tiles
+    for (int r0 = 0; r0 < s; r0 += 64) {
+      const int ni = min(64, s - r0);
       ZTile acc;
       ztile_zero(acc);
       zgemm_acc<false, false>(
-          s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
-          [&](int k, int j) { return j < nj ? Zf[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
+          s, [&](int i, int k) { return i < ni ? Ainv[(r0 + i) * s + k] : cz(); },
+          [&](int k, int j) { return j < nj ? rhs(k, j0 + j) : cz(); }, acc, sm);
       ztile_store(acc, [&](int i, int j, double re, double im) {
-        if (i < s && j < nj) Zf[(int64_t)i * sc + j0 + j] = make_double2(re, im);
+        if (i < ni && j < nj) Zf[(int64_t)(r0 + i) * sc + j0 + j] = make_double2(re, im);
       });
-    } else {
-      // 64-row tiles through the cluster's s x sc scratch, then copied back
-      double2* T = S + sel2(d.o_t, cc);
-      for (int r0 = 0; r0 < s; r0 += 64) {
-        const int ni = min(64, s - r0);
-        ZTile acc;
-        ztile_zero(acc);
-        zgemm_acc<false, false>(
-            s, [&](int i, int k) { return i < ni ? Ainv[(r0 + i) * s + k] : cz(); },
-            [&](int k, int j) { return j < nj ? Zf[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
-        ztile_store(acc, [&](int i, int j, double re, double im) {
-          if (i < ni && j < nj) T[(int64_t)(r0 + i) * sc + j0 + j] = make_double2(re, im);
-        });
-        __syncthreads();
-      }
-      for (int q = t; q < s * nj; q += 256) {
-        const int i = q / nj, j = q - i * nj;
-        Zf[(int64_t)i * sc + j0 + j] = T[(int64_t)i * sc + j0 + j];
-      }
     }
-    __syncthreads();
   }
 }
 
@@ -491,8 +473,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // stored rows of the clusters owning B (gather_bb): every cluster keeps only
 // its own rows [G_ii, G_{i,B}], which its descendants read.
 // ---------------------------------------------------------------------------
-template <int TM, bool P64>
-__device__ __forceinline__ void down_off_body(const Ctx& c, const ColItem* items, int lesser) {
+template <int TM, bool P64, int L>
+__device__ __forceinline__ void down_off_body(const Ctx& c, const ColItem* items) {
+  constexpr bool lesser = L != 0;
   using GM = Gemm<P64>;
   __shared__ typename GM::template SmemT<TM> sm;
   const ColItem it = items[blockIdx.x];
@@ -511,9 +494,13 @@ __device__ __forceinline__ void down_off_body(const Ctx& c, const ColItem* items
     const int ni = min(TM, s - r0);
     typename GM::Tile acc;
     GM::zero(acc);
-    GM::template acc<TM, false, false>(
-        b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
-        [&](int k, int j) { return j < nj ? gather_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm);
+    auto fa = [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); };
+    if (d.o_bbd >= 0)
+      GM::template acc<TM, false, false>(
+          b, fa, [&](int k, int j) { return j < nj ? direct_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm);
+    else
+      GM::template acc<TM, false, false>(
+          b, fa, [&](int k, int j) { return j < nj ? gather_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm);
     GM::template store<TM>(acc, [&](int i, int j, double re, double im) {
       if (i < ni && j < nj) {
         double2 v = make_double2(re, im);
@@ -526,24 +513,52 @@ __device__ __forceinline__ void down_off_body(const Ctx& c, const ColItem* items
   }
 }
 
-// 32- and 64-row tiles: three waves per SIMD; 16-row tiles (bound by the
-// gather of X_{B,B}, not the matrix cores) hold fewer registers and run six
-// to keep more gathers in flight.
-template <int TM, bool P64>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-k_down_off(Ctx c, const ColItem* items, int lesser) {
-  down_off_body<TM, P64>(c, items, lesser);
+// Occupancy targets without register spills (spilled registers go through
+// scratch memory, costing HBM traffic): 64-row tiles two waves per SIMD,
+// 32-row tiles three, 16-row tiles (bound by the gather of X_{B,B}, not the
+// matrix cores) four.
+template <int TM, bool P64, int L>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 64 ? 2 : 3)))
+k_down_off(Ctx c, const ColItem* items) {
+  down_off_body<TM, P64, L>(c, items);
 }
-template <bool P64>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
-k_down_off_narrow(Ctx c, const ColItem* items, int lesser) {
-  down_off_body<16, P64>(c, items, lesser);
+template <bool P64, int L>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_down_off_narrow(Ctx c, const ColItem* items) {
+  down_off_body<16, P64, L>(c, items);
 }
 
 //   G_ii = A_ii^{-1} + Psi_i G_{B,i},  G_{B,i} = G_{i,B}^T
 //   P_ii = P_init + Psi_i P_{B,i},     P_{B,i} = -P_{i,B}^+
-template <int TM, bool P64>
-__device__ __forceinline__ void down_diag_body(const Ctx& c, const int32_t* cls, int lesser) {
+// Tile (r0, c0) of the block (TM x 64) as the product Psi_i X_{B,i} in acc.
+template <int TM, bool P64, int L, class SM>
+__device__ __forceinline__ void down_diag_tile(const double2* Psi, const double2* X, int s, int b, int f, int r0,
+                                               int c0, typename Gemm<P64>::Tile& acc, SM& sm) {
+  using GM = Gemm<P64>;
+  const int ni = min(TM, s - r0), nj = min(64, s - c0);
+  GM::zero(acc);
+  if constexpr (L != 0) {
+    GM::template acc<TM, false, true>(
+        b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
+        [&](int k, int j) {
+          if (j >= nj) return cz();
+          const double2 x = X[(int64_t)(c0 + j) * f + s + k];
+          return make_double2(-x.x, x.y);
+        },
+        acc, sm);
+  } else {
+    GM::template acc<TM, false, true>(
+        b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
+        [&](int k, int j) { return j < nj ? X[(int64_t)(c0 + j) * f + s + k] : cz(); }, acc, sm);
+  }
+}
+
+// Blocks larger than one tile (and the FP32 tiles of the mixed path): TM x
+// 64 tiles, each stored with U_i (G) or the source (P) added, then the
+// block replaced by its symmetric (G) or anti-Hermitian (P) part in place.
+template <int TM, bool P64, int L>
+__device__ __forceinline__ void down_diag_body(const Ctx& c, const int32_t* cls) {
+  constexpr bool lesser = L != 0;
   using GM = Gemm<P64>;
   __shared__ typename GM::template SmemT<TM> sm;
   const int cl = cls[blockIdx.x];
@@ -557,32 +572,17 @@ __device__ __forceinline__ void down_diag_body(const Ctx& c, const int32_t* cls,
   double2* X = S + (lesser ? d.o_fp : d.o_fg);
   const int s = d.s, b = d.b, f = d.f;
   const bool has_src = lesser && (d.chain_mask || c.scat);
-  // TM x 64 tiles of the s x s block (one unless s > TM); the block's
-  // columns [0, s) are written, its columns [s, f) only read
+  // the block's columns [0, s) are written, its columns [s, f) only read
   for (int r0 = 0; r0 < s; r0 += TM)
     for (int c0 = 0; c0 < s; c0 += 64) {
       const int ni = min(TM, s - r0), nj = min(64, s - c0);
       typename GM::Tile acc;
-      GM::zero(acc);
-      if (lesser) {
-        GM::template acc<TM, false, true>(
-            b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
-            [&](int k, int j) {
-              if (j >= nj) return cz();
-              const double2 x = X[(int64_t)(c0 + j) * f + s + k];
-              return make_double2(-x.x, x.y);
-            },
-            acc, sm);
-      } else {
-        GM::template acc<TM, false, true>(
-            b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
-            [&](int k, int j) { return j < nj ? X[(int64_t)(c0 + j) * f + s + k] : cz(); }, acc, sm);
-      }
+      down_diag_tile<TM, P64, L>(Psi, X, s, b, f, r0, c0, acc, sm);
       GM::template store<TM>(acc, [&](int i, int j, double re, double im) {
         if (i < ni && j < nj) {
           double2 v = make_double2(re, im);
           const int64_t pos = (int64_t)(r0 + i) * f + c0 + j;
-          if (lesser) {
+          if constexpr (lesser) {
             if (has_src) { const double2 p0 = X[pos]; v.x += p0.x; v.y += p0.y; }
           } else {
             const double2 a = Ainv[(r0 + i) * s + c0 + j];
@@ -594,19 +594,83 @@ __device__ __forceinline__ void down_diag_body(const Ctx& c, const int32_t* cls,
       });
       if (r0 + TM < s || c0 + 64 < s) __syncthreads();
     }
-  symmetrize_block(X, s, f, lesser != 0);
+  symmetrize_block(X, s, f, lesser);
 }
 
-// Entry points as for k_down_off: 16-row tiles at six waves per SIMD.
-template <int TM, bool P64>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-k_down_diag(Ctx c, const int32_t* cls, int lesser) {
-  down_diag_body<TM, P64>(c, cls, lesser);
+// Blocks of one tile (s <= TM <= 64, FP64): the symmetric (G) or
+// anti-Hermitian (P) part formed on chip, the transposed entries exchanged
+// through the staging memory (free once the product is done) one plane at a
+// time, and every entry written once.
+template <int TM, int L>
+__device__ __forceinline__ void down_diag_single_body(const Ctx& c, const int32_t* cls) {
+  constexpr bool lesser = L != 0;
+  __shared__ GemmSmemR<TM> sm;
+  const int cl = cls[blockIdx.x];
+  const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
+  const ClusterDesc d = c.cl[cl];
+  double2* S = slab(c, e);
+  const double2* Psi = S + d.o_psi;
+  const double2* Ainv = S + d.o_ainv;
+  double2* X = S + (lesser ? d.o_fp : d.o_fg);
+  const int s = d.s, b = d.b, f = d.f;
+  const bool has_src = lesser && (d.chain_mask || c.scat);
+  ZTile acc;
+  down_diag_tile<TM, true, L>(Psi, X, s, b, f, 0, 0, acc, sm);
+  // the block before symmetrization: the product plus U_i (G) or the
+  // source (P, on the contact chains)
+  ztile_apply_t<TM>(acc, [&](int i, int j, double& re, double& im) {
+    if (i < s && j < s) {
+      if constexpr (lesser) {
+        if (has_src) {
+          const double2 p0 = X[(int64_t)i * f + j];
+          re += p0.x;
+          im += p0.y;
+        }
+      } else {
+        const double2 a = Ainv[i * s + j];
+        re += a.x;
+        im += a.y;
+      }
+    }
+  });
+  constexpr int LD = TM + 1;
+  static_assert(sizeof(sm) >= sizeof(double) * TM * LD, "staging holds one plane");
+  double* plane = reinterpret_cast<double*>(&sm);
+  double* Xd = reinterpret_cast<double*>(X);
+  for (int part = 0; part < 2; ++part) {
+    __syncthreads();
+    ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
+      if (i < s && j < s) plane[i * LD + j] = part ? im : re;
+    });
+    __syncthreads();
+    ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
+      if (i < s && j < s) {
+        const double t = plane[j * LD + i];
+        // (X + X^T) / 2, or (X - X^+) / 2: real parts subtract
+        const double o = part ? 0.5 * (im + t) : (lesser ? 0.5 * (re - t) : 0.5 * (re + t));
+        Xd[2 * (i * f + j) + part] = o;
+      }
+    });
+  }
 }
-template <bool P64>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
-k_down_diag_narrow(Ctx c, const int32_t* cls, int lesser) {
-  down_diag_body<16, P64>(c, cls, lesser);
+
+// Entry points as for k_down_off (occupancy without spills).
+template <int TM, bool P64, int L>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 64 ? 2 : 3)))
+k_down_diag(Ctx c, const int32_t* cls) {
+  down_diag_body<TM, P64, L>(c, cls);
+}
+template <bool P64, int L>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_down_diag_narrow(Ctx c, const int32_t* cls) {
+  down_diag_body<16, P64, L>(c, cls);
+}
+template <int TM, int L>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_down_diag_single(Ctx c, const int32_t* cls) {
+  down_diag_single_body<TM, L>(c, cls);
 }
 
 // diag G^r, G^<, G^> in the caller's site order; G^> = G^< + G^r - (G^r)^*.
@@ -685,31 +749,43 @@ void launch_update(const Ctx& c, const UpdItem* it, int nit, int nb, int tile_ro
 void launch_chain_fwd(const Ctx& c, const ChainItem* it, int nit, int nb, hipStream_t st) {
   if (nit > 0) hipLaunchKernelGGL(k_chain_fwd, dim3(nit, nb), dim3(256), 0, st, c, it);
 }
-template <bool P64>
-static void down_off_t(const Ctx& c, const ColItem* it, int nit, int nb, bool lesser, int cls_size,
-                       hipStream_t st) {
-  if (cls_size <= 16) hipLaunchKernelGGL((k_down_off_narrow<P64>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
-  else if (cls_size <= 32) hipLaunchKernelGGL((k_down_off<32, P64>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
-  else hipLaunchKernelGGL((k_down_off<64, P64>), dim3(nit, nb), dim3(256), 0, st, c, it, (int)lesser);
+template <bool P64, int L>
+static void down_off_t(const Ctx& c, const ColItem* it, int nit, int nb, int cls_size, hipStream_t st) {
+  if (cls_size <= 16) hipLaunchKernelGGL((k_down_off_narrow<P64, L>), dim3(nit, nb), dim3(256), 0, st, c, it);
+  else if (cls_size <= 32) hipLaunchKernelGGL((k_down_off<32, P64, L>), dim3(nit, nb), dim3(256), 0, st, c, it);
+  else hipLaunchKernelGGL((k_down_off<64, P64, L>), dim3(nit, nb), dim3(256), 0, st, c, it);
 }
 void launch_down_off(const Ctx& c, const ColItem* it, int nit, int nb, bool lesser, int cls_size,
                      hipStream_t st) {
   if (nit <= 0) return;
-  if (c.mixed) down_off_t<false>(c, it, nit, nb, lesser, cls_size, st);
-  else down_off_t<true>(c, it, nit, nb, lesser, cls_size, st);
+  if (c.mixed) {
+    if (lesser) down_off_t<false, 1>(c, it, nit, nb, cls_size, st);
+    else down_off_t<false, 0>(c, it, nit, nb, cls_size, st);
+  } else {
+    if (lesser) down_off_t<true, 1>(c, it, nit, nb, cls_size, st);
+    else down_off_t<true, 0>(c, it, nit, nb, cls_size, st);
+  }
 }
-template <bool P64>
-static void down_diag_t(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, int cls_size,
-                        hipStream_t st) {
-  if (cls_size <= 16) hipLaunchKernelGGL((k_down_diag_narrow<P64>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
-  else if (cls_size <= 32) hipLaunchKernelGGL((k_down_diag<32, P64>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
-  else hipLaunchKernelGGL((k_down_diag<64, P64>), dim3(ncl, nb), dim3(256), 0, st, c, cls, (int)lesser);
+template <bool P64, int L>
+static void down_diag_t(const Ctx& c, const int32_t* cls, int ncl, int nb, int cls_size, hipStream_t st) {
+  // FP64 blocks of one tile (every cluster of the group has s <= cls_size)
+  if (P64 && cls_size <= 16) hipLaunchKernelGGL((k_down_diag_single<16, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+  else if (P64 && cls_size <= 32) hipLaunchKernelGGL((k_down_diag_single<32, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+  else if (P64 && cls_size <= 64) hipLaunchKernelGGL((k_down_diag_single<64, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+  else if (cls_size <= 16) hipLaunchKernelGGL((k_down_diag_narrow<P64, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+  else if (cls_size <= 32) hipLaunchKernelGGL((k_down_diag<32, P64, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+  else hipLaunchKernelGGL((k_down_diag<64, P64, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
 }
 void launch_down_diag(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, int cls_size,
                       hipStream_t st) {
   if (ncl <= 0) return;
-  if (c.mixed) down_diag_t<false>(c, cls, ncl, nb, lesser, cls_size, st);
-  else down_diag_t<true>(c, cls, ncl, nb, lesser, cls_size, st);
+  if (c.mixed) {
+    if (lesser) down_diag_t<false, 1>(c, cls, ncl, nb, cls_size, st);
+    else down_diag_t<false, 0>(c, cls, ncl, nb, cls_size, st);
+  } else {
+    if (lesser) down_diag_t<true, 1>(c, cls, ncl, nb, cls_size, st);
+    else down_diag_t<true, 0>(c, cls, ncl, nb, cls_size, st);
+  }
 }
 void launch_chain_back(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st) {
   if (ncl > 0) hipLaunchKernelGGL(k_chain_back, dim3(ncl, nb), dim3(256), 0, st, c, cls);

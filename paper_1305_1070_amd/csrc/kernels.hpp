@@ -35,10 +35,15 @@ struct ClusterDesc {
   // extraction gather: slab offsets of the entries of X_{B,B} (b x b int32,
   // see Ctx::gaddr)
   int64_t o_gaddr;
+  // when B is a run of consecutive points of one ancestor (a contact chain's
+  // separator under its parent layer): X_{B,B} is a dense block of that
+  // ancestor's stored G^r rows, at o_bbd with row stride bbd_ld (-1: use the
+  // gather table)
+  int64_t o_bbd;
   // leading entries of B owned by the parent (B is sorted and the parent's
   // points precede its ancestors'): the rows of the contribution that land in
   // the parent's own rows
-  int32_t nself, pad2;
+  int32_t nself, bbd_ld;
 };
 
 // Per site in the caller's order: slab offsets of its diagonal entries in

@@ -185,7 +185,8 @@ __global__ void __launch_bounds__(NT) k_fold_small_wide(Ctx c, const int32_t* cl
 // Extraction of G^r (which = 0) or G^< (which = 1) for one small front; the
 // two run as separate launches on two streams.  X_{B,B} is gathered from the
 // stored rows of the clusters owning B (gather_bb).  Dynamic LDS holds
-// Psi (s x b), the gathered B x B block of the parent's front and X_{i,B}.
+// Psi (s x b), the gathered B x B block of the parent's front (later X_ii)
+// and X_{i,B}.
 // A leaf's blocks are read by nobody but the epilogue, so a leaf forms and
 // stores only the diagonal of X_ii.
 template <int NT>
@@ -209,7 +210,9 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
   const double2* Ainv = S + d.o_ainv;
   double2* Psl = sm;              // s x b, stride lb
   double2* XBB = sm + s * lb;     // b x b
-  double2* XIB = XBB + b * b;     // s x b, stride lb
+  const int ls = s | 1;           // odd row stride of X_ii (its transpose is read)
+  double2* XIB = XBB + max(b * b, s * ls);  // s x b, stride lb (X_{B,B} is later X_ii)
+  double2* XII = XBB;
   const double2* Psi = S + d.o_psi;
   for (int q = t; q < s * b; q += NT) {
     const int r = q / b, k = q - r * b;
@@ -275,7 +278,9 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
         X[(int64_t)r * f + r] = make_double2(a0.x + a1.x, a0.y + a1.y);
       }
     } else {
-      // two rows per thread share each X_{B,i} operand
+      // two rows per thread share each X_{B,i} operand; X_ii goes to the
+      // LDS of X_{B,B} (no longer read; sized for s x s too) and its
+      // symmetric (G) or anti-Hermitian (P) part to HBM once
       for (int q = t; q < sp2 * s; q += NT) {
         const int r0 = (q / s) << 1, j = q - (q / s) * s;
         const bool two = r0 + 1 < s;
@@ -290,17 +295,25 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
           cmac(a0, p0r[k], x);
           cmac(a1, p1r[k], x);
         }
-        X[(int64_t)r0 * f + j] = a0;
-        if (two) X[(int64_t)r1 * f + j] = a1;
+        XII[r0 * ls + j] = a0;
+        if (two) XII[r1 * ls + j] = a1;
       }
     }
     if (inner) {
-      // the cluster's rows [X_ii, X_{i,B}] are what its descendants gather
+      // the cluster's rows [X_ii, X_{i,B}] are what its descendants gather:
+      // X_ii as (X + X^T) / 2 for G^r, (X - X^+) / 2 for G^< (one value
+      // for both triangles, whichever a descendant reads)
+      __syncthreads();
+      for (int q = t; q < s * s; q += NT) {
+        const int r = q / s, j = q - r * s;
+        const double2 a = XII[r * ls + j], bt = XII[j * ls + r];
+        X[(int64_t)r * f + j] = lesser ? make_double2(0.5 * (a.x - bt.x), 0.5 * (a.y + bt.y))
+                                       : make_double2(0.5 * (a.x + bt.x), 0.5 * (a.y + bt.y));
+      }
       for (int q = t; q < s * b; q += NT) {
         const int r = q / b, j = q - r * b;
         X[(int64_t)r * f + s + j] = XIB[r * lb + j];
       }
-      symmetrize_block(X, s, f, lesser != 0);
     }
     __syncthreads();
   }

@@ -370,8 +370,9 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
         g.ncl++;
         if (q <= 2) {
           g.size = std::max(g.size, s_ + b);
-          // Psi and X_{i,B} rows padded to an odd stride (bank spread)
-          g.lds = std::max(g.lds, (size_t)(2 * s_ * (b | 1) + b * b) * 16);
+          // Psi and X_{i,B} rows padded to an odd stride (bank spread);
+          // X_{B,B}, later X_ii
+          g.lds = std::max(g.lds, (size_t)(2 * s_ * (b | 1) + std::max(b * b, s_ * (s_ | 1))) * 16);
         } else {
           g.size = std::max(g.size, s_);
           const int nt = (b + 63) / 64;
@@ -476,9 +477,23 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
   for (int k = 0; k < nc; ++k) {
     ClusterDesc& d = p->hdesc[k];
     d.o_gaddr = (int64_t)gaddr.size();
+    d.o_bbd = -1;
+    d.bbd_ld = 0;
     const int b = d.b;
     if (b == 0) continue;
     const int32_t* B = sy.bidx.data() + sy.bptr[k];
+    {
+      // B a run of consecutive points of one cluster a: X_{B,B} is the
+      // block of a's stored rows at (t0, t0), t0 = B[0] - a's first point
+      const int a = sy.owner[B[0]];
+      bool run = sy.owner[B[b - 1]] == a;
+      for (int u = 1; u < b && run; ++u) run = B[u] == B[0] + u;
+      if (run) {
+        const int64_t t0 = B[0] - sy.cl_off[a];
+        d.o_bbd = p->hdesc[a].o_fg + t0 * p->hdesc[a].f + t0;
+        d.bbd_ld = p->hdesc[a].f;
+      }
+    }
     gaddr.resize(gaddr.size() + (size_t)b * b);
     int32_t* ga = gaddr.data() + d.o_gaddr;
     for (int u = 0; u < b; ++u)
