@@ -100,9 +100,10 @@ __device__ __forceinline__ void fold_small_body(const Ctx& c, const int32_t* cls
           g.im[m][q] += u.y;
         }
   }
-  if (c.growth) {
-    for (int r = t; r < 2 * SF; r += NT) rsum[r / SF][r % SF] = 0.0;
-    __syncthreads();
+  // Row sums for the growth indicator: a row's JS owners are consecutive
+  // lanes (thread t holds columns t % JS + JS q), so a butterfly over them
+  // adds in a fixed order and the lane with jt = 0 stores the sum.
+  auto row_sums = [&](double(&dst)[SF], bool inverse) {
 #pragma unroll
     for (int m = 0; m < GJ::NR; ++m) {
       const int i = g.row(m);
@@ -110,11 +111,15 @@ __device__ __forceinline__ void fold_small_body(const Ctx& c, const int32_t* cls
 #pragma unroll
       for (int q = 0; q < GJ::NC; ++q) {
         const int j = g.col(q);
-        if (i < s && j >= s && j < f) acc += sqrt(g.re[m][q] * g.re[m][q] + g.im[m][q] * g.im[m][q]);
+        if (i < s && (inverse ? j < s : (j >= s && j < f)))
+          acc += sqrt(g.re[m][q] * g.re[m][q] + g.im[m][q] * g.im[m][q]);
       }
-      if (i < s && acc != 0.0) atomicAdd(&rsum[0][i], acc);
+#pragma unroll
+      for (int off = JS / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+      if (g.jt == 0 && i < s) dst[i] = acc;
     }
-  }
+  };
+  if (c.growth) row_sums(rsum[0], false);
   const bool ok = g.run(gsm, s);
   if (!ok && t == 0) raise_fault(c.status, -4, eb + e, cl);
   double2* Ainv = S + d.o_ainv;
@@ -137,15 +142,7 @@ __device__ __forceinline__ void fold_small_body(const Ctx& c, const int32_t* cls
     }
   if (c.growth && b > 0) {
     // ||A_ii^{-1}||_inf ||A_iB||_inf (row sums are permutation invariant)
-#pragma unroll
-    for (int m = 0; m < GJ::NR; ++m) {
-      const int i = g.row(m);
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < GJ::NC; ++q)
-        if (i < s && g.col(q) < s) acc += sqrt(g.re[m][q] * g.re[m][q] + g.im[m][q] * g.im[m][q]);
-      if (i < s && acc != 0.0) atomicAdd(&rsum[1][i], acc);
-    }
+    row_sums(rsum[1], true);
     __syncthreads();
     if (t < 64) {
       double ru = 0.0, rb = 0.0;
@@ -166,14 +163,15 @@ __device__ __forceinline__ void fold_small_body(const Ctx& c, const int32_t* cls
 }
 
 // Entry points: the 32- and 64-point classes fit 128 registers, so four
-// wavefronts per SIMD; the 48-point class (three columns per thread) does not.
+// wavefronts per SIMD; the 48-point class (three columns per thread) does not;
+// the 24-point class fits 102 (five), the most it takes without spills.
 template <int SF, int NT, int JS>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
 k_fold_small(Ctx c, const int32_t* cls) {
   fold_small_body<SF, NT, JS>(c, cls);
 }
 template <int SF, int NT, int JS>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
 k_fold_small_narrow(Ctx c, const int32_t* cls) {
   fold_small_body<SF, NT, JS>(c, cls);
 }

@@ -154,3 +154,44 @@ def test_adjoint_workload_512x64_fd_on_32_sites(lib):
         worst = max(worst, rel)
     _say("  worst FD mismatch (relative to max|g|) %.2e" % worst)
     assert worst < 1e-5
+
+
+def test_adjoint_workload_mixed_products_against_fp64(lib):
+    """The adjoint workload (512 x 64, 256 energies) with the fold's Schur
+    updates of fronts above 64 points in complex FP32 on the matrix cores
+    (NDG_MIXED; pivot inverses, Psi and the adjoint solves stay FP64): the
+    gradient against the FP64 one and against central differences (h = 1e-6
+    eV) of the FP64 density on 8 sampled sites, both within 1e-5 of max|g|."""
+    import torch
+    wl = workloads.adjoint_device()
+    dev = wl.device
+    rng = np.random.default_rng(52)
+    w = rng.uniform(0.5, 1.5, dev.n)
+    from inputs import devices
+    v_star = devices.smooth_random_potential(512, 64, 0.050, 8.0, seed=53)
+    _say("adjoint workload 512x64, mixed products")
+    plan, t, _ = _setup(lib, wl, leaf_max=16, max_batch=64)
+    v = wl.potential
+    n_star = _density(plan, wl, t, v_star)
+    n0 = _density(plan, wl, t, v)
+    nbar = 2 * w * (n0 - n_star)
+    g64 = _vjp(plan, wl, t, v, nbar)
+    V = torch.tensor(v, dtype=torch.float64, device="cuda:0")
+    nb = torch.tensor(nbar, dtype=torch.float64, device="cuda:0")
+    g32 = plan.density_vjp(t["E"], wl.eta, t["sig_r"], t["sig_l"], t["cE"], nb, V=V,
+                           prec=lib.NDG_MIXED).cpu().numpy()
+    scale = np.max(np.abs(g64))
+    d_mixed = np.max(np.abs(g32 - g64)) / scale
+    _say("  mixed vs FP64 gradient: %.2e of max|g|" % d_mixed)
+    h = 1e-6
+    loss = lambda n: np.sum(w * (n - n_star) ** 2)
+    worst = 0.0
+    for k in rng.choice(dev.n, 8, replace=False):
+        vp, vm = v.copy(), v.copy()
+        vp[k] += h
+        vm[k] -= h
+        fd = (loss(_density(plan, wl, t, vp)) - loss(_density(plan, wl, t, vm))) / (2 * h)
+        worst = max(worst, abs(fd - g32[k]) / scale)
+    _say("  mixed gradient vs central differences of FP64: worst %.2e of max|g|" % worst)
+    assert d_mixed < 1e-5
+    assert worst < 1e-5
