@@ -169,12 +169,13 @@ def bench_batch(ndg, workloads, torch, cuda, n_devices=64, per_plan=8, chain=Tru
     batch.solve(ins)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    launches = batch.launches()
     n_pts = sum(len(w.energies) for w in wls)
     del batch, plans, ins
     torch.cuda.empty_cache()
     return {"workload": "%d 2-D FD devices, widths 32..128, lengths 256..2048, 128 energies each"
                         % n_devices,
-            "device_energy_points_per_s": n_pts / dt, "s_per_pass": dt,
+            "device_energy_points_per_s": n_pts / dt, "s_per_pass": dt, "graph_launches_per_pass": launches,
             "algorithmic_tflop_per_s": gflop / dt / 1e3, "energies_per_plan_batch": per_plan,
             "tree": "open slab chain" if chain else "nested dissection",
             "shape_per_width": {str(k): v for k, v in leaf.items()}}

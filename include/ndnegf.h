@@ -394,9 +394,12 @@ ndg_status ndg_poisson_newton_step(ndg_plan* plan, int32_t nE, const double* E, 
  * batch of energies (each plan's max_batch) of every plan into one HIP graph
  * -- one branch per device, so the devices' level-by-level kernels run
  * concurrently -- whose first energies live in device memory and are
- * advanced by the graph's last node; the graph is then launched on `stream`
- * as many times as the longest energy range needs (each plan's workspace
- * stays that of one batch).  Later calls with identical arguments replay the
+ * advanced by the graph's last node.  A second graph holds the resets of
+ * those counters and then one copy of the batch graph per batch the longest
+ * energy range needs, in sequence (each plan's workspace stays that of one
+ * batch), so one call is one graph launch on `stream` (if that graph cannot
+ * be built, the batch graph is launched once per batch instead; see
+ * ndg_batch_launches).  Later calls with identical arguments relaunch the
  * instantiated graph.  Each args[i] holds the arguments ndg_solve
  * takes for plans[i] (device pointers; the growth pointer may be NULL).  The
  * plans must be distinct, on one device, and have profiling switched off.
@@ -426,6 +429,10 @@ ndg_status ndg_batch_create(int32_t nplans, ndg_plan* const* plans, ndg_batch** 
 ndg_status ndg_batch_destroy(ndg_batch* batch);
 ndg_status ndg_batch_solve(ndg_batch* batch, const ndg_solve_args* args, ndg_precision prec,
                            void* stream);
+/* Graph launches the last ndg_batch_solve on `batch` issued: 1 when the whole
+ * energy range ran as one graph, else the number of batches (0 before the
+ * first solve or for NULL). */
+int32_t ndg_batch_launches(const ndg_batch* batch);
 
 /* Status word of the last solves on this plan (call after synchronising the
  * stream).  *code = NDG_OK, NDG_ESINGULAR (a pivot of magnitude 0 in a

@@ -23,7 +23,7 @@ __all__ = ["analyze", "Symbolic", "Plan", "load", "NdgError", "NDG_FP64", "NDG_M
            "ndg_plan_export_block", "ndg_plan_set_profiling", "ndg_plan_profile", "ndg_symbolic_costs",
            "ndg_density", "ndg_plan_enable_adjoint", "ndg_density_vjp", "ndg_density_vjp_noalloc",
            "NDDensity",
-           "ndg_batch_create", "ndg_batch_destroy", "ndg_batch_solve", "Batch",
+           "ndg_batch_create", "ndg_batch_destroy", "ndg_batch_solve", "ndg_batch_launches", "Batch",
            "ndg_plan_enable_scattering", "ndg_solve_scattering", "ndg_scba", "ndg_poisson_newton_step",
            "ndg_solve_transport",
            "ndg_status_string", "ndg_last_error"]
@@ -241,6 +241,10 @@ def ndg_batch_create(plans):
 
 def ndg_batch_destroy(batch):
     _lib.check(load().ndg_batch_destroy(batch))
+
+
+def ndg_batch_launches(batch) -> int:
+    return int(load().ndg_batch_launches(batch))
 
 
 def ndg_batch_solve(batch, args, prec, stream_ptr):
@@ -609,6 +613,10 @@ class Batch:
         ndg_batch_solve(self.handle, args, prec, C.c_void_p(self._stream.cuda_stream))
         cur.wait_stream(self._stream)
         return list(self._outs)
+
+    def launches(self) -> int:
+        """Graph launches of the last solve (1: the whole energy range as one graph)."""
+        return ndg_batch_launches(self.handle)
 
     def __del__(self):
         lib = getattr(_lib, "_lib", None) if _lib is not None else None

@@ -105,6 +105,7 @@ SIGNATURES = {
     "ndg_batch_create": (C.c_int, [C.c_int32, C.POINTER(P), C.POINTER(P)]),
     "ndg_batch_destroy": (C.c_int, [P]),
     "ndg_batch_solve": (C.c_int, [P, C.POINTER(SolveArgs), C.c_int, P]),
+    "ndg_batch_launches": (C.c_int32, [P]),
     "ndg_status_string": (C.c_char_p, [C.c_int32]),
     "ndg_last_error": (C.c_char_p, []),
 }

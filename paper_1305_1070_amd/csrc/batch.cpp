@@ -29,8 +29,11 @@ struct ndg_batch {
   int32_t* d_e0 = nullptr;   // per plan: first energy of the current replay
   int32_t* d_inc = nullptr;  // per plan: its batch size
   int replays = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  int launches = 0;          // graph launches of the last solve
+  hipGraph_t graph = nullptr;      // one batch of energies of every plan
+  hipGraph_t whole = nullptr;      // the counter resets, then `replays` copies of graph
+  hipGraphExec_t exec = nullptr;   // of whole, or of graph when whole could not be built
+  bool single = false;             // exec runs the whole energy range
   // the argument set the cached graph was captured with
   std::vector<ndg_solve_args> key;
   std::vector<std::vector<const ndg_c128*>> key_sig;
@@ -41,9 +44,12 @@ namespace {
 
 void release_graph(ndg_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->whole) (void)hipGraphDestroy(b->whole);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
+  b->whole = nullptr;
   b->graph = nullptr;
+  b->single = false;
   b->key.clear();
   b->key_sig.clear();
   b->key_prec = -1;
@@ -119,6 +125,8 @@ ndg_status ndg_batch_create(int32_t nplans, ndg_plan* const* plans, ndg_batch** 
   return NDG_OK;
 }
 
+int32_t ndg_batch_launches(const ndg_batch* b) { return b ? b->launches : 0; }
+
 ndg_status ndg_batch_destroy(ndg_batch* b) {
   if (!b) return NDG_OK;
   // replays still in flight read the graph and the offsets freed below
@@ -182,13 +190,53 @@ ndg_status ndg_batch_solve(ndg_batch* b, const ndg_solve_args* args, ndg_precisi
       return (ndg_status)rc;
     }
     if (ec != hipSuccess || !g) { ndg::set_error("ndg_batch_solve: hipStreamEndCapture failed"); return NDG_EHIP; }
-    hipGraphExec_t ex = nullptr;
-    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
-      (void)hipGraphDestroy(g);
-      ndg::set_error("ndg_batch_solve: hipGraphInstantiate failed");
-      return NDG_EHIP;
-    }
     b->graph = g;
+    // The whole energy range as one graph: the resets of the first-energy
+    // counters and growth outputs (captured kernels), then one child copy
+    // of the batch graph per replay, in sequence.  If it cannot be built,
+    // the batch graph is launched once per replay instead.
+    int replays = 0;
+    for (int i = 0; i < np; ++i) {
+      const int mb = ndg::plan_max_batch(b->plans[i]);
+      replays = std::max(replays, (args[i].nE + mb - 1) / mb);
+    }
+    hipGraph_t w = nullptr;
+    bool whole_ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (whole_ok) {
+      ndg::launch_fill_zero_i32(b->d_e0, np, st);
+      for (int i = 0; i < np; ++i)
+        if (args[i].growth) ndg::launch_fill_zero(args[i].growth, args[i].nE, st);
+      whole_ok = hipStreamEndCapture(st, &w) == hipSuccess && w;
+    }
+    if (whole_ok) {
+      hipGraphNode_t prev = nullptr, node = nullptr;
+      // every reset node is a dependency of the first copy
+      std::vector<hipGraphNode_t> all;
+      size_t nall = 0;
+      whole_ok = hipGraphGetNodes(w, nullptr, &nall) == hipSuccess && nall > 0;
+      if (whole_ok) {
+        all.resize(nall);
+        whole_ok = hipGraphGetNodes(w, all.data(), &nall) == hipSuccess;
+      }
+      for (int r = 0; r < replays && whole_ok; ++r) {
+        whole_ok = hipGraphAddChildGraphNode(&node, w, r ? &prev : all.data(), r ? 1 : all.size(), g) == hipSuccess;
+        prev = node;
+      }
+    }
+    hipGraphExec_t ex = nullptr;
+    if (whole_ok && hipGraphInstantiate(&ex, w, nullptr, nullptr, 0) == hipSuccess) {
+      b->whole = w;
+      b->single = true;
+    } else {
+      (void)hipGetLastError();
+      if (w) (void)hipGraphDestroy(w);
+      ex = nullptr;
+      if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        release_graph(b);
+        ndg::set_error("ndg_batch_solve: hipGraphInstantiate failed");
+        return NDG_EHIP;
+      }
+    }
     b->exec = ex;
     b->key.assign(args, args + np);
     b->key_sig.assign(np, {});
@@ -204,21 +252,30 @@ ndg_status ndg_batch_solve(ndg_batch* b, const ndg_solve_args* args, ndg_precisi
     }
     b->key_prec = (int)prec;
   }
-  // replays needed for the longest energy range; the counters and the
-  // growth outputs are cleared by kernels outside the graph
+  // replays needed for the longest energy range
   int replays = 0;
   for (int i = 0; i < np; ++i) {
     const int mb = ndg::plan_max_batch(b->plans[i]);
     replays = std::max(replays, (args[i].nE + mb - 1) / mb);
   }
-  ndg::launch_fill_zero_i32(b->d_e0, np, st);
-  for (int i = 0; i < np; ++i)
-    if (args[i].growth) ndg::launch_fill_zero(args[i].growth, args[i].nE, st);
-  for (int r = 0; r < replays; ++r)
+  if (b->single) {
     if (hipGraphLaunch(b->exec, st) != hipSuccess) {
       ndg::set_error("ndg_batch_solve: hipGraphLaunch failed");
       return NDG_EHIP;
     }
+    b->launches = 1;
+  } else {
+    // the counters and the growth outputs cleared by kernels outside the graph
+    ndg::launch_fill_zero_i32(b->d_e0, np, st);
+    for (int i = 0; i < np; ++i)
+      if (args[i].growth) ndg::launch_fill_zero(args[i].growth, args[i].nE, st);
+    for (int r = 0; r < replays; ++r)
+      if (hipGraphLaunch(b->exec, st) != hipSuccess) {
+        ndg::set_error("ndg_batch_solve: hipGraphLaunch failed");
+        return NDG_EHIP;
+      }
+    b->launches = replays;
+  }
   b->replays = replays;
   return NDG_OK;
 }

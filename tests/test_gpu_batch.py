@@ -103,6 +103,8 @@ def test_batch_of_uneven_devices_replays_match_eager_and_oracle(lib):
         for k, (o, ref) in enumerate(zip(outs, eager)):
             for a, b in zip(o, ref):
                 assert np.array_equal(a.cpu().numpy(), b), "replay %d device %d" % (rep, k)
-        _say("  replay %d identical to eager (%.3f)" % (rep, float(x)))
+        _say("  replay %d identical to eager (%.3f), %d graph launch(es)" % (rep, float(x), batch.launches()))
+        # both batches of energies of every device in one graph launch
+        assert batch.launches() == 1
     for p in plans:
         assert p.status()[0] == 0
