@@ -78,7 +78,8 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
       if (ri < 0) continue;
       const int rj = inv[j];
       if (rj < 0) continue;
-      const double2 u = S[kid_upd[kq] + (int64_t)ri * kid_b[kq] + rj];
+      // the contribution's upper triangle holds both (symmetric)
+      const double2 u = S[kid_upd[kq] + (int64_t)min(ri, rj) * kid_b[kq] + max(ri, rj)];
       re += u.x;
       im += u.y;
     }
@@ -191,6 +192,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 
 // U = F_BB + Psi^T F_{i,B} (b x b), one TM x 64 tile per block.  Clusters
 // with s <= 16 (K = s: the tile is all gather and store) take 32-row tiles:
 // half the accumulators, more blocks in flight, less padding on ragged edges.
+// U is complex symmetric (A is), so only its upper triangle is formed and
+// stored (tiles wholly below the diagonal are not launched) and every
+// reader takes entry (u, v) from (min(u, v), max(u, v)): half the bytes
+// written, and one value for both triangles.
 template <int TM, bool P64>
 __device__ __forceinline__ void update_body(const Ctx& c, const UpdItem* items) {
   using GM = Gemm<P64>;
@@ -262,7 +267,8 @@ __device__ __forceinline__ void update_body(const Ctx& c, const UpdItem* items) 
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           if (ri[m][r] >= 0 && cj[n] >= 0) {
-            const double2 u = Uq[(int64_t)ri[m][r] * bq + cj[n]];
+            const int lo = min(ri[m][r], cj[n]), hi = max(ri[m][r], cj[n]);
+            const double2 u = Uq[(int64_t)lo * bq + hi];
             if constexpr (P64) {
               acc.re[m][n][r] += u.x;
               acc.im[m][n][r] += u.y;
@@ -280,7 +286,7 @@ __device__ __forceinline__ void update_body(const Ctx& c, const UpdItem* items) 
       for (int r = 0; r < 4; ++r) {
         const int i = wr + m * 16 + (P64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
         const int j = wc + n * 16 + (lane & 15);
-        if (i < ni && j < nj)
+        if (i < ni && j < nj && i0 + i <= j0 + j)
           U[(int64_t)(i0 + i) * b + j0 + j] =
               make_double2(cr[m][n][r] + (double)acc.re[m][n][r], ci[m][n][r] + (double)acc.im[m][n][r]);
       }
@@ -372,12 +378,43 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   }
 }
 
+// T_i = Zd_i Sigma^<_c (s x sc) for every (chain cluster, contact): it needs
+// only the forward solve's Zd_i and the source, so all chain clusters form
+// it in one launch after the fold instead of inside the sequential back
+// substitution.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_chain_t(Ctx c, const ChainItem* items) {
+  __shared__ GemmSmem sm;
+  const ChainItem it = items[blockIdx.x];
+  const int e = blockIdx.y;
+  const int eb = ebase(c);
+  if (eb + e >= c.nE) return;
+  const ClusterDesc d = c.cl[it.cl];
+  const int cc = it.c, sc = sel2(c.nc, cc), s = d.s;
+  double2* S = slab(c, e);
+  const double2* Zf = S + sel2(d.o_zf, cc);
+  double2* T = S + sel2(d.o_t, cc);
+  const double2* sl = sel2(c.sig_l, cc) + (int64_t)(eb + e - c.sl_e0) * sc * sc;
+  for (int r0 = 0; r0 < s; r0 += 64)
+    for (int j0 = 0; j0 < sc; j0 += 64) {
+      const int ni = min(64, s - r0), nj = min(64, sc - j0);
+      ZTile acc;
+      ztile_zero(acc);
+      zgemm_acc<false, false>(
+          sc, [&](int i, int k) { return i < ni ? Zf[(int64_t)(r0 + i) * sc + k] : cz(); },
+          [&](int k, int j) { return j < nj ? sl[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
+      ztile_store(acc, [&](int i, int j, double re, double im) {
+        if (i < ni && j < nj) T[(int64_t)(r0 + i) * sc + j0 + j] = make_double2(re, im);
+      });
+    }
+}
+
 // Back substitution along the chain: X = rows of the contact's column of G^r,
 // X_B gathered from the parent's front, X_i = Zd_i + Psi_i X_B.  Then the
 // source of the G^< extraction on the cluster's rows:
-// P_init = sum_c Zd_i Sigma^<_c (X_front)^+ (s x f), written into rows [0, s)
-// of the G^< front.  This is D^{-1} L^{-1} Sigma^< (G^r)^+ restricted to the
-// front, evaluated as (L^{-1} Sigma^<)(G^r)^+ so only s x sc panels are folded.
+// P_init = sum_c T_i (X_front)^+ (s x f) with T_i = Zd_i Sigma^<_c from
+// k_chain_t, written into rows [0, s) of the G^< front.  This is
+// D^{-1} L^{-1} Sigma^< (G^r)^+ restricted to the front, evaluated as
+// (L^{-1} Sigma^<)(G^r)^+ so only s x sc panels are folded.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_chain_back(Ctx c, const int32_t* cls) {
   __shared__ GemmSmem sm;
   const int cl = cls[blockIdx.x];
@@ -423,22 +460,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
           }
         });
       }
-    __syncthreads();
-    {
-      const double2* sl = sel2(c.sig_l, cc) + (int64_t)(eb + e - c.sl_e0) * sc * sc;
-      for (int r0 = 0; r0 < s; r0 += 64)
-        for (int j0 = 0; j0 < sc; j0 += 64) {
-          const int ni = min(64, s - r0), nj = min(64, sc - j0);
-          ZTile acc;
-          ztile_zero(acc);
-          zgemm_acc<false, false>(
-              sc, [&](int i, int k) { return i < ni ? Zf[(int64_t)(r0 + i) * sc + k] : cz(); },
-              [&](int k, int j) { return j < nj ? sl[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
-          ztile_store(acc, [&](int i, int j, double re, double im) {
-            if (i < ni && j < nj) T[(int64_t)(r0 + i) * sc + j0 + j] = make_double2(re, im);
-          });
-        }
-    }
     __syncthreads();
     for (int r0 = 0; r0 < s; r0 += 64)
       for (int j0 = 0; j0 < f; j0 += 64) {
@@ -786,6 +807,9 @@ void launch_down_diag(const Ctx& c, const int32_t* cls, int ncl, int nb, bool le
     if (lesser) down_diag_t<true, 1>(c, cls, ncl, nb, cls_size, st);
     else down_diag_t<true, 0>(c, cls, ncl, nb, cls_size, st);
   }
+}
+void launch_chain_t(const Ctx& c, const ChainItem* it, int nit, int nb, hipStream_t st) {
+  if (nit > 0) hipLaunchKernelGGL(k_chain_t, dim3(nit, nb), dim3(256), 0, st, c, it);
 }
 void launch_chain_back(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st) {
   if (ncl > 0) hipLaunchKernelGGL(k_chain_back, dim3(ncl, nb), dim3(256), 0, st, c, cls);

@@ -209,6 +209,9 @@ void launch_down_off(const Ctx& c, const ColItem* it, int nit, int nb, bool less
                      hipStream_t st);
 void launch_down_diag(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, int cls_size,
                       hipStream_t st);
+// T = Zd Sigma^< for all (chain cluster, contact) items at once (after the
+// fold, before the back substitution, with the Ctx the latter will use)
+void launch_chain_t(const Ctx& c, const ChainItem* it, int nit, int nb, hipStream_t st);
 void launch_chain_back(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st);
 // small fronts: f <= 32 (one wave per front) or f <= 64 (four waves)
 void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int front_size, hipStream_t st);

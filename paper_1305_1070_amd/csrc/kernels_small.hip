@@ -95,7 +95,8 @@ __device__ __forceinline__ void fold_small_body(const Ctx& c, const int32_t* cls
 #pragma unroll
       for (int q = 0; q < GJ::NC; ++q)
         if (ri[m] >= 0 && cj[q] >= 0) {
-          const double2 u = U[ri[m] * dc.b + cj[q]];
+          // the contribution's upper triangle holds both (symmetric)
+          const double2 u = U[min(ri[m], cj[q]) * dc.b + max(ri[m], cj[q])];
           g.re[m][q] += u.x;
           g.im[m][q] += u.y;
         }
@@ -136,7 +137,8 @@ __device__ __forceinline__ void fold_small_body(const Ctx& c, const int32_t* cls
       if (i < s) {
         if (j < s) Ainv[gsm.pinv[i] * s + gsm.piv[j]] = make_double2(vr, vi);
         else if (j < f) Psi[gsm.pinv[i] * b + (j - s)] = make_double2(-vr, -vi);
-      } else if (i < f && j >= s && j < f) {
+      } else if (i < f && j >= i && j < f) {
+        // the Schur contribution is complex symmetric: its upper triangle
         Upd[(i - s) * b + (j - s)] = make_double2(vr, vi);
       }
     }

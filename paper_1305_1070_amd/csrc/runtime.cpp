@@ -126,13 +126,13 @@ namespace {
 enum KernelId {
   K_ASSEMBLE, K_FACTOR, K_PSI, K_UPDATE, K_CHAIN_FWD, K_DOWN_OFF_G, K_DOWN_DIAG_G, K_CHAIN_BACK,
   K_DOWN_OFF_P, K_DOWN_DIAG_P, K_EPILOGUE, K_FOLD_SMALL, K_EXTRACT_SMALL, K_RHS_FWD, K_RHS_BACK,
-  K_VJP, K_EXTRACT_SMALL_P, K_ANC_G, K_ANC_N, K_ANC_P0, kKernels
+  K_VJP, K_EXTRACT_SMALL_P, K_ANC_G, K_ANC_N, K_ANC_P0, K_CHAIN_T, kKernels
 };
 const char* const kKernelNames[kKernels] = {
     "k_assemble", "k_factor", "k_psi", "k_update", "k_chain_fwd", "k_down_off(G)",
     "k_down_diag(G)", "k_chain_back", "k_down_off(P)", "k_down_diag(P)", "k_epilogue",
     "k_fold_small", "k_extract_small(G)", "k_rhs_fwd", "k_rhs_back", "k_vjp",
-    "k_extract_small(P)", "k_anc_g", "k_anc_n", "k_anc_p0"};
+    "k_extract_small(P)", "k_anc_g", "k_anc_n", "k_anc_p0", "k_chain_t"};
 
 int64_t align8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
@@ -297,8 +297,9 @@ void phonon_free_costs(const Symbolic& sy, const std::vector<ClusterDesc>& hd, c
       if (!((hd[k].chain_mask >> c) & 1)) continue;
       const double sc = nc_contact[c];
       addc(K_CHAIN_FWD, h, 0, 8.0 * (s * b * sc + s * s * sc), 16.0 * (s * b + s * s + 2 * f * sc));
-      addc(K_CHAIN_BACK, h, 0, 8.0 * (s * b * sc + s * sc * sc + s * sc * f),
-           16.0 * (s * b + 3 * f * sc + s * sc + sc * sc + s * f));
+      addc(K_CHAIN_BACK, h, 0, 8.0 * (s * b * sc + s * sc * f), 16.0 * (s * b + 3 * f * sc + s * sc + s * f));
+      // T = Zd Sigma^<: one launch for all chain clusters, after the fold
+      addc(K_CHAIN_T, 0, 0, 8.0 * s * sc * sc, 16.0 * (2 * s * sc + sc * sc));
     }
   }
   addc(K_EPILOGUE, 0, 0, 0.0, 16.0 * 5.0 * (double)sy.n);
@@ -377,10 +378,13 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
           g.size = std::max(g.size, s_);
           const int nt = (b + 63) / 64;
           for (int tc = 0; tc < nt; ++tc) cols.push_back(ColItem{k, tc});
-          // class 3 (s <= 16) updates in 32-row tiles
-          const int ntr = q == 3 ? (b + 31) / 32 : nt;
+          // class 3 (s <= 16) updates in 32-row tiles; the contribution is
+          // symmetric, so tiles wholly below its diagonal are skipped
+          const int tmr = q == 3 ? 32 : 64;
+          const int ntr = (b + tmr - 1) / tmr;
           for (int tr = 0; tr < ntr; ++tr)
-            for (int tc = 0; tc < nt; ++tc) upds.push_back(UpdItem{k, tr, tc, 0});
+            for (int tc = 0; tc < nt; ++tc)
+              if (tr * tmr <= tc * 64 + 63) upds.push_back(UpdItem{k, tr, tc, 0});
         }
       }
       g.ncol = (int)cols.size() - g.col0;
@@ -1191,6 +1195,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
       // G^(0) over all ancestors (top-down), the N fold and P_init
       // (bottom-up), then the G^< extraction
       for (int h = H; h >= 1; --h) extract(h, false, st);
+      timed(K_CHAIN_T, 0, 0, nb, [&] { launch_chain_t(c, p->d_chainitems, p->chain_ptr[H], nb, st); });
       for (int h = H; h >= 1; --h) {
         const int k0 = p->chaincl_ptr[h - 1], nck = p->chaincl_ptr[h] - k0;
         if (nck) timed(K_CHAIN_BACK, h, 0, nb, [&] { launch_chain_back(c, p->d_chaincls + k0, nck, nb, st); });
@@ -1234,6 +1239,8 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
     // time is its own (no overlap with the other extraction's kernels)
     const bool fork = cap == hipStreamCaptureStatusNone && !(p->profiling && p->profiling_mode == 2);
     hipStream_t sp = fork ? p->side : st;
+    // the back substitution's T panels of all chain clusters, in parallel
+    timed(K_CHAIN_T, 0, 0, nb, [&] { launch_chain_t(c, p->d_chainitems, p->chain_ptr[H], nb, st); });
     if (fork) {
       (void)hipEventRecord(p->ev_fork, st);
       (void)hipStreamWaitEvent(sp, p->ev_fork, 0);
@@ -1291,6 +1298,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         Ctx c2 = c;
         for (int q = 0; q < 2; ++q) c2.sig_l[q] = p->d_src[q];
         c2.sl_e0 = e0;
+        launch_chain_t(c2, p->d_chainitems, p->chain_ptr[H], nb, st);
         for (int h = H; h >= 1; --h) {
           const int k0 = p->chaincl_ptr[h - 1], nck = p->chaincl_ptr[h] - k0;
           if (nck) launch_chain_back(c2, p->d_chaincls + k0, nck, nb, st);

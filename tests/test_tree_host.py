@@ -312,7 +312,8 @@ def _recount(dev, arr):
             if k in c:
                 sc = len(cs)
                 add("k_chain_fwd", h, 0, 8 * (sk * bk * sc + sk * sk * sc))
-                add("k_chain_back", h, 0, 8 * (sk * bk * sc + sk * sc * sc + sk * sc * f))
+                add("k_chain_back", h, 0, 8 * (sk * bk * sc + sk * sc * f))
+                add("k_chain_t", 0, 0, 8 * sk * sc * sc)
     return out
 
 
