@@ -251,8 +251,9 @@ int cost_index(int kid, int h, int q, int H) { return (kid * (H + 1) + h) * kCos
 // (kernel, height, size class), in Section 4.1's convention: a product of
 // i x j by j x k counts ijk complex multiply-adds, an i x i inversion i^3,
 // 8 real flops each; bytes count each input block read once and each output
-// block written once (16 per complex entry).  The flops of all groups sum to
-// 8 times count_ops' total.
+// block written once (16 per complex entry), a symmetric block (a Schur
+// contribution, X_BB) by its distinct entries b (b + 1) / 2.  The flops of
+// all groups sum to 8 times count_ops' total.
 void phonon_free_costs(const Symbolic& sy, const std::vector<ClusterDesc>& hd, const int* nc_contact,
                        int ncontacts, std::vector<double>& fl, std::vector<double>& by) {
   const int nc = sy.nclusters, H = sy.max_height;
@@ -266,12 +267,13 @@ void phonon_free_costs(const Symbolic& sy, const std::vector<ClusterDesc>& hd, c
     const int h = sy.height[k], q = size_class(sy, k);
     const double s = sy.s(k), b = sy.b(k), f = s + b;
     const bool leaf = sy.children[k].empty();
+    // the children's contributions, symmetric: their distinct entries
     double kidb = 0;
-    for (int32_t ch : sy.children[k]) kidb += (double)sy.b(ch) * sy.b(ch);
+    for (int32_t ch : sy.children[k]) kidb += (double)sy.b(ch) * (sy.b(ch) + 1) / 2;
     if (s + b <= kSmallFront) {
       // pivot inverse, Psi and the Schur contribution of the whole front
       addc(K_FOLD_SMALL, h, q, 8.0 * (s * s * s + s * s * b + s * b * b),
-           16.0 * (kidb + s * s + s * b + b * b));
+           16.0 * (kidb + s * s + s * b + b * (b + 1) / 2));
       // X_BB counted by its distinct entries (symmetric for G^r,
       // anti-Hermitian for G^<): b (b + 1) / 2.  A leaf off the contact
       // chains forms the diagonal of X_ii only.
@@ -287,7 +289,8 @@ void phonon_free_costs(const Symbolic& sy, const std::vector<ClusterDesc>& hd, c
       addc(K_ASSEMBLE, h, q, 0.0, 16.0 * (s * f + kidrows));
       addc(K_FACTOR, h, q, 8.0 * s * s * s, 16.0 * 2 * s * s);
       addc(K_PSI, h, q, 8.0 * s * s * b, 16.0 * (s * s + 2 * s * b));
-      addc(K_UPDATE, h, q, 8.0 * s * b * b, 16.0 * (2 * s * b + 2 * b * b));
+      // F_BB gathered and U written by their distinct entries
+      addc(K_UPDATE, h, q, 8.0 * s * b * b, 16.0 * (2 * s * b + b * (b + 1)));
       for (int kid : {K_DOWN_OFF_G, K_DOWN_OFF_P})
         addc(kid, h, q, 8.0 * s * b * b, 16.0 * (s * b + b * (b + 1) / 2 + s * b));
       for (int kid : {K_DOWN_DIAG_G, K_DOWN_DIAG_P}) addc(kid, h, q, 8.0 * s * s * b, 16.0 * (2 * s * b + 2 * s * s));
