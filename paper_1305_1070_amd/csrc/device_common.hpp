@@ -166,6 +166,98 @@ __device__ void zgemm_acc_t(int K, FA fa, FB fb, ZTile& acc, GemmSmemR<R>& sm) {
   }
 }
 
+// acc += A (TM x K) * B (K x 64) with B gathered through an index table:
+// fidx(k, j) loads the table entry of B(k, j), fval(entry, j) the value it
+// points to (0 for columns outside the tile).  The table entries run one chunk ahead of the values: while the
+// matrix cores work on chunk k0, the values of chunk k0 + KC (whose entries
+// arrived during the previous chunk) and the entries of chunk k0 + 2 KC are
+// in flight, so each chunk waits for one memory round trip instead of two
+// dependent ones.  A is read as in zgemm_acc_t (A_IFAST), B with j fastest.
+template <int TM, bool A_IFAST, int R, class FA, class FI, class FV>
+__device__ void zgemm_acc_gather_t(int K, FA fa, FI fidx, FV fval, ZTile& acc, GemmSmemR<R>& sm) {
+  static_assert(R >= TM, "staging rows");
+  using T = TileShape<TM>;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
+  auto a_idx = [&](int q, int& i, int& kk) {
+    const int idx = t + 256 * q;
+    if (A_IFAST) { i = idx % TM; kk = idx / TM; }
+    else { kk = idx & (KC - 1); i = idx / KC; }
+  };
+  const int bj = t & 63, bk = t >> 6;  // B element q of this thread: (bk + 4q, bj)
+  double2 pa[TM / 16], pb[4];
+  int32_t pm[4];
+  auto load_a = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < TM / 16; ++q) {
+      int i, kk;
+      a_idx(q, i, kk);
+      pa[q] = (k0 + kk < K) ? fa(i, k0 + kk) : cz();
+    }
+  };
+  auto load_idx = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pm[q] = (k0 + bk + 4 * q < K) ? fidx(k0 + bk + 4 * q, bj) : 0;
+  };
+  auto load_val = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pb[q] = (k0 + bk + 4 * q < K) ? fval(pm[q], bj) : cz();
+  };
+  if (K > 0) {
+    load_a(0);
+    load_idx(0);
+    load_val(0);
+    load_idx(KC);
+  }
+  for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+    for (int q = 0; q < TM / 16; ++q) {
+      int i, kk;
+      a_idx(q, i, kk);
+      sm.ar[i][kk] = pa[q].x;
+      sm.ai[i][kk] = pa[q].y;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sm.br[bk + 4 * q][bj] = pb[q].x;
+      sm.bi[bk + 4 * q][bj] = pb[q].y;
+    }
+    __syncthreads();
+    if (k0 + KC < K) {
+      load_a(k0 + KC);
+      load_val(k0 + KC);
+      load_idx(k0 + 2 * KC);
+    }
+#pragma unroll
+    for (int k4 = 0; k4 < KC; k4 += 4) {
+      const int kq = k4 + (lane >> 4);
+      double are[T::MB], aim[T::MB], bre[T::NB], bim[T::NB];
+#pragma unroll
+      for (int m = 0; m < T::MB; ++m) {
+        const int i = wr + m * 16 + (lane & 15);
+        are[m] = sm.ar[i][kq];
+        aim[m] = sm.ai[i][kq];
+      }
+#pragma unroll
+      for (int n = 0; n < T::NB; ++n) {
+        const int j = wc + n * 16 + (lane & 15);
+        bre[n] = sm.br[kq][j];
+        bim[n] = sm.bi[kq][j];
+      }
+#pragma unroll
+      for (int m = 0; m < T::MB; ++m)
+#pragma unroll
+        for (int n = 0; n < T::NB; ++n) {
+          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bre[n], acc.re[m][n], 0, 0, 0);
+          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim[m], bim[n], acc.re[m][n], 0, 0, 0);
+          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bim[n], acc.im[m][n], 0, 0, 0);
+          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[m], bre[n], acc.im[m][n], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+}
+
 template <bool A_IFAST, bool B_KFAST, class FA, class FB>
 __device__ void zgemm_acc(int K, FA fa, FB fb, ZTile& acc, GemmSmem& sm) {
   zgemm_acc_t<64, A_IFAST, B_KFAST, false>(K, fa, fb, acc, sm);
@@ -591,11 +683,18 @@ __device__ inline double2* slab(const Ctx& c, int e) { return c.ws + (int64_t)e 
 // Entry (u, v) of X_{B,B} for a cluster with boundary B (X = G^r, or G^<
 // when lesser): read from the stored rows of the lower owning cluster, using
 // G^r_{yx} = G^r_{xy} and G^<_{yx} = -conj(G^<_{xy}) for the other order.
-__device__ inline double2 gather_bb(const Ctx& c, const double2* S, const ClusterDesc& d, int u,
-                                    int v, bool lesser) {
-  const int32_t m = c.gaddr[d.o_gaddr + (int64_t)u * d.b + v];
+// The table entry (offset in the energy's slab, sign bit set when the entry
+// is read in the other order) and the value it points to.
+__device__ inline int32_t gather_bb_entry(const Ctx& c, const ClusterDesc& d, int u, int v) {
+  return c.gaddr[d.o_gaddr + (int64_t)u * d.b + v];
+}
+__device__ inline double2 gather_bb_value(const Ctx& c, const double2* S, int32_t m, bool lesser) {
   const double2 x = S[(int64_t)(m & 0x7FFFFFFF) + (lesser ? c.pdelta : 0)];
   return (m < 0 && lesser) ? make_double2(-x.x, x.y) : x;
+}
+__device__ inline double2 gather_bb(const Ctx& c, const double2* S, const ClusterDesc& d, int u,
+                                    int v, bool lesser) {
+  return gather_bb_value(c, S, gather_bb_entry(c, d, u, v), lesser);
 }
 
 // Entry (u, v) of X_{B,B} where B is a run of one ancestor's points
@@ -636,5 +735,26 @@ __device__ inline void symmetrize_block(double2* X, int s, int f, bool lesser) {
 
 // First energy of the batch this launch processes.
 __device__ inline int ebase(const Ctx& c) { return c.e0p ? c.e0 + *c.e0p : c.e0; }
+
+// Workgroup -> (item, energy) of a grid (items, energies).  The dispatcher
+// deals workgroups to the eight XCDs round-robin by linear index, and each
+// XCD has its own L2.  Here every XCD takes every eighth energy and runs its
+// energies in groups of eight, item by item: the column tiles of one cluster
+// at one energy (which read the two triangles of the same symmetric block)
+// and one cluster's address tables over eight energies then meet in the same
+// L2 close together in time.  A bijection of the grid; the plain order when
+// the energy count is not a multiple of 8.
+struct WorkIdx {
+  int item, e;
+};
+__device__ inline WorkIdx xcd_work() {
+  const int nit = gridDim.x, nb = gridDim.y;
+  if (nb & 7) return {(int)blockIdx.x, (int)blockIdx.y};
+  const int lin = blockIdx.x + blockIdx.y * nit;
+  const int xcd = lin & 7, m = lin >> 3, per = nb >> 3;
+  const int g = (per & 7) ? 1 : 8;
+  const int grp = m / (nit * g), r = m - grp * nit * g;
+  return {r / g, ((grp * g + r % g) << 3) + xcd};
+}
 
 }  // namespace ndg

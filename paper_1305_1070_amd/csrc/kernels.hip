@@ -26,8 +26,9 @@ namespace ndg {
 // Schur update gathers it from the children directly.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
-  const int cl = cls[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const int cl = cls[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[cl];
@@ -98,8 +99,9 @@ __global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
   using GJ = RegGJ<SM, NT, (SM == 16 ? 8 : 16)>;
   static_assert(SM <= 64 || NT >= 512, "the 128-point inverse spreads over 512 threads");
   __shared__ typename GJ::Smem sm;
-  const int cl = cls[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const int cl = cls[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[cl];
@@ -162,8 +164,9 @@ __global__ void __launch_bounds__(NT) k_factor(Ctx c, const int32_t* cls) {
 template <int TM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 64 ? 2 : 3))) k_psi(Ctx c, const ColItem* items) {
   __shared__ GemmSmemR<TM> sm;
-  const ColItem it = items[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const ColItem it = items[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
@@ -200,8 +203,9 @@ template <int TM, bool P64>
 __device__ __forceinline__ void update_body(const Ctx& c, const UpdItem* items) {
   using GM = Gemm<P64>;
   __shared__ typename GM::template SmemT<TM> sm;
-  const UpdItem it = items[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const UpdItem it = items[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
@@ -312,8 +316,9 @@ k_update_narrow(Ctx c, const UpdItem* items) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_chain_fwd(Ctx c, const ChainItem* items) {
   __shared__ GemmSmem sm;
-  const ChainItem it = items[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const ChainItem it = items[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
@@ -384,8 +389,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // substitution.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_chain_t(Ctx c, const ChainItem* items) {
   __shared__ GemmSmem sm;
-  const ChainItem it = items[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const ChainItem it = items[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
@@ -417,8 +423,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // (L^{-1} Sigma^<)(G^r)^+ so only s x sc panels are folded.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_chain_back(Ctx c, const int32_t* cls) {
   __shared__ GemmSmem sm;
-  const int cl = cls[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const int cl = cls[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[cl];
@@ -499,8 +506,9 @@ __device__ __forceinline__ void down_off_body(const Ctx& c, const ColItem* items
   constexpr bool lesser = L != 0;
   using GM = Gemm<P64>;
   __shared__ typename GM::template SmemT<TM> sm;
-  const ColItem it = items[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const ColItem it = items[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
@@ -519,6 +527,10 @@ __device__ __forceinline__ void down_off_body(const Ctx& c, const ColItem* items
     if (d.o_bbd >= 0)
       GM::template acc<TM, false, false>(
           b, fa, [&](int k, int j) { return j < nj ? direct_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm);
+    else if constexpr (P64)
+      zgemm_acc_gather_t<TM, false>(
+          b, fa, [&](int k, int j) { return j < nj ? gather_bb_entry(c, d, k, j0 + j) : 0; },
+          [&](int32_t m, int j) { return j < nj ? gather_bb_value(c, S, m, ls) : cz(); }, acc, sm);
     else
       GM::template acc<TM, false, false>(
           b, fa, [&](int k, int j) { return j < nj ? gather_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm);
@@ -582,8 +594,9 @@ __device__ __forceinline__ void down_diag_body(const Ctx& c, const int32_t* cls)
   constexpr bool lesser = L != 0;
   using GM = Gemm<P64>;
   __shared__ typename GM::template SmemT<TM> sm;
-  const int cl = cls[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const int cl = cls[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[cl];
@@ -626,8 +639,9 @@ template <int TM, int L>
 __device__ __forceinline__ void down_diag_single_body(const Ctx& c, const int32_t* cls) {
   constexpr bool lesser = L != 0;
   __shared__ GemmSmemR<TM> sm;
-  const int cl = cls[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const int cl = cls[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[cl];
