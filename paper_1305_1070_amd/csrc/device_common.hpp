@@ -260,7 +260,7 @@ __device__ void zgemm_acc_gather_t(int K, FA fa, FI fidx, FV fval, ZTile& acc, G
 
 template <bool A_IFAST, bool B_KFAST, class FA, class FB>
 __device__ void zgemm_acc(int K, FA fa, FB fb, ZTile& acc, GemmSmem& sm) {
-  zgemm_acc_t<64, A_IFAST, B_KFAST, false>(K, fa, fb, acc, sm);
+  zgemm_acc_t<64, A_IFAST, B_KFAST, true>(K, fa, fb, acc, sm);
 }
 
 // Calls fs(i, j, re, im) for every tile element this thread holds

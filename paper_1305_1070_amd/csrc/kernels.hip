@@ -50,41 +50,66 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
   }
   __syncthreads();
   // -H, z - V on the diagonal, -Sigma, then the children's terms: one pass
-  // over all s f entries, so short rows do not idle threads
-  for (int q = t; q < s * f; q += 256) {
-    const int i = q / f, j = q - i * f;
-    double re = hf[q], im = 0.0;
-    if (j == i) {
-      const int site = c.perm[d.pt_off + i];
-      re += ez - (c.V ? c.V[site] : 0.0);
-      im = c.eta;
-      if (c.sig_r_ph) {
-        const double2 sp = c.sig_r_ph[(int64_t)(eb + e) * c.n + site];
-        re -= sp.x;
-        im -= sp.y;
-      }
+  // over all s f entries, so short rows do not idle threads.  Four entries
+  // per thread at a time, so that each round of dependent loads (map
+  // entries, then the values they point to) is issued for all four at once.
+  const int nq = s * f;
+  for (int q0 = t; q0 < nq; q0 += 4 * 256) {
+    int ii[4], jj[4], qq[4];
+    double re[4], im[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      qq[u] = min(q0 + u * 256, nq - 1);  // past the end: a repeat, not stored
+      ii[u] = qq[u] / f;
+      jj[u] = qq[u] - ii[u] * f;
+      re[u] = hf[qq[u]];
+      im[u] = 0.0;
     }
-    if (smp) {
-      const int code = smp[q];
-      if (code >= 0) {
-        const int cc = code >> 24, nc = sel2(c.nc, cc);
-        const double2 sv = sel2(c.sig_r, cc)[(int64_t)(eb + e) * nc * nc + (code & 0xFFFFFF)];
-        re -= sv.x;
-        im -= sv.y;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (jj[u] == ii[u]) {
+        const int site = c.perm[d.pt_off + ii[u]];
+        re[u] += ez - (c.V ? c.V[site] : 0.0);
+        im[u] = c.eta;
+        if (c.sig_r_ph) {
+          const double2 sp = c.sig_r_ph[(int64_t)(eb + e) * c.n + site];
+          re[u] -= sp.x;
+          im[u] -= sp.y;
+        }
       }
+    if (smp) {
+      int code[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) code[u] = smp[qq[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (code[u] >= 0) {
+          const int cc = code[u] >> 24, nc = sel2(c.nc, cc);
+          const double2 sv = sel2(c.sig_r, cc)[(int64_t)(eb + e) * nc * nc + (code[u] & 0xFFFFFF)];
+          re[u] -= sv.x;
+          im[u] -= sv.y;
+        }
     }
     for (int kq = 0; kq < nk; ++kq) {
       const int32_t* inv = c.pinv + kid_inv[kq];
-      const int ri = inv[i];
-      if (ri < 0) continue;
-      const int rj = inv[j];
-      if (rj < 0) continue;
-      // the contribution's upper triangle holds both (symmetric)
-      const double2 u = S[kid_upd[kq] + (int64_t)min(ri, rj) * kid_b[kq] + max(ri, rj)];
-      re += u.x;
-      im += u.y;
+      int ri[4], rj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ri[u] = inv[ii[u]];
+        rj[u] = inv[jj[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (ri[u] >= 0 && rj[u] >= 0) {
+          // the contribution's upper triangle holds both (symmetric)
+          const double2 x = S[kid_upd[kq] + (int64_t)min(ri[u], rj[u]) * kid_b[kq] + max(ri[u], rj[u])];
+          re[u] += x.x;
+          im[u] += x.y;
+        }
     }
-    F[q] = make_double2(re, im);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q0 + u * 256 < nq) F[q0 + u * 256] = make_double2(re[u], im[u]);
   }
 }
 
@@ -228,7 +253,7 @@ __device__ __forceinline__ void update_body(const Ctx& c, const UpdItem* items) 
   }
   typename GM::Tile acc;
   GM::zero(acc);
-  GM::template acc<TM, true, false, false>(
+  GM::template acc<TM, true, false>(
       s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
       [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm);
   // F_BB gathered from the children: each lane holds fixed tile rows and
@@ -302,7 +327,7 @@ k_update(Ctx c, const UpdItem* items) {
   update_body<64, P64>(c, items);
 }
 template <bool P64>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_update_narrow(Ctx c, const UpdItem* items) {
   update_body<32, P64>(c, items);
 }
@@ -457,7 +482,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         const int ni = min(64, s - r0), nj = min(64, sc - j0);
         ZTile acc;
         ztile_zero(acc);
-        zgemm_acc<false, false>(
+        zgemm_acc_t<64, false, false, false>(
             b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
             [&](int k, int j) { return j < nj ? Xf[(int64_t)(s + k) * sc + j0 + j] : cz(); }, acc, sm);
         ztile_store(acc, [&](int i, int j, double re, double im) {
@@ -473,7 +498,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         const int ni = min(64, s - r0), nj = min(64, f - j0);
         ZTile acc;
         ztile_zero(acc);
-        zgemm_acc<false, true>(
+        zgemm_acc_t<64, false, true, true>(
             sc, [&](int i, int k) { return i < ni ? T[(int64_t)(r0 + i) * sc + k] : cz(); },
             [&](int k, int j) {
               if (j >= nj) return cz();

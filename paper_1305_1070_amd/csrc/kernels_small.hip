@@ -216,9 +216,12 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
   double2* XIB = XBB + max(b * b, s * ls);  // s x b, stride lb (X_{B,B} is later X_ii)
   double2* XII = XBB;
   const double2* Psi = S + d.o_psi;
-  for (int q = t; q < s * b; q += NT) {
-    const int r = q / b, k = q - r * b;
-    Psl[r * lb + k] = Psi[q];
+  // two entries per thread at a time (their loads in flight together)
+  for (int q0 = t; q0 < s * b; q0 += 2 * NT) {
+    const int q1 = min(q0 + NT, s * b - 1);  // past the end: a repeat, not stored
+    const double2 v0 = Psi[q0], v1 = Psi[q1];
+    Psl[(q0 / b) * lb + q0 % b] = v0;
+    if (q0 + NT < s * b) Psl[(q1 / b) * lb + q1 % b] = v1;
   }
   {
     const int lesser = which;
