@@ -65,6 +65,44 @@ struct TileShape {
   static constexpr int NB = 64 / WN / 16;            // 16-column blocks per wave
 };
 
+// The matrix-core work on one staged chunk: the 4-deep steps below kend, on
+// this wave's 16 x 16 blocks of the tile (at rows wr, columns wc); with PRED
+// the blocks wholly outside the first live_m rows and live_n columns are
+// skipped (a choice uniform over the wave).
+template <int TM, bool PRED, bool RAGGED, int R>
+__device__ __forceinline__ void mma_chunk(const GemmSmemR<R>& sm, ZTile& acc, int wr, int wc, int lane, int kend,
+                                          int live_m, int live_n) {
+  using T = TileShape<TM>;
+#pragma unroll
+  for (int k4 = 0; k4 < KC; k4 += 4) {
+    if (RAGGED && k4 >= kend) break;
+    const int kq = k4 + (lane >> 4);
+    double are[T::MB], aim[T::MB], bre[T::NB], bim[T::NB];
+#pragma unroll
+    for (int m = 0; m < T::MB; ++m) {
+      const int i = wr + m * 16 + (lane & 15);
+      are[m] = sm.ar[i][kq];
+      aim[m] = sm.ai[i][kq];
+    }
+#pragma unroll
+    for (int n = 0; n < T::NB; ++n) {
+      const int j = wc + n * 16 + (lane & 15);
+      bre[n] = sm.br[kq][j];
+      bim[n] = sm.bi[kq][j];
+    }
+#pragma unroll
+    for (int m = 0; m < T::MB; ++m)
+#pragma unroll
+      for (int n = 0; n < T::NB; ++n) {
+        if (PRED && (wr + 16 * m >= live_m || wc + 16 * n >= live_n)) continue;
+        acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bre[n], acc.re[m][n], 0, 0, 0);
+        acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim[m], bim[n], acc.re[m][n], 0, 0, 0);
+        acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bim[n], acc.im[m][n], 0, 0, 0);
+        acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[m], bre[n], acc.im[m][n], 0, 0, 0);
+      }
+  }
+}
+
 // acc += A (TM x K) * B (K x 64).  fa(i, k) and fb(k, j) return the complex
 // operand (and 0 outside the live range); A_IFAST / B_KFAST select which index
 // runs fastest across threads while staging, to match the memory layout.
@@ -74,14 +112,19 @@ struct TileShape {
 // MFMAs); kernels that inline several products turn it off to stay within
 // the register file.  With RAGGED the last chunk runs only the 4-deep MFMA
 // steps that hold live K (products with short K, where a full 16-deep chunk
-// would mostly multiply zeros).
+// would mostly multiply zeros).  Only the first live_m rows and live_n
+// columns of the tile are live (fa and fb return 0 beyond them): in tiles of
+// fewer than 64 rows a wave skips the matrix-core work of its 16 x 16 blocks
+// that lie wholly outside (a ragged edge, or a block narrower than the tile;
+// the 64-row tiles keep one code path, within their register budget).
 template <int TM, bool A_IFAST, bool B_KFAST, bool PF = true, int R = 64, bool RAGGED = false, class FA,
           class FB>
-__device__ void zgemm_acc_t(int K, FA fa, FB fb, ZTile& acc, GemmSmemR<R>& sm) {
+__device__ void zgemm_acc_t(int K, FA fa, FB fb, ZTile& acc, GemmSmemR<R>& sm, int live_m = TM, int live_n = 64) {
   static_assert(R >= TM, "staging rows");
   using T = TileShape<TM>;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
+  const bool all_live = wr + 16 * T::MB <= live_m && wc + 16 * T::NB <= live_n;
   // staging index of operand element q of this thread
   auto a_idx = [&](int q, int& i, int& kk) {
     const int idx = t + 256 * q;
@@ -135,33 +178,8 @@ __device__ void zgemm_acc_t(int K, FA fa, FB fb, ZTile& acc, GemmSmemR<R>& sm) {
     __syncthreads();
     if (k0 + KC < K) load(k0 + KC);
     const int kend = RAGGED ? min(KC, K - k0) : KC;
-#pragma unroll
-    for (int k4 = 0; k4 < KC; k4 += 4) {
-      if (RAGGED && k4 >= kend) break;
-      const int kq = k4 + (lane >> 4);
-      double are[2], aim[2], bre[2], bim[2];
-#pragma unroll
-      for (int m = 0; m < T::MB; ++m) {
-        const int i = wr + m * 16 + (lane & 15);
-        are[m] = sm.ar[i][kq];
-        aim[m] = sm.ai[i][kq];
-      }
-#pragma unroll
-      for (int n = 0; n < T::NB; ++n) {
-        const int j = wc + n * 16 + (lane & 15);
-        bre[n] = sm.br[kq][j];
-        bim[n] = sm.bi[kq][j];
-      }
-#pragma unroll
-      for (int m = 0; m < T::MB; ++m)
-#pragma unroll
-        for (int n = 0; n < T::NB; ++n) {
-          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bre[n], acc.re[m][n], 0, 0, 0);
-          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim[m], bim[n], acc.re[m][n], 0, 0, 0);
-          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bim[n], acc.im[m][n], 0, 0, 0);
-          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[m], bre[n], acc.im[m][n], 0, 0, 0);
-        }
-    }
+    if (TM == 64 || all_live) mma_chunk<TM, false, RAGGED>(sm, acc, wr, wc, lane, kend, live_m, live_n);
+    else mma_chunk<TM, true, RAGGED>(sm, acc, wr, wc, lane, kend, live_m, live_n);
     __syncthreads();
   }
 }
@@ -172,13 +190,16 @@ __device__ void zgemm_acc_t(int K, FA fa, FB fb, ZTile& acc, GemmSmemR<R>& sm) {
 // matrix cores work on chunk k0, the values of chunk k0 + KC (whose entries
 // arrived during the previous chunk) and the entries of chunk k0 + 2 KC are
 // in flight, so each chunk waits for one memory round trip instead of two
-// dependent ones.  A is read as in zgemm_acc_t (A_IFAST), B with j fastest.
+// dependent ones.  A is read as in zgemm_acc_t (A_IFAST), B with j fastest;
+// live_m and live_n as there.
 template <int TM, bool A_IFAST, int R, class FA, class FI, class FV>
-__device__ void zgemm_acc_gather_t(int K, FA fa, FI fidx, FV fval, ZTile& acc, GemmSmemR<R>& sm) {
+__device__ void zgemm_acc_gather_t(int K, FA fa, FI fidx, FV fval, ZTile& acc, GemmSmemR<R>& sm, int live_m = TM,
+                                   int live_n = 64) {
   static_assert(R >= TM, "staging rows");
   using T = TileShape<TM>;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
+  const bool all_live = wr + 16 * T::MB <= live_m && wc + 16 * T::NB <= live_n;
   auto a_idx = [&](int q, int& i, int& kk) {
     const int idx = t + 256 * q;
     if (A_IFAST) { i = idx % TM; kk = idx / TM; }
@@ -228,39 +249,15 @@ __device__ void zgemm_acc_gather_t(int K, FA fa, FI fidx, FV fval, ZTile& acc, G
       load_val(k0 + KC);
       load_idx(k0 + 2 * KC);
     }
-#pragma unroll
-    for (int k4 = 0; k4 < KC; k4 += 4) {
-      const int kq = k4 + (lane >> 4);
-      double are[T::MB], aim[T::MB], bre[T::NB], bim[T::NB];
-#pragma unroll
-      for (int m = 0; m < T::MB; ++m) {
-        const int i = wr + m * 16 + (lane & 15);
-        are[m] = sm.ar[i][kq];
-        aim[m] = sm.ai[i][kq];
-      }
-#pragma unroll
-      for (int n = 0; n < T::NB; ++n) {
-        const int j = wc + n * 16 + (lane & 15);
-        bre[n] = sm.br[kq][j];
-        bim[n] = sm.bi[kq][j];
-      }
-#pragma unroll
-      for (int m = 0; m < T::MB; ++m)
-#pragma unroll
-        for (int n = 0; n < T::NB; ++n) {
-          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bre[n], acc.re[m][n], 0, 0, 0);
-          acc.re[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim[m], bim[n], acc.re[m][n], 0, 0, 0);
-          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[m], bim[n], acc.im[m][n], 0, 0, 0);
-          acc.im[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[m], bre[n], acc.im[m][n], 0, 0, 0);
-        }
-    }
+    if (TM == 64 || all_live) mma_chunk<TM, false, false>(sm, acc, wr, wc, lane, KC, live_m, live_n);
+    else mma_chunk<TM, true, false>(sm, acc, wr, wc, lane, KC, live_m, live_n);
     __syncthreads();
   }
 }
 
 template <bool A_IFAST, bool B_KFAST, class FA, class FB>
-__device__ void zgemm_acc(int K, FA fa, FB fb, ZTile& acc, GemmSmem& sm) {
-  zgemm_acc_t<64, A_IFAST, B_KFAST, true>(K, fa, fb, acc, sm);
+__device__ void zgemm_acc(int K, FA fa, FB fb, ZTile& acc, GemmSmem& sm, int live_m = 64, int live_n = 64) {
+  zgemm_acc_t<64, A_IFAST, B_KFAST, true>(K, fa, fb, acc, sm, live_m, live_n);
 }
 
 // Calls fs(i, j, re, im) for every tile element this thread holds
@@ -444,7 +441,9 @@ struct Gemm<true> {
   using SmemT = GemmSmemR<R>;
   __device__ static void zero(Tile& a) { ztile_zero(a); }
   template <int TM, bool AI, bool BK, bool PF = true, int R, class FA, class FB>
-  __device__ static void acc(int K, FA fa, FB fb, Tile& t, SmemT<R>& sm) { zgemm_acc_t<TM, AI, BK, PF>(K, fa, fb, t, sm); }
+  __device__ static void acc(int K, FA fa, FB fb, Tile& t, SmemT<R>& sm, int live_m = TM, int live_n = 64) {
+    zgemm_acc_t<TM, AI, BK, PF>(K, fa, fb, t, sm, live_m, live_n);
+  }
   template <int TM, class FS>
   __device__ static void store(const Tile& t, FS fs) { ztile_store_t<TM>(t, fs); }
 };
@@ -456,7 +455,9 @@ struct Gemm<false> {
   using SmemT = GemmSmem32R<R>;
   __device__ static void zero(Tile& a) { ztile32_zero(a); }
   template <int TM, bool AI, bool BK, bool PF = true, int R, class FA, class FB>
-  __device__ static void acc(int K, FA fa, FB fb, Tile& t, SmemT<R>& sm) { zgemm32_acc_t<TM, AI, BK>(K, fa, fb, t, sm); }
+  __device__ static void acc(int K, FA fa, FB fb, Tile& t, SmemT<R>& sm, int = TM, int = 64) {
+    zgemm32_acc_t<TM, AI, BK>(K, fa, fb, t, sm);
+  }
   template <int TM, class FS>
   __device__ static void store(const Tile& t, FS fs) { ztile32_store_t<TM>(t, fs); }
 };

@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 
     ztile_zero(acc);
     zgemm_acc_t<TM, false, false>(
         s, [&](int i, int k) { return i < ni ? Ainv[(r0 + i) * s + k] : cz(); },
-        [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm);
+        [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm, ni, nj);
     ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
       if (i < ni && j < nj) Psi[(int64_t)(r0 + i) * b + j0 + j] = make_double2(-re, -im);
     });
@@ -255,7 +255,7 @@ __device__ __forceinline__ void update_body(const Ctx& c, const UpdItem* items) 
   GM::zero(acc);
   GM::template acc<TM, true, false>(
       s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
-      [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm);
+      [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm, ni, nj);
   // F_BB gathered from the children: each lane holds fixed tile rows and
   // columns (lane l, register r -> column l%16 of each 16 x 16 block and row
   // l/16 + 4r for the FP64 matrix-core layout, 4(l/16) + r for the FP32
@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       ztile_zero(acc);
       zgemm_acc<true, false>(
           s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
-          [&](int k, int j) { return j < nj ? rhs(k, j0 + j) : cz(); }, acc, sm);
+          [&](int k, int j) { return j < nj ? rhs(k, j0 + j) : cz(); }, acc, sm, ni, nj);
       ztile_store(acc, [&](int i, int j, double re, double im) {
         if (i < ni && j < nj) {
           const double2 v = rhs(s + i0 + i, j0 + j);
@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       ztile_zero(acc);
       zgemm_acc<false, false>(
           s, [&](int i, int k) { return i < ni ? Ainv[(r0 + i) * s + k] : cz(); },
-          [&](int k, int j) { return j < nj ? rhs(k, j0 + j) : cz(); }, acc, sm);
+          [&](int k, int j) { return j < nj ? rhs(k, j0 + j) : cz(); }, acc, sm, ni, nj);
       ztile_store(acc, [&](int i, int j, double re, double im) {
         if (i < ni && j < nj) Zf[(int64_t)(r0 + i) * sc + j0 + j] = make_double2(re, im);
       });
@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       ztile_zero(acc);
       zgemm_acc<false, false>(
           sc, [&](int i, int k) { return i < ni ? Zf[(int64_t)(r0 + i) * sc + k] : cz(); },
-          [&](int k, int j) { return j < nj ? sl[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm);
+          [&](int k, int j) { return j < nj ? sl[(int64_t)k * sc + j0 + j] : cz(); }, acc, sm, ni, nj);
       ztile_store(acc, [&](int i, int j, double re, double im) {
         if (i < ni && j < nj) T[(int64_t)(r0 + i) * sc + j0 + j] = make_double2(re, im);
       });
@@ -484,7 +484,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         ztile_zero(acc);
         zgemm_acc_t<64, false, false, false>(
             b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
-            [&](int k, int j) { return j < nj ? Xf[(int64_t)(s + k) * sc + j0 + j] : cz(); }, acc, sm);
+            [&](int k, int j) { return j < nj ? Xf[(int64_t)(s + k) * sc + j0 + j] : cz(); }, acc, sm, ni, nj);
         ztile_store(acc, [&](int i, int j, double re, double im) {
           if (i < ni && j < nj) {
             const double2 z = Zf[(int64_t)(r0 + i) * sc + j0 + j];
@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
               const double2 x = Xf[(int64_t)(j0 + j) * sc + k];
               return make_double2(x.x, -x.y);
             },
-            acc, sm);
+            acc, sm, ni, nj);
         ztile_store(acc, [&](int i, int j, double re, double im) {
           if (i < ni && j < nj) {
             double2* p = FP + (int64_t)(r0 + i) * f + j0 + j;
@@ -551,14 +551,14 @@ __device__ __forceinline__ void down_off_body(const Ctx& c, const ColItem* items
     auto fa = [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); };
     if (d.o_bbd >= 0)
       GM::template acc<TM, false, false>(
-          b, fa, [&](int k, int j) { return j < nj ? direct_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm);
+          b, fa, [&](int k, int j) { return j < nj ? direct_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm, ni, nj);
     else if constexpr (P64)
       zgemm_acc_gather_t<TM, false>(
           b, fa, [&](int k, int j) { return j < nj ? gather_bb_entry(c, d, k, j0 + j) : 0; },
-          [&](int32_t m, int j) { return j < nj ? gather_bb_value(c, S, m, ls) : cz(); }, acc, sm);
+          [&](int32_t m, int j) { return j < nj ? gather_bb_value(c, S, m, ls) : cz(); }, acc, sm, ni, nj);
     else
       GM::template acc<TM, false, false>(
-          b, fa, [&](int k, int j) { return j < nj ? gather_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm);
+          b, fa, [&](int k, int j) { return j < nj ? gather_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm, ni, nj);
     GM::template store<TM>(acc, [&](int i, int j, double re, double im) {
       if (i < ni && j < nj) {
         double2 v = make_double2(re, im);
@@ -603,11 +603,11 @@ __device__ __forceinline__ void down_diag_tile(const double2* Psi, const double2
           const double2 x = X[(int64_t)(c0 + j) * f + s + k];
           return make_double2(-x.x, x.y);
         },
-        acc, sm);
+        acc, sm, ni, nj);
   } else {
     GM::template acc<TM, false, true>(
         b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
-        [&](int k, int j) { return j < nj ? X[(int64_t)(c0 + j) * f + s + k] : cz(); }, acc, sm);
+        [&](int k, int j) { return j < nj ? X[(int64_t)(c0 + j) * f + s + k] : cz(); }, acc, sm, ni, nj);
   }
 }
 
@@ -828,13 +828,18 @@ void launch_down_off(const Ctx& c, const ColItem* it, int nit, int nb, bool less
 }
 template <bool P64, int L>
 static void down_diag_t(const Ctx& c, const int32_t* cls, int ncl, int nb, int cls_size, hipStream_t st) {
-  // FP64 blocks of one tile (every cluster of the group has s <= cls_size)
-  if (P64 && cls_size <= 16) hipLaunchKernelGGL((k_down_diag_single<16, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
-  else if (P64 && cls_size <= 32) hipLaunchKernelGGL((k_down_diag_single<32, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
-  else if (P64 && cls_size <= 64) hipLaunchKernelGGL((k_down_diag_single<64, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
-  else if (cls_size <= 16) hipLaunchKernelGGL((k_down_diag_narrow<P64, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
-  else if (cls_size <= 32) hipLaunchKernelGGL((k_down_diag<32, P64, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
-  else hipLaunchKernelGGL((k_down_diag<64, P64, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+  if constexpr (P64) {
+    // FP64 blocks of one tile (every cluster of the group has s <= cls_size),
+    // larger blocks in 64-row tiles
+    if (cls_size <= 16) hipLaunchKernelGGL((k_down_diag_single<16, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+    else if (cls_size <= 32) hipLaunchKernelGGL((k_down_diag_single<32, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+    else if (cls_size <= 64) hipLaunchKernelGGL((k_down_diag_single<64, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+    else hipLaunchKernelGGL((k_down_diag<64, true, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+  } else {
+    if (cls_size <= 16) hipLaunchKernelGGL((k_down_diag_narrow<false, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+    else if (cls_size <= 32) hipLaunchKernelGGL((k_down_diag<32, false, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+    else hipLaunchKernelGGL((k_down_diag<64, false, L>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
+  }
 }
 void launch_down_diag(const Ctx& c, const int32_t* cls, int ncl, int nb, bool lesser, int cls_size,
                       hipStream_t st) {

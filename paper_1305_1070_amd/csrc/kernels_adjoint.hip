@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(256) k_rhs_fwd(Ctx c, RhsCtx r, const int32_t*
       }
       zgemm_acc_t<64, true, false, true>(
           s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
-          [&](int k, int j) { return j < nj ? Zf[(int64_t)k * m + j0 + j] : cz(); }, acc, sm);
+          [&](int k, int j) { return j < nj ? Zf[(int64_t)k * m + j0 + j] : cz(); }, acc, sm, ni, nj);
       ztile_store_t<64>(acc, [&](int i, int j, double re, double im) {
         if (i < ni && j < nj) Zf[(int64_t)(s + i0 + i) * m + j0 + j] = make_double2(re, im);
       });
@@ -278,11 +278,11 @@ __global__ void __launch_bounds__(256) k_rhs_back(Ctx c, RhsCtx r, const int32_t
     ztile_zero(acc);
     zgemm_acc_t<64, false, false, true>(
         s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
-        [&](int k, int j) { return j < nj ? Zf[(int64_t)k * m + j0 + j] : cz(); }, acc, sm);
+        [&](int k, int j) { return j < nj ? Zf[(int64_t)k * m + j0 + j] : cz(); }, acc, sm, s, nj);
     if (b > 0)
       zgemm_acc_t<64, false, false, true>(
           b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
-          [&](int k, int j) { return j < nj ? X[(int64_t)bidx[k] * m + j0 + j] : cz(); }, acc, sm);
+          [&](int k, int j) { return j < nj ? X[(int64_t)bidx[k] * m + j0 + j] : cz(); }, acc, sm, s, nj);
     ztile_store_t<64>(acc, [&](int i, int j, double re, double im) {
       if (i < s && j < nj) X[(int64_t)(d.pt_off + i) * m + j0 + j] = make_double2(re, im);
     });
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(256) k_vjp(Ctx c, RhsCtx r, int cc, int off) {
     ztile_zero(acc);
     zgemm_acc_t<64, false, false, true>(
         mc, [&](int i, int k) { return i < ni ? G[(int64_t)(i0 + i) * m + k] : cz(); },
-        [&](int k, int j) { return j < nj ? sg[(int64_t)k * mc + j0 + j] : cz(); }, acc, sm);
+        [&](int k, int j) { return j < nj ? sg[(int64_t)k * mc + j0 + j] : cz(); }, acc, sm, ni, nj);
 #pragma unroll
     for (int mm = 0; mm < T::MB; ++mm)
 #pragma unroll

@@ -108,7 +108,7 @@ __device__ __forceinline__ void anc_g_body(const Ctx& c, const ScatCtx& x, const
           else addr = fr.og[ay] + (int64_t)(y - fr.ao[ay]) * fr.gg[ay] + (u.col - fr.ao[ay]);
           return X[addr];
         },
-        acc, sm);
+        acc, sm, s, nj);
   ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
     const int y = j0 + j;
     if (i < s && j < nj) {
@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(256) k_anc_p0(Ctx c, ScatCtx x, const int32_t*
           const int col = cc < s ? cc : bp[cc - s].col;
           return Ni[(int64_t)k * g + col];
         },
-        acc, sm);
+        acc, sm, s, nj);
     ztile_store_t<TM>(acc, [&](int i, int j, double re, double im) {
       if (i < s && j < nj) {
         double2* p = FP + (int64_t)i * f + j0 + j;
