@@ -284,6 +284,38 @@ __device__ inline void ztile_store(const ZTile& acc, FS fs) {
   ztile_store_t<64>(acc, fs);
 }
 
+// ztile_store_t of acc + fl(i, j): every fl load of this thread is issued
+// before the first store (stores may alias the loads, so a load after a
+// store would wait for it), then fs(i, j, re, im) with the sums.
+// With BY_ROW the loads and stores go one 16-row block at a time (half the
+// registers for the loaded values, two rounds of loads).
+template <int TM, bool BY_ROW = false, class FL, class FS>
+__device__ inline void ztile_store_add_t(const ZTile& acc, FL fl, FS fs) {
+  using T = TileShape<TM>;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w / T::WN) * (TM / T::WM), wc = (w % T::WN) * (64 / T::WN);
+  constexpr int G = BY_ROW ? 1 : T::MB;  // row blocks per round
+#pragma unroll
+  for (int m0 = 0; m0 < T::MB; m0 += G) {
+    double2 add[G][T::NB][4];
+#pragma unroll
+    for (int m = 0; m < G; ++m)
+#pragma unroll
+      for (int n = 0; n < T::NB; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          add[m][n][r] = fl(wr + (m0 + m) * 16 + (lane >> 4) + 4 * r, wc + n * 16 + (lane & 15));
+#pragma unroll
+    for (int m = 0; m < G; ++m)
+#pragma unroll
+      for (int n = 0; n < T::NB; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          fs(wr + (m0 + m) * 16 + (lane >> 4) + 4 * r, wc + n * 16 + (lane & 15),
+             acc.re[m0 + m][n][r] + add[m][n][r].x, acc.im[m0 + m][n][r] + add[m][n][r].y);
+  }
+}
+
 // Calls fs(i, j, re, im) with references to every tile element this thread
 // holds (same layout as ztile_store_t), to update the tile in place.
 template <int TM, class FS>

@@ -339,6 +339,10 @@ k_update_narrow(Ctx c, const UpdItem* items) {
 // (passed up as V_d = Psi_d^T Z_d over B_d), then Zd_i = A_ii^{-1} Z_i.
 // Zf rows [0, s) end up holding Zd_i, rows [s, f) the contribution V_i.
 // ---------------------------------------------------------------------------
+// fronts and contacts up to this many points keep the chain solve's index
+// maps in LDS (larger ones read them from memory)
+constexpr int kChainMap = 512;
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_chain_fwd(Ctx c, const ChainItem* items) {
   __shared__ GemmSmem sm;
   const WorkIdx wk = xcd_work();
@@ -370,9 +374,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   }
   const int32_t* pos = sel2(c.cpos, cc);
   const int off = d.pt_off;
+  // the two maps in LDS, so that an entry of the right-hand side costs one
+  // dependent global load instead of three
+  __shared__ int rmap[kChainMap], cmap[kChainMap];
+  const bool lmap = f <= kChainMap && sc <= kChainMap;
+  if (lmap) {
+    for (int p = t; p < f; p += 256) rmap[p] = inv ? inv[p] : -1;
+    for (int a = t; a < sc; a += 256) cmap[a] = pos[a] - off;
+  }
+  __syncthreads();
   auto rhs = [&](int p, int a) {
-    if (p < s && pos[a] - off == p) return make_double2(1.0, 0.0);
-    const int r = inv ? inv[p] : -1;
+    if (p < s && (lmap ? cmap[a] : pos[a] - off) == p) return make_double2(1.0, 0.0);
+    const int r = lmap ? rmap[p] : (inv ? inv[p] : -1);
     return r >= 0 ? Zc[(int64_t)(cs + r) * sc + a] : cz();
   };
   // contacts wider than one tile: 64-column panels of Zf, independent
@@ -386,12 +399,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       zgemm_acc<true, false>(
           s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
           [&](int k, int j) { return j < nj ? rhs(k, j0 + j) : cz(); }, acc, sm, ni, nj);
-      ztile_store(acc, [&](int i, int j, double re, double im) {
-        if (i < ni && j < nj) {
-          const double2 v = rhs(s + i0 + i, j0 + j);
-          Zf[(int64_t)(s + i0 + i) * sc + j0 + j] = make_double2(v.x + re, v.y + im);
-        }
-      });
+      ztile_store_add_t<64, true>(
+          acc, [&](int i, int j) { return (i < ni && j < nj) ? rhs(s + i0 + i, j0 + j) : cz(); },
+          [&](int i, int j, double re, double im) {
+            if (i < ni && j < nj) Zf[(int64_t)(s + i0 + i) * sc + j0 + j] = make_double2(re, im);
+          });
     }
     // rows [0, s): Zd_i = A_ii^{-1} rhs_i, in 64-row tiles
     for (int r0 = 0; r0 < s; r0 += 64) {
@@ -485,12 +497,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         zgemm_acc_t<64, false, false, false>(
             b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
             [&](int k, int j) { return j < nj ? Xf[(int64_t)(s + k) * sc + j0 + j] : cz(); }, acc, sm, ni, nj);
-        ztile_store(acc, [&](int i, int j, double re, double im) {
-          if (i < ni && j < nj) {
-            const double2 z = Zf[(int64_t)(r0 + i) * sc + j0 + j];
-            Xf[(int64_t)(r0 + i) * sc + j0 + j] = make_double2(z.x + re, z.y + im);
-          }
-        });
+        ztile_store_add_t<64>(
+            acc, [&](int i, int j) { return (i < ni && j < nj) ? Zf[(int64_t)(r0 + i) * sc + j0 + j] : cz(); },
+            [&](int i, int j, double re, double im) {
+              if (i < ni && j < nj) Xf[(int64_t)(r0 + i) * sc + j0 + j] = make_double2(re, im);
+            });
       }
     __syncthreads();
     for (int r0 = 0; r0 < s; r0 += 64)
@@ -506,13 +517,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
               return make_double2(x.x, -x.y);
             },
             acc, sm, ni, nj);
-        ztile_store(acc, [&](int i, int j, double re, double im) {
-          if (i < ni && j < nj) {
-            double2* p = FP + (int64_t)(r0 + i) * f + j0 + j;
-            if (first) *p = make_double2(re, im);
-            else { double2 v = *p; v.x += re; v.y += im; *p = v; }
-          }
-        });
+        ztile_store_add_t<64>(
+            acc, [&](int i, int j) { return (!first && i < ni && j < nj) ? FP[(int64_t)(r0 + i) * f + j0 + j] : cz(); },
+            [&](int i, int j, double re, double im) {
+              if (i < ni && j < nj) FP[(int64_t)(r0 + i) * f + j0 + j] = make_double2(re, im);
+            });
       }
     __syncthreads();
     first = false;
@@ -559,14 +568,22 @@ __device__ __forceinline__ void down_off_body(const Ctx& c, const ColItem* items
     else
       GM::template acc<TM, false, false>(
           b, fa, [&](int k, int j) { return j < nj ? gather_bb(c, S, d, k, j0 + j, ls) : cz(); }, acc, sm, ni, nj);
-    GM::template store<TM>(acc, [&](int i, int j, double re, double im) {
-      if (i < ni && j < nj) {
-        double2 v = make_double2(re, im);
-        const int64_t pos = (int64_t)(r0 + i) * f + s + j0 + j;
-        if (has_src) { const double2 p0 = X[pos]; v.x += p0.x; v.y += p0.y; }
-        X[pos] = v;
-      }
-    });
+    if constexpr (P64) {
+      ztile_store_add_t<TM>(
+          acc, [&](int i, int j) { return (has_src && i < ni && j < nj) ? X[(int64_t)(r0 + i) * f + s + j0 + j] : cz(); },
+          [&](int i, int j, double re, double im) {
+            if (i < ni && j < nj) X[(int64_t)(r0 + i) * f + s + j0 + j] = make_double2(re, im);
+          });
+    } else {
+      GM::template store<TM>(acc, [&](int i, int j, double re, double im) {
+        if (i < ni && j < nj) {
+          double2 v = make_double2(re, im);
+          const int64_t pos = (int64_t)(r0 + i) * f + s + j0 + j;
+          if (has_src) { const double2 p0 = X[pos]; v.x += p0.x; v.y += p0.y; }
+          X[pos] = v;
+        }
+      });
+    }
     if (r0 + TM < s) __syncthreads();
   }
 }
