@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(256) k_rhs_fwd(Ctx c, RhsCtx r, const int32_t*
               }
             }
       }
-      zgemm_acc_t<64, true, false, true>(
+      zgemm_acc_t<64, true, false, false>(
           s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
           [&](int k, int j) { return j < nj ? Zf[(int64_t)k * m + j0 + j] : cz(); }, acc, sm, ni, nj);
       ztile_store_t<64>(acc, [&](int i, int j, double re, double im) {
@@ -276,11 +276,11 @@ __global__ void __launch_bounds__(256) k_rhs_back(Ctx c, RhsCtx r, const int32_t
     const int nj = min(64, m - j0);
     ZTile acc;
     ztile_zero(acc);
-    zgemm_acc_t<64, false, false, true>(
+    zgemm_acc_t<64, false, false, false>(
         s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
         [&](int k, int j) { return j < nj ? Zf[(int64_t)k * m + j0 + j] : cz(); }, acc, sm, s, nj);
     if (b > 0)
-      zgemm_acc_t<64, false, false, true>(
+      zgemm_acc_t<64, false, false, false>(
           b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
           [&](int k, int j) { return j < nj ? X[(int64_t)bidx[k] * m + j0 + j] : cz(); }, acc, sm, s, nj);
     ztile_store_t<64>(acc, [&](int i, int j, double re, double im) {
@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(256) k_vjp(Ctx c, RhsCtx r, int cc, int off) {
     const int nj = min(64, mc - j0);
     ZTile acc;
     ztile_zero(acc);
-    zgemm_acc_t<64, false, false, true>(
+    zgemm_acc_t<64, false, false, false>(
         mc, [&](int i, int k) { return i < ni ? G[(int64_t)(i0 + i) * m + k] : cz(); },
         [&](int k, int j) { return j < nj ? sg[(int64_t)k * mc + j0 + j] : cz(); }, acc, sm, ni, nj);
 #pragma unroll
