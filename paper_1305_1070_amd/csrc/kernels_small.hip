@@ -233,33 +233,47 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
     // starting at k b - k (k - 1) / 2.
     const int ntri = b * (b + 1) / 2;
     const float bh = (float)b + 0.5f;
-    // four entries per thread at a time: their table entries, then their
-    // values, are loaded together
-    for (int q0 = t; q0 < ntri; q0 += 4 * NT) {
-      int kk[4], jj[4];
-      int32_t m[4];
+    // four entries per thread at a time (their table entries, then their
+    // values, loaded together) where the triangle spans several rounds of
+    // the block; one at a time on tiny fronts
+    if (ntri > 2 * NT) {
+      for (int q0 = t; q0 < ntri; q0 += 4 * NT) {
+        int kk[4], jj[4];
+        int32_t m[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int q = q0 + u * NT;
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + u * NT;
+          int k = (int)(bh - sqrtf(bh * bh - 2.0f * (float)q));
+          k = min(max(k, 0), b - 1);
+          if (k * b - (k * (k - 1) >> 1) > q) --k;
+          else if (k + 1 < b && (k + 1) * b - ((k + 1) * k >> 1) <= q) ++k;
+          kk[u] = k;
+          jj[u] = k + q - (k * b - (k * (k - 1) >> 1));
+          if (q < ntri) m[u] = gather_bb_entry(c, d, k, jj[u]);
+        }
+        double2 x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (q0 + u * NT < ntri) x[u] = gather_bb_value(c, S, m[u], lesser != 0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (q0 + u * NT < ntri) {
+            const int k = kk[u], j = jj[u];
+            XBB[k * b + j] = x[u];
+            if (j != k) XBB[j * b + k] = lesser ? make_double2(-x[u].x, x[u].y) : x[u];
+          }
+      }
+    } else {
+      for (int q = t; q < ntri; q += NT) {
         int k = (int)(bh - sqrtf(bh * bh - 2.0f * (float)q));
         k = min(max(k, 0), b - 1);
         if (k * b - (k * (k - 1) >> 1) > q) --k;
         else if (k + 1 < b && (k + 1) * b - ((k + 1) * k >> 1) <= q) ++k;
-        kk[u] = k;
-        jj[u] = k + q - (k * b - (k * (k - 1) >> 1));
-        if (q < ntri) m[u] = gather_bb_entry(c, d, k, jj[u]);
+        const int j = k + q - (k * b - (k * (k - 1) >> 1));
+        const double2 x = gather_bb(c, S, d, k, j, lesser != 0);
+        XBB[k * b + j] = x;
+        if (j != k) XBB[j * b + k] = lesser ? make_double2(-x.x, x.y) : x;
       }
-      double2 x[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (q0 + u * NT < ntri) x[u] = gather_bb_value(c, S, m[u], lesser != 0);
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (q0 + u * NT < ntri) {
-          const int k = kk[u], j = jj[u];
-          XBB[k * b + j] = x[u];
-          if (j != k) XBB[j * b + k] = lesser ? make_double2(-x[u].x, x[u].y) : x[u];
-        }
     }
     __syncthreads();
     // X_{i,B} = P_init + Psi X_{B,B}: two rows per thread share each X_{B,B}
