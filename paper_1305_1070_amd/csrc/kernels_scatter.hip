@@ -69,8 +69,9 @@ __device__ __forceinline__ void anc_g_body(const Ctx& c, const ScatCtx& x, const
   __shared__ FrameLds fr;
   __shared__ int32_t col_a[64];
   __shared__ double2 sig_row[kClusterRows];
-  const ColItem it = items[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const ColItem it = items[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
@@ -248,8 +249,9 @@ template <int TM>
 __global__ void __launch_bounds__(256) k_anc_n(Ctx c, ScatCtx x, const ColItem* items) {
   __shared__ GemmSmemR<TM> sm;
   __shared__ double2 sig_row[kClusterRows];
-  const ColItem it = items[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const ColItem it = items[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[it.cl];
@@ -280,8 +282,9 @@ __global__ void __launch_bounds__(256) k_anc_n(Ctx c, ScatCtx x, const ColItem* 
 template <int TM>
 __global__ void __launch_bounds__(256) k_anc_p0(Ctx c, ScatCtx x, const int32_t* cls) {
   __shared__ GemmSmemR<TM> sm;
-  const int cl = cls[blockIdx.x];
-  const int e = blockIdx.y;
+  const WorkIdx wk = xcd_work();
+  const int cl = cls[wk.item];
+  const int e = wk.e;
   const int eb = ebase(c);
   if (eb + e >= c.nE) return;
   const ClusterDesc d = c.cl[cl];
