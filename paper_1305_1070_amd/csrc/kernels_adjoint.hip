@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(64) k_rhs_back_small(Ctx c, RhsCtx r, const in
 // matrix-core tile (children gathered through their index maps into the
 // accumulators, then the product on top).  Every row is written once; the
 // block diagonal D^{-1} is applied by the back substitution.
-__global__ void __launch_bounds__(256) k_rhs_fwd(Ctx c, RhsCtx r, const int32_t* cls) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_rhs_fwd(Ctx c, RhsCtx r, const int32_t* cls) {
   __shared__ GemmSmem sm;
   __shared__ int64_t kid_inv[kMaxKids], kid_z[kMaxKids];
   const int cl = cls[blockIdx.x];
@@ -197,18 +197,35 @@ __global__ void __launch_bounds__(256) k_rhs_fwd(Ctx c, RhsCtx r, const int32_t*
     kid_z[q] = r.o_vec[ch] + (int64_t)dc.s * m;         // the child's B rows
   }
   __syncthreads();
-  for (int q = t; q < s * m; q += 256) {
-    const int x = q / m, a = q - x * m;
-    double2 v = rhs_y(c, r, e, d.pt_off + x, a);
-    for (int kq = 0; kq < nk; ++kq) {
-      const int ci = c.pinv[kid_inv[kq] + x];
-      if (ci >= 0) {
-        const double2 u = Zsl[kid_z[kq] + (int64_t)ci * m + a];
-        v.x += u.x;
-        v.y += u.y;
-      }
+  // four entries per thread at a time: each round of dependent loads
+  // (right-hand side, children's maps, their rows) issued for all four
+  // before any entry is stored
+  const int nq = s * m;
+  for (int q0 = t; q0 < nq; q0 += 4 * 256) {
+    int xs[4], as[4];
+    double2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = min(q0 + u * 256, nq - 1);  // past the end: a repeat, not stored
+      xs[u] = q / m;
+      as[u] = q - xs[u] * m;
+      v[u] = rhs_y(c, r, e, d.pt_off + xs[u], as[u]);
     }
-    Zf[q] = v;
+    for (int kq = 0; kq < nk; ++kq) {
+      int ci[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ci[u] = c.pinv[kid_inv[kq] + xs[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (ci[u] >= 0) {
+          const double2 z = Zsl[kid_z[kq] + (int64_t)ci[u] * m + as[u]];
+          v[u].x += z.x;
+          v[u].y += z.y;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q0 + u * 256 < nq) Zf[q0 + u * 256] = v[u];
   }
   if (b == 0) return;  // the root passes nothing up
   __threadfence_block();
@@ -246,7 +263,7 @@ __global__ void __launch_bounds__(256) k_rhs_fwd(Ctx c, RhsCtx r, const int32_t*
               }
             }
       }
-      zgemm_acc_t<64, true, false, false>(
+      zgemm_acc_t<64, true, false, true>(
           s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
           [&](int k, int j) { return j < nj ? Zf[(int64_t)k * m + j0 + j] : cz(); }, acc, sm, ni, nj);
       ztile_store_t<64>(acc, [&](int i, int j, double re, double im) {
@@ -259,7 +276,7 @@ __global__ void __launch_bounds__(256) k_rhs_fwd(Ctx c, RhsCtx r, const int32_t*
 // Back substitution (top-down by levels): X_I = A_ii^{-1} Z_I + Psi_i X_{B_i},
 // both products into one tile, the B_i rows gathered from the ancestors'
 // final rows of X; the cluster's rows of X are written once.
-__global__ void __launch_bounds__(256) k_rhs_back(Ctx c, RhsCtx r, const int32_t* cls) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_rhs_back(Ctx c, RhsCtx r, const int32_t* cls) {
   __shared__ GemmSmem sm;
   const int cl = cls[blockIdx.x];
   const int e = blockIdx.y;
@@ -276,11 +293,11 @@ __global__ void __launch_bounds__(256) k_rhs_back(Ctx c, RhsCtx r, const int32_t
     const int nj = min(64, m - j0);
     ZTile acc;
     ztile_zero(acc);
-    zgemm_acc_t<64, false, false, false>(
+    zgemm_acc_t<64, false, false, true>(
         s, [&](int i, int k) { return i < s ? Ainv[i * s + k] : cz(); },
         [&](int k, int j) { return j < nj ? Zf[(int64_t)k * m + j0 + j] : cz(); }, acc, sm, s, nj);
     if (b > 0)
-      zgemm_acc_t<64, false, false, false>(
+      zgemm_acc_t<64, false, false, true>(
           b, [&](int i, int k) { return i < s ? Psi[(int64_t)i * b + k] : cz(); },
           [&](int k, int j) { return j < nj ? X[(int64_t)bidx[k] * m + j0 + j] : cz(); }, acc, sm, s, nj);
     ztile_store_t<64>(acc, [&](int i, int j, double re, double im) {
@@ -295,7 +312,7 @@ __global__ void __launch_bounds__(256) k_rhs_back(Ctx c, RhsCtx r, const int32_t
 // cores and consumed in registers (never stored); the row sums are reduced
 // across the lanes of a row and the two column halves of the tile, column
 // tiles in order (deterministic).
-__global__ void __launch_bounds__(256) k_vjp(Ctx c, RhsCtx r, int cc, int off) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_vjp(Ctx c, RhsCtx r, int cc, int off) {
   __shared__ GemmSmem sm;
   using T = TileShape<64>;
   __shared__ double rowsum[T::WN][64];
@@ -318,7 +335,7 @@ __global__ void __launch_bounds__(256) k_vjp(Ctx c, RhsCtx r, int cc, int off) {
     const int nj = min(64, mc - j0);
     ZTile acc;
     ztile_zero(acc);
-    zgemm_acc_t<64, false, false, false>(
+    zgemm_acc_t<64, false, false, true>(
         mc, [&](int i, int k) { return i < ni ? G[(int64_t)(i0 + i) * m + k] : cz(); },
         [&](int k, int j) { return j < nj ? sg[(int64_t)k * mc + j0 + j] : cz(); }, acc, sm, ni, nj);
 #pragma unroll
