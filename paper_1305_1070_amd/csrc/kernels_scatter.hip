@@ -245,8 +245,11 @@ __device__ __forceinline__ void anc_n_product(const Ctx& c, const ScatCtx& x, co
 
 // N_i over one 64-column tile of the frame.  The own term Sigma^<_ph conj(G)
 // reads the G^(0) entry that N_i replaces (same element, same thread).
+// An explicit occupancy target: left to itself the compiler keeps the
+// accumulators in AGPRs and runs the 64-row tiles at two wavefronts per SIMD.
 template <int TM>
-__global__ void __launch_bounds__(256) k_anc_n(Ctx c, ScatCtx x, const ColItem* items) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 64 ? 3 : 4)))
+k_anc_n(Ctx c, ScatCtx x, const ColItem* items) {
   __shared__ GemmSmemR<TM> sm;
   __shared__ double2 sig_row[kClusterRows];
   const WorkIdx wk = xcd_work();
