@@ -206,6 +206,28 @@ def test_equilibrium_lesser():
         assert _rel(gl, rhs) < 1e-11
 
 
+def test_density_is_occupied_lead_spectral_weight_in_equilibrium():
+    """definition.density's sign and factor -i, pinned by the equilibrium
+    identity above: -i G^<_ii = f (A_ii - 2 eta (G G^+)_ii) with
+    A = -2 Im G^r, i.e. f (G Gamma_leads G^+)_ii, so the density with
+    weights c_E is sum_E c_E f(E) (G Gamma_leads G^+)_ii >= 0."""
+    dev = devices.fd2d(8, 4)
+    wl = workloads.Workload("eq", dev, np.array([0.05, 0.1, 0.2]), 1e-2, (0.1, 0.1), 0.025)
+    e, sr, sl = _problem(wl)
+    c_e = np.array([0.3, 0.5, 0.2])
+    dgl, ref = [], np.zeros(dev.n)
+    for k in range(len(e)):
+        g, gl = definition.full_greens(dev.scipy_h(), None, e[k], wl.eta, dev.contacts,
+                                       [s[k] for s in sr], [s[k] for s in sl])
+        dgl.append(np.diag(gl))
+        f = leads.fermi(e[k], 0.1, 0.025)
+        a = -2.0 * np.imag(np.diag(g))
+        ref += c_e[k] * f * (a - 2.0 * wl.eta * np.real(np.diag(g @ g.conj().T)))
+    n = definition.density(np.array(dgl), c_e)
+    assert np.all(n > 0)
+    assert _rel(n, ref) < 1e-11
+
+
 # ---------------------------------------------------------------------------
 # diagonal phonon self-energies (Sigma^r_Phonon of equation defineA, diagonal
 # as Section 1 takes it; its lesser part adds to Sigma^<)
