@@ -253,7 +253,7 @@ __device__ __forceinline__ void update_body(const Ctx& c, const UpdItem* items) 
   }
   typename GM::Tile acc;
   GM::zero(acc);
-  GM::template acc<TM, true, false>(
+  GM::template acc<TM, true, false, (TM != 64)>(
       s, [&](int i, int k) { return i < ni ? Psi[(int64_t)k * b + i0 + i] : cz(); },
       [&](int k, int j) { return j < nj ? F[(int64_t)k * f + s + j0 + j] : cz(); }, acc, sm, ni, nj);
   // F_BB gathered from the children: each lane holds fixed tile rows and
@@ -322,7 +322,7 @@ __device__ __forceinline__ void update_body(const Ctx& c, const UpdItem* items) 
 }
 
 template <bool P64>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P64 ? 4 : 3)))
 k_update(Ctx c, const UpdItem* items) {
   update_body<64, P64>(c, items);
 }
@@ -606,14 +606,14 @@ k_down_off_narrow(Ctx c, const ColItem* items) {
 //   G_ii = A_ii^{-1} + Psi_i G_{B,i},  G_{B,i} = G_{i,B}^T
 //   P_ii = P_init + Psi_i P_{B,i},     P_{B,i} = -P_{i,B}^+
 // Tile (r0, c0) of the block (TM x 64) as the product Psi_i X_{B,i} in acc.
-template <int TM, bool P64, int L, class SM>
+template <int TM, bool P64, int L, bool PF = true, class SM>
 __device__ __forceinline__ void down_diag_tile(const double2* Psi, const double2* X, int s, int b, int f, int r0,
                                                int c0, typename Gemm<P64>::Tile& acc, SM& sm) {
   using GM = Gemm<P64>;
   const int ni = min(TM, s - r0), nj = min(64, s - c0);
   GM::zero(acc);
   if constexpr (L != 0) {
-    GM::template acc<TM, false, true>(
+    GM::template acc<TM, false, true, PF>(
         b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
         [&](int k, int j) {
           if (j >= nj) return cz();
@@ -622,7 +622,7 @@ __device__ __forceinline__ void down_diag_tile(const double2* Psi, const double2
         },
         acc, sm, ni, nj);
   } else {
-    GM::template acc<TM, false, true>(
+    GM::template acc<TM, false, true, PF>(
         b, [&](int i, int k) { return i < ni ? Psi[(int64_t)(r0 + i) * b + k] : cz(); },
         [&](int k, int j) { return j < nj ? X[(int64_t)(c0 + j) * f + s + k] : cz(); }, acc, sm, ni, nj);
   }
@@ -694,7 +694,7 @@ __device__ __forceinline__ void down_diag_single_body(const Ctx& c, const int32_
   const int s = d.s, b = d.b, f = d.f;
   const bool has_src = lesser && (d.chain_mask || c.scat);
   ZTile acc;
-  down_diag_tile<TM, true, L>(Psi, X, s, b, f, 0, 0, acc, sm);
+  down_diag_tile<TM, true, L, TM != 64>(Psi, X, s, b, f, 0, 0, acc, sm);
   // the block before symmetrization: the product plus U_i (G) or the
   // source (P, on the contact chains)
   ztile_apply_t<TM>(acc, [&](int i, int j, double& re, double& im) {
@@ -745,7 +745,7 @@ k_down_diag_narrow(Ctx c, const int32_t* cls) {
   down_diag_body<16, P64, L>(c, cls);
 }
 template <int TM, int L>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 64 ? 4 : 3)))
 k_down_diag_single(Ctx c, const int32_t* cls) {
   down_diag_single_body<TM, L>(c, cls);
 }
