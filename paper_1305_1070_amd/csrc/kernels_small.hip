@@ -165,8 +165,9 @@ __device__ __forceinline__ void fold_small_body(const Ctx& c, const int32_t* cls
   }
 }
 
-// Entry points: the 32- and 64-point classes fit 128 registers, so four
-// wavefronts per SIMD; the 48-point class (three columns per thread) does not;
+// Entry points: the 32-, 40- and 64-point classes fit 128 registers, so four
+// wavefronts per SIMD; the 48-point class runs four wavefronts per front
+// (three rows and three columns per thread) in 85 registers, five per SIMD;
 // the 24-point class fits 102 (five), the most it takes without spills.
 template <int SF, int NT, int JS>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
@@ -176,10 +177,6 @@ k_fold_small(Ctx c, const int32_t* cls) {
 template <int SF, int NT, int JS>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
 k_fold_small_narrow(Ctx c, const int32_t* cls) {
-  fold_small_body<SF, NT, JS>(c, cls);
-}
-template <int SF, int NT, int JS>
-__global__ void __launch_bounds__(NT) k_fold_small_wide(Ctx c, const int32_t* cls) {
   fold_small_body<SF, NT, JS>(c, cls);
 }
 
@@ -363,7 +360,7 @@ void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int fr
   if (front_size <= 24) hipLaunchKernelGGL((k_fold_small_narrow<24, 64, 8>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
   else if (front_size <= 32) hipLaunchKernelGGL((k_fold_small<32, 64, 8>), dim3(ncl, nb), dim3(64), 0, st, c, cls);
   else if (front_size <= 40) hipLaunchKernelGGL((k_fold_small<40, 128, 16>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
-  else if (front_size <= 48) hipLaunchKernelGGL((k_fold_small_wide<48, 128, 16>), dim3(ncl, nb), dim3(128), 0, st, c, cls);
+  else if (front_size <= 48) hipLaunchKernelGGL((k_fold_small<48, 256, 16>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
   else hipLaunchKernelGGL((k_fold_small<64, 256, 16>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
 }
 
