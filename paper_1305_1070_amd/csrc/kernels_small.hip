@@ -183,8 +183,8 @@ k_fold_small_narrow(Ctx c, const int32_t* cls) {
 // Extraction of G^r (which = 0) or G^< (which = 1) for one small front; the
 // two run as separate launches on two streams.  X_{B,B} is gathered from the
 // stored rows of the clusters owning B (gather_bb).  Dynamic LDS holds
-// Psi (s x b), the gathered B x B block of the parent's front (later X_ii)
-// and X_{i,B}.
+// Psi (s x b), the gathered upper triangle of the B x B block of the parent's
+// front (the space later holds X_ii) and X_{i,B}.
 // A leaf's blocks are read by nobody but the epilogue, so a leaf forms and
 // stores only the diagonal of X_ii.
 template <int NT>
@@ -208,9 +208,10 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
   const bool chain = c.scat || d.chain_mask != 0;
   const double2* Ainv = S + d.o_ainv;
   double2* Psl = sm;              // s x b, stride lb
-  double2* XBB = sm + s * lb;     // b x b
+  double2* XBB = sm + s * lb;     // upper triangle of X_{B,B}, row-major
   const int ls = s | 1;           // odd row stride of X_ii (its transpose is read)
-  double2* XIB = XBB + max(b * b, s * ls);  // s x b, stride lb (X_{B,B} is later X_ii)
+  const int ntri = b * (b + 1) / 2;
+  double2* XIB = XBB + max(ntri, s * ls);  // s x b, stride lb (X_{B,B} is later X_ii)
   double2* XII = XBB;
   const double2* Psi = S + d.o_psi;
   // two entries per thread at a time (their loads in flight together)
@@ -225,17 +226,16 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
     double2* X = S + (lesser ? d.o_fp : d.o_fg);
     const bool src = lesser && chain;
     // X_{B,B} is complex symmetric for G^r and anti-Hermitian for G^<
-    // (X_vu = -conj(X_uv)): the upper triangle is gathered and mirrored.
+    // (X_vu = -conj(X_uv)): only the upper triangle is gathered and kept.
     // Entry q of the triangle is (k, j), k <= j, rows of length b - k
     // starting at k b - k (k - 1) / 2.
-    const int ntri = b * (b + 1) / 2;
     const float bh = (float)b + 0.5f;
     // four entries per thread at a time (their table entries, then their
     // values, loaded together) where the triangle spans several rounds of
     // the block; one at a time on tiny fronts
     if (ntri > 2 * NT) {
       for (int q0 = t; q0 < ntri; q0 += 4 * NT) {
-        int kk[4], jj[4];
+        int jj[4];
         int32_t m[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -244,7 +244,6 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
           k = min(max(k, 0), b - 1);
           if (k * b - (k * (k - 1) >> 1) > q) --k;
           else if (k + 1 < b && (k + 1) * b - ((k + 1) * k >> 1) <= q) ++k;
-          kk[u] = k;
           jj[u] = k + q - (k * b - (k * (k - 1) >> 1));
           if (q < ntri) m[u] = gather_bb_entry(c, d, k, jj[u]);
         }
@@ -254,11 +253,7 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
           if (q0 + u * NT < ntri) x[u] = gather_bb_value(c, S, m[u], lesser != 0);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (q0 + u * NT < ntri) {
-            const int k = kk[u], j = jj[u];
-            XBB[k * b + j] = x[u];
-            if (j != k) XBB[j * b + k] = lesser ? make_double2(-x[u].x, x[u].y) : x[u];
-          }
+          if (q0 + u * NT < ntri) XBB[q0 + u * NT] = x[u];
       }
     } else {
       for (int q = t; q < ntri; q += NT) {
@@ -267,9 +262,7 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
         if (k * b - (k * (k - 1) >> 1) > q) --k;
         else if (k + 1 < b && (k + 1) * b - ((k + 1) * k >> 1) <= q) ++k;
         const int j = k + q - (k * b - (k * (k - 1) >> 1));
-        const double2 x = gather_bb(c, S, d, k, j, lesser != 0);
-        XBB[k * b + j] = x;
-        if (j != k) XBB[j * b + k] = lesser ? make_double2(-x.x, x.y) : x;
+        XBB[q] = gather_bb(c, S, d, k, j, lesser != 0);
       }
     }
     __syncthreads();
@@ -283,8 +276,16 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
       double2 a1 = (src && two) ? X[(int64_t)(r0 + 1) * f + s + j] : cz();
       const double2* p0r = Psl + r0 * lb;
       const double2* p1r = Psl + (two ? r0 + 1 : r0) * lb;
+      // X_{B,B}[k][j]: (k, j) of the triangle for k <= j, at up (from (0, j)
+      // = j, each row b - k - 1 further on), else the mirror of (j, k), at
+      // mj + k
+      const int mj = j * b - ((j * (j - 1)) >> 1) - j;
+      int up = j;
       for (int k = 0; k < b; ++k) {
-        const double2 x = XBB[k * b + j];
+        const bool upper = k <= j;
+        double2 x = XBB[upper ? up : mj + k];
+        if (lesser && !upper) x.x = -x.x;
+        up += upper ? b - k - 1 : 0;
         const double2 p0 = p0r[k], p1 = p1r[k];
         cmac(a0, p0, x);
         cmac(a1, p1, x);

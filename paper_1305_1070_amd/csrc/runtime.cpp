@@ -375,8 +375,8 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
         if (q <= 2) {
           g.size = std::max(g.size, s_ + b);
           // Psi and X_{i,B} rows padded to an odd stride (bank spread);
-          // X_{B,B}, later X_ii
-          g.lds = std::max(g.lds, (size_t)(2 * s_ * (b | 1) + std::max(b * b, s_ * (s_ | 1))) * 16);
+          // the upper triangle of X_{B,B}, later X_ii
+          g.lds = std::max(g.lds, (size_t)(2 * s_ * (b | 1) + std::max(b * (b + 1) / 2, s_ * (s_ | 1))) * 16);
         } else {
           g.size = std::max(g.size, s_);
           const int nt = (b + 63) / 64;
