@@ -52,7 +52,9 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
   // -H, z - V on the diagonal, -Sigma, then the children's terms: one pass
   // over all s f entries, so short rows do not idle threads.  Four entries
   // per thread at a time, so that each round of dependent loads (map
-  // entries, then the values they point to) is issued for all four at once.
+  // entries, then the values they point to) is issued for all four at once;
+  // the first child's map entries go out with the template's loads, and
+  // each later child's before the previous child's values are waited for.
   const int nq = s * f;
   for (int q0 = t; q0 < nq; q0 += 4 * 256) {
     int ii[4], jj[4], qq[4];
@@ -64,6 +66,15 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
       jj[u] = qq[u] - ii[u] * f;
       re[u] = hf[qq[u]];
       im[u] = 0.0;
+    }
+    int ri[4], rj[4];
+    if (nk > 0) {
+      const int32_t* inv = c.pinv + kid_inv[0];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ri[u] = inv[ii[u]];
+        rj[u] = inv[jj[u]];
+      }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -91,20 +102,27 @@ __global__ void __launch_bounds__(256) k_assemble(Ctx c, const int32_t* cls) {
         }
     }
     for (int kq = 0; kq < nk; ++kq) {
-      const int32_t* inv = c.pinv + kid_inv[kq];
-      int ri[4], rj[4];
+      bool in[4];
+      double2 x[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        ri[u] = inv[ii[u]];
-        rj[u] = inv[jj[u]];
+        in[u] = ri[u] >= 0 && rj[u] >= 0;
+        // the contribution's upper triangle holds both (symmetric)
+        if (in[u]) x[u] = S[kid_upd[kq] + (int64_t)min(ri[u], rj[u]) * kid_b[kq] + max(ri[u], rj[u])];
+      }
+      if (kq + 1 < nk) {
+        const int32_t* inv = c.pinv + kid_inv[kq + 1];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ri[u] = inv[ii[u]];
+          rj[u] = inv[jj[u]];
+        }
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (ri[u] >= 0 && rj[u] >= 0) {
-          // the contribution's upper triangle holds both (symmetric)
-          const double2 x = S[kid_upd[kq] + (int64_t)min(ri[u], rj[u]) * kid_b[kq] + max(ri[u], rj[u])];
-          re[u] += x.x;
-          im[u] += x.y;
+        if (in[u]) {
+          re[u] += x[u].x;
+          im[u] += x[u].y;
         }
     }
 #pragma unroll
