@@ -215,7 +215,13 @@ void launch_chain_t(const Ctx& c, const ChainItem* it, int nit, int nb, hipStrea
 void launch_chain_back(const Ctx& c, const int32_t* cls, int ncl, int nb, hipStream_t st);
 // small fronts: f <= 32 (one wave per front) or f <= 64 (four waves)
 void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int front_size, hipStream_t st);
-void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, size_t lds_bytes,
+// Small-front extraction: threads per block for a group's largest front, and
+// how many (row pair, column) items of X_{i,B} a thread of such a block may
+// hold in registers (ceil(s / 2) b is at most 136, 300, 528 for fronts of 32,
+// 48, 64 points: two items cover all but the few 32-point leaves above 128).
+constexpr int extract_threads(int front_size) { return front_size <= 32 ? 64 : front_size <= 48 ? 256 : 512; }
+constexpr int extract_leaf_items(int) { return 2; }
+void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, size_t lds_bytes, size_t lds_bytes_leaf,
                           int front_size, bool lesser, hipStream_t st);
 constexpr int kSmallFront = 64;
 constexpr int kMaxKids = 64;  // children per cluster (front assembly tables)  // fronts up to this size are handled whole on chip

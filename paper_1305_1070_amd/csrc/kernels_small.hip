@@ -206,12 +206,17 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
   // contact's clusters keep full rows for the terminal currents
   const bool inner = c.scat || d.chain_mask != 0 || c.kids_ptr[cl + 1] > c.kids_ptr[cl];
   const bool chain = c.scat || d.chain_mask != 0;
+  // a leaf forms only the diagonal of X_ii: its X_{i,B} can replace X_{B,B}
+  // in LDS (the launch sizes LDS for that when no cluster is inner)
+  constexpr int kLeafItems = extract_leaf_items(NT);
+  const bool leaf = !inner && ((s + 1) >> 1) * b <= kLeafItems * NT;
   const double2* Ainv = S + d.o_ainv;
   double2* Psl = sm;              // s x b, stride lb
   double2* XBB = sm + s * lb;     // upper triangle of X_{B,B}, row-major
   const int ls = s | 1;           // odd row stride of X_ii (its transpose is read)
   const int ntri = b * (b + 1) / 2;
-  double2* XIB = XBB + max(ntri, s * ls);  // s x b, stride lb (X_{B,B} is later X_ii)
+  // s x b, stride lb (X_{B,B} is later X_ii; a leaf's X_{i,B} replaces it)
+  double2* XIB = leaf ? XBB : XBB + max(ntri, s * ls);
   double2* XII = XBB;
   const double2* Psi = S + d.o_psi;
   // two entries per thread at a time (their loads in flight together)
@@ -269,11 +274,12 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
     // X_{i,B} = P_init + Psi X_{B,B}: two rows per thread share each X_{B,B}
     // operand (rows r0 and r0 + 1, one column)
     const int sp2 = (s + 1) >> 1;
-    for (int q = t; q < sp2 * b; q += NT) {
+    // item q: rows r0 = 2 (q / b) and r0 + 1 (if any), column j = q % b
+    auto item = [&](int q, double2& a0, double2& a1) {
       const int r0 = (q / b) << 1, j = q - (q / b) * b;
       const bool two = r0 + 1 < s;
-      double2 a0 = src ? X[(int64_t)r0 * f + s + j] : cz();
-      double2 a1 = (src && two) ? X[(int64_t)(r0 + 1) * f + s + j] : cz();
+      a0 = src ? X[(int64_t)r0 * f + s + j] : cz();
+      a1 = (src && two) ? X[(int64_t)(r0 + 1) * f + s + j] : cz();
       const double2* p0r = Psl + r0 * lb;
       const double2* p1r = Psl + (two ? r0 + 1 : r0) * lb;
       // X_{B,B}[k][j]: (k, j) of the triangle for k <= j, at up (from (0, j)
@@ -290,8 +296,30 @@ k_extract_small(Ctx c, const int32_t* cls, int which) {
         cmac(a0, p0, x);
         cmac(a1, p1, x);
       }
+    };
+    auto put = [&](int q, const double2& a0, const double2& a1) {
+      const int r0 = (q / b) << 1, j = q - (q / b) * b;
       XIB[r0 * lb + j] = a0;
-      if (two) XIB[(r0 + 1) * lb + j] = a1;
+      if (r0 + 1 < s) XIB[(r0 + 1) * lb + j] = a1;
+    };
+    if (leaf) {
+      // X_{i,B} takes the space of X_{B,B} once every thread has read that,
+      // so it waits in registers (at most kLeafItems items per thread; a
+      // leaf with more keeps X_{i,B} apart, as an inner cluster does)
+      double2 v0[kLeafItems], v1[kLeafItems];
+#pragma unroll
+      for (int it = 0; it < kLeafItems; ++it)
+        if (t + it * NT < sp2 * b) item(t + it * NT, v0[it], v1[it]);
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < kLeafItems; ++it)
+        if (t + it * NT < sp2 * b) put(t + it * NT, v0[it], v1[it]);
+    } else {
+      for (int q = t; q < sp2 * b; q += NT) {
+        double2 a0, a1;
+        item(q, a0, a1);
+        put(q, a0, a1);
+      }
     }
     __syncthreads();
     // X_ii = (A_ii^{-1} | P_init) + Psi X_{B,i};  X_{B,i}[k][j] = X_{i,B}[j][k]
@@ -365,7 +393,7 @@ void launch_fold_small(const Ctx& c, const int32_t* cls, int ncl, int nb, int fr
   else hipLaunchKernelGGL((k_fold_small<64, 256, 16>), dim3(ncl, nb), dim3(256), 0, st, c, cls);
 }
 
-void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, size_t lds_bytes,
+void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, size_t lds_bytes, size_t lds_bytes_leaf,
                           int front_size, bool lesser, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
@@ -380,12 +408,13 @@ void launch_extract_small(const Ctx& c, const int32_t* cls, int ncl, int nb, siz
   const int w = lesser ? 1 : 0;
   // the larger classes hold few blocks per CU (LDS), so each block runs more
   // threads: more independent outputs in flight per front
-  if (front_size <= 32)
-    hipLaunchKernelGGL((k_extract_small<64>), dim3(ncl, nb), dim3(64), lds_bytes, st, c, cls, w);
-  else if (front_size <= 48)
-    hipLaunchKernelGGL((k_extract_small<256>), dim3(ncl, nb), dim3(256), lds_bytes, st, c, cls, w);
-  else
-    hipLaunchKernelGGL((k_extract_small<512>), dim3(ncl, nb), dim3(512), lds_bytes, st, c, cls, w);
+  // with phonon sources every cluster keeps its full rows (no leaf layout)
+  const size_t lds = c.scat ? lds_bytes : lds_bytes_leaf;
+  switch (extract_threads(front_size)) {
+    case 64: hipLaunchKernelGGL((k_extract_small<64>), dim3(ncl, nb), dim3(64), lds, st, c, cls, w); break;
+    case 256: hipLaunchKernelGGL((k_extract_small<256>), dim3(ncl, nb), dim3(256), lds, st, c, cls, w); break;
+    default: hipLaunchKernelGGL((k_extract_small<512>), dim3(ncl, nb), dim3(512), lds, st, c, cls, w); break;
+  }
 }
 
 }  // namespace ndg

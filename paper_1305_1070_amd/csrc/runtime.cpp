@@ -66,7 +66,7 @@ struct ndg_plan {
   // per height, the clusters split into size classes: fronts f <= 32, f <= 64
   // (whole on chip), then larger fronts with s <= 16, s <= 32, s <= 64,
   // s <= 128 (separate kernels, tile height following s; 64-row tiles above)
-  struct Group { int cl0 = 0, ncl = 0, col0 = 0, ncol = 0, upd0 = 0, nupd = 0, size = 0; size_t lds = 0; };
+  struct Group { int cl0 = 0, ncl = 0, col0 = 0, ncol = 0, upd0 = 0, nupd = 0, size = 0; size_t lds = 0, lds_leaf = 0; };
   static constexpr int kClasses = 7;
   std::vector<Group> groups;  // [(H + 1) * kClasses]
   double2* d_ws = nullptr;
@@ -376,7 +376,15 @@ int plan_create(const Symbolic& sy, const OpCounts& oc, int max_batch, int devic
           g.size = std::max(g.size, s_ + b);
           // Psi and X_{i,B} rows padded to an odd stride (bank spread);
           // the upper triangle of X_{B,B}, later X_ii
-          g.lds = std::max(g.lds, (size_t)(2 * s_ * (b | 1) + std::max(b * (b + 1) / 2, s_ * (s_ | 1))) * 16);
+          const size_t full = (size_t)(2 * s_ * (b | 1) + std::max(b * (b + 1) / 2, s_ * (s_ | 1))) * 16;
+          g.lds = std::max(g.lds, full);
+          // without phonon sources a leaf off the contact chains keeps X_{i,B}
+          // in the space of X_{B,B} (the kernel's test, with this front's own
+          // block size: a larger group front only raises the items' bound)
+          const int nt = extract_threads(s_ + b);
+          const bool leaf_layout = sy.children[k].empty() && p->hdesc[k].chain_mask == 0 &&
+                                   ((s_ + 1) / 2) * b <= extract_leaf_items(nt) * nt;
+          g.lds_leaf = std::max(g.lds_leaf, leaf_layout ? (size_t)(s_ * (b | 1) + std::max(b * (b + 1) / 2, s_ * (b | 1))) * 16 : full);
         } else {
           g.size = std::max(g.size, s_);
           const int nt = (b + 63) / 64;
@@ -1181,7 +1189,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         const int32_t* cl = p->d_levels + g.cl0;
         if (q <= 2) {
           timed_on(on, lesser ? K_EXTRACT_SMALL_P : K_EXTRACT_SMALL, h, q, nb,
-                   [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, lesser, on); });
+                   [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.lds_leaf, g.size, lesser, on); });
           continue;
         }
         const ColItem* ci = p->d_colitems + g.col0;
@@ -1270,8 +1278,8 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
         // rows (its source comes from the chain kernels)
         const bool gr = mode != kRunDensity;
         if (q <= 2) {
-          timed_on(sp, K_EXTRACT_SMALL_P, h, q, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, true, sp); });
-          if (gr) timed(K_EXTRACT_SMALL, h, q, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.size, false, st); });
+          timed_on(sp, K_EXTRACT_SMALL_P, h, q, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.lds_leaf, g.size, true, sp); });
+          if (gr) timed(K_EXTRACT_SMALL, h, q, nb, [&] { launch_extract_small(c, cl, g.ncl, nb, g.lds, g.lds_leaf, g.size, false, st); });
           continue;
         }
         const ColItem* ci = p->d_colitems + g.col0;
@@ -1310,7 +1318,7 @@ int plan_run(ndg_plan* p, int mode, int nE, const double* E, double eta, const d
             if (!g.ncl) continue;
             const int32_t* cl = p->d_levels + g.cl0;
             if (q <= 2) {
-              launch_extract_small(c2, cl, g.ncl, nb, g.lds, g.size, true, st);
+              launch_extract_small(c2, cl, g.ncl, nb, g.lds, g.lds_leaf, g.size, true, st);
               continue;
             }
             if (g.ncol) launch_down_off(c2, p->d_colitems + g.col0, g.ncol, nb, true, g.size, st);
